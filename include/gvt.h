@@ -1,0 +1,217 @@
+/*
+ * gvt.h — C ABI of the MI355X (gfx950) generalized-vec-trick library.
+ *
+ * The library computes matrix-vector products with pairwise kernel matrices
+ * without forming them (Viljanen, Airola, Pahikkala, "Generalized vec trick
+ * for fast learning of pairwise kernel models"):
+ *
+ *   u = R(a, b) K R(c, e)^T v
+ *
+ * where (a_i, b_i), i < n_out, are the output pairs, (c_j, e_j), j < n_in,
+ * the input (training) pairs, R(.,.) the sampling operators of Section 3, and
+ * K the operator of a pairwise kernel written as a sum of Kronecker products
+ * (Corollary 1).  Each Kronecker term is applied with the generalized vec
+ * trick of Theorem 1 in O(min(qbar n + m nbar, mbar n + q nbar)) time.  The
+ * library also solves the kernel ridge regression system of Section 3
+ * eq. (1), (K + lambda I) a = y, by conjugate gradients on that operator.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers owned by the caller unless a
+ *    parameter says "host".  The library never frees them and keeps no
+ *    reference after the call returns (plans keep their own copies).
+ *  - Matrices are row-major with a leading dimension (elements between row
+ *    starts) >= the number of columns.  Base matrices: D is d_rows x d_cols
+ *    (rows: output-side drugs, columns: input-side drugs), T is
+ *    t_rows x t_cols (same for targets).  Index a_i < d_rows, b_i < t_rows,
+ *    c_j < d_cols, e_j < t_cols; all indices are 0-based int32.
+ *  - Vectors with several right-hand sides are column-major: V is
+ *    n_in x nrhs with column stride ldv >= n_in, U is n_out x nrhs with column
+ *    stride ldu >= n_out.
+ *  - Element type follows the precision: GVT_F64 uses double for D, T, V, U;
+ *    GVT_F32 uses float.  GVT_BF16X3 (bf16 split products with FP32
+ *    accumulation on matrix cores) uses float storage and is available on the
+ *    complete-data dense path only.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
+ *    and the call returns without synchronising unless stated.
+ *  - Errors: 0 = success, > 0 = warning (results written), < 0 = error.
+ *    gvt_last_error() returns a message for the calling thread's last error.
+ *    Error paths never leave kernels running on the stream.
+ *  - Results are deterministic: repeated calls with the same inputs give
+ *    bitwise identical outputs (no floating-point atomics).
+ */
+#ifndef GVT_H
+#define GVT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define GVT_OK 0
+#define GVT_NOT_CONVERGED 1     /* CG hit max_iter; results are written      */
+#define GVT_ERR_ARG (-1)        /* null pointer, negative size, ld < cols... */
+#define GVT_ERR_INDEX (-2)      /* an index is out of range                  */
+#define GVT_ERR_KIND (-3)       /* kind/base-matrix mismatch (homogeneous)   */
+#define GVT_ERR_HIP (-4)        /* HIP runtime failure                       */
+#define GVT_ERR_NOMEM (-5)      /* device allocation failed                  */
+#define GVT_ERR_BREAKDOWN (-6)  /* CG breakdown: p.w <= 0 or non-finite      */
+#define GVT_ERR_UNSUPPORTED (-7)/* precision/path combination not provided   */
+
+/* ---- arithmetic -------------------------------------------------------- */
+#define GVT_F64 0
+#define GVT_F32 1
+#define GVT_BF16X3 2
+#define GVT_BF16X6 3   /* three-way bf16 split, six products (dense path only) */
+
+/* ---- pairwise kernels (Table 4b / Corollary 1) ------------------------ */
+#define GVT_KRONECKER 0     /* D (x) T ; the pairwise Gaussian is this kind on Gaussian bases */
+#define GVT_LINEAR 1        /* D (x) 1 + 1 (x) T                                          */
+#define GVT_POLY2D 2        /* Q(D(x)D)Q^T + 2 D(x)T + PQ(T(x)T)Q^T P                     */
+#define GVT_CARTESIAN 3     /* D (x) I + I (x) T                                          */
+#define GVT_SYMMETRIC 4     /* (P + I)(D (x) D)                       homogeneous         */
+#define GVT_ANTISYMMETRIC 5 /* (I - P)(D (x) D)  (sign of the Table 4b function) homog.   */
+#define GVT_RANKING 6       /* (I - P)(D (x) 1)(I - P)                homogeneous         */
+#define GVT_MLPK 7          /* (I + P)(I - Q)(D (x) D)(I - Q)^T (I + P)  homogeneous      */
+
+/* ---- plan flags ---------------------------------------------------------- */
+#define GVT_FLAG_SYMMETRIC_BASES 1 /* D and T are square and symmetric (training
+                                      kernels): the library may read a column as
+                                      the equal row instead of transposing      */
+#define GVT_FLAG_ORDER_A 2         /* force stage order A (scatter by drug)      */
+#define GVT_FLAG_ORDER_B 4         /* force stage order B (scatter by target)    */
+
+typedef struct gvt_plan *gvt_plan_t;
+
+/*
+ * gvt_plan_create — index preprocessing shared by every product over the
+ * same pair sets (Theorem 1; Table 1 unique counts).
+ *
+ * Validates every index, counts unique drugs/targets per sample, chooses the
+ * cheaper stage order of Theorem 1 per Kronecker term (ties: order A when
+ * d_cols >= t_cols, else B), sorts the input pairs into key segments and
+ * groups the output pairs, and expands each kind into its Kronecker terms
+ * with common subexpressions shared across the `nkinds` kinds.
+ *
+ * kinds[nkinds] (host): GVT_* kind codes; one output block per kind.
+ * Homogeneous kinds need t_rows == d_rows and t_cols == d_cols (T is
+ * ignored; pass the D shape).  Index arrays are device pointers, read once
+ * (the call synchronises `stream`).  *plan receives an opaque handle owned by
+ * the caller; release it with gvt_plan_destroy.  n_in == 0 or n_out == 0 is
+ * valid (products then write zeros / nothing).
+ * Errors: GVT_ERR_ARG, GVT_ERR_INDEX, GVT_ERR_KIND, GVT_ERR_HIP, GVT_ERR_NOMEM.
+ */
+int gvt_plan_create(gvt_plan_t *plan, const int *kinds, int nkinds, int64_t d_rows,
+                    int64_t d_cols, int64_t t_rows, int64_t t_cols, const int32_t *out_a,
+                    const int32_t *out_b, int64_t n_out, const int32_t *in_c,
+                    const int32_t *in_e, int64_t n_in, int flags, void *stream);
+
+/* gvt_plan_destroy — synchronises the plan's last stream and frees its
+ * device memory.  NULL is accepted. */
+int gvt_plan_destroy(gvt_plan_t plan);
+
+/*
+ * gvt_plan_execute — U_k = R(a,b) K_{kinds[k]} R(c,e)^T V for every kind of
+ * the plan (Corollary 1: each kind is a sum of Kronecker terms, each term one
+ * generalized vec trick, Theorem 1).
+ *
+ * D (ldd) and T (ldt) must have the shapes given at plan creation (T may be
+ * NULL for homogeneous kinds).  V: n_in x nrhs, column stride ldv.  U: the
+ * plan's nkinds output blocks stacked, block k at U + k*nrhs*ldu, each
+ * n_out x nrhs with column stride ldu.  Asynchronous on `stream`.
+ * Errors: GVT_ERR_ARG, GVT_ERR_UNSUPPORTED (GVT_BF16X3 on the gather path),
+ * GVT_ERR_HIP, GVT_ERR_NOMEM.
+ */
+int gvt_plan_execute(gvt_plan_t plan, int prec, const void *D, int64_t ldd, const void *T,
+                     int64_t ldt, const void *V, int64_t nrhs, int64_t ldv, void *U,
+                     int64_t ldu, void *stream);
+
+/*
+ * gvt_matvec — one generalized vec trick product (Theorem 1):
+ *   U = R(a, b) (M (x) N) R(c, e)^T V
+ * M: m_rows x m_cols (rows: output drugs, cols: input drugs), N: n_rows x
+ * n_cols.  Plans internally and synchronises `stream` before returning.
+ * When the input and output pairs are each the complete grid in natural
+ * order (pair (d, t) at index d*cols + t, Section 4 Example), the product is
+ * the dense contraction Umat = M Vmat N^T and runs on matrix cores.
+ * Errors as gvt_plan_create / gvt_plan_execute.
+ */
+int gvt_matvec(int prec, const void *M, int64_t m_rows, int64_t m_cols, int64_t ldm,
+               const void *N, int64_t n_rows, int64_t n_cols, int64_t ldn,
+               const int32_t *out_a, const int32_t *out_b, int64_t n_out, const int32_t *in_c,
+               const int32_t *in_e, int64_t n_in, const void *V, int64_t nrhs, int64_t ldv,
+               void *U, int64_t ldu, void *stream);
+
+/*
+ * gvt_pairwise_matvec — U_k = R(a,b) K_{kinds[k]}(D, T) R(c,e)^T V for
+ * nkinds kinds in one planned, fused pass (Corollary 1; shared stage-1
+ * scatters and one-factor products across kinds).  Output blocks as in
+ * gvt_plan_execute.  `flags` as in gvt_plan_create.  Plans internally and
+ * synchronises `stream` before returning.
+ */
+int gvt_pairwise_matvec(int prec, const int *kinds, int nkinds, const void *D, int64_t d_rows,
+                        int64_t d_cols, int64_t ldd, const void *T, int64_t t_rows,
+                        int64_t t_cols, int64_t ldt, const int32_t *out_a, const int32_t *out_b,
+                        int64_t n_out, const int32_t *in_c, const int32_t *in_e, int64_t n_in,
+                        const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu,
+                        int flags, void *stream);
+
+/*
+ * gvt_dense_matvec — the complete-data case of the Kronecker product.  With
+ * every pair of the grid present in natural order (pair (d, t) at index
+ * d*cols + t, the ordering of the Section 4 Example), R(.,.) are identities
+ * and (M (x) N) vec(Vmat) = vec(M Vmat N^T) (row-major vec).
+ * M: m_rows x m_cols (ldm), N: n_rows x n_cols (ldn), Vmat: m_cols x n_cols
+ * (ldv), Umat: m_rows x n_rows (ldu), all row-major.  Two matrix-core GEMMs,
+ * W = M Vmat and Umat = W N^T; W is stream-ordered library workspace.
+ * prec: GVT_F64 (FP64 MFMA), GVT_F32 (FP32 MFMA) or GVT_BF16X3 (float
+ * storage; each operand split x = hi + lo into bf16 with round-to-nearest-
+ * even, products hi*hi' + hi*lo' + lo*hi' on bf16 MFMA with FP32
+ * accumulation; W is split again for the second GEMM).  Asynchronous.
+ */
+int gvt_dense_matvec(int prec, const void *M, int64_t m_rows, int64_t m_cols, int64_t ldm,
+                     const void *N, int64_t n_rows, int64_t n_cols, int64_t ldn, const void *V,
+                     int64_t ldv, void *U, int64_t ldu, void *stream);
+
+/*
+ * gvt_krr_cg — kernel ridge regression, Section 3 eq. (1):
+ *   (R K R^T + lambda_l I) a_l = y   for l < nlam (one shared operator,
+ *   nlam right-hand sides advanced together as one batched product)
+ * by conjugate gradients with FP64 vectors, inner products and step lengths
+ * (the paper solves the same SPD system with MINRES and early stopping).
+ *
+ * kind: any GVT_* kind.  D (d x d, ldd) and T (t x t, ldt) are double,
+ * square and symmetric (training kernels; T ignored for homogeneous kinds).
+ * c, e: the n training pairs (device).  y: n labels (device, double).
+ * lambdas[nlam] (host) > 0.  A: n x nlam solutions (device, double, column
+ * stride lda >= n).  A0: optional initial guess with the same layout
+ * (stride lda0), NULL = zero.  matvec_prec: GVT_F64 or GVT_F32 (products in
+ * FP32, everything else FP64; when the recurrence residual meets `tol` the
+ * true residual is recomputed with an FP64 product and CG restarts from it
+ * unless it also meets `tol`).  check_every: iterations between host
+ * convergence checks (>= 1).  iters_out[nlam] and relres_out[nlam] (host)
+ * receive the iteration counts and the TRUE relative residuals
+ * ||y - (K + lambda I) a|| / ||y|| computed with an FP64 product.
+ * Synchronises `stream`.  Returns GVT_OK when every system met `tol`,
+ * GVT_NOT_CONVERGED when some reached max_iter, GVT_ERR_BREAKDOWN on
+ * p.w <= 0 or a non-finite value, other errors as above.
+ */
+int gvt_krr_cg(int kind, const double *D, int64_t d, int64_t ldd, const double *T, int64_t t,
+               int64_t ldt, const int32_t *c, const int32_t *e, int64_t n, const double *y,
+               const double *lambdas, int nlam, double *A, int64_t lda, const double *A0,
+               int64_t lda0, int max_iter, double tol, int matvec_prec, int check_every,
+               int64_t *iters_out, double *relres_out, void *stream);
+
+/* Message describing the calling thread's most recent error ("" if none). */
+const char *gvt_last_error(void);
+
+/* Library version: major*10000 + minor*100 + patch. */
+int gvt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GVT_H */

@@ -1,0 +1,34 @@
+"""MI355X (gfx950) generalized vec trick for pairwise kernel learning.
+
+Thin Python binding over the C ABI in ``include/gvt.h`` (``libgvt.so``, built
+in-tree by ``paper_2009_01054_amd.build``).  The functions keep the C names
+and only marshal arguments: torch tensors provide device memory and the
+current HIP stream; every step of the computation runs in the library's HIP
+kernels.  There is no fallback: if the library is missing or the device is
+not available, calls raise.
+"""
+from __future__ import annotations
+
+from ._binding import (  # noqa: F401
+    BF16X3,
+    BF16X6,
+    F32,
+    F64,
+    FLAG_ORDER_A,
+    FLAG_ORDER_B,
+    FLAG_SYMMETRIC_BASES,
+    KINDS,
+    GvtError,
+    Plan,
+    gvt_dense_matvec,
+    gvt_krr_cg,
+    gvt_last_error,
+    gvt_matvec,
+    gvt_pairwise_matvec,
+    gvt_plan_create,
+    gvt_plan_destroy,
+    gvt_plan_execute,
+    gvt_version,
+    library_path,
+    load_library,
+)

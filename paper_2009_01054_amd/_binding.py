@@ -1,0 +1,270 @@
+"""ctypes marshalling for libgvt.so (no computation here)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libgvt.so")
+
+F64, F32, BF16X3, BF16X6 = 0, 1, 2, 3
+FLAG_SYMMETRIC_BASES, FLAG_ORDER_A, FLAG_ORDER_B = 1, 2, 4
+KINDS = {
+    "kronecker": 0,
+    "gaussian": 0,
+    "linear": 1,
+    "poly2d": 2,
+    "cartesian": 3,
+    "symmetric": 4,
+    "antisymmetric": 5,
+    "ranking": 6,
+    "mlpk": 7,
+}
+NOT_CONVERGED = 1
+
+_lib = None
+
+
+class GvtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libgvt error {code}: {msg}")
+        self.code = code
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load the in-tree HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            f"{_LIB_PATH} is missing: build it with `python -m paper_2009_01054_amd.build` "
+            "(there is no CPU fallback)"
+        )
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, I64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.gvt_last_error.restype = ctypes.c_char_p
+    lib.gvt_version.restype = I
+    lib.gvt_plan_create.argtypes = [ctypes.POINTER(P), P, I, I64, I64, I64, I64, P, P, I64, P, P, I64, I, P]
+    lib.gvt_plan_destroy.argtypes = [P]
+    lib.gvt_plan_execute.argtypes = [P, I, P, I64, P, I64, P, I64, I64, P, I64, P]
+    lib.gvt_matvec.argtypes = [I, P, I64, I64, I64, P, I64, I64, I64, P, P, I64, P, P, I64, P, I64, I64, P, I64, P]
+    lib.gvt_pairwise_matvec.argtypes = [I, P, I, P, I64, I64, I64, P, I64, I64, I64, P, P, I64, P, P, I64,
+                                        P, I64, I64, P, I64, I, P]
+    lib.gvt_dense_matvec.argtypes = [I, P, I64, I64, I64, P, I64, I64, I64, P, I64, P, I64, P]
+    lib.gvt_krr_cg.argtypes = [I, P, I64, I64, P, I64, I64, P, P, I64, P, P, I, P, I64, P, I64, I,
+                               ctypes.c_double, I, I, P, P, P]
+    for f in ("gvt_plan_create", "gvt_plan_destroy", "gvt_plan_execute", "gvt_matvec",
+              "gvt_pairwise_matvec", "gvt_dense_matvec", "gvt_krr_cg"):
+        getattr(lib, f).restype = I
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise GvtError(rc, load_library().gvt_last_error().decode())
+    return rc
+
+
+def gvt_last_error() -> str:
+    return load_library().gvt_last_error().decode()
+
+
+def gvt_version() -> int:
+    return int(load_library().gvt_version())
+
+
+# ------------------------------------------------------------------ helpers
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream_handle(device=None):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _ld(t):
+    """Row stride of a row-major 2-D tensor (elements)."""
+    assert t.dim() == 2 and t.stride(1) == 1, "base matrices must be row-major (stride(1) == 1)"
+    return max(t.stride(0), t.shape[1], 1)
+
+
+def _idx(x):
+    torch = _torch()
+    assert x.dtype == torch.int32 and x.is_cuda and x.is_contiguous(), "indices: contiguous int32 device tensors"
+    return x
+
+
+def _prec_of(dtype, prec):
+    torch = _torch()
+    if prec is not None:
+        return prec
+    if dtype == torch.float64:
+        return F64
+    if dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def _colmajor(V):
+    """(n,) or (n, r) tensor -> column-major (n, r) view/copy and ld."""
+    V2 = V.reshape(-1, 1) if V.dim() == 1 else V
+    if V2.stride(0) != 1:
+        V2 = V2.t().contiguous().t()
+    return V2, max(V2.stride(1) if V2.shape[1] > 1 else V2.shape[0], 1)
+
+
+def _kind_codes(kinds):
+    if isinstance(kinds, (str, int)):
+        kinds = [kinds]
+    return [KINDS[k] if isinstance(k, str) else int(k) for k in kinds]
+
+
+# --------------------------------------------------------------------- plans
+class Plan:
+    """Owning wrapper of a gvt_plan_t."""
+
+    def __init__(self, handle, nkinds, n_out, n_in):
+        self.handle = handle
+        self.nkinds = nkinds
+        self.n_out = n_out
+        self.n_in = n_in
+
+    def execute(self, D, T, V, prec=None, out=None):
+        return gvt_plan_execute(self, D, T, V, prec=prec, out=out)
+
+    def close(self):
+        if self.handle:
+            gvt_plan_destroy(self)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gvt_plan_create(kinds, d_shape, t_shape, out_pairs, in_pairs, flags=0):
+    lib = load_library()
+    codes = _kind_codes(kinds)
+    karr = (ctypes.c_int * len(codes))(*codes)
+    a, b = _idx(out_pairs[0]), _idx(out_pairs[1])
+    c, e = _idx(in_pairs[0]), _idx(in_pairs[1])
+    h = ctypes.c_void_p(0)
+    _check(lib.gvt_plan_create(ctypes.byref(h), karr, len(codes), d_shape[0], d_shape[1], t_shape[0],
+                               t_shape[1], _ptr(a), _ptr(b), a.numel(), _ptr(c), _ptr(e), c.numel(),
+                               int(flags), _stream_handle()))
+    return Plan(h, len(codes), a.numel(), c.numel())
+
+
+def gvt_plan_destroy(plan: Plan):
+    lib = load_library()
+    h, plan.handle = plan.handle, None
+    _check(lib.gvt_plan_destroy(h))
+
+
+def gvt_plan_execute(plan: Plan, D, T, V, prec=None, out=None):
+    """Returns U of shape (nkinds, n_out, nrhs) (squeezed like V)."""
+    torch = _torch()
+    lib = load_library()
+    p = _prec_of(D.dtype, prec)
+    V2, ldv = _colmajor(V)
+    nrhs = V2.shape[1]
+    U = out if out is not None else torch.empty((plan.nkinds, nrhs, max(plan.n_out, 1)),
+                                                 dtype=D.dtype, device=D.device)
+    ldu = U.shape[2]
+    _check(lib.gvt_plan_execute(plan.handle, p, _ptr(D), _ld(D), _ptr(T), _ld(T) if T is not None else 0,
+                                _ptr(V2), nrhs, ldv, _ptr(U), ldu, _stream_handle()))
+    res = U[:, :, : plan.n_out].transpose(1, 2)
+    if V.dim() == 1:
+        res = res[:, :, 0]
+    return res
+
+
+# ------------------------------------------------------------- one-shot calls
+def gvt_matvec(M, N, out_pairs, in_pairs, V, prec=None):
+    torch = _torch()
+    lib = load_library()
+    p = _prec_of(M.dtype, prec)
+    a, b = _idx(out_pairs[0]), _idx(out_pairs[1])
+    c, e = _idx(in_pairs[0]), _idx(in_pairs[1])
+    V2, ldv = _colmajor(V)
+    nrhs = V2.shape[1]
+    U = torch.empty((nrhs, max(a.numel(), 1)), dtype=M.dtype, device=M.device)
+    _check(lib.gvt_matvec(p, _ptr(M), M.shape[0], M.shape[1], _ld(M), _ptr(N), N.shape[0], N.shape[1],
+                          _ld(N), _ptr(a), _ptr(b), a.numel(), _ptr(c), _ptr(e), c.numel(), _ptr(V2),
+                          nrhs, ldv, _ptr(U), U.shape[1], _stream_handle()))
+    U = U[:, : a.numel()].t()
+    return U[:, 0] if V.dim() == 1 else U
+
+
+def gvt_pairwise_matvec(kinds, D, T, out_pairs, in_pairs, V, prec=None, flags=0):
+    """Returns U of shape (nkinds, n_out[, nrhs])."""
+    torch = _torch()
+    lib = load_library()
+    codes = _kind_codes(kinds)
+    karr = (ctypes.c_int * len(codes))(*codes)
+    p = _prec_of(D.dtype, prec)
+    a, b = _idx(out_pairs[0]), _idx(out_pairs[1])
+    c, e = _idx(in_pairs[0]), _idx(in_pairs[1])
+    V2, ldv = _colmajor(V)
+    nrhs = V2.shape[1]
+    Tm = T if T is not None else D
+    U = torch.empty((len(codes), nrhs, max(a.numel(), 1)), dtype=D.dtype, device=D.device)
+    _check(lib.gvt_pairwise_matvec(p, karr, len(codes), _ptr(D), D.shape[0], D.shape[1], _ld(D),
+                                   _ptr(Tm), Tm.shape[0], Tm.shape[1], _ld(Tm), _ptr(a), _ptr(b),
+                                   a.numel(), _ptr(c), _ptr(e), c.numel(), _ptr(V2), nrhs, ldv,
+                                   _ptr(U), U.shape[2], int(flags), _stream_handle()))
+    res = U[:, :, : a.numel()].transpose(1, 2)
+    return res[:, :, 0] if V.dim() == 1 else res
+
+
+def gvt_dense_matvec(M, N, Vmat, prec=None, out=None):
+    """Umat = M Vmat N^T on matrix cores (complete data)."""
+    torch = _torch()
+    lib = load_library()
+    p = _prec_of(M.dtype, prec)
+    U = out if out is not None else torch.empty((M.shape[0], N.shape[0]), dtype=M.dtype, device=M.device)
+    _check(lib.gvt_dense_matvec(p, _ptr(M), M.shape[0], M.shape[1], _ld(M), _ptr(N), N.shape[0],
+                                N.shape[1], _ld(N), _ptr(Vmat), _ld(Vmat), _ptr(U), _ld(U),
+                                _stream_handle()))
+    return U
+
+
+def gvt_krr_cg(kind, D, T, pairs, y, lambdas, max_iter=200, tol=1e-6, matvec_prec=F64,
+               check_every=8, A0=None, out=None):
+    """Ridge CG.  Returns (A[n, nlam], iters[nlam], true_relres[nlam], status)."""
+    torch = _torch()
+    lib = load_library()
+    code = _kind_codes(kind)[0]
+    c, e = _idx(pairs[0]), _idx(pairs[1])
+    lam = np.ascontiguousarray(np.atleast_1d(np.asarray(lambdas, dtype=np.float64)))
+    nlam = len(lam)
+    n = c.numel()
+    A = out if out is not None else torch.empty((nlam, n), dtype=torch.float64, device=D.device)
+    iters = np.zeros(nlam, dtype=np.int64)
+    rel = np.zeros(nlam, dtype=np.float64)
+    Tm = T if T is not None else D
+    A0p = _ptr(A0) if A0 is not None else ctypes.c_void_p(0)
+    lda0 = A0.stride(0) if A0 is not None else n
+    rc = lib.gvt_krr_cg(code, _ptr(D), D.shape[0], _ld(D), _ptr(Tm), Tm.shape[0], _ld(Tm), _ptr(c), _ptr(e),
+                        n, _ptr(y), lam.ctypes.data_as(ctypes.c_void_p), nlam, _ptr(A), A.stride(0), A0p,
+                        lda0, int(max_iter), float(tol), int(matvec_prec), int(check_every),
+                        iters.ctypes.data_as(ctypes.c_void_p), rel.ctypes.data_as(ctypes.c_void_p),
+                        _stream_handle())
+    _check(rc)
+    return A.t(), iters, rel, rc

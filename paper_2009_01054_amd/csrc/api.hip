@@ -1,0 +1,139 @@
+// extern "C" entry points declared in include/gvt.h.
+#include <cstdarg>
+
+#include "plan.h"
+
+namespace gvt {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+void clear_error() { g_last_error.clear(); }
+
+int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double *T, int64_t t,
+                int64_t ldt, const int32_t *c, const int32_t *e, int64_t n, const double *y,
+                const double *lambdas, int nlam, double *A, int64_t lda, const double *A0,
+                int64_t lda0, int max_iter, double tol, int mprec, int check_every,
+                int64_t *iters_out, double *relres_out, hipStream_t s);
+
+}  // namespace gvt
+
+using namespace gvt;
+
+extern "C" {
+
+const char *gvt_last_error(void) { return g_last_error.c_str(); }
+
+int gvt_version(void) { return 100; }
+
+int gvt_plan_create(gvt_plan_t *plan, const int *kinds, int nkinds, int64_t d_rows, int64_t d_cols,
+                    int64_t t_rows, int64_t t_cols, const int32_t *out_a, const int32_t *out_b,
+                    int64_t n_out, const int32_t *in_c, const int32_t *in_e, int64_t n_in,
+                    int flags, void *stream) {
+  return guarded([&]() {
+    GVT_REQUIRE(plan, GVT_ERR_ARG, "null plan pointer");
+    *plan = nullptr;
+    gvt_plan *P = new gvt_plan();
+    try {
+      plan_build(P, kinds, nkinds, d_rows, d_cols, t_rows, t_cols, out_a, out_b, n_out, in_c, in_e,
+                 n_in, flags, (hipStream_t)stream);
+      GVT_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
+    } catch (...) {
+      delete P;
+      throw;
+    }
+    *plan = P;
+    return GVT_OK;
+  });
+}
+
+int gvt_plan_destroy(gvt_plan_t plan) {
+  return guarded([&]() {
+    if (!plan) return GVT_OK;
+    (void)hipStreamSynchronize(plan->last_stream);
+    delete plan;
+    return GVT_OK;
+  });
+}
+
+int gvt_plan_execute(gvt_plan_t plan, int prec, const void *D, int64_t ldd, const void *T,
+                     int64_t ldt, const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu,
+                     void *stream) {
+  return guarded([&]() {
+    plan_execute(plan, prec, D, ldd, T, ldt, V, nrhs, ldv, U, ldu, (hipStream_t)stream);
+    return GVT_OK;
+  });
+}
+
+static int oneshot(int prec, const int *kinds, int nkinds, const void *D, int64_t d_rows,
+                   int64_t d_cols, int64_t ldd, const void *T, int64_t t_rows, int64_t t_cols,
+                   int64_t ldt, const int32_t *out_a, const int32_t *out_b, int64_t n_out,
+                   const int32_t *in_c, const int32_t *in_e, int64_t n_in, const void *V,
+                   int64_t nrhs, int64_t ldv, void *U, int64_t ldu, int flags, void *stream) {
+  return guarded([&]() {
+    hipStream_t s = (hipStream_t)stream;
+    gvt_plan P;
+    plan_build(&P, kinds, nkinds, d_rows, d_cols, t_rows, t_cols, out_a, out_b, n_out, in_c, in_e,
+               n_in, flags, s);
+    plan_execute(&P, prec, D, ldd, T, ldt, V, nrhs, ldv, U, ldu, s);
+    GVT_HIP_CHECK(hipStreamSynchronize(s));
+    return GVT_OK;
+  });
+}
+
+int gvt_matvec(int prec, const void *M, int64_t m_rows, int64_t m_cols, int64_t ldm, const void *N,
+               int64_t n_rows, int64_t n_cols, int64_t ldn, const int32_t *out_a,
+               const int32_t *out_b, int64_t n_out, const int32_t *in_c, const int32_t *in_e,
+               int64_t n_in, const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu,
+               void *stream) {
+  const int kind = GVT_KRONECKER;
+  return oneshot(prec, &kind, 1, M, m_rows, m_cols, ldm, N, n_rows, n_cols, ldn, out_a, out_b,
+                 n_out, in_c, in_e, n_in, V, nrhs, ldv, U, ldu, 0, stream);
+}
+
+int gvt_pairwise_matvec(int prec, const int *kinds, int nkinds, const void *D, int64_t d_rows,
+                        int64_t d_cols, int64_t ldd, const void *T, int64_t t_rows, int64_t t_cols,
+                        int64_t ldt, const int32_t *out_a, const int32_t *out_b, int64_t n_out,
+                        const int32_t *in_c, const int32_t *in_e, int64_t n_in, const void *V,
+                        int64_t nrhs, int64_t ldv, void *U, int64_t ldu, int flags, void *stream) {
+  return oneshot(prec, kinds, nkinds, D, d_rows, d_cols, ldd, T, t_rows, t_cols, ldt, out_a, out_b,
+                 n_out, in_c, in_e, n_in, V, nrhs, ldv, U, ldu, flags, stream);
+}
+
+int gvt_dense_matvec(int prec, const void *M, int64_t m_rows, int64_t m_cols, int64_t ldm,
+                     const void *N, int64_t n_rows, int64_t n_cols, int64_t ldn, const void *V,
+                     int64_t ldv, void *U, int64_t ldu, void *stream) {
+  return guarded([&]() {
+    GVT_REQUIRE(prec == GVT_F64 || prec == GVT_F32 || prec == GVT_BF16X3 || prec == GVT_BF16X6, GVT_ERR_ARG,
+                "unknown precision");
+    GVT_REQUIRE(m_rows >= 0 && m_cols >= 0 && n_rows >= 0 && n_cols >= 0, GVT_ERR_ARG,
+                "negative size");
+    GVT_REQUIRE(ldm >= m_cols && ldn >= n_cols && ldv >= n_cols && ldu >= n_rows, GVT_ERR_ARG,
+                "leading dimension too small");
+    GVT_REQUIRE((m_rows == 0 || n_rows == 0) || (M && N && V && U), GVT_ERR_ARG, "null pointer");
+    dense_matvec(prec, M, m_rows, m_cols, ldm, N, n_rows, n_cols, ldn, V, ldv, U, ldu,
+                 (hipStream_t)stream);
+    return GVT_OK;
+  });
+}
+
+int gvt_krr_cg(int kind, const double *D, int64_t d, int64_t ldd, const double *T, int64_t t,
+               int64_t ldt, const int32_t *c, const int32_t *e, int64_t n, const double *y,
+               const double *lambdas, int nlam, double *A, int64_t lda, const double *A0,
+               int64_t lda0, int max_iter, double tol, int matvec_prec, int check_every,
+               int64_t *iters_out, double *relres_out, void *stream) {
+  return guarded([&]() {
+    return krr_cg_impl(kind, D, d, ldd, T, t, ldt, c, e, n, y, lambdas, nlam, A, lda, A0, lda0,
+                       max_iter, tol, matvec_prec, check_every, iters_out, relres_out,
+                       (hipStream_t)stream);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Internal helpers shared by the library's translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "gvt.h"
+
+namespace gvt {
+
+// ---- error reporting ------------------------------------------------------
+void set_error(const char *fmt, ...);
+void clear_error();
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define GVT_HIP_CHECK(expr)                                                              \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) {                                                              \
+      throw ::gvt::Error{GVT_ERR_HIP,                                                    \
+                         std::string(#expr) + ": " + hipGetErrorString(e_)};             \
+    }                                                                                    \
+  } while (0)
+
+#define GVT_REQUIRE(cond, code, what)                                                    \
+  do {                                                                                   \
+    if (!(cond)) throw ::gvt::Error{(code), (what)};                                     \
+  } while (0)
+
+// Run `body` and convert exceptions into a status code + message.
+template <class F> int guarded(F &&body) {
+  try {
+    clear_error();
+    return body();
+  } catch (const Error &e) {
+    set_error("%s", e.msg.c_str());
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    set_error("host allocation failed");
+    return GVT_ERR_NOMEM;
+  } catch (...) {
+    set_error("unexpected internal error");
+    return GVT_ERR_HIP;
+  }
+}
+
+// ---- device memory ----------------------------------------------------------
+struct DevMem {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem &) = delete;
+  DevMem &operator=(const DevMem &) = delete;
+  DevMem(DevMem &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevMem &operator=(DevMem &&o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevMem() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // Grow-only; contents are not preserved.
+  void *ensure(size_t nbytes) {
+    if (nbytes <= bytes && p) return p;
+    release();
+    size_t want = nbytes ? nbytes : 256;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{GVT_ERR_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed"};
+    }
+    bytes = want;
+    return p;
+  }
+  template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Blocking copy: plan data comes from short-lived host vectors.
+template <class T> void upload(DevMem &m, const std::vector<T> &h, hipStream_t) {
+  m.ensure(h.size() * sizeof(T));
+  if (!h.empty()) GVT_HIP_CHECK(hipMemcpy(m.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Report a failed launch, except while `s` is being captured into a graph
+// (the runtime refuses error polling then; the capture itself reports it).
+inline void check_launch(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (s && hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return;
+  GVT_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace gvt

@@ -1,0 +1,98 @@
+// Plan object: index preprocessing + the per-kind Kronecker term program.
+#pragma once
+
+#include <array>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace gvt {
+
+// Index selectors: output-side a, b; input-side c, e.
+enum Sel { SA = 0, SB = 1, SC = 2, SE = 3 };
+// Base matrices.
+enum Mat { FD = 0, FT = 1 };
+
+struct InputSort {  // input pairs sorted (stably) by one index: key segments
+  bool built = false;
+  int64_t nkeys = 0;
+  DevMem perm;   // int32[n_in]: sorted position -> input index j
+  DevMem other;  // int32[n_in]: the other index of the pair at that position
+  DevMem seg;    // int64[nkeys + 1]: segment offsets
+};
+
+struct OutOrder {  // output pairs grouped by one output-side index
+  bool built = false;
+  std::vector<int32_t> h_perm;
+  DevMem perm;  // int32[n_out]: position -> output index i
+  DevMem xs;    // int32[n_out]: the grouping index at that position
+};
+
+struct SBufSpec {  // one stage-1 result S = scatter of F_sc by `key` with column index `other`
+  int fsc = FD, key = SC, other = SE;
+  bool degenerate = false;       // key == other: S[y, k] = F[y, k] * segsum[k]
+  std::vector<int32_t> rowmap;   // F_sc row -> compact S row (-1: not needed)
+  std::vector<int32_t> rows;     // compact S rows -> F_sc row
+  DevMem d_rows;
+};
+
+enum TermType { TG = 0, TO = 1, TM = 2 };
+
+struct TermSpec {
+  int type = TG;
+  // G (two-factor Kronecker term):  u_i = sum_k F_dot[x_i, k] S[y_i, k]
+  int fdot = FD, x = SA, y = SB, sbuf = -1;
+  DevMem yrows;  // int32[n_out] in OutOrder[x] order: compact S row of y_i
+  // O (one-factor term):  u_i = g[x_i], g = F^{o(1|2)} segsum_key
+  int gemv = -1;
+  // M (Cartesian sparse match):  u_i = sum_{j: key_j = outkey_i} F[x_i, other_j] v_j
+  int f = FD, outkey = SB, key = SE;
+  bool operator==(const TermSpec &) const = delete;
+};
+
+struct GemvSpec {
+  int f = FD, sq = 0, key = SC;
+};
+
+struct Workspace {
+  DevMem pool;
+  size_t need = 0;
+  int R = 0;
+  // offsets into pool (bytes); -1 = unused
+  std::array<int64_t, 2> vs{{-1, -1}}, sv{{-1, -1}}, trans{{-1, -1}};
+  std::vector<int64_t> sbuf, gemv, tvec;
+};
+
+}  // namespace gvt
+
+struct gvt_plan {
+  std::vector<int> kinds;
+  bool homogeneous = false;
+  bool dense = false;
+  int flags = 0;
+  int64_t d_rows = 0, d_cols = 0, t_rows = 0, t_cols = 0, n_out = 0, n_in = 0;
+  std::array<int64_t, 4> uniq{{0, 0, 0, 0}};
+  gvt::DevMem idx[4];  // device copies of a, b, c, e (int32)
+  gvt::InputSort insort[2];   // [0]: by c (other = e), [1]: by e (other = c)
+  gvt::OutOrder outord[2];    // [0]: grouped by a, [1]: grouped by b
+  std::vector<gvt::SBufSpec> sbufs;
+  std::vector<gvt::GemvSpec> gemvs;
+  std::vector<gvt::TermSpec> terms;
+  std::vector<std::vector<std::pair<int, double>>> outputs;  // per kind: (term, coef)
+  bool direct = false;  // single kind, single G term with coefficient 1
+  gvt::Workspace ws[2];  // per precision (F64, F32)
+  hipStream_t last_stream = nullptr;
+  // Theorem 1 cost of the chosen term program (FMA count per RHS), for reporting
+  double cost_fma = 0.0;
+};
+
+namespace gvt {
+int64_t rows_of(const gvt_plan *P, int f);
+int64_t cols_of(const gvt_plan *P, int f);
+int64_t nkeys_of(const gvt_plan *P, int key);
+void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64_t d_cols,
+                int64_t t_rows, int64_t t_cols, const int32_t *a, const int32_t *b, int64_t n_out,
+                const int32_t *c, const int32_t *e, int64_t n_in, int flags, hipStream_t s);
+void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,
+                  const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu, hipStream_t s);
+}  // namespace gvt

@@ -1,0 +1,541 @@
+// Plan construction and execution.
+//
+// A plan turns (kinds, base-matrix shapes, output pairs, input pairs) into a
+// term program: Corollary 1 writes every pairwise kernel as a sum of
+// Kronecker products whose index selectors come from the commutation and
+// unification rules R(d,t)P = R(t,d), R(d,t)Q = R(d,d).  Each two-factor term
+// is applied with the generalized vec trick (Theorem 1) in whichever stage
+// order is cheaper; one-factor terms (a base matrix times an all-ones
+// factor) collapse to segment sums, a GEMV and a gather; the Cartesian
+// kernel's identity factors become sparse key matches.  Identical stage-1
+// scatters, segment sums, GEMVs and terms are shared across all kinds of the
+// plan.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "plan.h"
+
+namespace gvt {
+
+int64_t rows_of(const gvt_plan *P, int f) { return f == FD ? P->d_rows : P->t_rows; }
+int64_t cols_of(const gvt_plan *P, int f) { return f == FD ? P->d_cols : P->t_cols; }
+int64_t nkeys_of(const gvt_plan *P, int key) { return key == SC ? P->d_cols : P->t_cols; }
+
+static bool kind_homogeneous(int k) {
+  return k == GVT_SYMMETRIC || k == GVT_ANTISYMMETRIC || k == GVT_RANKING || k == GVT_MLPK;
+}
+
+namespace {
+
+struct RawTerm {
+  int type;
+  int a0, a1, a2, a3, a4, a5;  // meaning depends on type
+  bool operator<(const RawTerm &o) const {
+    return std::tie(type, a0, a1, a2, a3, a4, a5) <
+           std::tie(o.type, o.a0, o.a1, o.a2, o.a3, o.a4, o.a5);
+  }
+};
+
+// G(fdot, fsc; x, y; key, other): u_i = sum_j fdot[x_i, key_j] fsc[y_i, other_j] v_j
+RawTerm G(int fdot, int fsc, int x, int y, int key, int other) {
+  return RawTerm{TG, fdot, fsc, x, y, key, other};
+}
+// O(f, sq; x, key): u_i = sum_j f[x_i, key_j]^{1|2} v_j
+RawTerm O(int f, int sq, int x, int key) { return RawTerm{TO, f, sq, x, key, 0, 0}; }
+// M(f; x, outkey, key, other): u_i = sum_{j: key_j == outkey_i} f[x_i, other_j] v_j
+RawTerm M(int f, int x, int outkey, int key, int other) {
+  return RawTerm{TM, f, x, outkey, key, other, 0};
+}
+
+// Corollary 1 term lists (readings: anti-symmetric follows the sign of its
+// Table 4b function, i.e. (I - P)(D x D); MLPK uses (I - Q)^T on the right).
+std::vector<std::pair<RawTerm, double>> expand_kind(int kind, bool hom) {
+  const int FTm = hom ? FD : FT;
+  switch (kind) {
+    case GVT_KRONECKER:  // D (x) T
+      return {{G(FD, FTm, SA, SB, SC, SE), 1.0}};
+    case GVT_LINEAR:  // D (x) 1 + 1 (x) T
+      return {{O(FD, 0, SA, SC), 1.0}, {O(FTm, 0, SB, SE), 1.0}};
+    case GVT_POLY2D:  // Q(D x D)Q^T + 2 D x T + PQ(T x T)Q^T P
+      return {{O(FD, 1, SA, SC), 1.0}, {G(FD, FTm, SA, SB, SC, SE), 2.0}, {O(FTm, 1, SB, SE), 1.0}};
+    case GVT_CARTESIAN:  // D (x) I + I (x) T
+      return {{M(FD, SA, SB, SE, SC), 1.0}, {M(FTm, SB, SA, SC, SE), 1.0}};
+    case GVT_SYMMETRIC:  // (P + I)(D x D)
+      return {{G(FD, FD, SA, SB, SC, SE), 1.0}, {G(FD, FD, SB, SA, SC, SE), 1.0}};
+    case GVT_ANTISYMMETRIC:  // (I - P)(D x D)
+      return {{G(FD, FD, SA, SB, SC, SE), 1.0}, {G(FD, FD, SB, SA, SC, SE), -1.0}};
+    case GVT_RANKING:  // (I - P)(D x 1)(I - P)
+      return {{O(FD, 0, SA, SC), 1.0}, {O(FD, 0, SA, SE), -1.0},
+              {O(FD, 0, SB, SC), -1.0}, {O(FD, 0, SB, SE), 1.0}};
+    case GVT_MLPK:  // (I + P)(I - Q)(D x D)(I - Q)^T(I + P), ten terms
+      return {{O(FD, 1, SA, SC), 1.0},  {O(FD, 1, SA, SE), 1.0},
+              {O(FD, 1, SB, SC), 1.0},  {O(FD, 1, SB, SE), 1.0},
+              {G(FD, FD, SA, SB, SC, SE), 2.0},  {G(FD, FD, SB, SA, SC, SE), 2.0},
+              {G(FD, FD, SA, SA, SC, SE), -2.0}, {G(FD, FD, SA, SB, SC, SC), -2.0},
+              {G(FD, FD, SB, SB, SC, SE), -2.0}, {G(FD, FD, SA, SB, SE, SE), -2.0}};
+    default:
+      throw Error{GVT_ERR_ARG, "unknown kind " + std::to_string(kind)};
+  }
+}
+
+void counting_sort(const std::vector<int32_t> &key, int64_t nkeys, std::vector<int32_t> &perm,
+                   std::vector<int64_t> &seg) {
+  const int64_t n = (int64_t)key.size();
+  seg.assign(nkeys + 1, 0);
+  for (int64_t j = 0; j < n; ++j) seg[key[j] + 1]++;
+  for (int64_t k = 0; k < nkeys; ++k) seg[k + 1] += seg[k];
+  std::vector<int64_t> pos(seg.begin(), seg.end() - 1);
+  perm.resize(n);
+  for (int64_t j = 0; j < n; ++j) perm[pos[key[j]]++] = (int32_t)j;
+}
+
+int64_t count_unique(const std::vector<int32_t> &v, int64_t range) {
+  std::vector<char> seen(range, 0);
+  int64_t u = 0;
+  for (int32_t x : v)
+    if (!seen[x]) { seen[x] = 1; ++u; }
+  return u;
+}
+
+}  // namespace
+
+void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64_t d_cols,
+                int64_t t_rows, int64_t t_cols, const int32_t *a, const int32_t *b, int64_t n_out,
+                const int32_t *c, const int32_t *e, int64_t n_in, int flags, hipStream_t s) {
+  GVT_REQUIRE(kinds && nkinds >= 1, GVT_ERR_ARG, "kinds must be a non-empty host array");
+  GVT_REQUIRE(nkinds <= kMaxCombineOut, GVT_ERR_ARG, "at most 8 kinds per plan");
+  GVT_REQUIRE(d_rows >= 0 && d_cols >= 0 && t_rows >= 0 && t_cols >= 0 && n_out >= 0 && n_in >= 0,
+              GVT_ERR_ARG, "negative size");
+  GVT_REQUIRE(n_out <= INT32_MAX && n_in <= INT32_MAX, GVT_ERR_ARG, "too many pairs for int32 positions");
+  GVT_REQUIRE((n_out == 0 || (a && b)) && (n_in == 0 || (c && e)), GVT_ERR_ARG, "null index array");
+  GVT_REQUIRE(!((flags & GVT_FLAG_ORDER_A) && (flags & GVT_FLAG_ORDER_B)), GVT_ERR_ARG,
+              "ORDER_A and ORDER_B are exclusive");
+  P->kinds.assign(kinds, kinds + nkinds);
+  P->flags = flags;
+  bool hom = false;
+  for (int k : P->kinds) {
+    GVT_REQUIRE(k >= GVT_KRONECKER && k <= GVT_MLPK, GVT_ERR_ARG, "unknown kind");
+    hom = hom || kind_homogeneous(k);
+  }
+  if (hom) {
+    GVT_REQUIRE(t_rows == d_rows && t_cols == d_cols, GVT_ERR_KIND,
+                "homogeneous kinds need T with the shape of D (T is taken to be D)");
+  }
+  if (flags & GVT_FLAG_SYMMETRIC_BASES) {
+    GVT_REQUIRE(d_rows == d_cols && t_rows == t_cols, GVT_ERR_KIND,
+                "GVT_FLAG_SYMMETRIC_BASES needs square base matrices");
+  }
+  P->homogeneous = hom;
+  P->d_rows = d_rows; P->d_cols = d_cols; P->t_rows = t_rows; P->t_cols = t_cols;
+  P->n_out = n_out; P->n_in = n_in;
+  P->last_stream = s;
+
+  // ---- indices to host, validation, unique counts (Table 1) -------------
+  std::vector<int32_t> h[4];
+  const int32_t *src[4] = {a, b, c, e};
+  const int64_t cnt[4] = {n_out, n_out, n_in, n_in};
+  const int64_t lim[4] = {d_rows, t_rows, d_cols, t_cols};
+  for (int i = 0; i < 4; ++i) {
+    h[i].resize(cnt[i]);
+    if (cnt[i])
+      GVT_HIP_CHECK(hipMemcpyAsync(h[i].data(), src[i], cnt[i] * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, s));
+  }
+  GVT_HIP_CHECK(hipStreamSynchronize(s));
+  static const char *nm[4] = {"out_a", "out_b", "in_c", "in_e"};
+  for (int i = 0; i < 4; ++i) {
+    for (int64_t j = 0; j < cnt[i]; ++j) {
+      const int32_t v = h[i][j];
+      if (v < 0 || v >= lim[i])
+        throw Error{GVT_ERR_INDEX, std::string(nm[i]) + "[" + std::to_string(j) + "] = " +
+                                       std::to_string(v) + " outside [0, " +
+                                       std::to_string(lim[i]) + ")"};
+    }
+    P->uniq[i] = count_unique(h[i], lim[i]);
+    upload(P->idx[i], h[i], s);
+  }
+
+  // ---- complete data: both pair sets are the full grid in natural order ----
+  if (nkinds == 1 && P->kinds[0] == GVT_KRONECKER && n_in == d_cols * t_cols &&
+      n_out == d_rows * t_rows && n_in > 0 && n_out > 0) {
+    bool nat = true;
+    for (int64_t j = 0; j < n_in && nat; ++j)
+      nat = h[2][j] == (int32_t)(j / t_cols) && h[3][j] == (int32_t)(j % t_cols);
+    for (int64_t i = 0; i < n_out && nat; ++i)
+      nat = h[0][i] == (int32_t)(i / t_rows) && h[1][i] == (int32_t)(i % t_rows);
+    P->dense = nat;
+  }
+  if (P->dense) {
+    P->outputs.assign(1, {});
+    P->cost_fma = (double)d_rows * d_cols * t_cols + (double)d_rows * t_cols * t_rows;
+    return;
+  }
+
+  // ---- term expansion, stage-order choice, common subexpressions ----------
+  const double n_in_d = (double)n_in, n_out_d = (double)n_out;
+  auto selval_uniq = [&](int sel) { return (double)P->uniq[sel]; };
+  std::map<std::tuple<int, int, int>, int> sbuf_index;  // (fsc, key, other) -> sbuf
+  std::map<RawTerm, int> term_index;
+  std::map<std::tuple<int, int, int>, int> gemv_index;
+  std::vector<RawTerm> raw_terms;
+
+  auto g_cost = [&](const RawTerm &t) {
+    const int y = t.a3, key = t.a4, other = t.a5;
+    const double s1 = (key == other) ? selval_uniq(y) * (double)nkeys_of(P, key)
+                                     : selval_uniq(y) * n_in_d;
+    return s1 + n_out_d * (double)nkeys_of(P, key);
+  };
+  const int prefer_key = (flags & GVT_FLAG_ORDER_A) ? SC
+                         : (flags & GVT_FLAG_ORDER_B) ? SE
+                         : (d_cols >= t_cols ? SC : SE);
+  const bool forced = (flags & (GVT_FLAG_ORDER_A | GVT_FLAG_ORDER_B)) != 0;
+
+  auto canon_g = [&](RawTerm t) {
+    // the same term with the two Kronecker factors exchanged (Lemma: P(D x T)P^T = T x D)
+    RawTerm sw = G(t.a1, t.a0, t.a3, t.a2, t.a5, t.a4);
+    if (forced) {
+      if (t.a4 == prefer_key) return t;
+      if (sw.a4 == prefer_key) return sw;
+      return t;
+    }
+    double c1 = g_cost(t), c2 = g_cost(sw);
+    if (c1 < c2) return t;
+    if (c2 < c1) return sw;
+    const bool has1 = sbuf_index.count({t.a1, t.a4, t.a5}) > 0;
+    const bool has2 = sbuf_index.count({sw.a1, sw.a4, sw.a5}) > 0;
+    if (has1 != has2) return has1 ? t : sw;
+    if (t.a4 == prefer_key) return t;
+    if (sw.a4 == prefer_key) return sw;
+    return t;
+  };
+
+  P->outputs.assign(nkinds, {});
+  for (int kk = 0; kk < nkinds; ++kk) {
+    for (auto &tc : expand_kind(P->kinds[kk], hom)) {
+      RawTerm t = tc.first;
+      if (t.type == TG) {
+        t = canon_g(t);
+        sbuf_index.emplace(std::make_tuple(t.a1, t.a4, t.a5), (int)sbuf_index.size());
+      }
+      auto it = term_index.find(t);
+      int id;
+      if (it == term_index.end()) {
+        id = (int)raw_terms.size();
+        term_index.emplace(t, id);
+        raw_terms.push_back(t);
+      } else {
+        id = it->second;
+      }
+      // merge repeated terms within a kind
+      bool merged = false;
+      for (auto &oc : P->outputs[kk])
+        if (oc.first == id) { oc.second += tc.second; merged = true; }
+      if (!merged) P->outputs[kk].push_back({id, tc.second});
+    }
+  }
+
+  // ---- materialise sorts, S buffers, gemvs and terms ----------------------
+  auto sel_host = [&](int sel) -> const std::vector<int32_t> & { return h[sel]; };
+  auto sel_dev = [&](int sel) -> const int32_t * { return P->idx[sel].as<int32_t>(); };
+  auto need_insort = [&](int key) {
+    InputSort &is = P->insort[key == SC ? 0 : 1];
+    if (is.built) return;
+    is.nkeys = nkeys_of(P, key);
+    std::vector<int32_t> perm;
+    std::vector<int64_t> seg;
+    counting_sort(h[key], is.nkeys, perm, seg);
+    std::vector<int32_t> oth(n_in);
+    const std::vector<int32_t> &ov = h[key == SC ? SE : SC];
+    for (int64_t p = 0; p < n_in; ++p) oth[p] = ov[perm[p]];
+    upload(is.perm, perm, s);
+    upload(is.other, oth, s);
+    upload(is.seg, seg, s);
+    is.built = true;
+  };
+  auto need_outord = [&](int x) {
+    OutOrder &oo = P->outord[x == SA ? 0 : 1];
+    if (oo.built) return;
+    const int64_t nk = (x == SA) ? d_rows : t_rows;
+    std::vector<int64_t> seg;
+    counting_sort(h[x], nk, oo.h_perm, seg);
+    std::vector<int32_t> xs(n_out);
+    for (int64_t q = 0; q < n_out; ++q) xs[q] = h[x][oo.h_perm[q]];
+    upload(oo.perm, oo.h_perm, s);
+    upload(oo.xs, xs, s);
+    oo.built = true;
+  };
+
+  // S buffers in creation order
+  P->sbufs.resize(sbuf_index.size());
+  for (auto &kv : sbuf_index) {
+    SBufSpec &sb = P->sbufs[kv.second];
+    std::tie(sb.fsc, sb.key, sb.other) = kv.first;
+    sb.degenerate = sb.key == sb.other;
+    sb.rowmap.assign(rows_of(P, sb.fsc), -1);
+  }
+  // rows needed per S buffer
+  for (const RawTerm &t : raw_terms) {
+    if (t.type != TG) continue;
+    SBufSpec &sb = P->sbufs[sbuf_index.at({t.a1, t.a4, t.a5})];
+    for (int32_t v : sel_host(t.a3)) sb.rowmap[v] = 0;
+  }
+  for (SBufSpec &sb : P->sbufs) {
+    sb.rows.clear();
+    for (int64_t r = 0; r < (int64_t)sb.rowmap.size(); ++r)
+      if (sb.rowmap[r] >= 0) { sb.rowmap[r] = (int32_t)sb.rows.size(); sb.rows.push_back((int32_t)r); }
+    upload(sb.d_rows, sb.rows, s);
+    if (sb.degenerate) need_insort(sb.key);  // for its segment sums
+    else need_insort(sb.key);
+  }
+
+  P->terms.resize(raw_terms.size());
+  P->cost_fma = 0.0;
+  for (size_t ti = 0; ti < raw_terms.size(); ++ti) {
+    const RawTerm &t = raw_terms[ti];
+    TermSpec &ts = P->terms[ti];
+    ts.type = t.type;
+    if (t.type == TG) {
+      ts.fdot = t.a0; ts.x = t.a2; ts.y = t.a3;
+      ts.sbuf = sbuf_index.at({t.a1, t.a4, t.a5});
+      need_outord(ts.x);
+      const OutOrder &oo = P->outord[ts.x == SA ? 0 : 1];
+      const SBufSpec &sb = P->sbufs[ts.sbuf];
+      std::vector<int32_t> yr(n_out);
+      for (int64_t q = 0; q < n_out; ++q) yr[q] = sb.rowmap[h[ts.y][oo.h_perm[q]]];
+      upload(ts.yrows, yr, s);
+      P->cost_fma += g_cost(t);
+    } else if (t.type == TO) {
+      auto gk = std::make_tuple(t.a0, t.a1, t.a3);
+      auto it = gemv_index.find(gk);
+      if (it == gemv_index.end()) {
+        it = gemv_index.emplace(gk, (int)P->gemvs.size()).first;
+        P->gemvs.push_back(GemvSpec{t.a0, t.a1, t.a3});
+        need_insort(t.a3);
+        P->cost_fma += (double)rows_of(P, t.a0) * (double)nkeys_of(P, t.a3) + n_in_d;
+      }
+      ts.gemv = it->second;
+      ts.f = t.a0; ts.x = t.a2;
+    } else {
+      ts.f = t.a0; ts.x = t.a1; ts.outkey = t.a2; ts.key = t.a3;
+      need_insort(ts.key);
+      P->cost_fma += n_out_d * (n_in_d / std::max<double>(1.0, (double)nkeys_of(P, ts.key)));
+    }
+  }
+  // S-buffer stage-1 cost (shared scatters counted once)
+  for (const SBufSpec &sb : P->sbufs)
+    P->cost_fma += sb.degenerate ? (double)sb.rows.size() * nkeys_of(P, sb.key)
+                                 : (double)sb.rows.size() * n_in_d;
+  // stage-2 costs were included in g_cost together with a per-term stage-1; remove those
+  for (const RawTerm &t : raw_terms)
+    if (t.type == TG) {
+      const int y = t.a3, key = t.a4, other = t.a5;
+      P->cost_fma -= (key == other) ? selval_uniq(y) * (double)nkeys_of(P, key)
+                                    : selval_uniq(y) * n_in_d;
+    }
+  P->direct = nkinds == 1 && P->outputs[0].size() == 1 && P->outputs[0][0].second == 1.0 &&
+              P->terms[P->outputs[0][0].first].type == TG;
+  for (auto &o : P->outputs)
+    GVT_REQUIRE(o.size() <= (size_t)kMaxCombineTerms, GVT_ERR_ARG, "too many terms");
+  GVT_REQUIRE(P->terms.size() <= (size_t)kMaxCombineTerms, GVT_ERR_ARG,
+              "the kinds of one plan may use at most 16 distinct terms");
+  (void)sel_dev;
+}
+
+// ---------------------------------------------------------------------------
+namespace {
+
+template <class T> int prec_slot() { return sizeof(T) == 8 ? 0 : 1; }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <class T> void layout_workspace(gvt_plan *P, int R) {
+  Workspace &W = P->ws[prec_slot<T>()];
+  if (W.R == R && W.need) return;
+  size_t off = 0;
+  auto take = [&](size_t elems) {
+    const size_t o = off;
+    off = align256(off + elems * sizeof(T));
+    return (int64_t)o;
+  };
+  W.vs = {-1, -1};
+  W.sv = {-1, -1};
+  W.trans = {-1, -1};
+  for (int k = 0; k < 2; ++k)
+    if (P->insort[k].built) {
+      W.vs[k] = take((size_t)P->n_in * R);
+      W.sv[k] = take((size_t)P->insort[k].nkeys * R);
+    }
+  if (!(P->flags & GVT_FLAG_SYMMETRIC_BASES)) {
+    for (const SBufSpec &sb : P->sbufs)
+      if (!sb.degenerate && W.trans[sb.fsc] < 0)
+        W.trans[sb.fsc] = take((size_t)rows_of(P, sb.fsc) * cols_of(P, sb.fsc));
+  }
+  W.sbuf.assign(P->sbufs.size(), -1);
+  for (size_t i = 0; i < P->sbufs.size(); ++i)
+    W.sbuf[i] = take(P->sbufs[i].rows.size() * (size_t)nkeys_of(P, P->sbufs[i].key) * R);
+  W.gemv.assign(P->gemvs.size(), -1);
+  for (size_t i = 0; i < P->gemvs.size(); ++i) W.gemv[i] = take((size_t)rows_of(P, P->gemvs[i].f) * R);
+  W.tvec.assign(P->terms.size(), -1);
+  if (!P->direct)
+    for (size_t i = 0; i < P->terms.size(); ++i) W.tvec[i] = take((size_t)P->n_out * R);
+  W.need = off;
+  W.R = R;
+  W.pool.ensure(off);
+}
+
+template <class T> T *wsp(gvt_plan *P, int64_t off) {
+  return off < 0 ? nullptr
+                 : reinterpret_cast<T *>(static_cast<char *>(P->ws[prec_slot<T>()].pool.p) + off);
+}
+
+template <class T>
+void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ldt, const T *V,
+                   int R, int64_t ldv, T *U, int64_t ldu, int64_t block_stride, hipStream_t s) {
+  layout_workspace<T>(P, R);
+  Workspace &W = P->ws[prec_slot<T>()];
+  const T *F[2] = {D, P->homogeneous ? D : Tm};
+  const int64_t ldF[2] = {ldd, P->homogeneous ? ldd : ldt};
+  const int32_t *dev_sel[4] = {P->idx[0].as<int32_t>(), P->idx[1].as<int32_t>(),
+                               P->idx[2].as<int32_t>(), P->idx[3].as<int32_t>()};
+
+  // input vector in key order, and segment sums where one-factor / degenerate terms need them
+  bool need_sv[2] = {false, false};
+  for (const GemvSpec &g : P->gemvs) need_sv[g.key == SC ? 0 : 1] = true;
+  for (const SBufSpec &sb : P->sbufs)
+    if (sb.degenerate) need_sv[sb.key == SC ? 0 : 1] = true;
+  for (int k = 0; k < 2; ++k) {
+    const InputSort &is = P->insort[k];
+    if (!is.built) continue;
+    launch_pack_v<T>(V, ldv, is.perm.as<int32_t>(), P->n_in, R, wsp<T>(P, W.vs[k]), s);
+    if (need_sv[k])
+      launch_segsum<T>(is.seg.as<int64_t>(), wsp<T>(P, W.vs[k]), is.nkeys, R, wsp<T>(P, W.sv[k]), s);
+  }
+  // one-factor products g = F^{o(1|2)} s
+  for (size_t i = 0; i < P->gemvs.size(); ++i) {
+    const GemvSpec &g = P->gemvs[i];
+    const int ks = g.key == SC ? 0 : 1;
+    launch_gemv<T>(F[g.f], ldF[g.f], rows_of(P, g.f), nkeys_of(P, g.key), g.sq != 0,
+                   wsp<T>(P, W.sv[ks]), R, wsp<T>(P, W.gemv[i]), s);
+  }
+  // stage 1 (shared scatters)
+  bool transposed[2] = {false, false};
+  for (size_t i = 0; i < P->sbufs.size(); ++i) {
+    const SBufSpec &sb = P->sbufs[i];
+    const int ks = sb.key == SC ? 0 : 1;
+    const InputSort &is = P->insort[ks];
+    T *S = wsp<T>(P, W.sbuf[i]);
+    if (sb.degenerate) {
+      launch_colscale<T>(F[sb.fsc], ldF[sb.fsc], sb.d_rows.as<int32_t>(), (int64_t)sb.rows.size(),
+                         wsp<T>(P, W.sv[ks]), is.nkeys, R, S, s);
+      continue;
+    }
+    const T *Fc;
+    int64_t ldc;
+    if (P->flags & GVT_FLAG_SYMMETRIC_BASES) {
+      Fc = F[sb.fsc];
+      ldc = ldF[sb.fsc];
+    } else {
+      T *Ft = wsp<T>(P, W.trans[sb.fsc]);
+      if (!transposed[sb.fsc]) {
+        launch_transpose<T>(F[sb.fsc], ldF[sb.fsc], rows_of(P, sb.fsc), cols_of(P, sb.fsc), Ft,
+                            rows_of(P, sb.fsc), s);
+        transposed[sb.fsc] = true;
+      }
+      Fc = Ft;
+      ldc = rows_of(P, sb.fsc);
+    }
+    launch_stage1<T>(Fc, ldc, sb.d_rows.as<int32_t>(), (int64_t)sb.rows.size(),
+                     is.seg.as<int64_t>(), is.other.as<int32_t>(), wsp<T>(P, W.vs[ks]), is.nkeys,
+                     R, S, s);
+  }
+  // terms
+  for (size_t ti = 0; ti < P->terms.size(); ++ti) {
+    const TermSpec &t = P->terms[ti];
+    if (t.type == TG) {
+      const SBufSpec &sb = P->sbufs[t.sbuf];
+      const OutOrder &oo = P->outord[t.x == SA ? 0 : 1];
+      T *out = P->direct ? U : wsp<T>(P, W.tvec[ti]);
+      const int64_t ldi = P->direct ? 1 : R, ldr = P->direct ? ldu : 1;
+      launch_stage2<T>(F[t.fdot], ldF[t.fdot], oo.xs.as<int32_t>(), t.yrows.as<int32_t>(),
+                       oo.perm.as<int32_t>(), P->n_out, wsp<T>(P, W.sbuf[t.sbuf]),
+                       nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s);
+    } else if (t.type == TO) {
+      launch_gather_rows<T>(wsp<T>(P, W.gemv[t.gemv]), dev_sel[t.x], P->n_out, R,
+                            wsp<T>(P, W.tvec[ti]), s);
+    } else {
+      const int ks = t.key == SC ? 0 : 1;
+      const InputSort &is = P->insort[ks];
+      launch_match<T>(F[t.f], ldF[t.f], dev_sel[t.x], dev_sel[t.outkey], P->n_out,
+                      is.seg.as<int64_t>(), is.other.as<int32_t>(), wsp<T>(P, W.vs[ks]), is.nkeys,
+                      R, wsp<T>(P, W.tvec[ti]), s);
+    }
+  }
+  if (!P->direct) {
+    CombineArgs<T> ca;
+    ca.nterms = (int)P->terms.size();
+    ca.nout = (int)P->outputs.size();
+    for (size_t ti = 0; ti < P->terms.size(); ++ti) ca.t[ti] = wsp<T>(P, W.tvec[ti]);
+    for (size_t o = 0; o < P->outputs.size(); ++o)
+      for (auto &tc : P->outputs[o]) ca.coef[o][tc.first] = (T)tc.second;
+    launch_combine<T>(ca, P->n_out, R, U, ldu, block_stride, s);
+  }
+}
+
+template <class T>
+void execute_t(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ldt, const T *V,
+               int64_t nrhs, int64_t ldv, T *U, int64_t ldu, hipStream_t s) {
+  const int64_t block_stride = nrhs * ldu;
+  if (P->n_out == 0) return;
+  if (P->n_in == 0) {
+    launch_fill<T>(U, P->n_out, nrhs * (int64_t)P->outputs.size(), ldu, T(0), s);
+    return;
+  }
+  int64_t r0 = 0;
+  while (r0 < nrhs) {
+    const int64_t left = nrhs - r0;
+    const int R = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    execute_block<T>(P, D, ldd, Tm, ldt, V + r0 * ldv, R, ldv, U + r0 * ldu, ldu, block_stride, s);
+    r0 += R;
+  }
+}
+
+}  // namespace
+
+void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,
+                  const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu, hipStream_t s) {
+  GVT_REQUIRE(P, GVT_ERR_ARG, "null plan");
+  GVT_REQUIRE(nrhs >= 1, GVT_ERR_ARG, "nrhs must be >= 1");
+  GVT_REQUIRE(prec == GVT_F64 || prec == GVT_F32 || prec == GVT_BF16X3 || prec == GVT_BF16X6, GVT_ERR_ARG, "unknown precision");
+  GVT_REQUIRE(ldu >= P->n_out && ldv >= P->n_in, GVT_ERR_ARG, "ldv < n_in or ldu < n_out");
+  GVT_REQUIRE(P->n_out == 0 || U, GVT_ERR_ARG, "null U");
+  GVT_REQUIRE(P->n_in == 0 || V, GVT_ERR_ARG, "null V");
+  const bool needT = !P->homogeneous && P->n_in > 0 && P->n_out > 0;
+  GVT_REQUIRE(D || P->n_in == 0 || P->n_out == 0, GVT_ERR_ARG, "null D");
+  GVT_REQUIRE(!needT || T, GVT_ERR_ARG, "null T (heterogeneous kinds need T)");
+  GVT_REQUIRE(ldd >= P->d_cols, GVT_ERR_ARG, "ldd < d_cols");
+  GVT_REQUIRE(!needT || ldt >= P->t_cols, GVT_ERR_ARG, "ldt < t_cols");
+  P->last_stream = s;
+  if (P->dense) {
+    // complete data: each RHS column is vec(Vmat) with Vmat d_cols x t_cols row-major
+    for (int64_t r = 0; r < nrhs; ++r) {
+      const size_t es = prec == GVT_F64 ? 8 : 4;
+      dense_matvec(prec, D, P->d_rows, P->d_cols, ldd, T, P->t_rows, P->t_cols, ldt,
+                   static_cast<const char *>(V) + r * ldv * es, P->t_cols,
+                   static_cast<char *>(U) + r * ldu * es, P->t_rows, s);
+    }
+    return;
+  }
+  GVT_REQUIRE(prec == GVT_F64 || prec == GVT_F32, GVT_ERR_UNSUPPORTED,
+              "split-bf16 products are provided on the complete-data (matrix-core) path only");
+  if (prec == GVT_F64)
+    execute_t<double>(P, (const double *)D, ldd, (const double *)T, ldt, (const double *)V, nrhs,
+                      ldv, (double *)U, ldu, s);
+  else
+    execute_t<float>(P, (const float *)D, ldd, (const float *)T, ldt, (const float *)V, nrhs, ldv,
+                     (float *)U, ldu, s);
+  check_launch(s);
+}
+
+}  // namespace gvt

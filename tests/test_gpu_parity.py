@@ -1,0 +1,284 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle (run on an MI355X).
+
+Tolerances (norm-wise relative error per right-hand side and kind):
+FP64 1e-10, FP32 1e-5, bf16x3 1e-5 — the accuracy targets of the gather and
+dense paths.  Inputs come from the seeded generators; the oracle never sees
+anything the GPU produced.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2009_01054_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16x3": 1e-5}
+HET = ["kronecker", "linear", "poly2d", "cartesian"]
+HOM = ["symmetric", "antisymmetric", "ranking", "mlpk"]
+
+
+@pytest.fixture(scope="module")
+def gvt():
+    import paper_2009_01054_amd as g
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    g.load_library()
+    return g
+
+
+def dev(x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def idx(x):
+    return dev(np.asarray(x, dtype=np.int32))
+
+
+def relerr(got, ref):
+    got = np.asarray(got, dtype=np.float64).reshape(len(ref), -1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(len(ref), -1)
+    out = []
+    for r in range(ref.shape[1]):
+        den = np.linalg.norm(ref[:, r])
+        out.append(np.linalg.norm(got[:, r] - ref[:, r]) / (den if den > 0 else 1.0))
+    return max(out)
+
+
+def tdt(prec):
+    return torch.float64 if prec == "f64" else torch.float32
+
+
+# ------------------------------------------------------------- config 1, full
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_config1_kronecker_full(gvt, prec):
+    p = W.config1()
+    ref = oracle.pairwise_matvec("kronecker", p["D"], p["T"], (p["a"], p["b"]), (p["c"], p["e"]), p["v"])
+    dt = tdt(prec)
+    u = gvt.gvt_matvec(dev(p["D"], dt), dev(p["T"], dt), (idx(p["a"]), idx(p["b"])),
+                       (idx(p["c"]), idx(p["e"])), dev(p["v"], dt))
+    assert relerr(u.cpu().double().numpy(), ref) < TOL[prec]
+
+
+# ----------------------------------------------- every kind, ragged, multi-RHS
+def _het_problem(seed, m=37, q=29, n=700, n_out=333, nrhs=1):
+    return W.make_heterogeneous(90, seed, m, q, n, 6, n_out=n_out, nrhs=nrhs)
+
+
+def _hom_problem(seed, m=41, n=650, n_out=321, nrhs=1):
+    return W.make_homogeneous(91, seed, m, n, 5, n_out=n_out, kernel="gaussian", nrhs=nrhs)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nrhs", [1, 3, 8, 13])
+@pytest.mark.parametrize("kind", HET + HOM)
+def test_every_kind_vs_oracle(gvt, kind, nrhs, prec):
+    p = _hom_problem(nrhs, nrhs=nrhs) if kind in HOM else _het_problem(nrhs, nrhs=nrhs)
+    T = None if kind in HOM else p["T"]
+    ref = oracle.pairwise_matvec(kind, p["D"], T, (p["a"], p["b"]), (p["c"], p["e"]), p["v"])
+    dt = tdt(prec)
+    Dd = dev(p["D"], dt)
+    Td = Dd if T is None else dev(T, dt)
+    u = gvt.gvt_pairwise_matvec([kind], Dd, Td, (idx(p["a"]), idx(p["b"])), (idx(p["c"]), idx(p["e"])),
+                                dev(p["v"], dt), flags=gvt.FLAG_SYMMETRIC_BASES)
+    assert relerr(u[0].cpu().double().numpy(), ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("order", [0, 2, 4])
+@pytest.mark.parametrize("kind", ["kronecker", "poly2d", "symmetric", "mlpk"])
+def test_stage_orders_and_nonsymmetric_bases(gvt, kind, order):
+    """Both stage orders of Theorem 1, with the transposing (non-symmetric) path."""
+    r = np.random.default_rng([5, order])
+    if kind in HOM:
+        p = _hom_problem(3, m=30, n=300, n_out=150)
+        D = p["D"] + 0.05 * r.standard_normal(p["D"].shape)  # not symmetric on purpose
+        T = None
+    else:
+        p = _het_problem(4, m=19, q=31, n=300, n_out=170)
+        D = p["D"] + 0.05 * r.standard_normal(p["D"].shape)
+        T = p["T"] + 0.05 * r.standard_normal(p["T"].shape)
+    ref = oracle.pairwise_matvec(kind, D, T, (p["a"], p["b"]), (p["c"], p["e"]), p["v"])
+    Dd = dev(D)
+    Td = Dd if T is None else dev(T)
+    u = gvt.gvt_pairwise_matvec([kind], Dd, Td, (idx(p["a"]), idx(p["b"])), (idx(p["c"]), idx(p["e"])),
+                                dev(p["v"]), flags=order)
+    assert relerr(u[0].cpu().numpy(), ref) < 1e-10
+
+
+def test_rectangular_prediction(gvt):
+    """Two-sample product: test objects x training objects (non-square bases)."""
+    r = np.random.default_rng(12)
+    Xd, Xt = r.standard_normal((60, 4)), r.standard_normal((45, 4))
+    D = W.gaussian_kernel(Xd, Xd[:40])  # 60 test drugs x 40 train drugs
+    T = W.gaussian_kernel(Xt, Xt[:30])
+    c, e = W.sample_grid_pairs(r, 40, 30, 500)
+    a, b = W.sample_grid_pairs(r, 60, 45, 800)
+    v = r.standard_normal(500)
+    for kind in ["kronecker", "linear", "poly2d", "cartesian"]:
+        ref = oracle.pairwise_matvec(kind, D, T, (a, b), (c, e), v)
+        u = gvt.gvt_pairwise_matvec([kind], dev(D), dev(T), (idx(a), idx(b)), (idx(c), idx(e)), dev(v))
+        assert relerr(u[0].cpu().numpy(), ref) < 1e-10, kind
+
+
+def test_duplicates_and_repeated_indices(gvt):
+    r = np.random.default_rng(13)
+    m = 9
+    X = r.standard_normal((m, 3))
+    D = W.gaussian_kernel(X)
+    c = r.integers(0, m, 400).astype(np.int32)
+    e = r.integers(0, m, 400).astype(np.int32)
+    c[:50] = 3
+    e[:50] = 3  # a heavily repeated self pair
+    a = r.integers(0, m, 250).astype(np.int32)
+    b = r.integers(0, m, 250).astype(np.int32)
+    v = r.standard_normal(400)
+    for kind in HOM + ["kronecker", "cartesian"]:
+        ref = oracle.pairwise_matvec(kind, D, D, (a, b), (c, e), v)
+        u = gvt.gvt_pairwise_matvec([kind], dev(D), dev(D), (idx(a), idx(b)), (idx(c), idx(e)), dev(v),
+                                    flags=gvt.FLAG_SYMMETRIC_BASES)
+        assert relerr(u[0].cpu().numpy(), ref) < 1e-10, kind
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fused_four_kinds(gvt, prec):
+    """Symmetric + anti-symmetric + Cartesian + Poly2D in one plan (shared stage 1)."""
+    kinds = ["symmetric", "antisymmetric", "cartesian", "poly2d"]
+    p = W.make_homogeneous(92, 0, 300, 6000, 16, kernel="linear", nrhs=2)
+    dt = tdt(prec)
+    Dd = dev(p["D"], dt)
+    u = gvt.gvt_pairwise_matvec(kinds, Dd, Dd, (idx(p["a"]), idx(p["b"])), (idx(p["c"]), idx(p["e"])),
+                                dev(p["v"], dt), flags=gvt.FLAG_SYMMETRIC_BASES)
+    for k, kind in enumerate(kinds):
+        ref = oracle.pairwise_matvec(kind, p["D"], p["D"], (p["a"], p["b"]), (p["c"], p["e"]), p["v"])
+        assert relerr(u[k].cpu().double().numpy(), ref) < TOL[prec], kind
+
+
+def test_plan_reuse_and_determinism(gvt):
+    p = _het_problem(7, m=70, q=50, n=2500, n_out=2500)
+    plan = gvt.gvt_plan_create(["kronecker", "poly2d"], p["D"].shape, p["T"].shape,
+                               (idx(p["a"]), idx(p["b"])), (idx(p["c"]), idx(p["e"])),
+                               flags=gvt.FLAG_SYMMETRIC_BASES)
+    Dd, Td, V = dev(p["D"]), dev(p["T"]), dev(np.stack([p["v"], -p["v"]], 1))
+    u1 = plan.execute(Dd, Td, V).clone()
+    for _ in range(3):
+        u2 = plan.execute(Dd, Td, V)
+        assert torch.equal(u1, u2)
+    ref = oracle.pairwise_matvec("poly2d", p["D"], p["T"], (p["a"], p["b"]), (p["c"], p["e"]), p["v"])
+    assert relerr(u1[1, :, 0].cpu().numpy(), ref) < 1e-10
+    plan.close()
+
+
+def test_empty_inputs(gvt):
+    D = dev(np.eye(5)); T = dev(np.eye(4))
+    z = idx(np.zeros(0))
+    a = idx([0, 1, 2]); b = idx([1, 2, 3])
+    u = gvt.gvt_matvec(D, T, (a, b), (z, z), dev(np.zeros(0)))
+    assert u.shape == (3,) and torch.count_nonzero(u) == 0
+    u = gvt.gvt_matvec(D, T, (z, z), (a, b), dev(np.ones(3)))
+    assert u.numel() == 0
+
+
+def test_index_errors(gvt):
+    D = dev(np.eye(5)); T = dev(np.eye(4))
+    a = idx([0, 1]); b = idx([0, 4])  # 4 is out of range for T (4 rows)
+    with pytest.raises(gvt.GvtError) as ei:
+        gvt.gvt_matvec(D, T, (a, b), (a, a), dev(np.ones(2)))
+    assert ei.value.code == -2
+    with pytest.raises(gvt.GvtError) as ei:
+        gvt.gvt_pairwise_matvec(["symmetric"], D, T, (a, a), (a, a), dev(np.ones(2)))
+    assert ei.value.code == -3
+    with pytest.raises(gvt.GvtError) as ei:
+        gvt.gvt_pairwise_matvec(["kronecker"], D, T, (a, a), (a, a), dev(np.ones(2)), prec=gvt.BF16X3)
+    assert ei.value.code == -7
+
+
+# -------------------------------------------------------------- dense path
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("shape", [(64, 48), (200, 136), (257, 130)])
+def test_dense_vs_oracle_and_gemm(gvt, prec, shape):
+    m, q = shape
+    r = np.random.default_rng([14, m, q])
+    D = W.gaussian_kernel(r.standard_normal((m, 8)))
+    T = W.gaussian_kernel(r.standard_normal((q, 8)))
+    V = r.standard_normal((m, q))
+    ref = D @ V @ T.T  # host BLAS
+    dt = tdt(prec)
+    pc = {"f64": gvt.F64, "f32": gvt.F32, "bf16x3": gvt.BF16X3, "bf16x6": gvt.BF16X6}[prec]
+    U = gvt.gvt_dense_matvec(dev(D, dt), dev(T, dt), dev(V, dt), prec=pc).cpu().double().numpy()
+    err = np.linalg.norm(U - ref) / np.linalg.norm(ref)
+    if prec == "bf16x3":
+        # bf16x3 keeps ~16 significant bits per operand (x - hi - lo = O(2^-17 |x|)), so its
+        # error is bounded by the magnitude product, not by |U|: |dU| <= 4 * 2^-16 |M||V||N|^T
+        mag = np.abs(D) @ np.abs(V) @ np.abs(T).T
+        assert np.linalg.norm(U - ref) <= 4 * 2.0 ** -16 * np.linalg.norm(mag)
+    else:
+        assert err < TOL.get(prec, 1e-5)
+    # sampled entries against the oracle's double loop
+    idxs = r.choice(m * q, 64, replace=False)
+    a_all = (np.arange(m * q) // q).astype(np.int32)
+    b_all = (np.arange(m * q) % q).astype(np.int32)
+    u_or = oracle.pairwise_matvec("kronecker", D, T, (a_all, b_all), (a_all, b_all), V.ravel(), rows=idxs)
+    assert relerr(U.ravel()[idxs], u_or) < (1e-10 if prec == "f64" else 1e-4)
+
+
+def test_dense_autodetect_via_matvec(gvt):
+    m, q = 40, 24
+    r = np.random.default_rng(15)
+    D = W.gaussian_kernel(r.standard_normal((m, 4)))
+    T = W.gaussian_kernel(r.standard_normal((q, 4)))
+    v = r.standard_normal(m * q)
+    a = (np.arange(m * q) // q).astype(np.int32)
+    b = (np.arange(m * q) % q).astype(np.int32)
+    u = gvt.gvt_matvec(dev(D), dev(T), (idx(a), idx(b)), (idx(a), idx(b)), dev(v))
+    ref = (D @ v.reshape(m, q) @ T.T).ravel()
+    assert relerr(u.cpu().numpy(), ref) < 1e-10
+
+
+# ---------------------------------------------------------------------- CG
+@pytest.mark.parametrize("kind", ["kronecker", "symmetric", "poly2d", "mlpk"])
+def test_cg_f64_matches_oracle_cg(gvt, kind):
+    if kind in HOM:
+        p = W.make_homogeneous(93, 1, 40, 500, 4, kernel="gaussian")
+        T = None
+    else:
+        p = W.make_heterogeneous(93, 2, 35, 30, 600, 4)
+        T = p["T"]
+    y = np.random.default_rng(16).standard_normal(len(p["c"]))
+    lams = [1e-1, 1.0]
+    A_or, it_or, _, rt_or = oracle.krr_cg(kind, p["D"], T, (p["c"], p["e"]), y, lams, max_iter=300, tol=1e-8)
+    Dd = dev(p["D"])
+    A, iters, rel, rc = gvt.gvt_krr_cg(kind, Dd, None if T is None else dev(T), (idx(p["c"]), idx(p["e"])),
+                                       dev(y), lams, max_iter=300, tol=1e-8, check_every=4)
+    A = A.cpu().numpy()
+    assert rc == 0
+    for l in range(len(lams)):
+        assert rel[l] < 1e-8
+        assert np.linalg.norm(A[:, l] - A_or[:, l]) / np.linalg.norm(A_or[:, l]) < 1e-7
+        assert abs(int(iters[l]) - int(it_or[l])) <= 2
+
+
+def test_cg_f32_products_certified(gvt):
+    p = W.make_heterogeneous(94, 0, 60, 50, 1500, 32, labels=True)
+    lams = [1e-1, 1.0]
+    A_or, it_or, _, rt_or = oracle.krr_cg("kronecker", p["D"], p["T"], (p["c"], p["e"]), p["y"], lams,
+                                          max_iter=300, tol=1e-6)
+    A, iters, rel, rc = gvt.gvt_krr_cg("kronecker", dev(p["D"]), dev(p["T"]), (idx(p["c"]), idx(p["e"])),
+                                       dev(p["y"]), lams, max_iter=300, tol=1e-6, matvec_prec=gvt.F32)
+    assert (rt_or < 1e-6).all()
+    assert rc == 0 and (rel < 1e-6).all()
+    A = A.cpu().numpy()
+    for l in range(len(lams)):
+        assert np.linalg.norm(A[:, l] - A_or[:, l]) / np.linalg.norm(A_or[:, l]) < 1e-4
+
+
+def test_cg_not_converged_status(gvt):
+    p = W.make_heterogeneous(94, 1, 30, 30, 400, 4, labels=True)
+    A, iters, rel, rc = gvt.gvt_krr_cg("kronecker", dev(p["D"]), dev(p["T"]), (idx(p["c"]), idx(p["e"])),
+                                       dev(p["y"]), [1e-6], max_iter=1, tol=1e-12, check_every=1)
+    assert rc == 1 and iters[0] == 1
