@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Benchmark: kernel ridge regression by CG with the Kronecker pairwise kernel.
+
+Workload (one GPU): m = 2000 drugs, q = 500 targets, Gaussian base kernels
+(sigma = 4) on 64-dim N(0,1) features, n = 200 000 training pairs (20% of the
+grid, uniform without replacement), labels = rank-10 bilinear signal plus
+N(0, 0.1^2) noise, lambda = 1e-2, CG to a true relative residual of 1e-6
+(at most 200 iterations).  Synthetic, seeded inputs shaped like the Merget
+interaction data (Table 5).
+
+One step = one complete ridge solve through the library's C ABI
+(gvt_krr_cg): plan (index sort), every CG iteration's generalized vec trick
+product, and the final FP64 true-residual product.  Inputs are resident in
+HBM before the timed region starts.
+
+Printed: one JSON line with the throughput in GVT products per second, the
+time per solve, a roofline record for the dominant kernel (stage-2
+gather-dot, timed with HIP events on the library's stream) and the CPU
+oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GVT matvecs/sec & KRR-CG time to 1e-6 rel. residual; fraction of HBM/MFMA roofline"
+PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X published FP64 vector peak
+PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X published FP32 vector peak (counts packed FP32)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage2_merget_shape.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2009_01054_amd", "csrc", "gather_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(prec_name):
+    """HBM bytes per stage-2 launch from the committed rocprofv3 counter summary,
+    or None when the summary is missing or was taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != source_sha():
+        return None
+    key = f"stage2_{prec_name}_hbm_bytes"
+    return float(kv[key]) if key in kv else None
+
+
+def cpu_baseline(p, seconds):
+    """Oracle (plain FP64 double loop) on a bounded row sample of one product."""
+    import numpy as np
+
+    import oracle
+
+    n_out = len(p["a"])
+    threads = oracle.max_threads()
+    rng = np.random.default_rng(12345)
+    rows = 512
+    done_rows, elapsed = 0, 0.0
+    while elapsed < seconds:
+        sel = rng.choice(n_out, rows, replace=False)
+        t0 = time.perf_counter()
+        oracle.pairwise_matvec("kronecker", p["D"], p["T"], (p["a"], p["b"]), (p["c"], p["e"]),
+                               p["v"] if "v" in p else p["y"], rows=sel)
+        dt = time.perf_counter() - t0
+        done_rows += rows
+        elapsed += dt
+        # grow the sample towards the time budget
+        remaining = seconds - elapsed
+        if remaining > 0:
+            rate = rows / max(dt, 1e-6)
+            rows = int(min(n_out, max(512, min(rate * remaining, rate * 5.0))))
+    value = (done_rows / n_out) / elapsed
+    return {
+        "value": value,
+        "unit": "matvecs/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{done_rows} of {n_out} output rows of the FP64 Table-4b double loop "
+                  f"(each row sums all {len(p['c'])} training pairs) in {elapsed:.1f} s on "
+                  f"{threads} OpenMP threads; rate scaled to whole products",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", choices=["f64", "f32"], default="f64",
+                    help="product arithmetic (CG vectors and scalars are FP64 either way)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-reps", type=int, default=20)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU; multi-GPU runs are not provided "
+              "(the path would shard the drug index space, see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2009_01054_amd as gvt
+    from paper_2009_01054_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    gvt.load_library()
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    p = W.config2()
+    log(f"[bench] inputs generated in {time.perf_counter() - t_gen:.1f} s")
+    D = torch.from_numpy(p["D"]).to(dev)
+    T = torch.from_numpy(p["T"]).to(dev)
+    c = torch.from_numpy(p["c"]).to(dev)
+    e = torch.from_numpy(p["e"]).to(dev)
+    y = torch.from_numpy(p["y"]).to(dev)
+    lam = [p["lam"]]
+    mprec = gvt.F64 if args.prec == "f64" else gvt.F32
+    torch.cuda.synchronize()
+
+    def solve(prec):
+        return gvt.gvt_krr_cg("kronecker", D, T, (c, e), y, lam, max_iter=200, tol=1e-6,
+                              matvec_prec=prec, check_every=8)
+
+    for i in range(args.warmup):
+        _, it, rel, rc = solve(mprec)
+        log(f"[bench] warmup {i}: iters {int(it[0])} true relres {rel[0]:.3e} rc {rc}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters_total = 0
+    rels = []
+    for _ in range(args.steps):
+        _, it, rel, rc = solve(mprec)
+        iters_total += int(it.sum())
+        rels.append(float(rel.max()))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    value = iters_total / elapsed
+    log(f"[bench] timed {args.steps} solves: {ms_per_step:.2f} ms/solve, {iters_total / args.steps:.1f} "
+        f"iterations/solve, max true relres {max(rels):.3e}")
+
+    # other precision, outside the timed region (for the FP64-vs-FP32 comparison)
+    other = gvt.F32 if mprec == gvt.F64 else gvt.F64
+    solve(other)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, it_o, rel_o, rc_o = solve(other)
+    torch.cuda.synchronize()
+    other_ms = (time.perf_counter() - t1) * 1e3
+
+    # ---- dominant kernel: stage-2 gather-dot, HIP events on the library's stream
+    plan = gvt.gvt_plan_create("kronecker", D.shape, T.shape, (c, e), (c, e), flags=gvt.FLAG_SYMMETRIC_BASES)
+    info = gvt.gvt_plan_info(plan)
+    n, m, q = len(p["c"]), p["m"], p["q"]
+    Dp = D if mprec == gvt.F64 else D.float()
+    Tp = T if mprec == gvt.F64 else T.float()
+    v = torch.randn(n, dtype=Dp.dtype, device=dev)
+    t_plan = time.perf_counter()
+    plan2 = gvt.gvt_plan_create("kronecker", D.shape, T.shape, (c, e), (c, e), flags=gvt.FLAG_SYMMETRIC_BASES)
+    plan_ms = (time.perf_counter() - t_plan) * 1e3
+    plan2.close()
+    gvt.gvt_plan_profile(plan, Dp, Tp, v, reps=3)  # warm
+    stage_ms = gvt.gvt_plan_profile(plan, Dp, Tp, v, reps=args.profile_reps)
+    # one full product timed with events for the matvec rate
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.profile_reps):
+        plan.execute(Dp, Tp, v)
+    ev1.record()
+    torch.cuda.synchronize()
+    matvec_ms = ev0.elapsed_time(ev1) / args.profile_reps
+    plan.close()
+    s_keys = info["s_keys"]
+    n_out = n
+    flops_stage2 = 2.0 * n_out * s_keys  # one FMA per (output, key) per RHS
+    stage2_s = stage_ms[2] * 1e-3
+    achieved_tflops = flops_stage2 / stage2_s / 1e12
+    peak = PEAK_FP64_VALU_TFLOPS if mprec == gvt.F64 else PEAK_FP32_VALU_TFLOPS
+    traffic = read_traffic(args.prec)
+    roofline = {
+        "kernel": "stage2_kernel (gather-dot)",
+        "bound": "alu",
+        "achieved": round(achieved_tflops, 4),
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": round(achieved_tflops / peak, 5),
+        "traffic": traffic,
+        "per_launch_flops": flops_stage2,
+        "avg_launch_ms": round(stage_ms[2], 5),
+        "stage_ms": {"prep": round(stage_ms[0], 5), "stage1": round(stage_ms[1], 5),
+                     "stage2": round(stage_ms[2], 5), "other": round(stage_ms[3], 5)},
+        "matvec_ms": round(matvec_ms, 5),
+        "theorem1_fma_per_matvec": info["cost_fma"],
+        "matvec_tflops": round(2.0 * info["cost_fma"] / (matvec_ms * 1e-3) / 1e12, 4),
+    }
+    log(f"[bench] stage ms {stage_ms}, matvec {matvec_ms:.4f} ms, plan {plan_ms:.1f} ms")
+
+    cpu = None
+    if not args.no_cpu:
+        t_c = time.perf_counter()
+        cpu = cpu_baseline({**p, "v": np.random.default_rng(7).standard_normal(n)}, args.cpu_seconds)
+        log(f"[bench] cpu baseline {cpu['value']:.4g} matvecs/s ({time.perf_counter() - t_c:.1f} s)")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {
+            "workload": "Kronecker-kernel ridge regression by CG (Gaussian bases, sigma=4, 64-dim), "
+                        "m=2000 drugs x q=500 targets, n=200000 pairs (20%), lambda=1e-2, tol=1e-6",
+            "global_batch": n,
+            "seq_len": None,
+            "parallelism": "single GPU",
+            "cg_vectors_and_scalars": "f64",
+            "products": args.prec,
+        },
+        "krr_cg": {
+            "seconds_per_solve": round(ms_per_step / 1e3, 6),
+            "iterations": iters_total // args.steps,
+            "true_relres_max": max(rels),
+            "plan_ms": round(plan_ms, 3),
+            "other_precision": {
+                "products": "f32" if other == gvt.F32 else "f64",
+                "seconds_per_solve": round(other_ms / 1e3, 6),
+                "iterations": int(it_o[0]),
+                "true_relres": float(rel_o[0]),
+                "status": int(rc_o),
+            },
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernel_source_sha": source_sha(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -204,6 +204,29 @@ int gvt_krr_cg(int kind, const double *D, int64_t d, int64_t ldd, const double *
                int64_t lda0, int max_iter, double tol, int matvec_prec, int check_every,
                int64_t *iters_out, double *relres_out, void *stream);
 
+/*
+ * gvt_plan_profile — diagnostic: runs gvt_plan_execute `reps` times
+ * (synchronising `stream` after each) with HIP events recorded at the stage
+ * boundaries of the generalized vec trick, and writes the mean milliseconds
+ * of each stage group to stage_ms[4] (host): [0] input gather + segment sums
+ * + one-factor GEMVs, [1] stage 1 (scatters into S), [2] stage 2 (gather-dot
+ * of every two-factor term), [3] match terms, gathers and the per-kind
+ * combination.  nrhs <= 8.  Gather path only (GVT_ERR_UNSUPPORTED for a
+ * complete-data plan).
+ */
+int gvt_plan_profile(gvt_plan_t plan, int prec, const void *D, int64_t ldd, const void *T,
+                     int64_t ldt, const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu,
+                     int reps, double *stage_ms, void *stream);
+
+/*
+ * gvt_plan_info — diagnostic: info[11] (host) receives the Theorem 1 FMA count
+ * of the plan's term program per right-hand side, whether it is a
+ * complete-data plan, the numbers of distinct terms and stage-1 buffers, the
+ * first buffer's row and key counts and key index (2 = drug, 3 = target, -1 =
+ * none), and the unique counts of a, b, c, e (Table 1).
+ */
+int gvt_plan_info(gvt_plan_t plan, double *info);
+
 /* Message describing the calling thread's most recent error ("" if none). */
 const char *gvt_last_error(void);
 

@@ -28,6 +28,8 @@ from ._binding import (  # noqa: F401
     gvt_plan_create,
     gvt_plan_destroy,
     gvt_plan_execute,
+    gvt_plan_info,
+    gvt_plan_profile,
     gvt_version,
     library_path,
     load_library,

@@ -60,7 +60,9 @@ def load_library():
     lib.gvt_dense_matvec.argtypes = [I, P, I64, I64, I64, P, I64, I64, I64, P, I64, P, I64, P]
     lib.gvt_krr_cg.argtypes = [I, P, I64, I64, P, I64, I64, P, P, I64, P, P, I, P, I64, P, I64, I,
                                ctypes.c_double, I, I, P, P, P]
-    for f in ("gvt_plan_create", "gvt_plan_destroy", "gvt_plan_execute", "gvt_matvec",
+    lib.gvt_plan_profile.argtypes = [P, I, P, I64, P, I64, P, I64, I64, P, I64, I, P, P]
+    lib.gvt_plan_info.argtypes = [P, P]
+    for f in ("gvt_plan_profile", "gvt_plan_info", "gvt_plan_create", "gvt_plan_destroy", "gvt_plan_execute", "gvt_matvec",
               "gvt_pairwise_matvec", "gvt_dense_matvec", "gvt_krr_cg"):
         getattr(lib, f).restype = I
     _lib = lib
@@ -193,6 +195,31 @@ def gvt_plan_execute(plan: Plan, D, T, V, prec=None, out=None):
     if V.dim() == 1:
         res = res[:, :, 0]
     return res
+
+
+def gvt_plan_profile(plan: Plan, D, T, V, prec=None, reps=10, out=None):
+    """Mean ms per stage group: [prep, stage1, stage2, other] (see gvt.h)."""
+    torch = _torch()
+    lib = load_library()
+    p = _prec_of(D.dtype, prec)
+    V2, ldv = _colmajor(V)
+    nrhs = V2.shape[1]
+    U = out if out is not None else torch.empty((plan.nkinds, nrhs, max(plan.n_out, 1)),
+                                                 dtype=D.dtype, device=D.device)
+    ms = np.zeros(4, dtype=np.float64)
+    _check(lib.gvt_plan_profile(plan.handle, p, _ptr(D), _ld(D), _ptr(T), _ld(T) if T is not None else 0,
+                                _ptr(V2), nrhs, ldv, _ptr(U), U.shape[2], int(reps),
+                                ms.ctypes.data_as(ctypes.c_void_p), _stream_handle()))
+    return ms
+
+
+def gvt_plan_info(plan: Plan):
+    lib = load_library()
+    info = np.zeros(11, dtype=np.float64)
+    _check(lib.gvt_plan_info(plan.handle, info.ctypes.data_as(ctypes.c_void_p)))
+    keys = ["cost_fma", "dense", "terms", "sbufs", "s_rows", "s_keys", "s_key", "uniq_a", "uniq_b",
+            "uniq_c", "uniq_e"]
+    return dict(zip(keys, info.tolist()))
 
 
 # ------------------------------------------------------------- one-shot calls

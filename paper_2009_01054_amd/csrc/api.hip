@@ -72,6 +72,39 @@ int gvt_plan_execute(gvt_plan_t plan, int prec, const void *D, int64_t ldd, cons
   });
 }
 
+int gvt_plan_profile(gvt_plan_t plan, int prec, const void *D, int64_t ldd, const void *T,
+                     int64_t ldt, const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu,
+                     int reps, double *stage_ms, void *stream) {
+  return guarded([&]() {
+    plan_profile(plan, prec, D, ldd, T, ldt, V, nrhs, ldv, U, ldu, reps, stage_ms,
+                 (hipStream_t)stream);
+    return GVT_OK;
+  });
+}
+
+int gvt_plan_info(gvt_plan_t plan, double *info) {
+  return guarded([&]() {
+    GVT_REQUIRE(plan && info, GVT_ERR_ARG, "null argument");
+    info[0] = plan->cost_fma;
+    info[1] = plan->dense ? 1.0 : 0.0;
+    info[2] = (double)plan->terms.size();
+    info[3] = (double)plan->sbufs.size();
+    int64_t srows = 0, skeys = 0;
+    if (!plan->sbufs.empty()) {
+      srows = (int64_t)plan->sbufs[0].rows.size();
+      skeys = nkeys_of(plan, plan->sbufs[0].key);
+    }
+    info[4] = (double)srows;
+    info[5] = (double)skeys;
+    info[6] = plan->sbufs.empty() ? -1.0 : (double)plan->sbufs[0].key;
+    info[7] = (double)plan->uniq[0];
+    info[8] = (double)plan->uniq[1];
+    info[9] = (double)plan->uniq[2];
+    info[10] = (double)plan->uniq[3];
+    return GVT_OK;
+  });
+}
+
 static int oneshot(int prec, const int *kinds, int nkinds, const void *D, int64_t d_rows,
                    int64_t d_cols, int64_t ldd, const void *T, int64_t t_rows, int64_t t_cols,
                    int64_t ldt, const int32_t *out_a, const int32_t *out_b, int64_t n_out,

@@ -19,6 +19,8 @@ __device__ __forceinline__ int wave_id_uniform() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
+__device__ __forceinline__ int64_t ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 // ---------------------------------------------------------------------------
 // vs[p*R + r] = V[perm[p] + r*ldv]  (input vector gathered into key order)
 template <class T>
@@ -45,54 +47,84 @@ __global__ void segsum_kernel(const int64_t *__restrict__ seg, const T *__restri
 }
 
 // ---------------------------------------------------------------------------
-// Stage 1.  Fc holds F2 column-accessible: F2[y, o] = Fc[o*ldc + y].
-// Block = 4 waves; lane <-> one S row (64 rows per block); each wave owns
-// KB/4 consecutive keys.  Segment data (other index, packed v) are wave-
-// uniform and come through the scalar cache; the F2 column segment load is
-// coalesced across lanes.  The [64 x KB*R] result tile is staged in LDS and
-// written row-contiguously.
-template <class T, int R, int KB>
+// Stage 1 (segmented scatter-reduce).  Fc holds F2 column-accessible:
+// F2[y, o] = Fc[o*ldc + y].  Block = 4 waves over 64 S rows (one per lane)
+// and KB keys (KPW per wave).  The other-index range is swept in tiles of
+// OCT: the tile Fc[o-tile][64 rows] sits in LDS (64 KB) and every input
+// pair of the block's keys whose other index falls in the tile reads its
+// factor from there.  Pairs are sorted by other index inside each key
+// segment, and seg2 gives the boundaries of each (key, 128-wide chunk).
+// Segment data (other index, packed v) are wave-uniform scalar loads; the
+// partial sums stay in registers across tiles; the [64 x KB*R] result is
+// staged through LDS and written row-contiguously.
+template <class T, int R> struct S1Cfg {
+  static constexpr int OCT = sizeof(T) == 8 ? 128 : 256;  // tile: OCT x 64 elements = 64 KB
+  static constexpr int KPW = (16 / R) > 2 ? 16 / R : 2;     // keys per wave
+  static constexpr int KB = 4 * KPW;                        // keys per block
+};
+
+template <class T, int R>
 __global__ __launch_bounds__(256) void stage1_kernel(
-    const T *__restrict__ Fc, int64_t ldc, const int32_t *__restrict__ rows, int64_t nrows,
-    const int64_t *__restrict__ seg, const int32_t *__restrict__ other,
-    const T *__restrict__ vs, int64_t nkeys, T *__restrict__ S) {
-  __shared__ T tile[64][KB * R + 1];
+    const T *__restrict__ Fc, int64_t ldc, int64_t nother, const int32_t *__restrict__ rows,
+    int64_t nrows, const int64_t *__restrict__ seg2, int noc, const int32_t *__restrict__ other,
+    const T *__restrict__ vs, int64_t nkeys, T *__restrict__ S, int64_t ldS) {
+  typedef S1Cfg<T, R> C;
+  __shared__ __attribute__((aligned(16))) T tile[C::OCT * 64];
   const int lane = threadIdx.x & 63;
   const int w = wave_id_uniform();
-  const int64_t k0 = (int64_t)blockIdx.x * KB;
+  const int64_t k0 = (int64_t)blockIdx.x * C::KB;
   const int64_t rho0 = (int64_t)blockIdx.y * 64;
   const int64_t rho = rho0 + lane;
   const bool live = rho < nrows;
   const int64_t y = live ? rows[rho] : 0;
-  constexpr int KPW = KB / 4;
-#pragma unroll 1
-  for (int t = 0; t < KPW; ++t) {
-    const int kk = w * KPW + t;
-    const int64_t k = k0 + kk;
-    T acc[R];
+  constexpr int CPT = C::OCT / kStage1Chunk;  // plan chunks per tile
+  T acc[C::KPW][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = T(0);
-    if (k < nkeys) {
-      const int64_t p0 = seg[k], p1 = seg[k + 1];
+  for (int kk = 0; kk < C::KPW; ++kk)
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[kk][r] = T(0);
+  const int ntile = (int)ceil_div_dev(nother, C::OCT);
+  for (int ot = 0; ot < ntile; ++ot) {
+    __syncthreads();
+    const int64_t obase = (int64_t)ot * C::OCT;
+    for (int oo = w; oo < C::OCT; oo += 4) {
+      const int64_t o = obase + oo;
+      tile[oo * 64 + lane] = (live && o < nother) ? Fc[o * ldc + y] : T(0);
+    }
+    __syncthreads();
+    const int c0 = ot * CPT;
+    const int c1 = (c0 + CPT) < noc ? (c0 + CPT) : noc;
+#pragma unroll
+    for (int kk = 0; kk < C::KPW; ++kk) {
+      const int64_t k = k0 + w * C::KPW + kk;
+      if (k < nkeys) {
+        const int64_t *sk = seg2 + k * (noc + 1);
+        const int64_t p0 = sk[c0], p1 = sk[c1];
 #pragma unroll 4
-      for (int64_t p = p0; p < p1; ++p) {
-        const int64_t o = other[p];
-        const T f = live ? Fc[o * ldc + y] : T(0);
+        for (int64_t p = p0; p < p1; ++p) {
+          const int o = (int)(other[p] - obase);
+          const T f = tile[o * 64 + lane];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] += f * vs[p * R + r];
+          for (int r = 0; r < R; ++r) acc[kk][r] += f * vs[p * R + r];
+        }
       }
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r) tile[lane][kk * R + r] = acc[r];
   }
+  // stage the [64 rows x KB*R] block through LDS for row-contiguous stores
+  constexpr int W = C::KB * R;
   __syncthreads();
-  const int64_t kcount = (nkeys - k0) < KB ? (nkeys - k0) : KB;
+  T *stg = tile;  // 64 x (W + 1) <= OCT * 64
+#pragma unroll
+  for (int kk = 0; kk < C::KPW; ++kk)
+#pragma unroll
+    for (int r = 0; r < R; ++r) stg[lane * (W + 1) + (w * C::KPW + kk) * R + r] = acc[kk][r];
+  __syncthreads();
+  const int64_t kcount = (nkeys - k0) < C::KB ? (nkeys - k0) : C::KB;
   const int width = (int)kcount * R;
-  for (int idx = threadIdx.x; idx < 64 * KB * R; idx += 256) {
-    const int rr = idx / (KB * R);
-    const int cc = idx - rr * (KB * R);
+  for (int idx = threadIdx.x; idx < 64 * W; idx += 256) {
+    const int rr = idx / W, cc = idx - rr * W;
     const int64_t orow = rho0 + rr;
-    if (orow < nrows && cc < width) S[(orow * nkeys + k0) * R + cc] = tile[rr][cc];
+    if (orow < nrows && cc < width) S[orow * ldS + k0 * R + cc] = stg[rr * (W + 1) + cc];
   }
 }
 
@@ -100,51 +132,131 @@ __global__ __launch_bounds__(256) void stage1_kernel(
 template <class T>
 __global__ void colscale_kernel(const T *__restrict__ F, int64_t ldf, const int32_t *__restrict__ rows,
                                 int64_t nrows, const T *__restrict__ s, int64_t nkeys, int R,
-                                T *__restrict__ S) {
+                                T *__restrict__ S, int64_t ldS) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t total = nrows * nkeys;
   if (idx >= total) return;
   int64_t rho = idx / nkeys, k = idx - rho * nkeys;
   T f = F[(int64_t)rows[rho] * ldf + k];
-  for (int r = 0; r < R; ++r) S[idx * R + r] = f * s[k * R + r];
+  for (int r = 0; r < R; ++r) S[rho * ldS + k * R + r] = f * s[k * R + r];
 }
 
 // ---------------------------------------------------------------------------
-// Stage 2.  Outputs are visited in plan order (grouped by x, the F1 row);
-// 8 lanes cooperate on one output, striding over k; the partial sums meet in
-// a fixed 3-step butterfly.  out[i*ldi + r*ldr] = coef * sum_k F1[x,k] S[yrow,k,r]
+// Stage 2 (gather-dot), 2-D tiles.  The plan cuts the (x, S-row) plane into
+// tiles of 32 consecutive F1 rows x one block of at most 64 S rows, orders
+// the outputs by (tile, x, S row), and numbers the tiles so that the S-row
+// block index is the fastest-varying digit.  Workgroups are dealt to the
+// eight XCDs round-robin, so with a multiple of eight S-row blocks each XCD
+// only ever touches its own slice of S, which then stays in that XCD's L2.
+// Inside a tile one 16-lane group owns one F1 row: it holds that row's slice
+// of the current key chunk in registers (loaded once per chunk) and walks
+// its outputs, reading the S rows from a shared LDS tile (one 1 KB chunk per
+// S row).  Partial sums stay in registers across chunks and meet in a fixed
+// butterfly at the end, so the result is deterministic.
+template <class T, int R> struct S2Cfg {
+  static constexpr int LPO = 16;                   // lanes per F1 row / output
+  static constexpr int NG = kStage2Rows;           // groups = F1 rows per tile (32)
+  static constexpr int NT = NG * LPO;              // threads per workgroup (512)
+  static constexpr int VEC = 16 / sizeof(T);       // elements per 16-byte LDS read
+  static constexpr int EPL = VEC > R ? VEC : R;    // elements per lane per step
+  static constexpr int KPL = EPL / R;              // keys per lane per step
+  static constexpr int ROWE = 1024 / sizeof(T);    // tile row: 1 KB
+  static constexpr int KC = ROWE / R;              // keys per chunk
+  static constexpr int STEPS = KC / (LPO * KPL);
+  static constexpr int OPG = (32 / R) > 4 ? 32 / R : 4;  // outputs per group per pass
+  static constexpr int PADE = VEC;                 // +16 B per tile row
+  static_assert(STEPS >= 1, "chunk smaller than one step");
+};
+
 template <class T, int R>
-__global__ __launch_bounds__(256) void stage2_kernel(
-    const T *__restrict__ F1, int64_t ld1, const int32_t *__restrict__ xs,
-    const int32_t *__restrict__ yrows, const int32_t *__restrict__ perm, int64_t nq,
-    const T *__restrict__ S, int64_t nkeys, T coef, T *__restrict__ out, int64_t ldi,
+__global__ __launch_bounds__(512) void stage2_kernel(
+    const T *__restrict__ F1, int64_t ld1, int64_t nx, const int64_t *__restrict__ tileoff,
+    const int32_t *__restrict__ tiley, const int32_t *__restrict__ tilemax,
+    const int32_t *__restrict__ yrows, const int32_t *__restrict__ perm, int nyb,
+    const T *__restrict__ S, int64_t ldS, int64_t nkeys, T coef, T *__restrict__ out, int64_t ldi,
     int64_t ldr) {
-  const int sub = threadIdx.x & 7;
-  const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
-  const bool live = q < nq;
-  T acc[R];
+  typedef S2Cfg<T, R> C;
+  constexpr int TROW = C::ROWE + C::PADE;
+  __shared__ __attribute__((aligned(16))) T tile[kStage2MaxS * TROW];
+  __shared__ unsigned char meta[C::NG][C::OPG];
+  const int t = blockIdx.x;
+  const int maxcnt = tilemax[t];
+  if (maxcnt == 0) return;  // uniform: empty tile
+  const int xb = t / nyb;
+  const int64_t y0 = tiley[2 * t], nyr = tiley[2 * t + 1];
+  const int sub = threadIdx.x % C::LPO, grp = threadIdx.x / C::LPO;
+  const int64_t x = (int64_t)xb * C::NG + grp;
+  const int64_t qb = tileoff[(int64_t)t * (C::NG + 1) + grp];
+  const int cnt = (int)(tileoff[(int64_t)t * (C::NG + 1) + grp + 1] - qb);
+  const T *frow = F1 + (x < nx ? x : 0) * ld1;
+  for (int pass0 = 0; pass0 < maxcnt; pass0 += C::OPG) {
+    const int npass = (cnt - pass0) < C::OPG ? (cnt - pass0) : C::OPG;  // may be <= 0
+    __syncthreads();
+    for (int o = sub; o < C::OPG; o += C::LPO)
+      meta[grp][o] = (o < npass) ? (unsigned char)(yrows[qb + pass0 + o] - y0) : 0;
+    T acc[C::OPG][R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = T(0);
-  if (live) {
-    const T *frow = F1 + (int64_t)xs[q] * ld1;
-    const T *srow = S + (int64_t)yrows[q] * nkeys * R;
-#pragma unroll 4
-    for (int64_t k = sub; k < nkeys; k += 8) {
-      const T f = frow[k];
+    for (int o = 0; o < C::OPG; ++o)
 #pragma unroll
-      for (int r = 0; r < R; ++r) acc[r] += f * srow[k * R + r];
+      for (int r = 0; r < R; ++r) acc[o][r] = T(0);
+    for (int64_t k0 = 0; k0 < nkeys; k0 += C::KC) {
+      __syncthreads();
+      const int64_t ecnt = ((nkeys - k0) < C::KC ? (nkeys - k0) : C::KC) * R;
+      for (int idx = threadIdx.x; idx < nyr * (C::ROWE / C::VEC); idx += C::NT) {
+        const int row = idx / (C::ROWE / C::VEC);
+        const int cc = (idx - row * (C::ROWE / C::VEC)) * C::VEC;
+        const T *src = S + (y0 + row) * ldS + k0 * R + cc;
+        T v[C::VEC];
+        if (cc + C::VEC <= ecnt) {
+#pragma unroll
+          for (int u = 0; u < C::VEC; ++u) v[u] = src[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < C::VEC; ++u) v[u] = (cc + u < ecnt) ? src[u] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < C::VEC; ++u) tile[row * TROW + cc + u] = v[u];
+      }
+      // this group's F1 row slice for the chunk
+      T dsl[C::STEPS][C::KPL];
+#pragma unroll
+      for (int st = 0; st < C::STEPS; ++st)
+#pragma unroll
+        for (int j = 0; j < C::KPL; ++j) {
+          const int64_t kk = k0 + (int64_t)st * C::LPO * C::KPL + sub * C::KPL + j;
+          dsl[st][j] = (npass > 0 && x < nx && kk < nkeys) ? frow[kk] : T(0);
+        }
+      __syncthreads();
+#pragma unroll
+      for (int o = 0; o < C::OPG; ++o) {
+        if (o < npass) {
+          const T *trow = tile + (int)meta[grp][o] * TROW + sub * C::EPL;
+#pragma unroll
+          for (int st = 0; st < C::STEPS; ++st) {
+            T sv[C::EPL];
+#pragma unroll
+            for (int u = 0; u < C::EPL; ++u) sv[u] = trow[st * C::LPO * C::EPL + u];
+#pragma unroll
+            for (int u = 0; u < C::EPL; ++u) acc[o][u % R] += dsl[st][u / R] * sv[u];
+          }
+        }
+      }
     }
-  }
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    acc[r] += __shfl_xor(acc[r], 1);
-    acc[r] += __shfl_xor(acc[r], 2);
-    acc[r] += __shfl_xor(acc[r], 4);
-  }
-  if (live && sub == 0) {
-    const int64_t i = perm[q];
+    for (int o = 0; o < C::OPG; ++o) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) out[i * ldi + r * ldr] = coef * acc[r];
+      for (int r = 0; r < R; ++r) {
+        T v = acc[o][r];
+#pragma unroll
+        for (int off = 1; off < C::LPO; off <<= 1) v += __shfl_xor(v, off);
+        acc[o][r] = v;
+      }
+      if (sub == 0 && o < npass) {
+        const int64_t i = perm[qb + pass0 + o];
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[i * ldi + r * ldr] = coef * acc[o][r];
+      }
+    }
   }
 }
 
@@ -266,44 +378,49 @@ void launch_segsum(const int64_t *seg, const T *vs, int64_t nkeys, int R, T *out
 }
 
 template <class T, int R>
-static void stage1_r(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
-                     const int32_t *other, const T *vs, int64_t nkeys, T *S, hipStream_t s) {
-  constexpr int KB = (R >= 8) ? 8 : 16;
-  dim3 grid((unsigned)ceil_div(nkeys, KB), (unsigned)ceil_div(nrows, 64));
-  stage1_kernel<T, R, KB><<<grid, 256, 0, s>>>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S);
+static void stage1_r(const T *Fc, int64_t ldc, int64_t nother, const int32_t *rows, int64_t nrows,
+                     const int64_t *seg2, int noc, const int32_t *other, const T *vs, int64_t nkeys,
+                     T *S, int64_t ldS, hipStream_t s) {
+  typedef S1Cfg<T, R> C;
+  dim3 grid((unsigned)ceil_div(nkeys, C::KB), (unsigned)ceil_div(nrows, 64));
+  stage1_kernel<T, R><<<grid, 256, 0, s>>>(Fc, ldc, nother, rows, nrows, seg2, noc, other, vs, nkeys,
+                                           S, ldS);
 }
 
 template <class T>
-void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
-                   const int32_t *other, const T *vs, int64_t nkeys, int R, T *S, hipStream_t s) {
+void launch_stage1(const T *Fc, int64_t ldc, int64_t nother, const int32_t *rows, int64_t nrows,
+                   const int64_t *seg2, int noc, const int32_t *other, const T *vs, int64_t nkeys,
+                   int R, T *S, int64_t ldS, hipStream_t s) {
   if (nrows <= 0 || nkeys <= 0) return;
   switch (R) {
-    case 1: stage1_r<T, 1>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, s); break;
-    case 2: stage1_r<T, 2>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, s); break;
-    case 4: stage1_r<T, 4>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, s); break;
-    case 8: stage1_r<T, 8>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, s); break;
+    case 1: stage1_r<T, 1>(Fc, ldc, nother, rows, nrows, seg2, noc, other, vs, nkeys, S, ldS, s); break;
+    case 2: stage1_r<T, 2>(Fc, ldc, nother, rows, nrows, seg2, noc, other, vs, nkeys, S, ldS, s); break;
+    case 4: stage1_r<T, 4>(Fc, ldc, nother, rows, nrows, seg2, noc, other, vs, nkeys, S, ldS, s); break;
+    case 8: stage1_r<T, 8>(Fc, ldc, nother, rows, nrows, seg2, noc, other, vs, nkeys, S, ldS, s); break;
     default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in stage 1"};
   }
 }
 
 template <class T>
 void launch_colscale(const T *F, int64_t ldf, const int32_t *rows, int64_t nrows, const T *sv,
-                     int64_t nkeys, int R, T *S, hipStream_t s) {
+                     int64_t nkeys, int R, T *S, int64_t ldS, hipStream_t s) {
   if (nrows * nkeys <= 0) return;
-  colscale_kernel<T><<<grid1(nrows * nkeys, 256), 256, 0, s>>>(F, ldf, rows, nrows, sv, nkeys, R, S);
+  colscale_kernel<T><<<grid1(nrows * nkeys, 256), 256, 0, s>>>(F, ldf, rows, nrows, sv, nkeys, R, S, ldS);
 }
 
 template <class T>
-void launch_stage2(const T *F1, int64_t ld1, const int32_t *xs, const int32_t *yrows,
-                   const int32_t *perm, int64_t nq, const T *S, int64_t nkeys, int R, T coef, T *out,
+void launch_stage2(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff, const int32_t *tiley,
+                   const int32_t *tilemax, int64_t ntiles, int nyb, const int32_t *yrows,
+                   const int32_t *perm, const T *S, int64_t ldS, int64_t nkeys, int R, T coef, T *out,
                    int64_t ldi, int64_t ldr, hipStream_t s) {
-  if (nq <= 0) return;
-  dim3 grid = grid1(nq * 8, 256);
+  if (ntiles <= 0) return;
+  dim3 grid((unsigned)ntiles);
+  const int nt = S2Cfg<T, 1>::NT;
   switch (R) {
-    case 1: stage2_kernel<T, 1><<<grid, 256, 0, s>>>(F1, ld1, xs, yrows, perm, nq, S, nkeys, coef, out, ldi, ldr); break;
-    case 2: stage2_kernel<T, 2><<<grid, 256, 0, s>>>(F1, ld1, xs, yrows, perm, nq, S, nkeys, coef, out, ldi, ldr); break;
-    case 4: stage2_kernel<T, 4><<<grid, 256, 0, s>>>(F1, ld1, xs, yrows, perm, nq, S, nkeys, coef, out, ldi, ldr); break;
-    case 8: stage2_kernel<T, 8><<<grid, 256, 0, s>>>(F1, ld1, xs, yrows, perm, nq, S, nkeys, coef, out, ldi, ldr); break;
+    case 1: stage2_kernel<T, 1><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr); break;
+    case 2: stage2_kernel<T, 2><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr); break;
+    case 4: stage2_kernel<T, 4><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr); break;
+    case 8: stage2_kernel<T, 8><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr); break;
     default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in stage 2"};
   }
 }
@@ -356,13 +473,15 @@ void launch_fill(T *U, int64_t rows, int64_t cols, int64_t ld, T val, hipStream_
   template void launch_pack_v<T>(const T *, int64_t, const int32_t *, int64_t, int, T *,          \
                                  hipStream_t);                                                   \
   template void launch_segsum<T>(const int64_t *, const T *, int64_t, int, T *, hipStream_t);    \
-  template void launch_stage1<T>(const T *, int64_t, const int32_t *, int64_t, const int64_t *,  \
-                                 const int32_t *, const T *, int64_t, int, T *, hipStream_t);    \
+  template void launch_stage1<T>(const T *, int64_t, int64_t, const int32_t *, int64_t,         \
+                                 const int64_t *, int, const int32_t *, const T *, int64_t, int, \
+                                 T *, int64_t, hipStream_t);                                     \
   template void launch_colscale<T>(const T *, int64_t, const int32_t *, int64_t, const T *,      \
-                                   int64_t, int, T *, hipStream_t);                              \
-  template void launch_stage2<T>(const T *, int64_t, const int32_t *, const int32_t *,           \
-                                 const int32_t *, int64_t, const T *, int64_t, int, T, T *,      \
-                                 int64_t, int64_t, hipStream_t);                                 \
+                                   int64_t, int, T *, int64_t, hipStream_t);                     \
+  template void launch_stage2<T>(const T *, int64_t, int64_t, const int64_t *, const int32_t *,  \
+                                 const int32_t *, int64_t, int, const int32_t *, const int32_t *,\
+                                 const T *, int64_t, int64_t, int, T, T *, int64_t, int64_t,     \
+                                 hipStream_t);                                                   \
   template void launch_gemv<T>(const T *, int64_t, int64_t, int64_t, bool, const T *, int, T *,  \
                                hipStream_t);                                                     \
   template void launch_gather_rows<T>(const T *, const int32_t *, int64_t, int, T *,             \

@@ -6,6 +6,12 @@
 namespace gvt {
 
 constexpr int kMaxCombineTerms = 16;
+// Stage-1 pairs are sorted by other index inside each key segment; seg2 marks
+// the boundaries of each (key, kStage1Chunk-wide other-index chunk).
+constexpr int kStage1Chunk = 128;
+// Stage-2 tiles: kStage2Rows consecutive F1 rows x at most kStage2MaxS S rows.
+constexpr int kStage2Rows = 32;
+constexpr int kStage2MaxS = 64;
 constexpr int kMaxCombineOut = 8;
 
 template <class T> struct CombineArgs {
@@ -21,14 +27,16 @@ void launch_pack_v(const T *V, int64_t ldv, const int32_t *perm, int64_t n, int 
 template <class T>
 void launch_segsum(const int64_t *seg, const T *vs, int64_t nkeys, int R, T *out, hipStream_t s);
 template <class T>
-void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
-                   const int32_t *other, const T *vs, int64_t nkeys, int R, T *S, hipStream_t s);
+void launch_stage1(const T *Fc, int64_t ldc, int64_t nother, const int32_t *rows, int64_t nrows,
+                   const int64_t *seg2, int noc, const int32_t *other, const T *vs, int64_t nkeys,
+                   int R, T *S, int64_t ldS, hipStream_t s);
 template <class T>
 void launch_colscale(const T *F, int64_t ldf, const int32_t *rows, int64_t nrows, const T *sv,
-                     int64_t nkeys, int R, T *S, hipStream_t s);
+                     int64_t nkeys, int R, T *S, int64_t ldS, hipStream_t s);
 template <class T>
-void launch_stage2(const T *F1, int64_t ld1, const int32_t *xs, const int32_t *yrows,
-                   const int32_t *perm, int64_t nq, const T *S, int64_t nkeys, int R, T coef, T *out,
+void launch_stage2(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff, const int32_t *tiley,
+                   const int32_t *tilemax, int64_t ntiles, int nyb, const int32_t *yrows,
+                   const int32_t *perm, const T *S, int64_t ldS, int64_t nkeys, int R, T coef, T *out,
                    int64_t ldi, int64_t ldr, hipStream_t s);
 template <class T>
 void launch_gemv(const T *F, int64_t ldf, int64_t nrows, int64_t ncols, bool sq, const T *sv, int R,

@@ -13,12 +13,15 @@ enum Sel { SA = 0, SB = 1, SC = 2, SE = 3 };
 // Base matrices.
 enum Mat { FD = 0, FT = 1 };
 
-struct InputSort {  // input pairs sorted (stably) by one index: key segments
+struct InputSort {  // input pairs sorted by one index (key segments), then by the other
   bool built = false;
   int64_t nkeys = 0;
+  int64_t nother = 0;  // range of the other index
+  int noc = 0;         // number of kStage1Chunk-wide other-index chunks
   DevMem perm;   // int32[n_in]: sorted position -> input index j
   DevMem other;  // int32[n_in]: the other index of the pair at that position
   DevMem seg;    // int64[nkeys + 1]: segment offsets
+  DevMem seg2;   // int64[nkeys * (noc + 1)]: start of each (key, chunk) sub-segment
 };
 
 struct OutOrder {  // output pairs grouped by one output-side index
@@ -42,7 +45,14 @@ struct TermSpec {
   int type = TG;
   // G (two-factor Kronecker term):  u_i = sum_k F_dot[x_i, k] S[y_i, k]
   int fdot = FD, x = SA, y = SB, sbuf = -1;
-  DevMem yrows;  // int32[n_out] in OutOrder[x] order: compact S row of y_i
+  // outputs ordered by (x block, S-row block, x, S row); tiles numbered
+  // x_block * nyb + y_block
+  DevMem g_perm, g_yrows;  // int32[n_out] per position
+  DevMem g_tileoff;        // int64[ntiles * (kStage2Rows + 1)]: start of each x row in a tile
+  DevMem g_tiley;          // int32[2 * ntiles]: first S row and S-row count of the tile
+  DevMem g_tilemax;        // int32[ntiles]: largest per-row output count in the tile
+  int64_t ntiles = 0;
+  int nyb = 0;
   // O (one-factor term):  u_i = g[x_i], g = F^{o(1|2)} segsum_key
   int gemv = -1;
   // M (Cartesian sparse match):  u_i = sum_{j: key_j = outkey_i} F[x_i, other_j] v_j
@@ -84,9 +94,13 @@ struct gvt_plan {
   hipStream_t last_stream = nullptr;
   // Theorem 1 cost of the chosen term program (FMA count per RHS), for reporting
   double cost_fma = 0.0;
+  // optional stage timing: events recorded at stage-group boundaries
+  hipEvent_t *prof = nullptr;  // [kStages][2] start/stop, or null
 };
 
 namespace gvt {
+// stage groups reported by gvt_plan_profile
+enum Stage { ST_PREP = 0, ST_STAGE1 = 1, ST_STAGE2 = 2, ST_OTHER = 3, kStages = 4 };
 int64_t rows_of(const gvt_plan *P, int f);
 int64_t cols_of(const gvt_plan *P, int f);
 int64_t nkeys_of(const gvt_plan *P, int key);
@@ -95,4 +109,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
                 const int32_t *c, const int32_t *e, int64_t n_in, int flags, hipStream_t s);
 void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,
                   const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu, hipStream_t s);
+void plan_profile(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,
+                  const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu, int reps,
+                  double *stage_ms, hipStream_t s);
 }  // namespace gvt

@@ -242,29 +242,34 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   auto need_insort = [&](int key) {
     InputSort &is = P->insort[key == SC ? 0 : 1];
     if (is.built) return;
+    const int okey = key == SC ? SE : SC;
     is.nkeys = nkeys_of(P, key);
-    std::vector<int32_t> perm;
-    std::vector<int64_t> seg;
-    counting_sort(h[key], is.nkeys, perm, seg);
+    is.nother = nkeys_of(P, okey);
+    is.noc = (int)ceil_div(std::max<int64_t>(is.nother, 1), kStage1Chunk);
+    // sort by other index first, then stably by key: segments ordered by other inside
+    std::vector<int32_t> perm_o, perm;
+    std::vector<int64_t> seg_o, seg;
+    counting_sort(h[okey], is.nother, perm_o, seg_o);
+    std::vector<int32_t> key_o(n_in);
+    for (int64_t p = 0; p < n_in; ++p) key_o[p] = h[key][perm_o[p]];
+    counting_sort(key_o, is.nkeys, perm, seg);
+    for (int64_t p = 0; p < n_in; ++p) perm[p] = perm_o[perm[p]];
     std::vector<int32_t> oth(n_in);
-    const std::vector<int32_t> &ov = h[key == SC ? SE : SC];
-    for (int64_t p = 0; p < n_in; ++p) oth[p] = ov[perm[p]];
+    for (int64_t p = 0; p < n_in; ++p) oth[p] = h[okey][perm[p]];
+    std::vector<int64_t> seg2((size_t)is.nkeys * (is.noc + 1));
+    for (int64_t k = 0; k < is.nkeys; ++k) {
+      int64_t p = seg[k];
+      for (int c = 0; c <= is.noc; ++c) {
+        const int64_t lim = (int64_t)c * kStage1Chunk;
+        while (p < seg[k + 1] && oth[p] < lim) ++p;
+        seg2[(size_t)k * (is.noc + 1) + c] = (c == is.noc) ? seg[k + 1] : p;
+      }
+    }
     upload(is.perm, perm, s);
     upload(is.other, oth, s);
     upload(is.seg, seg, s);
+    upload(is.seg2, seg2, s);
     is.built = true;
-  };
-  auto need_outord = [&](int x) {
-    OutOrder &oo = P->outord[x == SA ? 0 : 1];
-    if (oo.built) return;
-    const int64_t nk = (x == SA) ? d_rows : t_rows;
-    std::vector<int64_t> seg;
-    counting_sort(h[x], nk, oo.h_perm, seg);
-    std::vector<int32_t> xs(n_out);
-    for (int64_t q = 0; q < n_out; ++q) xs[q] = h[x][oo.h_perm[q]];
-    upload(oo.perm, oo.h_perm, s);
-    upload(oo.xs, xs, s);
-    oo.built = true;
   };
 
   // S buffers in creation order
@@ -299,12 +304,60 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     if (t.type == TG) {
       ts.fdot = t.a0; ts.x = t.a2; ts.y = t.a3;
       ts.sbuf = sbuf_index.at({t.a1, t.a4, t.a5});
-      need_outord(ts.x);
-      const OutOrder &oo = P->outord[ts.x == SA ? 0 : 1];
       const SBufSpec &sb = P->sbufs[ts.sbuf];
-      std::vector<int32_t> yr(n_out);
-      for (int64_t q = 0; q < n_out; ++q) yr[q] = sb.rowmap[h[ts.y][oo.h_perm[q]]];
-      upload(ts.yrows, yr, s);
+      // 2-D tiles: x blocks of kStage2Rows rows x S-row blocks; the number of
+      // S-row blocks is a multiple of 8 so that each XCD keeps one slice of S
+      const int64_t nsr = std::max<int64_t>((int64_t)sb.rows.size(), 1);
+      const int64_t nxr = std::max<int64_t>((ts.x == SA) ? d_rows : t_rows, 1);
+      const int64_t nyb = 8 * ceil_div(nsr, 8 * (int64_t)kStage2MaxS);
+      const int64_t ybs = ceil_div(nsr, nyb);
+      const int64_t nxb = ceil_div(nxr, kStage2Rows);
+      std::vector<int32_t> yrow_of(n_out), tkey(n_out), rowkey(n_out);
+      for (int64_t i = 0; i < n_out; ++i) {
+        yrow_of[i] = sb.rowmap[h[ts.y][i]];
+        const int64_t xv = h[ts.x][i];
+        tkey[i] = (int32_t)((xv / kStage2Rows) * nyb + yrow_of[i] / ybs);
+      }
+      // stable counting sorts, least significant key first: S row, x, tile
+      std::vector<int32_t> pa, pb, pc, key2(n_out);
+      std::vector<int64_t> sga, sgb, sgc;
+      counting_sort(yrow_of, nsr, pa, sga);
+      for (int64_t q = 0; q < n_out; ++q) key2[q] = h[ts.x][pa[q]];
+      counting_sort(key2, nxr, pb, sgb);
+      for (int64_t q = 0; q < n_out; ++q) pb[q] = pa[pb[q]];
+      const int64_t ntiles = nxb * nyb;
+      for (int64_t q = 0; q < n_out; ++q) key2[q] = tkey[pb[q]];
+      counting_sort(key2, ntiles, pc, sgc);
+      std::vector<int32_t> gperm(n_out), gy(n_out);
+      for (int64_t q = 0; q < n_out; ++q) {
+        const int32_t i = pb[pc[q]];
+        gperm[q] = i;
+        gy[q] = yrow_of[i];
+      }
+      std::vector<int64_t> toff((size_t)ntiles * (kStage2Rows + 1));
+      std::vector<int32_t> tiley((size_t)2 * ntiles), tmax(ntiles, 0);
+      for (int64_t tt = 0; tt < ntiles; ++tt) {
+        const int64_t xb = tt / nyb, yb = tt % nyb;
+        tiley[2 * tt] = (int32_t)std::min<int64_t>(yb * ybs, nsr);
+        tiley[2 * tt + 1] = (int32_t)std::max<int64_t>(0, std::min<int64_t>(ybs, nsr - yb * ybs));
+        int64_t q = sgc[tt];
+        for (int g = 0; g <= kStage2Rows; ++g) {
+          const int64_t xlim = xb * kStage2Rows + g;
+          while (q < sgc[tt + 1] && h[ts.x][gperm[q]] < xlim) ++q;
+          toff[(size_t)tt * (kStage2Rows + 1) + g] = (g == kStage2Rows) ? sgc[tt + 1] : q;
+        }
+        for (int g = 0; g < kStage2Rows; ++g) {
+          const int64_t c = toff[(size_t)tt * (kStage2Rows + 1) + g + 1] - toff[(size_t)tt * (kStage2Rows + 1) + g];
+          tmax[tt] = std::max<int32_t>(tmax[tt], (int32_t)c);
+        }
+      }
+      ts.ntiles = ntiles;
+      ts.nyb = (int)nyb;
+      upload(ts.g_perm, gperm, s);
+      upload(ts.g_yrows, gy, s);
+      upload(ts.g_tileoff, toff, s);
+      upload(ts.g_tiley, tiley, s);
+      upload(ts.g_tilemax, tmax, s);
       P->cost_fma += g_cost(t);
     } else if (t.type == TO) {
       auto gk = std::make_tuple(t.a0, t.a1, t.a3);
@@ -348,6 +401,11 @@ namespace {
 
 template <class T> int prec_slot() { return sizeof(T) == 8 ? 0 : 1; }
 
+// Row stride of a stage-1 buffer: keys x RHS, padded to 16-byte rows.
+int64_t sbuf_ld(const gvt_plan *P, int i, int R) {
+  return (nkeys_of(P, P->sbufs[i].key) * R + 3) / 4 * 4;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <class T> void layout_workspace(gvt_plan *P, int R) {
@@ -374,7 +432,7 @@ template <class T> void layout_workspace(gvt_plan *P, int R) {
   }
   W.sbuf.assign(P->sbufs.size(), -1);
   for (size_t i = 0; i < P->sbufs.size(); ++i)
-    W.sbuf[i] = take(P->sbufs[i].rows.size() * (size_t)nkeys_of(P, P->sbufs[i].key) * R);
+    W.sbuf[i] = take(P->sbufs[i].rows.size() * (size_t)sbuf_ld(P, (int)i, R) + 4);
   W.gemv.assign(P->gemvs.size(), -1);
   for (size_t i = 0; i < P->gemvs.size(); ++i) W.gemv[i] = take((size_t)rows_of(P, P->gemvs[i].f) * R);
   W.tvec.assign(P->terms.size(), -1);
@@ -390,6 +448,10 @@ template <class T> T *wsp(gvt_plan *P, int64_t off) {
                  : reinterpret_cast<T *>(static_cast<char *>(P->ws[prec_slot<T>()].pool.p) + off);
 }
 
+inline void mark(gvt_plan *P, int stage, int edge, hipStream_t s) {
+  if (P->prof) GVT_HIP_CHECK(hipEventRecord(P->prof[stage * 2 + edge], s));
+}
+
 template <class T>
 void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ldt, const T *V,
                    int R, int64_t ldv, T *U, int64_t ldu, int64_t block_stride, hipStream_t s) {
@@ -401,6 +463,7 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
                                P->idx[2].as<int32_t>(), P->idx[3].as<int32_t>()};
 
   // input vector in key order, and segment sums where one-factor / degenerate terms need them
+  mark(P, ST_PREP, 0, s);
   bool need_sv[2] = {false, false};
   for (const GemvSpec &g : P->gemvs) need_sv[g.key == SC ? 0 : 1] = true;
   for (const SBufSpec &sb : P->sbufs)
@@ -419,16 +482,19 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
     launch_gemv<T>(F[g.f], ldF[g.f], rows_of(P, g.f), nkeys_of(P, g.key), g.sq != 0,
                    wsp<T>(P, W.sv[ks]), R, wsp<T>(P, W.gemv[i]), s);
   }
+  mark(P, ST_PREP, 1, s);
   // stage 1 (shared scatters)
+  mark(P, ST_STAGE1, 0, s);
   bool transposed[2] = {false, false};
   for (size_t i = 0; i < P->sbufs.size(); ++i) {
     const SBufSpec &sb = P->sbufs[i];
     const int ks = sb.key == SC ? 0 : 1;
     const InputSort &is = P->insort[ks];
     T *S = wsp<T>(P, W.sbuf[i]);
+    const int64_t ldS = sbuf_ld(P, (int)i, R);
     if (sb.degenerate) {
       launch_colscale<T>(F[sb.fsc], ldF[sb.fsc], sb.d_rows.as<int32_t>(), (int64_t)sb.rows.size(),
-                         wsp<T>(P, W.sv[ks]), is.nkeys, R, S, s);
+                         wsp<T>(P, W.sv[ks]), is.nkeys, R, S, ldS, s);
       continue;
     }
     const T *Fc;
@@ -446,21 +512,32 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
       Fc = Ft;
       ldc = rows_of(P, sb.fsc);
     }
-    launch_stage1<T>(Fc, ldc, sb.d_rows.as<int32_t>(), (int64_t)sb.rows.size(),
-                     is.seg.as<int64_t>(), is.other.as<int32_t>(), wsp<T>(P, W.vs[ks]), is.nkeys,
-                     R, S, s);
+    launch_stage1<T>(Fc, ldc, is.nother, sb.d_rows.as<int32_t>(), (int64_t)sb.rows.size(),
+                     is.seg2.as<int64_t>(), is.noc, is.other.as<int32_t>(), wsp<T>(P, W.vs[ks]),
+                     is.nkeys, R, S, ldS, s);
   }
-  // terms
+  mark(P, ST_STAGE1, 1, s);
+  // two-factor terms: stage 2
+  mark(P, ST_STAGE2, 0, s);
   for (size_t ti = 0; ti < P->terms.size(); ++ti) {
     const TermSpec &t = P->terms[ti];
     if (t.type == TG) {
       const SBufSpec &sb = P->sbufs[t.sbuf];
-      const OutOrder &oo = P->outord[t.x == SA ? 0 : 1];
       T *out = P->direct ? U : wsp<T>(P, W.tvec[ti]);
       const int64_t ldi = P->direct ? 1 : R, ldr = P->direct ? ldu : 1;
-      launch_stage2<T>(F[t.fdot], ldF[t.fdot], oo.xs.as<int32_t>(), t.yrows.as<int32_t>(),
-                       oo.perm.as<int32_t>(), P->n_out, wsp<T>(P, W.sbuf[t.sbuf]),
-                       nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s);
+      launch_stage2<T>(F[t.fdot], ldF[t.fdot], rows_of(P, t.fdot), t.g_tileoff.as<int64_t>(),
+                       t.g_tiley.as<int32_t>(), t.g_tilemax.as<int32_t>(), t.ntiles, t.nyb,
+                       t.g_yrows.as<int32_t>(), t.g_perm.as<int32_t>(), wsp<T>(P, W.sbuf[t.sbuf]),
+                       sbuf_ld(P, t.sbuf, R), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s);
+    }
+  }
+  mark(P, ST_STAGE2, 1, s);
+  // one-factor and match terms, then the per-kind combination
+  mark(P, ST_OTHER, 0, s);
+  for (size_t ti = 0; ti < P->terms.size(); ++ti) {
+    const TermSpec &t = P->terms[ti];
+    if (t.type == TG) {
+      continue;
     } else if (t.type == TO) {
       launch_gather_rows<T>(wsp<T>(P, W.gemv[t.gemv]), dev_sel[t.x], P->n_out, R,
                             wsp<T>(P, W.tvec[ti]), s);
@@ -481,6 +558,7 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
       for (auto &tc : P->outputs[o]) ca.coef[o][tc.first] = (T)tc.second;
     launch_combine<T>(ca, P->n_out, R, U, ldu, block_stride, s);
   }
+  mark(P, ST_OTHER, 1, s);
 }
 
 template <class T>
@@ -506,6 +584,7 @@ void execute_t(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ldt, c
 void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,
                   const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu, hipStream_t s) {
   GVT_REQUIRE(P, GVT_ERR_ARG, "null plan");
+  GVT_REQUIRE(!P->prof || nrhs <= 8, GVT_ERR_ARG, "stage profile covers one RHS block (nrhs <= 8)");
   GVT_REQUIRE(nrhs >= 1, GVT_ERR_ARG, "nrhs must be >= 1");
   GVT_REQUIRE(prec == GVT_F64 || prec == GVT_F32 || prec == GVT_BF16X3 || prec == GVT_BF16X6, GVT_ERR_ARG, "unknown precision");
   GVT_REQUIRE(ldu >= P->n_out && ldv >= P->n_in, GVT_ERR_ARG, "ldv < n_in or ldu < n_out");
@@ -536,6 +615,35 @@ void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void 
     execute_t<float>(P, (const float *)D, ldd, (const float *)T, ldt, (const float *)V, nrhs, ldv,
                      (float *)U, ldu, s);
   check_launch(s);
+}
+
+void plan_profile(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,
+                  const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu, int reps,
+                  double *stage_ms, hipStream_t s) {
+  GVT_REQUIRE(P && stage_ms && reps >= 1, GVT_ERR_ARG, "bad profile arguments");
+  GVT_REQUIRE(!P->dense, GVT_ERR_UNSUPPORTED, "stage profile is for the gather path");
+  std::vector<hipEvent_t> ev(2 * kStages);
+  for (auto &e : ev) GVT_HIP_CHECK(hipEventCreate(&e));
+  for (int k = 0; k < kStages; ++k) stage_ms[k] = 0.0;
+  struct Cleanup {
+    gvt_plan *P;
+    std::vector<hipEvent_t> &ev;
+    ~Cleanup() {
+      P->prof = nullptr;
+      for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+  } cleanup{P, ev};
+  P->prof = ev.data();
+  for (int r = 0; r < reps; ++r) {
+    plan_execute(P, prec, D, ldd, T, ldt, V, nrhs, ldv, U, ldu, s);
+    GVT_HIP_CHECK(hipStreamSynchronize(s));
+    for (int k = 0; k < kStages; ++k) {
+      float ms = 0.f;
+      GVT_HIP_CHECK(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+      stage_ms[k] += ms;
+    }
+  }
+  for (int k = 0; k < kStages; ++k) stage_ms[k] /= reps;
 }
 
 }  // namespace gvt

