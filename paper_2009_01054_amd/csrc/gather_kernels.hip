@@ -48,28 +48,27 @@ __global__ void segsum_kernel(const int64_t *__restrict__ seg, const T *__restri
 
 // ---------------------------------------------------------------------------
 // Stage 1 (segmented scatter-reduce).  Fc holds F2 column-accessible:
-// F2[y, o] = Fc[o*ldc + y].  Block = 4 waves over 64 S rows (one per lane)
-// and KB keys (KPW per wave).  The other-index range is swept in tiles of
-// OCT: the tile Fc[o-tile][64 rows] sits in LDS (64 KB) and every input
-// pair of the block's keys whose other index falls in the tile reads its
-// factor from there.  Pairs are sorted by other index inside each key
-// segment, and seg2 gives the boundaries of each (key, 128-wide chunk).
-// Segment data (other index, packed v) are wave-uniform scalar loads; the
-// partial sums stay in registers across tiles; the [64 x KB*R] result is
-// staged through LDS and written row-contiguously.
+// F2[y, o] = Fc[o*ldc + y].  Block = 4 waves over 64 S rows (one per lane);
+// each wave owns KPW consecutive keys and walks each key's segment: the
+// pair's other index and packed v value are wave-uniform scalar loads, the
+// column load is coalesced over the 64 rows, and the loop is unrolled so
+// that several column loads are in flight.  Pairs inside a segment are
+// ordered by other index, which keeps consecutive column loads close in the
+// cache.  The [64 x KB*R] result tile is staged in LDS and written
+// row-contiguously.
 template <class T, int R> struct S1Cfg {
-  static constexpr int OCT = sizeof(T) == 8 ? 128 : 256;  // tile: OCT x 64 elements = 64 KB
-  static constexpr int KPW = (16 / R) > 2 ? 16 / R : 2;     // keys per wave
-  static constexpr int KB = 4 * KPW;                        // keys per block
+  static constexpr int KPW = 4;        // keys per wave
+  static constexpr int KB = 4 * KPW;   // keys per block
 };
 
 template <class T, int R>
 __global__ __launch_bounds__(256) void stage1_kernel(
-    const T *__restrict__ Fc, int64_t ldc, int64_t nother, const int32_t *__restrict__ rows,
-    int64_t nrows, const int64_t *__restrict__ seg2, int noc, const int32_t *__restrict__ other,
-    const T *__restrict__ vs, int64_t nkeys, T *__restrict__ S, int64_t ldS) {
+    const T *__restrict__ Fc, int64_t ldc, const int32_t *__restrict__ rows, int64_t nrows,
+    const int64_t *__restrict__ seg, const int32_t *__restrict__ other, const T *__restrict__ vs,
+    int64_t nkeys, T *__restrict__ S, int64_t ldS) {
   typedef S1Cfg<T, R> C;
-  __shared__ __attribute__((aligned(16))) T tile[C::OCT * 64];
+  constexpr int W = C::KB * R;
+  __shared__ T stg[64 * (W + 1)];
   const int lane = threadIdx.x & 63;
   const int w = wave_id_uniform();
   const int64_t k0 = (int64_t)blockIdx.x * C::KB;
@@ -77,47 +76,25 @@ __global__ __launch_bounds__(256) void stage1_kernel(
   const int64_t rho = rho0 + lane;
   const bool live = rho < nrows;
   const int64_t y = live ? rows[rho] : 0;
-  constexpr int CPT = C::OCT / kStage1Chunk;  // plan chunks per tile
-  T acc[C::KPW][R];
+#pragma unroll 1
+  for (int kk = 0; kk < C::KPW; ++kk) {
+    const int64_t k = k0 + w * C::KPW + kk;
+    T acc[R];
 #pragma unroll
-  for (int kk = 0; kk < C::KPW; ++kk)
+    for (int r = 0; r < R; ++r) acc[r] = T(0);
+    if (k < nkeys) {
+      const int64_t p0 = seg[k], p1 = seg[k + 1];
+      const T *fy = Fc + y;
+#pragma unroll 8
+      for (int64_t p = p0; p < p1; ++p) {
+        const T f = fy[(int64_t)other[p] * ldc];
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[kk][r] = T(0);
-  const int ntile = (int)ceil_div_dev(nother, C::OCT);
-  for (int ot = 0; ot < ntile; ++ot) {
-    __syncthreads();
-    const int64_t obase = (int64_t)ot * C::OCT;
-    for (int oo = w; oo < C::OCT; oo += 4) {
-      const int64_t o = obase + oo;
-      tile[oo * 64 + lane] = (live && o < nother) ? Fc[o * ldc + y] : T(0);
-    }
-    __syncthreads();
-    const int c0 = ot * CPT;
-    const int c1 = (c0 + CPT) < noc ? (c0 + CPT) : noc;
-#pragma unroll
-    for (int kk = 0; kk < C::KPW; ++kk) {
-      const int64_t k = k0 + w * C::KPW + kk;
-      if (k < nkeys) {
-        const int64_t *sk = seg2 + k * (noc + 1);
-        const int64_t p0 = sk[c0], p1 = sk[c1];
-#pragma unroll 4
-        for (int64_t p = p0; p < p1; ++p) {
-          const int o = (int)(other[p] - obase);
-          const T f = tile[o * 64 + lane];
-#pragma unroll
-          for (int r = 0; r < R; ++r) acc[kk][r] += f * vs[p * R + r];
-        }
+        for (int r = 0; r < R; ++r) acc[r] += f * vs[p * R + r];
       }
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) stg[lane * (W + 1) + (w * C::KPW + kk) * R + r] = acc[r];
   }
-  // stage the [64 rows x KB*R] block through LDS for row-contiguous stores
-  constexpr int W = C::KB * R;
-  __syncthreads();
-  T *stg = tile;  // 64 x (W + 1) <= OCT * 64
-#pragma unroll
-  for (int kk = 0; kk < C::KPW; ++kk)
-#pragma unroll
-    for (int r = 0; r < R; ++r) stg[lane * (W + 1) + (w * C::KPW + kk) * R + r] = acc[kk][r];
   __syncthreads();
   const int64_t kcount = (nkeys - k0) < C::KB ? (nkeys - k0) : C::KB;
   const int width = (int)kcount * R;
@@ -126,6 +103,14 @@ __global__ __launch_bounds__(256) void stage1_kernel(
     const int64_t orow = rho0 + rr;
     if (orow < nrows && cc < width) S[orow * ldS + k0 * R + cc] = stg[rr * (W + 1) + cc];
   }
+  // the last key block also clears the row padding (read by stage 2 as whole chunks)
+  if (k0 + C::KB >= nkeys) {
+    const int64_t padw = ldS - nkeys * R;
+    for (int64_t idx = threadIdx.x; idx < 64 * padw; idx += 256) {
+      const int64_t rr = idx / padw, cc = idx - rr * padw;
+      if (rho0 + rr < nrows) S[(rho0 + rr) * ldS + nkeys * R + cc] = T(0);
+    }
+  }
 }
 
 // Degenerate stage 1 (key == other index): S[rho, k] = F2[rows[rho], k] * s[k].
@@ -133,12 +118,18 @@ template <class T>
 __global__ void colscale_kernel(const T *__restrict__ F, int64_t ldf, const int32_t *__restrict__ rows,
                                 int64_t nrows, const T *__restrict__ s, int64_t nkeys, int R,
                                 T *__restrict__ S, int64_t ldS) {
+  // one thread per (row, padded key slot); slots past nkeys are zero padding
+  const int64_t kslots = ldS / R;
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t total = nrows * nkeys;
+  int64_t total = nrows * kslots;
   if (idx >= total) return;
-  int64_t rho = idx / nkeys, k = idx - rho * nkeys;
-  T f = F[(int64_t)rows[rho] * ldf + k];
-  for (int r = 0; r < R; ++r) S[rho * ldS + k * R + r] = f * s[k * R + r];
+  int64_t rho = idx / kslots, k = idx - rho * kslots;
+  if (k < nkeys) {
+    T f = F[(int64_t)rows[rho] * ldf + k];
+    for (int r = 0; r < R; ++r) S[rho * ldS + k * R + r] = f * s[k * R + r];
+  } else {
+    for (int r = 0; r < R; ++r) S[rho * ldS + k * R + r] = T(0);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -153,6 +144,10 @@ __global__ void colscale_kernel(const T *__restrict__ F, int64_t ldf, const int3
 // its outputs, reading the S rows from a shared LDS tile (one 1 KB chunk per
 // S row).  Partial sums stay in registers across chunks and meet in a fixed
 // butterfly at the end, so the result is deterministic.
+template <class T> struct Vec16;  // 16-byte vector of T
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+
 template <class T, int R> struct S2Cfg {
   static constexpr int LPO = 16;                   // lanes per F1 row / output
   static constexpr int NG = kStage2Rows;           // groups = F1 rows per tile (32)
@@ -176,7 +171,9 @@ __global__ __launch_bounds__(512) void stage2_kernel(
     const T *__restrict__ S, int64_t ldS, int64_t nkeys, T coef, T *__restrict__ out, int64_t ldi,
     int64_t ldr) {
   typedef S2Cfg<T, R> C;
+  typedef typename Vec16<T>::type V16;
   constexpr int TROW = C::ROWE + C::PADE;
+  constexpr int V16ROW = C::ROWE / C::VEC;  // 16-byte words per tile row (64)
   __shared__ __attribute__((aligned(16))) T tile[kStage2MaxS * TROW];
   __shared__ unsigned char meta[C::NG][C::OPG];
   const int t = blockIdx.x;
@@ -189,6 +186,7 @@ __global__ __launch_bounds__(512) void stage2_kernel(
   const int64_t qb = tileoff[(int64_t)t * (C::NG + 1) + grp];
   const int cnt = (int)(tileoff[(int64_t)t * (C::NG + 1) + grp + 1] - qb);
   const T *frow = F1 + (x < nx ? x : 0) * ld1;
+  const int64_t nch = (nkeys + C::KC - 1) / C::KC;
   for (int pass0 = 0; pass0 < maxcnt; pass0 += C::OPG) {
     const int npass = (cnt - pass0) < C::OPG ? (cnt - pass0) : C::OPG;  // may be <= 0
     __syncthreads();
@@ -199,26 +197,16 @@ __global__ __launch_bounds__(512) void stage2_kernel(
     for (int o = 0; o < C::OPG; ++o)
 #pragma unroll
       for (int r = 0; r < R; ++r) acc[o][r] = T(0);
-    for (int64_t k0 = 0; k0 < nkeys; k0 += C::KC) {
+    for (int64_t c = 0; c < nch; ++c) {
       __syncthreads();
-      const int64_t ecnt = ((nkeys - k0) < C::KC ? (nkeys - k0) : C::KC) * R;
-      for (int idx = threadIdx.x; idx < nyr * (C::ROWE / C::VEC); idx += C::NT) {
-        const int row = idx / (C::ROWE / C::VEC);
-        const int cc = (idx - row * (C::ROWE / C::VEC)) * C::VEC;
-        const T *src = S + (y0 + row) * ldS + k0 * R + cc;
-        T v[C::VEC];
-        if (cc + C::VEC <= ecnt) {
-#pragma unroll
-          for (int u = 0; u < C::VEC; ++u) v[u] = src[u];
-        } else {
-#pragma unroll
-          for (int u = 0; u < C::VEC; ++u) v[u] = (cc + u < ecnt) ? src[u] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < C::VEC; ++u) tile[row * TROW + cc + u] = v[u];
+      // S rows are padded with zeros to whole chunks: every row copy is a full 1 KB
+      for (int idx = threadIdx.x; idx < nyr * V16ROW; idx += C::NT) {
+        const int row = idx / V16ROW, cw = idx - row * V16ROW;
+        const V16 v = *reinterpret_cast<const V16 *>(S + (y0 + row) * ldS + c * C::ROWE + cw * C::VEC);
+        *reinterpret_cast<V16 *>(tile + row * TROW + cw * C::VEC) = v;
       }
-      // this group's F1 row slice for the chunk
       T dsl[C::STEPS][C::KPL];
+      const int64_t k0 = c * C::KC;
 #pragma unroll
       for (int st = 0; st < C::STEPS; ++st)
 #pragma unroll
@@ -231,14 +219,18 @@ __global__ __launch_bounds__(512) void stage2_kernel(
       for (int o = 0; o < C::OPG; ++o) {
         if (o < npass) {
           const T *trow = tile + (int)meta[grp][o] * TROW + sub * C::EPL;
+          // all reads of this output first (distinct registers), then the FMAs
+          V16 sv[C::STEPS][C::EPL / C::VEC];
 #pragma unroll
-          for (int st = 0; st < C::STEPS; ++st) {
-            T sv[C::EPL];
+          for (int st = 0; st < C::STEPS; ++st)
 #pragma unroll
-            for (int u = 0; u < C::EPL; ++u) sv[u] = trow[st * C::LPO * C::EPL + u];
+            for (int u0 = 0; u0 < C::EPL / C::VEC; ++u0)
+              sv[st][u0] = *reinterpret_cast<const V16 *>(trow + st * C::LPO * C::EPL + u0 * C::VEC);
 #pragma unroll
-            for (int u = 0; u < C::EPL; ++u) acc[o][u % R] += dsl[st][u / R] * sv[u];
-          }
+          for (int st = 0; st < C::STEPS; ++st)
+#pragma unroll
+            for (int u = 0; u < C::EPL; ++u)
+              acc[o][u % R] += dsl[st][u / R] * sv[st][u / C::VEC][u % C::VEC];
         }
       }
     }
@@ -378,25 +370,24 @@ void launch_segsum(const int64_t *seg, const T *vs, int64_t nkeys, int R, T *out
 }
 
 template <class T, int R>
-static void stage1_r(const T *Fc, int64_t ldc, int64_t nother, const int32_t *rows, int64_t nrows,
-                     const int64_t *seg2, int noc, const int32_t *other, const T *vs, int64_t nkeys,
-                     T *S, int64_t ldS, hipStream_t s) {
+static void stage1_r(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
+                     const int32_t *other, const T *vs, int64_t nkeys, T *S, int64_t ldS,
+                     hipStream_t s) {
   typedef S1Cfg<T, R> C;
   dim3 grid((unsigned)ceil_div(nkeys, C::KB), (unsigned)ceil_div(nrows, 64));
-  stage1_kernel<T, R><<<grid, 256, 0, s>>>(Fc, ldc, nother, rows, nrows, seg2, noc, other, vs, nkeys,
-                                           S, ldS);
+  stage1_kernel<T, R><<<grid, 256, 0, s>>>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS);
 }
 
 template <class T>
-void launch_stage1(const T *Fc, int64_t ldc, int64_t nother, const int32_t *rows, int64_t nrows,
-                   const int64_t *seg2, int noc, const int32_t *other, const T *vs, int64_t nkeys,
-                   int R, T *S, int64_t ldS, hipStream_t s) {
+void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
+                   const int32_t *other, const T *vs, int64_t nkeys, int R, T *S, int64_t ldS,
+                   hipStream_t s) {
   if (nrows <= 0 || nkeys <= 0) return;
   switch (R) {
-    case 1: stage1_r<T, 1>(Fc, ldc, nother, rows, nrows, seg2, noc, other, vs, nkeys, S, ldS, s); break;
-    case 2: stage1_r<T, 2>(Fc, ldc, nother, rows, nrows, seg2, noc, other, vs, nkeys, S, ldS, s); break;
-    case 4: stage1_r<T, 4>(Fc, ldc, nother, rows, nrows, seg2, noc, other, vs, nkeys, S, ldS, s); break;
-    case 8: stage1_r<T, 8>(Fc, ldc, nother, rows, nrows, seg2, noc, other, vs, nkeys, S, ldS, s); break;
+    case 1: stage1_r<T, 1>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
+    case 2: stage1_r<T, 2>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
+    case 4: stage1_r<T, 4>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
+    case 8: stage1_r<T, 8>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
     default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in stage 1"};
   }
 }
@@ -405,7 +396,8 @@ template <class T>
 void launch_colscale(const T *F, int64_t ldf, const int32_t *rows, int64_t nrows, const T *sv,
                      int64_t nkeys, int R, T *S, int64_t ldS, hipStream_t s) {
   if (nrows * nkeys <= 0) return;
-  colscale_kernel<T><<<grid1(nrows * nkeys, 256), 256, 0, s>>>(F, ldf, rows, nrows, sv, nkeys, R, S, ldS);
+  colscale_kernel<T><<<grid1(nrows * (ldS / R), 256), 256, 0, s>>>(F, ldf, rows, nrows, sv, nkeys, R, S,
+                                                                   ldS);
 }
 
 template <class T>
@@ -473,9 +465,9 @@ void launch_fill(T *U, int64_t rows, int64_t cols, int64_t ld, T val, hipStream_
   template void launch_pack_v<T>(const T *, int64_t, const int32_t *, int64_t, int, T *,          \
                                  hipStream_t);                                                   \
   template void launch_segsum<T>(const int64_t *, const T *, int64_t, int, T *, hipStream_t);    \
-  template void launch_stage1<T>(const T *, int64_t, int64_t, const int32_t *, int64_t,         \
-                                 const int64_t *, int, const int32_t *, const T *, int64_t, int, \
-                                 T *, int64_t, hipStream_t);                                     \
+  template void launch_stage1<T>(const T *, int64_t, const int32_t *, int64_t, const int64_t *,  \
+                                 const int32_t *, const T *, int64_t, int, T *, int64_t,         \
+                                 hipStream_t);                                                   \
   template void launch_colscale<T>(const T *, int64_t, const int32_t *, int64_t, const T *,      \
                                    int64_t, int, T *, int64_t, hipStream_t);                     \
   template void launch_stage2<T>(const T *, int64_t, int64_t, const int64_t *, const int32_t *,  \

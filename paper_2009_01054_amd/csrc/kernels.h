@@ -27,9 +27,9 @@ void launch_pack_v(const T *V, int64_t ldv, const int32_t *perm, int64_t n, int 
 template <class T>
 void launch_segsum(const int64_t *seg, const T *vs, int64_t nkeys, int R, T *out, hipStream_t s);
 template <class T>
-void launch_stage1(const T *Fc, int64_t ldc, int64_t nother, const int32_t *rows, int64_t nrows,
-                   const int64_t *seg2, int noc, const int32_t *other, const T *vs, int64_t nkeys,
-                   int R, T *S, int64_t ldS, hipStream_t s);
+void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
+                   const int32_t *other, const T *vs, int64_t nkeys, int R, T *S, int64_t ldS,
+                   hipStream_t s);
 template <class T>
 void launch_colscale(const T *F, int64_t ldf, const int32_t *rows, int64_t nrows, const T *sv,
                      int64_t nkeys, int R, T *S, int64_t ldS, hipStream_t s);

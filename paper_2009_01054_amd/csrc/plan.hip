@@ -401,9 +401,11 @@ namespace {
 
 template <class T> int prec_slot() { return sizeof(T) == 8 ? 0 : 1; }
 
-// Row stride of a stage-1 buffer: keys x RHS, padded to 16-byte rows.
-int64_t sbuf_ld(const gvt_plan *P, int i, int R) {
-  return (nkeys_of(P, P->sbufs[i].key) * R + 3) / 4 * 4;
+// Row stride of a stage-1 buffer in elements: keys x RHS padded to whole
+// 1 KB chunks (stage 2 copies rows chunk by chunk).  The padding is zero.
+template <class T> int64_t sbuf_ld(const gvt_plan *P, int i, int R) {
+  const int64_t chunk = 1024 / (int64_t)sizeof(T);
+  return ceil_div(nkeys_of(P, P->sbufs[i].key) * R, chunk) * chunk;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -432,7 +434,7 @@ template <class T> void layout_workspace(gvt_plan *P, int R) {
   }
   W.sbuf.assign(P->sbufs.size(), -1);
   for (size_t i = 0; i < P->sbufs.size(); ++i)
-    W.sbuf[i] = take(P->sbufs[i].rows.size() * (size_t)sbuf_ld(P, (int)i, R) + 4);
+    W.sbuf[i] = take(P->sbufs[i].rows.size() * (size_t)sbuf_ld<T>(P, (int)i, R));
   W.gemv.assign(P->gemvs.size(), -1);
   for (size_t i = 0; i < P->gemvs.size(); ++i) W.gemv[i] = take((size_t)rows_of(P, P->gemvs[i].f) * R);
   W.tvec.assign(P->terms.size(), -1);
@@ -491,7 +493,7 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
     const int ks = sb.key == SC ? 0 : 1;
     const InputSort &is = P->insort[ks];
     T *S = wsp<T>(P, W.sbuf[i]);
-    const int64_t ldS = sbuf_ld(P, (int)i, R);
+    const int64_t ldS = sbuf_ld<T>(P, (int)i, R);
     if (sb.degenerate) {
       launch_colscale<T>(F[sb.fsc], ldF[sb.fsc], sb.d_rows.as<int32_t>(), (int64_t)sb.rows.size(),
                          wsp<T>(P, W.sv[ks]), is.nkeys, R, S, ldS, s);
@@ -512,9 +514,9 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
       Fc = Ft;
       ldc = rows_of(P, sb.fsc);
     }
-    launch_stage1<T>(Fc, ldc, is.nother, sb.d_rows.as<int32_t>(), (int64_t)sb.rows.size(),
-                     is.seg2.as<int64_t>(), is.noc, is.other.as<int32_t>(), wsp<T>(P, W.vs[ks]),
-                     is.nkeys, R, S, ldS, s);
+    launch_stage1<T>(Fc, ldc, sb.d_rows.as<int32_t>(), (int64_t)sb.rows.size(),
+                     is.seg.as<int64_t>(), is.other.as<int32_t>(), wsp<T>(P, W.vs[ks]), is.nkeys, R,
+                     S, ldS, s);
   }
   mark(P, ST_STAGE1, 1, s);
   // two-factor terms: stage 2
@@ -528,7 +530,7 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
       launch_stage2<T>(F[t.fdot], ldF[t.fdot], rows_of(P, t.fdot), t.g_tileoff.as<int64_t>(),
                        t.g_tiley.as<int32_t>(), t.g_tilemax.as<int32_t>(), t.ntiles, t.nyb,
                        t.g_yrows.as<int32_t>(), t.g_perm.as<int32_t>(), wsp<T>(P, W.sbuf[t.sbuf]),
-                       sbuf_ld(P, t.sbuf, R), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s);
+                       sbuf_ld<T>(P, t.sbuf, R), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s);
     }
   }
   mark(P, ST_STAGE2, 1, s);
