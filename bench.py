@@ -98,6 +98,125 @@ def cpu_baseline(p, seconds):
     }
 
 
+def _relerr(got, ref):
+    import numpy as np
+
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def _event_ms(torch, fn, reps):
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def preset_kronecker_latency(args, gvt, W, torch, np, dev):
+    """64 x 64 Kronecker product, n = 2000 pairs (launch/latency bound)."""
+    import oracle
+
+    p = W.config1()
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    D, T, v = t(p["D"]), t(p["T"]), t(p["v"])
+    a, b, c, e = (t(p[k].astype(np.int32)) for k in "abce")
+    plan = gvt.gvt_plan_create("kronecker", D.shape, T.shape, (a, b), (c, e), flags=gvt.FLAG_SYMMETRIC_BASES)
+    out = torch.empty((1, 1, len(p["a"])), dtype=D.dtype, device=dev)
+    ms_exec = _event_ms(torch, lambda: plan.execute(D, T, v, out=out), 200)
+    t0 = time.perf_counter()
+    for _ in range(20):
+        u = gvt.gvt_matvec(D, T, (a, b), (c, e), v)
+    ms_oneshot = (time.perf_counter() - t0) / 20 * 1e3
+    ref = oracle.pairwise_matvec("kronecker", p["D"], p["T"], (p["a"], p["b"]), (p["c"], p["e"]), p["v"])
+    plan.close()
+    return {"config": "Kronecker GVT FP64, m=q=64, n=2000 (outputs = training pairs)",
+            "plan_execute_us": round(ms_exec * 1e3, 2), "oneshot_matvec_us": round(ms_oneshot * 1e3, 1),
+            "matvecs_per_s": round(1e3 / ms_exec, 1), "rel_err_vs_oracle": _relerr(u.cpu().numpy(), ref)}
+
+
+def preset_fused_kinds(args, gvt, W, torch, np, dev):
+    """Symmetric + anti-symmetric + Cartesian + Poly2D on 1M unordered pairs of 5000 objects."""
+    import oracle
+
+    kinds = ["symmetric", "antisymmetric", "cartesian", "poly2d"]
+    t_gen = time.perf_counter()
+    p = W.config3()
+    log(f"[bench] inputs generated in {time.perf_counter() - t_gen:.1f} s")
+    c, e = (torch.from_numpy(p[k]).to(dev) for k in "ce")
+    D64 = torch.from_numpy(p["D"]).to(dev)
+    v64 = torch.from_numpy(p["v"]).to(dev)
+    res = {"config": "fused sym+anti+cartesian+poly2d, homogeneous m=5000 linear kernel (128-dim), "
+                     "n=1M unordered pairs, outputs = training pairs"}
+    t0 = time.perf_counter()
+    plan = gvt.gvt_plan_create(kinds, D64.shape, D64.shape, (c, e), (c, e), flags=gvt.FLAG_SYMMETRIC_BASES)
+    res["plan_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    res["plan_info"] = gvt.gvt_plan_info(plan)
+    rng = np.random.default_rng(3)
+    rows = rng.choice(len(p["c"]), 512, replace=False)
+    refs = [oracle.pairwise_matvec(kind, p["D"], None, (p["c"], p["e"]), (p["c"], p["e"]), p["v"], rows=rows)
+            for kind in kinds]
+    for name, D, v in [("f32", D64.float(), v64.float()), ("f64", D64, v64)]:
+        out = torch.empty((4, 1, len(p["c"])), dtype=D.dtype, device=dev)
+        ms = _event_ms(torch, lambda: plan.execute(D, D, v, out=out), 5)
+        stage = gvt.gvt_plan_profile(plan, D, D, v, reps=3)
+        errs = {}
+        for k, kind in enumerate(kinds):
+            errs[kind] = _relerr(out[k, 0, rows].double().cpu().numpy(), refs[k])
+        # the same four kinds as four separate plans (no shared stage 1)
+        sep = []
+        for kind in kinds:
+            pl = gvt.gvt_plan_create([kind], D64.shape, D64.shape, (c, e), (c, e), flags=gvt.FLAG_SYMMETRIC_BASES)
+            o1 = torch.empty((1, 1, len(p["c"])), dtype=D.dtype, device=dev)
+            sep.append(_event_ms(torch, lambda: pl.execute(D, D, v, out=o1), 3))
+            pl.close()
+        res[name] = {"fused_ms": round(ms, 4), "stage_ms": [round(x, 4) for x in stage],
+                     "separate_plans_ms": round(sum(sep), 4), "per_kind_ms": [round(x, 4) for x in sep],
+                     "fusion_speedup": round(sum(sep) / ms, 3), "rel_err_sampled_512_rows": errs,
+                     "theorem1_tflops": round(2 * res["plan_info"]["cost_fma"] / (ms * 1e-3) / 1e12, 3)}
+        log(f"[bench] {name}: fused {ms:.3f} ms, separate {sum(sep):.3f} ms, stages {stage}, errs {errs}")
+    plan.close()
+    return res
+
+
+def preset_dense(args, gvt, W, torch, np, dev):
+    """Complete data: Umat = M Vmat N^T, m = 8192, q = 4096 (two MFMA GEMMs)."""
+    t_gen = time.perf_counter()
+    p = W.config4()
+    log(f"[bench] inputs generated in {time.perf_counter() - t_gen:.1f} s")
+    m, q = p["m"], p["q"]
+    flops = 2.0 * (m * m * q + m * q * q)
+    rng = np.random.default_rng(4)
+    rows = rng.choice(m, 64, replace=False)
+    # reference rows by host FP64 BLAS: U[i, :] = (D[i, :] V) T^T
+    ref = (p["D"][rows] @ p["V"]) @ p["T"].T
+    res = {"config": "complete-data dense product, m=8192 drugs, q=4096 targets, Gaussian bases (32-dim)",
+           "flops_per_product": flops}
+    peaks = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
+    for name, prec, dt in [("f64", gvt.F64, torch.float64), ("f32", gvt.F32, torch.float32),
+                           ("bf16x3", gvt.BF16X3, torch.float32), ("bf16x6", gvt.BF16X6, torch.float32)]:
+        D = torch.from_numpy(p["D"]).to(dev, dt)
+        T = torch.from_numpy(p["T"]).to(dev, dt)
+        V = torch.from_numpy(p["V"]).to(dev, dt)
+        U = torch.empty((m, q), dtype=dt, device=dev)
+        ms = _event_ms(torch, lambda: gvt.gvt_dense_matvec(D, T, V, prec=prec, out=U), 3)
+        err = _relerr(U[rows].double().cpu().numpy(), ref)
+        mult = {"bf16x3": 3, "bf16x6": 6}.get(name, 1)
+        achieved = flops / (ms * 1e-3) / 1e12
+        res[name] = {"ms": round(ms, 4), "tflops_effective": round(achieved, 2),
+                     "mfma_frac": round(achieved * mult / peaks[name], 4),
+                     "rel_err_sampled_64_rows": err}
+        log(f"[bench] dense {name}: {ms:.3f} ms, {achieved:.1f} TFLOP/s effective, err {err:.2e}")
+        del D, T, V, U
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +227,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=20)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4],
+                    help="workload preset: 2 = ridge CG (the headline line); 1 = 64x64 Kronecker "
+                         "product latency; 3 = fused four-kind product on 1M unordered pairs; "
+                         "4 = complete-data dense product (8192 x 4096)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -124,6 +247,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     gvt.load_library()
     dev = torch.device("cuda:0")
+    if args.config != 2:
+        fn = {1: preset_kronecker_latency, 3: preset_fused_kinds, 4: preset_dense}[args.config]
+        print(json.dumps(fn(args, gvt, W, torch, np, dev)), flush=True)
+        return
     t_gen = time.perf_counter()
     p = W.config2()
     log(f"[bench] inputs generated in {time.perf_counter() - t_gen:.1f} s")

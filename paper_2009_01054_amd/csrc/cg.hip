@@ -18,6 +18,7 @@ namespace gvt {
 
 static constexpr int RB = 256;   // reduction block size
 static constexpr int RNB = 240;  // reduction grid (fixed for determinism)
+static_assert(RNB <= RB, "partials are folded by one block");
 
 enum CgState { CG_DONE = 0, CG_ACTIVE = 1, CG_PENDING = 2, CG_BREAKDOWN = 3, CG_MAXITER = 4 };
 
@@ -54,10 +55,10 @@ __global__ __launch_bounds__(RB) void dot_partial_kernel(const double *__restric
   }
 }
 
-__device__ __forceinline__ double fold_partials(const double *partial, int nlam, int l) {
-  double s = 0.0;
-  for (int b = 0; b < RNB; ++b) s += partial[b * nlam + l];
-  return s;
+// Fixed-tree fold of the RNB block partials of system l by one 256-thread block.
+__device__ __forceinline__ double fold_partials(const double *partial, int nlam, int l, double *sh) {
+  const double v = threadIdx.x < RNB ? partial[threadIdx.x * nlam + l] : 0.0;
+  return block_sum(v, sh);
 }
 
 // w = K p (+ FP32 product cast) + lambda p ; partial dot p.w
@@ -84,10 +85,14 @@ __global__ __launch_bounds__(RB) void cg_pw_kernel(const TW *__restrict__ wraw, 
   }
 }
 
-__global__ void cg_alpha_kernel(CgScalars *sc, const double *__restrict__ partial, int nlam) {
-  const int l = threadIdx.x;
-  if (l >= nlam || sc[l].state != CG_ACTIVE) return;
-  const double pw = fold_partials(partial, nlam, l);
+// one block per system
+__global__ __launch_bounds__(RB) void cg_alpha_kernel(CgScalars *sc, const double *__restrict__ partial,
+                                                      int nlam) {
+  __shared__ double sh[RB];
+  const int l = blockIdx.x;
+  if (sc[l].state != CG_ACTIVE) return;  // uniform per block
+  const double pw = fold_partials(partial, nlam, l, sh);
+  if (threadIdx.x != 0) return;
   sc[l].pw = pw;
   if (!(pw > 0.0) || !isfinite(pw)) {
     sc[l].state = CG_BREAKDOWN;
@@ -120,11 +125,13 @@ __global__ __launch_bounds__(RB) void cg_update_kernel(double *__restrict__ a, i
   }
 }
 
-__global__ void cg_beta_kernel(CgScalars *sc, const double *__restrict__ partial, int nlam,
-                               double tol, int max_iter, int lowprec) {
-  const int l = threadIdx.x;
-  if (l >= nlam || sc[l].state != CG_ACTIVE) return;
-  const double rho_new = fold_partials(partial, nlam, l);
+__global__ __launch_bounds__(RB) void cg_beta_kernel(CgScalars *sc, const double *__restrict__ partial,
+                                                     int nlam, double tol, int max_iter, int lowprec) {
+  __shared__ double sh[RB];
+  const int l = blockIdx.x;
+  if (sc[l].state != CG_ACTIVE) return;  // uniform per block
+  const double rho_new = fold_partials(partial, nlam, l, sh);
+  if (threadIdx.x != 0) return;
   sc[l].iters += 1;
   if (!isfinite(rho_new)) {
     sc[l].state = CG_BREAKDOWN;
@@ -169,10 +176,13 @@ __global__ __launch_bounds__(RB) void residual_kernel(const double *__restrict__
   }
 }
 
-// fold partials into out[l] (one thread per system)
-__global__ void fold_kernel(const double *__restrict__ partial, int nlam, double *__restrict__ out) {
-  const int l = threadIdx.x;
-  if (l < nlam) out[l] = fold_partials(partial, nlam, l);
+// fold partials into out[l] (one block per system)
+__global__ __launch_bounds__(RB) void fold_kernel(const double *__restrict__ partial, int nlam,
+                                                  double *__restrict__ out) {
+  __shared__ double sh[RB];
+  const int l = blockIdx.x;
+  const double v = fold_partials(partial, nlam, l, sh);
+  if (threadIdx.x == 0) out[l] = v;
 }
 
 __global__ void copy_cols_kernel(const double *__restrict__ src, int64_t lds, double *__restrict__ dst,
@@ -277,7 +287,7 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
 
   // ||y||
   dot_partial_kernel<<<RNB, RB, 0, s>>>(y, 0, y, 0, n, 1, part);
-  fold_kernel<<<1, 64, 0, s>>>(part, 1, tmp);
+  fold_kernel<<<1, RB, 0, s>>>(part, 1, tmp);
   double ynorm2 = 0.0;
   GVT_HIP_CHECK(hipMemcpyAsync(&ynorm2, tmp, 8, hipMemcpyDeviceToHost, s));
   GVT_HIP_CHECK(hipStreamSynchronize(s));
@@ -301,7 +311,7 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
     bcast_col_kernel<<<g1(n), 256, 0, s>>>(y, r, n, n, nlam);
     dot_partial_kernel<<<RNB, RB, 0, s>>>(r, n, r, n, n, nlam, part);
   }
-  fold_kernel<<<1, 64, 0, s>>>(part, nlam, tmp);
+  fold_kernel<<<nlam, RB, 0, s>>>(part, nlam, tmp);
   std::vector<double> rho0(nlam);
   GVT_HIP_CHECK(hipMemcpyAsync(rho0.data(), tmp, nlam * 8, hipMemcpyDeviceToHost, s));
   copy_cols_kernel<<<g1(n), 256, 0, s>>>(r, n, p, n, n, nlam, -1, nullptr);
@@ -324,9 +334,9 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
       matvec64(p, wraw);
       cg_pw_kernel<double><<<RNB, RB, 0, s>>>(wraw, w, p, lam, n, nlam, sc, part);
     }
-    cg_alpha_kernel<<<1, 64, 0, s>>>(sc, part, nlam);
+    cg_alpha_kernel<<<nlam, RB, 0, s>>>(sc, part, nlam);
     cg_update_kernel<<<RNB, RB, 0, s>>>(A, lda, r, p, w, n, nlam, sc, part);
-    cg_beta_kernel<<<1, 64, 0, s>>>(sc, part, nlam, tol, max_iter, lowprec);
+    cg_beta_kernel<<<nlam, RB, 0, s>>>(sc, part, nlam, tol, max_iter, lowprec);
     cg_p_kernel<<<g1(n), 256, 0, s>>>(p, r, n, nlam, sc);
   };
 
@@ -350,7 +360,7 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
       copy_cols_kernel<<<g1(n), 256, 0, s>>>(A, lda, w, n, n, nlam, -1, nullptr);
       matvec64(w, wraw);
       residual_kernel<<<RNB, RB, 0, s>>>(y, wraw, A, lda, lam, n, nlam, w, part);
-      fold_kernel<<<1, 64, 0, s>>>(part, nlam, tmp);
+      fold_kernel<<<nlam, RB, 0, s>>>(part, nlam, tmp);
       std::vector<double> rt(nlam);
       GVT_HIP_CHECK(hipMemcpyAsync(rt.data(), tmp, nlam * 8, hipMemcpyDeviceToHost, s));
       GVT_HIP_CHECK(hipStreamSynchronize(s));
@@ -411,7 +421,7 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
   copy_cols_kernel<<<g1(n), 256, 0, s>>>(A, lda, w, n, n, nlam, -1, nullptr);
   matvec64(w, wraw);
   residual_kernel<<<RNB, RB, 0, s>>>(y, wraw, A, lda, lam, n, nlam, r, part);
-  fold_kernel<<<1, 64, 0, s>>>(part, nlam, tmp);
+  fold_kernel<<<nlam, RB, 0, s>>>(part, nlam, tmp);
   std::vector<double> rt(nlam);
   GVT_HIP_CHECK(hipMemcpyAsync(rt.data(), tmp, nlam * 8, hipMemcpyDeviceToHost, s));
   GVT_HIP_CHECK(hipMemcpyAsync(hs.data(), sc, sizeof(CgScalars) * nlam, hipMemcpyDeviceToHost, s));

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -56,19 +57,31 @@ template <class F> int guarded(F &&body) {
 struct DevMem {
   void *p = nullptr;
   size_t bytes = 0;
+  bool owned = true;  // false: a view into memory owned elsewhere
   DevMem() = default;
   DevMem(const DevMem &) = delete;
   DevMem &operator=(const DevMem &) = delete;
-  DevMem(DevMem &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevMem(DevMem &&o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned) { o.p = nullptr; o.bytes = 0; }
   DevMem &operator=(DevMem &&o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; owned = o.owned;
+      o.p = nullptr; o.bytes = 0;
+    }
     return *this;
   }
   ~DevMem() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    owned = true;
+  }
+  void view(void *ptr, size_t nbytes) {
+    release();
+    p = ptr;
+    bytes = nbytes;
+    owned = false;
   }
   // Grow-only; contents are not preserved.
   void *ensure(size_t nbytes) {
@@ -86,11 +99,31 @@ struct DevMem {
   template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
-// Blocking copy: plan data comes from short-lived host vectors.
-template <class T> void upload(DevMem &m, const std::vector<T> &h, hipStream_t) {
-  m.ensure(h.size() * sizeof(T));
-  if (!h.empty()) GVT_HIP_CHECK(hipMemcpy(m.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
-}
+// Host-to-device staging for plan data: arrays are collected on the host and
+// copied in one transfer into one device allocation (commit), each DevMem
+// becoming a view into it.
+struct Uploads {
+  std::vector<std::pair<DevMem *, std::vector<char>>> items;
+  template <class T> void add(DevMem &m, const std::vector<T> &h) {
+    std::vector<char> b(h.size() * sizeof(T));
+    if (!h.empty()) std::memcpy(b.data(), h.data(), b.size());
+    items.emplace_back(&m, std::move(b));
+  }
+  void commit(DevMem &blob) {
+    size_t total = 0;
+    for (auto &it : items) total += (it.second.size() + 255) & ~size_t(255);
+    blob.ensure(total ? total : 256);
+    std::vector<char> host(total);
+    size_t off = 0;
+    for (auto &it : items) {
+      if (!it.second.empty()) std::memcpy(host.data() + off, it.second.data(), it.second.size());
+      it.first->view(static_cast<char *>(blob.p) + off, it.second.size());
+      off += (it.second.size() + 255) & ~size_t(255);
+    }
+    if (total) GVT_HIP_CHECK(hipMemcpy(blob.p, host.data(), total, hipMemcpyHostToDevice));
+    items.clear();
+  }
+};
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -253,16 +253,19 @@ __global__ __launch_bounds__(256) void gemm_bf16s_kernel(const float *__restrict
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        f4 c = acc[i][j];
+        // The correction products of this k-step are summed from zero, then
+        // added to the running hi*hi sum with one FP32 add: accumulating them
+        // straight into the large running sum loses their low bits.
+        f4 c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[0][j], f4{0.f, 0.f, 0.f, 0.f},
+                                                       0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[1][j], c, 0, 0, 0);
         if (NS == 3) {
           c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[1][j], c, 0, 0, 0);
           c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[2][i], bfr[0][j], c, 0, 0, 0);
           c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[2][j], c, 0, 0, 0);
         }
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1][i], bfr[0][j], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[1][j], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], c, 0, 0, 0);
-        acc[i][j] = c;
+        f4 h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], acc[i][j], 0, 0, 0);
+        acc[i][j] = h + c;
       }
     __syncthreads();
   }

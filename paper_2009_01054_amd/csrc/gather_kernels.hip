@@ -286,22 +286,34 @@ __global__ void gather_rows_kernel(const T *__restrict__ g, const int32_t *__res
 }
 
 // Cartesian sparse-match term: t[i] = sum_{p in seg(kv_i)} F[x_i, other_p] vs[p]
-// (kv_i >= nkeys: the object never occurs on the input side -> 0).
+// (kv_i >= nkeys: the object never occurs on the input side -> 0).  A
+// 16-lane group per output strides the key segment; the lanes' partial sums
+// meet in a fixed butterfly.
 template <class T>
-__global__ void match_kernel(const T *__restrict__ F, int64_t ldf, const int32_t *__restrict__ xsel,
-                             const int32_t *__restrict__ ksel, int64_t n, const int64_t *__restrict__ seg,
-                             const int32_t *__restrict__ other, const T *__restrict__ vs,
-                             int64_t nkeys, int R, T *__restrict__ t) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t kv = ksel[i];
-  const T *frow = F + (int64_t)xsel[i] * ldf;
+__global__ __launch_bounds__(256) void match_kernel(const T *__restrict__ F, int64_t ldf,
+                                                    const int32_t *__restrict__ xsel,
+                                                    const int32_t *__restrict__ ksel, int64_t n,
+                                                    const int64_t *__restrict__ seg,
+                                                    const int32_t *__restrict__ other,
+                                                    const T *__restrict__ vs, int64_t nkeys, int R,
+                                                    T *__restrict__ t) {
+  constexpr int G = 16;
+  const int sub = threadIdx.x % G;
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const bool live = i < n;
   int64_t p0 = 0, p1 = 0;
-  if (kv < nkeys) { p0 = seg[kv]; p1 = seg[kv + 1]; }
+  const T *frow = F;
+  if (live) {
+    const int64_t kv = ksel[i];
+    frow = F + (int64_t)xsel[i] * ldf;
+    if (kv < nkeys) { p0 = seg[kv]; p1 = seg[kv + 1]; }
+  }
   for (int r = 0; r < R; ++r) {
     T acc = T(0);
-    for (int64_t p = p0; p < p1; ++p) acc += frow[other[p]] * vs[p * R + r];
-    t[i * R + r] = acc;
+    for (int64_t p = p0 + sub; p < p1; p += G) acc += frow[other[p]] * vs[p * R + r];
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) acc += __shfl_xor(acc, off);
+    if (live && sub == 0) t[i * R + r] = acc;
   }
 }
 
@@ -437,7 +449,7 @@ void launch_match(const T *F, int64_t ldf, const int32_t *xsel, const int32_t *k
                   const int64_t *seg, const int32_t *other, const T *vs, int64_t nkeys, int R, T *t,
                   hipStream_t s) {
   if (n <= 0) return;
-  match_kernel<T><<<grid1(n, 256), 256, 0, s>>>(F, ldf, xsel, ksel, n, seg, other, vs, nkeys, R, t);
+  match_kernel<T><<<grid1(n * 16, 256), 256, 0, s>>>(F, ldf, xsel, ksel, n, seg, other, vs, nkeys, R, t);
 }
 
 template <class T>

@@ -6,9 +6,6 @@
 namespace gvt {
 
 constexpr int kMaxCombineTerms = 16;
-// Stage-1 pairs are sorted by other index inside each key segment; seg2 marks
-// the boundaries of each (key, kStage1Chunk-wide other-index chunk).
-constexpr int kStage1Chunk = 128;
 // Stage-2 tiles: kStage2Rows consecutive F1 rows x at most kStage2MaxS S rows.
 constexpr int kStage2Rows = 32;
 constexpr int kStage2MaxS = 64;

@@ -17,11 +17,9 @@ struct InputSort {  // input pairs sorted by one index (key segments), then by t
   bool built = false;
   int64_t nkeys = 0;
   int64_t nother = 0;  // range of the other index
-  int noc = 0;         // number of kStage1Chunk-wide other-index chunks
   DevMem perm;   // int32[n_in]: sorted position -> input index j
   DevMem other;  // int32[n_in]: the other index of the pair at that position
   DevMem seg;    // int64[nkeys + 1]: segment offsets
-  DevMem seg2;   // int64[nkeys * (noc + 1)]: start of each (key, chunk) sub-segment
 };
 
 struct OutOrder {  // output pairs grouped by one output-side index
@@ -82,7 +80,8 @@ struct gvt_plan {
   int flags = 0;
   int64_t d_rows = 0, d_cols = 0, t_rows = 0, t_cols = 0, n_out = 0, n_in = 0;
   std::array<int64_t, 4> uniq{{0, 0, 0, 0}};
-  gvt::DevMem idx[4];  // device copies of a, b, c, e (int32)
+  gvt::DevMem blob;    // one device allocation holding every index array below
+  gvt::DevMem idx[4];  // device copies of a, b, c, e (int32), when a term reads them
   gvt::InputSort insort[2];   // [0]: by c (other = e), [1]: by e (other = c)
   gvt::OutOrder outord[2];    // [0]: grouped by a, [1]: grouped by b
   std::vector<gvt::SBufSpec> sbufs;

@@ -15,9 +15,25 @@
 #include <map>
 #include <tuple>
 
+#include <chrono>
+#include <cstdlib>
+
 #include "plan.h"
 
 namespace gvt {
+
+// GVT_PLAN_TIMING=1 prints the host time of each plan phase to stderr.
+struct PhaseTimer {
+  bool on = std::getenv("GVT_PLAN_TIMING") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void lap(const char *what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "[gvt plan] %-24s %8.3f ms\n", what,
+                 std::chrono::duration<double, std::milli>(now - t).count());
+    t = now;
+  }
+};
 
 int64_t rows_of(const gvt_plan *P, int f) { return f == FD ? P->d_rows : P->t_rows; }
 int64_t cols_of(const gvt_plan *P, int f) { return f == FD ? P->d_cols : P->t_cols; }
@@ -132,6 +148,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   P->n_out = n_out; P->n_in = n_in;
   P->last_stream = s;
 
+  PhaseTimer tm;
   // ---- indices to host, validation, unique counts (Table 1) -------------
   std::vector<int32_t> h[4];
   const int32_t *src[4] = {a, b, c, e};
@@ -144,6 +161,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
                                    hipMemcpyDeviceToHost, s));
   }
   GVT_HIP_CHECK(hipStreamSynchronize(s));
+  tm.lap("indices to host");
   static const char *nm[4] = {"out_a", "out_b", "in_c", "in_e"};
   for (int i = 0; i < 4; ++i) {
     for (int64_t j = 0; j < cnt[i]; ++j) {
@@ -154,8 +172,9 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
                                        std::to_string(lim[i]) + ")"};
     }
     P->uniq[i] = count_unique(h[i], lim[i]);
-    upload(P->idx[i], h[i], s);
   }
+  tm.lap("validate + unique");
+  Uploads up;
 
   // ---- complete data: both pair sets are the full grid in natural order ----
   if (nkinds == 1 && P->kinds[0] == GVT_KRONECKER && n_in == d_cols * t_cols &&
@@ -245,7 +264,6 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     const int okey = key == SC ? SE : SC;
     is.nkeys = nkeys_of(P, key);
     is.nother = nkeys_of(P, okey);
-    is.noc = (int)ceil_div(std::max<int64_t>(is.nother, 1), kStage1Chunk);
     // sort by other index first, then stably by key: segments ordered by other inside
     std::vector<int32_t> perm_o, perm;
     std::vector<int64_t> seg_o, seg;
@@ -256,22 +274,13 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     for (int64_t p = 0; p < n_in; ++p) perm[p] = perm_o[perm[p]];
     std::vector<int32_t> oth(n_in);
     for (int64_t p = 0; p < n_in; ++p) oth[p] = h[okey][perm[p]];
-    std::vector<int64_t> seg2((size_t)is.nkeys * (is.noc + 1));
-    for (int64_t k = 0; k < is.nkeys; ++k) {
-      int64_t p = seg[k];
-      for (int c = 0; c <= is.noc; ++c) {
-        const int64_t lim = (int64_t)c * kStage1Chunk;
-        while (p < seg[k + 1] && oth[p] < lim) ++p;
-        seg2[(size_t)k * (is.noc + 1) + c] = (c == is.noc) ? seg[k + 1] : p;
-      }
-    }
-    upload(is.perm, perm, s);
-    upload(is.other, oth, s);
-    upload(is.seg, seg, s);
-    upload(is.seg2, seg2, s);
+    up.add(is.perm, perm);
+    up.add(is.other, oth);
+    up.add(is.seg, seg);
     is.built = true;
   };
 
+  tm.lap("term expansion");
   // S buffers in creation order
   P->sbufs.resize(sbuf_index.size());
   for (auto &kv : sbuf_index) {
@@ -290,11 +299,12 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     sb.rows.clear();
     for (int64_t r = 0; r < (int64_t)sb.rowmap.size(); ++r)
       if (sb.rowmap[r] >= 0) { sb.rowmap[r] = (int32_t)sb.rows.size(); sb.rows.push_back((int32_t)r); }
-    upload(sb.d_rows, sb.rows, s);
+    up.add(sb.d_rows, sb.rows);
     if (sb.degenerate) need_insort(sb.key);  // for its segment sums
     else need_insort(sb.key);
   }
 
+  tm.lap("input sorts + S rows");
   P->terms.resize(raw_terms.size());
   P->cost_fma = 0.0;
   for (size_t ti = 0; ti < raw_terms.size(); ++ti) {
@@ -312,52 +322,45 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       const int64_t nyb = 8 * ceil_div(nsr, 8 * (int64_t)kStage2MaxS);
       const int64_t ybs = ceil_div(nsr, nyb);
       const int64_t nxb = ceil_div(nxr, kStage2Rows);
-      std::vector<int32_t> yrow_of(n_out), tkey(n_out), rowkey(n_out);
+      // one stable counting sort on (tile, row inside the tile); the S-row order
+      // inside a row group does not matter
+      const int64_t ntiles = nxb * nyb;
+      std::vector<int32_t> yrow_of(n_out), tkey(n_out);
       for (int64_t i = 0; i < n_out; ++i) {
         yrow_of[i] = sb.rowmap[h[ts.y][i]];
         const int64_t xv = h[ts.x][i];
-        tkey[i] = (int32_t)((xv / kStage2Rows) * nyb + yrow_of[i] / ybs);
+        const int64_t tile_id = (xv / kStage2Rows) * nyb + yrow_of[i] / ybs;
+        tkey[i] = (int32_t)(tile_id * kStage2Rows + xv % kStage2Rows);
       }
-      // stable counting sorts, least significant key first: S row, x, tile
-      std::vector<int32_t> pa, pb, pc, key2(n_out);
-      std::vector<int64_t> sga, sgb, sgc;
-      counting_sort(yrow_of, nsr, pa, sga);
-      for (int64_t q = 0; q < n_out; ++q) key2[q] = h[ts.x][pa[q]];
-      counting_sort(key2, nxr, pb, sgb);
-      for (int64_t q = 0; q < n_out; ++q) pb[q] = pa[pb[q]];
-      const int64_t ntiles = nxb * nyb;
-      for (int64_t q = 0; q < n_out; ++q) key2[q] = tkey[pb[q]];
-      counting_sort(key2, ntiles, pc, sgc);
+      std::vector<int32_t> pc;
+      std::vector<int64_t> sgk;
+      counting_sort(tkey, ntiles * kStage2Rows, pc, sgk);
       std::vector<int32_t> gperm(n_out), gy(n_out);
       for (int64_t q = 0; q < n_out; ++q) {
-        const int32_t i = pb[pc[q]];
+        const int32_t i = pc[q];
         gperm[q] = i;
         gy[q] = yrow_of[i];
       }
       std::vector<int64_t> toff((size_t)ntiles * (kStage2Rows + 1));
       std::vector<int32_t> tiley((size_t)2 * ntiles), tmax(ntiles, 0);
       for (int64_t tt = 0; tt < ntiles; ++tt) {
-        const int64_t xb = tt / nyb, yb = tt % nyb;
+        const int64_t yb = tt % nyb;
         tiley[2 * tt] = (int32_t)std::min<int64_t>(yb * ybs, nsr);
         tiley[2 * tt + 1] = (int32_t)std::max<int64_t>(0, std::min<int64_t>(ybs, nsr - yb * ybs));
-        int64_t q = sgc[tt];
-        for (int g = 0; g <= kStage2Rows; ++g) {
-          const int64_t xlim = xb * kStage2Rows + g;
-          while (q < sgc[tt + 1] && h[ts.x][gperm[q]] < xlim) ++q;
-          toff[(size_t)tt * (kStage2Rows + 1) + g] = (g == kStage2Rows) ? sgc[tt + 1] : q;
-        }
+        for (int g = 0; g <= kStage2Rows; ++g)
+          toff[(size_t)tt * (kStage2Rows + 1) + g] = sgk[(size_t)tt * kStage2Rows + g];
         for (int g = 0; g < kStage2Rows; ++g) {
-          const int64_t c = toff[(size_t)tt * (kStage2Rows + 1) + g + 1] - toff[(size_t)tt * (kStage2Rows + 1) + g];
+          const int64_t c = sgk[(size_t)tt * kStage2Rows + g + 1] - sgk[(size_t)tt * kStage2Rows + g];
           tmax[tt] = std::max<int32_t>(tmax[tt], (int32_t)c);
         }
       }
       ts.ntiles = ntiles;
       ts.nyb = (int)nyb;
-      upload(ts.g_perm, gperm, s);
-      upload(ts.g_yrows, gy, s);
-      upload(ts.g_tileoff, toff, s);
-      upload(ts.g_tiley, tiley, s);
-      upload(ts.g_tilemax, tmax, s);
+      up.add(ts.g_perm, gperm);
+      up.add(ts.g_yrows, gy);
+      up.add(ts.g_tileoff, toff);
+      up.add(ts.g_tiley, tiley);
+      up.add(ts.g_tilemax, tmax);
       P->cost_fma += g_cost(t);
     } else if (t.type == TO) {
       auto gk = std::make_tuple(t.a0, t.a1, t.a3);
@@ -387,6 +390,13 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       P->cost_fma -= (key == other) ? selval_uniq(y) * (double)nkeys_of(P, key)
                                     : selval_uniq(y) * n_in_d;
     }
+  tm.lap("term orderings");
+  bool need_idx = false;
+  for (const TermSpec &t : P->terms) need_idx = need_idx || t.type != TG;
+  if (need_idx)
+    for (int i = 0; i < 4; ++i) up.add(P->idx[i], h[i]);
+  up.commit(P->blob);
+  tm.lap("upload");
   P->direct = nkinds == 1 && P->outputs[0].size() == 1 && P->outputs[0][0].second == 1.0 &&
               P->terms[P->outputs[0][0].first].type == TG;
   for (auto &o : P->outputs)

@@ -227,6 +227,28 @@ def test_dense_vs_oracle_and_gemm(gvt, prec, shape):
     assert relerr(U.ravel()[idxs], u_or) < (1e-10 if prec == "f64" else 1e-4)
 
 
+@pytest.mark.parametrize("shape", [(1024, 512), (2048, 1024)])
+def test_dense_split_bf16_error_does_not_grow(gvt, shape):
+    # Two chained GEMMs accumulate over m and then q terms. The 3-way split keeps ~24
+    # significant bits per operand, so its norm-wise error must stay at the FP32 level at
+    # sizes where the accumulation is long; the 2-way split stays within its 2^-16 bound.
+    m, q = shape
+    r = np.random.default_rng([19, m, q])
+    D = W.gaussian_kernel(r.standard_normal((m, 32)))
+    T = W.gaussian_kernel(r.standard_normal((q, 32)))
+    V = r.standard_normal((m, q))
+    ref = D @ V @ T.T
+    out = {}
+    for name, pc in [("f32", gvt.F32), ("bf16x3", gvt.BF16X3), ("bf16x6", gvt.BF16X6)]:
+        U = gvt.gvt_dense_matvec(dev(D, torch.float32), dev(T, torch.float32), dev(V, torch.float32),
+                                 prec=pc).cpu().double().numpy()
+        out[name] = np.linalg.norm(U - ref) / np.linalg.norm(ref)
+    assert out["f32"] < 1e-5
+    assert out["bf16x6"] < max(2 * out["f32"], 1e-6)
+    mag = np.abs(D) @ np.abs(V) @ np.abs(T).T
+    assert out["bf16x3"] * np.linalg.norm(ref) <= 4 * 2.0 ** -16 * np.linalg.norm(mag)
+
+
 def test_dense_autodetect_via_matvec(gvt):
     m, q = 40, 24
     r = np.random.default_rng(15)
