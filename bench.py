@@ -217,6 +217,31 @@ def preset_dense(args, gvt, W, torch, np, dev):
     return res
 
 
+def counter_workload(args, gvt, W, torch, np, dev):
+    """Short run for hardware-counter passes: three products of the ridge workload in
+    each precision and one elementwise copy of 512 MiB (256 MiB read, 256 MiB written),
+    the known-size kernel that calibrates FETCH_SIZE and WRITE_SIZE."""
+    p = W.config2()
+    D64 = torch.from_numpy(p["D"]).to(dev)
+    T64 = torch.from_numpy(p["T"]).to(dev)
+    c = torch.from_numpy(p["c"]).to(dev)
+    e = torch.from_numpy(p["e"]).to(dev)
+    plan = gvt.gvt_plan_create("kronecker", D64.shape, T64.shape, (c, e), (c, e), flags=gvt.FLAG_SYMMETRIC_BASES)
+    for D, T in [(D64, T64), (D64.float(), T64.float())]:
+        v = torch.randn(len(p["c"]), dtype=D.dtype, device=dev)
+        for _ in range(3):
+            plan.execute(D, T, v)
+        torch.cuda.synchronize()
+    plan.close()
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    return {"config": "counter passes: ridge workload products (f64, f32) and a 256 MiB elementwise copy",
+            "copy_read_bytes": nbytes, "copy_write_bytes": nbytes}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +252,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-reps", type=int, default=20)
+    ap.add_argument("--counters", action="store_true",
+                    help="run only the short kernel sequence that the hardware-counter passes read")
     ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4],
                     help="workload preset: 2 = ridge CG (the headline line); 1 = 64x64 Kronecker "
                          "product latency; 3 = fused four-kind product on 1M unordered pairs; "
@@ -247,6 +274,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     gvt.load_library()
     dev = torch.device("cuda:0")
+    if args.counters:
+        print(json.dumps(counter_workload(args, gvt, W, torch, np, dev)), flush=True)
+        return
     if args.config != 2:
         fn = {1: preset_kronecker_latency, 3: preset_fused_kinds, 4: preset_dense}[args.config]
         print(json.dumps(fn(args, gvt, W, torch, np, dev)), flush=True)
