@@ -205,6 +205,47 @@ int gvt_krr_cg(int kind, const double *D, int64_t d, int64_t ldd, const double *
                int64_t *iters_out, double *relres_out, void *stream);
 
 /*
+ * One ridge problem of a batch (all pointers DEVICE, double, as in
+ * gvt_krr_cg): base kernels D (d x d, ldd) and T (t x t, ldt; ignored for
+ * homogeneous kinds), the n training pairs c, e, labels y[n], solutions A
+ * (n x nlam, column stride lda >= n) and an optional initial guess A0 (same
+ * layout, stride lda0; NULL = zero).
+ */
+typedef struct gvt_krr_problem {
+  const double *D;
+  int64_t d, ldd;
+  const double *T;
+  int64_t t, ldt;
+  const int32_t *c, *e;
+  int64_t n;
+  const double *y;
+  double *A;
+  int64_t lda;
+  const double *A0;
+  int64_t lda0;
+} gvt_krr_problem;
+
+/*
+ * gvt_krr_cg_batched — many independent kernel ridge problems (Section 3
+ * eq. (1), each with its own base kernels, pairs and labels), every one
+ * solved for the same grid lambdas[nlam] (host), all advanced together:
+ * one set of CG vectors holds the nprob x nlam systems, the products of all
+ * problems run as grouped launches (one launch per stage of the generalized
+ * vec trick covers every problem), finished problems drop out of the
+ * launches, and blocks of check_every iterations replay from one HIP graph.
+ * kind, max_iter, tol, matvec_prec and check_every as in gvt_krr_cg.
+ * problems[nprob] (host array of descriptors).  iters_out and relres_out
+ * (host, nprob x nlam, problem-major: [p * nlam + l]) receive iteration
+ * counts and true relative residuals (FP64 products).  Synchronises
+ * `stream`.  Returns GVT_OK when every system met tol, GVT_NOT_CONVERGED
+ * when some hit max_iter, GVT_ERR_BREAKDOWN on breakdown, and the errors of
+ * gvt_krr_cg, with the problem's index in the message.
+ */
+int gvt_krr_cg_batched(int kind, const gvt_krr_problem *problems, int nprob, const double *lambdas,
+                       int nlam, int max_iter, double tol, int matvec_prec, int check_every,
+                       int64_t *iters_out, double *relres_out, void *stream);
+
+/*
  * gvt_plan_profile — diagnostic: runs gvt_plan_execute `reps` times
  * (synchronising `stream` after each) with HIP events recorded at the stage
  * boundaries of the generalized vec trick, and writes the mean milliseconds

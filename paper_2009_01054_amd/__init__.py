@@ -22,6 +22,7 @@ from ._binding import (  # noqa: F401
     Plan,
     gvt_dense_matvec,
     gvt_krr_cg,
+    gvt_krr_cg_batched,
     gvt_last_error,
     gvt_matvec,
     gvt_pairwise_matvec,

@@ -60,10 +60,11 @@ def load_library():
     lib.gvt_dense_matvec.argtypes = [I, P, I64, I64, I64, P, I64, I64, I64, P, I64, P, I64, P]
     lib.gvt_krr_cg.argtypes = [I, P, I64, I64, P, I64, I64, P, P, I64, P, P, I, P, I64, P, I64, I,
                                ctypes.c_double, I, I, P, P, P]
+    lib.gvt_krr_cg_batched.argtypes = [I, P, I, P, I, I, ctypes.c_double, I, I, P, P, P]
     lib.gvt_plan_profile.argtypes = [P, I, P, I64, P, I64, P, I64, I64, P, I64, I, P, P]
     lib.gvt_plan_info.argtypes = [P, P]
     for f in ("gvt_plan_profile", "gvt_plan_info", "gvt_plan_create", "gvt_plan_destroy", "gvt_plan_execute", "gvt_matvec",
-              "gvt_pairwise_matvec", "gvt_dense_matvec", "gvt_krr_cg"):
+              "gvt_pairwise_matvec", "gvt_dense_matvec", "gvt_krr_cg", "gvt_krr_cg_batched"):
         getattr(lib, f).restype = I
     _lib = lib
     return lib
@@ -270,6 +271,51 @@ def gvt_dense_matvec(M, N, Vmat, prec=None, out=None):
                                 N.shape[1], _ld(N), _ptr(Vmat), _ld(Vmat), _ptr(U), _ld(U),
                                 _stream_handle()))
     return U
+
+
+class _KrrProblem(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_void_p), ("d", ctypes.c_int64), ("ldd", ctypes.c_int64),
+                ("T", ctypes.c_void_p), ("t", ctypes.c_int64), ("ldt", ctypes.c_int64),
+                ("c", ctypes.c_void_p), ("e", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("y", ctypes.c_void_p), ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("A0", ctypes.c_void_p), ("lda0", ctypes.c_int64)]
+
+
+def gvt_krr_cg_batched(kind, problems, lambdas, max_iter=200, tol=1e-6, matvec_prec=F64,
+                       check_every=8):
+    """Many ridge problems at once.  problems: sequence of dicts with D, T (None for
+    homogeneous kinds), c, e, y and optionally A0 ([n, nlam] view with unit row stride).
+    Returns (list of A[n, nlam], iters[nprob, nlam], true_relres[nprob, nlam], status)."""
+    torch = _torch()
+    lib = load_library()
+    code = _kind_codes(kind)[0]
+    lam = np.ascontiguousarray(np.atleast_1d(np.asarray(lambdas, dtype=np.float64)))
+    nlam = len(lam)
+    arr = (_KrrProblem * len(problems))()
+    outs, keep = [], []
+    for k, pr in enumerate(problems):
+        D = pr["D"]
+        Tm = pr.get("T") if pr.get("T") is not None else D
+        c, e = _idx(pr["c"]), _idx(pr["e"])
+        n = c.numel()
+        A = torch.empty((nlam, n), dtype=torch.float64, device=D.device)
+        outs.append(A)
+        A0 = pr.get("A0")
+        if A0 is not None and A0.stride(0) != 1:
+            A0 = A0.t().contiguous().t()  # column-major n x nlam
+        keep.append(A0)  # alive until the call returns
+        arr[k] = _KrrProblem(D.data_ptr(), D.shape[0], _ld(D), Tm.data_ptr(), Tm.shape[0], _ld(Tm),
+                             c.data_ptr(), e.data_ptr(), n, pr["y"].data_ptr(), A.data_ptr(), n,
+                             A0.data_ptr() if A0 is not None else None,
+                             A0.stride(1) if A0 is not None else n)
+    iters = np.zeros((len(problems), nlam), dtype=np.int64)
+    rel = np.zeros((len(problems), nlam), dtype=np.float64)
+    rc = lib.gvt_krr_cg_batched(code, ctypes.cast(arr, ctypes.c_void_p), len(problems),
+                                lam.ctypes.data_as(ctypes.c_void_p), nlam, int(max_iter), float(tol),
+                                int(matvec_prec), int(check_every), iters.ctypes.data_as(ctypes.c_void_p),
+                                rel.ctypes.data_as(ctypes.c_void_p), _stream_handle())
+    _check(rc)
+    return [A.t() for A in outs], iters, rel, rc
 
 
 def gvt_krr_cg(kind, D, T, pairs, y, lambdas, max_iter=200, tol=1e-6, matvec_prec=F64,

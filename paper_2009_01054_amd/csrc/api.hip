@@ -22,6 +22,9 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
                 const double *lambdas, int nlam, double *A, int64_t lda, const double *A0,
                 int64_t lda0, int max_iter, double tol, int mprec, int check_every,
                 int64_t *iters_out, double *relres_out, hipStream_t s);
+int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const double *lambdas,
+                        int nlam, int max_iter, double tol, int mprec, int check_every,
+                        int64_t *iters_out, double *relres_out, hipStream_t s);
 
 }  // namespace gvt
 
@@ -166,6 +169,15 @@ int gvt_krr_cg(int kind, const double *D, int64_t d, int64_t ldd, const double *
     return krr_cg_impl(kind, D, d, ldd, T, t, ldt, c, e, n, y, lambdas, nlam, A, lda, A0, lda0,
                        max_iter, tol, matvec_prec, check_every, iters_out, relres_out,
                        (hipStream_t)stream);
+  });
+}
+
+int gvt_krr_cg_batched(int kind, const gvt_krr_problem *problems, int nprob, const double *lambdas,
+                       int nlam, int max_iter, double tol, int matvec_prec, int check_every,
+                       int64_t *iters_out, double *relres_out, void *stream) {
+  return guarded([&]() {
+    return krr_cg_batched_impl(kind, problems, nprob, lambdas, nlam, max_iter, tol, matvec_prec,
+                               check_every, iters_out, relres_out, (hipStream_t)stream);
   });
 }
 

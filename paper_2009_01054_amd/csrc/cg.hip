@@ -9,7 +9,9 @@
 // bitwise reproducible.  The per-iteration scalar work stays on the device;
 // the host only looks at the state every `check_every` iterations, and those
 // iteration blocks are replayed from a captured HIP graph.
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <cstring>
 
 #include "plan.h"
@@ -433,6 +435,644 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
     relres_out[l] = std::sqrt(rt[l]) / ynorm;
     if (hs[l].state == CG_BREAKDOWN) status = GVT_ERR_BREAKDOWN;
     if (hs[l].state != CG_DONE) all_done = false;
+  }
+  if (status == GVT_OK && !all_done) status = GVT_NOT_CONVERGED;
+  return status;
+}
+
+// ===========================================================================
+// Many independent ridge problems, each with its own base kernels, pairs and
+// labels, solved together for one grid of lambdas.  One set of CG vectors
+// holds every problem's nlam systems back to back (problem p, system l at
+// voff_p + l * n_p); the vector kernels walk fixed chunks that each belong to
+// one system, and per-system sums fold the chunk partials in a fixed order,
+// so results are reproducible.  The products of all problems run as grouped
+// launches (one launch per stage covers every problem's blocks, largest
+// problems first), problems whose systems have all stopped are skipped by a
+// device-side mask, and blocks of iterations are replayed from a HIP graph.
+// ===========================================================================
+static constexpr int BCH = 4096;  // elements per chunk
+
+struct BChunk {
+  int64_t start;  // element offset in the concatenated vectors
+  int64_t yoff;   // offset of the chunk's first pair in the concatenated labels
+  int32_t sys;    // system index = problem * nlam + lambda index
+  int32_t len;
+};
+
+// fold the chunk partials [c0, c1) of one system in a fixed order
+__device__ __forceinline__ double fold_range(const double *part, int64_t c0, int64_t c1, double *sh) {
+  double v = 0.0;
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += RB) v += part[c];
+  return block_sum(v, sh);
+}
+
+// w = wraw + lambda p; partial p.w
+template <class TW>
+__global__ __launch_bounds__(RB) void bcg_pw_kernel(const BChunk *__restrict__ ch,
+                                                    const TW *__restrict__ wraw, double *__restrict__ w,
+                                                    const double *__restrict__ p,
+                                                    const double *__restrict__ lam, int nlam,
+                                                    const CgScalars *__restrict__ sc,
+                                                    double *__restrict__ part) {
+  __shared__ double sh[RB];
+  const BChunk c = ch[blockIdx.x];
+  double acc = 0.0;
+  if (sc[c.sys].state == CG_ACTIVE) {  // uniform per block
+    const double lm = lam[c.sys % nlam];
+    for (int i = threadIdx.x; i < c.len; i += RB) {
+      const int64_t g = c.start + i;
+      const double pi = p[g];
+      const double wi = (double)wraw[g] + lm * pi;
+      w[g] = wi;
+      acc += pi * wi;
+    }
+  }
+  const double v = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(RB) void bcg_alpha_kernel(CgScalars *sc, const double *__restrict__ part,
+                                                       const int64_t *__restrict__ cfirst) {
+  __shared__ double sh[RB];
+  const int sy = blockIdx.x;
+  if (sc[sy].state != CG_ACTIVE) return;  // uniform per block
+  const double pw = fold_range(part, cfirst[sy], cfirst[sy + 1], sh);
+  if (threadIdx.x != 0) return;
+  sc[sy].pw = pw;
+  if (!(pw > 0.0) || !isfinite(pw)) {
+    sc[sy].state = CG_BREAKDOWN;
+    return;
+  }
+  sc[sy].alpha = sc[sy].rho / pw;
+}
+
+// a += alpha p; r -= alpha w; partial r.r
+__global__ __launch_bounds__(RB) void bcg_update_kernel(const BChunk *__restrict__ ch,
+                                                        double *__restrict__ a, double *__restrict__ r,
+                                                        const double *__restrict__ p,
+                                                        const double *__restrict__ w,
+                                                        const CgScalars *__restrict__ sc,
+                                                        double *__restrict__ part) {
+  __shared__ double sh[RB];
+  const BChunk c = ch[blockIdx.x];
+  double acc = 0.0;
+  if (sc[c.sys].state == CG_ACTIVE) {
+    const double al = sc[c.sys].alpha;
+    for (int i = threadIdx.x; i < c.len; i += RB) {
+      const int64_t g = c.start + i;
+      a[g] += al * p[g];
+      const double ri = r[g] - al * w[g];
+      r[g] = ri;
+      acc += ri * ri;
+    }
+  }
+  const double v = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(RB) void bcg_beta_kernel(CgScalars *sc, const double *__restrict__ part,
+                                                      const int64_t *__restrict__ cfirst, double tol,
+                                                      int max_iter, int lowprec) {
+  __shared__ double sh[RB];
+  const int sy = blockIdx.x;
+  if (sc[sy].state != CG_ACTIVE) return;  // uniform per block
+  const double rho_new = fold_range(part, cfirst[sy], cfirst[sy + 1], sh);
+  if (threadIdx.x != 0) return;
+  sc[sy].iters += 1;
+  if (!isfinite(rho_new)) {
+    sc[sy].state = CG_BREAKDOWN;
+    return;
+  }
+  sc[sy].beta = rho_new / sc[sy].rho;
+  sc[sy].rho = rho_new;
+  if (sqrt(rho_new) / sc[sy].ynorm < tol) {
+    sc[sy].state = lowprec ? CG_PENDING : CG_DONE;
+  } else if (sc[sy].iters >= max_iter) {
+    sc[sy].state = CG_MAXITER;
+  }
+}
+
+// p = r + beta p (active systems)
+__global__ __launch_bounds__(RB) void bcg_p_kernel(const BChunk *__restrict__ ch, double *__restrict__ p,
+                                                   const double *__restrict__ r,
+                                                   const CgScalars *__restrict__ sc) {
+  const BChunk c = ch[blockIdx.x];
+  if (sc[c.sys].state != CG_ACTIVE) return;
+  const double be = sc[c.sys].beta;
+  for (int i = threadIdx.x; i < c.len; i += RB) {
+    const int64_t g = c.start + i;
+    p[g] = r[g] + be * p[g];
+  }
+}
+
+// active[p] = some system of problem p is still iterating
+__global__ void bcg_mask_kernel(const CgScalars *__restrict__ sc, int nprob, int nlam,
+                                uint8_t *__restrict__ active) {
+  const int pb = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pb >= nprob) return;
+  uint8_t any = 0;
+  for (int l = 0; l < nlam; ++l) any |= sc[pb * nlam + l].state == CG_ACTIVE ? 1 : 0;
+  active[pb] = any;
+}
+
+// r = y (every system of a problem starts from its labels); partial r.r
+__global__ __launch_bounds__(RB) void bcg_bcast_kernel(const BChunk *__restrict__ ch,
+                                                       const double *__restrict__ y,
+                                                       double *__restrict__ r,
+                                                       double *__restrict__ part) {
+  __shared__ double sh[RB];
+  const BChunk c = ch[blockIdx.x];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < c.len; i += RB) {
+    const double yi = y[c.yoff + i];
+    r[c.start + i] = yi;
+    acc += yi * yi;
+  }
+  const double v = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// out = y - (wraw + lambda a); partial out.out
+__global__ __launch_bounds__(RB) void bcg_residual_kernel(const BChunk *__restrict__ ch,
+                                                          const double *__restrict__ y,
+                                                          const double *__restrict__ wraw,
+                                                          const double *__restrict__ a,
+                                                          const double *__restrict__ lam, int nlam,
+                                                          double *__restrict__ out,
+                                                          double *__restrict__ part) {
+  __shared__ double sh[RB];
+  const BChunk c = ch[blockIdx.x];
+  const double lm = lam[c.sys % nlam];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < c.len; i += RB) {
+    const int64_t g = c.start + i;
+    const double ri = y[c.yoff + i] - (wraw[g] + lm * a[g]);
+    out[g] = ri;
+    acc += ri * ri;
+  }
+  const double v = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(RB) void bcg_fold_kernel(const double *__restrict__ part,
+                                                      const int64_t *__restrict__ cfirst,
+                                                      double *__restrict__ out) {
+  __shared__ double sh[RB];
+  const int sy = blockIdx.x;
+  const double v = fold_range(part, cfirst[sy], cfirst[sy + 1], sh);
+  if (threadIdx.x == 0) out[sy] = v;
+}
+
+// dst = src for the systems in `only_state` (every system when only_state < 0)
+__global__ __launch_bounds__(RB) void bcg_copy_kernel(const BChunk *__restrict__ ch,
+                                                      const double *__restrict__ src,
+                                                      double *__restrict__ dst, int only_state,
+                                                      const CgScalars *__restrict__ sc) {
+  const BChunk c = ch[blockIdx.x];
+  if (only_state >= 0 && sc[c.sys].state != only_state) return;
+  for (int i = threadIdx.x; i < c.len; i += RB) dst[c.start + i] = src[c.start + i];
+}
+
+namespace {
+
+struct PlanSet {
+  std::vector<gvt_plan *> plans;
+  hipStream_t s = nullptr;
+  ~PlanSet() {
+    if (!plans.empty()) (void)hipStreamSynchronize(s);
+    for (gvt_plan *P : plans) delete P;
+  }
+};
+
+// Largest RHS block the products use for nlam systems per problem.
+int rhs_block(int64_t left) { return left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1; }
+
+}  // namespace
+
+int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const double *lambdas,
+                        int nlam, int max_iter, double tol, int mprec, int check_every,
+                        int64_t *iters_out, double *relres_out, hipStream_t s) {
+  GVT_REQUIRE(pr && lambdas && iters_out && relres_out, GVT_ERR_ARG, "null argument");
+  GVT_REQUIRE(nprob >= 1 && nlam >= 1 && nlam <= 64, GVT_ERR_ARG, "need nprob >= 1 and 1 <= nlam <= 64");
+  GVT_REQUIRE(max_iter >= 1 && tol > 0 && check_every >= 1, GVT_ERR_ARG, "bad max_iter/tol/check_every");
+  GVT_REQUIRE(mprec == GVT_F64 || mprec == GVT_F32, GVT_ERR_UNSUPPORTED,
+              "CG products run in GVT_F64 or GVT_F32");
+  for (int l = 0; l < nlam; ++l)
+    GVT_REQUIRE(lambdas[l] > 0 && std::isfinite(lambdas[l]), GVT_ERR_ARG, "lambda must be > 0");
+  const bool hom = kind == GVT_SYMMETRIC || kind == GVT_ANTISYMMETRIC || kind == GVT_RANKING ||
+                   kind == GVT_MLPK;
+
+  // ---- per-problem plans and offsets
+  struct Prob {
+    const double *D, *T;
+    int64_t d, t, ldd, ldt, n, noff, voff;
+    float *D32, *T32;
+  };
+  std::vector<Prob> pb(nprob);
+  PlanSet ps;
+  ps.s = s;
+  int64_t ntot = 0;
+  for (int i = 0; i < nprob; ++i) {
+    const gvt_krr_problem &q = pr[i];
+    Prob &b = pb[i];
+    GVT_REQUIRE(q.D && q.c && q.e && q.y && q.A, GVT_ERR_ARG,
+                "problem " + std::to_string(i) + ": null argument");
+    GVT_REQUIRE(q.n >= 1 && q.lda >= q.n && (!q.A0 || q.lda0 >= q.n), GVT_ERR_ARG,
+                "problem " + std::to_string(i) + ": need n >= 1 and lda, lda0 >= n");
+    b.D = q.D;
+    b.d = q.d;
+    b.ldd = q.ldd;
+    if (hom) {
+      b.T = b.D; b.t = b.d; b.ldt = b.ldd;
+    } else {
+      GVT_REQUIRE(q.T, GVT_ERR_ARG, "problem " + std::to_string(i) + ": null T");
+      b.T = q.T; b.t = q.t; b.ldt = q.ldt;
+    }
+    GVT_REQUIRE(b.ldd >= b.d && b.ldt >= b.t, GVT_ERR_ARG,
+                "problem " + std::to_string(i) + ": ld < cols");
+    b.n = q.n;
+    b.noff = ntot;
+    b.voff = ntot * nlam;
+    ntot += q.n;
+    gvt_plan *P = new gvt_plan();
+    ps.plans.push_back(P);
+    try {
+      plan_build(P, &kind, 1, b.d, b.d, b.t, b.t, q.c, q.e, q.n, q.c, q.e, q.n,
+                 GVT_FLAG_SYMMETRIC_BASES, s);
+    } catch (Error &e) {
+      e.msg = "problem " + std::to_string(i) + ": " + e.msg;
+      throw;
+    }
+    GVT_REQUIRE(!P->dense, GVT_ERR_UNSUPPORTED,
+                "problem " + std::to_string(i) + ": complete-data training grid");
+  }
+  const int64_t nv = ntot * nlam;
+  const int nsys = nprob * nlam;
+
+  // ---- chunks of the concatenated vectors
+  std::vector<BChunk> hch;
+  std::vector<int64_t> hcf(nsys + 1);
+  for (int i = 0; i < nprob; ++i)
+    for (int l = 0; l < nlam; ++l) {
+      hcf[i * nlam + l] = (int64_t)hch.size();
+      for (int64_t k = 0; k < pb[i].n; k += BCH)
+        hch.push_back({pb[i].voff + l * pb[i].n + k, pb[i].noff + k, i * nlam + l,
+                       (int32_t)std::min<int64_t>(BCH, pb[i].n - k)});
+    }
+  hcf[nsys] = (int64_t)hch.size();
+  const int64_t nch = (int64_t)hch.size();
+  GVT_REQUIRE(nch < (int64_t)1 << 31, GVT_ERR_ARG, "too many chunks");
+
+  // ---- grouped products when every plan is one plain Kronecker term
+  bool grouped = true;
+  for (gvt_plan *P : ps.plans)
+    grouped = grouped && P->direct && P->sbufs.size() == 1 && !P->sbufs[0].degenerate;
+  const int Rmax = rhs_block(nlam);
+
+  // ---- device memory
+  DevMem m_a, m_r, m_p, m_w, m_wraw, m_p32, m_w32, m_y, m_part, m_sc, m_lam, m_tmp, m_act, m_cmask,
+      m_ch, m_cf, m_mat32, m_vs, m_S, m_desc, m_items;
+  double *A = (double *)m_a.ensure(nv * 8);
+  double *r = (double *)m_r.ensure(nv * 8);
+  double *p = (double *)m_p.ensure(nv * 8);
+  double *w = (double *)m_w.ensure(nv * 8);
+  double *wraw = (double *)m_wraw.ensure(nv * 8);
+  double *ycat = (double *)m_y.ensure(ntot * 8);
+  double *part = (double *)m_part.ensure(nch * 8);
+  CgScalars *sc = (CgScalars *)m_sc.ensure(sizeof(CgScalars) * nsys);
+  double *lam = (double *)m_lam.ensure(nlam * 8);
+  double *tmp = (double *)m_tmp.ensure(nsys * 8);
+  uint8_t *active = (uint8_t *)m_act.ensure(nprob);
+  uint8_t *cmask = (uint8_t *)m_cmask.ensure(nprob);
+  BChunk *ch = (BChunk *)m_ch.ensure(sizeof(BChunk) * nch);
+  int64_t *cf = (int64_t *)m_cf.ensure(8 * (nsys + 1));
+  float *p32 = nullptr, *w32 = nullptr;
+  GVT_HIP_CHECK(hipMemcpyAsync(lam, lambdas, nlam * 8, hipMemcpyHostToDevice, s));
+  GVT_HIP_CHECK(hipMemcpyAsync(ch, hch.data(), sizeof(BChunk) * nch, hipMemcpyHostToDevice, s));
+  GVT_HIP_CHECK(hipMemcpyAsync(cf, hcf.data(), 8 * (nsys + 1), hipMemcpyHostToDevice, s));
+  if (mprec == GVT_F32) {
+    p32 = (float *)m_p32.ensure(nv * 4);
+    w32 = (float *)m_w32.ensure(nv * 4);
+    size_t tot = 0;
+    for (int i = 0; i < nprob; ++i)
+      tot += (size_t)(pb[i].d * pb[i].d + (hom ? 0 : pb[i].t * pb[i].t));
+    float *base = (float *)m_mat32.ensure(tot * 4);
+    size_t off = 0;
+    for (int i = 0; i < nprob; ++i) {
+      Prob &b = pb[i];
+      b.D32 = base + off;
+      off += (size_t)(b.d * b.d);
+      mat_to_f32_kernel<<<g1(b.d * b.d), 256, 0, s>>>(b.D, b.ldd, b.D32, b.d, b.d);
+      if (hom) {
+        b.T32 = b.D32;
+      } else {
+        b.T32 = base + off;
+        off += (size_t)(b.t * b.t);
+        mat_to_f32_kernel<<<g1(b.t * b.t), 256, 0, s>>>(b.T, b.ldt, b.T32, b.t, b.t);
+      }
+    }
+  }
+
+  // descriptor sets: [0] FP64 iteration (p -> wraw), [1] FP32 iteration
+  // (p32 -> w32), [2] FP64 residual product (w -> wraw)
+  GroupDesc<double> *dd_it = nullptr, *dd_res = nullptr;
+  GroupDesc<float> *df_it = nullptr;
+  GroupItem *it_pack = nullptr, *it_s1 = nullptr, *it_s2 = nullptr;
+  int64_t n_pack = 0, n_s1 = 0, n_s2 = 0;
+  if (grouped) {
+    std::vector<size_t> vs_off(nprob), S_off(nprob);
+    size_t vs_tot = 0, S_tot = 0;
+    for (int i = 0; i < nprob; ++i) {
+      const gvt_plan *P = ps.plans[i];
+      const SBufSpec &sb = P->sbufs[0];
+      vs_off[i] = vs_tot;
+      vs_tot += ((size_t)pb[i].n * Rmax * 8 + 255) & ~size_t(255);
+      S_off[i] = S_tot;
+      S_tot += ((size_t)sb.rows.size() * sbuf_row_ld<double>(nkeys_of(P, sb.key), Rmax) * 8 + 255) &
+               ~size_t(255);
+    }
+    char *vs_base = (char *)m_vs.ensure(vs_tot);
+    char *S_base = (char *)m_S.ensure(S_tot);
+    std::vector<GroupDesc<double>> h64(nprob), hres(nprob);
+    std::vector<GroupDesc<float>> h32(nprob);
+    auto fill = [&](auto &dsc, int i, auto *F0, int64_t ld0, auto *F1m, int64_t ld1m, auto *V, auto *U) {
+      const gvt_plan *P = ps.plans[i];
+      const TermSpec &t = P->terms[P->outputs[0][0].first];
+      const SBufSpec &sb = P->sbufs[t.sbuf];
+      const InputSort &is = P->insort[sb.key == SC ? 0 : 1];
+      typedef typename std::remove_pointer<decltype(V)>::type Tv;
+      typedef typename std::remove_const<Tv>::type T;
+      const T *F[2] = {F0, F1m};
+      const int64_t ldF[2] = {ld0, ld1m};
+      dsc.V = V;
+      dsc.ldv = pb[i].n;
+      dsc.perm_in = is.perm.as<int32_t>();
+      dsc.n_in = pb[i].n;
+      dsc.vs = (T *)(vs_base + vs_off[i]);
+      dsc.Fc = F[sb.fsc];
+      dsc.ldc = ldF[sb.fsc];
+      dsc.rows = sb.d_rows.as<int32_t>();
+      dsc.nrows = (int64_t)sb.rows.size();
+      dsc.seg = is.seg.as<int64_t>();
+      dsc.other = is.other.as<int32_t>();
+      dsc.nkeys = is.nkeys;
+      dsc.S = (T *)(S_base + S_off[i]);
+      dsc.nkb = group_stage1_blocks(is.nkeys, 1);  // key blocks of one row block
+      dsc.F1 = F[t.fdot];
+      dsc.ld1 = ldF[t.fdot];
+      dsc.nx = rows_of(P, t.fdot);
+      dsc.tileoff = t.g_tileoff.as<int64_t>();
+      dsc.tiley = t.g_tiley.as<int32_t>();
+      dsc.tilemax = t.g_tilemax.as<int32_t>();
+      dsc.yrows = t.g_yrows.as<int32_t>();
+      dsc.perm_out = t.g_perm.as<int32_t>();
+      dsc.nyb = t.nyb;
+      dsc.U = U;
+      dsc.ldu = pb[i].n;
+    };
+    for (int i = 0; i < nprob; ++i) {
+      const Prob &b = pb[i];
+      fill(h64[i], i, b.D, b.ldd, b.T, b.ldt, (const double *)(p + b.voff), wraw + b.voff);
+      fill(hres[i], i, b.D, b.ldd, b.T, b.ldt, (const double *)(w + b.voff), wraw + b.voff);
+      if (mprec == GVT_F32)
+        fill(h32[i], i, (const float *)b.D32, b.d, (const float *)b.T32, b.t,
+             (const float *)(p32 + b.voff), w32 + b.voff);
+    }
+    // work lists: problems by decreasing Theorem 1 cost, each problem's blocks in order
+    std::vector<int> order(nprob);
+    for (int i = 0; i < nprob; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return ps.plans[x]->cost_fma > ps.plans[y]->cost_fma;
+    });
+    std::vector<GroupItem> hp, h1, h2;
+    for (int i : order) {
+      const GroupDesc<double> &g = h64[i];
+      const int64_t np = group_pack_blocks(g.n_in);
+      const int64_t n1 = group_stage1_blocks(g.nkeys, g.nrows);
+      const int64_t n2 = ps.plans[i]->terms[ps.plans[i]->outputs[0][0].first].ntiles;
+      GVT_REQUIRE(np < (1 << 30) && n1 < (1 << 30) && n2 < (1 << 30), GVT_ERR_ARG, "problem too large");
+      for (int64_t k = 0; k < np; ++k) hp.push_back({i, (int32_t)k});
+      for (int64_t k = 0; k < n1; ++k) h1.push_back({i, (int32_t)k});
+      for (int64_t k = 0; k < n2; ++k) h2.push_back({i, (int32_t)k});
+    }
+    n_pack = (int64_t)hp.size();
+    n_s1 = (int64_t)h1.size();
+    n_s2 = (int64_t)h2.size();
+    const size_t dsz64 = sizeof(GroupDesc<double>) * nprob, dsz32 = sizeof(GroupDesc<float>) * nprob;
+    char *db = (char *)m_desc.ensure(2 * dsz64 + dsz32 + 256);
+    dd_it = (GroupDesc<double> *)db;
+    dd_res = (GroupDesc<double> *)(db + dsz64);
+    df_it = (GroupDesc<float> *)(db + 2 * dsz64);
+    GVT_HIP_CHECK(hipMemcpyAsync(dd_it, h64.data(), dsz64, hipMemcpyHostToDevice, s));
+    GVT_HIP_CHECK(hipMemcpyAsync(dd_res, hres.data(), dsz64, hipMemcpyHostToDevice, s));
+    if (mprec == GVT_F32)
+      GVT_HIP_CHECK(hipMemcpyAsync(df_it, h32.data(), dsz32, hipMemcpyHostToDevice, s));
+    GroupItem *ib = (GroupItem *)m_items.ensure(sizeof(GroupItem) * (n_pack + n_s1 + n_s2));
+    it_pack = ib;
+    it_s1 = ib + n_pack;
+    it_s2 = ib + n_pack + n_s1;
+    GVT_HIP_CHECK(hipMemcpyAsync(it_pack, hp.data(), sizeof(GroupItem) * n_pack, hipMemcpyHostToDevice, s));
+    GVT_HIP_CHECK(hipMemcpyAsync(it_s1, h1.data(), sizeof(GroupItem) * n_s1, hipMemcpyHostToDevice, s));
+    GVT_HIP_CHECK(hipMemcpyAsync(it_s2, h2.data(), sizeof(GroupItem) * n_s2, hipMemcpyHostToDevice, s));
+    // the host vectors above are released at scope end: wait for the copies
+    GVT_HIP_CHECK(hipStreamSynchronize(s));
+  }
+
+  // ---- products of every problem: out = K in (RHS blocks of at most 8)
+  auto grouped_product = [&](auto *desc, const uint8_t *mask) {
+    for (int64_t r0 = 0; r0 < nlam;) {
+      const int R = rhs_block(nlam - r0);
+      launch_group_pack(desc, it_pack, n_pack, R, r0, mask, s);
+      launch_group_stage1(desc, it_s1, n_s1, R, mask, s);
+      launch_group_stage2(desc, it_s2, n_s2, R, r0, mask, s);
+      r0 += R;
+    }
+  };
+  auto product64 = [&](const double *in, double *out, bool residual_set, const uint8_t *mask) {
+    if (grouped) {
+      grouped_product(residual_set ? dd_res : dd_it, mask);
+      return;
+    }
+    for (int i = 0; i < nprob; ++i)
+      plan_execute(ps.plans[i], GVT_F64, pb[i].D, pb[i].ldd, pb[i].T, pb[i].ldt, in + pb[i].voff, nlam,
+                   pb[i].n, out + pb[i].voff, pb[i].n, s);
+  };
+  auto product32 = [&]() {
+    if (grouped) {
+      grouped_product(df_it, active);
+      return;
+    }
+    for (int i = 0; i < nprob; ++i)
+      plan_execute(ps.plans[i], GVT_F32, pb[i].D32, pb[i].d, pb[i].T32, pb[i].t, p32 + pb[i].voff, nlam,
+                   pb[i].n, w32 + pb[i].voff, pb[i].n, s);
+  };
+
+  // ---- labels, norms, initial residuals
+  bool any_a0 = false;
+  for (int i = 0; i < nprob; ++i) {
+    GVT_HIP_CHECK(hipMemcpyAsync(ycat + pb[i].noff, pr[i].y, pb[i].n * 8, hipMemcpyDeviceToDevice, s));
+    if (pr[i].A0) {
+      any_a0 = true;
+      GVT_HIP_CHECK(hipMemcpy2DAsync(A + pb[i].voff, pb[i].n * 8, pr[i].A0, pr[i].lda0 * 8, pb[i].n * 8,
+                                     nlam, hipMemcpyDeviceToDevice, s));
+    } else {
+      GVT_HIP_CHECK(hipMemsetAsync(A + pb[i].voff, 0, (size_t)pb[i].n * nlam * 8, s));
+    }
+  }
+  bcg_bcast_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, ycat, r, part);
+  bcg_fold_kernel<<<nsys, RB, 0, s>>>(part, cf, tmp);
+  std::vector<double> ynorm(nsys), rho0(nsys);
+  GVT_HIP_CHECK(hipMemcpyAsync(ynorm.data(), tmp, nsys * 8, hipMemcpyDeviceToHost, s));
+  if (any_a0) {
+    bcg_copy_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, A, w, -1, nullptr);
+    product64(w, wraw, true, nullptr);
+    bcg_residual_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, ycat, wraw, A, lam, nlam, r, part);
+    bcg_fold_kernel<<<nsys, RB, 0, s>>>(part, cf, tmp);
+  }
+  GVT_HIP_CHECK(hipMemcpyAsync(rho0.data(), tmp, nsys * 8, hipMemcpyDeviceToHost, s));
+  bcg_copy_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, r, p, -1, nullptr);
+  GVT_HIP_CHECK(hipStreamSynchronize(s));
+  std::vector<CgScalars> hs(nsys);
+  std::vector<uint8_t> hmask(nprob);
+  for (int sy = 0; sy < nsys; ++sy) {
+    ynorm[sy] = std::sqrt(ynorm[sy]);
+    GVT_REQUIRE(std::isfinite(ynorm[sy]), GVT_ERR_BREAKDOWN, "non-finite labels");
+    std::memset(&hs[sy], 0, sizeof(CgScalars));
+    hs[sy].rho = rho0[sy];
+    // all-zero labels: a = 0 is the exact solution
+    hs[sy].ynorm = ynorm[sy] > 0 ? ynorm[sy] : 1.0;
+    hs[sy].state = (std::sqrt(rho0[sy]) / hs[sy].ynorm < tol) ? CG_DONE : CG_ACTIVE;
+  }
+  auto upload_states = [&]() {
+    for (int i = 0; i < nprob; ++i) {
+      hmask[i] = 0;
+      for (int l = 0; l < nlam; ++l) hmask[i] |= hs[i * nlam + l].state == CG_ACTIVE ? 1 : 0;
+    }
+    GVT_HIP_CHECK(hipMemcpyAsync(sc, hs.data(), sizeof(CgScalars) * nsys, hipMemcpyHostToDevice, s));
+    GVT_HIP_CHECK(hipMemcpyAsync(active, hmask.data(), nprob, hipMemcpyHostToDevice, s));
+    GVT_HIP_CHECK(hipStreamSynchronize(s));  // the host arrays are reused
+  };
+  upload_states();
+
+  const int lowprec = mprec == GVT_F32 ? 1 : 0;
+  const unsigned gm = (unsigned)ceil_div(nprob, 256);
+  auto iteration = [&]() {
+    if (lowprec) {
+      to_f32_kernel<<<g1(nv), 256, 0, s>>>(p, p32, nv);
+      product32();
+      bcg_pw_kernel<float><<<(unsigned)nch, RB, 0, s>>>(ch, w32, w, p, lam, nlam, sc, part);
+    } else {
+      product64(p, wraw, false, active);
+      bcg_pw_kernel<double><<<(unsigned)nch, RB, 0, s>>>(ch, wraw, w, p, lam, nlam, sc, part);
+    }
+    bcg_alpha_kernel<<<nsys, RB, 0, s>>>(sc, part, cf);
+    bcg_update_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, A, r, p, w, sc, part);
+    bcg_beta_kernel<<<nsys, RB, 0, s>>>(sc, part, cf, tol, max_iter, lowprec);
+    bcg_p_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, p, r, sc);
+    bcg_mask_kernel<<<gm, 256, 0, s>>>(sc, nprob, nlam, active);
+  };
+
+  const bool use_graph = s != nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int status = GVT_OK;
+  int total_iter = 0;
+  bool first = true;
+  std::vector<double> rt(nsys);
+  try {
+    while (true) {
+      bool any_active = false;
+      for (int sy = 0; sy < nsys; ++sy) any_active |= hs[sy].state == CG_ACTIVE;
+      if (!any_active) {
+        // certify systems whose FP32 recurrence claims convergence
+        bool pending = false;
+        for (int i = 0; i < nprob; ++i) {
+          hmask[i] = 0;
+          for (int l = 0; l < nlam; ++l) hmask[i] |= hs[i * nlam + l].state == CG_PENDING ? 1 : 0;
+          pending |= hmask[i] != 0;
+        }
+        if (!pending) break;
+        GVT_HIP_CHECK(hipMemcpyAsync(cmask, hmask.data(), nprob, hipMemcpyHostToDevice, s));
+        bcg_copy_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, A, w, -1, nullptr);
+        product64(w, wraw, true, cmask);
+        bcg_residual_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, ycat, wraw, A, lam, nlam, w, part);
+        bcg_fold_kernel<<<nsys, RB, 0, s>>>(part, cf, tmp);
+        GVT_HIP_CHECK(hipMemcpyAsync(rt.data(), tmp, nsys * 8, hipMemcpyDeviceToHost, s));
+        GVT_HIP_CHECK(hipStreamSynchronize(s));
+        for (int sy = 0; sy < nsys; ++sy) {
+          if (hs[sy].state != CG_PENDING) continue;
+          if (std::sqrt(rt[sy]) / hs[sy].ynorm < tol) {
+            hs[sy].state = CG_DONE;
+          } else if (hs[sy].iters >= max_iter) {
+            hs[sy].state = CG_MAXITER;
+          } else {
+            hs[sy].state = CG_ACTIVE;  // restart from the true residual
+            hs[sy].rho = rt[sy];
+          }
+        }
+        upload_states();
+        bcg_copy_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, w, r, CG_ACTIVE, sc);
+        bcg_copy_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, w, p, CG_ACTIVE, sc);
+        continue;
+      }
+      if (first) {
+        iteration();  // eager: every workspace is in place before a capture
+        ++total_iter;
+        first = false;
+        if (use_graph) {
+          GVT_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+          try {
+            for (int k = 0; k < check_every; ++k) iteration();
+          } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+          }
+          GVT_HIP_CHECK(hipStreamEndCapture(s, &graph));
+          GVT_HIP_CHECK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        }
+      } else if (use_graph) {
+        GVT_HIP_CHECK(hipGraphLaunch(gexec, s));
+        total_iter += check_every;
+      } else {
+        for (int k = 0; k < check_every; ++k) iteration();
+        total_iter += check_every;
+      }
+      GVT_HIP_CHECK(hipMemcpyAsync(hs.data(), sc, sizeof(CgScalars) * nsys, hipMemcpyDeviceToHost, s));
+      GVT_HIP_CHECK(hipStreamSynchronize(s));
+      for (int sy = 0; sy < nsys; ++sy)
+        if (hs[sy].state == CG_BREAKDOWN) status = GVT_ERR_BREAKDOWN;
+      if (status != GVT_OK) break;
+      if (total_iter > 4 * max_iter + 8) break;  // safety net; states already cap iterations
+    }
+  } catch (...) {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  if (gexec) (void)hipGraphExecDestroy(gexec);
+  if (graph) (void)hipGraphDestroy(graph);
+
+  // ---- final true residuals (FP64 products of every problem) and results
+  bcg_copy_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, A, w, -1, nullptr);
+  product64(w, wraw, true, nullptr);
+  bcg_residual_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, ycat, wraw, A, lam, nlam, r, part);
+  bcg_fold_kernel<<<nsys, RB, 0, s>>>(part, cf, tmp);
+  GVT_HIP_CHECK(hipMemcpyAsync(rt.data(), tmp, nsys * 8, hipMemcpyDeviceToHost, s));
+  GVT_HIP_CHECK(hipMemcpyAsync(hs.data(), sc, sizeof(CgScalars) * nsys, hipMemcpyDeviceToHost, s));
+  for (int i = 0; i < nprob; ++i)
+    GVT_HIP_CHECK(hipMemcpy2DAsync(pr[i].A, pr[i].lda * 8, A + pb[i].voff, pb[i].n * 8, pb[i].n * 8,
+                                   nlam, hipMemcpyDeviceToDevice, s));
+  GVT_HIP_CHECK(hipStreamSynchronize(s));
+  check_launch(s);
+  bool all_done = true;
+  for (int sy = 0; sy < nsys; ++sy) {
+    iters_out[sy] = hs[sy].iters;
+    relres_out[sy] = std::sqrt(rt[sy]) / hs[sy].ynorm;
+    if (hs[sy].state == CG_BREAKDOWN) status = GVT_ERR_BREAKDOWN;
+    if (hs[sy].state != CG_DONE) all_done = false;
   }
   if (status == GVT_OK && !all_done) status = GVT_NOT_CONVERGED;
   return status;

@@ -61,18 +61,22 @@ template <class T, int R> struct S1Cfg {
   static constexpr int KB = 4 * KPW;   // keys per block
 };
 
+// Body of one stage-1 block (key block kb, row block rb); shared by the
+// single-product kernel and the grouped kernel of batched products.
 template <class T, int R>
-__global__ __launch_bounds__(256) void stage1_kernel(
-    const T *__restrict__ Fc, int64_t ldc, const int32_t *__restrict__ rows, int64_t nrows,
-    const int64_t *__restrict__ seg, const int32_t *__restrict__ other, const T *__restrict__ vs,
-    int64_t nkeys, T *__restrict__ S, int64_t ldS) {
+__device__ __forceinline__ void stage1_block(const T *__restrict__ Fc, int64_t ldc,
+                                             const int32_t *__restrict__ rows, int64_t nrows,
+                                             const int64_t *__restrict__ seg,
+                                             const int32_t *__restrict__ other,
+                                             const T *__restrict__ vs, int64_t nkeys,
+                                             T *__restrict__ S, int64_t ldS, int64_t kb, int64_t rb,
+                                             T *stg) {
   typedef S1Cfg<T, R> C;
   constexpr int W = C::KB * R;
-  __shared__ T stg[64 * (W + 1)];
   const int lane = threadIdx.x & 63;
   const int w = wave_id_uniform();
-  const int64_t k0 = (int64_t)blockIdx.x * C::KB;
-  const int64_t rho0 = (int64_t)blockIdx.y * 64;
+  const int64_t k0 = kb * C::KB;
+  const int64_t rho0 = rb * 64;
   const int64_t rho = rho0 + lane;
   const bool live = rho < nrows;
   const int64_t y = live ? rows[rho] : 0;
@@ -111,6 +115,15 @@ __global__ __launch_bounds__(256) void stage1_kernel(
       if (rho0 + rr < nrows) S[(rho0 + rr) * ldS + nkeys * R + cc] = T(0);
     }
   }
+}
+
+template <class T, int R>
+__global__ __launch_bounds__(256) void stage1_kernel(
+    const T *__restrict__ Fc, int64_t ldc, const int32_t *__restrict__ rows, int64_t nrows,
+    const int64_t *__restrict__ seg, const int32_t *__restrict__ other, const T *__restrict__ vs,
+    int64_t nkeys, T *__restrict__ S, int64_t ldS) {
+  __shared__ T stg[64 * (S1Cfg<T, R>::KB * R + 1)];
+  stage1_block<T, R>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, blockIdx.x, blockIdx.y, stg);
 }
 
 // Degenerate stage 1 (key == other index): S[rho, k] = F2[rows[rho], k] * s[k].
@@ -163,20 +176,26 @@ template <class T, int R> struct S2Cfg {
   static_assert(STEPS >= 1, "chunk smaller than one step");
 };
 
+template <class T, int R> struct S2Smem {
+  __attribute__((aligned(16))) T tile[kStage2MaxS * (S2Cfg<T, R>::ROWE + S2Cfg<T, R>::PADE)];
+  unsigned char meta[S2Cfg<T, R>::NG][S2Cfg<T, R>::OPG];
+};
+
+// Body of one stage-2 tile t; shared by the single-product kernel and the
+// grouped kernel of batched products.
 template <class T, int R>
-__global__ __launch_bounds__(512) void stage2_kernel(
+__device__ __forceinline__ void stage2_tile(
     const T *__restrict__ F1, int64_t ld1, int64_t nx, const int64_t *__restrict__ tileoff,
     const int32_t *__restrict__ tiley, const int32_t *__restrict__ tilemax,
     const int32_t *__restrict__ yrows, const int32_t *__restrict__ perm, int nyb,
     const T *__restrict__ S, int64_t ldS, int64_t nkeys, T coef, T *__restrict__ out, int64_t ldi,
-    int64_t ldr) {
+    int64_t ldr, int t, S2Smem<T, R> &sm) {
   typedef S2Cfg<T, R> C;
   typedef typename Vec16<T>::type V16;
   constexpr int TROW = C::ROWE + C::PADE;
   constexpr int V16ROW = C::ROWE / C::VEC;  // 16-byte words per tile row (64)
-  __shared__ __attribute__((aligned(16))) T tile[kStage2MaxS * TROW];
-  __shared__ unsigned char meta[C::NG][C::OPG];
-  const int t = blockIdx.x;
+  T *tile = sm.tile;
+  auto &meta = sm.meta;
   const int maxcnt = tilemax[t];
   if (maxcnt == 0) return;  // uniform: empty tile
   const int xb = t / nyb;
@@ -250,6 +269,18 @@ __global__ __launch_bounds__(512) void stage2_kernel(
       }
     }
   }
+}
+
+template <class T, int R>
+__global__ __launch_bounds__(512) void stage2_kernel(
+    const T *__restrict__ F1, int64_t ld1, int64_t nx, const int64_t *__restrict__ tileoff,
+    const int32_t *__restrict__ tiley, const int32_t *__restrict__ tilemax,
+    const int32_t *__restrict__ yrows, const int32_t *__restrict__ perm, int nyb,
+    const T *__restrict__ S, int64_t ldS, int64_t nkeys, T coef, T *__restrict__ out, int64_t ldi,
+    int64_t ldr) {
+  __shared__ S2Smem<T, R> sm;
+  stage2_tile<T, R>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out,
+                    ldi, ldr, blockIdx.x, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -363,6 +394,56 @@ __global__ void fill_kernel(T *__restrict__ U, int64_t rows, int64_t cols, int64
   U[r + c * ld] = val;
 }
 
+// ---------------------------------------------------------------------------
+// Grouped kernels: one launch over the blocks of many independent problems.
+// Each workgroup reads its (problem, local block) item and the problem's
+// descriptor, then runs the same block body as the single-product kernels.
+// Problems whose active flag is 0 are skipped as a whole.
+static constexpr int kGroupPackBlock = 256;
+
+template <class T>
+__global__ __launch_bounds__(256) void group_pack_kernel(const GroupDesc<T> *__restrict__ desc,
+                                                         const GroupItem *__restrict__ items, int R,
+                                                         int64_t r0,
+                                                         const uint8_t *__restrict__ active) {
+  const GroupItem it = items[blockIdx.x];
+  if (active && !active[it.p]) return;
+  const GroupDesc<T> &d = desc[it.p];
+  const int64_t pos = (int64_t)it.li * kGroupPackBlock + threadIdx.x;
+  if (pos >= d.n_in) return;
+  const int64_t j = d.perm_in[pos];
+  const T *V = d.V + r0 * d.ldv;
+  for (int r = 0; r < R; ++r) d.vs[pos * R + r] = V[j + r * d.ldv];
+}
+
+template <class T, int R>
+__global__ __launch_bounds__(256) void group_stage1_kernel(const GroupDesc<T> *__restrict__ desc,
+                                                           const GroupItem *__restrict__ items,
+                                                           const uint8_t *__restrict__ active) {
+  __shared__ T stg[64 * (S1Cfg<T, R>::KB * R + 1)];
+  const GroupItem it = items[blockIdx.x];
+  if (active && !active[it.p]) return;
+  const GroupDesc<T> &d = desc[it.p];
+  const int nkb = (int)d.nkb;
+  const int kb = it.li % nkb, rb = it.li / nkb;
+  stage1_block<T, R>(d.Fc, d.ldc, d.rows, d.nrows, d.seg, d.other, d.vs, d.nkeys, d.S,
+                     sbuf_row_ld<T>(d.nkeys, R), kb, rb, stg);
+}
+
+template <class T, int R>
+__global__ __launch_bounds__(512) void group_stage2_kernel(const GroupDesc<T> *__restrict__ desc,
+                                                           const GroupItem *__restrict__ items,
+                                                           int64_t r0,
+                                                           const uint8_t *__restrict__ active) {
+  __shared__ S2Smem<T, R> sm;
+  const GroupItem it = items[blockIdx.x];
+  if (active && !active[it.p]) return;
+  const GroupDesc<T> &d = desc[it.p];
+  stage2_tile<T, R>(d.F1, d.ld1, d.nx, d.tileoff, d.tiley, d.tilemax, d.yrows, d.perm_out,
+                    (int)d.nyb, d.S, sbuf_row_ld<T>(d.nkeys, R), d.nkeys, T(1), d.U + r0 * d.ldu, 1,
+                    d.ldu, it.li, sm);
+}
+
 // ===========================================================================
 // Launchers
 // ===========================================================================
@@ -473,6 +554,48 @@ void launch_fill(T *U, int64_t rows, int64_t cols, int64_t ld, T val, hipStream_
   fill_kernel<T><<<grid1(rows * cols, 256), 256, 0, s>>>(U, rows, cols, ld, val);
 }
 
+int64_t group_pack_blocks(int64_t n_in) { return ceil_div(n_in, kGroupPackBlock); }
+
+int64_t group_stage1_blocks(int64_t nkeys, int64_t nrows) {
+  return ceil_div(nkeys, S1Cfg<double, 1>::KB) * ceil_div(nrows, 64);
+}
+
+template <class T>
+void launch_group_pack(const GroupDesc<T> *desc, const GroupItem *items, int64_t nitems, int R,
+                       int64_t r0, const uint8_t *active, hipStream_t s) {
+  if (nitems <= 0) return;
+  group_pack_kernel<T><<<(unsigned)nitems, kGroupPackBlock, 0, s>>>(desc, items, R, r0, active);
+}
+
+template <class T>
+void launch_group_stage1(const GroupDesc<T> *desc, const GroupItem *items, int64_t nitems, int R,
+                         const uint8_t *active, hipStream_t s) {
+  if (nitems <= 0) return;
+  const unsigned g = (unsigned)nitems;
+  switch (R) {
+    case 1: group_stage1_kernel<T, 1><<<g, 256, 0, s>>>(desc, items, active); break;
+    case 2: group_stage1_kernel<T, 2><<<g, 256, 0, s>>>(desc, items, active); break;
+    case 4: group_stage1_kernel<T, 4><<<g, 256, 0, s>>>(desc, items, active); break;
+    case 8: group_stage1_kernel<T, 8><<<g, 256, 0, s>>>(desc, items, active); break;
+    default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in grouped stage 1"};
+  }
+}
+
+template <class T>
+void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64_t nitems, int R,
+                         int64_t r0, const uint8_t *active, hipStream_t s) {
+  if (nitems <= 0) return;
+  const unsigned g = (unsigned)nitems;
+  const int nt = S2Cfg<T, 1>::NT;
+  switch (R) {
+    case 1: group_stage2_kernel<T, 1><<<g, nt, 0, s>>>(desc, items, r0, active); break;
+    case 2: group_stage2_kernel<T, 2><<<g, nt, 0, s>>>(desc, items, r0, active); break;
+    case 4: group_stage2_kernel<T, 4><<<g, nt, 0, s>>>(desc, items, r0, active); break;
+    case 8: group_stage2_kernel<T, 8><<<g, nt, 0, s>>>(desc, items, r0, active); break;
+    default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in grouped stage 2"};
+  }
+}
+
 #define GVT_INSTANTIATE(T)                                                                      \
   template void launch_pack_v<T>(const T *, int64_t, const int32_t *, int64_t, int, T *,          \
                                  hipStream_t);                                                   \
@@ -497,7 +620,13 @@ void launch_fill(T *U, int64_t rows, int64_t cols, int64_t ld, T val, hipStream_
                                     hipStream_t);                                                \
   template void launch_combine<T>(const CombineArgs<T> &, int64_t, int, T *, int64_t, int64_t,   \
                                   hipStream_t);                                                  \
-  template void launch_fill<T>(T *, int64_t, int64_t, int64_t, T, hipStream_t);
+  template void launch_fill<T>(T *, int64_t, int64_t, int64_t, T, hipStream_t);                 \
+  template void launch_group_pack<T>(const GroupDesc<T> *, const GroupItem *, int64_t, int,      \
+                                     int64_t, const uint8_t *, hipStream_t);                     \
+  template void launch_group_stage1<T>(const GroupDesc<T> *, const GroupItem *, int64_t, int,    \
+                                       const uint8_t *, hipStream_t);                            \
+  template void launch_group_stage2<T>(const GroupDesc<T> *, const GroupItem *, int64_t, int,    \
+                                       int64_t, const uint8_t *, hipStream_t);
 
 GVT_INSTANTIATE(double)
 GVT_INSTANTIATE(float)

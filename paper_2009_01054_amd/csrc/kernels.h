@@ -11,6 +11,13 @@ constexpr int kStage2Rows = 32;
 constexpr int kStage2MaxS = 64;
 constexpr int kMaxCombineOut = 8;
 
+// Row stride (elements) of a stage-1 buffer: nkeys x R values padded to whole
+// 1 KB chunks, the unit in which stage 2 copies S rows into LDS.
+template <class T> __host__ __device__ inline int64_t sbuf_row_ld(int64_t nkeys, int R) {
+  const int64_t chunk = 1024 / (int64_t)sizeof(T);
+  return (nkeys * R + chunk - 1) / chunk * chunk;
+}
+
 template <class T> struct CombineArgs {
   int nterms = 0;
   int nout = 0;
@@ -52,6 +59,61 @@ void launch_combine(const CombineArgs<T> &a, int64_t n, int R, T *U, int64_t ldu
                     int64_t block_stride, hipStream_t s);
 template <class T>
 void launch_fill(T *U, int64_t rows, int64_t cols, int64_t ld, T val, hipStream_t s);
+
+// ---- grouped launches over many independent single-term products ----------
+// One descriptor per problem holds everything a Kronecker-term product
+// u = stage2(F1, stage1(Fc, V)) needs; one launch covers the blocks of all
+// problems through a work list of (problem, local block) items.
+template <class T> struct GroupDesc {
+  // input vector (RHS r at V + r * ldv) and its key-ordered copy
+  const T *V;
+  int64_t ldv;
+  const int32_t *perm_in;
+  int64_t n_in;
+  T *vs;
+  // stage 1
+  const T *Fc;
+  int64_t ldc;
+  const int32_t *rows;
+  int64_t nrows;
+  const int64_t *seg;
+  const int32_t *other;
+  int64_t nkeys;
+  T *S;         // row stride sbuf_row_ld<T>(nkeys, R) for an R-column RHS block
+  int64_t nkb;  // stage-1 key blocks
+  // stage 2
+  const T *F1;
+  int64_t ld1;
+  int64_t nx;
+  const int64_t *tileoff;
+  const int32_t *tiley;
+  const int32_t *tilemax;
+  const int32_t *yrows;
+  const int32_t *perm_out;
+  int64_t nyb;
+  T *U;  // RHS r at U + r * ldu
+  int64_t ldu;
+};
+
+struct GroupItem {
+  int32_t p;   // problem
+  int32_t li;  // block within the problem
+};
+
+// Work items per problem for each grouped launch, in the problem's natural block order.
+int64_t group_pack_blocks(int64_t n_in);
+int64_t group_stage1_blocks(int64_t nkeys, int64_t nrows);
+
+// active[p] == 0 skips problem p (null: every problem runs).  r0: first RHS of the block.
+template <class T>
+void launch_group_pack(const GroupDesc<T> *desc, const GroupItem *items, int64_t nitems, int R,
+                       int64_t r0, const uint8_t *active, hipStream_t s);
+template <class T>
+void launch_group_stage1(const GroupDesc<T> *desc, const GroupItem *items, int64_t nitems, int R,
+                         const uint8_t *active, hipStream_t s);
+template <class T>
+void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64_t nitems, int R,
+                         int64_t r0, const uint8_t *active, hipStream_t s);
 
 // Dense complete-data path (matrix cores).
 void dense_matvec(int prec, const void *M, int64_t mr, int64_t mc, int64_t ldm, const void *N,

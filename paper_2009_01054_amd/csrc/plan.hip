@@ -315,11 +315,15 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       ts.fdot = t.a0; ts.x = t.a2; ts.y = t.a3;
       ts.sbuf = sbuf_index.at({t.a1, t.a4, t.a5});
       const SBufSpec &sb = P->sbufs[ts.sbuf];
-      // 2-D tiles: x blocks of kStage2Rows rows x S-row blocks; the number of
-      // S-row blocks is a multiple of 8 so that each XCD keeps one slice of S
+      // 2-D tiles: x blocks of kStage2Rows rows x S-row blocks of at most
+      // kStage2MaxS rows.  A large S is cut into a multiple of 8 row blocks so
+      // that each XCD keeps one slice of S in its L2; a small S (at most four
+      // blocks' worth of rows) into the fewest blocks.
       const int64_t nsr = std::max<int64_t>((int64_t)sb.rows.size(), 1);
       const int64_t nxr = std::max<int64_t>((ts.x == SA) ? d_rows : t_rows, 1);
-      const int64_t nyb = 8 * ceil_div(nsr, 8 * (int64_t)kStage2MaxS);
+      const int64_t nyb = nsr <= 4 * (int64_t)kStage2MaxS
+                              ? ceil_div(nsr, (int64_t)kStage2MaxS)
+                              : 8 * ceil_div(nsr, 8 * (int64_t)kStage2MaxS);
       const int64_t ybs = ceil_div(nsr, nyb);
       const int64_t nxb = ceil_div(nxr, kStage2Rows);
       // one stable counting sort on (tile, row inside the tile); the S-row order
@@ -414,8 +418,7 @@ template <class T> int prec_slot() { return sizeof(T) == 8 ? 0 : 1; }
 // Row stride of a stage-1 buffer in elements: keys x RHS padded to whole
 // 1 KB chunks (stage 2 copies rows chunk by chunk).  The padding is zero.
 template <class T> int64_t sbuf_ld(const gvt_plan *P, int i, int R) {
-  const int64_t chunk = 1024 / (int64_t)sizeof(T);
-  return ceil_div(nkeys_of(P, P->sbufs[i].key) * R, chunk) * chunk;
+  return sbuf_row_ld<T>(nkeys_of(P, P->sbufs[i].key), R);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }

@@ -305,3 +305,96 @@ def test_cg_not_converged_status(gvt):
     A, iters, rel, rc = gvt.gvt_krr_cg("kronecker", dev(p["D"]), dev(p["T"]), (idx(p["c"]), idx(p["e"])),
                                        dev(p["y"]), [1e-6], max_iter=1, tol=1e-12, check_every=1)
     assert rc == 1 and iters[0] == 1
+
+
+# ------------------------------------------------------------- batched CG
+def _batch(cfg, shapes, dim=8, hom=False):
+    probs = []
+    for pid, sh in enumerate(shapes):
+        if hom:
+            m, n = sh
+            p = W.make_homogeneous(cfg, pid, m, n, dim, kernel="gaussian")
+            p["y"] = np.random.default_rng([cfg, pid, 7]).standard_normal(n)
+        else:
+            m, q, n = sh
+            p = W.make_heterogeneous(cfg, pid, m, q, n, dim, labels=True)
+        probs.append(p)
+    return probs
+
+
+def _dev_problems(probs, hom=False):
+    return [dict(D=dev(p["D"]), T=None if hom else dev(p["T"]), c=idx(p["c"]), e=idx(p["e"]), y=dev(p["y"]))
+            for p in probs]
+
+
+@pytest.mark.parametrize("nlam", [3, 5])
+def test_cg_batched_f64_matches_oracle(gvt, nlam):
+    # uneven problems; nlam = 5 runs the products as RHS blocks of 4 and 1
+    shapes = [(23, 31, 400), (60, 17, 700), (41, 45, 1500), (12, 90, 500), (70, 70, 2100), (35, 9, 250)]
+    probs = _batch(95, shapes)
+    lams = [1e-1, 1.0, 10.0, 0.5, 3.0][:nlam]
+    A, iters, rel, rc = gvt.gvt_krr_cg_batched("kronecker", _dev_problems(probs), lams, max_iter=400,
+                                               tol=1e-8, check_every=4)
+    assert rc == 0
+    assert iters.shape == (len(probs), nlam) and (rel < 1e-8).all()
+    for k, p in enumerate(probs):
+        A_or, it_or, _, rt_or = oracle.krr_cg("kronecker", p["D"], p["T"], (p["c"], p["e"]), p["y"], lams,
+                                              max_iter=400, tol=1e-8)
+        a = A[k].cpu().numpy()
+        for l in range(nlam):
+            assert np.linalg.norm(a[:, l] - A_or[:, l]) / np.linalg.norm(A_or[:, l]) < 1e-7
+            # counts are a sanity check only: the chunked sums round differently, and near a
+            # tight tolerance single iterations move with summation order
+            assert abs(int(iters[k, l]) - int(it_or[l])) <= max(3, 0.1 * int(it_or[l]))
+
+
+def test_cg_batched_f32_products_certified(gvt):
+    shapes = [(60, 50, 1500), (30, 80, 1200), (45, 45, 900), (20, 20, 300)]
+    probs = _batch(96, shapes, dim=32)
+    lams = [1e-1, 1.0]
+    A, iters, rel, rc = gvt.gvt_krr_cg_batched("kronecker", _dev_problems(probs), lams, max_iter=300,
+                                               tol=1e-6, matvec_prec=gvt.F32)
+    assert rc == 0 and (rel < 1e-6).all()
+    for k, p in enumerate(probs):
+        A_or, _, _, rt_or = oracle.krr_cg("kronecker", p["D"], p["T"], (p["c"], p["e"]), p["y"], lams,
+                                          max_iter=300, tol=1e-6)
+        assert (rt_or < 1e-6).all()
+        a = A[k].cpu().numpy()
+        for l in range(len(lams)):
+            assert np.linalg.norm(a[:, l] - A_or[:, l]) / np.linalg.norm(A_or[:, l]) < 1e-4
+
+
+def test_cg_batched_homogeneous_kind(gvt):
+    # symmetric kind: two terms per product, run problem by problem inside the batch
+    probs = _batch(97, [(30, 300), (45, 600), (20, 150)], hom=True)
+    lams = [0.5, 2.0]
+    A, iters, rel, rc = gvt.gvt_krr_cg_batched("symmetric", _dev_problems(probs, hom=True), lams,
+                                               max_iter=300, tol=1e-8)
+    assert rc == 0 and (rel < 1e-8).all()
+    for k, p in enumerate(probs):
+        A_or, _, _, _ = oracle.krr_cg("symmetric", p["D"], None, (p["c"], p["e"]), p["y"], lams,
+                                      max_iter=300, tol=1e-8)
+        a = A[k].cpu().numpy()
+        for l in range(len(lams)):
+            assert np.linalg.norm(a[:, l] - A_or[:, l]) / np.linalg.norm(A_or[:, l]) < 1e-7
+
+
+def test_cg_batched_warm_start_and_cap(gvt):
+    shapes = [(25, 30, 500), (40, 20, 600), (33, 33, 800)]
+    probs = _batch(98, shapes)
+    lams = [1e-2, 1.0]
+    dp = _dev_problems(probs)
+    # warm start problem 1 from its converged solution: it must stop at once
+    A, iters, rel, rc = gvt.gvt_krr_cg_batched("kronecker", dp, lams, max_iter=500, tol=1e-9)
+    assert rc == 0
+    dp[1]["A0"] = A[1].clone()
+    A2, iters2, rel2, rc2 = gvt.gvt_krr_cg_batched("kronecker", dp, lams, max_iter=500, tol=1e-9)
+    assert rc2 == 0 and (iters2[1] <= 1).all() and (rel2 < 1e-9).all()
+    # bitwise reproducible for the problems without a warm start
+    for k in (0, 2):
+        assert torch.equal(A[k], A2[k])
+    # a cap too small for the small-lambda systems: status 1, results still written
+    A3, iters3, rel3, rc3 = gvt.gvt_krr_cg_batched("kronecker", _dev_problems(probs), lams, max_iter=3,
+                                                   tol=1e-12, check_every=2)
+    assert rc3 == 1 and (iters3 <= 3).all() and (iters3 >= 1).all()
+    assert np.isfinite(rel3).all() and (rel3 < 1.0).all()
