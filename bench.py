@@ -217,6 +217,74 @@ def preset_dense(args, gvt, W, torch, np, dev):
     return res
 
 
+def preset_batched(args, gvt, W, torch, np, dev):
+    """256 independent ridge problems x 8 lambdas in one batched CG solve (FP32 products,
+    FP64 CG), against FP64 products and against the plain form (one FP64 solve per problem
+    and lambda, host check every iteration)."""
+    import oracle
+
+    t_gen = time.perf_counter()
+    shapes = W.config5_shapes()
+    probs = [W.config5_problem(i, sh) for i, sh in enumerate(shapes)]
+    log(f"[bench] {len(probs)} problems generated in {time.perf_counter() - t_gen:.1f} s; "
+        f"sum n = {sum(sh[2] for sh in shapes)}")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    dp = [dict(D=t(p["D"]), T=t(p["T"]), c=t(p["c"]), e=t(p["e"]), y=t(p["y"])) for p in probs]
+    lams = list(W.LAMBDA_GRID)
+    theorem1 = [(min(q, len(set(p["e"]))) + m) * n for p, (m, q, n) in zip(probs, shapes)]
+    res = {"config": "batched ridge CG: 256 problems, m,q ~ U{50..1000}, n ~ U{1000..min(200000, mq/2)}, "
+                     "Gaussian bases (32-dim), 8 lambdas 1e-4..1e3, tol 1e-6, <= 200 iterations",
+           "sum_n": int(sum(sh[2] for sh in shapes)), "systems": len(probs) * len(lams)}
+    out = {}
+    for name, prec in [("f32", gvt.F32), ("f64", gvt.F64)]:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A, iters, rel, rc = gvt.gvt_krr_cg_batched("kronecker", dp, lams, max_iter=200, tol=1e-6,
+                                                   matvec_prec=prec, check_every=8)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[name] = (A, iters, rel)
+        res[name] = {"seconds": round(sec, 4), "status": int(rc), "iterations_max": int(iters.max()),
+                     "iterations_mean": round(float(iters.mean()), 2),
+                     "systems_converged": int((rel < 1e-6).sum()),
+                     "true_relres_max_converged": float(rel[rel < 1e-6].max()) if (rel < 1e-6).any() else None}
+        log(f"[bench] batched {name}: {sec:.3f} s, status {rc}, iterations mean {iters.mean():.1f} "
+            f"max {iters.max()}, converged {(rel < 1e-6).sum()} of {rel.size}")
+    # plain form on every 16th problem, scaled by the Theorem 1 cost share
+    sub = list(range(0, len(probs), 16))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in sub:
+        for lam in lams:
+            gvt.gvt_krr_cg("kronecker", dp[i]["D"], dp[i]["T"], (dp[i]["c"], dp[i]["e"]), dp[i]["y"], [lam],
+                           max_iter=200, tol=1e-6, matvec_prec=gvt.F64, check_every=1)
+    torch.cuda.synchronize()
+    sec_sub = time.perf_counter() - t0
+    scale = sum(theorem1) / sum(theorem1[i] for i in sub)
+    res["plain_f64"] = {"seconds_extrapolated": round(sec_sub * scale, 3), "measured_problems": len(sub),
+                        "measured_seconds": round(sec_sub, 3), "scale": round(scale, 3)}
+    res["speedup_f32_batched_vs_plain_f64"] = round(sec_sub * scale / res["f32"]["seconds"], 2)
+    res["speedup_f64_batched_vs_plain_f64"] = round(sec_sub * scale / res["f64"]["seconds"], 2)
+    log(f"[bench] plain f64 on {len(sub)} problems: {sec_sub:.2f} s -> {sec_sub * scale:.1f} s extrapolated")
+    # oracle CG on the four smallest problems
+    small = sorted(range(len(probs)), key=lambda i: shapes[i][2])[:4]
+    par = []
+    for i in small:
+        p = probs[i]
+        A_or, it_or, _, rt_or = oracle.krr_cg("kronecker", p["D"], p["T"], (p["c"], p["e"]), p["y"], lams,
+                                              max_iter=200, tol=1e-6)
+        for name in ("f32", "f64"):
+            A, iters, rel = out[name]
+            a = A[i].cpu().numpy()
+            err = [float(np.linalg.norm(a[:, l] - A_or[:, l]) / np.linalg.norm(A_or[:, l]))
+                   for l in range(len(lams))]
+            par.append({"problem": i, "shape": shapes[i], "products": name,
+                        "oracle_relres": [float(x) for x in rt_or], "gpu_relres": [float(x) for x in rel[i]],
+                        "solution_relerr": err})
+    res["oracle_parity_smallest4"] = par
+    return res
+
+
 def counter_workload(args, gvt, W, torch, np, dev):
     """Short run for hardware-counter passes: three products of the ridge workload in
     each precision and one elementwise copy of 512 MiB (256 MiB read, 256 MiB written),
@@ -254,10 +322,10 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=20)
     ap.add_argument("--counters", action="store_true",
                     help="run only the short kernel sequence that the hardware-counter passes read")
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4],
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
                     help="workload preset: 2 = ridge CG (the headline line); 1 = 64x64 Kronecker "
                          "product latency; 3 = fused four-kind product on 1M unordered pairs; "
-                         "4 = complete-data dense product (8192 x 4096)")
+                         "4 = complete-data dense product (8192 x 4096); 5 = batched CG of 256 problems")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -278,7 +346,8 @@ def main():
         print(json.dumps(counter_workload(args, gvt, W, torch, np, dev)), flush=True)
         return
     if args.config != 2:
-        fn = {1: preset_kronecker_latency, 3: preset_fused_kinds, 4: preset_dense}[args.config]
+        fn = {1: preset_kronecker_latency, 3: preset_fused_kinds, 4: preset_dense,
+              5: preset_batched}[args.config]
         print(json.dumps(fn(args, gvt, W, torch, np, dev)), flush=True)
         return
     t_gen = time.perf_counter()

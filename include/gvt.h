@@ -121,6 +121,11 @@ int gvt_plan_destroy(gvt_plan_t plan);
  * NULL for homogeneous kinds).  V: n_in x nrhs, column stride ldv.  U: the
  * plan's nkinds output blocks stacked, block k at U + k*nrhs*ldu, each
  * n_out x nrhs with column stride ldu.  Asynchronous on `stream`.
+ * Right-hand sides run in blocks of 8, 4, 2, 1; blocks of 1-2 and of 4-8
+ * use stage-2 tiles of their own.  The plan holds those for one RHS
+ * (gvt_plan_create); the first product with a block of 4 or more builds the
+ * other set (host work and a synchronous copy), so that first call must not
+ * be captured into a graph (GVT_ERR_ARG if it is).
  * Errors: GVT_ERR_ARG, GVT_ERR_UNSUPPORTED (GVT_BF16X3 on the gather path),
  * GVT_ERR_HIP, GVT_ERR_NOMEM.
  */

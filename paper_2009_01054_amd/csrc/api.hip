@@ -1,4 +1,5 @@
 // extern "C" entry points declared in include/gvt.h.
+#include <algorithm>
 #include <cstdarg>
 
 #include "plan.h"
@@ -117,7 +118,7 @@ static int oneshot(int prec, const int *kinds, int nkinds, const void *D, int64_
     hipStream_t s = (hipStream_t)stream;
     gvt_plan P;
     plan_build(&P, kinds, nkinds, d_rows, d_cols, t_rows, t_cols, out_a, out_b, n_out, in_c, in_e,
-               n_in, flags, s);
+               n_in, flags, s, (int)std::min<int64_t>(nrhs, 8));
     plan_execute(&P, prec, D, ldd, T, ldt, V, nrhs, ldv, U, ldu, s);
     GVT_HIP_CHECK(hipStreamSynchronize(s));
     return GVT_OK;

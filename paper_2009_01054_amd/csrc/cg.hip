@@ -255,7 +255,7 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
   CgRun run;
   run.plan = new gvt_plan();
   gvt_plan *P = run.plan;
-  plan_build(P, &kind, 1, d, d, t, t, c, e, n, c, e, n, GVT_FLAG_SYMMETRIC_BASES, s);
+  plan_build(P, &kind, 1, d, d, t, t, c, e, n, c, e, n, GVT_FLAG_SYMMETRIC_BASES, s, nlam);
   GVT_REQUIRE(!P->dense, GVT_ERR_UNSUPPORTED, "complete-data training grid: use the dense product");
 
   // workspace
@@ -699,7 +699,7 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     ps.plans.push_back(P);
     try {
       plan_build(P, &kind, 1, b.d, b.d, b.t, b.t, q.c, q.e, q.n, q.c, q.e, q.n,
-                 GVT_FLAG_SYMMETRIC_BASES, s);
+                 GVT_FLAG_SYMMETRIC_BASES, s, nlam);
     } catch (Error &e) {
       e.msg = "problem " + std::to_string(i) + ": " + e.msg;
       throw;
@@ -822,12 +822,14 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
       dsc.F1 = F[t.fdot];
       dsc.ld1 = ldF[t.fdot];
       dsc.nx = rows_of(P, t.fdot);
-      dsc.tileoff = t.g_tileoff.as<int64_t>();
-      dsc.tiley = t.g_tiley.as<int32_t>();
-      dsc.tilemax = t.g_tilemax.as<int32_t>();
-      dsc.yrows = t.g_yrows.as<int32_t>();
-      dsc.perm_out = t.g_perm.as<int32_t>();
-      dsc.nyb = t.nyb;
+      // one tile set serves every RHS block of the batch: that of the largest block
+      const TileSet &tl = t.tiles[tile_class(Rmax)];
+      dsc.tileoff = tl.tileoff.as<int64_t>();
+      dsc.tiley = tl.tiley.as<int32_t>();
+      dsc.tilemax = tl.tilemax.as<int32_t>();
+      dsc.yrows = tl.yrows.as<int32_t>();
+      dsc.perm_out = tl.perm.as<int32_t>();
+      dsc.nyb = tl.nyb;
       dsc.U = U;
       dsc.ldu = pb[i].n;
     };
@@ -850,7 +852,8 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
       const GroupDesc<double> &g = h64[i];
       const int64_t np = group_pack_blocks(g.n_in);
       const int64_t n1 = group_stage1_blocks(g.nkeys, g.nrows);
-      const int64_t n2 = ps.plans[i]->terms[ps.plans[i]->outputs[0][0].first].ntiles;
+      const int64_t n2 =
+          ps.plans[i]->terms[ps.plans[i]->outputs[0][0].first].tiles[tile_class(Rmax)].ntiles;
       GVT_REQUIRE(np < (1 << 30) && n1 < (1 << 30) && n2 < (1 << 30), GVT_ERR_ARG, "problem too large");
       for (int64_t k = 0; k < np; ++k) hp.push_back({i, (int32_t)k});
       for (int64_t k = 0; k < n1; ++k) h1.push_back({i, (int32_t)k});

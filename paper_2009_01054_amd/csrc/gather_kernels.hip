@@ -171,7 +171,10 @@ template <class T, int R> struct S2Cfg {
   static constexpr int ROWE = 1024 / sizeof(T);    // tile row: 1 KB
   static constexpr int KC = ROWE / R;              // keys per chunk
   static constexpr int STEPS = KC / (LPO * KPL);
-  static constexpr int OPG = (32 / R) > 4 ? 32 / R : 4;  // outputs per group per pass
+  // outputs per group per pass: 32 accumulators per lane, 64 for FP32 with
+  // four or more RHS (fewer passes, each re-copying the S tile)
+  static constexpr int ACC = (sizeof(T) == 4 && R >= 4) ? 64 : 32;
+  static constexpr int OPG = (ACC / R) > 4 ? ACC / R : 4;
   static constexpr int PADE = VEC;                 // +16 B per tile row
   static_assert(STEPS >= 1, "chunk smaller than one step");
 };

@@ -39,18 +39,30 @@ struct SBufSpec {  // one stage-1 result S = scatter of F_sc by `key` with colum
 
 enum TermType { TG = 0, TO = 1, TM = 2 };
 
+// Stage-2 tiles of one two-factor term for one S-row block size.  Outputs are
+// ordered by (x block, S-row block, x, S row); tiles are numbered
+// x_block * nyb + y_block.
+struct TileSet {
+  bool built = false;
+  int ysz = 0;          // S rows per block (<= kStage2MaxS)
+  DevMem perm, yrows;   // int32[n_out] per position
+  DevMem tileoff;       // int64[ntiles * (kStage2Rows + 1)]: start of each x row in a tile
+  DevMem tiley;         // int32[2 * ntiles]: first S row and S-row count of the tile
+  DevMem tilemax;       // int32[ntiles]: largest per-row output count in the tile
+  int64_t ntiles = 0;
+  int nyb = 0;
+  DevMem blob;          // the arrays' allocation when built after the plan
+};
+
+// RHS classes with their own stage-2 tiles: [0] blocks of 1-2 RHS, [1] of 4-8.
+constexpr int kTileClasses = 2;
+inline int tile_class(int R) { return R >= 4 ? 1 : 0; }
+
 struct TermSpec {
   int type = TG;
   // G (two-factor Kronecker term):  u_i = sum_k F_dot[x_i, k] S[y_i, k]
   int fdot = FD, x = SA, y = SB, sbuf = -1;
-  // outputs ordered by (x block, S-row block, x, S row); tiles numbered
-  // x_block * nyb + y_block
-  DevMem g_perm, g_yrows;  // int32[n_out] per position
-  DevMem g_tileoff;        // int64[ntiles * (kStage2Rows + 1)]: start of each x row in a tile
-  DevMem g_tiley;          // int32[2 * ntiles]: first S row and S-row count of the tile
-  DevMem g_tilemax;        // int32[ntiles]: largest per-row output count in the tile
-  int64_t ntiles = 0;
-  int nyb = 0;
+  TileSet tiles[kTileClasses];
   // O (one-factor term):  u_i = g[x_i], g = F^{o(1|2)} segsum_key
   int gemv = -1;
   // M (Cartesian sparse match):  u_i = sum_{j: key_j = outkey_i} F[x_i, other_j] v_j
@@ -84,6 +96,7 @@ struct gvt_plan {
   gvt::DevMem idx[4];  // device copies of a, b, c, e (int32), when a term reads them
   gvt::InputSort insort[2];   // [0]: by c (other = e), [1]: by e (other = c)
   gvt::OutOrder outord[2];    // [0]: grouped by a, [1]: grouped by b
+  std::vector<int32_t> h_out[2];  // host copies of a, b (stage-2 tiles built on demand)
   std::vector<gvt::SBufSpec> sbufs;
   std::vector<gvt::GemvSpec> gemvs;
   std::vector<gvt::TermSpec> terms;
@@ -103,9 +116,19 @@ enum Stage { ST_PREP = 0, ST_STAGE1 = 1, ST_STAGE2 = 2, ST_OTHER = 3, kStages = 
 int64_t rows_of(const gvt_plan *P, int f);
 int64_t cols_of(const gvt_plan *P, int f);
 int64_t nkeys_of(const gvt_plan *P, int key);
+// rhs_hint: the number of right-hand sides the caller expects; the stage-2
+// tiles of its class are built now, those of the other class on first use.
 void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64_t d_cols,
                 int64_t t_rows, int64_t t_cols, const int32_t *a, const int32_t *b, int64_t n_out,
-                const int32_t *c, const int32_t *e, int64_t n_in, int flags, hipStream_t s);
+                const int32_t *c, const int32_t *e, int64_t n_in, int flags, hipStream_t s,
+                int rhs_hint = 1);
+// Build the stage-2 tiles of RHS class `cls` for every two-factor term (no-op
+// when built).  Synchronous host work and a copy: not allowed while `s` is
+// being captured.
+void plan_ensure_tiles(gvt_plan *P, int cls, hipStream_t s);
+// S rows per stage-2 block for a term: from the tuning target of the class
+// (or the GVT_STAGE2_TARGET_R1 / GVT_STAGE2_TARGET_R8 environment override).
+int stage2_block_rows(const gvt_plan *P, const TermSpec &t, int cls);
 void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,
                   const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu, hipStream_t s);
 void plan_profile(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,

@@ -19,6 +19,7 @@
 #include <cstdlib>
 
 #include "plan.h"
+#include "tuning.h"
 
 namespace gvt {
 
@@ -115,11 +116,118 @@ int64_t count_unique(const std::vector<int32_t> &v, int64_t range) {
   return u;
 }
 
+// Stage-2 tuning targets (tuning.h): outputs per F1 row per tile that each
+// RHS class aims for (a pass over a tile serves a fixed number of outputs per
+// row, and every pass re-copies the tile's S rows).  Overridable for tuning
+// sweeps.
+double stage2_target(int cls) {
+  const char *ev = std::getenv(cls ? "GVT_STAGE2_TARGET_R8" : "GVT_STAGE2_TARGET_R1");
+  if (ev) {
+    const double v = std::atof(ev);
+    if (v > 0) return v;
+  }
+  return cls ? kStage2TargetR8 : kStage2TargetR1;
+}
+
 }  // namespace
+
+int stage2_block_rows(const gvt_plan *P, const TermSpec &t, int cls) {
+  const SBufSpec &sb = P->sbufs[t.sbuf];
+  const double nsr = (double)std::max<size_t>(sb.rows.size(), 1);
+  const double nx = (double)std::max<int64_t>(P->uniq[t.x], 1);
+  const double rho = (double)P->n_out / (nx * nsr);  // outputs per (F1 row, S row)
+  double rows = rho > 0 ? stage2_target(cls) / rho : kStage2MaxS;
+  int ysz = (int)std::ceil(std::min<double>(std::max<double>(rows, 8.0), kStage2MaxS) / 8.0) * 8;
+  return std::min(ysz, kStage2MaxS);
+}
+
+namespace {
+
+// Stage-2 tiles of term `ts` for RHS class `cls`.  2-D tiles: x blocks of
+// kStage2Rows rows x S-row blocks of at most stage2_block_rows() rows.  More
+// than four blocks are rounded up to a multiple of 8 so that each XCD keeps
+// one slice of S in its L2.  One stable counting sort on (tile, row inside
+// the tile) orders the outputs; the S-row order inside a row group does not
+// matter.  With `up` the arrays join the plan's upload, else they are copied
+// into the tile set's own allocation at once.
+void build_tile_set(gvt_plan *P, TermSpec &ts, int cls, Uploads *up) {
+  TileSet &tl = ts.tiles[cls];
+  if (tl.built) return;
+  const SBufSpec &sb = P->sbufs[ts.sbuf];
+  const std::vector<int32_t> &hx = P->h_out[ts.x == SA ? 0 : 1];
+  const std::vector<int32_t> &hy = P->h_out[ts.y == SA ? 0 : 1];
+  const int64_t n_out = P->n_out;
+  const int ysz = stage2_block_rows(P, ts, cls);
+  const int64_t nsr = std::max<int64_t>((int64_t)sb.rows.size(), 1);
+  const int64_t nxr = std::max<int64_t>(rows_of(P, ts.fdot), 1);
+  int64_t nyb = ceil_div(nsr, (int64_t)ysz);
+  if (nyb > 4) nyb = 8 * ceil_div(nyb, (int64_t)8);
+  const int64_t ybs = ceil_div(nsr, nyb);
+  const int64_t nxb = ceil_div(nxr, kStage2Rows);
+  const int64_t ntiles = nxb * nyb;
+  GVT_REQUIRE(ntiles * kStage2Rows < INT32_MAX, GVT_ERR_ARG, "too many stage-2 tiles");
+  std::vector<int32_t> yrow_of(n_out), tkey(n_out);
+  for (int64_t i = 0; i < n_out; ++i) {
+    yrow_of[i] = sb.rowmap[hy[i]];
+    const int64_t xv = hx[i];
+    const int64_t tile_id = (xv / kStage2Rows) * nyb + yrow_of[i] / ybs;
+    tkey[i] = (int32_t)(tile_id * kStage2Rows + xv % kStage2Rows);
+  }
+  std::vector<int32_t> pc;
+  std::vector<int64_t> sgk;
+  counting_sort(tkey, ntiles * kStage2Rows, pc, sgk);
+  std::vector<int32_t> gperm(n_out), gy(n_out);
+  for (int64_t q = 0; q < n_out; ++q) {
+    const int32_t i = pc[q];
+    gperm[q] = i;
+    gy[q] = yrow_of[i];
+  }
+  std::vector<int64_t> toff((size_t)ntiles * (kStage2Rows + 1));
+  std::vector<int32_t> tiley((size_t)2 * ntiles), tmax(ntiles, 0);
+  for (int64_t tt = 0; tt < ntiles; ++tt) {
+    const int64_t yb = tt % nyb;
+    tiley[2 * tt] = (int32_t)std::min<int64_t>(yb * ybs, nsr);
+    tiley[2 * tt + 1] = (int32_t)std::max<int64_t>(0, std::min<int64_t>(ybs, nsr - yb * ybs));
+    for (int g = 0; g <= kStage2Rows; ++g)
+      toff[(size_t)tt * (kStage2Rows + 1) + g] = sgk[(size_t)tt * kStage2Rows + g];
+    for (int g = 0; g < kStage2Rows; ++g) {
+      const int64_t c = sgk[(size_t)tt * kStage2Rows + g + 1] - sgk[(size_t)tt * kStage2Rows + g];
+      tmax[tt] = std::max<int32_t>(tmax[tt], (int32_t)c);
+    }
+  }
+  tl.ysz = ysz;
+  tl.ntiles = ntiles;
+  tl.nyb = (int)nyb;
+  Uploads local;
+  Uploads &u = up ? *up : local;
+  u.add(tl.perm, gperm);
+  u.add(tl.yrows, gy);
+  u.add(tl.tileoff, toff);
+  u.add(tl.tiley, tiley);
+  u.add(tl.tilemax, tmax);
+  if (!up) local.commit(tl.blob);
+  tl.built = true;
+}
+
+}  // namespace
+
+void plan_ensure_tiles(gvt_plan *P, int cls, hipStream_t s) {
+  bool need = false;
+  for (const TermSpec &t : P->terms) need = need || (t.type == TG && !t.tiles[cls].built);
+  if (!need || P->n_out == 0) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (s && hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    throw Error{GVT_ERR_ARG,
+                "the first product with a new RHS block size builds stage-2 tiles and cannot be "
+                "captured; run it once before capturing"};
+  for (TermSpec &t : P->terms)
+    if (t.type == TG) build_tile_set(P, t, cls, nullptr);
+}
 
 void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64_t d_cols,
                 int64_t t_rows, int64_t t_cols, const int32_t *a, const int32_t *b, int64_t n_out,
-                const int32_t *c, const int32_t *e, int64_t n_in, int flags, hipStream_t s) {
+                const int32_t *c, const int32_t *e, int64_t n_in, int flags, hipStream_t s,
+                int rhs_hint) {
   GVT_REQUIRE(kinds && nkinds >= 1, GVT_ERR_ARG, "kinds must be a non-empty host array");
   GVT_REQUIRE(nkinds <= kMaxCombineOut, GVT_ERR_ARG, "at most 8 kinds per plan");
   GVT_REQUIRE(d_rows >= 0 && d_cols >= 0 && t_rows >= 0 && t_cols >= 0 && n_out >= 0 && n_in >= 0,
@@ -175,6 +283,8 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   }
   tm.lap("validate + unique");
   Uploads up;
+  P->h_out[0] = h[0];
+  P->h_out[1] = h[1];
 
   // ---- complete data: both pair sets are the full grid in natural order ----
   if (nkinds == 1 && P->kinds[0] == GVT_KRONECKER && n_in == d_cols * t_cols &&
@@ -315,56 +425,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       ts.fdot = t.a0; ts.x = t.a2; ts.y = t.a3;
       ts.sbuf = sbuf_index.at({t.a1, t.a4, t.a5});
       const SBufSpec &sb = P->sbufs[ts.sbuf];
-      // 2-D tiles: x blocks of kStage2Rows rows x S-row blocks of at most
-      // kStage2MaxS rows.  A large S is cut into a multiple of 8 row blocks so
-      // that each XCD keeps one slice of S in its L2; a small S (at most four
-      // blocks' worth of rows) into the fewest blocks.
-      const int64_t nsr = std::max<int64_t>((int64_t)sb.rows.size(), 1);
-      const int64_t nxr = std::max<int64_t>((ts.x == SA) ? d_rows : t_rows, 1);
-      const int64_t nyb = nsr <= 4 * (int64_t)kStage2MaxS
-                              ? ceil_div(nsr, (int64_t)kStage2MaxS)
-                              : 8 * ceil_div(nsr, 8 * (int64_t)kStage2MaxS);
-      const int64_t ybs = ceil_div(nsr, nyb);
-      const int64_t nxb = ceil_div(nxr, kStage2Rows);
-      // one stable counting sort on (tile, row inside the tile); the S-row order
-      // inside a row group does not matter
-      const int64_t ntiles = nxb * nyb;
-      std::vector<int32_t> yrow_of(n_out), tkey(n_out);
-      for (int64_t i = 0; i < n_out; ++i) {
-        yrow_of[i] = sb.rowmap[h[ts.y][i]];
-        const int64_t xv = h[ts.x][i];
-        const int64_t tile_id = (xv / kStage2Rows) * nyb + yrow_of[i] / ybs;
-        tkey[i] = (int32_t)(tile_id * kStage2Rows + xv % kStage2Rows);
-      }
-      std::vector<int32_t> pc;
-      std::vector<int64_t> sgk;
-      counting_sort(tkey, ntiles * kStage2Rows, pc, sgk);
-      std::vector<int32_t> gperm(n_out), gy(n_out);
-      for (int64_t q = 0; q < n_out; ++q) {
-        const int32_t i = pc[q];
-        gperm[q] = i;
-        gy[q] = yrow_of[i];
-      }
-      std::vector<int64_t> toff((size_t)ntiles * (kStage2Rows + 1));
-      std::vector<int32_t> tiley((size_t)2 * ntiles), tmax(ntiles, 0);
-      for (int64_t tt = 0; tt < ntiles; ++tt) {
-        const int64_t yb = tt % nyb;
-        tiley[2 * tt] = (int32_t)std::min<int64_t>(yb * ybs, nsr);
-        tiley[2 * tt + 1] = (int32_t)std::max<int64_t>(0, std::min<int64_t>(ybs, nsr - yb * ybs));
-        for (int g = 0; g <= kStage2Rows; ++g)
-          toff[(size_t)tt * (kStage2Rows + 1) + g] = sgk[(size_t)tt * kStage2Rows + g];
-        for (int g = 0; g < kStage2Rows; ++g) {
-          const int64_t c = sgk[(size_t)tt * kStage2Rows + g + 1] - sgk[(size_t)tt * kStage2Rows + g];
-          tmax[tt] = std::max<int32_t>(tmax[tt], (int32_t)c);
-        }
-      }
-      ts.ntiles = ntiles;
-      ts.nyb = (int)nyb;
-      up.add(ts.g_perm, gperm);
-      up.add(ts.g_yrows, gy);
-      up.add(ts.g_tileoff, toff);
-      up.add(ts.g_tiley, tiley);
-      up.add(ts.g_tilemax, tmax);
+      if (n_out > 0) build_tile_set(P, ts, tile_class(rhs_hint), &up);
       P->cost_fma += g_cost(t);
     } else if (t.type == TO) {
       auto gk = std::make_tuple(t.a0, t.a1, t.a3);
@@ -540,9 +601,10 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
       const SBufSpec &sb = P->sbufs[t.sbuf];
       T *out = P->direct ? U : wsp<T>(P, W.tvec[ti]);
       const int64_t ldi = P->direct ? 1 : R, ldr = P->direct ? ldu : 1;
-      launch_stage2<T>(F[t.fdot], ldF[t.fdot], rows_of(P, t.fdot), t.g_tileoff.as<int64_t>(),
-                       t.g_tiley.as<int32_t>(), t.g_tilemax.as<int32_t>(), t.ntiles, t.nyb,
-                       t.g_yrows.as<int32_t>(), t.g_perm.as<int32_t>(), wsp<T>(P, W.sbuf[t.sbuf]),
+      const TileSet &tl = t.tiles[tile_class(R)];
+      launch_stage2<T>(F[t.fdot], ldF[t.fdot], rows_of(P, t.fdot), tl.tileoff.as<int64_t>(),
+                       tl.tiley.as<int32_t>(), tl.tilemax.as<int32_t>(), tl.ntiles, tl.nyb,
+                       tl.yrows.as<int32_t>(), tl.perm.as<int32_t>(), wsp<T>(P, W.sbuf[t.sbuf]),
                        sbuf_ld<T>(P, t.sbuf, R), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s);
     }
   }
@@ -589,6 +651,7 @@ void execute_t(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ldt, c
   while (r0 < nrhs) {
     const int64_t left = nrhs - r0;
     const int R = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    plan_ensure_tiles(P, tile_class(R), s);
     execute_block<T>(P, D, ldd, Tm, ldt, V + r0 * ldv, R, ldv, U + r0 * ldu, ldu, block_stride, s);
     r0 += R;
   }
