@@ -778,9 +778,14 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
   // (p32 -> w32), [2] FP64 residual product (w -> wraw)
   GroupDesc<double> *dd_it = nullptr, *dd_res = nullptr;
   GroupDesc<float> *df_it = nullptr;
-  GroupItem *it_pack = nullptr, *it_s1 = nullptr, *it_s2 = nullptr;
-  int64_t n_pack = 0, n_s1 = 0, n_s2 = 0;
+  GroupItem *it_pack = nullptr, *it_s1 = nullptr, *it_s2[kTileClasses] = {nullptr, nullptr};
+  int64_t n_pack = 0, n_s1 = 0, n_s2[kTileClasses] = {0, 0};
+  bool need_cls[kTileClasses] = {false, false};
+  for (int64_t r0 = 0; r0 < nlam; r0 += rhs_block(nlam - r0)) need_cls[tile_class(rhs_block(nlam - r0))] = true;
   if (grouped) {
+    for (gvt_plan *P : ps.plans)
+      for (int cls = 0; cls < kTileClasses; ++cls)
+        if (need_cls[cls]) plan_ensure_tiles(P, cls, s);
     std::vector<size_t> vs_off(nprob), S_off(nprob);
     size_t vs_tot = 0, S_tot = 0;
     for (int i = 0; i < nprob; ++i) {
@@ -822,14 +827,15 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
       dsc.F1 = F[t.fdot];
       dsc.ld1 = ldF[t.fdot];
       dsc.nx = rows_of(P, t.fdot);
-      // one tile set serves every RHS block of the batch: that of the largest block
-      const TileSet &tl = t.tiles[tile_class(Rmax)];
-      dsc.tileoff = tl.tileoff.as<int64_t>();
-      dsc.tiley = tl.tiley.as<int32_t>();
-      dsc.tilemax = tl.tilemax.as<int32_t>();
-      dsc.yrows = tl.yrows.as<int32_t>();
-      dsc.perm_out = tl.perm.as<int32_t>();
-      dsc.nyb = tl.nyb;
+      for (int cls = 0; cls < kTileClasses; ++cls) {  // unbuilt classes stay unused
+        const TileSet &tl = t.tiles[cls];
+        dsc.tileoff[cls] = tl.tileoff.as<int64_t>();
+        dsc.tiley[cls] = tl.tiley.as<int32_t>();
+        dsc.tilemax[cls] = tl.tilemax.as<int32_t>();
+        dsc.yrows[cls] = tl.yrows.as<int32_t>();
+        dsc.perm_out[cls] = tl.perm.as<int32_t>();
+        dsc.nyb[cls] = tl.nyb;
+      }
       dsc.U = U;
       dsc.ldu = pb[i].n;
     };
@@ -847,21 +853,26 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
       return ps.plans[x]->cost_fma > ps.plans[y]->cost_fma;
     });
-    std::vector<GroupItem> hp, h1, h2;
+    std::vector<GroupItem> hp, h1, h2[kTileClasses];
     for (int i : order) {
       const GroupDesc<double> &g = h64[i];
       const int64_t np = group_pack_blocks(g.n_in);
       const int64_t n1 = group_stage1_blocks(g.nkeys, g.nrows);
-      const int64_t n2 =
-          ps.plans[i]->terms[ps.plans[i]->outputs[0][0].first].tiles[tile_class(Rmax)].ntiles;
-      GVT_REQUIRE(np < (1 << 30) && n1 < (1 << 30) && n2 < (1 << 30), GVT_ERR_ARG, "problem too large");
+      GVT_REQUIRE(np < (1 << 30) && n1 < (1 << 30), GVT_ERR_ARG, "problem too large");
       for (int64_t k = 0; k < np; ++k) hp.push_back({i, (int32_t)k});
       for (int64_t k = 0; k < n1; ++k) h1.push_back({i, (int32_t)k});
-      for (int64_t k = 0; k < n2; ++k) h2.push_back({i, (int32_t)k});
+      const TermSpec &t = ps.plans[i]->terms[ps.plans[i]->outputs[0][0].first];
+      for (int cls = 0; cls < kTileClasses; ++cls) {
+        if (!need_cls[cls]) continue;
+        const int64_t n2 = t.tiles[cls].ntiles;
+        GVT_REQUIRE(n2 < (1 << 30), GVT_ERR_ARG, "problem too large");
+        for (int64_t k = 0; k < n2; ++k) h2[cls].push_back({i, (int32_t)k});
+      }
     }
     n_pack = (int64_t)hp.size();
     n_s1 = (int64_t)h1.size();
-    n_s2 = (int64_t)h2.size();
+    n_s2[0] = (int64_t)h2[0].size();
+    n_s2[1] = (int64_t)h2[1].size();
     const size_t dsz64 = sizeof(GroupDesc<double>) * nprob, dsz32 = sizeof(GroupDesc<float>) * nprob;
     char *db = (char *)m_desc.ensure(2 * dsz64 + dsz32 + 256);
     dd_it = (GroupDesc<double> *)db;
@@ -871,13 +882,18 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     GVT_HIP_CHECK(hipMemcpyAsync(dd_res, hres.data(), dsz64, hipMemcpyHostToDevice, s));
     if (mprec == GVT_F32)
       GVT_HIP_CHECK(hipMemcpyAsync(df_it, h32.data(), dsz32, hipMemcpyHostToDevice, s));
-    GroupItem *ib = (GroupItem *)m_items.ensure(sizeof(GroupItem) * (n_pack + n_s1 + n_s2));
+    GroupItem *ib =
+        (GroupItem *)m_items.ensure(sizeof(GroupItem) * (n_pack + n_s1 + n_s2[0] + n_s2[1] + 1));
     it_pack = ib;
     it_s1 = ib + n_pack;
-    it_s2 = ib + n_pack + n_s1;
+    it_s2[0] = ib + n_pack + n_s1;
+    it_s2[1] = ib + n_pack + n_s1 + n_s2[0];
     GVT_HIP_CHECK(hipMemcpyAsync(it_pack, hp.data(), sizeof(GroupItem) * n_pack, hipMemcpyHostToDevice, s));
     GVT_HIP_CHECK(hipMemcpyAsync(it_s1, h1.data(), sizeof(GroupItem) * n_s1, hipMemcpyHostToDevice, s));
-    GVT_HIP_CHECK(hipMemcpyAsync(it_s2, h2.data(), sizeof(GroupItem) * n_s2, hipMemcpyHostToDevice, s));
+    for (int cls = 0; cls < kTileClasses; ++cls)
+      if (n_s2[cls])
+        GVT_HIP_CHECK(hipMemcpyAsync(it_s2[cls], h2[cls].data(), sizeof(GroupItem) * n_s2[cls],
+                                     hipMemcpyHostToDevice, s));
     // the host vectors above are released at scope end: wait for the copies
     GVT_HIP_CHECK(hipStreamSynchronize(s));
   }
@@ -888,7 +904,7 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
       const int R = rhs_block(nlam - r0);
       launch_group_pack(desc, it_pack, n_pack, R, r0, mask, s);
       launch_group_stage1(desc, it_s1, n_s1, R, mask, s);
-      launch_group_stage2(desc, it_s2, n_s2, R, r0, mask, s);
+      launch_group_stage2(desc, it_s2[tile_class(R)], n_s2[tile_class(R)], R, r0, mask, s);
       r0 += R;
     }
   };

@@ -287,6 +287,133 @@ __global__ __launch_bounds__(512) void stage2_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Stage 2 for blocks of R >= 4 right-hand sides, grouped by S row.  Each S
+// element carries R values, so the roles swap: a 16-lane group owns one S row
+// and holds that row's slice of the current key chunk (KPL keys x R values per
+// lane) in registers, loaded once per chunk; the tile's F1 rows (at most
+// kStage2MaxS of them) are staged in LDS, and every output of the row costs
+// one 16-byte LDS read per KPL x R FMAs.  Tiles: 32 consecutive compact S rows
+// x one block of F1 rows, outputs ordered by (tile, S row, F1 row).
+template <class T, int R> struct S2yCfg {
+  static_assert(R >= 4, "S-row grouped stage 2 is for blocks of 4 or more RHS");
+  static constexpr int LPO = 16;                         // lanes per S row / output
+  static constexpr int NG = kStage2Rows;                 // S rows per tile (32)
+  static constexpr int NT = NG * LPO;                    // 512 threads
+  static constexpr int KPL = 16 / (int)sizeof(T);        // keys per lane per chunk (one 16-byte F1 read)
+  static constexpr int KC = LPO * KPL;                   // keys per chunk
+  static constexpr int ACC = sizeof(T) == 4 ? 64 : 32;   // accumulators per lane
+  static constexpr int OPG = ACC / R;                    // outputs per row per pass
+  static constexpr int FROW = KC + 16 / (int)sizeof(T);  // LDS row: chunk + 16 B
+  static_assert(KPL * sizeof(T) == 16, "one 16-byte LDS read per output and chunk");
+};
+
+template <class T, int R> struct S2ySmem {
+  __attribute__((aligned(16))) T ftile[kStage2MaxS * S2yCfg<T, R>::FROW];
+  unsigned char meta[S2yCfg<T, R>::NG][S2yCfg<T, R>::OPG];
+};
+
+template <class T, int R>
+__device__ __forceinline__ void stage2y_tile(
+    const T *__restrict__ F1, int64_t ld1, const int64_t *__restrict__ tileoff,
+    const int32_t *__restrict__ tilex, const int32_t *__restrict__ tilemax,
+    const int32_t *__restrict__ xrows, const int32_t *__restrict__ perm, int nxb,
+    const T *__restrict__ S, int64_t ldS, int64_t nsr, int64_t nkeys, T coef, T *__restrict__ out,
+    int64_t ldi, int64_t ldr, int t, S2ySmem<T, R> &sm) {
+  typedef S2yCfg<T, R> C;
+  typedef typename Vec16<T>::type V16;
+  constexpr int VEC = 16 / sizeof(T);
+  const int maxcnt = tilemax[t];
+  if (maxcnt == 0) return;  // uniform: empty tile
+  const int gb = t / nxb;
+  const int64_t x0 = tilex[2 * t], nxr = tilex[2 * t + 1];
+  const int sub = threadIdx.x % C::LPO, grp = threadIdx.x / C::LPO;
+  const int64_t yrow = (int64_t)gb * C::NG + grp;
+  const int64_t qb = tileoff[(int64_t)t * (C::NG + 1) + grp];
+  const int cnt = (int)(tileoff[(int64_t)t * (C::NG + 1) + grp + 1] - qb);
+  const T *srow = S + (yrow < nsr ? yrow : 0) * ldS;
+  const int64_t nch = (nkeys + C::KC - 1) / C::KC;
+  for (int pass0 = 0; pass0 < maxcnt; pass0 += C::OPG) {
+    const int npass = (cnt - pass0) < C::OPG ? (cnt - pass0) : C::OPG;  // may be <= 0
+    __syncthreads();
+    for (int o = sub; o < C::OPG; o += C::LPO)
+      sm.meta[grp][o] = (o < npass) ? (unsigned char)(xrows[qb + pass0 + o] - x0) : 0;
+    T acc[C::OPG][R];
+#pragma unroll
+    for (int o = 0; o < C::OPG; ++o)
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[o][r] = T(0);
+    for (int64_t c = 0; c < nch; ++c) {
+      const int64_t k0 = c * C::KC;
+      __syncthreads();
+      // F1 rows of the tile, this chunk's keys (zero past the last key)
+      for (int idx = threadIdx.x; idx < nxr * C::KC; idx += C::NT) {
+        const int row = idx / C::KC, kk = idx - row * C::KC;
+        const int64_t k = k0 + kk;
+        sm.ftile[row * C::FROW + kk] = k < nkeys ? F1[(x0 + row) * ld1 + k] : T(0);
+      }
+      // this lane's S slice: keys k0 + sub*KPL .. + KPL-1, R values each (KPL x R registers)
+      T sv[C::KPL][R];
+#pragma unroll
+      for (int kk = 0; kk < C::KPL; ++kk) {
+        const int64_t k = k0 + sub * C::KPL + kk;
+        const bool ok = npass > 0 && k < nkeys;
+#pragma unroll
+        for (int r0 = 0; r0 < R; r0 += VEC) {
+          V16 v;
+          if (ok) {
+            v = *reinterpret_cast<const V16 *>(srow + k * R + r0);
+          } else {
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) v[u] = T(0);
+          }
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) sv[kk][r0 + u] = v[u];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int o = 0; o < C::OPG; ++o) {
+        if (o < npass) {
+          const V16 f = *reinterpret_cast<const V16 *>(sm.ftile + (int)sm.meta[grp][o] * C::FROW +
+                                                       sub * C::KPL);
+#pragma unroll
+          for (int kk = 0; kk < C::KPL; ++kk)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[o][r] += f[kk] * sv[kk][r];
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < C::OPG; ++o) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        T v = acc[o][r];
+#pragma unroll
+        for (int off = 1; off < C::LPO; off <<= 1) v += __shfl_xor(v, off);
+        acc[o][r] = v;
+      }
+      if (sub == 0 && o < npass) {
+        const int64_t i = perm[qb + pass0 + o];
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[i * ldi + r * ldr] = coef * acc[o][r];
+      }
+    }
+  }
+}
+
+template <class T, int R>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void stage2y_kernel(
+    const T *__restrict__ F1, int64_t ld1, const int64_t *__restrict__ tileoff,
+    const int32_t *__restrict__ tilex, const int32_t *__restrict__ tilemax,
+    const int32_t *__restrict__ xrows, const int32_t *__restrict__ perm, int nxb,
+    const T *__restrict__ S, int64_t ldS, int64_t nsr, int64_t nkeys, T coef, T *__restrict__ out,
+    int64_t ldi, int64_t ldr) {
+  __shared__ S2ySmem<T, R> sm;
+  stage2y_tile<T, R>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out,
+                     ldi, ldr, blockIdx.x, sm);
+}
+
+// ---------------------------------------------------------------------------
 // One-factor terms: g[x*R + r] = sum_k F(x,k)^{1|2} s[k*R + r]; one wave per row.
 template <class T, bool SQ>
 __global__ __launch_bounds__(256) void gemv_kernel(const T *__restrict__ F, int64_t ldf,
@@ -442,9 +569,23 @@ __global__ __launch_bounds__(512) void group_stage2_kernel(const GroupDesc<T> *_
   const GroupItem it = items[blockIdx.x];
   if (active && !active[it.p]) return;
   const GroupDesc<T> &d = desc[it.p];
-  stage2_tile<T, R>(d.F1, d.ld1, d.nx, d.tileoff, d.tiley, d.tilemax, d.yrows, d.perm_out,
-                    (int)d.nyb, d.S, sbuf_row_ld<T>(d.nkeys, R), d.nkeys, T(1), d.U + r0 * d.ldu, 1,
-                    d.ldu, it.li, sm);
+  stage2_tile<T, R>(d.F1, d.ld1, d.nx, d.tileoff[0], d.tiley[0], d.tilemax[0], d.yrows[0],
+                    d.perm_out[0], (int)d.nyb[0], d.S, sbuf_row_ld<T>(d.nkeys, R), d.nkeys, T(1),
+                    d.U + r0 * d.ldu, 1, d.ldu, it.li, sm);
+}
+
+template <class T, int R>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void group_stage2y_kernel(const GroupDesc<T> *__restrict__ desc,
+                                                            const GroupItem *__restrict__ items,
+                                                            int64_t r0,
+                                                            const uint8_t *__restrict__ active) {
+  __shared__ S2ySmem<T, R> sm;
+  const GroupItem it = items[blockIdx.x];
+  if (active && !active[it.p]) return;
+  const GroupDesc<T> &d = desc[it.p];
+  stage2y_tile<T, R>(d.F1, d.ld1, d.tileoff[1], d.tiley[1], d.tilemax[1], d.yrows[1], d.perm_out[1],
+                     (int)d.nyb[1], d.S, sbuf_row_ld<T>(d.nkeys, R), d.nrows, d.nkeys, T(1),
+                     d.U + r0 * d.ldu, 1, d.ldu, it.li, sm);
 }
 
 // ===========================================================================
@@ -510,6 +651,20 @@ void launch_stage2(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff,
     case 4: stage2_kernel<T, 4><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr); break;
     case 8: stage2_kernel<T, 8><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr); break;
     default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in stage 2"};
+  }
+}
+
+template <class T>
+void launch_stage2y(const T *F1, int64_t ld1, const int64_t *tileoff, const int32_t *tilex,
+                    const int32_t *tilemax, int64_t ntiles, int nxb, const int32_t *xrows,
+                    const int32_t *perm, const T *S, int64_t ldS, int64_t nsr, int64_t nkeys, int R,
+                    T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s) {
+  if (ntiles <= 0) return;
+  dim3 grid((unsigned)ntiles);
+  switch (R) {
+    case 4: stage2y_kernel<T, 4><<<grid, 512, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr); break;
+    case 8: stage2y_kernel<T, 8><<<grid, 512, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr); break;
+    default: throw Error{GVT_ERR_ARG, "internal: S-row grouped stage 2 needs a block of 4 or 8 RHS"};
   }
 }
 
@@ -590,11 +745,12 @@ void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64
   if (nitems <= 0) return;
   const unsigned g = (unsigned)nitems;
   const int nt = S2Cfg<T, 1>::NT;
+  // items: the tiles of R's class (F1-row groups for 1-2 RHS, S-row groups for 4-8)
   switch (R) {
     case 1: group_stage2_kernel<T, 1><<<g, nt, 0, s>>>(desc, items, r0, active); break;
     case 2: group_stage2_kernel<T, 2><<<g, nt, 0, s>>>(desc, items, r0, active); break;
-    case 4: group_stage2_kernel<T, 4><<<g, nt, 0, s>>>(desc, items, r0, active); break;
-    case 8: group_stage2_kernel<T, 8><<<g, nt, 0, s>>>(desc, items, r0, active); break;
+    case 4: group_stage2y_kernel<T, 4><<<g, 512, 0, s>>>(desc, items, r0, active); break;
+    case 8: group_stage2y_kernel<T, 8><<<g, 512, 0, s>>>(desc, items, r0, active); break;
     default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in grouped stage 2"};
   }
 }
@@ -612,6 +768,10 @@ void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64
                                  const int32_t *, int64_t, int, const int32_t *, const int32_t *,\
                                  const T *, int64_t, int64_t, int, T, T *, int64_t, int64_t,     \
                                  hipStream_t);                                                   \
+  template void launch_stage2y<T>(const T *, int64_t, const int64_t *, const int32_t *,          \
+                                  const int32_t *, int64_t, int, const int32_t *, const int32_t *,\
+                                  const T *, int64_t, int64_t, int64_t, int, T, T *, int64_t,     \
+                                  int64_t, hipStream_t);                                          \
   template void launch_gemv<T>(const T *, int64_t, int64_t, int64_t, bool, const T *, int, T *,  \
                                hipStream_t);                                                     \
   template void launch_gather_rows<T>(const T *, const int32_t *, int64_t, int, T *,             \

@@ -42,6 +42,12 @@ void launch_stage2(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff,
                    const int32_t *tilemax, int64_t ntiles, int nyb, const int32_t *yrows,
                    const int32_t *perm, const T *S, int64_t ldS, int64_t nkeys, int R, T coef, T *out,
                    int64_t ldi, int64_t ldr, hipStream_t s);
+// Stage 2 with S-row grouped tiles (blocks of R = 4 or 8 RHS).
+template <class T>
+void launch_stage2y(const T *F1, int64_t ld1, const int64_t *tileoff, const int32_t *tilex,
+                    const int32_t *tilemax, int64_t ntiles, int nxb, const int32_t *xrows,
+                    const int32_t *perm, const T *S, int64_t ldS, int64_t nsr, int64_t nkeys, int R,
+                    T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s);
 template <class T>
 void launch_gemv(const T *F, int64_t ldf, int64_t nrows, int64_t ncols, bool sq, const T *sv, int R,
                  T *g, hipStream_t s);
@@ -81,16 +87,18 @@ template <class T> struct GroupDesc {
   int64_t nkeys;
   T *S;         // row stride sbuf_row_ld<T>(nkeys, R) for an R-column RHS block
   int64_t nkb;  // stage-1 key blocks
-  // stage 2
+  // stage 2, one tile set per RHS class ([0]: blocks of 1-2 RHS, F1-row groups;
+  // [1]: blocks of 4-8 RHS, S-row groups, where tiley holds each tile's F1-row
+  // block, yrows each output's F1 row and nyb the number of F1-row blocks)
   const T *F1;
   int64_t ld1;
   int64_t nx;
-  const int64_t *tileoff;
-  const int32_t *tiley;
-  const int32_t *tilemax;
-  const int32_t *yrows;
-  const int32_t *perm_out;
-  int64_t nyb;
+  const int64_t *tileoff[2];
+  const int32_t *tiley[2];
+  const int32_t *tilemax[2];
+  const int32_t *yrows[2];
+  const int32_t *perm_out[2];
+  int64_t nyb[2];
   T *U;  // RHS r at U + r * ldu
   int64_t ldu;
 };

@@ -143,13 +143,17 @@ int stage2_block_rows(const gvt_plan *P, const TermSpec &t, int cls) {
 
 namespace {
 
-// Stage-2 tiles of term `ts` for RHS class `cls`.  2-D tiles: x blocks of
-// kStage2Rows rows x S-row blocks of at most stage2_block_rows() rows.  More
-// than four blocks are rounded up to a multiple of 8 so that each XCD keeps
-// one slice of S in its L2.  One stable counting sort on (tile, row inside
-// the tile) orders the outputs; the S-row order inside a row group does not
-// matter.  With `up` the arrays join the plan's upload, else they are copied
-// into the tile set's own allocation at once.
+// Stage-2 tiles of term `ts` for RHS class `cls`.
+//  class 0 (1-2 RHS): groups of kStage2Rows consecutive F1 rows x blocks of
+//    S rows staged in LDS; per output the compact S row.
+//  class 1 (4-8 RHS): groups of kStage2Rows consecutive compact S rows x
+//    blocks of F1 rows staged in LDS; per output the F1 row.
+// The staged block is at most stage2_block_rows() rows high; more than four
+// blocks are rounded up to a multiple of 8 so that each XCD keeps one slice
+// of the staged matrix in its L2.  One stable counting sort on (tile, group
+// row) orders the outputs; the order inside a group row does not matter.
+// With `up` the arrays join the plan's upload, else they are copied into the
+// tile set's own allocation at once.
 void build_tile_set(gvt_plan *P, TermSpec &ts, int cls, Uploads *up) {
   TileSet &tl = ts.tiles[cls];
   if (tl.built) return;
@@ -157,37 +161,40 @@ void build_tile_set(gvt_plan *P, TermSpec &ts, int cls, Uploads *up) {
   const std::vector<int32_t> &hx = P->h_out[ts.x == SA ? 0 : 1];
   const std::vector<int32_t> &hy = P->h_out[ts.y == SA ? 0 : 1];
   const int64_t n_out = P->n_out;
-  const int ysz = stage2_block_rows(P, ts, cls);
+  const int bsz = stage2_block_rows(P, ts, cls);
   const int64_t nsr = std::max<int64_t>((int64_t)sb.rows.size(), 1);
   const int64_t nxr = std::max<int64_t>(rows_of(P, ts.fdot), 1);
-  int64_t nyb = ceil_div(nsr, (int64_t)ysz);
-  if (nyb > 4) nyb = 8 * ceil_div(nyb, (int64_t)8);
-  const int64_t ybs = ceil_div(nsr, nyb);
-  const int64_t nxb = ceil_div(nxr, kStage2Rows);
-  const int64_t ntiles = nxb * nyb;
+  const int64_t ngrp_rows = cls ? nsr : nxr;   // grouped dimension
+  const int64_t nstg_rows = cls ? nxr : nsr;   // staged dimension
+  int64_t nsb = ceil_div(nstg_rows, (int64_t)bsz);
+  if (nsb > 4) nsb = 8 * ceil_div(nsb, (int64_t)8);
+  const int64_t sbs = ceil_div(nstg_rows, nsb);
+  const int64_t ngb = ceil_div(ngrp_rows, kStage2Rows);
+  const int64_t ntiles = ngb * nsb;
   GVT_REQUIRE(ntiles * kStage2Rows < INT32_MAX, GVT_ERR_ARG, "too many stage-2 tiles");
-  std::vector<int32_t> yrow_of(n_out), tkey(n_out);
+  std::vector<int32_t> grp_of(n_out), stg_of(n_out), tkey(n_out);
   for (int64_t i = 0; i < n_out; ++i) {
-    yrow_of[i] = sb.rowmap[hy[i]];
-    const int64_t xv = hx[i];
-    const int64_t tile_id = (xv / kStage2Rows) * nyb + yrow_of[i] / ybs;
-    tkey[i] = (int32_t)(tile_id * kStage2Rows + xv % kStage2Rows);
+    const int32_t yr = sb.rowmap[hy[i]], xv = hx[i];
+    grp_of[i] = cls ? yr : xv;
+    stg_of[i] = cls ? xv : yr;
+    const int64_t tile_id = (grp_of[i] / kStage2Rows) * nsb + stg_of[i] / sbs;
+    tkey[i] = (int32_t)(tile_id * kStage2Rows + grp_of[i] % kStage2Rows);
   }
   std::vector<int32_t> pc;
   std::vector<int64_t> sgk;
   counting_sort(tkey, ntiles * kStage2Rows, pc, sgk);
-  std::vector<int32_t> gperm(n_out), gy(n_out);
+  std::vector<int32_t> gperm(n_out), gstg(n_out);
   for (int64_t q = 0; q < n_out; ++q) {
     const int32_t i = pc[q];
     gperm[q] = i;
-    gy[q] = yrow_of[i];
+    gstg[q] = stg_of[i];
   }
   std::vector<int64_t> toff((size_t)ntiles * (kStage2Rows + 1));
-  std::vector<int32_t> tiley((size_t)2 * ntiles), tmax(ntiles, 0);
+  std::vector<int32_t> tstg((size_t)2 * ntiles), tmax(ntiles, 0);
   for (int64_t tt = 0; tt < ntiles; ++tt) {
-    const int64_t yb = tt % nyb;
-    tiley[2 * tt] = (int32_t)std::min<int64_t>(yb * ybs, nsr);
-    tiley[2 * tt + 1] = (int32_t)std::max<int64_t>(0, std::min<int64_t>(ybs, nsr - yb * ybs));
+    const int64_t sbk = tt % nsb;
+    tstg[2 * tt] = (int32_t)std::min<int64_t>(sbk * sbs, nstg_rows);
+    tstg[2 * tt + 1] = (int32_t)std::max<int64_t>(0, std::min<int64_t>(sbs, nstg_rows - sbk * sbs));
     for (int g = 0; g <= kStage2Rows; ++g)
       toff[(size_t)tt * (kStage2Rows + 1) + g] = sgk[(size_t)tt * kStage2Rows + g];
     for (int g = 0; g < kStage2Rows; ++g) {
@@ -195,15 +202,15 @@ void build_tile_set(gvt_plan *P, TermSpec &ts, int cls, Uploads *up) {
       tmax[tt] = std::max<int32_t>(tmax[tt], (int32_t)c);
     }
   }
-  tl.ysz = ysz;
+  tl.ysz = bsz;
   tl.ntiles = ntiles;
-  tl.nyb = (int)nyb;
+  tl.nyb = (int)nsb;
   Uploads local;
   Uploads &u = up ? *up : local;
   u.add(tl.perm, gperm);
-  u.add(tl.yrows, gy);
+  u.add(tl.yrows, gstg);
   u.add(tl.tileoff, toff);
-  u.add(tl.tiley, tiley);
+  u.add(tl.tiley, tstg);
   u.add(tl.tilemax, tmax);
   if (!up) local.commit(tl.blob);
   tl.built = true;
@@ -602,10 +609,16 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
       T *out = P->direct ? U : wsp<T>(P, W.tvec[ti]);
       const int64_t ldi = P->direct ? 1 : R, ldr = P->direct ? ldu : 1;
       const TileSet &tl = t.tiles[tile_class(R)];
-      launch_stage2<T>(F[t.fdot], ldF[t.fdot], rows_of(P, t.fdot), tl.tileoff.as<int64_t>(),
-                       tl.tiley.as<int32_t>(), tl.tilemax.as<int32_t>(), tl.ntiles, tl.nyb,
-                       tl.yrows.as<int32_t>(), tl.perm.as<int32_t>(), wsp<T>(P, W.sbuf[t.sbuf]),
-                       sbuf_ld<T>(P, t.sbuf, R), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s);
+      if (tile_class(R) == 0)
+        launch_stage2<T>(F[t.fdot], ldF[t.fdot], rows_of(P, t.fdot), tl.tileoff.as<int64_t>(),
+                         tl.tiley.as<int32_t>(), tl.tilemax.as<int32_t>(), tl.ntiles, tl.nyb,
+                         tl.yrows.as<int32_t>(), tl.perm.as<int32_t>(), wsp<T>(P, W.sbuf[t.sbuf]),
+                         sbuf_ld<T>(P, t.sbuf, R), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s);
+      else
+        launch_stage2y<T>(F[t.fdot], ldF[t.fdot], tl.tileoff.as<int64_t>(), tl.tiley.as<int32_t>(),
+                          tl.tilemax.as<int32_t>(), tl.ntiles, tl.nyb, tl.yrows.as<int32_t>(),
+                          tl.perm.as<int32_t>(), wsp<T>(P, W.sbuf[t.sbuf]), sbuf_ld<T>(P, t.sbuf, R),
+                          (int64_t)sb.rows.size(), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s);
     }
   }
   mark(P, ST_STAGE2, 1, s);

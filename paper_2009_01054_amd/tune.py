@@ -154,7 +154,7 @@ def main():
 
     assert torch.cuda.is_available(), "the tuner measures on the GPU"
     gvt.load_library()
-    device = torch.cuda.get_device_name(0)
+    device = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     r1 = ridge_products(gvt, W, torch, 1, args.reps)
     r8 = ridge_products(gvt, W, torch, 8, max(2, args.reps // 4)) + batched_iterations(
         gvt, W, torch, args.batched_problems)
