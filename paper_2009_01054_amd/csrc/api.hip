@@ -1,6 +1,7 @@
 // extern "C" entry points declared in include/gvt.h.
 #include <algorithm>
 #include <cstdarg>
+#include <mutex>
 
 #include "plan.h"
 
@@ -17,6 +18,40 @@ void set_error(const char *fmt, ...) {
   g_last_error = buf;
 }
 void clear_error() { g_last_error.clear(); }
+
+// Pinned staging buffer shared by every plan upload of the process (grow-only).
+static std::mutex g_stage_mu;
+static void *g_stage = nullptr;
+static size_t g_stage_bytes = 0;
+
+void Uploads::commit(DevMem &blob) {
+  size_t total = 0;
+  for (auto &it : items) total += (it.bytes + 255) & ~size_t(255);
+  blob.ensure(total ? total : 256);
+  size_t off = 0;
+  for (auto &it : items) {
+    it.m->view(static_cast<char *>(blob.p) + off, it.bytes);
+    off += (it.bytes + 255) & ~size_t(255);
+  }
+  if (total) {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    if (g_stage_bytes < total) {
+      if (g_stage) (void)hipHostFree(g_stage);
+      g_stage = nullptr;
+      g_stage_bytes = 0;
+      const size_t want = std::max<size_t>(total, (size_t)4 << 20);
+      GVT_HIP_CHECK(hipHostMalloc(&g_stage, want, hipHostMallocDefault));
+      g_stage_bytes = want;
+    }
+    off = 0;
+    for (auto &it : items) {
+      if (it.bytes) std::memcpy(static_cast<char *>(g_stage) + off, it.data, it.bytes);
+      off += (it.bytes + 255) & ~size_t(255);
+    }
+    GVT_HIP_CHECK(hipMemcpy(blob.p, g_stage, total, hipMemcpyHostToDevice));
+  }
+  items.clear();
+}
 
 int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double *T, int64_t t,
                 int64_t ldt, const int32_t *c, const int32_t *e, int64_t n, const double *y,

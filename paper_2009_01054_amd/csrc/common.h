@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -99,30 +100,26 @@ struct DevMem {
   template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
-// Host-to-device staging for plan data: arrays are collected on the host and
-// copied in one transfer into one device allocation (commit), each DevMem
-// becoming a view into it.
+// Host-to-device staging for plan data: arrays are collected on the host
+// (moved in, not copied) and copied in one transfer through a pinned staging
+// buffer into one device allocation (commit), each DevMem becoming a view
+// into it.
 struct Uploads {
-  std::vector<std::pair<DevMem *, std::vector<char>>> items;
+  struct Item {
+    DevMem *m;
+    std::shared_ptr<void> keep;
+    const void *data;
+    size_t bytes;
+  };
+  std::vector<Item> items;
+  template <class T> void add(DevMem &m, std::vector<T> &&h) {
+    auto sp = std::make_shared<std::vector<T>>(std::move(h));
+    items.push_back({&m, sp, sp->data(), sp->size() * sizeof(T)});
+  }
   template <class T> void add(DevMem &m, const std::vector<T> &h) {
-    std::vector<char> b(h.size() * sizeof(T));
-    if (!h.empty()) std::memcpy(b.data(), h.data(), b.size());
-    items.emplace_back(&m, std::move(b));
+    add(m, std::vector<T>(h));
   }
-  void commit(DevMem &blob) {
-    size_t total = 0;
-    for (auto &it : items) total += (it.second.size() + 255) & ~size_t(255);
-    blob.ensure(total ? total : 256);
-    std::vector<char> host(total);
-    size_t off = 0;
-    for (auto &it : items) {
-      if (!it.second.empty()) std::memcpy(host.data() + off, it.second.data(), it.second.size());
-      it.first->view(static_cast<char *>(blob.p) + off, it.second.size());
-      off += (it.second.size() + 255) & ~size_t(255);
-    }
-    if (total) GVT_HIP_CHECK(hipMemcpy(blob.p, host.data(), total, hipMemcpyHostToDevice));
-    items.clear();
-  }
+  void commit(DevMem &blob);  // synchronous
 };
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -17,6 +17,8 @@
 
 #include <chrono>
 #include <cstdlib>
+#include <exception>
+#include <thread>
 
 #include "plan.h"
 #include "tuning.h"
@@ -154,9 +156,15 @@ namespace {
 // row) orders the outputs; the order inside a group row does not matter.
 // With `up` the arrays join the plan's upload, else they are copied into the
 // tile set's own allocation at once.
-void build_tile_set(gvt_plan *P, TermSpec &ts, int cls, Uploads *up) {
-  TileSet &tl = ts.tiles[cls];
-  if (tl.built) return;
+struct TileHost {
+  int bsz = 0, nsb = 0;
+  int64_t ntiles = 0;
+  std::vector<int32_t> perm, stg, tstg, tmax;
+  std::vector<int64_t> toff;
+};
+
+TileHost compute_tiles(const gvt_plan *P, const TermSpec &ts, int cls) {
+  TileHost o;
   const SBufSpec &sb = P->sbufs[ts.sbuf];
   const std::vector<int32_t> &hx = P->h_out[ts.x == SA ? 0 : 1];
   const std::vector<int32_t> &hy = P->h_out[ts.y == SA ? 0 : 1];
@@ -172,46 +180,51 @@ void build_tile_set(gvt_plan *P, TermSpec &ts, int cls, Uploads *up) {
   const int64_t ngb = ceil_div(ngrp_rows, kStage2Rows);
   const int64_t ntiles = ngb * nsb;
   GVT_REQUIRE(ntiles * kStage2Rows < INT32_MAX, GVT_ERR_ARG, "too many stage-2 tiles");
-  std::vector<int32_t> grp_of(n_out), stg_of(n_out), tkey(n_out);
+  std::vector<int32_t> stg_of(n_out), tkey(n_out);
   for (int64_t i = 0; i < n_out; ++i) {
     const int32_t yr = sb.rowmap[hy[i]], xv = hx[i];
-    grp_of[i] = cls ? yr : xv;
+    const int32_t grp = cls ? yr : xv;
     stg_of[i] = cls ? xv : yr;
-    const int64_t tile_id = (grp_of[i] / kStage2Rows) * nsb + stg_of[i] / sbs;
-    tkey[i] = (int32_t)(tile_id * kStage2Rows + grp_of[i] % kStage2Rows);
+    const int64_t tile_id = (grp / kStage2Rows) * nsb + stg_of[i] / sbs;
+    tkey[i] = (int32_t)(tile_id * kStage2Rows + grp % kStage2Rows);
   }
-  std::vector<int32_t> pc;
   std::vector<int64_t> sgk;
-  counting_sort(tkey, ntiles * kStage2Rows, pc, sgk);
-  std::vector<int32_t> gperm(n_out), gstg(n_out);
-  for (int64_t q = 0; q < n_out; ++q) {
-    const int32_t i = pc[q];
-    gperm[q] = i;
-    gstg[q] = stg_of[i];
-  }
-  std::vector<int64_t> toff((size_t)ntiles * (kStage2Rows + 1));
-  std::vector<int32_t> tstg((size_t)2 * ntiles), tmax(ntiles, 0);
+  counting_sort(tkey, ntiles * kStage2Rows, o.perm, sgk);
+  o.stg.resize(n_out);
+  for (int64_t q = 0; q < n_out; ++q) o.stg[q] = stg_of[o.perm[q]];
+  o.toff.resize((size_t)ntiles * (kStage2Rows + 1));
+  o.tstg.resize((size_t)2 * ntiles);
+  o.tmax.assign(ntiles, 0);
   for (int64_t tt = 0; tt < ntiles; ++tt) {
     const int64_t sbk = tt % nsb;
-    tstg[2 * tt] = (int32_t)std::min<int64_t>(sbk * sbs, nstg_rows);
-    tstg[2 * tt + 1] = (int32_t)std::max<int64_t>(0, std::min<int64_t>(sbs, nstg_rows - sbk * sbs));
+    o.tstg[2 * tt] = (int32_t)std::min<int64_t>(sbk * sbs, nstg_rows);
+    o.tstg[2 * tt + 1] = (int32_t)std::max<int64_t>(0, std::min<int64_t>(sbs, nstg_rows - sbk * sbs));
     for (int g = 0; g <= kStage2Rows; ++g)
-      toff[(size_t)tt * (kStage2Rows + 1) + g] = sgk[(size_t)tt * kStage2Rows + g];
+      o.toff[(size_t)tt * (kStage2Rows + 1) + g] = sgk[(size_t)tt * kStage2Rows + g];
     for (int g = 0; g < kStage2Rows; ++g) {
       const int64_t c = sgk[(size_t)tt * kStage2Rows + g + 1] - sgk[(size_t)tt * kStage2Rows + g];
-      tmax[tt] = std::max<int32_t>(tmax[tt], (int32_t)c);
+      o.tmax[tt] = std::max<int32_t>(o.tmax[tt], (int32_t)c);
     }
   }
-  tl.ysz = bsz;
-  tl.ntiles = ntiles;
-  tl.nyb = (int)nsb;
+  o.bsz = bsz;
+  o.ntiles = ntiles;
+  o.nsb = (int)nsb;
+  return o;
+}
+
+// With `up` the arrays join the plan's upload, else they are copied into the
+// tile set's own allocation at once.
+void install_tiles(TileSet &tl, TileHost &&o, Uploads *up) {
+  tl.ysz = o.bsz;
+  tl.ntiles = o.ntiles;
+  tl.nyb = o.nsb;
   Uploads local;
   Uploads &u = up ? *up : local;
-  u.add(tl.perm, gperm);
-  u.add(tl.yrows, gstg);
-  u.add(tl.tileoff, toff);
-  u.add(tl.tiley, tstg);
-  u.add(tl.tilemax, tmax);
+  u.add(tl.perm, std::move(o.perm));
+  u.add(tl.yrows, std::move(o.stg));
+  u.add(tl.tileoff, std::move(o.toff));
+  u.add(tl.tiley, std::move(o.tstg));
+  u.add(tl.tilemax, std::move(o.tmax));
   if (!up) local.commit(tl.blob);
   tl.built = true;
 }
@@ -228,7 +241,7 @@ void plan_ensure_tiles(gvt_plan *P, int cls, hipStream_t s) {
                 "the first product with a new RHS block size builds stage-2 tiles and cannot be "
                 "captured; run it once before capturing"};
   for (TermSpec &t : P->terms)
-    if (t.type == TG) build_tile_set(P, t, cls, nullptr);
+    if (t.type == TG && !t.tiles[cls].built) install_tiles(t.tiles[cls], compute_tiles(P, t, cls), nullptr);
 }
 
 void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64_t d_cols,
@@ -265,11 +278,14 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
 
   PhaseTimer tm;
   // ---- indices to host, validation, unique counts (Table 1) -------------
+  // When the output pairs are the input pairs (training products), the two
+  // index arrays are copied and checked once.
   std::vector<int32_t> h[4];
   const int32_t *src[4] = {a, b, c, e};
   const int64_t cnt[4] = {n_out, n_out, n_in, n_in};
   const int64_t lim[4] = {d_rows, t_rows, d_cols, t_cols};
-  for (int i = 0; i < 4; ++i) {
+  const bool alias = n_out == n_in && a == c && b == e;
+  for (int i = 0; i < (alias ? 2 : 4); ++i) {
     h[i].resize(cnt[i]);
     if (cnt[i])
       GVT_HIP_CHECK(hipMemcpyAsync(h[i].data(), src[i], cnt[i] * sizeof(int32_t),
@@ -278,15 +294,37 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   GVT_HIP_CHECK(hipStreamSynchronize(s));
   tm.lap("indices to host");
   static const char *nm[4] = {"out_a", "out_b", "in_c", "in_e"};
-  for (int i = 0; i < 4; ++i) {
-    for (int64_t j = 0; j < cnt[i]; ++j) {
-      const int32_t v = h[i][j];
-      if (v < 0 || v >= lim[i])
-        throw Error{GVT_ERR_INDEX, std::string(nm[i]) + "[" + std::to_string(j) + "] = " +
-                                       std::to_string(v) + " outside [0, " +
-                                       std::to_string(lim[i]) + ")"};
-    }
-    P->uniq[i] = count_unique(h[i], lim[i]);
+  // first index outside [0, lim) per array (-1: none), unique counts
+  int64_t bad[4] = {-1, -1, -1, -1};
+  auto check = [&](int i) {
+    const int i2 = alias ? i + 2 : -1;  // the aliased input array, with its own limit
+    const int64_t L = i2 >= 0 ? std::min(lim[i], lim[i2]) : lim[i];
+    const std::vector<int32_t> &v = h[i];
+    for (int64_t j = 0; j < (int64_t)v.size(); ++j)
+      if (v[j] < 0 || v[j] >= L) { bad[i] = j; return; }
+    P->uniq[i] = count_unique(v, L > 0 ? std::max(lim[i], i2 >= 0 ? lim[i2] : 0) : 0);
+  };
+  {
+    std::vector<std::thread> th;
+    const int na = alias ? 2 : 4;
+    for (int i = 1; i < na; ++i) th.emplace_back(check, i);
+    check(0);
+    for (auto &t : th) t.join();
+  }
+  for (int i = 0; i < (alias ? 2 : 4); ++i) {
+    if (bad[i] < 0) continue;
+    const int32_t v = h[i][bad[i]];
+    int which = i;
+    if (alias && (v < 0 || v >= lim[i + 2]) && !(v < 0 || v >= lim[i])) which = i + 2;
+    throw Error{GVT_ERR_INDEX, std::string(nm[which]) + "[" + std::to_string(bad[i]) + "] = " +
+                                   std::to_string(v) + " outside [0, " + std::to_string(lim[which]) +
+                                   ")"};
+  }
+  if (alias) {
+    h[2] = h[0];
+    h[3] = h[1];
+    P->uniq[2] = P->uniq[0];
+    P->uniq[3] = P->uniq[1];
   }
   tm.lap("validate + unique");
   Uploads up;
@@ -375,26 +413,25 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   // ---- materialise sorts, S buffers, gemvs and terms ----------------------
   auto sel_host = [&](int sel) -> const std::vector<int32_t> & { return h[sel]; };
   auto sel_dev = [&](int sel) -> const int32_t * { return P->idx[sel].as<int32_t>(); };
-  auto need_insort = [&](int key) {
-    InputSort &is = P->insort[key == SC ? 0 : 1];
-    if (is.built) return;
-    const int okey = key == SC ? SE : SC;
-    is.nkeys = nkeys_of(P, key);
-    is.nother = nkeys_of(P, okey);
-    // sort by other index first, then stably by key: segments ordered by other inside
-    std::vector<int32_t> perm_o, perm;
-    std::vector<int64_t> seg_o, seg;
-    counting_sort(h[okey], is.nother, perm_o, seg_o);
+  bool insort_needed[2] = {false, false};
+  auto need_insort = [&](int key) { insort_needed[key == SC ? 0 : 1] = true; };
+  // sort by other index first, then stably by key: segments ordered by other inside
+  struct SortHost {
+    std::vector<int32_t> perm, other;
+    std::vector<int64_t> seg;
+  } sort_host[2];
+  auto build_insort = [&](int ks) {
+    const int key = ks == 0 ? SC : SE, okey = ks == 0 ? SE : SC;
+    SortHost &o = sort_host[ks];
+    std::vector<int32_t> perm_o;
+    std::vector<int64_t> seg_o;
+    counting_sort(h[okey], nkeys_of(P, okey), perm_o, seg_o);
     std::vector<int32_t> key_o(n_in);
     for (int64_t p = 0; p < n_in; ++p) key_o[p] = h[key][perm_o[p]];
-    counting_sort(key_o, is.nkeys, perm, seg);
-    for (int64_t p = 0; p < n_in; ++p) perm[p] = perm_o[perm[p]];
-    std::vector<int32_t> oth(n_in);
-    for (int64_t p = 0; p < n_in; ++p) oth[p] = h[okey][perm[p]];
-    up.add(is.perm, perm);
-    up.add(is.other, oth);
-    up.add(is.seg, seg);
-    is.built = true;
+    counting_sort(key_o, nkeys_of(P, key), o.perm, o.seg);
+    for (int64_t p = 0; p < n_in; ++p) o.perm[p] = perm_o[o.perm[p]];
+    o.other.resize(n_in);
+    for (int64_t p = 0; p < n_in; ++p) o.other[p] = h[okey][o.perm[p]];
   };
 
   tm.lap("term expansion");
@@ -417,11 +454,9 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     for (int64_t r = 0; r < (int64_t)sb.rowmap.size(); ++r)
       if (sb.rowmap[r] >= 0) { sb.rowmap[r] = (int32_t)sb.rows.size(); sb.rows.push_back((int32_t)r); }
     up.add(sb.d_rows, sb.rows);
-    if (sb.degenerate) need_insort(sb.key);  // for its segment sums
-    else need_insort(sb.key);
+    need_insort(sb.key);  // scatter segments, or the segment sums of a degenerate buffer
   }
-
-  tm.lap("input sorts + S rows");
+  tm.lap("S rows");
   P->terms.resize(raw_terms.size());
   P->cost_fma = 0.0;
   for (size_t ti = 0; ti < raw_terms.size(); ++ti) {
@@ -431,8 +466,6 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     if (t.type == TG) {
       ts.fdot = t.a0; ts.x = t.a2; ts.y = t.a3;
       ts.sbuf = sbuf_index.at({t.a1, t.a4, t.a5});
-      const SBufSpec &sb = P->sbufs[ts.sbuf];
-      if (n_out > 0) build_tile_set(P, ts, tile_class(rhs_hint), &up);
       P->cost_fma += g_cost(t);
     } else if (t.type == TO) {
       auto gk = std::make_tuple(t.a0, t.a1, t.a3);
@@ -462,7 +495,48 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       P->cost_fma -= (key == other) ? selval_uniq(y) * (double)nkeys_of(P, key)
                                     : selval_uniq(y) * n_in_d;
     }
-  tm.lap("term orderings");
+  // input sorts and stage-2 tiles are independent host work: one thread each
+  {
+    std::vector<std::pair<TermSpec *, TileHost>> tiles;
+    for (TermSpec &ts : P->terms)
+      if (ts.type == TG && n_out > 0) tiles.push_back({&ts, TileHost{}});
+    std::vector<std::thread> th;
+    std::vector<std::exception_ptr> errs(tiles.size() + 2);
+    auto guard = [&](size_t slot, auto fn) {
+      try {
+        fn();
+      } catch (...) {
+        errs[slot] = std::current_exception();
+      }
+    };
+    for (int ks = 0; ks < 2; ++ks)
+      if (insort_needed[ks] && n_in > 0)
+        th.emplace_back([&, ks]() { guard(ks, [&]() { build_insort(ks); }); });
+    const int cls = tile_class(rhs_hint);
+    for (size_t k = 0; k < tiles.size(); ++k)
+      th.emplace_back([&, k]() {
+        guard(2 + k, [&]() { tiles[k].second = compute_tiles(P, *tiles[k].first, cls); });
+      });
+    for (auto &t : th) t.join();
+    for (auto &ep : errs)
+      if (ep) std::rethrow_exception(ep);
+    for (int ks = 0; ks < 2; ++ks) {
+      if (!insort_needed[ks]) continue;
+      InputSort &is = P->insort[ks];
+      is.nkeys = nkeys_of(P, ks == 0 ? SC : SE);
+      is.nother = nkeys_of(P, ks == 0 ? SE : SC);
+      if (n_in > 0) {
+        up.add(is.perm, std::move(sort_host[ks].perm));
+        up.add(is.other, std::move(sort_host[ks].other));
+        up.add(is.seg, std::move(sort_host[ks].seg));
+      } else {
+        up.add(is.seg, std::vector<int64_t>(is.nkeys + 1, 0));
+      }
+      is.built = true;
+    }
+    for (auto &tk : tiles) install_tiles(tk.first->tiles[cls], std::move(tk.second), &up);
+  }
+  tm.lap("input sorts + term orderings");
   bool need_idx = false;
   for (const TermSpec &t : P->terms) need_idx = need_idx || t.type != TG;
   if (need_idx)
