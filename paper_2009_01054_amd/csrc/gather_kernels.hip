@@ -8,8 +8,11 @@
 // sum is a sequential loop or a fixed lane tree: results are deterministic
 // (no atomics).  Several right-hand sides (R) ride along in the innermost
 // dimension so that each gathered base-matrix element feeds R FMAs.
+#include <cstdlib>
+
 #include "common.h"
 #include "kernels.h"
+#include "tuning.h"
 
 namespace gvt {
 
@@ -56,14 +59,14 @@ __global__ void segsum_kernel(const int64_t *__restrict__ seg, const T *__restri
 // ordered by other index, which keeps consecutive column loads close in the
 // cache.  The [64 x KB*R] result tile is staged in LDS and written
 // row-contiguously.
-template <class T, int R> struct S1Cfg {
-  static constexpr int KPW = 4;        // keys per wave
+template <class T, int R, int KPW_ = 4> struct S1Cfg {
+  static constexpr int KPW = KPW_;     // keys per wave
   static constexpr int KB = 4 * KPW;   // keys per block
 };
 
 // Body of one stage-1 block (key block kb, row block rb); shared by the
 // single-product kernel and the grouped kernel of batched products.
-template <class T, int R>
+template <class T, int R, int KPW = 4>
 __device__ __forceinline__ void stage1_block(const T *__restrict__ Fc, int64_t ldc,
                                              const int32_t *__restrict__ rows, int64_t nrows,
                                              const int64_t *__restrict__ seg,
@@ -71,7 +74,7 @@ __device__ __forceinline__ void stage1_block(const T *__restrict__ Fc, int64_t l
                                              const T *__restrict__ vs, int64_t nkeys,
                                              T *__restrict__ S, int64_t ldS, int64_t kb, int64_t rb,
                                              T *stg) {
-  typedef S1Cfg<T, R> C;
+  typedef S1Cfg<T, R, KPW> C;
   constexpr int W = C::KB * R;
   const int lane = threadIdx.x & 63;
   const int w = wave_id_uniform();
@@ -117,13 +120,14 @@ __device__ __forceinline__ void stage1_block(const T *__restrict__ Fc, int64_t l
   }
 }
 
-template <class T, int R>
+template <class T, int R, int KPW>
 __global__ __launch_bounds__(256) void stage1_kernel(
     const T *__restrict__ Fc, int64_t ldc, const int32_t *__restrict__ rows, int64_t nrows,
     const int64_t *__restrict__ seg, const int32_t *__restrict__ other, const T *__restrict__ vs,
     int64_t nkeys, T *__restrict__ S, int64_t ldS) {
-  __shared__ T stg[64 * (S1Cfg<T, R>::KB * R + 1)];
-  stage1_block<T, R>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, blockIdx.x, blockIdx.y, stg);
+  __shared__ T stg[64 * (S1Cfg<T, R, KPW>::KB * R + 1)];
+  stage1_block<T, R, KPW>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, blockIdx.x, blockIdx.y,
+                          stg);
 }
 
 // Degenerate stage 1 (key == other index): S[rho, k] = F2[rows[rho], k] * s[k].
@@ -606,13 +610,32 @@ void launch_segsum(const int64_t *seg, const T *vs, int64_t nkeys, int R, T *out
   segsum_kernel<T><<<grid1(nkeys, 256), 256, 0, s>>>(seg, vs, nkeys, R, out);
 }
 
+template <class T, int R, int KPW>
+static void stage1_rk(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
+                      const int32_t *other, const T *vs, int64_t nkeys, T *S, int64_t ldS,
+                      hipStream_t s) {
+  typedef S1Cfg<T, R, KPW> C;
+  dim3 grid((unsigned)ceil_div(nkeys, C::KB), (unsigned)ceil_div(nrows, 64));
+  stage1_kernel<T, R, KPW><<<grid, 256, 0, s>>>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS);
+}
+
+// Keys per wave of the single-product stage 1 (tuning.h; GVT_STAGE1_KPW = 1, 2
+// or 4 overrides it for tuning sweeps).
+static int stage1_kpw() {
+  const char *ev = std::getenv("GVT_STAGE1_KPW");
+  const int k = ev ? std::atoi(ev) : kStage1KeysPerWave;
+  return (k == 1 || k == 2 || k == 4) ? k : 4;
+}
+
 template <class T, int R>
 static void stage1_r(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
                      const int32_t *other, const T *vs, int64_t nkeys, T *S, int64_t ldS,
                      hipStream_t s) {
-  typedef S1Cfg<T, R> C;
-  dim3 grid((unsigned)ceil_div(nkeys, C::KB), (unsigned)ceil_div(nrows, 64));
-  stage1_kernel<T, R><<<grid, 256, 0, s>>>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS);
+  switch (stage1_kpw()) {
+    case 1: stage1_rk<T, R, 1>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
+    case 2: stage1_rk<T, R, 2>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
+    default: stage1_rk<T, R, 4>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
+  }
 }
 
 template <class T>

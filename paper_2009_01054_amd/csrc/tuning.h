@@ -1,20 +1,26 @@
-// Stage-2 tile targets: outputs per F1 row per tile for each RHS class.
-// Written by paper_2009_01054_amd/tune.py on AMD Radeon Graphics; measured times (ms):
-//   class R1: ridge f64 x1; ridge f32 x1
-//     target      8: 0.2050, 0.1526  (score 1.220)
-//     target     16: 0.1767, 0.1193  (score 1.002)
-//     target     32: 0.1769, 0.1190  (score 1.001)
-//     target     64: 0.1765, 0.1197  (score 1.003)
-//     target    128: 0.1774, 0.1190  (score 1.002)
-//   class R8: ridge f64 x8; ridge f32 x8; batched f32 (64 problems, 8 RHS), per iteration
-//     target      2: 2.0699, 0.8793, 8.4911  (score 1.150)
-//     target      4: 2.0509, 0.7777, 7.2171  (score 1.042)
-//     target      8: 1.9983, 0.7538, 6.9383  (score 1.009)
-//     target     16: 2.0069, 0.7351, 7.0487  (score 1.008)
-//     target     32: 2.0060, 0.7333, 7.1532  (score 1.012)
+// Tuned launch shapes: stage-2 tile targets (outputs per group row per tile) for
+// each RHS class, and the keys each wave walks in stage 1.
+// Written by paper_2009_01054_amd/tune.py on gfx950; measured times (ms):
+//   KPW: ridge f64 x1; ridge f32 x1
+//          1: 0.1755, 0.1103  (score 1.008)
+//          2: 0.1726, 0.1109  (score 1.003)
+//          4: 0.1786, 0.1178  (score 1.051)
+//   R1: ridge f64 x1; ridge f32 x1
+//          8: 0.2041, 0.1522  (score 1.216)
+//         16: 0.1788, 0.1189  (score 1.006)
+//         32: 0.1785, 0.1183  (score 1.003)
+//         64: 0.1775, 0.1196  (score 1.005)
+//        128: 0.1786, 0.1188  (score 1.005)
+//   R8: ridge f64 x8; ridge f32 x8; batched f32 (64 problems, 8 RHS), per iteration
+//          2: 2.0586, 0.8747, 8.4489  (score 1.150)
+//          4: 2.0303, 0.7808, 7.2601  (score 1.048)
+//          8: 1.9597, 0.7463, 7.0419  (score 1.010)
+//         16: 1.9658, 0.7253, 7.0319  (score 1.001)
+//         32: 2.0023, 0.7387, 7.2150  (score 1.022)
 #pragma once
 
 namespace gvt {
 constexpr double kStage2TargetR1 = 32.0;
 constexpr double kStage2TargetR8 = 16.0;
+constexpr int kStage1KeysPerWave = 2;
 }  // namespace gvt

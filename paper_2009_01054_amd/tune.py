@@ -1,18 +1,20 @@
-"""Autotuner for the stage-2 tile shape (run on the GPU).
+"""Autotuner for the launch shapes of the two stages (run on the GPU).
 
 Stage 2 cuts the (F1 row, S row) plane of a two-factor term into tiles of 32
-F1 rows by a block of S rows.  The block height is chosen at plan time from
-the density of the outputs so that each F1 row of a tile holds about
+group rows (F1 rows for blocks of 1-2 RHS, S rows for blocks of 4-8 RHS) by a
+block of staged rows.  The block height is chosen at plan time from the
+density of the outputs so that each group row of a tile holds about
 ``target`` outputs; a pass of the kernel serves a fixed number of outputs per
-row and re-copies the tile's S rows, so the best target depends on how many
-right-hand sides share a pass.  There is one target per RHS class (blocks of
-1-2 RHS and of 4-8 RHS).
+row and re-reads the staged rows, so the best target depends on how many
+right-hand sides share a pass.  There is one target per RHS class.  Stage 1
+walks key segments with one wave per key; the number of keys each wave walks
+trades waves in flight against per-wave work.
 
-This script sweeps both targets on synthetic workloads shaped like the
+This script sweeps the three knobs on synthetic workloads shaped like the
 library's benchmarks, through the library's environment overrides
-(GVT_STAGE2_TARGET_R1 / GVT_STAGE2_TARGET_R8, read when a plan is built), and
-writes the winners as a C++ header that ``build.py`` compiles into the
-library:
+(GVT_STAGE1_KPW, GVT_STAGE2_TARGET_R1, GVT_STAGE2_TARGET_R8; the targets are
+read when a plan is built), and writes the winners as a C++ header that
+``build.py`` compiles into the library:
 
     python -m paper_2009_01054_amd.tune --out paper_2009_01054_amd/csrc/tuning.h
 
@@ -33,6 +35,7 @@ if ROOT not in sys.path:
 
 R1_CANDIDATES = (8.0, 16.0, 32.0, 64.0, 128.0)
 R8_CANDIDATES = (2.0, 4.0, 8.0, 16.0, 32.0)
+KPW_CANDIDATES = (1, 2, 4)
 
 
 def _log(*a):
@@ -51,8 +54,11 @@ def _events_ms(torch, fn, reps):
     return s.elapsed_time(e) / reps
 
 
+_KNOBS = {0: "GVT_STAGE2_TARGET_R1", 1: "GVT_STAGE2_TARGET_R8", "kpw": "GVT_STAGE1_KPW"}
+
+
 def _set_target(cls, value):
-    os.environ["GVT_STAGE2_TARGET_R8" if cls else "GVT_STAGE2_TARGET_R1"] = repr(float(value))
+    os.environ[_KNOBS[cls]] = str(int(value)) if cls == "kpw" else repr(float(value))
 
 
 def ridge_products(gvt, W, torch, nrhs, reps):
@@ -113,9 +119,9 @@ def sweep(cls, candidates, workloads):
         for name, run in workloads:
             ms = run()
             row.append(ms)
-            _log(f"[tune] class {'R8' if cls else 'R1'} target {cand:g}: {name}: {ms:.4f} ms")
+            _log(f"[tune] {_KNOBS[cls]}={cand:g}: {name}: {ms:.4f} ms")
         table[cand] = row
-    os.environ.pop("GVT_STAGE2_TARGET_R8" if cls else "GVT_STAGE2_TARGET_R1", None)
+    os.environ.pop(_KNOBS[cls], None)
     best_per = [min(table[c][k] for c in candidates) for k in range(len(workloads))]
     score = {c: math.exp(sum(math.log(table[c][k] / best_per[k]) for k in range(len(workloads)))
                          / len(workloads)) for c in candidates}
@@ -124,16 +130,18 @@ def sweep(cls, candidates, workloads):
 
 
 def write_header(path, results, device):
-    lines = ["// Stage-2 tile targets: outputs per F1 row per tile for each RHS class.",
+    lines = ["// Tuned launch shapes: stage-2 tile targets (outputs per group row per tile) for",
+             "// each RHS class, and the keys each wave walks in stage 1.",
              "// Written by paper_2009_01054_amd/tune.py on " + device + "; measured times (ms):"]
-    for cls, (winner, table, score, names) in results.items():
-        lines.append(f"//   class {cls}: " + "; ".join(names))
+    for key, (winner, table, score, names) in results.items():
+        lines.append(f"//   {key}: " + "; ".join(names))
         for cand, row in table.items():
-            lines.append(f"//     target {cand:6g}: " + ", ".join(f"{x:.4f}" for x in row)
+            lines.append(f"//     {cand:6g}: " + ", ".join(f"{x:.4f}" for x in row)
                          + f"  (score {score[cand]:.3f})")
     lines += ["#pragma once", "", "namespace gvt {",
               f"constexpr double kStage2TargetR1 = {results['R1'][0]:.1f};",
               f"constexpr double kStage2TargetR8 = {results['R8'][0]:.1f};",
+              f"constexpr int kStage1KeysPerWave = {int(results['KPW'][0])};",
               "}  // namespace gvt", ""]
     with open(path, "w") as f:
         f.write("\n".join(lines))
@@ -159,12 +167,14 @@ def main():
     r8 = ridge_products(gvt, W, torch, 8, max(2, args.reps // 4)) + batched_iterations(
         gvt, W, torch, args.batched_problems)
     results = {}
-    for key, cls, cands, wl in (("R1", 0, R1_CANDIDATES, r1), ("R8", 1, R8_CANDIDATES, r8)):
+    for key, cls, cands, wl in (("KPW", "kpw", KPW_CANDIDATES, r1), ("R1", 0, R1_CANDIDATES, r1),
+                                ("R8", 1, R8_CANDIDATES, r8)):
         winner, table, score = sweep(cls, cands, wl)
         results[key] = (winner, table, score, [n for n, _ in wl])
         _log(f"[tune] class {key}: target {winner:g}")
     write_header(args.out, results, device)
-    print(f"wrote {args.out}: R1 target {results['R1'][0]:g}, R8 target {results['R8'][0]:g}")
+    print(f"wrote {args.out}: stage-1 keys per wave {results['KPW'][0]}, R1 target {results['R1'][0]:g}, "
+          f"R8 target {results['R8'][0]:g}")
 
 
 if __name__ == "__main__":

@@ -398,3 +398,16 @@ def test_cg_batched_warm_start_and_cap(gvt):
                                                    tol=1e-12, check_every=2)
     assert rc3 == 1 and (iters3 <= 3).all() and (iters3 >= 1).all()
     assert np.isfinite(rel3).all() and (rel3 < 1.0).all()
+
+
+@pytest.mark.parametrize("kpw", ["1", "2"])
+def test_stage1_keys_per_wave_variants_are_bitwise_equal(gvt, kpw, monkeypatch):
+    # every variant sums a key's segment in the same order, so products agree exactly
+    p = W.make_heterogeneous(99, 0, 150, 70, 3000, 8)
+    Dd, Td = dev(p["D"]), dev(p["T"])
+    c, e = idx(p["c"]), idx(p["e"])
+    v = dev(np.random.default_rng(5).standard_normal((len(p["c"]), 3)))
+    ref = gvt.gvt_matvec(Dd, Td, (c, e), (c, e), v)
+    monkeypatch.setenv("GVT_STAGE1_KPW", kpw)
+    got = gvt.gvt_matvec(Dd, Td, (c, e), (c, e), v)
+    assert torch.equal(got, ref)
