@@ -8,8 +8,9 @@
 //   F64    v_mfma_f64_16x16x4f64
 //   F32    v_mfma_f32_16x16x4f32
 //   BF16X3 v_mfma_f32_16x16x32_bf16 on split operands x = hi + lo (bf16, RNE),
-//          product ~ hi*hi' + hi*lo' + lo*hi' accumulated in FP32; the FP32
-//          intermediate W is split again for the second GEMM.
+//          product ~ hi*hi' + hi*lo' + lo*hi' accumulated in FP32.  The
+//          operands are split once in a bandwidth-bound pass; the first GEMM
+//          writes W already split for the second.
 //   BF16X6 the same with a three-way split x = hi + mid + lo and the six
 //          products down to the FP32 rounding level.
 //
@@ -163,15 +164,71 @@ __device__ __forceinline__ void split_bf16(float x, unsigned short (&s)[NS]) {
   }
 }
 
-// Split-operand GEMM on bf16 MFMA with FP32 accumulation.  NS = 2 keeps the
-// products hi*hi + hi*lo + lo*hi (bf16x3); NS = 3 keeps every product whose
-// order is at most the FP32 rounding level: hh + hm + mh + hl + lh + mm
-// (bf16x6).  Small terms are accumulated first.
-template <int NS, bool BT>
-__global__ __launch_bounds__(256) void gemm_bf16s_kernel(const float *__restrict__ A, int64_t lda,
-                                                         const float *__restrict__ B, int64_t ldb,
-                                                         float *__restrict__ C, int64_t ldc,
-                                                         int64_t M, int64_t N, int64_t K) {
+// ---- operand splitting (one bandwidth-bound pass per operand) ---------------
+// P[k*ps + r*cols_pad + c] = piece k of X[r][c] for c < cols, 0 for
+// cols <= c < cols_pad.  Four columns per thread.
+template <int NS>
+__global__ void split_rows_kernel(const float *__restrict__ X, int64_t ldx, int64_t rows,
+                                  int64_t cols, int64_t cols_pad, unsigned short *__restrict__ P,
+                                  int64_t ps) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t qpr = cols_pad / 4;
+  if (q >= rows * qpr) return;
+  const int64_t r = q / qpr, c0 = (q - r * qpr) * 4;
+  unsigned short sp[4][NS];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) split_bf16<NS>(c0 + u < cols ? X[r * ldx + c0 + u] : 0.f, sp[u]);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    typedef unsigned short us4 __attribute__((ext_vector_type(4)));
+    us4 v = {sp[0][k], sp[1][k], sp[2][k], sp[3][k]};
+    *reinterpret_cast<us4 *>(P + k * ps + r * cols_pad + c0) = v;
+  }
+}
+
+// P[k*ps + c*rows_pad + r] = piece k of X[r][c] (X: rows x cols), 0 for
+// rows <= r < rows_pad: the transposed split, through 32 x 32 LDS tiles.
+template <int NS>
+__global__ __launch_bounds__(256) void split_transpose_kernel(const float *__restrict__ X, int64_t ldx,
+                                                              int64_t rows, int64_t cols,
+                                                              int64_t rows_pad,
+                                                              unsigned short *__restrict__ P,
+                                                              int64_t ps) {
+  __shared__ float tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t r = r0 + j, c = c0 + tx;
+    tile[j][tx] = (r < rows && c < cols) ? X[r * ldx + c] : 0.f;
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t c = c0 + j, r = r0 + tx;  // output row c, column r
+    if (c < cols && r < rows_pad) {
+      unsigned short sp[NS];
+      split_bf16<NS>(tile[tx][j], sp);
+#pragma unroll
+      for (int k = 0; k < NS; ++k) P[k * ps + c * rows_pad + r] = sp[k];
+    }
+  }
+}
+
+// Split-operand GEMM on bf16 MFMA with FP32 accumulation, on operands split
+// beforehand: C[M x N] = sum of the kept piece products of A (M x Kp) and
+// B (N x Kp), both row-major along k with Kp a multiple of 32 (zero-padded).
+// NS = 2 keeps hi*hi + hi*lo + lo*hi (bf16x3); NS = 3 keeps every product
+// whose order is at most the FP32 rounding level: hh + hm + mh + hl + lh + mm
+// (bf16x6).  SPLIT_OUT writes C as NS split pieces (row stride ldcs, piece
+// stride cps, columns up to ncols_pad, the padding being exact zeros) for a
+// following GEMM; otherwise C is FP32.  Each thread prefetches the next k
+// step of every piece with 16-byte loads while the MFMAs consume the LDS
+// tile.
+template <int NS, bool SPLIT_OUT>
+__global__ __launch_bounds__(256) void gemm_bf16p_kernel(
+    const unsigned short *__restrict__ A, int64_t lda, int64_t aps,
+    const unsigned short *__restrict__ B, int64_t ldb, int64_t bps, float *__restrict__ C,
+    int64_t ldc, unsigned short *__restrict__ Cs, int64_t ldcs, int64_t cps, int64_t ncols_pad,
+    int64_t M, int64_t N, int64_t Kp) {
   constexpr int BM = 128, BN = 128, BK = 32, PK = BK + 8;
   __shared__ __attribute__((aligned(16))) unsigned short As[NS][BM][PK];
   __shared__ __attribute__((aligned(16))) unsigned short Bs[NS][BN][PK];
@@ -184,62 +241,42 @@ __global__ __launch_bounds__(256) void gemm_bf16s_kernel(const float *__restrict
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  // A tile BM x BK: thread -> row tid/2, 16 k's at (tid&1)*16
-  const int ar = tid >> 1, ak = (tid & 1) * 16;
-  // B: NT like A; NN: k-row tid/8 (0..31), 16 n's at (tid%8)*16
-  const int br = BT ? (tid >> 1) : (tid >> 3);
-  const int bc = BT ? ((tid & 1) * 16) : ((tid & 7) * 16);
-  float ra[16], rb[16];
-  auto load_tiles = [&](int64_t k0) {
-    const int64_t gm = m0 + ar;
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int64_t gk = k0 + ak + u;
-      ra[u] = (gm < M && gk < K) ? A[gm * lda + gk] : 0.f;
-    }
-    if (BT) {
-      const int64_t gn = n0 + br;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int64_t gk = k0 + bc + u;
-        rb[u] = (gn < N && gk < K) ? B[gn * ldb + gk] : 0.f;
-      }
-    } else {
-      const int64_t gk = k0 + br;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int64_t gn = n0 + bc + u;
-        rb[u] = (gk < K && gn < N) ? B[gk * ldb + gn] : 0.f;
-      }
-    }
-  };
-  auto store_tiles = [&]() {
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      unsigned short sp[NS];
-      split_bf16<NS>(ra[u], sp);
-#pragma unroll
-      for (int k = 0; k < NS; ++k) As[k][ar][ak + u] = sp[k];
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      unsigned short sp[NS];
-      split_bf16<NS>(rb[u], sp);
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        if (BT) Bs[k][br][bc + u] = sp[k];
-        else Bs[k][bc + u][br] = sp[k];
-      }
-    }
-  };
+  // global -> LDS: thread -> tile row tid/2, 16 k's (two 16-byte words) at
+  // (tid&1)*16.  Rows past M (N) read row 0 and are stored as zeros.
+  const int lr = tid >> 1, lk = (tid & 1) * 16;
+  const bool arow = m0 + lr < M, brow = n0 + lr < N;
+  const unsigned short *ag = A + (arow ? (m0 + lr) * lda : 0) + lk;
+  const unsigned short *bg = B + (brow ? (n0 + lr) * ldb : 0) + lk;
+  // rows past the edge are zeroed by masking (a select between two vectors
+  // would be lowered to a select between their addresses)
+  const unsigned am = arow ? 0xffffffffu : 0u, bm = brow ? 0xffffffffu : 0u;
+  const uint4 amask = {am, am, am, am}, bmask = {bm, bm, bm, bm};
+  uint4 pa[2 * NS], pb[2 * NS];
+#define GVT_BF16P_LOAD(k0)                                                                   \
+  _Pragma("unroll") for (int k = 0; k < NS; ++k) {                                           \
+    const uint4 *sa = reinterpret_cast<const uint4 *>(ag + k * aps + (k0));                  \
+    const uint4 *sb = reinterpret_cast<const uint4 *>(bg + k * bps + (k0));                  \
+    pa[2 * k] = sa[0] & amask;                                                               \
+    pa[2 * k + 1] = sa[1] & amask;                                                           \
+    pb[2 * k] = sb[0] & bmask;                                                               \
+    pb[2 * k + 1] = sb[1] & bmask;                                                           \
+  }
   auto frag = [&](const unsigned short(&X)[BM][PK], int row, int kofs) {
     return __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(&X[row][kofs]));
   };
-  load_tiles(0);
-  for (int64_t k0 = 0; k0 < K; k0 += BK) {
-    store_tiles();
+  GVT_BF16P_LOAD(0)
+  for (int64_t k0 = 0; k0 < Kp; k0 += BK) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      *reinterpret_cast<uint4 *>(&As[k][lr][lk]) = pa[2 * k];
+      *reinterpret_cast<uint4 *>(&As[k][lr][lk + 8]) = pa[2 * k + 1];
+      *reinterpret_cast<uint4 *>(&Bs[k][lr][lk]) = pb[2 * k];
+      *reinterpret_cast<uint4 *>(&Bs[k][lr][lk + 8]) = pb[2 * k + 1];
+    }
     __syncthreads();
-    if (k0 + BK < K) load_tiles(k0 + BK);
+    if (k0 + BK < Kp) {
+      GVT_BF16P_LOAD(k0 + BK)
+    }
     const int kofs = 8 * (lane >> 4), rl = lane & 15;
     bf8 af[NS][4], bfr[NS][4];
 #pragma unroll
@@ -277,7 +314,16 @@ __global__ __launch_bounds__(256) void gemm_bf16s_kernel(const float *__restrict
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
-        if (row < M && col < N) C[row * ldc + col] = acc[i][j][v];
+        if (SPLIT_OUT) {
+          if (row < M && col < ncols_pad) {
+            unsigned short sp[NS];
+            split_bf16<NS>(acc[i][j][v], sp);
+#pragma unroll
+            for (int k = 0; k < NS; ++k) Cs[k * cps + row * ldcs + col] = sp[k];
+          }
+        } else if (row < M && col < N) {
+          C[row * ldc + col] = acc[i][j][v];
+        }
       }
     }
 }
@@ -289,11 +335,37 @@ static void gemm(const T *A, int64_t lda, const T *B, int64_t ldb, T *C, int64_t
   gemm_mfma_kernel<T, BT><<<grid, 256, 0, s>>>(A, lda, B, ldb, C, ldc, M, N, K);
 }
 
-template <int NS, bool BT>
-static void gemm_bf16s(const float *A, int64_t lda, const float *B, int64_t ldb, float *C,
-                       int64_t ldc, int64_t M, int64_t N, int64_t K, hipStream_t s) {
-  dim3 grid((unsigned)ceil_div(N, 128), (unsigned)ceil_div(M, 128));
-  gemm_bf16s_kernel<NS, BT><<<grid, 256, 0, s>>>(A, lda, B, ldb, C, ldc, M, N, K);
+// Umat = M Vmat N^T with split-bf16 products: split M and N by rows and Vmat
+// transposed (k padded to a multiple of 32), W = M Vmat written as split
+// pieces by the first GEMM, then Umat = W N^T.
+template <int NS>
+static void dense_split_bf16(const float *M, int64_t mr, int64_t mc, int64_t ldm, const float *N,
+                             int64_t nr, int64_t nc, int64_t ldn, const float *V, int64_t ldv,
+                             float *U, int64_t ldu, hipStream_t s) {
+  const int64_t k1 = ceil_div(mc, 32) * 32, k2 = ceil_div(nc, 32) * 32;
+  const int64_t pm = mr * k1, pv = nc * k1, pw = mr * k2, pn = nr * k2;  // piece sizes
+  auto al = [](int64_t e) { return (e * 2 + 255) / 256 * 128; };          // elements, 256 B aligned
+  const int64_t om = 0, ov = om + NS * al(pm), ow = ov + NS * al(pv), on = ow + NS * al(pw);
+  const int64_t total = on + NS * al(pn);
+  void *buf = nullptr;
+  GVT_HIP_CHECK(hipMallocAsync(&buf, (size_t)total * 2 + 256, s));
+  unsigned short *base = (unsigned short *)buf;
+  unsigned short *Ms = base + om, *Vt = base + ov, *Ws = base + ow, *Ns = base + on;
+  // pieces of one operand are al(size) elements apart
+  split_rows_kernel<NS><<<(unsigned)ceil_div(mr * (k1 / 4), 256), 256, 0, s>>>(M, ldm, mr, mc, k1, Ms,
+                                                                             al(pm));
+  split_rows_kernel<NS><<<(unsigned)ceil_div(nr * (k2 / 4), 256), 256, 0, s>>>(N, ldn, nr, nc, k2, Ns,
+                                                                             al(pn));
+  split_transpose_kernel<NS><<<dim3((unsigned)ceil_div(k1, 32), (unsigned)ceil_div(nc, 32)), 256, 0, s>>>(
+      V, ldv, mc, nc, k1, Vt, al(pv));
+  dim3 g1((unsigned)ceil_div(nc, 128), (unsigned)ceil_div(mr, 128));
+  gemm_bf16p_kernel<NS, true><<<g1, 256, 0, s>>>(Ms, k1, al(pm), Vt, k1, al(pv), nullptr, 0, Ws, k2,
+                                                  al(pw), k2, mr, nc, k1);
+  dim3 g2((unsigned)ceil_div(nr, 128), (unsigned)ceil_div(mr, 128));
+  gemm_bf16p_kernel<NS, false><<<g2, 256, 0, s>>>(Ws, k2, al(pw), Ns, k2, al(pn), U, ldu, nullptr, 0, 0,
+                                                   0, mr, nr, k2);
+  check_launch(s);
+  GVT_HIP_CHECK(hipFreeAsync(buf, s));
 }
 
 // Umat (mr x nr) = M (mr x mc) Vmat (mc x nc) N^T (N: nr x nc)
@@ -301,6 +373,15 @@ void dense_matvec(int prec, const void *Mp, int64_t mr, int64_t mc, int64_t ldm,
                   int64_t nr, int64_t nc, int64_t ldn, const void *Vp, int64_t ldv, void *Up,
                   int64_t ldu, hipStream_t s) {
   if (mr == 0 || nr == 0) return;
+  if (prec == GVT_BF16X3 || prec == GVT_BF16X6) {
+    if (prec == GVT_BF16X3)
+      dense_split_bf16<2>((const float *)Mp, mr, mc, ldm, (const float *)Np, nr, nc, ldn,
+                          (const float *)Vp, ldv, (float *)Up, ldu, s);
+    else
+      dense_split_bf16<3>((const float *)Mp, mr, mc, ldm, (const float *)Np, nr, nc, ldn,
+                          (const float *)Vp, ldv, (float *)Up, ldu, s);
+    return;
+  }
   const size_t es = prec == GVT_F64 ? sizeof(double) : sizeof(float);
   void *W = nullptr;
   GVT_HIP_CHECK(hipMallocAsync(&W, (size_t)mr * nc * es + 256, s));
@@ -310,12 +391,6 @@ void dense_matvec(int prec, const void *Mp, int64_t mr, int64_t mc, int64_t ldm,
   } else if (prec == GVT_F32) {
     gemm<float, false>((const float *)Mp, ldm, (const float *)Vp, ldv, (float *)W, nc, mr, nc, mc, s);
     gemm<float, true>((const float *)W, nc, (const float *)Np, ldn, (float *)Up, ldu, mr, nr, nc, s);
-  } else if (prec == GVT_BF16X3) {
-    gemm_bf16s<2, false>((const float *)Mp, ldm, (const float *)Vp, ldv, (float *)W, nc, mr, nc, mc, s);
-    gemm_bf16s<2, true>((const float *)W, nc, (const float *)Np, ldn, (float *)Up, ldu, mr, nr, nc, s);
-  } else {
-    gemm_bf16s<3, false>((const float *)Mp, ldm, (const float *)Vp, ldv, (float *)W, nc, mr, nc, mc, s);
-    gemm_bf16s<3, true>((const float *)W, nc, (const float *)Np, ldn, (float *)Up, ldu, mr, nr, nc, s);
   }
   check_launch(s);
   GVT_HIP_CHECK(hipFreeAsync(W, s));
