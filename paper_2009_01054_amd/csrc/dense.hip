@@ -223,13 +223,14 @@ __global__ __launch_bounds__(256) void split_transpose_kernel(const float *__res
 // following GEMM; otherwise C is FP32.  Each thread prefetches the next k
 // step of every piece with 16-byte loads while the MFMAs consume the LDS
 // tile.
-template <int NS, bool SPLIT_OUT>
+template <int NS, bool SPLIT_OUT, int BK>
 __global__ __launch_bounds__(256) void gemm_bf16p_kernel(
     const unsigned short *__restrict__ A, int64_t lda, int64_t aps,
     const unsigned short *__restrict__ B, int64_t ldb, int64_t bps, float *__restrict__ C,
     int64_t ldc, unsigned short *__restrict__ Cs, int64_t ldcs, int64_t cps, int64_t ncols_pad,
     int64_t M, int64_t N, int64_t Kp) {
-  constexpr int BM = 128, BN = 128, BK = 32, PK = BK + 8;
+  constexpr int BM = 128, BN = 128, PK = BK + 8, WPR = BK / 16;  // 16-byte words per thread-row
+  static_assert(BK % 32 == 0, "k step: whole MFMA k blocks");
   __shared__ __attribute__((aligned(16))) unsigned short As[NS][BM][PK];
   __shared__ __attribute__((aligned(16))) unsigned short Bs[NS][BN][PK];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(256) void gemm_bf16p_kernel(
 
   // global -> LDS: thread -> tile row tid/2, 16 k's (two 16-byte words) at
   // (tid&1)*16.  Rows past M (N) read row 0 and are stored as zeros.
-  const int lr = tid >> 1, lk = (tid & 1) * 16;
+  const int lr = tid >> 1, lk = (tid & 1) * (BK / 2);
   const bool arow = m0 + lr < M, brow = n0 + lr < N;
   const unsigned short *ag = A + (arow ? (m0 + lr) * lda : 0) + lk;
   const unsigned short *bg = B + (brow ? (n0 + lr) * ldb : 0) + lk;
@@ -251,15 +252,15 @@ __global__ __launch_bounds__(256) void gemm_bf16p_kernel(
   // would be lowered to a select between their addresses)
   const unsigned am = arow ? 0xffffffffu : 0u, bm = brow ? 0xffffffffu : 0u;
   const uint4 amask = {am, am, am, am}, bmask = {bm, bm, bm, bm};
-  uint4 pa[2 * NS], pb[2 * NS];
+  uint4 pa[WPR * NS], pb[WPR * NS];
 #define GVT_BF16P_LOAD(k0)                                                                   \
   _Pragma("unroll") for (int k = 0; k < NS; ++k) {                                           \
     const uint4 *sa = reinterpret_cast<const uint4 *>(ag + k * aps + (k0));                  \
     const uint4 *sb = reinterpret_cast<const uint4 *>(bg + k * bps + (k0));                  \
-    pa[2 * k] = sa[0] & amask;                                                               \
-    pa[2 * k + 1] = sa[1] & amask;                                                           \
-    pb[2 * k] = sb[0] & bmask;                                                               \
-    pb[2 * k + 1] = sb[1] & bmask;                                                           \
+    _Pragma("unroll") for (int w = 0; w < WPR; ++w) {                                        \
+      pa[WPR * k + w] = sa[w] & amask;                                                       \
+      pb[WPR * k + w] = sb[w] & bmask;                                                       \
+    }                                                                                        \
   }
   auto frag = [&](const unsigned short(&X)[BM][PK], int row, int kofs) {
     return __builtin_bit_cast(bf8, *reinterpret_cast<const us8 *>(&X[row][kofs]));
@@ -267,17 +268,19 @@ __global__ __launch_bounds__(256) void gemm_bf16p_kernel(
   GVT_BF16P_LOAD(0)
   for (int64_t k0 = 0; k0 < Kp; k0 += BK) {
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      *reinterpret_cast<uint4 *>(&As[k][lr][lk]) = pa[2 * k];
-      *reinterpret_cast<uint4 *>(&As[k][lr][lk + 8]) = pa[2 * k + 1];
-      *reinterpret_cast<uint4 *>(&Bs[k][lr][lk]) = pb[2 * k];
-      *reinterpret_cast<uint4 *>(&Bs[k][lr][lk + 8]) = pb[2 * k + 1];
-    }
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+      for (int w = 0; w < WPR; ++w) {
+        *reinterpret_cast<uint4 *>(&As[k][lr][lk + 8 * w]) = pa[WPR * k + w];
+        *reinterpret_cast<uint4 *>(&Bs[k][lr][lk + 8 * w]) = pb[WPR * k + w];
+      }
     __syncthreads();
     if (k0 + BK < Kp) {
       GVT_BF16P_LOAD(k0 + BK)
     }
-    const int kofs = 8 * (lane >> 4), rl = lane & 15;
+#pragma unroll
+    for (int kb = 0; kb < BK; kb += 32) {
+    const int kofs = kb + 8 * (lane >> 4), rl = lane & 15;
     bf8 af[NS][4], bfr[NS][4];
 #pragma unroll
     for (int k = 0; k < NS; ++k)
@@ -304,6 +307,7 @@ __global__ __launch_bounds__(256) void gemm_bf16p_kernel(
         f4 h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0][i], bfr[0][j], acc[i][j], 0, 0, 0);
         acc[i][j] = h + c;
       }
+    }
     __syncthreads();
   }
 #pragma unroll
@@ -342,7 +346,8 @@ template <int NS>
 static void dense_split_bf16(const float *M, int64_t mr, int64_t mc, int64_t ldm, const float *N,
                              int64_t nr, int64_t nc, int64_t ldn, const float *V, int64_t ldv,
                              float *U, int64_t ldu, hipStream_t s) {
-  const int64_t k1 = ceil_div(mc, 32) * 32, k2 = ceil_div(nc, 32) * 32;
+  constexpr int KQ = NS == 2 ? 64 : 32;  // k padding: whole k steps of the GEMM
+  const int64_t k1 = ceil_div(mc, KQ) * KQ, k2 = ceil_div(nc, KQ) * KQ;
   const int64_t pm = mr * k1, pv = nc * k1, pw = mr * k2, pn = nr * k2;  // piece sizes
   auto al = [](int64_t e) { return (e * 2 + 255) / 256 * 128; };          // elements, 256 B aligned
   const int64_t om = 0, ov = om + NS * al(pm), ow = ov + NS * al(pv), on = ow + NS * al(pw);
@@ -359,11 +364,12 @@ static void dense_split_bf16(const float *M, int64_t mr, int64_t mc, int64_t ldm
   split_transpose_kernel<NS><<<dim3((unsigned)ceil_div(k1, 32), (unsigned)ceil_div(nc, 32)), 256, 0, s>>>(
       V, ldv, mc, nc, k1, Vt, al(pv));
   dim3 g1((unsigned)ceil_div(nc, 128), (unsigned)ceil_div(mr, 128));
-  gemm_bf16p_kernel<NS, true><<<g1, 256, 0, s>>>(Ms, k1, al(pm), Vt, k1, al(pv), nullptr, 0, Ws, k2,
-                                                  al(pw), k2, mr, nc, k1);
+  constexpr int BK = NS == 2 ? 64 : 32;  // k step: LDS of two blocks per CU
+  gemm_bf16p_kernel<NS, true, BK><<<g1, 256, 0, s>>>(Ms, k1, al(pm), Vt, k1, al(pv), nullptr, 0, Ws,
+                                                      k2, al(pw), k2, mr, nc, k1);
   dim3 g2((unsigned)ceil_div(nr, 128), (unsigned)ceil_div(mr, 128));
-  gemm_bf16p_kernel<NS, false><<<g2, 256, 0, s>>>(Ws, k2, al(pw), Ns, k2, al(pn), U, ldu, nullptr, 0, 0,
-                                                   0, mr, nr, k2);
+  gemm_bf16p_kernel<NS, false, BK><<<g2, 256, 0, s>>>(Ws, k2, al(pw), Ns, k2, al(pn), U, ldu, nullptr,
+                                                       0, 0, 0, mr, nr, k2);
   check_launch(s);
   GVT_HIP_CHECK(hipFreeAsync(buf, s));
 }
