@@ -130,6 +130,105 @@ __global__ __launch_bounds__(256) void stage1_kernel(
                           stg);
 }
 
+// Stage 1 with LDS-staged columns.  The keys of a block reference the same
+// F2 columns many times (every key segment runs over the same range of other
+// indices), so the block stages the columns of one chunk of
+// kStage1OtherChunk other indices, for its 64 rows, in LDS with one coalesced
+// pass, and every wave then walks the part of its keys' segments that falls
+// in the chunk, reading the column values from LDS.  The accumulators of all
+// of a wave's keys stay in registers across chunks.  Segments are sorted by
+// other index, so each key still sums its pairs in segment order: the result
+// equals the direct walk's bit for bit.  The staging buffer is reused for the
+// result tile.
+template <class T, int R, int KPW> struct S1LdsCfg {
+  static constexpr int KB = 4 * KPW;
+  static constexpr int COLS = kStage1OtherChunk * 64;  // staged column values
+  static constexpr int STG = 64 * (KB * R + 1);        // result tile
+  static constexpr int SIZE = COLS > STG ? COLS : STG;
+};
+
+template <class T, int R, int KPW>
+__device__ __forceinline__ void stage1_lds_block(
+    const T *__restrict__ Fc, int64_t ldc, const int32_t *__restrict__ rows, int64_t nrows,
+    const int32_t *__restrict__ cseg, int64_t nch, const int32_t *__restrict__ other,
+    const T *__restrict__ vs, int64_t nkeys, int64_t nother, T *__restrict__ S, int64_t ldS,
+    int64_t kb, int64_t rb, T *lds) {
+  typedef S1LdsCfg<T, R, KPW> C;
+  constexpr int OC = kStage1OtherChunk;
+  constexpr int W = C::KB * R;
+  const int lane = threadIdx.x & 63;
+  const int w = wave_id_uniform();
+  const int64_t k0 = kb * C::KB;
+  const int64_t rho0 = rb * 64;
+  // staging: this thread fills row `lane` of the chunk's columns oc = wave, wave + 4, ...
+  const int64_t frho = rho0 + lane;
+  const bool frow_ok = frho < nrows;
+  const int64_t fy = frow_ok ? rows[frho] : 0;  // row 0 stands in for rows past the end
+  T acc[KPW][R];
+#pragma unroll
+  for (int kk = 0; kk < KPW; ++kk)
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[kk][r] = T(0);
+  for (int64_t c = 0; c < nch; ++c) {
+    const int64_t o0 = c * OC;
+    __syncthreads();  // the previous chunk's reads are done
+    // unconditional loads from clamped in-range addresses, so that they all
+    // issue before the first wait; out-of-range values are replaced by zero
+#pragma unroll 8
+    for (int oc = w; oc < OC; oc += 4) {
+      const int64_t o = o0 + oc;
+      const T v = Fc[(o < nother ? o : nother - 1) * ldc + fy];
+      lds[oc * 64 + lane] = (o < nother && frow_ok) ? v : T(0);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int kk = 0; kk < KPW; ++kk) {
+      const int64_t k = k0 + w * KPW + kk;
+      if (k < nkeys) {  // uniform
+        const int64_t p0 = cseg[k * (nch + 1) + c], p1 = cseg[k * (nch + 1) + c + 1];
+        const T *col = lds + lane - o0 * 64;
+#pragma unroll 8
+        for (int64_t p = p0; p < p1; ++p) {
+          const T f = col[(int64_t)other[p] * 64];
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[kk][r] += f * vs[p * R + r];
+        }
+      }
+    }
+  }
+  __syncthreads();  // done with the columns: the buffer becomes the result tile
+#pragma unroll
+  for (int kk = 0; kk < KPW; ++kk)
+#pragma unroll
+    for (int r = 0; r < R; ++r) lds[lane * (W + 1) + (w * KPW + kk) * R + r] = acc[kk][r];
+  __syncthreads();
+  const int64_t kcount = (nkeys - k0) < C::KB ? (nkeys - k0) : C::KB;
+  const int width = (int)kcount * R;
+  for (int idx = threadIdx.x; idx < 64 * W; idx += 256) {
+    const int rr = idx / W, cc = idx - rr * W;
+    const int64_t orow = rho0 + rr;
+    if (orow < nrows && cc < width) S[orow * ldS + k0 * R + cc] = lds[rr * (W + 1) + cc];
+  }
+  // the last key block also clears the row padding (read by stage 2 as whole chunks)
+  if (k0 + C::KB >= nkeys) {
+    const int64_t padw = ldS - nkeys * R;
+    for (int64_t idx = threadIdx.x; idx < 64 * padw; idx += 256) {
+      const int64_t rr = idx / padw, cc = idx - rr * padw;
+      if (rho0 + rr < nrows) S[(rho0 + rr) * ldS + nkeys * R + cc] = T(0);
+    }
+  }
+}
+
+template <class T, int R, int KPW>
+__global__ __launch_bounds__(256) void stage1_lds_kernel(
+    const T *__restrict__ Fc, int64_t ldc, const int32_t *__restrict__ rows, int64_t nrows,
+    const int32_t *__restrict__ cseg, int64_t nch, const int32_t *__restrict__ other,
+    const T *__restrict__ vs, int64_t nkeys, int64_t nother, T *__restrict__ S, int64_t ldS) {
+  __shared__ T lds[S1LdsCfg<T, R, KPW>::SIZE];
+  stage1_lds_block<T, R, KPW>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys, nother, S, ldS,
+                              blockIdx.x, blockIdx.y, lds);
+}
+
 // Degenerate stage 1 (key == other index): S[rho, k] = F2[rows[rho], k] * s[k].
 template <class T>
 __global__ void colscale_kernel(const T *__restrict__ F, int64_t ldf, const int32_t *__restrict__ rows,
@@ -638,11 +737,58 @@ static void stage1_r(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrow
   }
 }
 
+template <class T, int R, int KPW>
+static void stage1_lds_rk(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows,
+                          const int32_t *cseg, int64_t nch, const int32_t *other, const T *vs,
+                          int64_t nkeys, int64_t nother, T *S, int64_t ldS, hipStream_t s) {
+  dim3 grid((unsigned)ceil_div(nkeys, S1LdsCfg<T, R, KPW>::KB), (unsigned)ceil_div(nrows, 64));
+  stage1_lds_kernel<T, R, KPW><<<grid, 256, 0, s>>>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys,
+                                                     nother, S, ldS);
+}
+
+// Keys per wave of the LDS-staged stage 1 (more keys = more reuse of each
+// staged column, bounded by the accumulator registers KPW x R).
+static int stage1_lds_kpw(int R) {
+  const char *ev = std::getenv("GVT_STAGE1_LDS_KPW");
+  int k = ev ? std::atoi(ev) : kStage1LdsKeysPerWave;
+  if (k != 2 && k != 4 && k != 8) k = 4;
+  while (k > 2 && k * R > 16) k /= 2;
+  return k;
+}
+
+// Whether the LDS-staged walk pays: each staged column must be used about
+// kStage1LdsMinReuse times by the block's keys (GVT_STAGE1_LDS = 0 / 1 forces it).
+static bool stage1_use_lds(int64_t npairs, int64_t nkeys, int64_t nother, int kb) {
+  const char *ev = std::getenv("GVT_STAGE1_LDS");
+  if (ev) return std::atoi(ev) != 0;
+  if (nkeys <= 0 || nother <= 0) return false;
+  const double reuse = (double)npairs / (double)nkeys * kb / (double)nother;
+  return reuse >= kStage1LdsMinReuse;
+}
+
 template <class T>
 void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
-                   const int32_t *other, const T *vs, int64_t nkeys, int R, T *S, int64_t ldS,
+                   const int32_t *cseg, int64_t nch, const int32_t *other, int64_t npairs,
+                   int64_t nother, const T *vs, int64_t nkeys, int R, T *S, int64_t ldS,
                    hipStream_t s) {
   if (nrows <= 0 || nkeys <= 0) return;
+  const int kl = stage1_lds_kpw(R);
+  if (cseg && stage1_use_lds(npairs, nkeys, nother, 4 * kl)) {
+#define GVT_S1L(RR, KK) stage1_lds_rk<T, RR, KK>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys, nother, S, ldS, s)
+    switch (R * 16 + kl) {
+      case 16 + 2: GVT_S1L(1, 2); return;
+      case 16 + 4: GVT_S1L(1, 4); return;
+      case 16 + 8: GVT_S1L(1, 8); return;
+      case 32 + 2: GVT_S1L(2, 2); return;
+      case 32 + 4: GVT_S1L(2, 4); return;
+      case 32 + 8: GVT_S1L(2, 8); return;
+      case 64 + 2: GVT_S1L(4, 2); return;
+      case 64 + 4: GVT_S1L(4, 4); return;
+      case 128 + 2: GVT_S1L(8, 2); return;
+      default: break;
+    }
+#undef GVT_S1L
+  }
   switch (R) {
     case 1: stage1_r<T, 1>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
     case 2: stage1_r<T, 2>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
@@ -783,8 +929,8 @@ void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64
                                  hipStream_t);                                                   \
   template void launch_segsum<T>(const int64_t *, const T *, int64_t, int, T *, hipStream_t);    \
   template void launch_stage1<T>(const T *, int64_t, const int32_t *, int64_t, const int64_t *,  \
-                                 const int32_t *, const T *, int64_t, int, T *, int64_t,         \
-                                 hipStream_t);                                                   \
+                                 const int32_t *, int64_t, const int32_t *, int64_t, int64_t,    \
+                                 const T *, int64_t, int, T *, int64_t, hipStream_t);            \
   template void launch_colscale<T>(const T *, int64_t, const int32_t *, int64_t, const T *,      \
                                    int64_t, int, T *, int64_t, hipStream_t);                     \
   template void launch_stage2<T>(const T *, int64_t, int64_t, const int64_t *, const int32_t *,  \

@@ -10,6 +10,8 @@ constexpr int kMaxCombineTerms = 16;
 constexpr int kStage2Rows = 32;
 constexpr int kStage2MaxS = 64;
 constexpr int kMaxCombineOut = 8;
+// Stage 1 with LDS-staged columns: other indices per staged chunk.
+constexpr int kStage1OtherChunk = 128;
 
 // Row stride (elements) of a stage-1 buffer: nkeys x R values padded to whole
 // 1 KB chunks, the unit in which stage 2 copies S rows into LDS.
@@ -30,9 +32,12 @@ void launch_pack_v(const T *V, int64_t ldv, const int32_t *perm, int64_t n, int 
                    hipStream_t s);
 template <class T>
 void launch_segsum(const int64_t *seg, const T *vs, int64_t nkeys, int R, T *out, hipStream_t s);
+// Stage 1: the direct segment walk, or with LDS-staged columns when each
+// column is reused enough (cseg: per-key chunk starts, nch chunks; null = direct).
 template <class T>
 void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
-                   const int32_t *other, const T *vs, int64_t nkeys, int R, T *S, int64_t ldS,
+                   const int32_t *cseg, int64_t nch, const int32_t *other, int64_t npairs,
+                   int64_t nother, const T *vs, int64_t nkeys, int R, T *S, int64_t ldS,
                    hipStream_t s);
 template <class T>
 void launch_colscale(const T *F, int64_t ldf, const int32_t *rows, int64_t nrows, const T *sv,

@@ -417,7 +417,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   auto need_insort = [&](int key) { insort_needed[key == SC ? 0 : 1] = true; };
   // sort by other index first, then stably by key: segments ordered by other inside
   struct SortHost {
-    std::vector<int32_t> perm, other;
+    std::vector<int32_t> perm, other, cseg;
     std::vector<int64_t> seg;
   } sort_host[2];
   auto build_insort = [&](int ks) {
@@ -432,6 +432,17 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     for (int64_t p = 0; p < n_in; ++p) o.perm[p] = perm_o[o.perm[p]];
     o.other.resize(n_in);
     for (int64_t p = 0; p < n_in; ++p) o.other[p] = h[okey][o.perm[p]];
+    // chunk starts inside each key segment (positions fit int32: n_in <= INT32_MAX)
+    const int64_t nk = nkeys_of(P, key), nch = ceil_div(nkeys_of(P, okey), kStage1OtherChunk);
+    o.cseg.resize((size_t)nk * (nch + 1));
+    for (int64_t k = 0; k < nk; ++k) {
+      int64_t p = o.seg[k];
+      for (int64_t c = 0; c <= nch; ++c) {
+        const int64_t lim = c * kStage1OtherChunk;
+        while (p < o.seg[k + 1] && o.other[p] < lim) ++p;
+        o.cseg[(size_t)k * (nch + 1) + c] = (int32_t)(c == nch ? o.seg[k + 1] : p);
+      }
+    }
   };
 
   tm.lap("term expansion");
@@ -529,6 +540,8 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
         up.add(is.perm, std::move(sort_host[ks].perm));
         up.add(is.other, std::move(sort_host[ks].other));
         up.add(is.seg, std::move(sort_host[ks].seg));
+        up.add(is.cseg, std::move(sort_host[ks].cseg));
+        is.nchunks = ceil_div(is.nother, kStage1OtherChunk);
       } else {
         up.add(is.seg, std::vector<int64_t>(is.nkeys + 1, 0));
       }
@@ -670,8 +683,9 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
       ldc = rows_of(P, sb.fsc);
     }
     launch_stage1<T>(Fc, ldc, sb.d_rows.as<int32_t>(), (int64_t)sb.rows.size(),
-                     is.seg.as<int64_t>(), is.other.as<int32_t>(), wsp<T>(P, W.vs[ks]), is.nkeys, R,
-                     S, ldS, s);
+                     is.seg.as<int64_t>(), is.cseg.as<int32_t>(), is.nchunks,
+                     is.other.as<int32_t>(), P->n_in, is.nother, wsp<T>(P, W.vs[ks]), is.nkeys, R, S,
+                     ldS, s);
   }
   mark(P, ST_STAGE1, 1, s);
   // two-factor terms: stage 2

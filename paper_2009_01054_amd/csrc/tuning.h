@@ -23,4 +23,6 @@ namespace gvt {
 constexpr double kStage2TargetR1 = 32.0;
 constexpr double kStage2TargetR8 = 16.0;
 constexpr int kStage1KeysPerWave = 2;
+constexpr int kStage1LdsKeysPerWave = 4;
+constexpr double kStage1LdsMinReuse = 1e300;  // LDS-staged stage 1 off
 }  // namespace gvt

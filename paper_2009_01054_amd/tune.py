@@ -10,11 +10,14 @@ right-hand sides share a pass.  There is one target per RHS class.  Stage 1
 walks key segments with one wave per key; the number of keys each wave walks
 trades waves in flight against per-wave work.
 
-This script sweeps the three knobs on synthetic workloads shaped like the
+Stage 1 can also stage the F2 columns of a chunk of other indices in LDS
+and read them from there (worth it only if each column is reused enough).
+
+This script sweeps the four knobs on synthetic workloads shaped like the
 library's benchmarks, through the library's environment overrides
-(GVT_STAGE1_KPW, GVT_STAGE2_TARGET_R1, GVT_STAGE2_TARGET_R8; the targets are
-read when a plan is built), and writes the winners as a C++ header that
-``build.py`` compiles into the library:
+(GVT_STAGE1_LDS, GVT_STAGE1_KPW, GVT_STAGE2_TARGET_R1, GVT_STAGE2_TARGET_R8;
+the targets are read when a plan is built), and writes the winners as a C++
+header that ``build.py`` compiles into the library:
 
     python -m paper_2009_01054_amd.tune --out paper_2009_01054_amd/csrc/tuning.h
 
@@ -36,6 +39,7 @@ if ROOT not in sys.path:
 R1_CANDIDATES = (8.0, 16.0, 32.0, 64.0, 128.0)
 R8_CANDIDATES = (2.0, 4.0, 8.0, 16.0, 32.0)
 KPW_CANDIDATES = (1, 2, 4)
+LDS_CANDIDATES = (0, 1)  # stage 1: direct walk, or LDS-staged columns where reused >= 1.5 times
 
 
 def _log(*a):
@@ -54,11 +58,12 @@ def _events_ms(torch, fn, reps):
     return s.elapsed_time(e) / reps
 
 
-_KNOBS = {0: "GVT_STAGE2_TARGET_R1", 1: "GVT_STAGE2_TARGET_R8", "kpw": "GVT_STAGE1_KPW"}
+_KNOBS = {0: "GVT_STAGE2_TARGET_R1", 1: "GVT_STAGE2_TARGET_R8", "kpw": "GVT_STAGE1_KPW",
+          "lds": "GVT_STAGE1_LDS"}
 
 
 def _set_target(cls, value):
-    os.environ[_KNOBS[cls]] = str(int(value)) if cls == "kpw" else repr(float(value))
+    os.environ[_KNOBS[cls]] = str(int(value)) if cls in ("kpw", "lds") else repr(float(value))
 
 
 def ridge_products(gvt, W, torch, nrhs, reps):
@@ -142,6 +147,9 @@ def write_header(path, results, device):
               f"constexpr double kStage2TargetR1 = {results['R1'][0]:.1f};",
               f"constexpr double kStage2TargetR8 = {results['R8'][0]:.1f};",
               f"constexpr int kStage1KeysPerWave = {int(results['KPW'][0])};",
+              "constexpr int kStage1LdsKeysPerWave = 4;",
+              "constexpr double kStage1LdsMinReuse = "
+              + ("1.5;" if results["LDS"][0] else "1e300;  // LDS-staged stage 1 off"),
               "}  // namespace gvt", ""]
     with open(path, "w") as f:
         f.write("\n".join(lines))
@@ -167,8 +175,8 @@ def main():
     r8 = ridge_products(gvt, W, torch, 8, max(2, args.reps // 4)) + batched_iterations(
         gvt, W, torch, args.batched_problems)
     results = {}
-    for key, cls, cands, wl in (("KPW", "kpw", KPW_CANDIDATES, r1), ("R1", 0, R1_CANDIDATES, r1),
-                                ("R8", 1, R8_CANDIDATES, r8)):
+    for key, cls, cands, wl in (("LDS", "lds", LDS_CANDIDATES, r1), ("KPW", "kpw", KPW_CANDIDATES, r1),
+                                ("R1", 0, R1_CANDIDATES, r1), ("R8", 1, R8_CANDIDATES, r8)):
         winner, table, score = sweep(cls, cands, wl)
         results[key] = (winner, table, score, [n for n, _ in wl])
         _log(f"[tune] class {key}: target {winner:g}")

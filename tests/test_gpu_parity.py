@@ -400,14 +400,23 @@ def test_cg_batched_warm_start_and_cap(gvt):
     assert np.isfinite(rel3).all() and (rel3 < 1.0).all()
 
 
-@pytest.mark.parametrize("kpw", ["1", "2"])
-def test_stage1_keys_per_wave_variants_are_bitwise_equal(gvt, kpw, monkeypatch):
-    # every variant sums a key's segment in the same order, so products agree exactly
-    p = W.make_heterogeneous(99, 0, 150, 70, 3000, 8)
+@pytest.mark.parametrize("env", [{"GVT_STAGE1_KPW": "1"}, {"GVT_STAGE1_KPW": "2"},
+                                 {"GVT_STAGE1_LDS": "1", "GVT_STAGE1_LDS_KPW": "2"},
+                                 {"GVT_STAGE1_LDS": "1", "GVT_STAGE1_LDS_KPW": "4"},
+                                 {"GVT_STAGE1_LDS": "1", "GVT_STAGE1_LDS_KPW": "8"}])
+@pytest.mark.parametrize("nrhs", [1, 3, 8])
+def test_stage1_variants_are_bitwise_equal(gvt, env, nrhs, monkeypatch):
+    # every stage-1 variant (direct walk with 1, 2 or 4 keys per wave; LDS-staged columns with
+    # 2, 4 or 8) sums a key's segment in the same order, so products agree exactly; the
+    # other-index range (700) spans several staged chunks of 128 and a ragged last one
+    p = W.make_heterogeneous(99, 0, 900, 700, 30000, 8)
     Dd, Td = dev(p["D"]), dev(p["T"])
     c, e = idx(p["c"]), idx(p["e"])
-    v = dev(np.random.default_rng(5).standard_normal((len(p["c"]), 3)))
+    v = dev(np.random.default_rng(5).standard_normal((len(p["c"]), nrhs)))
+    monkeypatch.setenv("GVT_STAGE1_LDS", "0")
+    monkeypatch.setenv("GVT_STAGE1_KPW", "4")
     ref = gvt.gvt_matvec(Dd, Td, (c, e), (c, e), v)
-    monkeypatch.setenv("GVT_STAGE1_KPW", kpw)
+    for k, val in env.items():
+        monkeypatch.setenv(k, val)
     got = gvt.gvt_matvec(Dd, Td, (c, e), (c, e), v)
     assert torch.equal(got, ref)
