@@ -581,6 +581,53 @@ __global__ __launch_bounds__(256) void match_kernel(const T *__restrict__ F, int
   }
 }
 
+// Cartesian match terms with the F row staged in LDS: one block per F row x
+// stages F[x, :] and its 16-lane groups walk the outputs of that row, each
+// summing its key segment; the gathers F[x, other_p] then hit LDS instead of
+// scattered cache lines.  All R right-hand sides share one walk.
+template <class T, int R>
+__global__ __launch_bounds__(256) void match_row_kernel(const T *__restrict__ F, int64_t ldf,
+                                                        int64_t ncols,
+                                                        const int32_t *__restrict__ operm,
+                                                        const int64_t *__restrict__ xoff,
+                                                        const int32_t *__restrict__ ksel,
+                                                        const int64_t *__restrict__ seg,
+                                                        const int32_t *__restrict__ other,
+                                                        const T *__restrict__ vs, int64_t nkeys,
+                                                        T *__restrict__ t) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char match_smem[];
+  T *row = reinterpret_cast<T *>(match_smem);
+  constexpr int G = 16;
+  const int64_t x = blockIdx.x;
+  const int64_t q0 = xoff[x], q1 = xoff[x + 1];
+  if (q0 == q1) return;  // uniform: no outputs on this row
+  const T *frow = F + x * ldf;
+  for (int64_t c = threadIdx.x; c < ncols; c += 256) row[c] = frow[c];
+  __syncthreads();
+  const int sub = threadIdx.x % G, grp = threadIdx.x / G;
+  for (int64_t q = q0 + grp; q < q1; q += 256 / G) {
+    const int64_t i = operm[q];
+    const int64_t kv = ksel[i];
+    int64_t p0 = 0, p1 = 0;
+    if (kv < nkeys) { p0 = seg[kv]; p1 = seg[kv + 1]; }
+    T acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = T(0);
+    for (int64_t p = p0 + sub; p < p1; p += G) {
+      const T f = row[other[p]];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += f * vs[p * R + r];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      T v = acc[r];
+#pragma unroll
+      for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off);
+      if (sub == 0) t[i * R + r] = v;
+    }
+  }
+}
+
 // Ft[o*ldt + y] = F[y*ldf + o]  (32x32 LDS tiles)
 template <class T>
 __global__ __launch_bounds__(256) void transpose_kernel(const T *__restrict__ F, int64_t ldf,
@@ -853,10 +900,23 @@ void launch_gather_rows(const T *g, const int32_t *sel, int64_t n, int R, T *t, 
 }
 
 template <class T>
-void launch_match(const T *F, int64_t ldf, const int32_t *xsel, const int32_t *ksel, int64_t n,
+void launch_match(const T *F, int64_t ldf, int64_t ncols, const int32_t *xsel, const int32_t *ksel,
+                  int64_t n, const int32_t *operm, const int64_t *xoff, int64_t nxrows,
                   const int64_t *seg, const int32_t *other, const T *vs, int64_t nkeys, int R, T *t,
                   hipStream_t s) {
   if (n <= 0) return;
+  const size_t row_bytes = (size_t)ncols * sizeof(T);
+  if (operm && xoff && nxrows > 0 && row_bytes <= (64 << 10)) {
+    const unsigned g = (unsigned)nxrows;
+    const size_t sh = row_bytes ? row_bytes : sizeof(T);
+    switch (R) {
+      case 1: match_row_kernel<T, 1><<<g, 256, sh, s>>>(F, ldf, ncols, operm, xoff, ksel, seg, other, vs, nkeys, t); return;
+      case 2: match_row_kernel<T, 2><<<g, 256, sh, s>>>(F, ldf, ncols, operm, xoff, ksel, seg, other, vs, nkeys, t); return;
+      case 4: match_row_kernel<T, 4><<<g, 256, sh, s>>>(F, ldf, ncols, operm, xoff, ksel, seg, other, vs, nkeys, t); return;
+      case 8: match_row_kernel<T, 8><<<g, 256, sh, s>>>(F, ldf, ncols, operm, xoff, ksel, seg, other, vs, nkeys, t); return;
+      default: break;
+    }
+  }
   match_kernel<T><<<grid1(n * 16, 256), 256, 0, s>>>(F, ldf, xsel, ksel, n, seg, other, vs, nkeys, R, t);
 }
 
@@ -945,7 +1005,8 @@ void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64
                                hipStream_t);                                                     \
   template void launch_gather_rows<T>(const T *, const int32_t *, int64_t, int, T *,             \
                                       hipStream_t);                                              \
-  template void launch_match<T>(const T *, int64_t, const int32_t *, const int32_t *, int64_t,   \
+  template void launch_match<T>(const T *, int64_t, int64_t, const int32_t *, const int32_t *,   \
+                                int64_t, const int32_t *, const int64_t *, int64_t,              \
                                 const int64_t *, const int32_t *, const T *, int64_t, int, T *,  \
                                 hipStream_t);                                                    \
   template void launch_transpose<T>(const T *, int64_t, int64_t, int64_t, T *, int64_t,          \

@@ -58,8 +58,12 @@ void launch_gemv(const T *F, int64_t ldf, int64_t nrows, int64_t ncols, bool sq,
                  T *g, hipStream_t s);
 template <class T>
 void launch_gather_rows(const T *g, const int32_t *sel, int64_t n, int R, T *t, hipStream_t s);
+// Cartesian match terms.  With outputs grouped by F row (operm/xoff over
+// nxrows rows) and a row of at most 64 KB, one block stages its row in LDS;
+// otherwise one 16-lane group per output gathers from global memory.
 template <class T>
-void launch_match(const T *F, int64_t ldf, const int32_t *xsel, const int32_t *ksel, int64_t n,
+void launch_match(const T *F, int64_t ldf, int64_t ncols, const int32_t *xsel, const int32_t *ksel,
+                  int64_t n, const int32_t *operm, const int64_t *xoff, int64_t nxrows,
                   const int64_t *seg, const int32_t *other, const T *vs, int64_t nkeys, int R, T *t,
                   hipStream_t s);
 template <class T>

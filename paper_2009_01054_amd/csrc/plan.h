@@ -28,9 +28,9 @@ struct InputSort {  // input pairs sorted by one index (key segments), then by t
 
 struct OutOrder {  // output pairs grouped by one output-side index
   bool built = false;
-  std::vector<int32_t> h_perm;
-  DevMem perm;  // int32[n_out]: position -> output index i
-  DevMem xs;    // int32[n_out]: the grouping index at that position
+  int64_t nrows = 0;  // range of the grouping index
+  DevMem perm;        // int32[n_out]: position -> output index i
+  DevMem off;         // int64[nrows + 1]: first position of each index value
 };
 
 struct SBufSpec {  // one stage-1 result S = scatter of F_sc by `key` with column index `other`

@@ -414,6 +414,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   auto sel_host = [&](int sel) -> const std::vector<int32_t> & { return h[sel]; };
   auto sel_dev = [&](int sel) -> const int32_t * { return P->idx[sel].as<int32_t>(); };
   bool insort_needed[2] = {false, false};
+  bool outord_needed[2] = {false, false};  // outputs grouped by a / by b (match terms)
   auto need_insort = [&](int key) { insort_needed[key == SC ? 0 : 1] = true; };
   // sort by other index first, then stably by key: segments ordered by other inside
   struct SortHost {
@@ -492,6 +493,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     } else {
       ts.f = t.a0; ts.x = t.a1; ts.outkey = t.a2; ts.key = t.a3;
       need_insort(ts.key);
+      outord_needed[ts.x == SA ? 0 : 1] = true;
       P->cost_fma += n_out_d * (n_in_d / std::max<double>(1.0, (double)nkeys_of(P, ts.key)));
     }
   }
@@ -523,6 +525,13 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     for (int ks = 0; ks < 2; ++ks)
       if (insort_needed[ks] && n_in > 0)
         th.emplace_back([&, ks]() { guard(ks, [&]() { build_insort(ks); }); });
+    std::vector<int32_t> oo_perm[2];
+    std::vector<int64_t> oo_off[2];
+    for (int xs = 0; xs < 2; ++xs)
+      if (outord_needed[xs] && n_out > 0)
+        th.emplace_back([&, xs]() {
+          counting_sort(h[xs == 0 ? SA : SB], xs == 0 ? d_rows : t_rows, oo_perm[xs], oo_off[xs]);
+        });
     const int cls = tile_class(rhs_hint);
     for (size_t k = 0; k < tiles.size(); ++k)
       th.emplace_back([&, k]() {
@@ -548,6 +557,14 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       is.built = true;
     }
     for (auto &tk : tiles) install_tiles(tk.first->tiles[cls], std::move(tk.second), &up);
+    for (int xs = 0; xs < 2; ++xs) {
+      if (!outord_needed[xs] || n_out == 0) continue;
+      OutOrder &oo = P->outord[xs];
+      oo.nrows = xs == 0 ? d_rows : t_rows;
+      up.add(oo.perm, std::move(oo_perm[xs]));
+      up.add(oo.off, std::move(oo_off[xs]));
+      oo.built = true;
+    }
   }
   tm.lap("input sorts + term orderings");
   bool need_idx = false;
@@ -722,9 +739,11 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
     } else {
       const int ks = t.key == SC ? 0 : 1;
       const InputSort &is = P->insort[ks];
-      launch_match<T>(F[t.f], ldF[t.f], dev_sel[t.x], dev_sel[t.outkey], P->n_out,
-                      is.seg.as<int64_t>(), is.other.as<int32_t>(), wsp<T>(P, W.vs[ks]), is.nkeys,
-                      R, wsp<T>(P, W.tvec[ti]), s);
+      const OutOrder &oo = P->outord[t.x == SA ? 0 : 1];
+      launch_match<T>(F[t.f], ldF[t.f], cols_of(P, t.f), dev_sel[t.x], dev_sel[t.outkey], P->n_out,
+                      oo.perm.as<int32_t>(), oo.off.as<int64_t>(), oo.nrows, is.seg.as<int64_t>(),
+                      is.other.as<int32_t>(), wsp<T>(P, W.vs[ks]), is.nkeys, R,
+                      wsp<T>(P, W.tvec[ti]), s);
     }
   }
   if (!P->direct) {
