@@ -236,6 +236,14 @@ def preset_batched(args, gvt, W, torch, np, dev):
                      "Gaussian bases (32-dim), 8 lambdas 1e-4..1e3, tol 1e-6, <= 200 iterations",
            "sum_n": int(sum(sh[2] for sh in shapes)), "systems": len(probs) * len(lams)}
     out = {}
+    # setup cost inside each solve (256 plans, workspaces, descriptors): a one-iteration solve
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gvt.gvt_krr_cg_batched("kronecker", dp, lams, max_iter=1, tol=1e-6, matvec_prec=gvt.F32, check_every=8)
+    torch.cuda.synchronize()
+    res["one_iteration_solve_seconds"] = round(time.perf_counter() - t0, 4)
+    log(f"[bench] one-iteration solve (setup + 1 iteration + final residual): "
+        f"{res['one_iteration_solve_seconds']:.3f} s")
     for name, prec in [("f32", gvt.F32), ("f64", gvt.F64)]:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
