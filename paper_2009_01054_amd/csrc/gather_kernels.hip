@@ -284,7 +284,7 @@ template <class T, int R> struct S2Cfg {
 
 template <class T, int R> struct S2Smem {
   __attribute__((aligned(16))) T tile[kStage2MaxS * (S2Cfg<T, R>::ROWE + S2Cfg<T, R>::PADE)];
-  unsigned char meta[S2Cfg<T, R>::NG][S2Cfg<T, R>::OPG];
+  __attribute__((aligned(4))) unsigned char meta[S2Cfg<T, R>::NG][S2Cfg<T, R>::OPG];
 };
 
 // Body of one stage-2 tile t; shared by the single-product kernel and the
@@ -317,6 +317,16 @@ __device__ __forceinline__ void stage2_tile(
     __syncthreads();
     for (int o = sub; o < C::OPG; o += C::LPO)
       meta[grp][o] = (o < npass) ? (unsigned char)(yrows[qb + pass0 + o] - y0) : 0;
+    // FP32: this group's S-row bytes for the pass, packed four to a register
+    // (FP64 has no registers to spare and reads them from LDS per chunk)
+    constexpr bool kPack = sizeof(T) == 4;
+    static_assert(C::OPG % 4 == 0, "whole 32-bit words of meta");
+    unsigned mp[C::OPG / 4];
+    if (kPack) {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < C::OPG / 4; ++j) mp[j] = *reinterpret_cast<const unsigned *>(&meta[grp][4 * j]);
+    }
     T acc[C::OPG][R];
 #pragma unroll
     for (int o = 0; o < C::OPG; ++o)
@@ -343,7 +353,8 @@ __device__ __forceinline__ void stage2_tile(
 #pragma unroll
       for (int o = 0; o < C::OPG; ++o) {
         if (o < npass) {
-          const T *trow = tile + (int)meta[grp][o] * TROW + sub * C::EPL;
+          const int mrow = kPack ? (int)((mp[o >> 2] >> (8 * (o & 3))) & 0xffu) : (int)meta[grp][o];
+          const T *trow = tile + mrow * TROW + sub * C::EPL;
           // all reads of this output first (distinct registers), then the FMAs
           V16 sv[C::STEPS][C::EPL / C::VEC];
 #pragma unroll
