@@ -143,6 +143,119 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(const T *__restrict__ A,
     }
 }
 
+// MFMA GEMM with 16-byte loads (rows 16-byte aligned, K and N multiples of the
+// vector length): C[M x N] = A[M x K] * op(B), op(B)[k][n] = BT ? B[n*ldb + k]
+// : B[k*ldb + n].  A (and B^T) tiles are stored row-major along k with a row
+// stride of BK + 16 bytes, which keeps both the 16-byte stores and the MFMA
+// operand reads (16 rows at one k, four k's per wave) free of bank conflicts;
+// a row-major B tile keeps n contiguous.  k steps of 32 (FP32) or 16 (FP64)
+// elements, the next step prefetched into registers.
+template <class T, bool BT>
+__global__ __launch_bounds__(256) void gemm_vec_kernel(const T *__restrict__ A, int64_t lda,
+                                                       const T *__restrict__ B, int64_t ldb,
+                                                       T *__restrict__ C, int64_t ldc, int64_t M,
+                                                       int64_t N, int64_t K) {
+  constexpr int VEC = 16 / sizeof(T);            // elements per 16-byte vector
+  constexpr int BM = 128, BN = 128, BK = sizeof(T) == 4 ? 32 : 16;
+  constexpr int AS = BK + VEC;                   // row stride: k step + 16 bytes
+  constexpr int KPT = BK / 2, NV = KPT / VEC;    // elements / vectors per thread and operand
+  constexpr int TPR = 256 / BK;                  // threads per k-row of a row-major B tile
+  typedef T vt __attribute__((ext_vector_type(VEC)));
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ __attribute__((aligned(16))) T As[BM][AS];
+  __shared__ __attribute__((aligned(16))) T Bs[BT ? BN : BK][BT ? AS : BN + VEC];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  acc_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
+  // A (and B^T): thread -> row tid/2, KPT k's at (tid&1)*KPT
+  const int ar = tid >> 1, ak = (tid & 1) * KPT;
+  // row-major B: thread -> k-row tid/TPR, KPT n's at (tid%TPR)*KPT
+  const int bk = tid / TPR, bn = (tid % TPR) * KPT;
+  const bool arow = m0 + ar < M;
+  const bool brow = BT ? (n0 + ar < N) : true;
+  const unsigned am = arow ? 0xffffffffu : 0u, bm = brow ? 0xffffffffu : 0u;
+  // row starts (row 0 stands in for rows past the edge); every fallback address is a
+  // row start, valid because the vector path needs K >= VEC
+  const T *ag = A + (arow ? (m0 + ar) * lda : 0);
+  const T *bg = BT ? B + (brow ? (n0 + ar) * ldb : 0) : B;
+  vt pa[NV], pb[NV];
+  auto masked = [](vt v, unsigned mk) {
+    return __builtin_bit_cast(vt, __builtin_bit_cast(uint4, v) & uint4{mk, mk, mk, mk});
+  };
+  auto load = [&](int64_t k0) {
+    // rows past the edge and vectors past K are zeroed by a mask (not a select of
+    // addresses); K is a multiple of VEC, so a vector is wholly inside or outside
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const bool kin = k0 + ak + VEC * u < K;
+      pa[u] = masked(*reinterpret_cast<const vt *>(ag + (kin ? k0 + ak + VEC * u : 0)), kin ? am : 0u);
+    }
+    if (BT) {
+#pragma unroll
+      for (int u = 0; u < NV; ++u) {
+        const bool kin = k0 + ak + VEC * u < K;
+        pb[u] = masked(*reinterpret_cast<const vt *>(bg + (kin ? k0 + ak + VEC * u : 0)), kin ? bm : 0u);
+      }
+    } else {
+      const int64_t gk = k0 + bk;
+#pragma unroll
+      for (int u = 0; u < NV; ++u) {
+        const int64_t gn = n0 + bn + VEC * u;
+        const bool ok = gk < K && gn < N;  // N is a multiple of VEC
+        pb[u] = masked(*reinterpret_cast<const vt *>(B + (ok ? gk * ldb + gn : 0)), ok ? 0xffffffffu : 0u);
+      }
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) *reinterpret_cast<vt *>(&As[ar][ak + VEC * u]) = pa[u];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      if (BT) *reinterpret_cast<vt *>(&Bs[ar][ak + VEC * u]) = pb[u];
+      else *reinterpret_cast<vt *>(&Bs[bk][bn + VEC * u]) = pb[u];
+    }
+  };
+  const int64_t kend = (K + BK - 1) / BK * BK;
+  load(0);
+  for (int64_t k0 = 0; k0 < kend; k0 += BK) {
+    store();
+    __syncthreads();
+    if (k0 + BK < kend) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4), cl = lane & 15;
+      T af[4], bf[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = As[wm * 64 + i * 16 + cl][kr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bf[j] = BT ? Bs[wn * 64 + j * 16 + cl][kr] : Bs[kr][wn * 64 + j * 16 + cl];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::op(af[i], bf[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = n0 + wn * 64 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = m0 + wm * 64 + i * 16 + Mfma<T>::row(lane, v);
+        if (row < M && col < N) C[row * ldc + col] = acc[i][j][v];
+      }
+    }
+}
+
 // ---- split-bf16 products ------------------------------------------------------
 __device__ __forceinline__ unsigned short bf16_rne_bits(float x) {
   unsigned int u = __float_as_uint(x);
@@ -336,6 +449,13 @@ template <class T, bool BT>
 static void gemm(const T *A, int64_t lda, const T *B, int64_t ldb, T *C, int64_t ldc, int64_t M,
                  int64_t N, int64_t K, hipStream_t s) {
   dim3 grid((unsigned)ceil_div(N, 128), (unsigned)ceil_div(M, 128));
+  // 16-byte loads need aligned rows and whole vectors along k (and along n for B)
+  constexpr int64_t V = 16 / sizeof(T);
+  auto al16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+  if (al16(A) && al16(B) && lda % V == 0 && ldb % V == 0 && K % V == 0 && (BT || N % V == 0)) {
+    gemm_vec_kernel<T, BT><<<grid, 256, 0, s>>>(A, lda, B, ldb, C, ldc, M, N, K);
+    return;
+  }
   gemm_mfma_kernel<T, BT><<<grid, 256, 0, s>>>(A, lda, B, ldb, C, ldc, M, N, K);
 }
 
