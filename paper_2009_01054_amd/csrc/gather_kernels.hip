@@ -8,6 +8,7 @@
 // sum is a sequential loop or a fixed lane tree: results are deterministic
 // (no atomics).  Several right-hand sides (R) ride along in the innermost
 // dimension so that each gathered base-matrix element feeds R FMAs.
+#include <atomic>
 #include <cstdlib>
 
 #include "common.h"
@@ -776,13 +777,25 @@ static void stage1_rk(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nro
   stage1_kernel<T, R, KPW><<<grid, 256, 0, s>>>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS);
 }
 
-// Keys per wave of the single-product stage 1 (tuning.h; GVT_STAGE1_KPW = 1, 2
-// or 4 overrides it for tuning sweeps).
-static int stage1_kpw() {
-  const char *ev = std::getenv("GVT_STAGE1_KPW");
-  const int k = ev ? std::atoi(ev) : kStage1KeysPerWave;
-  return (k == 1 || k == 2 || k == 4) ? k : 4;
+// Launch knobs of stage 1: the tuned constants (tuning.h), overridable through
+// GVT_STAGE1_KPW (1, 2 or 4 keys per wave), GVT_STAGE1_LDS (0 / 1 forces the
+// LDS-staged walk off / on) and GVT_STAGE1_LDS_KPW (2, 4 or 8) for tuning
+// sweeps.  The environment is read when a plan is built, not per launch.
+static std::atomic<int> g_s1_kpw{kStage1KeysPerWave}, g_s1_lds{-1},
+    g_s1_lds_kpw{kStage1LdsKeysPerWave};
+
+void refresh_launch_knobs() {
+  const char *e1 = std::getenv("GVT_STAGE1_KPW");
+  const int k = e1 ? std::atoi(e1) : kStage1KeysPerWave;
+  g_s1_kpw.store((k == 1 || k == 2 || k == 4) ? k : 4, std::memory_order_relaxed);
+  const char *e2 = std::getenv("GVT_STAGE1_LDS");
+  g_s1_lds.store(e2 ? (std::atoi(e2) != 0) : -1, std::memory_order_relaxed);
+  const char *e3 = std::getenv("GVT_STAGE1_LDS_KPW");
+  const int kl = e3 ? std::atoi(e3) : kStage1LdsKeysPerWave;
+  g_s1_lds_kpw.store((kl == 2 || kl == 4 || kl == 8) ? kl : 4, std::memory_order_relaxed);
 }
+
+static int stage1_kpw() { return g_s1_kpw.load(std::memory_order_relaxed); }
 
 template <class T, int R>
 static void stage1_r(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
@@ -807,9 +820,7 @@ static void stage1_lds_rk(const T *Fc, int64_t ldc, const int32_t *rows, int64_t
 // Keys per wave of the LDS-staged stage 1 (more keys = more reuse of each
 // staged column, bounded by the accumulator registers KPW x R).
 static int stage1_lds_kpw(int R) {
-  const char *ev = std::getenv("GVT_STAGE1_LDS_KPW");
-  int k = ev ? std::atoi(ev) : kStage1LdsKeysPerWave;
-  if (k != 2 && k != 4 && k != 8) k = 4;
+  int k = g_s1_lds_kpw.load(std::memory_order_relaxed);
   while (k > 2 && k * R > 16) k /= 2;
   return k;
 }
@@ -817,8 +828,8 @@ static int stage1_lds_kpw(int R) {
 // Whether the LDS-staged walk pays: each staged column must be used about
 // kStage1LdsMinReuse times by the block's keys (GVT_STAGE1_LDS = 0 / 1 forces it).
 static bool stage1_use_lds(int64_t npairs, int64_t nkeys, int64_t nother, int kb) {
-  const char *ev = std::getenv("GVT_STAGE1_LDS");
-  if (ev) return std::atoi(ev) != 0;
+  const int forced = g_s1_lds.load(std::memory_order_relaxed);
+  if (forced >= 0) return forced != 0;
   if (nkeys <= 0 || nother <= 0) return false;
   const double reuse = (double)npairs / (double)nkeys * kb / (double)nother;
   return reuse >= kStage1LdsMinReuse;

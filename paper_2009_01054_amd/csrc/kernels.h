@@ -32,6 +32,10 @@ void launch_pack_v(const T *V, int64_t ldv, const int32_t *perm, int64_t n, int 
                    hipStream_t s);
 template <class T>
 void launch_segsum(const int64_t *seg, const T *vs, int64_t nkeys, int R, T *out, hipStream_t s);
+// Re-read the environment overrides of the tuned launch shapes (called when a
+// plan is built).
+void refresh_launch_knobs();
+
 // Stage 1: the direct segment walk, or with LDS-staged columns when each
 // column is reused enough (cseg: per-key chunk starts, nch chunks; null = direct).
 template <class T>

@@ -131,6 +131,23 @@ double stage2_target(int cls) {
   return cls ? kStage2TargetR8 : kStage2TargetR1;
 }
 
+// Host tasks of a plan build: on their own threads for large inputs, inline
+// for small ones (where starting a thread costs more than the task).
+struct TaskGroup {
+  bool par;
+  std::vector<std::thread> th;
+  explicit TaskGroup(bool parallel) : par(parallel) {}
+  template <class F> void run(F f) {
+    if (par) th.emplace_back(std::move(f));
+    else f();
+  }
+  void join() {
+    for (auto &t : th) t.join();
+    th.clear();
+  }
+  ~TaskGroup() { join(); }
+};
+
 }  // namespace
 
 int stage2_block_rows(const gvt_plan *P, const TermSpec &t, int cls) {
@@ -256,6 +273,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   GVT_REQUIRE((n_out == 0 || (a && b)) && (n_in == 0 || (c && e)), GVT_ERR_ARG, "null index array");
   GVT_REQUIRE(!((flags & GVT_FLAG_ORDER_A) && (flags & GVT_FLAG_ORDER_B)), GVT_ERR_ARG,
               "ORDER_A and ORDER_B are exclusive");
+  refresh_launch_knobs();
   P->kinds.assign(kinds, kinds + nkinds);
   P->flags = flags;
   bool hom = false;
@@ -305,11 +323,11 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     P->uniq[i] = count_unique(v, L > 0 ? std::max(lim[i], i2 >= 0 ? lim[i2] : 0) : 0);
   };
   {
-    std::vector<std::thread> th;
+    TaskGroup tg(n_in + n_out >= (1 << 16));
     const int na = alias ? 2 : 4;
-    for (int i = 1; i < na; ++i) th.emplace_back(check, i);
+    for (int i = 1; i < na; ++i) tg.run([&, i]() { check(i); });
     check(0);
-    for (auto &t : th) t.join();
+    tg.join();
   }
   for (int i = 0; i < (alias ? 2 : 4); ++i) {
     if (bad[i] < 0) continue;
@@ -513,7 +531,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     std::vector<std::pair<TermSpec *, TileHost>> tiles;
     for (TermSpec &ts : P->terms)
       if (ts.type == TG && n_out > 0) tiles.push_back({&ts, TileHost{}});
-    std::vector<std::thread> th;
+    TaskGroup tg(n_in + n_out >= (1 << 16));
     std::vector<std::exception_ptr> errs(tiles.size() + 2);
     auto guard = [&](size_t slot, auto fn) {
       try {
@@ -524,20 +542,20 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     };
     for (int ks = 0; ks < 2; ++ks)
       if (insort_needed[ks] && n_in > 0)
-        th.emplace_back([&, ks]() { guard(ks, [&]() { build_insort(ks); }); });
+        tg.run([&, ks]() { guard(ks, [&]() { build_insort(ks); }); });
     std::vector<int32_t> oo_perm[2];
     std::vector<int64_t> oo_off[2];
     for (int xs = 0; xs < 2; ++xs)
       if (outord_needed[xs] && n_out > 0)
-        th.emplace_back([&, xs]() {
+        tg.run([&, xs]() {
           counting_sort(h[xs == 0 ? SA : SB], xs == 0 ? d_rows : t_rows, oo_perm[xs], oo_off[xs]);
         });
     const int cls = tile_class(rhs_hint);
     for (size_t k = 0; k < tiles.size(); ++k)
-      th.emplace_back([&, k]() {
+      tg.run([&, k]() {
         guard(2 + k, [&]() { tiles[k].second = compute_tiles(P, *tiles[k].first, cls); });
       });
-    for (auto &t : th) t.join();
+    tg.join();
     for (auto &ep : errs)
       if (ep) std::rethrow_exception(ep);
     for (int ks = 0; ks < 2; ++ks) {
