@@ -351,23 +351,34 @@ __device__ __forceinline__ void stage2_tile(
           dsl[st][j] = (npass > 0 && x < nx && kk < nkeys) ? frow[kk] : T(0);
         }
       __syncthreads();
+      // outputs in batches of four behind one branch: slots past npass read tile
+      // row 0 (meta is 0 there) into accumulators that are never stored, so the
+      // reads of a batch's four outputs are in flight together at every step
+      static_assert(C::OPG % 4 == 0, "whole batches of four outputs");
 #pragma unroll
-      for (int o = 0; o < C::OPG; ++o) {
-        if (o < npass) {
-          const int mrow = kPack ? (int)((mp[o >> 2] >> (8 * (o & 3))) & 0xffu) : (int)meta[grp][o];
-          const T *trow = tile + mrow * TROW + sub * C::EPL;
-          // all reads of this output first (distinct registers), then the FMAs
-          V16 sv[C::STEPS][C::EPL / C::VEC];
+      for (int o0 = 0; o0 < C::OPG; o0 += 4) {
+        if (o0 < npass) {
+          const T *trow[4];
 #pragma unroll
-          for (int st = 0; st < C::STEPS; ++st)
+          for (int q = 0; q < 4; ++q) {
+            const int o = o0 + q;
+            const int mrow = kPack ? (int)((mp[o >> 2] >> (8 * (o & 3))) & 0xffu) : (int)meta[grp][o];
+            trow[q] = tile + mrow * TROW + sub * C::EPL;
+          }
 #pragma unroll
-            for (int u0 = 0; u0 < C::EPL / C::VEC; ++u0)
-              sv[st][u0] = *reinterpret_cast<const V16 *>(trow + st * C::LPO * C::EPL + u0 * C::VEC);
+          for (int st = 0; st < C::STEPS; ++st) {
+            V16 sv[4][C::EPL / C::VEC];
 #pragma unroll
-          for (int st = 0; st < C::STEPS; ++st)
+            for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int u = 0; u < C::EPL; ++u)
-              acc[o][u % R] += dsl[st][u / R] * sv[st][u / C::VEC][u % C::VEC];
+              for (int u0 = 0; u0 < C::EPL / C::VEC; ++u0)
+                sv[q][u0] = *reinterpret_cast<const V16 *>(trow[q] + st * C::LPO * C::EPL + u0 * C::VEC);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+              for (int u = 0; u < C::EPL; ++u)
+                acc[o0 + q][u % R] += dsl[st][u / R] * sv[q][u / C::VEC][u % C::VEC];
+          }
         }
       }
     }
