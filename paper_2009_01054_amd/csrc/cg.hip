@@ -26,7 +26,10 @@ enum CgState { CG_DONE = 0, CG_ACTIVE = 1, CG_PENDING = 2, CG_BREAKDOWN = 3, CG_
 
 struct CgScalars {
   double rho, pw, alpha, beta, ynorm;
-  int state, iters, pad0, pad1;
+  double rho_prev;  // the rho the last update step used
+  int state, iters;
+  int gate;         // last update step: 0 system not active, 1 stepped, 2 breakdown (p.w <= 0)
+  int pad0;
 };
 
 __device__ __forceinline__ double block_sum(double v, double *sh) {
@@ -63,9 +66,24 @@ __device__ __forceinline__ double fold_partials(const double *partial, int nlam,
   return block_sum(v, sh);
 }
 
-// w = K p (+ FP32 product cast) + lambda p ; partial dot p.w
+// Per iteration the vector work is three kernels: p.w, then the update of a
+// and r with alpha, then the new search direction with beta.  The step
+// lengths come from block partials folded by a fixed tree; instead of a
+// kernel of its own, every block of the next kernel folds them itself (the
+// same reads in the same order, so every block gets the same value) and
+// block 0 records the scalars.  No kernel reads a scalar field that it also
+// writes: the update writes alpha, p.w, rho_prev and gate, the direction
+// kernel reads gate and rho_prev and writes rho, beta, iters and state.
+
+// w = K p (+ FP32 product cast) + lambda p ; partial dot p.w.  The update
+// kernel recomputes w the same way rather than reading it back.
 template <class TW>
-__global__ __launch_bounds__(RB) void cg_pw_kernel(const TW *__restrict__ wraw, double *__restrict__ w,
+__device__ __forceinline__ double cg_w(const TW *wraw, const double *p, double lm, int64_t i) {
+  return (double)wraw[i] + lm * p[i];
+}
+
+template <class TW>
+__global__ __launch_bounds__(RB) void cg_pw_kernel(const TW *__restrict__ wraw,
                                                    const double *__restrict__ p,
                                                    const double *__restrict__ lam, int64_t n,
                                                    int nlam, const CgScalars *__restrict__ sc,
@@ -75,86 +93,96 @@ __global__ __launch_bounds__(RB) void cg_pw_kernel(const TW *__restrict__ wraw, 
     double acc = 0.0;
     if (sc[l].state == CG_ACTIVE) {
       const double lm = lam[l];
-      for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)RNB * RB) {
-        const double pi = p[i + l * n];
-        const double wi = (double)wraw[i + l * n] + lm * pi;
-        w[i + l * n] = wi;
-        acc += pi * wi;
-      }
+      for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)RNB * RB)
+        acc += p[i + l * n] * cg_w(wraw, p, lm, i + l * n);
     }
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) partial[blockIdx.x * nlam + l] = s;
   }
 }
 
-// one block per system
-__global__ __launch_bounds__(RB) void cg_alpha_kernel(CgScalars *sc, const double *__restrict__ partial,
-                                                      int nlam) {
-  __shared__ double sh[RB];
-  const int l = blockIdx.x;
-  if (sc[l].state != CG_ACTIVE) return;  // uniform per block
-  const double pw = fold_partials(partial, nlam, l, sh);
-  if (threadIdx.x != 0) return;
-  sc[l].pw = pw;
-  if (!(pw > 0.0) || !isfinite(pw)) {
-    sc[l].state = CG_BREAKDOWN;
-    return;
-  }
-  sc[l].alpha = sc[l].rho / pw;
-}
-
-// a += alpha p; r -= alpha w; partial r.r
+// alpha = rho / p.w; a += alpha p; r -= alpha w; partial r.r
+template <class TW>
 __global__ __launch_bounds__(RB) void cg_update_kernel(double *__restrict__ a, int64_t lda,
                                                        double *__restrict__ r,
                                                        const double *__restrict__ p,
-                                                       const double *__restrict__ w, int64_t n,
-                                                       int nlam, const CgScalars *__restrict__ sc,
-                                                       double *__restrict__ partial) {
+                                                       const TW *__restrict__ wraw,
+                                                       const double *__restrict__ lam, int64_t n,
+                                                       int nlam, CgScalars *sc,
+                                                       const double *__restrict__ part_pw,
+                                                       double *__restrict__ part_rr) {
   __shared__ double sh[RB];
+  const bool rec = blockIdx.x == 0 && threadIdx.x == 0;
   for (int l = 0; l < nlam; ++l) {
     double acc = 0.0;
-    if (sc[l].state == CG_ACTIVE) {
-      const double al = sc[l].alpha;
-      for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)RNB * RB) {
-        a[i + l * lda] += al * p[i + l * n];
-        const double ri = r[i + l * n] - al * w[i + l * n];
-        r[i + l * n] = ri;
-        acc += ri * ri;
+    if (sc[l].state == CG_ACTIVE) {  // uniform: state is not written by this kernel
+      const double pw = fold_partials(part_pw, nlam, l, sh);
+      const double rho = sc[l].rho;
+      const bool ok = pw > 0.0 && isfinite(pw);
+      const double al = rho / pw;
+      if (ok) {
+        const double lm = lam[l];
+        for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)RNB * RB) {
+          a[i + l * lda] += al * p[i + l * n];
+          const double ri = r[i + l * n] - al * cg_w(wraw, p, lm, i + l * n);
+          r[i + l * n] = ri;
+          acc += ri * ri;
+        }
       }
+      if (rec) {
+        sc[l].pw = pw;
+        sc[l].alpha = al;
+        sc[l].rho_prev = rho;
+        sc[l].gate = ok ? 1 : 2;
+      }
+    } else if (rec) {
+      sc[l].gate = 0;
     }
     const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x * nlam + l] = s;
+    if (threadIdx.x == 0) part_rr[blockIdx.x * nlam + l] = s;
   }
 }
 
-__global__ __launch_bounds__(RB) void cg_beta_kernel(CgScalars *sc, const double *__restrict__ partial,
-                                                     int nlam, double tol, int max_iter, int lowprec) {
+// beta = rho_new / rho; p = r + beta p (and its FP32 copy p32, if given) for
+// systems that stepped; block 0 advances iters, rho and the state.  A system
+// that has just stopped gets its p updated too; nothing reads it afterwards
+// (a restart sets p again).
+__global__ __launch_bounds__(RB) void cg_p_kernel(double *__restrict__ p, float *__restrict__ p32,
+                                                  const double *__restrict__ r, int64_t n, int nlam,
+                                                  CgScalars *sc, const double *__restrict__ part_rr,
+                                                  double tol, int max_iter, int lowprec) {
   __shared__ double sh[RB];
-  const int l = blockIdx.x;
-  if (sc[l].state != CG_ACTIVE) return;  // uniform per block
-  const double rho_new = fold_partials(partial, nlam, l, sh);
-  if (threadIdx.x != 0) return;
-  sc[l].iters += 1;
-  if (!isfinite(rho_new)) {
-    sc[l].state = CG_BREAKDOWN;
-    return;
+  const bool rec = blockIdx.x == 0 && threadIdx.x == 0;
+  for (int l = 0; l < nlam; ++l) {
+    const int gate = sc[l].gate;  // uniform: written only by the update kernel
+    if (gate == 0) continue;
+    if (gate == 2) {
+      if (rec) sc[l].state = CG_BREAKDOWN;
+      continue;
+    }
+    const double rho_new = fold_partials(part_rr, nlam, l, sh);
+    const double beta = rho_new / sc[l].rho_prev;
+    if (isfinite(rho_new)) {
+      for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)RNB * RB) {
+        const double pi = r[i + l * n] + beta * p[i + l * n];
+        p[i + l * n] = pi;
+        if (p32) p32[i + l * n] = (float)pi;
+      }
+    }
+    if (rec) {
+      sc[l].iters += 1;
+      if (!isfinite(rho_new)) {
+        sc[l].state = CG_BREAKDOWN;
+      } else {
+        sc[l].beta = beta;
+        sc[l].rho = rho_new;
+        if (sqrt(rho_new) / sc[l].ynorm < tol)
+          sc[l].state = lowprec ? CG_PENDING : CG_DONE;
+        else if (sc[l].iters >= max_iter)
+          sc[l].state = CG_MAXITER;
+      }
+    }
   }
-  sc[l].beta = rho_new / sc[l].rho;
-  sc[l].rho = rho_new;
-  if (sqrt(rho_new) / sc[l].ynorm < tol) {
-    sc[l].state = lowprec ? CG_PENDING : CG_DONE;
-  } else if (sc[l].iters >= max_iter) {
-    sc[l].state = CG_MAXITER;
-  }
-}
-
-// p = r + beta p  (active systems)
-__global__ void cg_p_kernel(double *__restrict__ p, const double *__restrict__ r, int64_t n, int nlam,
-                            const CgScalars *__restrict__ sc) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  for (int l = 0; l < nlam; ++l)
-    if (sc[l].state == CG_ACTIVE) p[i + l * n] = r[i + l * n] + sc[l].beta * p[i + l * n];
 }
 
 // r = y - (wraw + lambda a)  (true residual after an FP64 product w = K a); partial r.r
@@ -265,7 +293,8 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
   double *p = (double *)m_p.ensure(nv * 8);
   double *w = (double *)m_w.ensure(nv * 8);
   double *wraw = (double *)m_wraw.ensure(nv * 8);
-  double *part = (double *)m_part.ensure((size_t)RNB * nlam * 8);
+  double *part = (double *)m_part.ensure((size_t)RNB * nlam * 8 * 2);
+  double *part2 = part + (size_t)RNB * nlam;  // r.r partials (part holds p.w)
   CgScalars *sc = (CgScalars *)m_sc.ensure(sizeof(CgScalars) * nlam);
   double *lam = (double *)m_lam.ensure(nlam * 8);
   double *tmp = (double *)m_tmp.ensure(64 * 8);
@@ -327,19 +356,23 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
   GVT_HIP_CHECK(hipMemcpyAsync(sc, hs.data(), sizeof(CgScalars) * nlam, hipMemcpyHostToDevice, s));
 
   const int lowprec = mprec == GVT_F32 ? 1 : 0;
+  // p32 (FP32 products) is kept in step with p by the direction kernel; after
+  // the host sets p (start, restart) it is refreshed here
+  auto refresh_p32 = [&]() {
+    if (lowprec) to_f32_kernel<<<g1((int64_t)nv), 256, 0, s>>>(p, p32, (int64_t)nv);
+  };
+  refresh_p32();
   auto iteration = [&]() {
     if (lowprec) {
-      to_f32_kernel<<<g1((int64_t)nv), 256, 0, s>>>(p, p32, (int64_t)nv);
       plan_execute(P, GVT_F32, D32, d, T32, t, p32, nlam, n, w32, n, s);
-      cg_pw_kernel<float><<<RNB, RB, 0, s>>>(w32, w, p, lam, n, nlam, sc, part);
+      cg_pw_kernel<float><<<RNB, RB, 0, s>>>(w32, p, lam, n, nlam, sc, part);
+      cg_update_kernel<float><<<RNB, RB, 0, s>>>(A, lda, r, p, w32, lam, n, nlam, sc, part, part2);
     } else {
       matvec64(p, wraw);
-      cg_pw_kernel<double><<<RNB, RB, 0, s>>>(wraw, w, p, lam, n, nlam, sc, part);
+      cg_pw_kernel<double><<<RNB, RB, 0, s>>>(wraw, p, lam, n, nlam, sc, part);
+      cg_update_kernel<double><<<RNB, RB, 0, s>>>(A, lda, r, p, wraw, lam, n, nlam, sc, part, part2);
     }
-    cg_alpha_kernel<<<nlam, RB, 0, s>>>(sc, part, nlam);
-    cg_update_kernel<<<RNB, RB, 0, s>>>(A, lda, r, p, w, n, nlam, sc, part);
-    cg_beta_kernel<<<nlam, RB, 0, s>>>(sc, part, nlam, tol, max_iter, lowprec);
-    cg_p_kernel<<<g1(n), 256, 0, s>>>(p, r, n, nlam, sc);
+    cg_p_kernel<<<RNB, RB, 0, s>>>(p, p32, r, n, nlam, sc, part2, tol, max_iter, lowprec);
   };
 
   // warm-up layout of plan workspaces (allocation must not happen inside a capture)
@@ -381,6 +414,7 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
       GVT_HIP_CHECK(hipMemcpyAsync(sc, hs.data(), sizeof(CgScalars) * nlam, hipMemcpyHostToDevice, s));
       copy_cols_kernel<<<g1(n), 256, 0, s>>>(w, n, r, n, n, nlam, CG_ACTIVE, sc);
       copy_cols_kernel<<<g1(n), 256, 0, s>>>(w, n, p, n, n, nlam, CG_ACTIVE, sc);
+      refresh_p32();
       continue;
     }
     if (first) {
