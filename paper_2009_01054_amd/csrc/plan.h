@@ -5,6 +5,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "plan_dev.h"
 
 namespace gvt {
 
@@ -39,6 +40,7 @@ struct SBufSpec {  // one stage-1 result S = scatter of F_sc by `key` with colum
   std::vector<int32_t> rowmap;   // F_sc row -> compact S row (-1: not needed)
   std::vector<int32_t> rows;     // compact S rows -> F_sc row
   DevMem d_rows;
+  DevMem d_rowmap;               // device copy of rowmap (device-built plans)
 };
 
 enum TermType { TG = 0, TO = 1, TM = 2 };
@@ -96,11 +98,17 @@ struct gvt_plan {
   int flags = 0;
   int64_t d_rows = 0, d_cols = 0, t_rows = 0, t_cols = 0, n_out = 0, n_in = 0;
   std::array<int64_t, 4> uniq{{0, 0, 0, 0}};
-  gvt::DevMem blob;    // one device allocation holding every index array below
+  gvt::DevMem blob;    // one device allocation holding the uploaded index arrays below
+  // Device-built plans (large index sets): the index work runs on the GPU;
+  // idx always holds the plan's own copies of a, b, c, e, devblob the sorted
+  // arrays and tile orders, scratch the sort buffers.
+  bool on_device = false;
+  gvt::DevMem idxblob, devblob;
+  gvt::DevScratch scratch;
   gvt::DevMem idx[4];  // device copies of a, b, c, e (int32), when a term reads them
   gvt::InputSort insort[2];   // [0]: by c (other = e), [1]: by e (other = c)
   gvt::OutOrder outord[2];    // [0]: grouped by a, [1]: grouped by b
-  std::vector<int32_t> h_out[2];  // host copies of a, b (stage-2 tiles built on demand)
+  std::vector<int32_t> h_out[2];  // host copies of a, b (host-built plans: tiles built on demand)
   std::vector<gvt::SBufSpec> sbufs;
   std::vector<gvt::GemvSpec> gemvs;
   std::vector<gvt::TermSpec> terms;

@@ -131,6 +131,16 @@ double stage2_target(int cls) {
   return cls ? kStage2TargetR8 : kStage2TargetR1;
 }
 
+// Where the index work of a plan runs: on the device for large index sets,
+// where sorting on the host costs more than the launches; GVT_PLAN_DEVICE=0/1
+// forces either side.
+constexpr int64_t kDevicePlanMinPairs = 1 << 16;
+bool device_plan(int64_t n_in, int64_t n_out) {
+  const char *ev = std::getenv("GVT_PLAN_DEVICE");
+  if (ev && *ev) return std::atoi(ev) != 0;
+  return n_in + n_out >= kDevicePlanMinPairs;
+}
+
 // Host tasks of a plan build: on their own threads for large inputs, inline
 // for small ones (where starting a thread costs more than the task).
 struct TaskGroup {
@@ -180,23 +190,39 @@ struct TileHost {
   std::vector<int64_t> toff;
 };
 
+struct TileGeom {
+  int bsz = 0;
+  TileDims d{};
+};
+
+TileGeom tile_geom(const gvt_plan *P, const TermSpec &ts, int cls) {
+  TileGeom g;
+  const SBufSpec &sb = P->sbufs[ts.sbuf];
+  g.bsz = stage2_block_rows(P, ts, cls);
+  const int64_t nsr = std::max<int64_t>((int64_t)sb.rows.size(), 1);
+  const int64_t nxr = std::max<int64_t>(rows_of(P, ts.fdot), 1);
+  const int64_t ngrp_rows = cls ? nsr : nxr;   // grouped dimension
+  const int64_t nstg_rows = cls ? nxr : nsr;   // staged dimension
+  int64_t nsb = ceil_div(nstg_rows, (int64_t)g.bsz);
+  if (nsb > 4) nsb = 8 * ceil_div(nsb, (int64_t)8);
+  g.d.nsb = nsb;
+  g.d.sbs = ceil_div(nstg_rows, nsb);
+  g.d.ntiles = ceil_div(ngrp_rows, kStage2Rows) * nsb;
+  g.d.nstg_rows = nstg_rows;
+  g.d.rows_per_tile = kStage2Rows;
+  g.d.swap = cls != 0;
+  GVT_REQUIRE(g.d.ntiles * kStage2Rows < INT32_MAX, GVT_ERR_ARG, "too many stage-2 tiles");
+  return g;
+}
+
 TileHost compute_tiles(const gvt_plan *P, const TermSpec &ts, int cls) {
   TileHost o;
   const SBufSpec &sb = P->sbufs[ts.sbuf];
   const std::vector<int32_t> &hx = P->h_out[ts.x == SA ? 0 : 1];
   const std::vector<int32_t> &hy = P->h_out[ts.y == SA ? 0 : 1];
   const int64_t n_out = P->n_out;
-  const int bsz = stage2_block_rows(P, ts, cls);
-  const int64_t nsr = std::max<int64_t>((int64_t)sb.rows.size(), 1);
-  const int64_t nxr = std::max<int64_t>(rows_of(P, ts.fdot), 1);
-  const int64_t ngrp_rows = cls ? nsr : nxr;   // grouped dimension
-  const int64_t nstg_rows = cls ? nxr : nsr;   // staged dimension
-  int64_t nsb = ceil_div(nstg_rows, (int64_t)bsz);
-  if (nsb > 4) nsb = 8 * ceil_div(nsb, (int64_t)8);
-  const int64_t sbs = ceil_div(nstg_rows, nsb);
-  const int64_t ngb = ceil_div(ngrp_rows, kStage2Rows);
-  const int64_t ntiles = ngb * nsb;
-  GVT_REQUIRE(ntiles * kStage2Rows < INT32_MAX, GVT_ERR_ARG, "too many stage-2 tiles");
+  const TileGeom g = tile_geom(P, ts, cls);
+  const int64_t nsb = g.d.nsb, sbs = g.d.sbs, ntiles = g.d.ntiles, nstg_rows = g.d.nstg_rows;
   std::vector<int32_t> stg_of(n_out), tkey(n_out);
   for (int64_t i = 0; i < n_out; ++i) {
     const int32_t yr = sb.rowmap[hy[i]], xv = hx[i];
@@ -216,17 +242,54 @@ TileHost compute_tiles(const gvt_plan *P, const TermSpec &ts, int cls) {
     const int64_t sbk = tt % nsb;
     o.tstg[2 * tt] = (int32_t)std::min<int64_t>(sbk * sbs, nstg_rows);
     o.tstg[2 * tt + 1] = (int32_t)std::max<int64_t>(0, std::min<int64_t>(sbs, nstg_rows - sbk * sbs));
-    for (int g = 0; g <= kStage2Rows; ++g)
-      o.toff[(size_t)tt * (kStage2Rows + 1) + g] = sgk[(size_t)tt * kStage2Rows + g];
-    for (int g = 0; g < kStage2Rows; ++g) {
-      const int64_t c = sgk[(size_t)tt * kStage2Rows + g + 1] - sgk[(size_t)tt * kStage2Rows + g];
+    for (int g2 = 0; g2 <= kStage2Rows; ++g2)
+      o.toff[(size_t)tt * (kStage2Rows + 1) + g2] = sgk[(size_t)tt * kStage2Rows + g2];
+    for (int g2 = 0; g2 < kStage2Rows; ++g2) {
+      const int64_t c = sgk[(size_t)tt * kStage2Rows + g2 + 1] - sgk[(size_t)tt * kStage2Rows + g2];
       o.tmax[tt] = std::max<int32_t>(o.tmax[tt], (int32_t)c);
     }
   }
-  o.bsz = bsz;
+  o.bsz = g.bsz;
   o.ntiles = ntiles;
   o.nsb = (int)nsb;
   return o;
+}
+
+// Device arrays of known sizes laid out in one allocation.
+struct DevLayout {
+  std::vector<std::pair<DevMem *, size_t>> items;
+  void add(DevMem &m, size_t bytes) { items.push_back({&m, bytes}); }
+  void commit(DevMem &blob) {
+    size_t total = 0;
+    for (auto &it : items) total += (it.second + 255) & ~size_t(255);
+    blob.ensure(total ? total : 256);
+    size_t off = 0;
+    for (auto &it : items) {
+      it.first->view(static_cast<char *>(blob.p) + off, it.second);
+      off += (it.second + 255) & ~size_t(255);
+    }
+    items.clear();
+  }
+};
+
+// Device-built tiles: the arrays' sizes, then the kernels that fill them.
+void dev_tiles_layout(TileSet &tl, const TileGeom &g, int64_t n_out, DevLayout &L) {
+  tl.ysz = g.bsz;
+  tl.ntiles = g.d.ntiles;
+  tl.nyb = (int)g.d.nsb;
+  L.add(tl.perm, (size_t)n_out * 4);
+  L.add(tl.yrows, (size_t)n_out * 4);
+  L.add(tl.tileoff, (size_t)g.d.ntiles * (kStage2Rows + 1) * 8);
+  L.add(tl.tiley, (size_t)g.d.ntiles * 2 * 4);
+  L.add(tl.tilemax, (size_t)g.d.ntiles * 4);
+}
+
+void dev_tiles_fill(gvt_plan *P, const TermSpec &ts, TileSet &tl, const TileGeom &g, hipStream_t s) {
+  const SBufSpec &sb = P->sbufs[ts.sbuf];
+  dev_tiles(P->idx[ts.x].as<int32_t>(), P->idx[ts.y].as<int32_t>(), sb.d_rowmap.as<int32_t>(),
+            P->n_out, g.d, tl.perm.as<int32_t>(), tl.yrows.as<int32_t>(), tl.tileoff.as<int64_t>(),
+            tl.tiley.as<int32_t>(), tl.tilemax.as<int32_t>(), P->scratch, s);
+  tl.built = true;
 }
 
 // With `up` the arrays join the plan's upload, else they are copied into the
@@ -257,8 +320,19 @@ void plan_ensure_tiles(gvt_plan *P, int cls, hipStream_t s) {
     throw Error{GVT_ERR_ARG,
                 "the first product with a new RHS block size builds stage-2 tiles and cannot be "
                 "captured; run it once before capturing"};
-  for (TermSpec &t : P->terms)
-    if (t.type == TG && !t.tiles[cls].built) install_tiles(t.tiles[cls], compute_tiles(P, t, cls), nullptr);
+  for (TermSpec &t : P->terms) {
+    if (t.type != TG || t.tiles[cls].built) continue;
+    if (P->on_device) {
+      TileSet &tl = t.tiles[cls];
+      const TileGeom g = tile_geom(P, t, cls);
+      DevLayout L;
+      dev_tiles_layout(tl, g, P->n_out, L);
+      L.commit(tl.blob);
+      dev_tiles_fill(P, t, tl, g, s);
+    } else {
+      install_tiles(t.tiles[cls], compute_tiles(P, t, cls), nullptr);
+    }
+  }
 }
 
 void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64_t d_cols,
@@ -295,70 +369,122 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   P->last_stream = s;
 
   PhaseTimer tm;
-  // ---- indices to host, validation, unique counts (Table 1) -------------
-  // When the output pairs are the input pairs (training products), the two
-  // index arrays are copied and checked once.
-  std::vector<int32_t> h[4];
-  const int32_t *src[4] = {a, b, c, e};
+  const bool alias = n_out == n_in && a == c && b == e;
   const int64_t cnt[4] = {n_out, n_out, n_in, n_in};
   const int64_t lim[4] = {d_rows, t_rows, d_cols, t_cols};
-  const bool alias = n_out == n_in && a == c && b == e;
-  for (int i = 0; i < (alias ? 2 : 4); ++i) {
-    h[i].resize(cnt[i]);
-    if (cnt[i])
-      GVT_HIP_CHECK(hipMemcpyAsync(h[i].data(), src[i], cnt[i] * sizeof(int32_t),
-                                   hipMemcpyDeviceToHost, s));
-  }
-  GVT_HIP_CHECK(hipStreamSynchronize(s));
-  tm.lap("indices to host");
   static const char *nm[4] = {"out_a", "out_b", "in_c", "in_e"};
-  // first index outside [0, lim) per array (-1: none), unique counts
+  // first index outside [0, lim) per array (-1: none), then the error naming
+  // the array and limit the value violates (aliased arrays carry two limits)
   int64_t bad[4] = {-1, -1, -1, -1};
-  auto check = [&](int i) {
-    const int i2 = alias ? i + 2 : -1;  // the aliased input array, with its own limit
-    const int64_t L = i2 >= 0 ? std::min(lim[i], lim[i2]) : lim[i];
-    const std::vector<int32_t> &v = h[i];
-    for (int64_t j = 0; j < (int64_t)v.size(); ++j)
-      if (v[j] < 0 || v[j] >= L) { bad[i] = j; return; }
-    P->uniq[i] = count_unique(v, L > 0 ? std::max(lim[i], i2 >= 0 ? lim[i2] : 0) : 0);
-  };
-  {
-    TaskGroup tg(n_in + n_out >= (1 << 16));
-    const int na = alias ? 2 : 4;
-    for (int i = 1; i < na; ++i) tg.run([&, i]() { check(i); });
-    check(0);
-    tg.join();
-  }
-  for (int i = 0; i < (alias ? 2 : 4); ++i) {
-    if (bad[i] < 0) continue;
-    const int32_t v = h[i][bad[i]];
+  auto report_bad = [&](int i, int32_t v) {
     int which = i;
     if (alias && (v < 0 || v >= lim[i + 2]) && !(v < 0 || v >= lim[i])) which = i + 2;
     throw Error{GVT_ERR_INDEX, std::string(nm[which]) + "[" + std::to_string(bad[i]) + "] = " +
                                    std::to_string(v) + " outside [0, " + std::to_string(lim[which]) +
                                    ")"};
-  }
-  if (alias) {
-    h[2] = h[0];
-    h[3] = h[1];
-    P->uniq[2] = P->uniq[0];
-    P->uniq[3] = P->uniq[1];
+  };
+  const bool dense_candidate = nkinds == 1 && P->kinds[0] == GVT_KRONECKER && n_in == d_cols * t_cols &&
+                               n_out == d_rows * t_rows && n_in > 0 && n_out > 0;
+  P->on_device = device_plan(n_in, n_out);
+  std::vector<int32_t> h[4];
+  std::vector<uint8_t> seen_dev[4];  // device-built plans: which values occur, per array
+  if (P->on_device) {
+    // ---- the plan's own device copies of the indices, validation and unique
+    // marks by one kernel; the only host synchronisation of the build -------
+    const int narr = alias ? 2 : 4;
+    const int32_t *src[4] = {a, b, c, e};
+    DevLayout L;
+    for (int i = 0; i < narr; ++i) L.add(P->idx[i], (size_t)cnt[i] * 4);
+    L.commit(P->idxblob);
+    for (int i = 0; i < narr; ++i)
+      if (cnt[i])
+        GVT_HIP_CHECK(hipMemcpyAsync(P->idx[i].p, src[i], cnt[i] * 4, hipMemcpyDeviceToDevice, s));
+    if (alias) {
+      P->idx[2].view(P->idx[0].p, P->idx[0].bytes);
+      P->idx[3].view(P->idx[1].p, P->idx[1].bytes);
+    }
+    const int32_t *x[4];
+    int64_t L2[4], range[4];
+    for (int i = 0; i < narr; ++i) {
+      x[i] = P->idx[i].as<int32_t>();
+      L2[i] = alias ? std::min(lim[i], lim[i + 2]) : lim[i];
+      range[i] = alias ? std::max(lim[i], lim[i + 2]) : lim[i];
+    }
+    ProbeResult pr;
+    dev_probe(x, cnt, L2, range, narr, dense_candidate ? t_rows : 0, dense_candidate ? t_cols : 0,
+              P->scratch, pr, s);
+    tm.lap("indices: device probe");
+    for (int i = 0; i < narr; ++i) {
+      if (pr.bad[i] < 0) continue;
+      bad[i] = pr.bad[i];
+      int32_t v = 0;
+      GVT_HIP_CHECK(hipMemcpy(&v, x[i] + bad[i], 4, hipMemcpyDeviceToHost));
+      report_bad(i, v);
+    }
+    for (int i = 0; i < narr; ++i) {
+      int64_t u = 0;
+      for (uint8_t f : pr.seen[i]) u += f;
+      P->uniq[i] = u;
+      seen_dev[i] = std::move(pr.seen[i]);
+    }
+    if (alias) {
+      P->uniq[2] = P->uniq[0];
+      P->uniq[3] = P->uniq[1];
+    }
+    P->dense = dense_candidate && pr.nat;
+  } else {
+    // ---- indices to host, validation, unique counts (Table 1) -------------
+    // When the output pairs are the input pairs (training products), the two
+    // index arrays are copied and checked once.
+    const int32_t *src[4] = {a, b, c, e};
+    for (int i = 0; i < (alias ? 2 : 4); ++i) {
+      h[i].resize(cnt[i]);
+      if (cnt[i])
+        GVT_HIP_CHECK(hipMemcpyAsync(h[i].data(), src[i], cnt[i] * sizeof(int32_t),
+                                     hipMemcpyDeviceToHost, s));
+    }
+    GVT_HIP_CHECK(hipStreamSynchronize(s));
+    tm.lap("indices to host");
+    auto check = [&](int i) {
+      const int i2 = alias ? i + 2 : -1;  // the aliased input array, with its own limit
+      const int64_t Lm = i2 >= 0 ? std::min(lim[i], lim[i2]) : lim[i];
+      const std::vector<int32_t> &v = h[i];
+      for (int64_t j = 0; j < (int64_t)v.size(); ++j)
+        if (v[j] < 0 || v[j] >= Lm) { bad[i] = j; return; }
+      P->uniq[i] = count_unique(v, Lm > 0 ? std::max(lim[i], i2 >= 0 ? lim[i2] : 0) : 0);
+    };
+    {
+      TaskGroup tg(n_in + n_out >= (1 << 16));
+      const int na = alias ? 2 : 4;
+      for (int i = 1; i < na; ++i) tg.run([&, i]() { check(i); });
+      check(0);
+      tg.join();
+    }
+    for (int i = 0; i < (alias ? 2 : 4); ++i)
+      if (bad[i] >= 0) report_bad(i, h[i][bad[i]]);
+    if (alias) {
+      h[2] = h[0];
+      h[3] = h[1];
+      P->uniq[2] = P->uniq[0];
+      P->uniq[3] = P->uniq[1];
+    }
+    // complete data: both pair sets are the full grid in natural order
+    if (dense_candidate) {
+      bool nat = true;
+      for (int64_t j = 0; j < n_in && nat; ++j)
+        nat = h[2][j] == (int32_t)(j / t_cols) && h[3][j] == (int32_t)(j % t_cols);
+      for (int64_t i = 0; i < n_out && nat; ++i)
+        nat = h[0][i] == (int32_t)(i / t_rows) && h[1][i] == (int32_t)(i % t_rows);
+      P->dense = nat;
+    }
   }
   tm.lap("validate + unique");
   Uploads up;
-  P->h_out[0] = h[0];
-  P->h_out[1] = h[1];
-
-  // ---- complete data: both pair sets are the full grid in natural order ----
-  if (nkinds == 1 && P->kinds[0] == GVT_KRONECKER && n_in == d_cols * t_cols &&
-      n_out == d_rows * t_rows && n_in > 0 && n_out > 0) {
-    bool nat = true;
-    for (int64_t j = 0; j < n_in && nat; ++j)
-      nat = h[2][j] == (int32_t)(j / t_cols) && h[3][j] == (int32_t)(j % t_cols);
-    for (int64_t i = 0; i < n_out && nat; ++i)
-      nat = h[0][i] == (int32_t)(i / t_rows) && h[1][i] == (int32_t)(i % t_rows);
-    P->dense = nat;
+  if (!P->on_device) {
+    P->h_out[0] = h[0];
+    P->h_out[1] = h[1];
   }
+
   if (P->dense) {
     P->outputs.assign(1, {});
     P->cost_fma = (double)d_rows * d_cols * t_cols + (double)d_rows * t_cols * t_rows;
@@ -477,13 +603,21 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   for (const RawTerm &t : raw_terms) {
     if (t.type != TG) continue;
     SBufSpec &sb = P->sbufs[sbuf_index.at({t.a1, t.a4, t.a5})];
-    for (int32_t v : sel_host(t.a3)) sb.rowmap[v] = 0;
+    if (P->on_device) {
+      const std::vector<uint8_t> &seen = seen_dev[alias && t.a3 >= 2 ? t.a3 - 2 : t.a3];
+      const size_t nr = std::min(seen.size(), sb.rowmap.size());
+      for (size_t v = 0; v < nr; ++v)
+        if (seen[v]) sb.rowmap[v] = 0;
+    } else {
+      for (int32_t v : sel_host(t.a3)) sb.rowmap[v] = 0;
+    }
   }
   for (SBufSpec &sb : P->sbufs) {
     sb.rows.clear();
     for (int64_t r = 0; r < (int64_t)sb.rowmap.size(); ++r)
       if (sb.rowmap[r] >= 0) { sb.rowmap[r] = (int32_t)sb.rows.size(); sb.rows.push_back((int32_t)r); }
     up.add(sb.d_rows, sb.rows);
+    if (P->on_device) up.add(sb.d_rowmap, sb.rowmap);
     need_insort(sb.key);  // scatter segments, or the segment sums of a degenerate buffer
   }
   tm.lap("S rows");
@@ -526,71 +660,131 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       P->cost_fma -= (key == other) ? selval_uniq(y) * (double)nkeys_of(P, key)
                                     : selval_uniq(y) * n_in_d;
     }
-  // input sorts and stage-2 tiles are independent host work: one thread each
-  {
-    std::vector<std::pair<TermSpec *, TileHost>> tiles;
-    for (TermSpec &ts : P->terms)
-      if (ts.type == TG && n_out > 0) tiles.push_back({&ts, TileHost{}});
-    TaskGroup tg(n_in + n_out >= (1 << 16));
-    std::vector<std::exception_ptr> errs(tiles.size() + 2);
-    auto guard = [&](size_t slot, auto fn) {
-      try {
-        fn();
-      } catch (...) {
-        errs[slot] = std::current_exception();
-      }
-    };
-    for (int ks = 0; ks < 2; ++ks)
-      if (insort_needed[ks] && n_in > 0)
-        tg.run([&, ks]() { guard(ks, [&]() { build_insort(ks); }); });
-    std::vector<int32_t> oo_perm[2];
-    std::vector<int64_t> oo_off[2];
-    for (int xs = 0; xs < 2; ++xs)
-      if (outord_needed[xs] && n_out > 0)
-        tg.run([&, xs]() {
-          counting_sort(h[xs == 0 ? SA : SB], xs == 0 ? d_rows : t_rows, oo_perm[xs], oo_off[xs]);
-        });
+  if (P->on_device) {
+    // ---- sorts and tile orders on the device: sizes first (one allocation),
+    // then the small host arrays, then the kernels, all queued on s --------
     const int cls = tile_class(rhs_hint);
-    for (size_t k = 0; k < tiles.size(); ++k)
-      tg.run([&, k]() {
-        guard(2 + k, [&]() { tiles[k].second = compute_tiles(P, *tiles[k].first, cls); });
-      });
-    tg.join();
-    for (auto &ep : errs)
-      if (ep) std::rethrow_exception(ep);
+    DevLayout L;
     for (int ks = 0; ks < 2; ++ks) {
       if (!insort_needed[ks]) continue;
       InputSort &is = P->insort[ks];
       is.nkeys = nkeys_of(P, ks == 0 ? SC : SE);
       is.nother = nkeys_of(P, ks == 0 ? SE : SC);
-      if (n_in > 0) {
-        up.add(is.perm, std::move(sort_host[ks].perm));
-        up.add(is.other, std::move(sort_host[ks].other));
-        up.add(is.seg, std::move(sort_host[ks].seg));
-        up.add(is.cseg, std::move(sort_host[ks].cseg));
-        is.nchunks = ceil_div(is.nother, kStage1OtherChunk);
-      } else {
-        up.add(is.seg, std::vector<int64_t>(is.nkeys + 1, 0));
-      }
-      is.built = true;
+      is.nchunks = ceil_div(is.nother, kStage1OtherChunk);
+      L.add(is.perm, (size_t)n_in * 4);
+      L.add(is.other, (size_t)n_in * 4);
+      L.add(is.seg, (size_t)(is.nkeys + 1) * 8);
+      L.add(is.cseg, (size_t)is.nkeys * (is.nchunks + 1) * 4);
     }
-    for (auto &tk : tiles) install_tiles(tk.first->tiles[cls], std::move(tk.second), &up);
     for (int xs = 0; xs < 2; ++xs) {
       if (!outord_needed[xs] || n_out == 0) continue;
       OutOrder &oo = P->outord[xs];
       oo.nrows = xs == 0 ? d_rows : t_rows;
-      up.add(oo.perm, std::move(oo_perm[xs]));
-      up.add(oo.off, std::move(oo_off[xs]));
+      L.add(oo.perm, (size_t)n_out * 4);
+      L.add(oo.off, (size_t)(oo.nrows + 1) * 8);
+    }
+    std::vector<std::pair<TermSpec *, TileGeom>> tiles;
+    for (TermSpec &ts : P->terms)
+      if (ts.type == TG && n_out > 0) {
+        tiles.push_back({&ts, tile_geom(P, ts, cls)});
+        dev_tiles_layout(ts.tiles[cls], tiles.back().second, n_out, L);
+      }
+    size_t sneed = 0;
+    for (int ks = 0; ks < 2; ++ks)
+      if (insort_needed[ks])
+        sneed = std::max(sneed, dev_input_sort_bytes(P->insort[ks].nkeys, P->insort[ks].nother, n_in));
+    for (int xs = 0; xs < 2; ++xs)
+      if (outord_needed[xs] && n_out > 0) sneed = std::max(sneed, dev_group_rows_bytes(n_out));
+    for (auto &tk : tiles)
+      sneed = std::max(sneed, dev_tiles_bytes(n_out, tk.second.d.ntiles * tk.second.d.rows_per_tile));
+    dev_reserve(P->scratch, sneed, s);
+    L.commit(P->devblob);
+    up.commit(P->blob);
+    for (int ks = 0; ks < 2; ++ks) {
+      if (!insort_needed[ks]) continue;
+      InputSort &is = P->insort[ks];
+      const int key = ks == 0 ? SC : SE, okey = ks == 0 ? SE : SC;
+      dev_input_sort(P->idx[key].as<int32_t>(), is.nkeys, P->idx[okey].as<int32_t>(), is.nother, n_in,
+                     kStage1OtherChunk, is.perm.as<int32_t>(), is.other.as<int32_t>(),
+                     is.seg.as<int64_t>(), is.cseg.as<int32_t>(), P->scratch, s);
+      is.built = true;
+    }
+    for (int xs = 0; xs < 2; ++xs) {
+      if (!outord_needed[xs] || n_out == 0) continue;
+      OutOrder &oo = P->outord[xs];
+      dev_group_rows(P->idx[xs == 0 ? SA : SB].as<int32_t>(), oo.nrows, n_out, oo.perm.as<int32_t>(),
+                     oo.off.as<int64_t>(), P->scratch, s);
       oo.built = true;
     }
+    for (auto &tk : tiles) dev_tiles_fill(P, *tk.first, tk.first->tiles[cls], tk.second, s);
+    tm.lap("device sorts queued");
+  } else {
+    // input sorts and stage-2 tiles are independent host work: one thread each
+    {
+      std::vector<std::pair<TermSpec *, TileHost>> tiles;
+      for (TermSpec &ts : P->terms)
+        if (ts.type == TG && n_out > 0) tiles.push_back({&ts, TileHost{}});
+      TaskGroup tg(n_in + n_out >= (1 << 16));
+      std::vector<std::exception_ptr> errs(tiles.size() + 2);
+      auto guard = [&](size_t slot, auto fn) {
+        try {
+          fn();
+        } catch (...) {
+          errs[slot] = std::current_exception();
+        }
+      };
+      for (int ks = 0; ks < 2; ++ks)
+        if (insort_needed[ks] && n_in > 0)
+          tg.run([&, ks]() { guard(ks, [&]() { build_insort(ks); }); });
+      std::vector<int32_t> oo_perm[2];
+      std::vector<int64_t> oo_off[2];
+      for (int xs = 0; xs < 2; ++xs)
+        if (outord_needed[xs] && n_out > 0)
+          tg.run([&, xs]() {
+            counting_sort(h[xs == 0 ? SA : SB], xs == 0 ? d_rows : t_rows, oo_perm[xs], oo_off[xs]);
+          });
+      const int cls = tile_class(rhs_hint);
+      for (size_t k = 0; k < tiles.size(); ++k)
+        tg.run([&, k]() {
+          guard(2 + k, [&]() { tiles[k].second = compute_tiles(P, *tiles[k].first, cls); });
+        });
+      tg.join();
+      for (auto &ep : errs)
+        if (ep) std::rethrow_exception(ep);
+      for (int ks = 0; ks < 2; ++ks) {
+        if (!insort_needed[ks]) continue;
+        InputSort &is = P->insort[ks];
+        is.nkeys = nkeys_of(P, ks == 0 ? SC : SE);
+        is.nother = nkeys_of(P, ks == 0 ? SE : SC);
+        if (n_in > 0) {
+          up.add(is.perm, std::move(sort_host[ks].perm));
+          up.add(is.other, std::move(sort_host[ks].other));
+          up.add(is.seg, std::move(sort_host[ks].seg));
+          up.add(is.cseg, std::move(sort_host[ks].cseg));
+          is.nchunks = ceil_div(is.nother, kStage1OtherChunk);
+        } else {
+          up.add(is.seg, std::vector<int64_t>(is.nkeys + 1, 0));
+        }
+        is.built = true;
+      }
+      for (auto &tk : tiles) install_tiles(tk.first->tiles[cls], std::move(tk.second), &up);
+      for (int xs = 0; xs < 2; ++xs) {
+        if (!outord_needed[xs] || n_out == 0) continue;
+        OutOrder &oo = P->outord[xs];
+        oo.nrows = xs == 0 ? d_rows : t_rows;
+        up.add(oo.perm, std::move(oo_perm[xs]));
+        up.add(oo.off, std::move(oo_off[xs]));
+        oo.built = true;
+      }
+    }
+    tm.lap("input sorts + term orderings");
+    bool need_idx = false;
+    for (const TermSpec &t : P->terms) need_idx = need_idx || t.type != TG;
+    if (need_idx)
+      for (int i = 0; i < 4; ++i) up.add(P->idx[i], h[i]);
+    up.commit(P->blob);
+    tm.lap("upload");
   }
-  tm.lap("input sorts + term orderings");
-  bool need_idx = false;
-  for (const TermSpec &t : P->terms) need_idx = need_idx || t.type != TG;
-  if (need_idx)
-    for (int i = 0; i < 4; ++i) up.add(P->idx[i], h[i]);
-  up.commit(P->blob);
-  tm.lap("upload");
   P->direct = nkinds == 1 && P->outputs[0].size() == 1 && P->outputs[0][0].second == 1.0 &&
               P->terms[P->outputs[0][0].first].type == TG;
   for (auto &o : P->outputs)

@@ -1,0 +1,316 @@
+// Device-side plan construction: index validation and unique marks (Table 1),
+// the input pairs sorted into stage-1 key segments, output groupings for the
+// Cartesian match terms and the stage-2 tile orders of Theorem 1's two
+// stages.  Sorts are stable LSD radix sorts over the packed keys, so each
+// array equals the one a stable host counting sort gives.
+#include <hipcub/hipcub.hpp>
+
+#include <climits>
+
+#include "kernels.h"
+#include "plan_dev.h"
+
+namespace gvt {
+
+namespace {
+
+constexpr int PB = 256;  // threads per block of the plan kernels
+
+inline unsigned grid_for(int64_t n) {
+  const int64_t b = ceil_div(n > 0 ? n : 1, PB);
+  return (unsigned)(b < 65535 * 16 ? b : 65535 * 16);
+}
+
+void *scratch_get(DevScratch &sc, size_t bytes, hipStream_t s) {
+  if (bytes > sc.mem.bytes && sc.mem.p) {
+    // the old buffer may still be read by kernels queued on s
+    GVT_HIP_CHECK(hipStreamSynchronize(s));
+  }
+  return sc.mem.ensure(bytes);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---- probe ------------------------------------------------------------------
+struct ProbeArgs {
+  const int32_t *x[4];
+  int64_t n[4];
+  int64_t lim[4];
+  uint8_t *seen[4];
+  int64_t div[4][2];  // natural-order check: x[j] == j / div (even arrays) or j % div (odd); 0 = none
+};
+
+__global__ __launch_bounds__(PB) void probe_kernel(ProbeArgs a, unsigned long long *bad, int *notnat) {
+  const int y = blockIdx.y;
+  const int32_t *x = a.x[y];
+  const int64_t n = a.n[y], lim = a.lim[y];
+  uint8_t *seen = a.seen[y];
+  int mism = 0;
+  for (int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x; j < n; j += (int64_t)gridDim.x * PB) {
+    const int32_t v = x[j];
+    if (v < 0 || v >= lim) {
+      atomicMin(bad + y, (unsigned long long)j);
+    } else {
+      seen[v] = 1;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int64_t d = a.div[y][q];
+      if (d > 0) mism |= (int64_t)v != ((y & 1) ? j % d : j / d);
+    }
+  }
+  if (mism) *notnat = 1;
+}
+
+// ---- sorting helpers ----------------------------------------------------------
+template <class K>
+size_t sort_temp_bytes(int64_t n) {
+  size_t b = 0;
+  GVT_HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const K *)nullptr, (K *)nullptr,
+                                                   (const int32_t *)nullptr, (int32_t *)nullptr,
+                                                   (int)n, 0, (int)(8 * sizeof(K)), (hipStream_t)0));
+  return b;
+}
+
+template <class K>
+void sort_pairs(const K *kin, K *kout, const int32_t *vin, int32_t *vout, int64_t n, int nbits,
+                void *temp, size_t temp_bytes, hipStream_t s) {
+  if (n <= 0) return;
+  size_t tb = temp_bytes;
+  GVT_HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(temp, tb, kin, kout, vin, vout, (int)n, 0,
+                                                   nbits > 0 ? nbits : 1, s));
+}
+
+__global__ void iota_kernel(int32_t *v, int64_t n) {
+  for (int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x; j < n; j += (int64_t)gridDim.x * PB)
+    v[j] = (int32_t)j;
+}
+
+// start[k] = first position p of sorted keys whose bucket (key >> sh) is >= k,
+// k in [0, nb]; every k is written by exactly one position p in [0, n].
+template <class K>
+__global__ void bucket_starts_kernel(const K *__restrict__ key, int64_t n, int sh, int64_t nb,
+                                     int64_t *__restrict__ start) {
+  for (int64_t p = (int64_t)blockIdx.x * PB + threadIdx.x; p <= n; p += (int64_t)gridDim.x * PB) {
+    const int64_t kprev = p == 0 ? -1 : (int64_t)(key[p - 1] >> sh);
+    const int64_t kcur = p == n ? nb : (int64_t)(key[p] >> sh);
+    for (int64_t k = kprev + 1; k <= kcur; ++k) start[k] = p;
+  }
+}
+
+// ---- input sort -------------------------------------------------------------------
+template <class K>
+__global__ void pair_keys_kernel(const int32_t *__restrict__ key, const int32_t *__restrict__ other,
+                                 int64_t n, int ob, K *__restrict__ ck, int32_t *__restrict__ val) {
+  for (int64_t j = (int64_t)blockIdx.x * PB + threadIdx.x; j < n; j += (int64_t)gridDim.x * PB) {
+    ck[j] = ((K)(uint32_t)key[j] << ob) | (K)(uint32_t)other[j];
+    val[j] = (int32_t)j;
+  }
+}
+
+template <class K>
+__global__ void split_other_kernel(const K *__restrict__ ck, int64_t n, int ob,
+                                   int32_t *__restrict__ other) {
+  const K mask = ob > 0 ? (((K)1 << ob) - 1) : (K)0;
+  for (int64_t p = (int64_t)blockIdx.x * PB + threadIdx.x; p < n; p += (int64_t)gridDim.x * PB)
+    other[p] = (int32_t)(ck[p] & mask);
+}
+
+// cseg[k * (nch + 1) + c]: first position in segment k with other >= c * chunk
+// (binary search: others ascend inside a segment); the last entry ends the segment
+__global__ void cseg_kernel(const int64_t *__restrict__ seg, const int32_t *__restrict__ other,
+                            int64_t nkeys, int64_t nch, int64_t chunk, int32_t *__restrict__ cseg) {
+  const int64_t total = nkeys * (nch + 1);
+  for (int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * PB) {
+    const int64_t k = idx / (nch + 1), c = idx - k * (nch + 1);
+    int64_t lo = seg[k], hi = seg[k + 1];
+    if (c < nch) {
+      const int64_t lim = c * chunk;
+      while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (other[mid] < lim) lo = mid + 1;
+        else hi = mid;
+      }
+    } else {
+      lo = hi;
+    }
+    cseg[idx] = (int32_t)lo;
+  }
+}
+
+template <class K> size_t input_sort_bytes(int64_t n) {
+  return 2 * align256(n * sizeof(K)) + align256(n * sizeof(int32_t)) + sort_temp_bytes<K>(n);
+}
+
+template <class K>
+void input_sort_t(const int32_t *key, int64_t nkeys, const int32_t *other, int64_t nother, int64_t n,
+                  int64_t chunk, int32_t *perm, int32_t *other_out, int64_t *seg, int32_t *cseg,
+                  DevScratch &sc, hipStream_t s) {
+  const int ob = bits_for(nother), kb = bits_for(nkeys);
+  const size_t tb = sort_temp_bytes<K>(n);
+  const size_t o_kout = align256(n * sizeof(K)), o_val = o_kout + align256(n * sizeof(K));
+  const size_t o_tmp = o_val + align256(n * sizeof(int32_t));
+  char *base = static_cast<char *>(scratch_get(sc, o_tmp + tb, s));
+  K *kin = reinterpret_cast<K *>(base);
+  K *kout = reinterpret_cast<K *>(base + o_kout);
+  int32_t *val = reinterpret_cast<int32_t *>(base + o_val);
+  pair_keys_kernel<K><<<grid_for(n), PB, 0, s>>>(key, other, n, ob, kin, val);
+  sort_pairs<K>(kin, kout, val, perm, n, ob + kb, base + o_tmp, tb, s);
+  split_other_kernel<K><<<grid_for(n), PB, 0, s>>>(kout, n, ob, other_out);
+  bucket_starts_kernel<K><<<grid_for(n + 1), PB, 0, s>>>(kout, n, ob, nkeys, seg);
+  const int64_t nch = ceil_div(nother, chunk);
+  cseg_kernel<<<grid_for(nkeys * (nch + 1)), PB, 0, s>>>(seg, other_out, nkeys, nch, chunk, cseg);
+  check_launch(s);
+}
+
+// ---- stage-2 tiles ---------------------------------------------------------------
+__global__ void tile_keys_kernel(const int32_t *__restrict__ gx, const int32_t *__restrict__ sy,
+                                 const int32_t *__restrict__ rowmap, int64_t n, TileDims td,
+                                 uint32_t *__restrict__ tkey, int32_t *__restrict__ stg,
+                                 int32_t *__restrict__ val) {
+  for (int64_t i = (int64_t)blockIdx.x * PB + threadIdx.x; i < n; i += (int64_t)gridDim.x * PB) {
+    const int64_t yr = rowmap[sy[i]], xv = gx[i];
+    const int64_t grp = td.swap ? yr : xv, st = td.swap ? xv : yr;
+    const int64_t tile = (grp / td.rows_per_tile) * td.nsb + st / td.sbs;
+    tkey[i] = (uint32_t)(tile * td.rows_per_tile + grp % td.rows_per_tile);
+    stg[i] = (int32_t)st;
+    val[i] = (int32_t)i;
+  }
+}
+
+__global__ void gather_kernel(const int32_t *__restrict__ src, const int32_t *__restrict__ idx,
+                              int64_t n, int32_t *__restrict__ dst) {
+  for (int64_t q = (int64_t)blockIdx.x * PB + threadIdx.x; q < n; q += (int64_t)gridDim.x * PB)
+    dst[q] = src[idx[q]];
+}
+
+__global__ void tile_meta_kernel(const int64_t *__restrict__ sgk, TileDims td,
+                                 int64_t *__restrict__ toff, int32_t *__restrict__ tiley,
+                                 int32_t *__restrict__ tilemax) {
+  const int64_t R = td.rows_per_tile;
+  for (int64_t t = (int64_t)blockIdx.x * PB + threadIdx.x; t < td.ntiles;
+       t += (int64_t)gridDim.x * PB) {
+    int32_t mx = 0;
+    for (int64_t g = 0; g <= R; ++g) {
+      toff[t * (R + 1) + g] = sgk[t * R + g];
+      if (g < R) {
+        const int64_t c = sgk[t * R + g + 1] - sgk[t * R + g];
+        mx = c > mx ? (int32_t)c : mx;
+      }
+    }
+    tilemax[t] = mx;
+    const int64_t sbk = t % td.nsb, y0 = sbk * td.sbs;
+    const int64_t cnt = td.nstg_rows - y0 < td.sbs ? td.nstg_rows - y0 : td.sbs;
+    tiley[2 * t] = (int32_t)(y0 < td.nstg_rows ? y0 : td.nstg_rows);
+    tiley[2 * t + 1] = (int32_t)(cnt > 0 ? cnt : 0);
+  }
+}
+
+}  // namespace
+
+void dev_probe(const int32_t *const *x, const int64_t *n, const int64_t *lim, const int64_t *range,
+               int narr, int64_t nat_out_cols, int64_t nat_in_cols, DevScratch &sc,
+               ProbeResult &res, hipStream_t s) {
+  ProbeArgs a{};
+  size_t off = 64;  // bad[4] (u64) + notnat (int), padded
+  size_t soff[4] = {0, 0, 0, 0};
+  int64_t nmax = 0;
+  for (int i = 0; i < narr; ++i) {
+    a.x[i] = x[i];
+    a.n[i] = n[i];
+    a.lim[i] = lim[i];
+    soff[i] = off;
+    off += align256((size_t)std::max<int64_t>(range[i], 1));
+    nmax = std::max(nmax, n[i]);
+    // arrays 0/1 (output a, b) and 2/3 (input c, e); with two arrays the
+    // output pairs are the input pairs and carry both checks
+    const int64_t own = i < 2 ? nat_out_cols : nat_in_cols;
+    a.div[i][0] = own;
+    a.div[i][1] = (narr == 2) ? nat_in_cols : 0;
+  }
+  const size_t total = off;
+  char *base = static_cast<char *>(scratch_get(sc, total, s));
+  for (int i = 0; i < narr; ++i) a.seen[i] = reinterpret_cast<uint8_t *>(base + soff[i]);
+  GVT_HIP_CHECK(hipMemsetAsync(base, 0, total, s));
+  GVT_HIP_CHECK(hipMemsetAsync(base, 0xff, 32, s));
+  if (nmax > 0) {
+    const dim3 grid(std::min<unsigned>(grid_for(nmax), 2048u), (unsigned)narr);
+    probe_kernel<<<grid, PB, 0, s>>>(a, reinterpret_cast<unsigned long long *>(base),
+                                     reinterpret_cast<int *>(base + 32));
+    check_launch(s);
+  }
+  std::vector<uint8_t> h(total);
+  GVT_HIP_CHECK(hipMemcpyAsync(h.data(), base, total, hipMemcpyDeviceToHost, s));
+  GVT_HIP_CHECK(hipStreamSynchronize(s));
+  for (int i = 0; i < 4; ++i) res.bad[i] = -1;
+  for (int i = 0; i < narr; ++i) {
+    unsigned long long b;
+    std::memcpy(&b, h.data() + 8 * i, 8);
+    res.bad[i] = b == ULLONG_MAX ? -1 : (int64_t)b;
+    res.seen[i].assign(h.data() + soff[i], h.data() + soff[i] + range[i]);
+  }
+  int notnat;
+  std::memcpy(&notnat, h.data() + 32, 4);
+  res.nat = (nat_out_cols > 0 || nat_in_cols > 0) && notnat == 0;
+}
+
+size_t dev_input_sort_bytes(int64_t nkeys, int64_t nother, int64_t n) {
+  return bits_for(nkeys) + bits_for(nother) <= 32 ? input_sort_bytes<uint32_t>(n)
+                                                  : input_sort_bytes<uint64_t>(n);
+}
+
+size_t dev_group_rows_bytes(int64_t n) { return 2 * align256(n * 4) + sort_temp_bytes<uint32_t>(n); }
+
+size_t dev_tiles_bytes(int64_t n, int64_t nbuckets) {
+  return 4 * align256(n * 4) + align256((nbuckets + 1) * 8) + sort_temp_bytes<uint32_t>(n);
+}
+
+void dev_reserve(DevScratch &sc, size_t bytes, hipStream_t s) { (void)scratch_get(sc, bytes, s); }
+
+void dev_input_sort(const int32_t *key, int64_t nkeys, const int32_t *other, int64_t nother,
+                    int64_t n, int64_t chunk, int32_t *perm, int32_t *other_out, int64_t *seg,
+                    int32_t *cseg, DevScratch &sc, hipStream_t s) {
+  if (bits_for(nkeys) + bits_for(nother) <= 32)
+    input_sort_t<uint32_t>(key, nkeys, other, nother, n, chunk, perm, other_out, seg, cseg, sc, s);
+  else
+    input_sort_t<uint64_t>(key, nkeys, other, nother, n, chunk, perm, other_out, seg, cseg, sc, s);
+}
+
+void dev_group_rows(const int32_t *row, int64_t nrows, int64_t n, int32_t *perm, int64_t *off,
+                    DevScratch &sc, hipStream_t s) {
+  const size_t tb = sort_temp_bytes<uint32_t>(n);
+  const size_t o_val = align256(n * 4), o_tmp = o_val + align256(n * 4);
+  char *base = static_cast<char *>(scratch_get(sc, o_tmp + tb, s));
+  uint32_t *kout = reinterpret_cast<uint32_t *>(base);
+  int32_t *val = reinterpret_cast<int32_t *>(base + o_val);
+  iota_kernel<<<grid_for(n), PB, 0, s>>>(val, n);
+  sort_pairs<uint32_t>(reinterpret_cast<const uint32_t *>(row), kout, val, perm, n, bits_for(nrows),
+                       base + o_tmp, tb, s);
+  bucket_starts_kernel<uint32_t><<<grid_for(n + 1), PB, 0, s>>>(kout, n, 0, nrows, off);
+  check_launch(s);
+}
+
+void dev_tiles(const int32_t *gx, const int32_t *sy, const int32_t *rowmap, int64_t n,
+               const TileDims &td, int32_t *perm, int32_t *yrows, int64_t *toff, int32_t *tiley,
+               int32_t *tilemax, DevScratch &sc, hipStream_t s) {
+  const int64_t nb = td.ntiles * td.rows_per_tile;
+  const size_t tb = sort_temp_bytes<uint32_t>(n);
+  const size_t o_kout = align256(n * 4), o_stg = o_kout + align256(n * 4);
+  const size_t o_val = o_stg + align256(n * 4), o_sgk = o_val + align256(n * 4);
+  const size_t o_tmp = o_sgk + align256((nb + 1) * 8);
+  char *base = static_cast<char *>(scratch_get(sc, o_tmp + tb, s));
+  uint32_t *tkey = reinterpret_cast<uint32_t *>(base);
+  uint32_t *kout = reinterpret_cast<uint32_t *>(base + o_kout);
+  int32_t *stg = reinterpret_cast<int32_t *>(base + o_stg);
+  int32_t *val = reinterpret_cast<int32_t *>(base + o_val);
+  int64_t *sgk = reinterpret_cast<int64_t *>(base + o_sgk);
+  tile_keys_kernel<<<grid_for(n), PB, 0, s>>>(gx, sy, rowmap, n, td, tkey, stg, val);
+  sort_pairs<uint32_t>(tkey, kout, val, perm, n, bits_for(nb), base + o_tmp, tb, s);
+  gather_kernel<<<grid_for(n), PB, 0, s>>>(stg, perm, n, yrows);
+  bucket_starts_kernel<uint32_t><<<grid_for(n + 1), PB, 0, s>>>(kout, n, 0, nb, sgk);
+  tile_meta_kernel<<<grid_for(td.ntiles), PB, 0, s>>>(sgk, td, toff, tiley, tilemax);
+  check_launch(s);
+}
+
+}  // namespace gvt
