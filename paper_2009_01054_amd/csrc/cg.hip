@@ -144,13 +144,15 @@ __global__ __launch_bounds__(RB) void cg_update_kernel(double *__restrict__ a, i
 }
 
 // beta = rho_new / rho; p = r + beta p (and its FP32 copy p32, if given) for
-// systems that stepped; block 0 advances iters, rho and the state.  A system
-// that has just stopped gets its p updated too; nothing reads it afterwards
-// (a restart sets p again).
+// systems that stepped; block 0 advances iters, rho and the state, and sets
+// *run to whether any system is still active (the next product's gate).  A
+// system that has just stopped gets its p updated too; nothing reads it
+// afterwards (a restart sets p again).
 __global__ __launch_bounds__(RB) void cg_p_kernel(double *__restrict__ p, float *__restrict__ p32,
                                                   const double *__restrict__ r, int64_t n, int nlam,
                                                   CgScalars *sc, const double *__restrict__ part_rr,
-                                                  double tol, int max_iter, int lowprec) {
+                                                  double tol, int max_iter, int lowprec,
+                                                  int *__restrict__ run) {
   __shared__ double sh[RB];
   const bool rec = blockIdx.x == 0 && threadIdx.x == 0;
   for (int l = 0; l < nlam; ++l) {
@@ -182,6 +184,11 @@ __global__ __launch_bounds__(RB) void cg_p_kernel(double *__restrict__ p, float 
           sc[l].state = CG_MAXITER;
       }
     }
+  }
+  if (rec) {
+    int any = 0;
+    for (int l = 0; l < nlam; ++l) any |= sc[l].state == CG_ACTIVE;
+    *run = any;
   }
 }
 
@@ -297,7 +304,8 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
   double *part2 = part + (size_t)RNB * nlam;  // r.r partials (part holds p.w)
   CgScalars *sc = (CgScalars *)m_sc.ensure(sizeof(CgScalars) * nlam);
   double *lam = (double *)m_lam.ensure(nlam * 8);
-  double *tmp = (double *)m_tmp.ensure(64 * 8);
+  double *tmp = (double *)m_tmp.ensure(64 * 8 + 256);
+  int *gate = reinterpret_cast<int *>(tmp + 64);  // run flag of the iteration products
   float *p32 = nullptr, *w32 = nullptr, *D32 = nullptr, *T32 = nullptr;
   GVT_HIP_CHECK(hipMemcpyAsync(lam, lambdas, nlam * 8, hipMemcpyHostToDevice, s));
   if (mprec == GVT_F32) {
@@ -362,7 +370,11 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
     if (lowprec) to_f32_kernel<<<g1((int64_t)nv), 256, 0, s>>>(p, p32, (int64_t)nv);
   };
   refresh_p32();
+  // Products inside iterations are gated by `gate`: once every system has
+  // stopped, the rest of a captured block of iterations skips its products.
+  // Products outside iterations (certification, final residual) always run.
   auto iteration = [&]() {
+    P->gate = gate;
     if (lowprec) {
       plan_execute(P, GVT_F32, D32, d, T32, t, p32, nlam, n, w32, n, s);
       cg_pw_kernel<float><<<RNB, RB, 0, s>>>(w32, p, lam, n, nlam, sc, part);
@@ -372,8 +384,10 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
       cg_pw_kernel<double><<<RNB, RB, 0, s>>>(wraw, p, lam, n, nlam, sc, part);
       cg_update_kernel<double><<<RNB, RB, 0, s>>>(A, lda, r, p, wraw, lam, n, nlam, sc, part, part2);
     }
-    cg_p_kernel<<<RNB, RB, 0, s>>>(p, p32, r, n, nlam, sc, part2, tol, max_iter, lowprec);
+    cg_p_kernel<<<RNB, RB, 0, s>>>(p, p32, r, n, nlam, sc, part2, tol, max_iter, lowprec, gate);
+    P->gate = nullptr;
   };
+  GVT_HIP_CHECK(hipMemsetD32Async(gate, 1, 1, s));
 
   // warm-up layout of plan workspaces (allocation must not happen inside a capture)
   // by running one iteration eagerly, then capture blocks of check_every iterations.
@@ -415,6 +429,7 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
       copy_cols_kernel<<<g1(n), 256, 0, s>>>(w, n, r, n, n, nlam, CG_ACTIVE, sc);
       copy_cols_kernel<<<g1(n), 256, 0, s>>>(w, n, p, n, n, nlam, CG_ACTIVE, sc);
       refresh_p32();
+      GVT_HIP_CHECK(hipMemsetD32Async(gate, 1, 1, s));
       continue;
     }
     if (first) {

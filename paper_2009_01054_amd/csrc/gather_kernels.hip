@@ -29,7 +29,8 @@ __device__ __forceinline__ int64_t ceil_div_dev(int64_t a, int64_t b) { return (
 // vs[p*R + r] = V[perm[p] + r*ldv]  (input vector gathered into key order)
 template <class T>
 __global__ void pack_v_kernel(const T *__restrict__ V, int64_t ldv, const int32_t *__restrict__ perm,
-                              int64_t n, int R, T *__restrict__ vs) {
+                              int64_t n, int R, T *__restrict__ vs, const int *__restrict__ gate) {
+  if (gate && *gate == 0) return;
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   int64_t j = perm[p];
@@ -125,8 +126,9 @@ template <class T, int R, int KPW>
 __global__ __launch_bounds__(256) void stage1_kernel(
     const T *__restrict__ Fc, int64_t ldc, const int32_t *__restrict__ rows, int64_t nrows,
     const int64_t *__restrict__ seg, const int32_t *__restrict__ other, const T *__restrict__ vs,
-    int64_t nkeys, T *__restrict__ S, int64_t ldS) {
+    int64_t nkeys, T *__restrict__ S, int64_t ldS, const int *__restrict__ gate) {
   __shared__ T stg[64 * (S1Cfg<T, R, KPW>::KB * R + 1)];
+  if (gate && *gate == 0) return;
   stage1_block<T, R, KPW>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, blockIdx.x, blockIdx.y,
                           stg);
 }
@@ -224,8 +226,10 @@ template <class T, int R, int KPW>
 __global__ __launch_bounds__(256) void stage1_lds_kernel(
     const T *__restrict__ Fc, int64_t ldc, const int32_t *__restrict__ rows, int64_t nrows,
     const int32_t *__restrict__ cseg, int64_t nch, const int32_t *__restrict__ other,
-    const T *__restrict__ vs, int64_t nkeys, int64_t nother, T *__restrict__ S, int64_t ldS) {
+    const T *__restrict__ vs, int64_t nkeys, int64_t nother, T *__restrict__ S, int64_t ldS,
+    const int *__restrict__ gate) {
   __shared__ T lds[S1LdsCfg<T, R, KPW>::SIZE];
+  if (gate && *gate == 0) return;
   stage1_lds_block<T, R, KPW>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys, nother, S, ldS,
                               blockIdx.x, blockIdx.y, lds);
 }
@@ -406,8 +410,9 @@ __global__ __launch_bounds__(512) void stage2_kernel(
     const int32_t *__restrict__ tiley, const int32_t *__restrict__ tilemax,
     const int32_t *__restrict__ yrows, const int32_t *__restrict__ perm, int nyb,
     const T *__restrict__ S, int64_t ldS, int64_t nkeys, T coef, T *__restrict__ out, int64_t ldi,
-    int64_t ldr) {
+    int64_t ldr, const int *__restrict__ gate) {
   __shared__ S2Smem<T, R> sm;
+  if (gate && *gate == 0) return;
   stage2_tile<T, R>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out,
                     ldi, ldr, blockIdx.x, sm);
 }
@@ -533,8 +538,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void s
     const int32_t *__restrict__ tilex, const int32_t *__restrict__ tilemax,
     const int32_t *__restrict__ xrows, const int32_t *__restrict__ perm, int nxb,
     const T *__restrict__ S, int64_t ldS, int64_t nsr, int64_t nkeys, T coef, T *__restrict__ out,
-    int64_t ldi, int64_t ldr) {
+    int64_t ldi, int64_t ldr, const int *__restrict__ gate) {
   __shared__ S2ySmem<T, R> sm;
+  if (gate && *gate == 0) return;
   stage2y_tile<T, R>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out,
                      ldi, ldr, blockIdx.x, sm);
 }
@@ -768,9 +774,9 @@ static inline dim3 grid1(int64_t n, int bs) { return dim3((unsigned)ceil_div(n, 
 
 template <class T>
 void launch_pack_v(const T *V, int64_t ldv, const int32_t *perm, int64_t n, int R, T *vs,
-                   hipStream_t s) {
+                   hipStream_t s, const int *gate) {
   if (n <= 0) return;
-  pack_v_kernel<T><<<grid1(n, 256), 256, 0, s>>>(V, ldv, perm, n, R, vs);
+  pack_v_kernel<T><<<grid1(n, 256), 256, 0, s>>>(V, ldv, perm, n, R, vs, gate);
 }
 
 template <class T>
@@ -782,10 +788,10 @@ void launch_segsum(const int64_t *seg, const T *vs, int64_t nkeys, int R, T *out
 template <class T, int R, int KPW>
 static void stage1_rk(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
                       const int32_t *other, const T *vs, int64_t nkeys, T *S, int64_t ldS,
-                      hipStream_t s) {
+                      hipStream_t s, const int *gate) {
   typedef S1Cfg<T, R, KPW> C;
   dim3 grid((unsigned)ceil_div(nkeys, C::KB), (unsigned)ceil_div(nrows, 64));
-  stage1_kernel<T, R, KPW><<<grid, 256, 0, s>>>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS);
+  stage1_kernel<T, R, KPW><<<grid, 256, 0, s>>>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, gate);
 }
 
 // Launch knobs of stage 1: the tuned constants (tuning.h), overridable through
@@ -811,21 +817,22 @@ static int stage1_kpw() { return g_s1_kpw.load(std::memory_order_relaxed); }
 template <class T, int R>
 static void stage1_r(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
                      const int32_t *other, const T *vs, int64_t nkeys, T *S, int64_t ldS,
-                     hipStream_t s) {
+                     hipStream_t s, const int *gate) {
   switch (stage1_kpw()) {
-    case 1: stage1_rk<T, R, 1>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
-    case 2: stage1_rk<T, R, 2>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
-    default: stage1_rk<T, R, 4>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
+    case 1: stage1_rk<T, R, 1>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
+    case 2: stage1_rk<T, R, 2>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
+    default: stage1_rk<T, R, 4>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
   }
 }
 
 template <class T, int R, int KPW>
 static void stage1_lds_rk(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows,
                           const int32_t *cseg, int64_t nch, const int32_t *other, const T *vs,
-                          int64_t nkeys, int64_t nother, T *S, int64_t ldS, hipStream_t s) {
+                          int64_t nkeys, int64_t nother, T *S, int64_t ldS, hipStream_t s,
+                          const int *gate) {
   dim3 grid((unsigned)ceil_div(nkeys, S1LdsCfg<T, R, KPW>::KB), (unsigned)ceil_div(nrows, 64));
   stage1_lds_kernel<T, R, KPW><<<grid, 256, 0, s>>>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys,
-                                                     nother, S, ldS);
+                                                     nother, S, ldS, gate);
 }
 
 // Keys per wave of the LDS-staged stage 1 (more keys = more reuse of each
@@ -850,11 +857,11 @@ template <class T>
 void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
                    const int32_t *cseg, int64_t nch, const int32_t *other, int64_t npairs,
                    int64_t nother, const T *vs, int64_t nkeys, int R, T *S, int64_t ldS,
-                   hipStream_t s) {
+                   hipStream_t s, const int *gate) {
   if (nrows <= 0 || nkeys <= 0) return;
   const int kl = stage1_lds_kpw(R);
   if (cseg && stage1_use_lds(npairs, nkeys, nother, 4 * kl)) {
-#define GVT_S1L(RR, KK) stage1_lds_rk<T, RR, KK>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys, nother, S, ldS, s)
+#define GVT_S1L(RR, KK) stage1_lds_rk<T, RR, KK>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys, nother, S, ldS, s, gate)
     switch (R * 16 + kl) {
       case 16 + 2: GVT_S1L(1, 2); return;
       case 16 + 4: GVT_S1L(1, 4); return;
@@ -870,10 +877,10 @@ void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows,
 #undef GVT_S1L
   }
   switch (R) {
-    case 1: stage1_r<T, 1>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
-    case 2: stage1_r<T, 2>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
-    case 4: stage1_r<T, 4>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
-    case 8: stage1_r<T, 8>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s); break;
+    case 1: stage1_r<T, 1>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
+    case 2: stage1_r<T, 2>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
+    case 4: stage1_r<T, 4>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
+    case 8: stage1_r<T, 8>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
     default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in stage 1"};
   }
 }
@@ -890,15 +897,15 @@ template <class T>
 void launch_stage2(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff, const int32_t *tiley,
                    const int32_t *tilemax, int64_t ntiles, int nyb, const int32_t *yrows,
                    const int32_t *perm, const T *S, int64_t ldS, int64_t nkeys, int R, T coef, T *out,
-                   int64_t ldi, int64_t ldr, hipStream_t s) {
+                   int64_t ldi, int64_t ldr, hipStream_t s, const int *gate) {
   if (ntiles <= 0) return;
   dim3 grid((unsigned)ntiles);
   const int nt = S2Cfg<T, 1>::NT;
   switch (R) {
-    case 1: stage2_kernel<T, 1><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr); break;
-    case 2: stage2_kernel<T, 2><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr); break;
-    case 4: stage2_kernel<T, 4><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr); break;
-    case 8: stage2_kernel<T, 8><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr); break;
+    case 1: stage2_kernel<T, 1><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
+    case 2: stage2_kernel<T, 2><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
+    case 4: stage2_kernel<T, 4><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
+    case 8: stage2_kernel<T, 8><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
     default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in stage 2"};
   }
 }
@@ -907,12 +914,12 @@ template <class T>
 void launch_stage2y(const T *F1, int64_t ld1, const int64_t *tileoff, const int32_t *tilex,
                     const int32_t *tilemax, int64_t ntiles, int nxb, const int32_t *xrows,
                     const int32_t *perm, const T *S, int64_t ldS, int64_t nsr, int64_t nkeys, int R,
-                    T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s) {
+                    T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s, const int *gate) {
   if (ntiles <= 0) return;
   dim3 grid((unsigned)ntiles);
   switch (R) {
-    case 4: stage2y_kernel<T, 4><<<grid, 512, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr); break;
-    case 8: stage2y_kernel<T, 8><<<grid, 512, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr); break;
+    case 4: stage2y_kernel<T, 4><<<grid, 512, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate); break;
+    case 8: stage2y_kernel<T, 8><<<grid, 512, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate); break;
     default: throw Error{GVT_ERR_ARG, "internal: S-row grouped stage 2 needs a block of 4 or 8 RHS"};
   }
 }
@@ -1019,21 +1026,21 @@ void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64
 
 #define GVT_INSTANTIATE(T)                                                                      \
   template void launch_pack_v<T>(const T *, int64_t, const int32_t *, int64_t, int, T *,          \
-                                 hipStream_t);                                                   \
+                                 hipStream_t, const int *);                                      \
   template void launch_segsum<T>(const int64_t *, const T *, int64_t, int, T *, hipStream_t);    \
   template void launch_stage1<T>(const T *, int64_t, const int32_t *, int64_t, const int64_t *,  \
                                  const int32_t *, int64_t, const int32_t *, int64_t, int64_t,    \
-                                 const T *, int64_t, int, T *, int64_t, hipStream_t);            \
+                                 const T *, int64_t, int, T *, int64_t, hipStream_t, const int *);\
   template void launch_colscale<T>(const T *, int64_t, const int32_t *, int64_t, const T *,      \
                                    int64_t, int, T *, int64_t, hipStream_t);                     \
   template void launch_stage2<T>(const T *, int64_t, int64_t, const int64_t *, const int32_t *,  \
                                  const int32_t *, int64_t, int, const int32_t *, const int32_t *,\
                                  const T *, int64_t, int64_t, int, T, T *, int64_t, int64_t,     \
-                                 hipStream_t);                                                   \
+                                 hipStream_t, const int *);                                      \
   template void launch_stage2y<T>(const T *, int64_t, const int64_t *, const int32_t *,          \
                                   const int32_t *, int64_t, int, const int32_t *, const int32_t *,\
                                   const T *, int64_t, int64_t, int64_t, int, T, T *, int64_t,     \
-                                  int64_t, hipStream_t);                                          \
+                                  int64_t, hipStream_t, const int *);                             \
   template void launch_gemv<T>(const T *, int64_t, int64_t, int64_t, bool, const T *, int, T *,  \
                                hipStream_t);                                                     \
   template void launch_gather_rows<T>(const T *, const int32_t *, int64_t, int, T *,             \

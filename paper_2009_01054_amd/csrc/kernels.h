@@ -27,9 +27,12 @@ template <class T> struct CombineArgs {
   T coef[kMaxCombineOut][kMaxCombineTerms] = {};
 };
 
+// gate (optional device flag): when it reads 0 at run time, the launch does
+// nothing.  The product kernels of two-factor terms take one, so a captured
+// iteration whose systems have all stopped skips its product.
 template <class T>
 void launch_pack_v(const T *V, int64_t ldv, const int32_t *perm, int64_t n, int R, T *vs,
-                   hipStream_t s);
+                   hipStream_t s, const int *gate = nullptr);
 template <class T>
 void launch_segsum(const int64_t *seg, const T *vs, int64_t nkeys, int R, T *out, hipStream_t s);
 // Re-read the environment overrides of the tuned launch shapes (called when a
@@ -42,7 +45,7 @@ template <class T>
 void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
                    const int32_t *cseg, int64_t nch, const int32_t *other, int64_t npairs,
                    int64_t nother, const T *vs, int64_t nkeys, int R, T *S, int64_t ldS,
-                   hipStream_t s);
+                   hipStream_t s, const int *gate = nullptr);
 template <class T>
 void launch_colscale(const T *F, int64_t ldf, const int32_t *rows, int64_t nrows, const T *sv,
                      int64_t nkeys, int R, T *S, int64_t ldS, hipStream_t s);
@@ -50,13 +53,14 @@ template <class T>
 void launch_stage2(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff, const int32_t *tiley,
                    const int32_t *tilemax, int64_t ntiles, int nyb, const int32_t *yrows,
                    const int32_t *perm, const T *S, int64_t ldS, int64_t nkeys, int R, T coef, T *out,
-                   int64_t ldi, int64_t ldr, hipStream_t s);
+                   int64_t ldi, int64_t ldr, hipStream_t s, const int *gate = nullptr);
 // Stage 2 with S-row grouped tiles (blocks of R = 4 or 8 RHS).
 template <class T>
 void launch_stage2y(const T *F1, int64_t ld1, const int64_t *tileoff, const int32_t *tilex,
                     const int32_t *tilemax, int64_t ntiles, int nxb, const int32_t *xrows,
                     const int32_t *perm, const T *S, int64_t ldS, int64_t nsr, int64_t nkeys, int R,
-                    T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s);
+                    T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s,
+                    const int *gate = nullptr);
 template <class T>
 void launch_gemv(const T *F, int64_t ldf, int64_t nrows, int64_t ncols, bool sq, const T *sv, int R,
                  T *g, hipStream_t s);

@@ -114,6 +114,9 @@ struct gvt_plan {
   std::vector<gvt::TermSpec> terms;
   std::vector<std::vector<std::pair<int, double>>> outputs;  // per kind: (term, coef)
   bool direct = false;  // single kind, single G term with coefficient 1
+  // Device flag gating the two-factor product kernels (see launch_pack_v);
+  // set by a solver around the products it may want to skip, else null.
+  const int *gate = nullptr;
   gvt::Workspace ws[2];  // per precision (F64, F32)
   hipStream_t last_stream = nullptr;
   // Theorem 1 cost of the chosen term program (FMA count per RHS), for reporting

@@ -870,7 +870,7 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
   for (int k = 0; k < 2; ++k) {
     const InputSort &is = P->insort[k];
     if (!is.built) continue;
-    launch_pack_v<T>(V, ldv, is.perm.as<int32_t>(), P->n_in, R, wsp<T>(P, W.vs[k]), s);
+    launch_pack_v<T>(V, ldv, is.perm.as<int32_t>(), P->n_in, R, wsp<T>(P, W.vs[k]), s, P->gate);
     if (need_sv[k])
       launch_segsum<T>(is.seg.as<int64_t>(), wsp<T>(P, W.vs[k]), is.nkeys, R, wsp<T>(P, W.sv[k]), s);
   }
@@ -914,7 +914,7 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
     launch_stage1<T>(Fc, ldc, sb.d_rows.as<int32_t>(), (int64_t)sb.rows.size(),
                      is.seg.as<int64_t>(), is.cseg.as<int32_t>(), is.nchunks,
                      is.other.as<int32_t>(), P->n_in, is.nother, wsp<T>(P, W.vs[ks]), is.nkeys, R, S,
-                     ldS, s);
+                     ldS, s, P->gate);
   }
   mark(P, ST_STAGE1, 1, s);
   // two-factor terms: stage 2
@@ -930,12 +930,14 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
         launch_stage2<T>(F[t.fdot], ldF[t.fdot], rows_of(P, t.fdot), tl.tileoff.as<int64_t>(),
                          tl.tiley.as<int32_t>(), tl.tilemax.as<int32_t>(), tl.ntiles, tl.nyb,
                          tl.yrows.as<int32_t>(), tl.perm.as<int32_t>(), wsp<T>(P, W.sbuf[t.sbuf]),
-                         sbuf_ld<T>(P, t.sbuf, R), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s);
+                         sbuf_ld<T>(P, t.sbuf, R), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s,
+                         P->gate);
       else
         launch_stage2y<T>(F[t.fdot], ldF[t.fdot], tl.tileoff.as<int64_t>(), tl.tiley.as<int32_t>(),
                           tl.tilemax.as<int32_t>(), tl.ntiles, tl.nyb, tl.yrows.as<int32_t>(),
                           tl.perm.as<int32_t>(), wsp<T>(P, W.sbuf[t.sbuf]), sbuf_ld<T>(P, t.sbuf, R),
-                          (int64_t)sb.rows.size(), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s);
+                          (int64_t)sb.rows.size(), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s,
+                          P->gate);
     }
   }
   mark(P, ST_STAGE2, 1, s);

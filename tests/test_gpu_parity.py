@@ -300,6 +300,21 @@ def test_cg_f32_products_certified(gvt):
         assert np.linalg.norm(A[:, l] - A_or[:, l]) / np.linalg.norm(A_or[:, l]) < 1e-4
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cg_blocks_past_convergence_skip_products(gvt, prec):
+    # With a check every 256 iterations the captured block runs on past the
+    # last system's convergence; those iterations' products are gated off and
+    # their vector kernels leave every stopped system alone, so the results
+    # equal those of a check after every iteration, bit for bit.
+    p = W.make_heterogeneous(94, 2, 50, 40, 1200, 6, labels=True)
+    pr = gvt.F64 if prec == "f64" else gvt.F32
+    args = ("kronecker", dev(p["D"]), dev(p["T"]), (idx(p["c"]), idx(p["e"])), dev(p["y"]), [1e-1, 1.0])
+    A1, it1, rel1, rc1 = gvt.gvt_krr_cg(*args, max_iter=300, tol=1e-6, matvec_prec=pr, check_every=1)
+    A2, it2, rel2, rc2 = gvt.gvt_krr_cg(*args, max_iter=300, tol=1e-6, matvec_prec=pr, check_every=256)
+    assert rc1 == rc2 == 0 and (it1 < 200).all()
+    assert torch.equal(A1, A2) and (it1 == it2).all() and (rel1 == rel2).all()
+
+
 def test_cg_not_converged_status(gvt):
     p = W.make_heterogeneous(94, 1, 30, 30, 400, 4, labels=True)
     A, iters, rel, rc = gvt.gvt_krr_cg("kronecker", dev(p["D"]), dev(p["T"]), (idx(p["c"]), idx(p["e"])),
