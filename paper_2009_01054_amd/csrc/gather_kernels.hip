@@ -265,6 +265,35 @@ __global__ void colscale_kernel(const T *__restrict__ F, int64_t ldf, const int3
 // its outputs, reading the S rows from a shared LDS tile (one 1 KB chunk per
 // S row).  Partial sums stay in registers across chunks and meet in a fixed
 // butterfly at the end, so the result is deterministic.
+// Sum over the 16 lanes of a DPP row, in every lane, by data-parallel moves
+// inside the row (quad swaps, then half-row and row mirrors): no LDS traffic.
+// Each add pairs two partial sums, so every lane ends with the same value.
+template <int CTRL> __device__ __forceinline__ int dpp_mov(int x) {
+  return __builtin_amdgcn_mov_dpp(x, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL> __device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(dpp_mov<CTRL>(__float_as_int(x)));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_mov(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = dpp_mov<CTRL>((int)(b & 0xffffffffll)), hi = dpp_mov<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <class T> __device__ __forceinline__ T row16_sum(T v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+  v += dpp_mov<0x141>(v);  // row_half_mirror: quad q <-> the mirrored quad of its half
+  v += dpp_mov<0x140>(v);  // row_mirror: half <-> other half
+  return v;
+}
+
+// Largest value of x over the wave (x per 16-lane group), as a scalar.
+__device__ __forceinline__ int wave_max_of_groups(int x) {
+  x = max(x, __shfl_xor(x, 16));
+  x = max(x, __shfl_xor(x, 32));
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
 template <class T> struct Vec16;  // 16-byte vector of T
 template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
 template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
@@ -386,14 +415,15 @@ __device__ __forceinline__ void stage2_tile(
         }
       }
     }
+    // lane partial sums meet inside each 16-lane row; slots past every
+    // group's count in this wave are skipped (wave-uniform bound)
+    static_assert(C::LPO == 16, "one DPP row per output");
+    const int wn = wave_max_of_groups(npass);
 #pragma unroll
     for (int o = 0; o < C::OPG; ++o) {
+      if (o < wn) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        T v = acc[o][r];
-#pragma unroll
-        for (int off = 1; off < C::LPO; off <<= 1) v += __shfl_xor(v, off);
-        acc[o][r] = v;
+        for (int r = 0; r < R; ++r) acc[o][r] = row16_sum(acc[o][r]);
       }
       if (sub == 0 && o < npass) {
         const int64_t i = perm[qb + pass0 + o];
@@ -514,14 +544,15 @@ __device__ __forceinline__ void stage2y_tile(
         }
       }
     }
+    // lane partial sums meet inside each 16-lane row; slots past every
+    // group's count in this wave are skipped (wave-uniform bound)
+    static_assert(C::LPO == 16, "one DPP row per output");
+    const int wn = wave_max_of_groups(npass);
 #pragma unroll
     for (int o = 0; o < C::OPG; ++o) {
+      if (o < wn) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        T v = acc[o][r];
-#pragma unroll
-        for (int off = 1; off < C::LPO; off <<= 1) v += __shfl_xor(v, off);
-        acc[o][r] = v;
+        for (int r = 0; r < R; ++r) acc[o][r] = row16_sum(acc[o][r]);
       }
       if (sub == 0 && o < npass) {
         const int64_t i = perm[qb + pass0 + o];
