@@ -287,6 +287,13 @@ template <class T> __device__ __forceinline__ T row16_sum(T v) {
   return v;
 }
 
+// One wave instruction copying 64 x 16 bytes from global memory into LDS:
+// lane i reads 16 bytes at its own address g and they land at bytes 16i..16i+15
+// after l (l must be the same for the whole wave).
+__device__ __forceinline__ void lds_load_row16(const void *g, void *l) {
+  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)l, 16, 0, 0);
+}
+
 // Largest value of x over the wave (x per 16-lane group), as a scalar.
 __device__ __forceinline__ int wave_max_of_groups(int x) {
   x = max(x, __shfl_xor(x, 16));
@@ -333,7 +340,6 @@ __device__ __forceinline__ void stage2_tile(
   typedef S2Cfg<T, R> C;
   typedef typename Vec16<T>::type V16;
   constexpr int TROW = C::ROWE + C::PADE;
-  constexpr int V16ROW = C::ROWE / C::VEC;  // 16-byte words per tile row (64)
   T *tile = sm.tile;
   auto &meta = sm.meta;
   const int maxcnt = tilemax[t];
@@ -368,11 +374,15 @@ __device__ __forceinline__ void stage2_tile(
       for (int r = 0; r < R; ++r) acc[o][r] = T(0);
     for (int64_t c = 0; c < nch; ++c) {
       __syncthreads();
-      // S rows are padded with zeros to whole chunks: every row copy is a full 1 KB
-      for (int idx = threadIdx.x; idx < nyr * V16ROW; idx += C::NT) {
-        const int row = idx / V16ROW, cw = idx - row * V16ROW;
-        const V16 v = *reinterpret_cast<const V16 *>(S + (y0 + row) * ldS + c * C::ROWE + cw * C::VEC);
-        *reinterpret_cast<V16 *>(tile + row * TROW + cw * C::VEC) = v;
+      // S rows are padded with zeros to whole chunks, so every row is a full
+      // 1 KB: one wave instruction moves a row from global memory straight into
+      // its LDS tile row (lane i fills bytes 16i..16i+15), without registers,
+      // and all of a wave's rows are in flight together
+      {
+        const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+        static_assert(C::ROWE * sizeof(T) == 64 * 16, "a tile row is one wave-wide 16-byte load");
+        for (int row = wv; row < nyr; row += C::NT / 64)
+          lds_load_row16(S + (y0 + row) * ldS + c * C::ROWE + ln * C::VEC, tile + row * TROW);
       }
       T dsl[C::STEPS][C::KPL];
       const int64_t k0 = c * C::KC;
@@ -383,6 +393,7 @@ __device__ __forceinline__ void stage2_tile(
           const int64_t kk = k0 + (int64_t)st * C::LPO * C::KPL + sub * C::KPL + j;
           dsl[st][j] = (npass > 0 && x < nx && kk < nkeys) ? frow[kk] : T(0);
         }
+      __builtin_amdgcn_s_waitcnt(0);  // the tile rows have landed in LDS
       __syncthreads();
       // outputs in batches of four behind one branch: slots past npass read tile
       // row 0 (meta is 0 there) into accumulators that are never stored, so the
