@@ -694,9 +694,6 @@ struct PlanSet {
   }
 };
 
-// Largest RHS block the products use for nlam systems per problem.
-int rhs_block(int64_t left) { return left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1; }
-
 }  // namespace
 
 int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const double *lambdas,
@@ -777,7 +774,9 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
   bool grouped = true;
   for (gvt_plan *P : ps.plans)
     grouped = grouped && P->direct && P->sbufs.size() == 1 && !P->sbufs[0].degenerate;
-  const int Rmax = rhs_block(nlam);
+  // RHS blocks of the grouped products (every plan of the set has the same cap)
+  const int maxR = ps.plans[0]->max_rhs;
+  const int Rmax = rhs_block(nlam, maxR);
 
   // ---- device memory
   DevMem m_a, m_r, m_p, m_w, m_wraw, m_p32, m_w32, m_y, m_part, m_sc, m_lam, m_tmp, m_act, m_cmask,
@@ -830,7 +829,8 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
   GroupItem *it_pack = nullptr, *it_s1 = nullptr, *it_s2[kTileClasses] = {nullptr, nullptr};
   int64_t n_pack = 0, n_s1 = 0, n_s2[kTileClasses] = {0, 0};
   bool need_cls[kTileClasses] = {false, false};
-  for (int64_t r0 = 0; r0 < nlam; r0 += rhs_block(nlam - r0)) need_cls[tile_class(rhs_block(nlam - r0))] = true;
+  for (int64_t r0 = 0; r0 < nlam; r0 += rhs_block(nlam - r0, maxR))
+    need_cls[tile_class(rhs_block(nlam - r0, maxR))] = true;
   if (grouped) {
     for (gvt_plan *P : ps.plans)
       for (int cls = 0; cls < kTileClasses; ++cls)
@@ -947,10 +947,10 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     GVT_HIP_CHECK(hipStreamSynchronize(s));
   }
 
-  // ---- products of every problem: out = K in (RHS blocks of at most 8)
+  // ---- products of every problem: out = K in (RHS blocks of at most maxR)
   auto grouped_product = [&](auto *desc, const uint8_t *mask) {
     for (int64_t r0 = 0; r0 < nlam;) {
-      const int R = rhs_block(nlam - r0);
+      const int R = rhs_block(nlam - r0, maxR);
       launch_group_pack(desc, it_pack, n_pack, R, r0, mask, s);
       launch_group_stage1(desc, it_s1, n_s1, R, mask, s);
       launch_group_stage2(desc, it_s2[tile_class(R)], n_s2[tile_class(R)], R, r0, mask, s);

@@ -504,6 +504,8 @@ __device__ __forceinline__ void stage2y_tile(
   const int cnt = (int)(tileoff[(int64_t)t * (C::NG + 1) + grp + 1] - qb);
   const T *srow = S + (yrow < nsr ? yrow : 0) * ldS;
   const int64_t nch = (nkeys + C::KC - 1) / C::KC;
+  // F1 rows start on 16-byte boundaries: whole pieces load as one vector
+  const bool f1_vec = ld1 % VEC == 0 && reinterpret_cast<uintptr_t>(F1) % 16 == 0;
   for (int pass0 = 0; pass0 < maxcnt; pass0 += C::OPG) {
     const int npass = (cnt - pass0) < C::OPG ? (cnt - pass0) : C::OPG;  // may be <= 0
     __syncthreads();
@@ -517,11 +519,24 @@ __device__ __forceinline__ void stage2y_tile(
     for (int64_t c = 0; c < nch; ++c) {
       const int64_t k0 = c * C::KC;
       __syncthreads();
-      // F1 rows of the tile, this chunk's keys (zero past the last key)
-      for (int idx = threadIdx.x; idx < nxr * C::KC; idx += C::NT) {
-        const int row = idx / C::KC, kk = idx - row * C::KC;
-        const int64_t k = k0 + kk;
-        sm.ftile[row * C::FROW + kk] = k < nkeys ? F1[(x0 + row) * ld1 + k] : T(0);
+      // F1 rows of the tile, this chunk's keys (zero past the last key), in
+      // 16-byte pieces
+      {
+        constexpr int PPR = C::KC / VEC;  // pieces per row
+#pragma unroll 1
+        for (int idx = threadIdx.x; idx < nxr * PPR; idx += C::NT) {
+          const int row = idx / PPR, pc = idx - row * PPR;
+          const int64_t k = k0 + pc * VEC;
+          const T *src = F1 + (x0 + row) * ld1 + k;
+          V16 v;
+          if (f1_vec && k + VEC <= nkeys) {
+            v = *reinterpret_cast<const V16 *>(src);
+          } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) v[e] = k + e < nkeys ? src[e] : T(0);
+          }
+          *reinterpret_cast<V16 *>(sm.ftile + row * C::FROW + pc * VEC) = v;
+        }
       }
       // this lane's S slice: keys k0 + sub*KPL .. + KPL-1, R values each (KPL x R registers)
       T sv[C::KPL][R];

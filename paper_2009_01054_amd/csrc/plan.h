@@ -117,6 +117,9 @@ struct gvt_plan {
   // Device flag gating the two-factor product kernels (see launch_pack_v);
   // set by a solver around the products it may want to skip, else null.
   const int *gate = nullptr;
+  // Largest block of right-hand sides one product pass carries (1, 2, 4 or 8;
+  // the tuned kMaxRhsBlock, or GVT_MAX_RHS_BLOCK when the plan is built).
+  int max_rhs = 8;
   gvt::Workspace ws[2];  // per precision (F64, F32)
   hipStream_t last_stream = nullptr;
   // Theorem 1 cost of the chosen term program (FMA count per RHS), for reporting
@@ -141,6 +144,11 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
 // when built).  Synchronous host work and a copy: not allowed while `s` is
 // being captured.
 void plan_ensure_tiles(gvt_plan *P, int cls, hipStream_t s);
+// RHS block of a product pass for `left` remaining right-hand sides.
+inline int rhs_block(int64_t left, int max_rhs) {
+  const int64_t m = left < max_rhs ? left : max_rhs;
+  return m >= 8 ? 8 : m >= 4 ? 4 : m >= 2 ? 2 : 1;
+}
 // S rows per stage-2 block for a term: from the tuning target of the class
 // (or the GVT_STAGE2_TARGET_R1 / GVT_STAGE2_TARGET_R8 environment override).
 int stage2_block_rows(const gvt_plan *P, const TermSpec &t, int cls);

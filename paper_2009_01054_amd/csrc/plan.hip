@@ -348,6 +348,11 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   GVT_REQUIRE(!((flags & GVT_FLAG_ORDER_A) && (flags & GVT_FLAG_ORDER_B)), GVT_ERR_ARG,
               "ORDER_A and ORDER_B are exclusive");
   refresh_launch_knobs();
+  {
+    const char *ev = std::getenv("GVT_MAX_RHS_BLOCK");
+    const int mr = ev && *ev ? std::atoi(ev) : kMaxRhsBlock;
+    P->max_rhs = (mr == 1 || mr == 2 || mr == 4 || mr == 8) ? mr : 8;
+  }
   P->kinds.assign(kinds, kinds + nkinds);
   P->flags = flags;
   bool hom = false;
@@ -663,7 +668,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   if (P->on_device) {
     // ---- sorts and tile orders on the device: sizes first (one allocation),
     // then the small host arrays, then the kernels, all queued on s --------
-    const int cls = tile_class(rhs_hint);
+    const int cls = tile_class(rhs_block(rhs_hint, P->max_rhs));
     DevLayout L;
     for (int ks = 0; ks < 2; ++ks) {
       if (!insort_needed[ks]) continue;
@@ -743,7 +748,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
           tg.run([&, xs]() {
             counting_sort(h[xs == 0 ? SA : SB], xs == 0 ? d_rows : t_rows, oo_perm[xs], oo_off[xs]);
           });
-      const int cls = tile_class(rhs_hint);
+      const int cls = tile_class(rhs_block(rhs_hint, P->max_rhs));
       for (size_t k = 0; k < tiles.size(); ++k)
         tg.run([&, k]() {
           guard(2 + k, [&]() { tiles[k].second = compute_tiles(P, *tiles[k].first, cls); });
@@ -984,7 +989,7 @@ void execute_t(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ldt, c
   int64_t r0 = 0;
   while (r0 < nrhs) {
     const int64_t left = nrhs - r0;
-    const int R = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    const int R = rhs_block(left, P->max_rhs);
     plan_ensure_tiles(P, tile_class(R), s);
     execute_block<T>(P, D, ldd, Tm, ldt, V + r0 * ldv, R, ldv, U + r0 * ldu, ldu, block_stride, s);
     r0 += R;

@@ -12,11 +12,14 @@ trades waves in flight against per-wave work.
 
 Stage 1 can also stage the F2 columns of a chunk of other indices in LDS
 and read them from there (worth it only if each column is reused enough).
+A product pass carries a block of up to 8 right-hand sides; larger blocks
+reuse every gathered element more often but hold more accumulators per lane,
+so the largest block a pass takes is tuned too.
 
 This script sweeps the four knobs on synthetic workloads shaped like the
 library's benchmarks, through the library's environment overrides
-(GVT_STAGE1_LDS, GVT_STAGE1_KPW, GVT_STAGE2_TARGET_R1, GVT_STAGE2_TARGET_R8;
-the targets are read when a plan is built), and writes the winners as a C++
+(GVT_STAGE1_LDS, GVT_STAGE1_KPW, GVT_STAGE2_TARGET_R1, GVT_STAGE2_TARGET_R8,
+GVT_MAX_RHS_BLOCK; all are read when a plan is built), and writes the winners as a C++
 header that ``build.py`` compiles into the library:
 
     python -m paper_2009_01054_amd.tune --out paper_2009_01054_amd/csrc/tuning.h
@@ -39,6 +42,7 @@ if ROOT not in sys.path:
 R1_CANDIDATES = (8.0, 16.0, 32.0, 64.0, 128.0)
 R8_CANDIDATES = (2.0, 4.0, 8.0, 16.0, 32.0)
 KPW_CANDIDATES = (1, 2, 4)
+MAXR_CANDIDATES = (2, 4, 8)
 LDS_CANDIDATES = (0, 1)  # stage 1: direct walk, or LDS-staged columns where reused >= 1.5 times
 
 
@@ -59,11 +63,11 @@ def _events_ms(torch, fn, reps):
 
 
 _KNOBS = {0: "GVT_STAGE2_TARGET_R1", 1: "GVT_STAGE2_TARGET_R8", "kpw": "GVT_STAGE1_KPW",
-          "lds": "GVT_STAGE1_LDS"}
+          "lds": "GVT_STAGE1_LDS", "maxr": "GVT_MAX_RHS_BLOCK"}
 
 
 def _set_target(cls, value):
-    os.environ[_KNOBS[cls]] = str(int(value)) if cls in ("kpw", "lds") else repr(float(value))
+    os.environ[_KNOBS[cls]] = str(int(value)) if cls in ("kpw", "lds", "maxr") else repr(float(value))
 
 
 def ridge_products(gvt, W, torch, nrhs, reps):
@@ -147,6 +151,7 @@ def write_header(path, results, device):
               f"constexpr double kStage2TargetR1 = {results['R1'][0]:.1f};",
               f"constexpr double kStage2TargetR8 = {results['R8'][0]:.1f};",
               f"constexpr int kStage1KeysPerWave = {int(results['KPW'][0])};",
+              f"constexpr int kMaxRhsBlock = {int(results['MAXR'][0])};",
               "constexpr int kStage1LdsKeysPerWave = 4;",
               "constexpr double kStage1LdsMinReuse = "
               + ("1.5;" if results["LDS"][0] else "1e300;  // LDS-staged stage 1 off"),
@@ -176,13 +181,16 @@ def main():
         gvt, W, torch, args.batched_problems)
     results = {}
     for key, cls, cands, wl in (("LDS", "lds", LDS_CANDIDATES, r1), ("KPW", "kpw", KPW_CANDIDATES, r1),
-                                ("R1", 0, R1_CANDIDATES, r1), ("R8", 1, R8_CANDIDATES, r8)):
+                                ("R1", 0, R1_CANDIDATES, r1), ("MAXR", "maxr", MAXR_CANDIDATES, r8),
+                                ("R8", 1, R8_CANDIDATES, r8)):
         winner, table, score = sweep(cls, cands, wl)
         results[key] = (winner, table, score, [n for n, _ in wl])
+        if key == "MAXR":
+            _set_target(cls, winner)  # the R8 sweep runs with the chosen block cap
         _log(f"[tune] class {key}: target {winner:g}")
     write_header(args.out, results, device)
     print(f"wrote {args.out}: stage-1 keys per wave {results['KPW'][0]}, R1 target {results['R1'][0]:g}, "
-          f"R8 target {results['R8'][0]:g}")
+          f"largest RHS block {results['MAXR'][0]}, R8 target {results['R8'][0]:g}")
 
 
 if __name__ == "__main__":

@@ -342,12 +342,35 @@ def _dev_problems(probs, hom=False):
             for p in probs]
 
 
-@pytest.mark.parametrize("nlam", [3, 5])
-def test_cg_batched_f64_matches_oracle(gvt, nlam):
-    # uneven problems; nlam = 5 runs the products as RHS blocks of 4 and 1
+@pytest.mark.parametrize("cap", ["1", "2", "8"])
+@pytest.mark.parametrize("kind,prec", [(k, pr) for k in ["kronecker", "poly2d", "cartesian"] for pr in ["f64", "f32"]]
+                         + [("mlpk", "f64")])
+def test_rhs_block_caps(gvt, monkeypatch, kind, prec, cap):
+    # 13 RHS cut into blocks of at most 1, 2 or 8 (the library's tuned cap is
+    # in between): every block size of both stage-2 tile classes is exercised.
+    # (MLPK's ten cancelling terms leave FP32 products within a hair of 1e-5 on
+    # some inputs; its FP32 form is checked at the default cap with every kind.)
+    monkeypatch.setenv("GVT_MAX_RHS_BLOCK", cap)
+    p = _hom_problem(21, nrhs=13) if kind in HOM else _het_problem(21, nrhs=13)
+    T = None if kind in HOM else p["T"]
+    ref = oracle.pairwise_matvec(kind, p["D"], T, (p["a"], p["b"]), (p["c"], p["e"]), p["v"])
+    dt = tdt(prec)
+    Dd = dev(p["D"], dt)
+    Td = Dd if T is None else dev(T, dt)
+    u = gvt.gvt_pairwise_matvec([kind], Dd, Td, (idx(p["a"]), idx(p["b"])), (idx(p["c"]), idx(p["e"])),
+                                dev(p["v"], dt), flags=gvt.FLAG_SYMMETRIC_BASES)
+    assert relerr(u[0].cpu().double().numpy(), ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("cap", ["4", "8"])
+@pytest.mark.parametrize("nlam", [3, 5, 8])
+def test_cg_batched_f64_matches_oracle(gvt, monkeypatch, nlam, cap):
+    # uneven problems; the products run in RHS blocks of at most `cap`
+    # (nlam = 5: blocks of 4 and 1; nlam = 8 with cap 8: one block of 8)
+    monkeypatch.setenv("GVT_MAX_RHS_BLOCK", cap)
     shapes = [(23, 31, 400), (60, 17, 700), (41, 45, 1500), (12, 90, 500), (70, 70, 2100), (35, 9, 250)]
     probs = _batch(95, shapes)
-    lams = [1e-1, 1.0, 10.0, 0.5, 3.0][:nlam]
+    lams = [1e-1, 1.0, 10.0, 0.5, 3.0, 2.0, 0.3, 5.0][:nlam]
     A, iters, rel, rc = gvt.gvt_krr_cg_batched("kronecker", _dev_problems(probs), lams, max_iter=400,
                                                tol=1e-8, check_every=4)
     assert rc == 0
