@@ -446,7 +446,7 @@ __device__ __forceinline__ void stage2_tile(
 }
 
 template <class T, int R>
-__global__ __launch_bounds__(512) void stage2_kernel(
+__global__ __launch_bounds__(kStage2Rows * 16) void stage2_kernel(
     const T *__restrict__ F1, int64_t ld1, int64_t nx, const int64_t *__restrict__ tileoff,
     const int32_t *__restrict__ tiley, const int32_t *__restrict__ tilemax,
     const int32_t *__restrict__ yrows, const int32_t *__restrict__ perm, int nyb,
@@ -590,7 +590,7 @@ __device__ __forceinline__ void stage2y_tile(
 }
 
 template <class T, int R>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void stage2y_kernel(
+__global__ __launch_bounds__(kStage2Rows * 16) __attribute__((amdgpu_waves_per_eu(4))) void stage2y_kernel(
     const T *__restrict__ F1, int64_t ld1, const int64_t *__restrict__ tileoff,
     const int32_t *__restrict__ tilex, const int32_t *__restrict__ tilemax,
     const int32_t *__restrict__ xrows, const int32_t *__restrict__ perm, int nxb,
@@ -797,7 +797,7 @@ __global__ __launch_bounds__(256) void group_stage1_kernel(const GroupDesc<T> *_
 }
 
 template <class T, int R>
-__global__ __launch_bounds__(512) void group_stage2_kernel(const GroupDesc<T> *__restrict__ desc,
+__global__ __launch_bounds__(kStage2Rows * 16) void group_stage2_kernel(const GroupDesc<T> *__restrict__ desc,
                                                            const GroupItem *__restrict__ items,
                                                            int64_t r0,
                                                            const uint8_t *__restrict__ active) {
@@ -811,7 +811,7 @@ __global__ __launch_bounds__(512) void group_stage2_kernel(const GroupDesc<T> *_
 }
 
 template <class T, int R>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void group_stage2y_kernel(const GroupDesc<T> *__restrict__ desc,
+__global__ __launch_bounds__(kStage2Rows * 16) __attribute__((amdgpu_waves_per_eu(4))) void group_stage2y_kernel(const GroupDesc<T> *__restrict__ desc,
                                                             const GroupItem *__restrict__ items,
                                                             int64_t r0,
                                                             const uint8_t *__restrict__ active) {
@@ -975,8 +975,8 @@ void launch_stage2y(const T *F1, int64_t ld1, const int64_t *tileoff, const int3
   if (ntiles <= 0) return;
   dim3 grid((unsigned)ntiles);
   switch (R) {
-    case 4: stage2y_kernel<T, 4><<<grid, 512, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate); break;
-    case 8: stage2y_kernel<T, 8><<<grid, 512, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate); break;
+    case 4: stage2y_kernel<T, 4><<<grid, kStage2Rows * 16, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate); break;
+    case 8: stage2y_kernel<T, 8><<<grid, kStage2Rows * 16, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate); break;
     default: throw Error{GVT_ERR_ARG, "internal: S-row grouped stage 2 needs a block of 4 or 8 RHS"};
   }
 }
@@ -1075,8 +1075,8 @@ void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64
   switch (R) {
     case 1: group_stage2_kernel<T, 1><<<g, nt, 0, s>>>(desc, items, r0, active); break;
     case 2: group_stage2_kernel<T, 2><<<g, nt, 0, s>>>(desc, items, r0, active); break;
-    case 4: group_stage2y_kernel<T, 4><<<g, 512, 0, s>>>(desc, items, r0, active); break;
-    case 8: group_stage2y_kernel<T, 8><<<g, 512, 0, s>>>(desc, items, r0, active); break;
+    case 4: group_stage2y_kernel<T, 4><<<g, kStage2Rows * 16, 0, s>>>(desc, items, r0, active); break;
+    case 8: group_stage2y_kernel<T, 8><<<g, kStage2Rows * 16, 0, s>>>(desc, items, r0, active); break;
     default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in grouped stage 2"};
   }
 }
