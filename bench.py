@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 METRIC = "GVT matvecs/sec & KRR-CG time to 1e-6 rel. residual; fraction of HBM/MFMA roofline"
 PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X published FP64 vector peak
 PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X published FP32 vector peak (counts packed FP32)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage2_merget_shape.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage2_ridge_m2000_q500_n200k.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2009_01054_amd", "csrc", "gather_kernels.hip")
 
 
