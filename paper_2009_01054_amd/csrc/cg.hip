@@ -147,12 +147,21 @@ __global__ __launch_bounds__(RB) void cg_update_kernel(double *__restrict__ a, i
 // systems that stepped; block 0 advances iters, rho and the state, and sets
 // *run to whether any system is still active (the next product's gate).  A
 // system that has just stopped gets its p updated too; nothing reads it
-// afterwards (a restart sets p again).
+// afterwards (a restart sets p again).  With pack targets (vs[k] non-null)
+// the new p also goes straight into the key order the next product reads
+// (element (i, l) to vs[k][inv[k][i] * nlam + l]), which saves that product
+// its pack.
+template <class TV> struct PackTo {
+  TV *vs[2];
+  const int32_t *inv[2];
+};
+
+template <class TV>
 __global__ __launch_bounds__(RB) void cg_p_kernel(double *__restrict__ p, float *__restrict__ p32,
                                                   const double *__restrict__ r, int64_t n, int nlam,
                                                   CgScalars *sc, const double *__restrict__ part_rr,
                                                   double tol, int max_iter, int lowprec,
-                                                  int *__restrict__ run) {
+                                                  int *__restrict__ run, PackTo<TV> pk) {
   __shared__ double sh[RB];
   const bool rec = blockIdx.x == 0 && threadIdx.x == 0;
   for (int l = 0; l < nlam; ++l) {
@@ -169,6 +178,9 @@ __global__ __launch_bounds__(RB) void cg_p_kernel(double *__restrict__ p, float 
         const double pi = r[i + l * n] + beta * p[i + l * n];
         p[i + l * n] = pi;
         if (p32) p32[i + l * n] = (float)pi;
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+          if (pk.vs[k]) pk.vs[k][(int64_t)pk.inv[k][i] * nlam + l] = (TV)pi;
       }
     }
     if (rec) {
@@ -370,11 +382,37 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
     if (lowprec) to_f32_kernel<<<g1((int64_t)nv), 256, 0, s>>>(p, p32, (int64_t)nv);
   };
   refresh_p32();
+  // When the nlam systems form one RHS block of the plan, the direction kernel
+  // writes p in the key order of the iteration products as well, and those
+  // products skip their pack; after the host sets p it is packed here.
+  const int iprec = lowprec ? GVT_F32 : GVT_F64;
+  const bool fuse_pack = rhs_block(nlam, P->max_rhs) == nlam;
+  PackTo<double> pk64{{nullptr, nullptr}, {nullptr, nullptr}};
+  PackTo<float> pk32{{nullptr, nullptr}, {nullptr, nullptr}};
+  if (fuse_pack) {
+    void *vs[2] = {nullptr, nullptr};
+    const int32_t *inv[2] = {nullptr, nullptr};
+    const int nk = plan_pack_targets(P, iprec, nlam, vs, inv);
+    for (int k = 0; k < nk; ++k) {
+      if (lowprec) {
+        pk32.vs[k] = static_cast<float *>(vs[k]);
+        pk32.inv[k] = inv[k];
+      } else {
+        pk64.vs[k] = static_cast<double *>(vs[k]);
+        pk64.inv[k] = inv[k];
+      }
+    }
+  }
+  auto repack = [&]() {
+    if (fuse_pack) plan_pack(P, iprec, lowprec ? (const void *)p32 : (const void *)p, n, nlam, s);
+  };
   // Products inside iterations are gated by `gate`: once every system has
   // stopped, the rest of a captured block of iterations skips its products.
   // Products outside iterations (certification, final residual) always run.
+  bool packed = false;  // whether the key-ordered copy of p is current
   auto iteration = [&]() {
     P->gate = gate;
+    P->prepacked = fuse_pack && packed;
     if (lowprec) {
       plan_execute(P, GVT_F32, D32, d, T32, t, p32, nlam, n, w32, n, s);
       cg_pw_kernel<float><<<RNB, RB, 0, s>>>(w32, p, lam, n, nlam, sc, part);
@@ -384,7 +422,12 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
       cg_pw_kernel<double><<<RNB, RB, 0, s>>>(wraw, p, lam, n, nlam, sc, part);
       cg_update_kernel<double><<<RNB, RB, 0, s>>>(A, lda, r, p, wraw, lam, n, nlam, sc, part, part2);
     }
-    cg_p_kernel<<<RNB, RB, 0, s>>>(p, p32, r, n, nlam, sc, part2, tol, max_iter, lowprec, gate);
+    P->prepacked = false;
+    if (lowprec)
+      cg_p_kernel<float><<<RNB, RB, 0, s>>>(p, p32, r, n, nlam, sc, part2, tol, max_iter, lowprec, gate, pk32);
+    else
+      cg_p_kernel<double><<<RNB, RB, 0, s>>>(p, p32, r, n, nlam, sc, part2, tol, max_iter, lowprec, gate, pk64);
+    packed = true;
     P->gate = nullptr;
   };
   GVT_HIP_CHECK(hipMemsetD32Async(gate, 1, 1, s));
@@ -429,6 +472,7 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
       copy_cols_kernel<<<g1(n), 256, 0, s>>>(w, n, r, n, n, nlam, CG_ACTIVE, sc);
       copy_cols_kernel<<<g1(n), 256, 0, s>>>(w, n, p, n, n, nlam, CG_ACTIVE, sc);
       refresh_p32();
+      repack();
       GVT_HIP_CHECK(hipMemsetD32Async(gate, 1, 1, s));
       continue;
     }

@@ -19,6 +19,7 @@ struct InputSort {  // input pairs sorted by one index (key segments), then by t
   int64_t nkeys = 0;
   int64_t nother = 0;  // range of the other index
   DevMem perm;   // int32[n_in]: sorted position -> input index j
+  DevMem inv;    // int32[n_in]: input index j -> sorted position (inverse of perm)
   DevMem other;  // int32[n_in]: the other index of the pair at that position
   DevMem seg;    // int64[nkeys + 1]: segment offsets
   // per key, the start of each chunk of kStage1OtherChunk other indices inside
@@ -117,6 +118,9 @@ struct gvt_plan {
   // Device flag gating the two-factor product kernels (see launch_pack_v);
   // set by a solver around the products it may want to skip, else null.
   const int *gate = nullptr;
+  // Set by a solver whose own kernels have already written the input vector
+  // in key order (plan_pack_targets): the products then skip their pack.
+  bool prepacked = false;
   // Largest block of right-hand sides one product pass carries (1, 2, 4 or 8;
   // the tuned kMaxRhsBlock, or GVT_MAX_RHS_BLOCK when the plan is built).
   int max_rhs = 8;
@@ -154,6 +158,13 @@ inline int rhs_block(int64_t left, int max_rhs) {
 int stage2_block_rows(const gvt_plan *P, const TermSpec &t, int cls);
 void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,
                   const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu, hipStream_t s);
+// Where a product with one block of R right-hand sides (R a block size the
+// plan runs whole: rhs_block(R, max_rhs) == R) reads its input in key order:
+// for each input sort k < the returned count, element (j, r) of the input
+// goes to vs[k][inv[k][j] * R + r].  Lays out the precision's workspace for R.
+int plan_pack_targets(gvt_plan *P, int prec, int R, void **vs, const int32_t **inv);
+// The pack alone: V (n_in x R, column stride ldv) into those places.
+void plan_pack(gvt_plan *P, int prec, const void *V, int64_t ldv, int R, hipStream_t s);
 void plan_profile(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,
                   const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu, int reps,
                   double *stage_ms, hipStream_t s);

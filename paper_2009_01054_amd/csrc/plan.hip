@@ -567,7 +567,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   auto need_insort = [&](int key) { insort_needed[key == SC ? 0 : 1] = true; };
   // sort by other index first, then stably by key: segments ordered by other inside
   struct SortHost {
-    std::vector<int32_t> perm, other, cseg;
+    std::vector<int32_t> perm, inv, other, cseg;
     std::vector<int64_t> seg;
   } sort_host[2];
   auto build_insort = [&](int ks) {
@@ -580,6 +580,8 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     for (int64_t p = 0; p < n_in; ++p) key_o[p] = h[key][perm_o[p]];
     counting_sort(key_o, nkeys_of(P, key), o.perm, o.seg);
     for (int64_t p = 0; p < n_in; ++p) o.perm[p] = perm_o[o.perm[p]];
+    o.inv.resize(n_in);
+    for (int64_t p = 0; p < n_in; ++p) o.inv[o.perm[p]] = (int32_t)p;
     o.other.resize(n_in);
     for (int64_t p = 0; p < n_in; ++p) o.other[p] = h[okey][o.perm[p]];
     // chunk starts inside each key segment (positions fit int32: n_in <= INT32_MAX)
@@ -677,6 +679,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       is.nother = nkeys_of(P, ks == 0 ? SE : SC);
       is.nchunks = ceil_div(is.nother, kStage1OtherChunk);
       L.add(is.perm, (size_t)n_in * 4);
+      L.add(is.inv, (size_t)n_in * 4);
       L.add(is.other, (size_t)n_in * 4);
       L.add(is.seg, (size_t)(is.nkeys + 1) * 8);
       L.add(is.cseg, (size_t)is.nkeys * (is.nchunks + 1) * 4);
@@ -712,6 +715,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       dev_input_sort(P->idx[key].as<int32_t>(), is.nkeys, P->idx[okey].as<int32_t>(), is.nother, n_in,
                      kStage1OtherChunk, is.perm.as<int32_t>(), is.other.as<int32_t>(),
                      is.seg.as<int64_t>(), is.cseg.as<int32_t>(), P->scratch, s);
+      dev_invert(is.perm.as<int32_t>(), n_in, is.inv.as<int32_t>(), s);
       is.built = true;
     }
     for (int xs = 0; xs < 2; ++xs) {
@@ -763,6 +767,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
         is.nother = nkeys_of(P, ks == 0 ? SE : SC);
         if (n_in > 0) {
           up.add(is.perm, std::move(sort_host[ks].perm));
+          up.add(is.inv, std::move(sort_host[ks].inv));
           up.add(is.other, std::move(sort_host[ks].other));
           up.add(is.seg, std::move(sort_host[ks].seg));
           up.add(is.cseg, std::move(sort_host[ks].cseg));
@@ -875,7 +880,8 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
   for (int k = 0; k < 2; ++k) {
     const InputSort &is = P->insort[k];
     if (!is.built) continue;
-    launch_pack_v<T>(V, ldv, is.perm.as<int32_t>(), P->n_in, R, wsp<T>(P, W.vs[k]), s, P->gate);
+    if (!P->prepacked)
+      launch_pack_v<T>(V, ldv, is.perm.as<int32_t>(), P->n_in, R, wsp<T>(P, W.vs[k]), s, P->gate);
     if (need_sv[k])
       launch_segsum<T>(is.seg.as<int64_t>(), wsp<T>(P, W.vs[k]), is.nkeys, R, wsp<T>(P, W.sv[k]), s);
   }
@@ -986,6 +992,8 @@ void execute_t(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ldt, c
     launch_fill<T>(U, P->n_out, nrhs * (int64_t)P->outputs.size(), ldu, T(0), s);
     return;
   }
+  GVT_REQUIRE(!P->prepacked || rhs_block(nrhs, P->max_rhs) == nrhs, GVT_ERR_ARG,
+              "internal: a prepacked input is one whole RHS block");
   int64_t r0 = 0;
   while (r0 < nrhs) {
     const int64_t left = nrhs - r0;
@@ -1032,6 +1040,45 @@ void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void 
     execute_t<float>(P, (const float *)D, ldd, (const float *)T, ldt, (const float *)V, nrhs, ldv,
                      (float *)U, ldu, s);
   check_launch(s);
+}
+
+namespace {
+template <class T> int pack_targets_t(gvt_plan *P, int R, void **vs, const int32_t **inv) {
+  layout_workspace<T>(P, R);
+  Workspace &W = P->ws[prec_slot<T>()];
+  int k = 0;
+  for (int ks = 0; ks < 2; ++ks) {
+    if (!P->insort[ks].built) continue;
+    vs[k] = wsp<T>(P, W.vs[ks]);
+    inv[k] = P->insort[ks].inv.as<int32_t>();
+    ++k;
+  }
+  return k;
+}
+}  // namespace
+
+int plan_pack_targets(gvt_plan *P, int prec, int R, void **vs, const int32_t **inv) {
+  GVT_REQUIRE(P && !P->dense && (prec == GVT_F64 || prec == GVT_F32), GVT_ERR_ARG,
+              "pack targets exist for gather-path plans in F64 or F32");
+  GVT_REQUIRE(rhs_block(R, P->max_rhs) == R, GVT_ERR_ARG, "R is not a whole RHS block of the plan");
+  return prec == GVT_F64 ? pack_targets_t<double>(P, R, vs, inv) : pack_targets_t<float>(P, R, vs, inv);
+}
+
+void plan_pack(gvt_plan *P, int prec, const void *V, int64_t ldv, int R, hipStream_t s) {
+  void *vs[2];
+  const int32_t *inv[2];
+  const int nk = plan_pack_targets(P, prec, R, vs, inv);
+  int k = 0;
+  for (int ks = 0; ks < 2 && k < nk; ++ks) {
+    if (!P->insort[ks].built) continue;
+    if (prec == GVT_F64)
+      launch_pack_v<double>((const double *)V, ldv, P->insort[ks].perm.as<int32_t>(), P->n_in, R,
+                            (double *)vs[k], s);
+    else
+      launch_pack_v<float>((const float *)V, ldv, P->insort[ks].perm.as<int32_t>(), P->n_in, R,
+                           (float *)vs[k], s);
+    ++k;
+  }
 }
 
 void plan_profile(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,

@@ -52,6 +52,9 @@ void dev_input_sort(const int32_t *key, int64_t nkeys, const int32_t *other, int
                     int64_t n, int64_t chunk, int32_t *perm, int32_t *other_out, int64_t *seg,
                     int32_t *cseg, DevScratch &sc, hipStream_t s);
 
+// inv[perm[p]] = p for p < n.
+void dev_invert(const int32_t *perm, int64_t n, int32_t *inv, hipStream_t s);
+
 // Output positions grouped by `row` (stable): perm[q] = output index, off[r]
 // the first position of row value r (off[nrows] = n).
 void dev_group_rows(const int32_t *row, int64_t nrows, int64_t n, int32_t *perm, int64_t *off,

@@ -179,6 +179,11 @@ __global__ void tile_keys_kernel(const int32_t *__restrict__ gx, const int32_t *
   }
 }
 
+__global__ void invert_kernel(const int32_t *__restrict__ perm, int64_t n, int32_t *__restrict__ inv) {
+  for (int64_t p = (int64_t)blockIdx.x * PB + threadIdx.x; p < n; p += (int64_t)gridDim.x * PB)
+    inv[perm[p]] = (int32_t)p;
+}
+
 __global__ void gather_kernel(const int32_t *__restrict__ src, const int32_t *__restrict__ idx,
                               int64_t n, int32_t *__restrict__ dst) {
   for (int64_t q = (int64_t)blockIdx.x * PB + threadIdx.x; q < n; q += (int64_t)gridDim.x * PB)
@@ -275,6 +280,12 @@ void dev_input_sort(const int32_t *key, int64_t nkeys, const int32_t *other, int
     input_sort_t<uint32_t>(key, nkeys, other, nother, n, chunk, perm, other_out, seg, cseg, sc, s);
   else
     input_sort_t<uint64_t>(key, nkeys, other, nother, n, chunk, perm, other_out, seg, cseg, sc, s);
+}
+
+void dev_invert(const int32_t *perm, int64_t n, int32_t *inv, hipStream_t s) {
+  if (n <= 0) return;
+  invert_kernel<<<grid_for(n), PB, 0, s>>>(perm, n, inv);
+  check_launch(s);
 }
 
 void dev_group_rows(const int32_t *row, int64_t nrows, int64_t n, int32_t *perm, int64_t *off,
