@@ -92,9 +92,9 @@ def cpu_baseline(p, seconds):
         "unit": "matvecs/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{done_rows} of {n_out} output rows of the FP64 Table-4b double loop "
-                  f"(each row sums all {len(p['c'])} training pairs) in {elapsed:.1f} s on "
-                  f"{threads} OpenMP threads; rate scaled to whole products",
+        "sample": f"{done_rows} output rows, in random batches drawn from the {n_out} of one product, "
+                  f"of the FP64 Table-4b double loop (each row sums all {len(p['c'])} training pairs) "
+                  f"in {elapsed:.1f} s on {threads} OpenMP threads; rate scaled to whole products",
     }
 
 
