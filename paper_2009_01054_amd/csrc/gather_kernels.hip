@@ -61,6 +61,13 @@ __global__ void segsum_kernel(const int64_t *__restrict__ seg, const T *__restri
 // ordered by other index, which keeps consecutive column loads close in the
 // cache.  The [64 x KB*R] result tile is staged in LDS and written
 // row-contiguously.
+// One wave instruction copying 64 x 16 bytes from global memory into LDS:
+// lane i reads 16 bytes at its own address g and they land at bytes 16i..16i+15
+// after l (l must be the same for the whole wave).
+__device__ __forceinline__ void lds_load_row16(const void *g, void *l) {
+  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)l, 16, 0, 0);
+}
+
 template <class T, int R, int KPW_ = 4> struct S1Cfg {
   static constexpr int KPW = KPW_;     // keys per wave
   static constexpr int KB = 4 * KPW;   // keys per block
@@ -172,16 +179,43 @@ __device__ __forceinline__ void stage1_lds_block(
   for (int kk = 0; kk < KPW; ++kk)
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[kk][r] = T(0);
+  // A full block whose 64 rows are consecutive F rows, 16-byte aligned, reads
+  // each staged column as one contiguous run: wave-wide global-to-LDS loads
+  // then fill CPI columns per instruction without registers.  Other blocks
+  // gather the column values through registers.
+  constexpr int VEC = 16 / (int)sizeof(T);  // values per 16-byte piece
+  constexpr int LPC = 64 / VEC;             // lanes per staged column
+  constexpr int CPI = 64 / LPC;             // columns per wave instruction
+  static_assert(OC % (4 * CPI) == 0, "whole instructions per wave and chunk");
+  bool dma = false;
+  if (rho0 + 64 <= nrows) {  // uniform
+    const int64_t y0 = rows[rho0];
+    dma = rows[rho0 + 63] - y0 == 63 && y0 % VEC == 0 && ldc % VEC == 0 &&
+          reinterpret_cast<uintptr_t>(Fc) % 16 == 0;
+  }
+  const int64_t dy0 = dma ? (int64_t)rows[rho0] : 0;
   for (int64_t c = 0; c < nch; ++c) {
     const int64_t o0 = c * OC;
     __syncthreads();  // the previous chunk's reads are done
-    // unconditional loads from clamped in-range addresses, so that they all
-    // issue before the first wait; out-of-range values are replaced by zero
+    if (dma) {
+      // columns past the last other index load an in-range column; no key
+      // segment refers to them
+      const int col_in = lane / LPC, piece = lane % LPC;
+      for (int q = w; q < OC / CPI; q += 4) {
+        const int64_t o = o0 + q * CPI + col_in;
+        lds_load_row16(Fc + (o < nother ? o : nother - 1) * ldc + dy0 + piece * VEC,
+                       lds + q * CPI * 64);
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+    } else {
+      // unconditional loads from clamped in-range addresses, so that they all
+      // issue before the first wait; out-of-range values are replaced by zero
 #pragma unroll 8
-    for (int oc = w; oc < OC; oc += 4) {
-      const int64_t o = o0 + oc;
-      const T v = Fc[(o < nother ? o : nother - 1) * ldc + fy];
-      lds[oc * 64 + lane] = (o < nother && frow_ok) ? v : T(0);
+      for (int oc = w; oc < OC; oc += 4) {
+        const int64_t o = o0 + oc;
+        const T v = Fc[(o < nother ? o : nother - 1) * ldc + fy];
+        lds[oc * 64 + lane] = (o < nother && frow_ok) ? v : T(0);
+      }
     }
     __syncthreads();
 #pragma unroll 1
@@ -228,7 +262,7 @@ __global__ __launch_bounds__(256) void stage1_lds_kernel(
     const int32_t *__restrict__ cseg, int64_t nch, const int32_t *__restrict__ other,
     const T *__restrict__ vs, int64_t nkeys, int64_t nother, T *__restrict__ S, int64_t ldS,
     const int *__restrict__ gate) {
-  __shared__ T lds[S1LdsCfg<T, R, KPW>::SIZE];
+  __shared__ __attribute__((aligned(16))) T lds[S1LdsCfg<T, R, KPW>::SIZE];
   if (gate && *gate == 0) return;
   stage1_lds_block<T, R, KPW>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys, nother, S, ldS,
                               blockIdx.x, blockIdx.y, lds);
@@ -285,13 +319,6 @@ template <class T> __device__ __forceinline__ T row16_sum(T v) {
   v += dpp_mov<0x141>(v);  // row_half_mirror: quad q <-> the mirrored quad of its half
   v += dpp_mov<0x140>(v);  // row_mirror: half <-> other half
   return v;
-}
-
-// One wave instruction copying 64 x 16 bytes from global memory into LDS:
-// lane i reads 16 bytes at its own address g and they land at bytes 16i..16i+15
-// after l (l must be the same for the whole wave).
-__device__ __forceinline__ void lds_load_row16(const void *g, void *l) {
-  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)l, 16, 0, 0);
 }
 
 // Largest value of x over the wave (x per 16-lane group), as a scalar.
