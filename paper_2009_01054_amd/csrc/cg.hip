@@ -386,7 +386,7 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
   // writes p in the key order of the iteration products as well, and those
   // products skip their pack; after the host sets p it is packed here.
   const int iprec = lowprec ? GVT_F32 : GVT_F64;
-  const bool fuse_pack = rhs_block(nlam, P->max_rhs) == nlam;
+  const bool fuse_pack = rhs_block(nlam, rhs_cap(P, iprec)) == nlam;
   PackTo<double> pk64{{nullptr, nullptr}, {nullptr, nullptr}};
   PackTo<float> pk32{{nullptr, nullptr}, {nullptr, nullptr}};
   if (fuse_pack) {
@@ -818,9 +818,10 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
   bool grouped = true;
   for (gvt_plan *P : ps.plans)
     grouped = grouped && P->direct && P->sbufs.size() == 1 && !P->sbufs[0].degenerate;
-  // RHS blocks of the grouped products (every plan of the set has the same cap)
-  const int maxR = ps.plans[0]->max_rhs;
-  const int Rmax = rhs_block(nlam, maxR);
+  // RHS blocks of the grouped products, per product precision (every plan of
+  // the set has the same caps); buffers are sized for the larger first block
+  const int maxR64 = ps.plans[0]->max_rhs[0], maxR32 = ps.plans[0]->max_rhs[1];
+  const int Rmax = std::max(rhs_block(nlam, maxR64), rhs_block(nlam, maxR32));
 
   // ---- device memory
   DevMem m_a, m_r, m_p, m_w, m_wraw, m_p32, m_w32, m_y, m_part, m_sc, m_lam, m_tmp, m_act, m_cmask,
@@ -873,8 +874,9 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
   GroupItem *it_pack = nullptr, *it_s1 = nullptr, *it_s2[kTileClasses] = {nullptr, nullptr};
   int64_t n_pack = 0, n_s1 = 0, n_s2[kTileClasses] = {0, 0};
   bool need_cls[kTileClasses] = {false, false};
-  for (int64_t r0 = 0; r0 < nlam; r0 += rhs_block(nlam - r0, maxR))
-    need_cls[tile_class(rhs_block(nlam - r0, maxR))] = true;
+  for (int maxR : {maxR64, maxR32})
+    for (int64_t r0 = 0; r0 < nlam; r0 += rhs_block(nlam - r0, maxR))
+      need_cls[tile_class(rhs_block(nlam - r0, maxR))] = true;
   if (grouped) {
     for (gvt_plan *P : ps.plans)
       for (int cls = 0; cls < kTileClasses; ++cls)
@@ -991,8 +993,11 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     GVT_HIP_CHECK(hipStreamSynchronize(s));
   }
 
-  // ---- products of every problem: out = K in (RHS blocks of at most maxR)
+  // ---- products of every problem: out = K in (RHS blocks of at most the
+  // precision's cap)
   auto grouped_product = [&](auto *desc, const uint8_t *mask) {
+    constexpr bool f64 = std::is_same<std::remove_pointer_t<decltype(desc)>, GroupDesc<double>>::value;
+    const int maxR = f64 ? maxR64 : maxR32;
     for (int64_t r0 = 0; r0 < nlam;) {
       const int R = rhs_block(nlam - r0, maxR);
       launch_group_pack(desc, it_pack, n_pack, R, r0, mask, s);

@@ -121,9 +121,11 @@ struct gvt_plan {
   // Set by a solver whose own kernels have already written the input vector
   // in key order (plan_pack_targets): the products then skip their pack.
   bool prepacked = false;
-  // Largest block of right-hand sides one product pass carries (1, 2, 4 or 8;
-  // the tuned kMaxRhsBlock, or GVT_MAX_RHS_BLOCK when the plan is built).
-  int max_rhs = 8;
+  // Largest block of right-hand sides one product pass carries (1, 2, 4 or
+  // 8), for FP64 [0] and FP32 [1] products: the tuned kMaxRhsBlockF64/F32,
+  // or GVT_MAX_RHS_BLOCK (both) / GVT_MAX_RHS_BLOCK_F64 / _F32 when the plan
+  // is built.
+  int max_rhs[2] = {8, 8};
   gvt::Workspace ws[2];  // per precision (F64, F32)
   hipStream_t last_stream = nullptr;
   // Theorem 1 cost of the chosen term program (FMA count per RHS), for reporting
@@ -148,6 +150,8 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
 // when built).  Synchronous host work and a copy: not allowed while `s` is
 // being captured.
 void plan_ensure_tiles(gvt_plan *P, int cls, hipStream_t s);
+// The RHS cap of a plan for products in precision prec (GVT_F64 or GVT_F32).
+inline int rhs_cap(const gvt_plan *P, int prec) { return P->max_rhs[prec == GVT_F64 ? 0 : 1]; }
 // RHS block of a product pass for `left` remaining right-hand sides.
 inline int rhs_block(int64_t left, int max_rhs) {
   const int64_t m = left < max_rhs ? left : max_rhs;

@@ -141,6 +141,14 @@ bool device_plan(int64_t n_in, int64_t n_out) {
   return n_in + n_out >= kDevicePlanMinPairs;
 }
 
+// Stage-2 tile classes a plan builds up front: those of the first RHS block
+// of `rhs_hint` right-hand sides under the FP64 and the FP32 cap.
+std::vector<int> hint_classes(const gvt_plan *P, int rhs_hint) {
+  const int a = tile_class(rhs_block(rhs_hint, P->max_rhs[0]));
+  const int b = tile_class(rhs_block(rhs_hint, P->max_rhs[1]));
+  return a == b ? std::vector<int>{a} : std::vector<int>{a, b};
+}
+
 // Host tasks of a plan build: on their own threads for large inputs, inline
 // for small ones (where starting a thread costs more than the task).
 struct TaskGroup {
@@ -349,9 +357,13 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
               "ORDER_A and ORDER_B are exclusive");
   refresh_launch_knobs();
   {
-    const char *ev = std::getenv("GVT_MAX_RHS_BLOCK");
-    const int mr = ev && *ev ? std::atoi(ev) : kMaxRhsBlock;
-    P->max_rhs = (mr == 1 || mr == 2 || mr == 4 || mr == 8) ? mr : 8;
+    const char *both = std::getenv("GVT_MAX_RHS_BLOCK");
+    const char *ev[2] = {std::getenv("GVT_MAX_RHS_BLOCK_F64"), std::getenv("GVT_MAX_RHS_BLOCK_F32")};
+    const int tuned[2] = {kMaxRhsBlockF64, kMaxRhsBlockF32};
+    for (int k = 0; k < 2; ++k) {
+      const int mr = ev[k] && *ev[k] ? std::atoi(ev[k]) : both && *both ? std::atoi(both) : tuned[k];
+      P->max_rhs[k] = (mr == 1 || mr == 2 || mr == 4 || mr == 8) ? mr : 8;
+    }
   }
   P->kinds.assign(kinds, kinds + nkinds);
   P->flags = flags;
@@ -670,7 +682,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   if (P->on_device) {
     // ---- sorts and tile orders on the device: sizes first (one allocation),
     // then the small host arrays, then the kernels, all queued on s --------
-    const int cls = tile_class(rhs_block(rhs_hint, P->max_rhs));
+    const std::vector<int> hcls = hint_classes(P, rhs_hint);
     DevLayout L;
     for (int ks = 0; ks < 2; ++ks) {
       if (!insort_needed[ks]) continue;
@@ -691,12 +703,18 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       L.add(oo.perm, (size_t)n_out * 4);
       L.add(oo.off, (size_t)(oo.nrows + 1) * 8);
     }
-    std::vector<std::pair<TermSpec *, TileGeom>> tiles;
+    struct DevTiles {
+      TermSpec *ts;
+      int cls;
+      TileGeom g;
+    };
+    std::vector<DevTiles> tiles;
     for (TermSpec &ts : P->terms)
-      if (ts.type == TG && n_out > 0) {
-        tiles.push_back({&ts, tile_geom(P, ts, cls)});
-        dev_tiles_layout(ts.tiles[cls], tiles.back().second, n_out, L);
-      }
+      if (ts.type == TG && n_out > 0)
+        for (int cls : hcls) {
+          tiles.push_back({&ts, cls, tile_geom(P, ts, cls)});
+          dev_tiles_layout(ts.tiles[cls], tiles.back().g, n_out, L);
+        }
     size_t sneed = 0;
     for (int ks = 0; ks < 2; ++ks)
       if (insort_needed[ks])
@@ -704,7 +722,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     for (int xs = 0; xs < 2; ++xs)
       if (outord_needed[xs] && n_out > 0) sneed = std::max(sneed, dev_group_rows_bytes(n_out));
     for (auto &tk : tiles)
-      sneed = std::max(sneed, dev_tiles_bytes(n_out, tk.second.d.ntiles * tk.second.d.rows_per_tile));
+      sneed = std::max(sneed, dev_tiles_bytes(n_out, tk.g.d.ntiles * tk.g.d.rows_per_tile));
     dev_reserve(P->scratch, sneed, s);
     L.commit(P->devblob);
     up.commit(P->blob);
@@ -725,14 +743,20 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
                      oo.off.as<int64_t>(), P->scratch, s);
       oo.built = true;
     }
-    for (auto &tk : tiles) dev_tiles_fill(P, *tk.first, tk.first->tiles[cls], tk.second, s);
+    for (auto &tk : tiles) dev_tiles_fill(P, *tk.ts, tk.ts->tiles[tk.cls], tk.g, s);
     tm.lap("device sorts queued");
   } else {
     // input sorts and stage-2 tiles are independent host work: one thread each
     {
-      std::vector<std::pair<TermSpec *, TileHost>> tiles;
+      struct HostTiles {
+        TermSpec *ts;
+        int cls;
+        TileHost t;
+      };
+      std::vector<HostTiles> tiles;
       for (TermSpec &ts : P->terms)
-        if (ts.type == TG && n_out > 0) tiles.push_back({&ts, TileHost{}});
+        if (ts.type == TG && n_out > 0)
+          for (int cls : hint_classes(P, rhs_hint)) tiles.push_back({&ts, cls, TileHost{}});
       TaskGroup tg(n_in + n_out >= (1 << 16));
       std::vector<std::exception_ptr> errs(tiles.size() + 2);
       auto guard = [&](size_t slot, auto fn) {
@@ -752,10 +776,9 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
           tg.run([&, xs]() {
             counting_sort(h[xs == 0 ? SA : SB], xs == 0 ? d_rows : t_rows, oo_perm[xs], oo_off[xs]);
           });
-      const int cls = tile_class(rhs_block(rhs_hint, P->max_rhs));
       for (size_t k = 0; k < tiles.size(); ++k)
         tg.run([&, k]() {
-          guard(2 + k, [&]() { tiles[k].second = compute_tiles(P, *tiles[k].first, cls); });
+          guard(2 + k, [&]() { tiles[k].t = compute_tiles(P, *tiles[k].ts, tiles[k].cls); });
         });
       tg.join();
       for (auto &ep : errs)
@@ -777,7 +800,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
         }
         is.built = true;
       }
-      for (auto &tk : tiles) install_tiles(tk.first->tiles[cls], std::move(tk.second), &up);
+      for (auto &tk : tiles) install_tiles(tk.ts->tiles[tk.cls], std::move(tk.t), &up);
       for (int xs = 0; xs < 2; ++xs) {
         if (!outord_needed[xs] || n_out == 0) continue;
         OutOrder &oo = P->outord[xs];
@@ -992,12 +1015,12 @@ void execute_t(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ldt, c
     launch_fill<T>(U, P->n_out, nrhs * (int64_t)P->outputs.size(), ldu, T(0), s);
     return;
   }
-  GVT_REQUIRE(!P->prepacked || rhs_block(nrhs, P->max_rhs) == nrhs, GVT_ERR_ARG,
+  GVT_REQUIRE(!P->prepacked || rhs_block(nrhs, P->max_rhs[prec_slot<T>()]) == nrhs, GVT_ERR_ARG,
               "internal: a prepacked input is one whole RHS block");
   int64_t r0 = 0;
   while (r0 < nrhs) {
     const int64_t left = nrhs - r0;
-    const int R = rhs_block(left, P->max_rhs);
+    const int R = rhs_block(left, P->max_rhs[prec_slot<T>()]);
     plan_ensure_tiles(P, tile_class(R), s);
     execute_block<T>(P, D, ldd, Tm, ldt, V + r0 * ldv, R, ldv, U + r0 * ldu, ldu, block_stride, s);
     r0 += R;
@@ -1060,7 +1083,7 @@ template <class T> int pack_targets_t(gvt_plan *P, int R, void **vs, const int32
 int plan_pack_targets(gvt_plan *P, int prec, int R, void **vs, const int32_t **inv) {
   GVT_REQUIRE(P && !P->dense && (prec == GVT_F64 || prec == GVT_F32), GVT_ERR_ARG,
               "pack targets exist for gather-path plans in F64 or F32");
-  GVT_REQUIRE(rhs_block(R, P->max_rhs) == R, GVT_ERR_ARG, "R is not a whole RHS block of the plan");
+  GVT_REQUIRE(rhs_block(R, rhs_cap(P, prec)) == R, GVT_ERR_ARG, "R is not a whole RHS block of the plan");
   return prec == GVT_F64 ? pack_targets_t<double>(P, R, vs, inv) : pack_targets_t<float>(P, R, vs, inv);
 }
 

@@ -2,35 +2,40 @@
 // each RHS class, and the keys each wave walks in stage 1.
 // Written by paper_2009_01054_amd/tune.py on gfx950; measured times (ms):
 //   LDS: ridge f64 x1; ridge f32 x1
-//          0: 0.1604, 0.0963  (score 1.000)
-//          1: 0.2088, 0.1136  (score 1.239)
+//          0: 0.1406, 0.0932  (score 1.000)
+//          1: 0.1855, 0.1087  (score 1.241)
 //   KPW: ridge f64 x1; ridge f32 x1
-//          1: 0.1479, 0.0894  (score 1.002)
-//          2: 0.1473, 0.0900  (score 1.003)
-//          4: 0.1480, 0.0978  (score 1.048)
+//          1: 0.1326, 0.0903  (score 1.000)
+//          2: 0.1338, 0.0911  (score 1.009)
+//          4: 0.1370, 0.0992  (score 1.066)
 //   R1: ridge f64 x1; ridge f32 x1
-//          8: 0.1803, 0.1262  (score 1.328)
-//         16: 0.1454, 0.0892  (score 1.002)
-//         32: 0.1446, 0.0898  (score 1.004)
-//         64: 0.1448, 0.0894  (score 1.002)
-//        128: 0.1458, 0.0899  (score 1.008)
-//   MAXR: ridge f64 x8; ridge f32 x8; batched f32 (64 problems, 8 RHS), per iteration
-//          2: 1.0566, 0.5943, 7.1096  (score 1.128)
-//          4: 1.1038, 0.4755, 6.1912  (score 1.015)
-//          8: 1.8292, 0.5896, 6.7899  (score 1.330)
+//          8: 0.1470, 0.1255  (score 1.295)
+//         16: 0.1288, 0.0881  (score 1.015)
+//         32: 0.1280, 0.0872  (score 1.007)
+//         64: 0.1278, 0.0871  (score 1.006)
+//        128: 0.1273, 0.0865  (score 1.000)
+//   MAXR64: ridge f64 x8; batched f64 (64 problems, 8 RHS), per iteration
+//          2: 0.8954, 12.2322  (score 1.016)
+//          4: 1.0977, 11.8597  (score 1.107)
+//          8: 1.8186, 16.2070  (score 1.666)
+//   MAXR32: ridge f32 x8; batched f32 (64 problems, 8 RHS), per iteration
+//          2: 0.6320, 9.5217  (score 1.433)
+//          4: 0.4744, 6.1803  (score 1.000)
+//          8: 0.5878, 6.6582  (score 1.155)
 //   R8: ridge f64 x8; ridge f32 x8; batched f32 (64 problems, 8 RHS), per iteration
-//          2: 1.1928, 0.6734, 8.1585  (score 1.261)
-//          4: 1.1614, 0.5266, 6.6703  (score 1.077)
-//          8: 1.1185, 0.5296, 8.1834  (score 1.140)
-//         16: 1.1263, 0.4825, 6.1314  (score 1.007)
-//         32: 1.1099, 0.4802, 6.1842  (score 1.003)
+//          2: 0.9743, 0.6738, 8.0772  (score 1.240)
+//          4: 0.9744, 0.5265, 6.7524  (score 1.076)
+//          8: 0.9818, 0.5225, 6.0088  (score 1.035)
+//         16: 0.9797, 0.4777, 6.2174  (score 1.016)
+//         32: 0.9794, 0.4745, 6.1962  (score 1.012)
 #pragma once
 
 namespace gvt {
-constexpr double kStage2TargetR1 = 64.0;
+constexpr double kStage2TargetR1 = 128.0;
 constexpr double kStage2TargetR8 = 32.0;
 constexpr int kStage1KeysPerWave = 1;
-constexpr int kMaxRhsBlock = 4;
+constexpr int kMaxRhsBlockF64 = 2;
+constexpr int kMaxRhsBlockF32 = 4;
 constexpr int kStage1LdsKeysPerWave = 4;
 constexpr double kStage1LdsMinReuse = 1e300;  // LDS-staged stage 1 off
 }  // namespace gvt

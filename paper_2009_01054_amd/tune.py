@@ -14,12 +14,13 @@ Stage 1 can also stage the F2 columns of a chunk of other indices in LDS
 and read them from there (worth it only if each column is reused enough).
 A product pass carries a block of up to 8 right-hand sides; larger blocks
 reuse every gathered element more often but hold more accumulators per lane,
-so the largest block a pass takes is tuned too.
+so the largest block a pass takes is tuned too, per product precision.
 
 This script sweeps the four knobs on synthetic workloads shaped like the
 library's benchmarks, through the library's environment overrides
 (GVT_STAGE1_LDS, GVT_STAGE1_KPW, GVT_STAGE2_TARGET_R1, GVT_STAGE2_TARGET_R8,
-GVT_MAX_RHS_BLOCK; all are read when a plan is built), and writes the winners as a C++
+GVT_MAX_RHS_BLOCK_F64, GVT_MAX_RHS_BLOCK_F32; all are read when a plan is built),
+and writes the winners as a C++
 header that ``build.py`` compiles into the library:
 
     python -m paper_2009_01054_amd.tune --out paper_2009_01054_amd/csrc/tuning.h
@@ -63,11 +64,12 @@ def _events_ms(torch, fn, reps):
 
 
 _KNOBS = {0: "GVT_STAGE2_TARGET_R1", 1: "GVT_STAGE2_TARGET_R8", "kpw": "GVT_STAGE1_KPW",
-          "lds": "GVT_STAGE1_LDS", "maxr": "GVT_MAX_RHS_BLOCK"}
+          "lds": "GVT_STAGE1_LDS", "maxr64": "GVT_MAX_RHS_BLOCK_F64", "maxr32": "GVT_MAX_RHS_BLOCK_F32"}
 
 
 def _set_target(cls, value):
-    os.environ[_KNOBS[cls]] = str(int(value)) if cls in ("kpw", "lds", "maxr") else repr(float(value))
+    os.environ[_KNOBS[cls]] = (str(int(value)) if cls in ("kpw", "lds", "maxr64", "maxr32")
+                               else repr(float(value)))
 
 
 def ridge_products(gvt, W, torch, nrhs, reps):
@@ -95,9 +97,10 @@ def ridge_products(gvt, W, torch, nrhs, reps):
     return out
 
 
-def batched_iterations(gvt, W, torch, nprob):
-    """Workload: per-iteration time of the batched FP32 ridge solver on the first
-    `nprob` problems of the 256-problem set (difference of two capped solves)."""
+def batched_iterations(gvt, W, torch, nprob, prec="f32"):
+    """Workload: per-iteration time of the batched ridge solver (FP32 or FP64
+    products) on the first `nprob` problems of the 256-problem set (difference
+    of two capped solves)."""
     dev = torch.device("cuda:0")
     shapes = W.config5_shapes()[:nprob]
     probs = [W.config5_problem(i, sh) for i, sh in enumerate(shapes)]
@@ -108,8 +111,8 @@ def batched_iterations(gvt, W, torch, nprob):
     def solve(iters):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        gvt.gvt_krr_cg_batched("kronecker", dp, lams, max_iter=iters, tol=1e-300, matvec_prec=gvt.F32,
-                               check_every=4)
+        gvt.gvt_krr_cg_batched("kronecker", dp, lams, max_iter=iters, tol=1e-300,
+                               matvec_prec=gvt.F32 if prec == "f32" else gvt.F64, check_every=4)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
@@ -117,7 +120,7 @@ def batched_iterations(gvt, W, torch, nprob):
         solve(3)
         return (solve(19) - solve(3)) / 16 * 1e3
 
-    return [(f"batched f32 ({nprob} problems, 8 RHS), per iteration", run)]
+    return [(f"batched {prec} ({nprob} problems, 8 RHS), per iteration", run)]
 
 
 def sweep(cls, candidates, workloads):
@@ -151,7 +154,8 @@ def write_header(path, results, device):
               f"constexpr double kStage2TargetR1 = {results['R1'][0]:.1f};",
               f"constexpr double kStage2TargetR8 = {results['R8'][0]:.1f};",
               f"constexpr int kStage1KeysPerWave = {int(results['KPW'][0])};",
-              f"constexpr int kMaxRhsBlock = {int(results['MAXR'][0])};",
+              f"constexpr int kMaxRhsBlockF64 = {int(results['MAXR64'][0])};",
+              f"constexpr int kMaxRhsBlockF32 = {int(results['MAXR32'][0])};",
               "constexpr int kStage1LdsKeysPerWave = 4;",
               "constexpr double kStage1LdsMinReuse = "
               + ("1.5;" if results["LDS"][0] else "1e300;  // LDS-staged stage 1 off"),
@@ -181,16 +185,20 @@ def main():
         gvt, W, torch, args.batched_problems)
     results = {}
     for key, cls, cands, wl in (("LDS", "lds", LDS_CANDIDATES, r1), ("KPW", "kpw", KPW_CANDIDATES, r1),
-                                ("R1", 0, R1_CANDIDATES, r1), ("MAXR", "maxr", MAXR_CANDIDATES, r8),
+                                ("R1", 0, R1_CANDIDATES, r1),
+                                ("MAXR64", "maxr64", MAXR_CANDIDATES,
+                                 r8[:1] + batched_iterations(gvt, W, torch, args.batched_problems, "f64")),
+                                ("MAXR32", "maxr32", MAXR_CANDIDATES, r8[1:]),
                                 ("R8", 1, R8_CANDIDATES, r8)):
         winner, table, score = sweep(cls, cands, wl)
         results[key] = (winner, table, score, [n for n, _ in wl])
-        if key == "MAXR":
-            _set_target(cls, winner)  # the R8 sweep runs with the chosen block cap
+        if key.startswith("MAXR"):
+            _set_target(cls, winner)  # the later sweeps run with the chosen block caps
         _log(f"[tune] class {key}: target {winner:g}")
     write_header(args.out, results, device)
     print(f"wrote {args.out}: stage-1 keys per wave {results['KPW'][0]}, R1 target {results['R1'][0]:g}, "
-          f"largest RHS block {results['MAXR'][0]}, R8 target {results['R8'][0]:g}")
+          f"largest RHS block F64 {results['MAXR64'][0]} / F32 {results['MAXR32'][0]}, "
+          f"R8 target {results['R8'][0]:g}")
 
 
 if __name__ == "__main__":
