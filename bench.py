@@ -62,14 +62,15 @@ def read_traffic(prec_name):
     return float(kv[key]) if key in kv else None
 
 
-def cpu_baseline(p, seconds):
-    """Oracle (plain FP64 double loop) on a bounded row sample of one product."""
+def cpu_baseline(p, seconds, threads=0):
+    """Oracle (plain FP64 double loop) on a bounded row sample of one product,
+    on `threads` OpenMP threads (0: all host threads)."""
     import numpy as np
 
     import oracle
 
     n_out = len(p["a"])
-    threads = oracle.max_threads()
+    threads = threads or oracle.max_threads()
     rng = np.random.default_rng(12345)
     rows = 512
     done_rows, elapsed = 0, 0.0
@@ -77,7 +78,7 @@ def cpu_baseline(p, seconds):
         sel = rng.choice(n_out, rows, replace=False)
         t0 = time.perf_counter()
         oracle.pairwise_matvec("kronecker", p["D"], p["T"], (p["a"], p["b"]), (p["c"], p["e"]),
-                               p["v"] if "v" in p else p["y"], rows=sel)
+                               p["v"] if "v" in p else p["y"], rows=sel, nthreads=threads)
         dt = time.perf_counter() - t0
         done_rows += rows
         elapsed += dt
@@ -386,8 +387,11 @@ def main():
     t0 = time.perf_counter()
     iters_total = 0
     rels = []
+    solve_ms = []  # each solve ends with a device synchronisation
     for _ in range(args.steps):
+        ts = time.perf_counter()
         _, it, rel, rc = solve(mprec)
+        solve_ms.append((time.perf_counter() - ts) * 1e3)
         iters_total += int(it.sum())
         rels.append(float(rel.max()))
     torch.cuda.synchronize()
@@ -453,11 +457,14 @@ def main():
     }
     log(f"[bench] stage ms {stage_ms}, matvec {matvec_ms:.4f} ms, plan {plan_ms:.1f} ms")
 
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu:
+        pv = {**p, "v": np.random.default_rng(7).standard_normal(n)}
         t_c = time.perf_counter()
-        cpu = cpu_baseline({**p, "v": np.random.default_rng(7).standard_normal(n)}, args.cpu_seconds)
+        cpu = cpu_baseline(pv, args.cpu_seconds)
         log(f"[bench] cpu baseline {cpu['value']:.4g} matvecs/s ({time.perf_counter() - t_c:.1f} s)")
+        cpu1 = cpu_baseline(pv, max(2.0, args.cpu_seconds / 3), threads=1)
+        log(f"[bench] cpu baseline, one core: {cpu1['value']:.4g} matvecs/s")
 
     out = {
         "metric": METRIC,
@@ -483,6 +490,9 @@ def main():
         },
         "krr_cg": {
             "seconds_per_solve": round(ms_per_step / 1e3, 6),
+            "solve_ms": {"median": round(float(np.median(solve_ms)), 4),
+                         "p10": round(float(np.percentile(solve_ms, 10)), 4),
+                         "p90": round(float(np.percentile(solve_ms, 90)), 4), "n": len(solve_ms)},
             "iterations": iters_total // args.steps,
             "true_relres_max": max(rels),
             "plan_ms": round(plan_ms, 3),
@@ -496,6 +506,7 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_one_core": cpu1,
         "kernel_source_sha": source_sha(),
     }
     print(json.dumps(out), flush=True)
