@@ -98,9 +98,12 @@ typedef struct gvt_plan *gvt_plan_t;
  * kinds[nkinds] (host): GVT_* kind codes; one output block per kind.
  * Homogeneous kinds need t_rows == d_rows and t_cols == d_cols (T is
  * ignored; pass the D shape).  Index arrays are device pointers, read once
- * (the call synchronises `stream`).  *plan receives an opaque handle owned by
- * the caller; release it with gvt_plan_destroy.  n_in == 0 or n_out == 0 is
- * valid (products then write zeros / nothing).
+ * (the call synchronises `stream`; the plan keeps no pointer to them).
+ * Index sets of 65536 pairs or more (n_in + n_out) are validated, counted
+ * and sorted on the device, smaller ones on the host; both give the same
+ * plan (environment GVT_PLAN_DEVICE=0/1 forces either).  *plan receives an
+ * opaque handle owned by the caller; release it with gvt_plan_destroy.
+ * n_in == 0 or n_out == 0 is valid (products then write zeros / nothing).
  * Errors: GVT_ERR_ARG, GVT_ERR_INDEX, GVT_ERR_KIND, GVT_ERR_HIP, GVT_ERR_NOMEM.
  */
 int gvt_plan_create(gvt_plan_t *plan, const int *kinds, int nkinds, int64_t d_rows,
@@ -121,11 +124,13 @@ int gvt_plan_destroy(gvt_plan_t plan);
  * NULL for homogeneous kinds).  V: n_in x nrhs, column stride ldv.  U: the
  * plan's nkinds output blocks stacked, block k at U + k*nrhs*ldu, each
  * n_out x nrhs with column stride ldu.  Asynchronous on `stream`.
- * Right-hand sides run in blocks of 8, 4, 2, 1; blocks of 1-2 and of 4-8
- * use stage-2 tiles of their own.  The plan holds those for one RHS
- * (gvt_plan_create); the first product with a block of 4 or more builds the
- * other set (host work and a synchronous copy), so that first call must not
- * be captured into a graph (GVT_ERR_ARG if it is).
+ * Right-hand sides run in blocks of 8, 4, 2, 1, capped per precision by
+ * tuned limits (FP64 2, FP32 4; environment GVT_MAX_RHS_BLOCK[_F64|_F32],
+ * read at plan creation); blocks of 1-2 and of 4-8 use stage-2 tiles of their
+ * own.  The plan holds those for one RHS (gvt_plan_create); the first
+ * product with a block of the other kind builds that set (device or host
+ * work, and allocation), so that first call must not be captured into a
+ * graph (GVT_ERR_ARG if it is).
  * Errors: GVT_ERR_ARG, GVT_ERR_UNSUPPORTED (GVT_BF16X3 on the gather path),
  * GVT_ERR_HIP, GVT_ERR_NOMEM.
  */
