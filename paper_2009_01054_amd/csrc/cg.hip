@@ -93,6 +93,8 @@ __global__ __launch_bounds__(RB) void cg_pw_kernel(const TW *__restrict__ wraw,
     double acc = 0.0;
     if (sc[l].state == CG_ACTIVE) {
       const double lm = lam[l];
+      // a few elements per thread: unrolled so that their loads are in flight together
+#pragma unroll 4
       for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)RNB * RB)
         acc += p[i + l * n] * cg_w(wraw, p, lm, i + l * n);
     }
@@ -122,6 +124,7 @@ __global__ __launch_bounds__(RB) void cg_update_kernel(double *__restrict__ a, i
       const double al = rho / pw;
       if (ok) {
         const double lm = lam[l];
+#pragma unroll 4
         for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)RNB * RB) {
           a[i + l * lda] += al * p[i + l * n];
           const double ri = r[i + l * n] - al * cg_w(wraw, p, lm, i + l * n);
@@ -174,13 +177,17 @@ __global__ __launch_bounds__(RB) void cg_p_kernel(double *__restrict__ p, float 
     const double rho_new = fold_partials(part_rr, nlam, l, sh);
     const double beta = rho_new / sc[l].rho_prev;
     if (isfinite(rho_new)) {
+      TV *__restrict__ vs0 = pk.vs[0];
+      TV *__restrict__ vs1 = pk.vs[1];
+      const int32_t *__restrict__ inv0 = pk.inv[0];
+      const int32_t *__restrict__ inv1 = pk.inv[1];
+#pragma unroll 4
       for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)RNB * RB) {
         const double pi = r[i + l * n] + beta * p[i + l * n];
         p[i + l * n] = pi;
         if (p32) p32[i + l * n] = (float)pi;
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-          if (pk.vs[k]) pk.vs[k][(int64_t)pk.inv[k][i] * nlam + l] = (TV)pi;
+        if (vs0) vs0[(int64_t)inv0[i] * nlam + l] = (TV)pi;
+        if (vs1) vs1[(int64_t)inv1[i] * nlam + l] = (TV)pi;
       }
     }
     if (rec) {
