@@ -211,6 +211,27 @@ __global__ __launch_bounds__(RB) void cg_p_kernel(double *__restrict__ p, float 
   }
 }
 
+// Initial per-system state from ||y||^2 (ynorm2) and the starting r.r (rho0,
+// or ||y||^2 for every system when rho0 is null); *run = any system active.
+__global__ void cg_init_kernel(CgScalars *sc, const double *__restrict__ ynorm2,
+                               const double *__restrict__ rho0, int nlam, double tol,
+                               int *__restrict__ run) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const double yn = sqrt(*ynorm2);
+  int any = 0;
+  for (int l = 0; l < nlam; ++l) {
+    CgScalars c;
+    c.pw = c.alpha = c.beta = c.rho_prev = 0.0;
+    c.iters = c.gate = c.pad0 = 0;
+    c.ynorm = yn;
+    c.rho = rho0 ? rho0[l] : *ynorm2;
+    c.state = !isfinite(yn) ? CG_BREAKDOWN : (sqrt(c.rho) / yn < tol ? CG_DONE : CG_ACTIVE);
+    any |= c.state == CG_ACTIVE;
+    sc[l] = c;
+  }
+  *run = any;
+}
+
 // r = y - (wraw + lambda a)  (true residual after an FP64 product w = K a); partial r.r
 __global__ __launch_bounds__(RB) void residual_kernel(const double *__restrict__ y,
                                                       const double *__restrict__ wraw,
@@ -323,8 +344,9 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
   double *part2 = part + (size_t)RNB * nlam;  // r.r partials (part holds p.w)
   CgScalars *sc = (CgScalars *)m_sc.ensure(sizeof(CgScalars) * nlam);
   double *lam = (double *)m_lam.ensure(nlam * 8);
-  double *tmp = (double *)m_tmp.ensure(64 * 8 + 256);
-  int *gate = reinterpret_cast<int *>(tmp + 64);  // run flag of the iteration products
+  // tmp: up to 65 fold results (||y||^2, then one per system); the products' run flag after them
+  double *tmp = (double *)m_tmp.ensure(128 * 8 + 256);
+  int *gate = reinterpret_cast<int *>(tmp + 128);  // run flag of the iteration products
   float *p32 = nullptr, *w32 = nullptr, *D32 = nullptr, *T32 = nullptr;
   GVT_HIP_CHECK(hipMemcpyAsync(lam, lambdas, nlam * 8, hipMemcpyHostToDevice, s));
   if (mprec == GVT_F32) {
@@ -343,16 +365,13 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
     plan_execute(P, GVT_F64, D, ldd, T, ldt, X, nlam, n, Y, n, s);
   };
 
-  // ||y||
+  // ||y||^2 into tmp[0]
   dot_partial_kernel<<<RNB, RB, 0, s>>>(y, 0, y, 0, n, 1, part);
   fold_kernel<<<1, RB, 0, s>>>(part, 1, tmp);
-  double ynorm2 = 0.0;
-  GVT_HIP_CHECK(hipMemcpyAsync(&ynorm2, tmp, 8, hipMemcpyDeviceToHost, s));
-  GVT_HIP_CHECK(hipStreamSynchronize(s));
-  const double ynorm = std::sqrt(ynorm2);
-  GVT_REQUIRE(std::isfinite(ynorm), GVT_ERR_BREAKDOWN, "non-finite labels");
 
-  // init: a = A0 or 0; r = y - (K + lambda) a; p = r; rho = r.r
+  // init: a = A0 or 0; r = y - (K + lambda) a; p = r; rho = r.r.  The states
+  // are set on the device; the host first reads them after the first block
+  // of iterations (until then it takes every system to be active).
   std::vector<CgScalars> hs(nlam);
   if (A0) {
     copy_cols_kernel<<<g1(n), 256, 0, s>>>(A0, lda0, A, lda, n, nlam, -1, nullptr);
@@ -365,22 +384,17 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
     copy_cols_kernel<<<g1(n), 256, 0, s>>>(A, lda, acopy, n, n, nlam, -1, nullptr);
     matvec64(acopy, wraw);
     residual_kernel<<<RNB, RB, 0, s>>>(y, wraw, A, lda, lam, n, nlam, r, part);
+    fold_kernel<<<nlam, RB, 0, s>>>(part, nlam, tmp + 1);
   } else {
+    // r = y for every system: its r.r is ||y||^2, summed above in the same order
     bcast_col_kernel<<<g1(n), 256, 0, s>>>(y, r, n, n, nlam);
-    dot_partial_kernel<<<RNB, RB, 0, s>>>(r, n, r, n, n, nlam, part);
   }
-  fold_kernel<<<nlam, RB, 0, s>>>(part, nlam, tmp);
-  std::vector<double> rho0(nlam);
-  GVT_HIP_CHECK(hipMemcpyAsync(rho0.data(), tmp, nlam * 8, hipMemcpyDeviceToHost, s));
   copy_cols_kernel<<<g1(n), 256, 0, s>>>(r, n, p, n, n, nlam, -1, nullptr);
-  GVT_HIP_CHECK(hipStreamSynchronize(s));
+  cg_init_kernel<<<1, 64, 0, s>>>(sc, tmp, A0 ? tmp + 1 : nullptr, nlam, tol, gate);
   for (int l = 0; l < nlam; ++l) {
     std::memset(&hs[l], 0, sizeof(CgScalars));
-    hs[l].rho = rho0[l];
-    hs[l].ynorm = ynorm;
-    hs[l].state = (std::sqrt(rho0[l]) / ynorm < tol) ? CG_DONE : CG_ACTIVE;
+    hs[l].state = CG_ACTIVE;
   }
-  GVT_HIP_CHECK(hipMemcpyAsync(sc, hs.data(), sizeof(CgScalars) * nlam, hipMemcpyHostToDevice, s));
 
   const int lowprec = mprec == GVT_F32 ? 1 : 0;
   // p32 (FP32 products) is kept in step with p by the direction kernel; after
@@ -437,7 +451,6 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
     packed = true;
     P->gate = nullptr;
   };
-  GVT_HIP_CHECK(hipMemsetD32Async(gate, 1, 1, s));
 
   // warm-up layout of plan workspaces (allocation must not happen inside a capture)
   // by running one iteration eagerly, then capture blocks of check_every iterations.
@@ -465,7 +478,7 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
       GVT_HIP_CHECK(hipStreamSynchronize(s));
       for (int l = 0; l < nlam; ++l) {
         if (hs[l].state != CG_PENDING) continue;
-        if (std::sqrt(rt[l]) / ynorm < tol) {
+        if (std::sqrt(rt[l]) / hs[l].ynorm < tol) {
           hs[l].state = CG_DONE;
         } else if (hs[l].iters >= max_iter) {
           hs[l].state = CG_MAXITER;
@@ -529,10 +542,11 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
   GVT_HIP_CHECK(hipMemcpyAsync(hs.data(), sc, sizeof(CgScalars) * nlam, hipMemcpyDeviceToHost, s));
   GVT_HIP_CHECK(hipStreamSynchronize(s));
   check_launch(s);
+  GVT_REQUIRE(std::isfinite(hs[0].ynorm), GVT_ERR_BREAKDOWN, "non-finite labels");
   bool all_done = true;
   for (int l = 0; l < nlam; ++l) {
     iters_out[l] = hs[l].iters;
-    relres_out[l] = std::sqrt(rt[l]) / ynorm;
+    relres_out[l] = std::sqrt(rt[l]) / hs[l].ynorm;
     if (hs[l].state == CG_BREAKDOWN) status = GVT_ERR_BREAKDOWN;
     if (hs[l].state != CG_DONE) all_done = false;
   }

@@ -315,6 +315,15 @@ def test_cg_blocks_past_convergence_skip_products(gvt, prec):
     assert torch.equal(A1, A2) and (it1 == it2).all() and (rel1 == rel2).all()
 
 
+def test_cg_non_finite_labels(gvt):
+    p = W.make_heterogeneous(94, 3, 20, 20, 200, 4, labels=True)
+    y = p["y"].copy()
+    y[17] = np.nan
+    with pytest.raises(gvt.GvtError) as ei:
+        gvt.gvt_krr_cg("kronecker", dev(p["D"]), dev(p["T"]), (idx(p["c"]), idx(p["e"])), dev(y), [1.0])
+    assert ei.value.code == -6 and "non-finite labels" in str(ei.value)
+
+
 def test_cg_not_converged_status(gvt):
     p = W.make_heterogeneous(94, 1, 30, 30, 400, 4, labels=True)
     A, iters, rel, rc = gvt.gvt_krr_cg("kronecker", dev(p["D"]), dev(p["T"]), (idx(p["c"]), idx(p["e"])),
