@@ -948,6 +948,7 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
         dsc.tileoff[cls] = tl.tileoff.as<int64_t>();
         dsc.tiley[cls] = tl.tiley.as<int32_t>();
         dsc.tilemax[cls] = tl.tilemax.as<int32_t>();
+        dsc.grow[cls] = tl.grow.as<uint8_t>();
         dsc.yrows[cls] = tl.yrows.as<int32_t>();
         dsc.perm_out[cls] = tl.perm.as<int32_t>();
         dsc.nyb[cls] = tl.nyb;

@@ -25,6 +25,10 @@ __device__ __forceinline__ int wave_id_uniform() {
 
 __device__ __forceinline__ int64_t ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+template <class T> struct Vec16;  // 16-byte vector of T
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+
 // ---------------------------------------------------------------------------
 // vs[p*R + r] = V[perm[p] + r*ldv]  (input vector gathered into key order)
 template <class T>
@@ -138,6 +142,77 @@ __global__ __launch_bounds__(256) void stage1_kernel(
   if (gate && *gate == 0) return;
   stage1_block<T, R, KPW>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, blockIdx.x, blockIdx.y,
                           stg);
+}
+
+// Stage 1 over a contiguous range of S rows (S row i is F2 row row0 + i), each
+// lane holding VPL = 16 / sizeof(T) consecutive rows: one 16-byte load per pair
+// and lane fetches the lane's rows of the F2 column, so a block covers 64 * VPL
+// rows with the instruction count of 64.  Each (row, key) sum runs over the
+// key's segment in the same order as in the one-row-per-lane walk, so the two
+// agree bit for bit.  nrows must be a multiple of VPL, row0, ldc and Fc
+// 16-byte aligned in units of T (the launcher checks and hands any ragged tail
+// rows to the one-row walk).
+template <class T, int R, int KPW>
+__global__ __launch_bounds__(256) void stage1_wide_kernel(
+    const T *__restrict__ Fc, int64_t ldc, int64_t row0, int64_t nrows,
+    const int64_t *__restrict__ seg, const int32_t *__restrict__ other, const T *__restrict__ vs,
+    int64_t nkeys, T *__restrict__ S, int64_t ldS, const int *__restrict__ gate) {
+  typedef typename Vec16<T>::type V;
+  constexpr int VPL = 16 / sizeof(T);
+  constexpr int KB = S1Cfg<T, R, KPW>::KB;
+  constexpr int W = KB * R;
+  constexpr int ROWS = 64 * VPL;
+  __shared__ T stg[ROWS * (W + 1)];
+  if (gate && *gate == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int w = wave_id_uniform();
+  const int64_t k0 = (int64_t)blockIdx.x * KB;
+  const int64_t rho0 = (int64_t)blockIdx.y * ROWS;
+  const int64_t rho = rho0 + lane * VPL;
+  // lanes past the last row load the block's first rows (in bounds) and store nothing
+  const T *fy = Fc + row0 + (rho < nrows ? rho : rho0);
+#pragma unroll 1
+  for (int kk = 0; kk < KPW; ++kk) {
+    const int64_t k = k0 + w * KPW + kk;
+    T acc[R][VPL];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < VPL; ++j) acc[r][j] = T(0);
+    if (k < nkeys) {
+      const int64_t p0 = seg[k], p1 = seg[k + 1];
+#pragma unroll 8
+      for (int64_t p = p0; p < p1; ++p) {
+        const V f = *reinterpret_cast<const V *>(fy + (int64_t)other[p] * ldc);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const T x = vs[p * R + r];
+#pragma unroll
+          for (int j = 0; j < VPL; ++j) acc[r][j] += f[j] * x;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < VPL; ++j)
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        stg[(lane * VPL + j) * (W + 1) + (w * KPW + kk) * R + r] = acc[r][j];
+  }
+  __syncthreads();
+  const int64_t kcount = (nkeys - k0) < KB ? (nkeys - k0) : KB;
+  const int width = (int)kcount * R;
+  for (int idx = threadIdx.x; idx < ROWS * W; idx += 256) {
+    const int rr = idx / W, cc = idx - rr * W;
+    const int64_t orow = rho0 + rr;
+    if (orow < nrows && cc < width) S[orow * ldS + k0 * R + cc] = stg[rr * (W + 1) + cc];
+  }
+  if (k0 + KB >= nkeys) {
+    const int64_t padw = ldS - nkeys * R;
+    for (int64_t idx = threadIdx.x; idx < ROWS * padw; idx += 256) {
+      const int64_t rr = idx / padw, cc = idx - rr * padw;
+      if (rho0 + rr < nrows) S[(rho0 + rr) * ldS + nkeys * R + cc] = T(0);
+    }
+  }
 }
 
 // Stage 1 with LDS-staged columns.  The keys of a block reference the same
@@ -328,10 +403,6 @@ __device__ __forceinline__ int wave_max_of_groups(int x) {
   return __builtin_amdgcn_readfirstlane(x);
 }
 
-template <class T> struct Vec16;  // 16-byte vector of T
-template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
-template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
-
 template <class T, int R> struct S2Cfg {
   static constexpr int LPO = 16;                   // lanes per F1 row / output
   static constexpr int NG = kStage2Rows;           // groups = F1 rows per tile (32)
@@ -346,6 +417,11 @@ template <class T, int R> struct S2Cfg {
   // four or more RHS (fewer passes, each re-copying the S tile)
   static constexpr int ACC = (sizeof(T) == 4 && R >= 4) ? 64 : 32;
   static constexpr int OPG = (ACC / R) > 4 ? ACC / R : 4;
+  // outputs per batch, whose S reads are in flight together; idle slots cost
+  // reads too (measured on the ridge workload: FP64 one RHS 72 us with 4 against
+  // 74 with 2 and 85 with 1; two RHS 149 us with 2 against 155 with 4; FP32 one
+  // RHS 52 us with 2 against 53-54 with 4, two RHS 90 against 99)
+  static constexpr int OB = (sizeof(T) == 8 && R == 1) ? 4 : 2;
   // tile row stride: 1 KB for FP64, 1 KB + 16 B for FP32 (measured on the
   // ridge workload: FP64 76 us unpadded against 92 us with 16 B, 82 us with
   // 128 B; FP32 52 us with 16 B against 62 us unpadded)
@@ -364,9 +440,9 @@ template <class T, int R>
 __device__ __forceinline__ void stage2_tile(
     const T *__restrict__ F1, int64_t ld1, int64_t nx, const int64_t *__restrict__ tileoff,
     const int32_t *__restrict__ tiley, const int32_t *__restrict__ tilemax,
-    const int32_t *__restrict__ yrows, const int32_t *__restrict__ perm, int nyb,
-    const T *__restrict__ S, int64_t ldS, int64_t nkeys, T coef, T *__restrict__ out, int64_t ldi,
-    int64_t ldr, int t, S2Smem<T, R> &sm) {
+    const uint8_t *__restrict__ grow, const int32_t *__restrict__ yrows,
+    const int32_t *__restrict__ perm, int nyb, const T *__restrict__ S, int64_t ldS, int64_t nkeys,
+    T coef, T *__restrict__ out, int64_t ldi, int64_t ldr, int t, S2Smem<T, R> &sm) {
   typedef S2Cfg<T, R> C;
   typedef typename Vec16<T>::type V16;
   constexpr int TROW = C::ROWE + C::PADE;
@@ -377,9 +453,12 @@ __device__ __forceinline__ void stage2_tile(
   const int xb = t / nyb;
   const int64_t y0 = tiley[2 * t], nyr = tiley[2 * t + 1];
   const int sub = threadIdx.x % C::LPO, grp = threadIdx.x / C::LPO;
-  const int64_t x = (int64_t)xb * C::NG + grp;
-  const int64_t qb = tileoff[(int64_t)t * (C::NG + 1) + grp];
-  const int cnt = (int)(tileoff[(int64_t)t * (C::NG + 1) + grp + 1] - qb);
+  // the tile's rows by descending output count: a wave's four groups carry
+  // similar counts, so few output slots run idle behind the wave's largest
+  const int gr = grow[(int64_t)t * C::NG + grp];
+  const int64_t x = (int64_t)xb * C::NG + gr;
+  const int64_t qb = tileoff[(int64_t)t * (C::NG + 1) + gr];
+  const int cnt = (int)(tileoff[(int64_t)t * (C::NG + 1) + gr + 1] - qb);
   const T *frow = F1 + (x < nx ? x : 0) * ld1;
   const int64_t nch = (nkeys + C::KC - 1) / C::KC;
   for (int pass0 = 0; pass0 < maxcnt; pass0 += C::OPG) {
@@ -425,30 +504,30 @@ __device__ __forceinline__ void stage2_tile(
         }
       __builtin_amdgcn_s_waitcnt(0);  // the tile rows have landed in LDS
       __syncthreads();
-      // outputs in batches of four behind one branch: slots past npass read tile
+      // outputs in batches of OB behind one branch: slots past npass read tile
       // row 0 (meta is 0 there) into accumulators that are never stored, so the
-      // reads of a batch's four outputs are in flight together at every step
-      static_assert(C::OPG % 4 == 0, "whole batches of four outputs");
+      // reads of a batch's outputs are in flight together at every step
+      static_assert(C::OPG % C::OB == 0, "whole batches of outputs");
 #pragma unroll
-      for (int o0 = 0; o0 < C::OPG; o0 += 4) {
+      for (int o0 = 0; o0 < C::OPG; o0 += C::OB) {
         if (o0 < npass) {
-          const T *trow[4];
+          const T *trow[C::OB];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int q = 0; q < C::OB; ++q) {
             const int o = o0 + q;
             const int mrow = kPack ? (int)((mp[o >> 2] >> (8 * (o & 3))) & 0xffu) : (int)meta[grp][o];
             trow[q] = tile + mrow * TROW + sub * C::EPL;
           }
 #pragma unroll
           for (int st = 0; st < C::STEPS; ++st) {
-            V16 sv[4][C::EPL / C::VEC];
+            V16 sv[C::OB][C::EPL / C::VEC];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < C::OB; ++q)
 #pragma unroll
               for (int u0 = 0; u0 < C::EPL / C::VEC; ++u0)
                 sv[q][u0] = *reinterpret_cast<const V16 *>(trow[q] + st * C::LPO * C::EPL + u0 * C::VEC);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < C::OB; ++q)
 #pragma unroll
               for (int u = 0; u < C::EPL; ++u)
                 acc[o0 + q][u % R] += dsl[st][u / R] * sv[q][u / C::VEC][u % C::VEC];
@@ -479,13 +558,13 @@ template <class T, int R>
 __global__ __launch_bounds__(kStage2Rows * 16) void stage2_kernel(
     const T *__restrict__ F1, int64_t ld1, int64_t nx, const int64_t *__restrict__ tileoff,
     const int32_t *__restrict__ tiley, const int32_t *__restrict__ tilemax,
-    const int32_t *__restrict__ yrows, const int32_t *__restrict__ perm, int nyb,
-    const T *__restrict__ S, int64_t ldS, int64_t nkeys, T coef, T *__restrict__ out, int64_t ldi,
-    int64_t ldr, const int *__restrict__ gate) {
+    const uint8_t *__restrict__ grow, const int32_t *__restrict__ yrows,
+    const int32_t *__restrict__ perm, int nyb, const T *__restrict__ S, int64_t ldS, int64_t nkeys,
+    T coef, T *__restrict__ out, int64_t ldi, int64_t ldr, const int *__restrict__ gate) {
   __shared__ S2Smem<T, R> sm;
   if (gate && *gate == 0) return;
-  stage2_tile<T, R>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out,
-                    ldi, ldr, blockIdx.x, sm);
+  stage2_tile<T, R>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef,
+                    out, ldi, ldr, blockIdx.x, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -518,9 +597,10 @@ template <class T, int R>
 __device__ __forceinline__ void stage2y_tile(
     const T *__restrict__ F1, int64_t ld1, const int64_t *__restrict__ tileoff,
     const int32_t *__restrict__ tilex, const int32_t *__restrict__ tilemax,
-    const int32_t *__restrict__ xrows, const int32_t *__restrict__ perm, int nxb,
-    const T *__restrict__ S, int64_t ldS, int64_t nsr, int64_t nkeys, T coef, T *__restrict__ out,
-    int64_t ldi, int64_t ldr, int t, S2ySmem<T, R> &sm) {
+    const uint8_t *__restrict__ grow, const int32_t *__restrict__ xrows,
+    const int32_t *__restrict__ perm, int nxb, const T *__restrict__ S, int64_t ldS, int64_t nsr,
+    int64_t nkeys, T coef, T *__restrict__ out, int64_t ldi, int64_t ldr, int t,
+    S2ySmem<T, R> &sm) {
   typedef S2yCfg<T, R> C;
   typedef typename Vec16<T>::type V16;
   constexpr int VEC = 16 / sizeof(T);
@@ -529,9 +609,10 @@ __device__ __forceinline__ void stage2y_tile(
   const int gb = t / nxb;
   const int64_t x0 = tilex[2 * t], nxr = tilex[2 * t + 1];
   const int sub = threadIdx.x % C::LPO, grp = threadIdx.x / C::LPO;
-  const int64_t yrow = (int64_t)gb * C::NG + grp;
-  const int64_t qb = tileoff[(int64_t)t * (C::NG + 1) + grp];
-  const int cnt = (int)(tileoff[(int64_t)t * (C::NG + 1) + grp + 1] - qb);
+  const int gr = grow[(int64_t)t * C::NG + grp];  // rows by descending output count
+  const int64_t yrow = (int64_t)gb * C::NG + gr;
+  const int64_t qb = tileoff[(int64_t)t * (C::NG + 1) + gr];
+  const int cnt = (int)(tileoff[(int64_t)t * (C::NG + 1) + gr + 1] - qb);
   const T *srow = S + (yrow < nsr ? yrow : 0) * ldS;
   const int64_t nch = (nkeys + C::KC - 1) / C::KC;
   // F1 rows start on 16-byte boundaries: whole pieces load as one vector
@@ -623,13 +704,14 @@ template <class T, int R>
 __global__ __launch_bounds__(kStage2Rows * 16) __attribute__((amdgpu_waves_per_eu(4))) void stage2y_kernel(
     const T *__restrict__ F1, int64_t ld1, const int64_t *__restrict__ tileoff,
     const int32_t *__restrict__ tilex, const int32_t *__restrict__ tilemax,
-    const int32_t *__restrict__ xrows, const int32_t *__restrict__ perm, int nxb,
-    const T *__restrict__ S, int64_t ldS, int64_t nsr, int64_t nkeys, T coef, T *__restrict__ out,
-    int64_t ldi, int64_t ldr, const int *__restrict__ gate) {
+    const uint8_t *__restrict__ grow, const int32_t *__restrict__ xrows,
+    const int32_t *__restrict__ perm, int nxb, const T *__restrict__ S, int64_t ldS, int64_t nsr,
+    int64_t nkeys, T coef, T *__restrict__ out, int64_t ldi, int64_t ldr,
+    const int *__restrict__ gate) {
   __shared__ S2ySmem<T, R> sm;
   if (gate && *gate == 0) return;
-  stage2y_tile<T, R>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out,
-                     ldi, ldr, blockIdx.x, sm);
+  stage2y_tile<T, R>(F1, ld1, tileoff, tilex, tilemax, grow, xrows, perm, nxb, S, ldS, nsr, nkeys, coef,
+                     out, ldi, ldr, blockIdx.x, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -835,7 +917,7 @@ __global__ __launch_bounds__(kStage2Rows * 16) void group_stage2_kernel(const Gr
   const GroupItem it = items[blockIdx.x];
   if (active && !active[it.p]) return;
   const GroupDesc<T> &d = desc[it.p];
-  stage2_tile<T, R>(d.F1, d.ld1, d.nx, d.tileoff[0], d.tiley[0], d.tilemax[0], d.yrows[0],
+  stage2_tile<T, R>(d.F1, d.ld1, d.nx, d.tileoff[0], d.tiley[0], d.tilemax[0], d.grow[0], d.yrows[0],
                     d.perm_out[0], (int)d.nyb[0], d.S, sbuf_row_ld<T>(d.nkeys, R), d.nkeys, T(1),
                     d.U + r0 * d.ldu, 1, d.ldu, it.li, sm);
 }
@@ -849,7 +931,8 @@ __global__ __launch_bounds__(kStage2Rows * 16) __attribute__((amdgpu_waves_per_e
   const GroupItem it = items[blockIdx.x];
   if (active && !active[it.p]) return;
   const GroupDesc<T> &d = desc[it.p];
-  stage2y_tile<T, R>(d.F1, d.ld1, d.tileoff[1], d.tiley[1], d.tilemax[1], d.yrows[1], d.perm_out[1],
+  stage2y_tile<T, R>(d.F1, d.ld1, d.tileoff[1], d.tiley[1], d.tilemax[1], d.grow[1], d.yrows[1],
+                     d.perm_out[1],
                      (int)d.nyb[1], d.S, sbuf_row_ld<T>(d.nkeys, R), d.nrows, d.nkeys, T(1),
                      d.U + r0 * d.ldu, 1, d.ldu, it.li, sm);
 }
@@ -883,10 +966,11 @@ static void stage1_rk(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nro
 
 // Launch knobs of stage 1: the tuned constants (tuning.h), overridable through
 // GVT_STAGE1_KPW (1, 2 or 4 keys per wave), GVT_STAGE1_LDS (0 / 1 forces the
-// LDS-staged walk off / on) and GVT_STAGE1_LDS_KPW (2, 4 or 8) for tuning
-// sweeps.  The environment is read when a plan is built, not per launch.
+// LDS-staged walk off / on), GVT_STAGE1_LDS_KPW (2, 4 or 8) and
+// GVT_STAGE1_WIDE (0 / 1: several rows per lane over contiguous rows) for
+// tuning sweeps.  The environment is read when a plan is built, not per launch.
 static std::atomic<int> g_s1_kpw{kStage1KeysPerWave}, g_s1_lds{-1},
-    g_s1_lds_kpw{kStage1LdsKeysPerWave};
+    g_s1_lds_kpw{kStage1LdsKeysPerWave}, g_s1_wide{kStage1Wide};
 
 void refresh_launch_knobs() {
   const char *e1 = std::getenv("GVT_STAGE1_KPW");
@@ -897,9 +981,12 @@ void refresh_launch_knobs() {
   const char *e3 = std::getenv("GVT_STAGE1_LDS_KPW");
   const int kl = e3 ? std::atoi(e3) : kStage1LdsKeysPerWave;
   g_s1_lds_kpw.store((kl == 2 || kl == 4 || kl == 8) ? kl : 4, std::memory_order_relaxed);
+  const char *e4 = std::getenv("GVT_STAGE1_WIDE");
+  g_s1_wide.store(e4 ? (std::atoi(e4) != 0) : kStage1Wide, std::memory_order_relaxed);
 }
 
 static int stage1_kpw() { return g_s1_kpw.load(std::memory_order_relaxed); }
+static bool stage1_use_wide() { return g_s1_wide.load(std::memory_order_relaxed) != 0; }
 
 template <class T, int R>
 static void stage1_r(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
@@ -940,11 +1027,58 @@ static bool stage1_use_lds(int64_t npairs, int64_t nkeys, int64_t nother, int kb
   return reuse >= kStage1LdsMinReuse;
 }
 
+template <class T, int R, int KPW>
+static void stage1_wide_rk(const T *Fc, int64_t ldc, int64_t row0, int64_t nrows, const int64_t *seg,
+                           const int32_t *other, const T *vs, int64_t nkeys, T *S, int64_t ldS,
+                           hipStream_t s, const int *gate) {
+  constexpr int ROWS = 64 * (16 / sizeof(T));
+  dim3 grid((unsigned)ceil_div(nkeys, S1Cfg<T, R, KPW>::KB), (unsigned)ceil_div(nrows, ROWS));
+  stage1_wide_kernel<T, R, KPW><<<grid, 256, 0, s>>>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, S,
+                                                      ldS, gate);
+}
+
 template <class T>
-void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
-                   const int32_t *cseg, int64_t nch, const int32_t *other, int64_t npairs,
-                   int64_t nother, const T *vs, int64_t nkeys, int R, T *S, int64_t ldS,
-                   hipStream_t s, const int *gate) {
+static void stage1_wide(const T *Fc, int64_t ldc, int64_t row0, int64_t nrows, const int64_t *seg,
+                        const int32_t *other, const T *vs, int64_t nkeys, int R, T *S, int64_t ldS,
+                        hipStream_t s, const int *gate) {
+#define GVT_S1W(RR, KK) stage1_wide_rk<T, RR, KK>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, S, ldS, s, gate)
+  switch (R * 16 + stage1_kpw()) {
+    case 16 + 1: GVT_S1W(1, 1); return;
+    case 16 + 2: GVT_S1W(1, 2); return;
+    case 16 + 4: GVT_S1W(1, 4); return;
+    case 32 + 1: GVT_S1W(2, 1); return;
+    case 32 + 2: GVT_S1W(2, 2); return;
+    case 32 + 4: GVT_S1W(2, 4); return;
+    case 64 + 1: GVT_S1W(4, 1); return;
+    case 64 + 2: GVT_S1W(4, 2); return;
+    case 64 + 4: GVT_S1W(4, 4); return;
+    case 128 + 1: GVT_S1W(8, 1); return;
+    case 128 + 2: GVT_S1W(8, 2); return;
+    case 128 + 4: GVT_S1W(8, 4); return;
+    default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in stage 1"};
+  }
+#undef GVT_S1W
+}
+
+template <class T>
+static void stage1_direct(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows,
+                          const int64_t *seg, const int32_t *other, const T *vs, int64_t nkeys, int R,
+                          T *S, int64_t ldS, hipStream_t s, const int *gate) {
+  if (nrows <= 0) return;
+  switch (R) {
+    case 1: stage1_r<T, 1>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
+    case 2: stage1_r<T, 2>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
+    case 4: stage1_r<T, 4>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
+    case 8: stage1_r<T, 8>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
+    default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in stage 1"};
+  }
+}
+
+template <class T>
+void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, int64_t row0,
+                   const int64_t *seg, const int32_t *cseg, int64_t nch, const int32_t *other,
+                   int64_t npairs, int64_t nother, const T *vs, int64_t nkeys, int R, T *S,
+                   int64_t ldS, hipStream_t s, const int *gate) {
   if (nrows <= 0 || nkeys <= 0) return;
   const int kl = stage1_lds_kpw(R);
   if (cseg && stage1_use_lds(npairs, nkeys, nother, 4 * kl)) {
@@ -963,13 +1097,22 @@ void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows,
     }
 #undef GVT_S1L
   }
-  switch (R) {
-    case 1: stage1_r<T, 1>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
-    case 2: stage1_r<T, 2>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
-    case 4: stage1_r<T, 4>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
-    case 8: stage1_r<T, 8>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
-    default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in stage 1"};
+  // contiguous rows: rows [h, h + nw) (aligned to VPL, a multiple of VPL) by the
+  // several-rows-per-lane walk, the few rows before and after by the one-row walk
+  constexpr int VPL = 16 / sizeof(T);
+  if (row0 >= 0 && stage1_use_wide() && ldc % VPL == 0 &&
+      reinterpret_cast<uintptr_t>(Fc) % 16 == 0) {
+    const int64_t h = std::min<int64_t>((VPL - row0 % VPL) % VPL, nrows);
+    const int64_t nw = (nrows - h) / VPL * VPL;
+    if (nw > 0) {
+      stage1_direct<T>(Fc, ldc, rows, h, seg, other, vs, nkeys, R, S, ldS, s, gate);
+      stage1_wide<T>(Fc, ldc, row0 + h, nw, seg, other, vs, nkeys, R, S + h * ldS, ldS, s, gate);
+      stage1_direct<T>(Fc, ldc, rows + h + nw, nrows - h - nw, seg, other, vs, nkeys, R,
+                       S + (h + nw) * ldS, ldS, s, gate);
+      return;
+    }
   }
+  stage1_direct<T>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, R, S, ldS, s, gate);
 }
 
 template <class T>
@@ -982,31 +1125,32 @@ void launch_colscale(const T *F, int64_t ldf, const int32_t *rows, int64_t nrows
 
 template <class T>
 void launch_stage2(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff, const int32_t *tiley,
-                   const int32_t *tilemax, int64_t ntiles, int nyb, const int32_t *yrows,
-                   const int32_t *perm, const T *S, int64_t ldS, int64_t nkeys, int R, T coef, T *out,
-                   int64_t ldi, int64_t ldr, hipStream_t s, const int *gate) {
+                   const int32_t *tilemax, const uint8_t *grow, int64_t ntiles, int nyb,
+                   const int32_t *yrows, const int32_t *perm, const T *S, int64_t ldS, int64_t nkeys,
+                   int R, T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s, const int *gate) {
   if (ntiles <= 0) return;
   dim3 grid((unsigned)ntiles);
   const int nt = S2Cfg<T, 1>::NT;
   switch (R) {
-    case 1: stage2_kernel<T, 1><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
-    case 2: stage2_kernel<T, 2><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
-    case 4: stage2_kernel<T, 4><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
-    case 8: stage2_kernel<T, 8><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
+    case 1: stage2_kernel<T, 1><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
+    case 2: stage2_kernel<T, 2><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
+    case 4: stage2_kernel<T, 4><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
+    case 8: stage2_kernel<T, 8><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
     default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in stage 2"};
   }
 }
 
 template <class T>
 void launch_stage2y(const T *F1, int64_t ld1, const int64_t *tileoff, const int32_t *tilex,
-                    const int32_t *tilemax, int64_t ntiles, int nxb, const int32_t *xrows,
-                    const int32_t *perm, const T *S, int64_t ldS, int64_t nsr, int64_t nkeys, int R,
-                    T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s, const int *gate) {
+                    const int32_t *tilemax, const uint8_t *grow, int64_t ntiles, int nxb,
+                    const int32_t *xrows, const int32_t *perm, const T *S, int64_t ldS, int64_t nsr,
+                    int64_t nkeys, int R, T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s,
+                    const int *gate) {
   if (ntiles <= 0) return;
   dim3 grid((unsigned)ntiles);
   switch (R) {
-    case 4: stage2y_kernel<T, 4><<<grid, kStage2Rows * 16, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate); break;
-    case 8: stage2y_kernel<T, 8><<<grid, kStage2Rows * 16, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate); break;
+    case 4: stage2y_kernel<T, 4><<<grid, kStage2Rows * 16, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, grow, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate); break;
+    case 8: stage2y_kernel<T, 8><<<grid, kStage2Rows * 16, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, grow, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate); break;
     default: throw Error{GVT_ERR_ARG, "internal: S-row grouped stage 2 needs a block of 4 or 8 RHS"};
   }
 }
@@ -1115,17 +1259,20 @@ void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64
   template void launch_pack_v<T>(const T *, int64_t, const int32_t *, int64_t, int, T *,          \
                                  hipStream_t, const int *);                                      \
   template void launch_segsum<T>(const int64_t *, const T *, int64_t, int, T *, hipStream_t);    \
-  template void launch_stage1<T>(const T *, int64_t, const int32_t *, int64_t, const int64_t *,  \
+  template void launch_stage1<T>(const T *, int64_t, const int32_t *, int64_t, int64_t,         \
+                                 const int64_t *,                                                \
                                  const int32_t *, int64_t, const int32_t *, int64_t, int64_t,    \
                                  const T *, int64_t, int, T *, int64_t, hipStream_t, const int *);\
   template void launch_colscale<T>(const T *, int64_t, const int32_t *, int64_t, const T *,      \
                                    int64_t, int, T *, int64_t, hipStream_t);                     \
   template void launch_stage2<T>(const T *, int64_t, int64_t, const int64_t *, const int32_t *,  \
-                                 const int32_t *, int64_t, int, const int32_t *, const int32_t *,\
+                                 const int32_t *, const uint8_t *, int64_t, int, const int32_t *,\
+                                 const int32_t *,                                                \
                                  const T *, int64_t, int64_t, int, T, T *, int64_t, int64_t,     \
                                  hipStream_t, const int *);                                      \
   template void launch_stage2y<T>(const T *, int64_t, const int64_t *, const int32_t *,          \
-                                  const int32_t *, int64_t, int, const int32_t *, const int32_t *,\
+                                  const int32_t *, const uint8_t *, int64_t, int,                 \
+                                  const int32_t *, const int32_t *,                               \
                                   const T *, int64_t, int64_t, int64_t, int, T, T *, int64_t,     \
                                   int64_t, hipStream_t, const int *);                             \
   template void launch_gemv<T>(const T *, int64_t, int64_t, int64_t, bool, const T *, int, T *,  \

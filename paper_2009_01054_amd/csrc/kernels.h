@@ -41,8 +41,11 @@ void refresh_launch_knobs();
 
 // Stage 1: the direct segment walk, or with LDS-staged columns when each
 // column is reused enough (cseg: per-key chunk starts, nch chunks; null = direct).
+// row0 >= 0 states that rows[i] = row0 + i for every i, which allows the walk
+// with several rows per lane; -1 otherwise.
 template <class T>
-void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
+void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, int64_t row0,
+                   const int64_t *seg,
                    const int32_t *cseg, int64_t nch, const int32_t *other, int64_t npairs,
                    int64_t nother, const T *vs, int64_t nkeys, int R, T *S, int64_t ldS,
                    hipStream_t s, const int *gate = nullptr);
@@ -51,15 +54,16 @@ void launch_colscale(const T *F, int64_t ldf, const int32_t *rows, int64_t nrows
                      int64_t nkeys, int R, T *S, int64_t ldS, hipStream_t s);
 template <class T>
 void launch_stage2(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff, const int32_t *tiley,
-                   const int32_t *tilemax, int64_t ntiles, int nyb, const int32_t *yrows,
-                   const int32_t *perm, const T *S, int64_t ldS, int64_t nkeys, int R, T coef, T *out,
-                   int64_t ldi, int64_t ldr, hipStream_t s, const int *gate = nullptr);
+                   const int32_t *tilemax, const uint8_t *grow, int64_t ntiles, int nyb,
+                   const int32_t *yrows, const int32_t *perm, const T *S, int64_t ldS, int64_t nkeys,
+                   int R, T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s,
+                   const int *gate = nullptr);
 // Stage 2 with S-row grouped tiles (blocks of R = 4 or 8 RHS).
 template <class T>
 void launch_stage2y(const T *F1, int64_t ld1, const int64_t *tileoff, const int32_t *tilex,
-                    const int32_t *tilemax, int64_t ntiles, int nxb, const int32_t *xrows,
-                    const int32_t *perm, const T *S, int64_t ldS, int64_t nsr, int64_t nkeys, int R,
-                    T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s,
+                    const int32_t *tilemax, const uint8_t *grow, int64_t ntiles, int nxb,
+                    const int32_t *xrows, const int32_t *perm, const T *S, int64_t ldS, int64_t nsr,
+                    int64_t nkeys, int R, T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s,
                     const int *gate = nullptr);
 template <class T>
 void launch_gemv(const T *F, int64_t ldf, int64_t nrows, int64_t ncols, bool sq, const T *sv, int R,
@@ -113,6 +117,7 @@ template <class T> struct GroupDesc {
   const int64_t *tileoff[2];
   const int32_t *tiley[2];
   const int32_t *tilemax[2];
+  const uint8_t *grow[2];  // per tile, the group row of each group (descending output count)
   const int32_t *yrows[2];
   const int32_t *perm_out[2];
   int64_t nyb[2];

@@ -40,6 +40,7 @@ struct SBufSpec {  // one stage-1 result S = scatter of F_sc by `key` with colum
   bool degenerate = false;       // key == other: S[y, k] = F[y, k] * segsum[k]
   std::vector<int32_t> rowmap;   // F_sc row -> compact S row (-1: not needed)
   std::vector<int32_t> rows;     // compact S rows -> F_sc row
+  int64_t row0 = -1;             // rows[i] = row0 + i for all i (contiguous), else -1
   DevMem d_rows;
   DevMem d_rowmap;               // device copy of rowmap (device-built plans)
 };
@@ -56,6 +57,8 @@ struct TileSet {
   DevMem tileoff;       // int64[ntiles * (kStage2Rows + 1)]: start of each x row in a tile
   DevMem tiley;         // int32[2 * ntiles]: first S row and S-row count of the tile
   DevMem tilemax;       // int32[ntiles]: largest per-row output count in the tile
+  DevMem grow;          // uint8[ntiles * kStage2Rows]: the group row each group of a tile
+                        // works on, rows by descending output count (ties by row)
   int64_t ntiles = 0;
   int nyb = 0;
   DevMem blob;          // the arrays' allocation when built after the plan

@@ -196,6 +196,7 @@ struct TileHost {
   int64_t ntiles = 0;
   std::vector<int32_t> perm, stg, tstg, tmax;
   std::vector<int64_t> toff;
+  std::vector<uint8_t> grow;
 };
 
 struct TileGeom {
@@ -246,15 +247,23 @@ TileHost compute_tiles(const gvt_plan *P, const TermSpec &ts, int cls) {
   o.toff.resize((size_t)ntiles * (kStage2Rows + 1));
   o.tstg.resize((size_t)2 * ntiles);
   o.tmax.assign(ntiles, 0);
+  o.grow.resize((size_t)ntiles * kStage2Rows);
   for (int64_t tt = 0; tt < ntiles; ++tt) {
     const int64_t sbk = tt % nsb;
     o.tstg[2 * tt] = (int32_t)std::min<int64_t>(sbk * sbs, nstg_rows);
     o.tstg[2 * tt + 1] = (int32_t)std::max<int64_t>(0, std::min<int64_t>(sbs, nstg_rows - sbk * sbs));
     for (int g2 = 0; g2 <= kStage2Rows; ++g2)
       o.toff[(size_t)tt * (kStage2Rows + 1) + g2] = sgk[(size_t)tt * kStage2Rows + g2];
+    int64_t c[kStage2Rows];
     for (int g2 = 0; g2 < kStage2Rows; ++g2) {
-      const int64_t c = sgk[(size_t)tt * kStage2Rows + g2 + 1] - sgk[(size_t)tt * kStage2Rows + g2];
-      o.tmax[tt] = std::max<int32_t>(o.tmax[tt], (int32_t)c);
+      c[g2] = sgk[(size_t)tt * kStage2Rows + g2 + 1] - sgk[(size_t)tt * kStage2Rows + g2];
+      o.tmax[tt] = std::max<int32_t>(o.tmax[tt], (int32_t)c[g2]);
+    }
+    // group order: rows by descending output count, ties by row
+    for (int g2 = 0; g2 < kStage2Rows; ++g2) {
+      int rank = 0;
+      for (int h = 0; h < kStage2Rows; ++h) rank += c[h] > c[g2] || (c[h] == c[g2] && h < g2);
+      o.grow[(size_t)tt * kStage2Rows + rank] = (uint8_t)g2;
     }
   }
   o.bsz = g.bsz;
@@ -290,13 +299,14 @@ void dev_tiles_layout(TileSet &tl, const TileGeom &g, int64_t n_out, DevLayout &
   L.add(tl.tileoff, (size_t)g.d.ntiles * (kStage2Rows + 1) * 8);
   L.add(tl.tiley, (size_t)g.d.ntiles * 2 * 4);
   L.add(tl.tilemax, (size_t)g.d.ntiles * 4);
+  L.add(tl.grow, (size_t)g.d.ntiles * kStage2Rows);
 }
 
 void dev_tiles_fill(gvt_plan *P, const TermSpec &ts, TileSet &tl, const TileGeom &g, hipStream_t s) {
   const SBufSpec &sb = P->sbufs[ts.sbuf];
   dev_tiles(P->idx[ts.x].as<int32_t>(), P->idx[ts.y].as<int32_t>(), sb.d_rowmap.as<int32_t>(),
             P->n_out, g.d, tl.perm.as<int32_t>(), tl.yrows.as<int32_t>(), tl.tileoff.as<int64_t>(),
-            tl.tiley.as<int32_t>(), tl.tilemax.as<int32_t>(), P->scratch, s);
+            tl.tiley.as<int32_t>(), tl.tilemax.as<int32_t>(), tl.grow.as<uint8_t>(), P->scratch, s);
   tl.built = true;
 }
 
@@ -313,6 +323,7 @@ void install_tiles(TileSet &tl, TileHost &&o, Uploads *up) {
   u.add(tl.tileoff, std::move(o.toff));
   u.add(tl.tiley, std::move(o.tstg));
   u.add(tl.tilemax, std::move(o.tmax));
+  u.add(tl.grow, std::move(o.grow));
   if (!up) local.commit(tl.blob);
   tl.built = true;
 }
@@ -635,6 +646,8 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     sb.rows.clear();
     for (int64_t r = 0; r < (int64_t)sb.rowmap.size(); ++r)
       if (sb.rowmap[r] >= 0) { sb.rowmap[r] = (int32_t)sb.rows.size(); sb.rows.push_back((int32_t)r); }
+    sb.row0 = !sb.rows.empty() && sb.rows.back() - sb.rows.front() + 1 == (int64_t)sb.rows.size()
+                  ? sb.rows.front() : -1;
     up.add(sb.d_rows, sb.rows);
     if (P->on_device) up.add(sb.d_rowmap, sb.rowmap);
     need_insort(sb.key);  // scatter segments, or the segment sums of a degenerate buffer
@@ -945,7 +958,7 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
       Fc = Ft;
       ldc = rows_of(P, sb.fsc);
     }
-    launch_stage1<T>(Fc, ldc, sb.d_rows.as<int32_t>(), (int64_t)sb.rows.size(),
+    launch_stage1<T>(Fc, ldc, sb.d_rows.as<int32_t>(), (int64_t)sb.rows.size(), sb.row0,
                      is.seg.as<int64_t>(), is.cseg.as<int32_t>(), is.nchunks,
                      is.other.as<int32_t>(), P->n_in, is.nother, wsp<T>(P, W.vs[ks]), is.nkeys, R, S,
                      ldS, s, P->gate);
@@ -962,13 +975,15 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
       const TileSet &tl = t.tiles[tile_class(R)];
       if (tile_class(R) == 0)
         launch_stage2<T>(F[t.fdot], ldF[t.fdot], rows_of(P, t.fdot), tl.tileoff.as<int64_t>(),
-                         tl.tiley.as<int32_t>(), tl.tilemax.as<int32_t>(), tl.ntiles, tl.nyb,
-                         tl.yrows.as<int32_t>(), tl.perm.as<int32_t>(), wsp<T>(P, W.sbuf[t.sbuf]),
+                         tl.tiley.as<int32_t>(), tl.tilemax.as<int32_t>(), tl.grow.as<uint8_t>(),
+                         tl.ntiles, tl.nyb, tl.yrows.as<int32_t>(), tl.perm.as<int32_t>(),
+                         wsp<T>(P, W.sbuf[t.sbuf]),
                          sbuf_ld<T>(P, t.sbuf, R), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s,
                          P->gate);
       else
         launch_stage2y<T>(F[t.fdot], ldF[t.fdot], tl.tileoff.as<int64_t>(), tl.tiley.as<int32_t>(),
-                          tl.tilemax.as<int32_t>(), tl.ntiles, tl.nyb, tl.yrows.as<int32_t>(),
+                          tl.tilemax.as<int32_t>(), tl.grow.as<uint8_t>(), tl.ntiles, tl.nyb,
+                          tl.yrows.as<int32_t>(),
                           tl.perm.as<int32_t>(), wsp<T>(P, W.sbuf[t.sbuf]), sbuf_ld<T>(P, t.sbuf, R),
                           (int64_t)sb.rows.size(), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s,
                           P->gate);

@@ -62,13 +62,14 @@ void dev_group_rows(const int32_t *row, int64_t nrows, int64_t n, int32_t *perm,
 
 // Stage-2 tiles (see compute_tiles): outputs keyed by (tile, group row) with
 // grp / stg the grouped and staged coordinate of each output (grp from `gx`,
-// stg from `sy` through `rowmap`, swapped when `swap`).
+// stg from `sy` through `rowmap`, swapped when `swap`); `grow` lists each
+// tile's group rows by descending output count (ties by row).
 struct TileDims {
   int64_t ntiles, nsb, sbs, nstg_rows, rows_per_tile;
   bool swap;  // class 1: group by compact S row, stage F1 rows
 };
 void dev_tiles(const int32_t *gx, const int32_t *sy, const int32_t *rowmap, int64_t n,
                const TileDims &td, int32_t *perm, int32_t *yrows, int64_t *toff, int32_t *tiley,
-               int32_t *tilemax, DevScratch &sc, hipStream_t s);
+               int32_t *tilemax, uint8_t *grow, DevScratch &sc, hipStream_t s);
 
 }  // namespace gvt

@@ -190,6 +190,24 @@ __global__ void gather_kernel(const int32_t *__restrict__ src, const int32_t *__
     dst[q] = src[idx[q]];
 }
 
+// Group order of each tile: 32 lanes per tile (two tiles per wave), lane g
+// holds row g's output count and finds its rank among the tile's rows by
+// descending count, ties by row, by reading the other counts across lanes.
+__global__ void tile_order_kernel(const int64_t *__restrict__ sgk, int64_t ntiles,
+                                  uint8_t *__restrict__ grow) {
+  static_assert(kStage2Rows == 32 && PB % 64 == 0, "two tiles per wave");
+  const int lane = threadIdx.x & 63, g = lane & 31, half = lane & 32;
+  const int64_t t = ((int64_t)blockIdx.x * PB + threadIdx.x) / kStage2Rows;
+  const bool live = t < ntiles;
+  const int c = live ? (int)(sgk[t * kStage2Rows + g + 1] - sgk[t * kStage2Rows + g]) : 0;
+  int rank = 0;
+  for (int h = 0; h < kStage2Rows; ++h) {
+    const int ch = __shfl(c, half | h, 64);
+    rank += ch > c || (ch == c && h < g);
+  }
+  if (live) grow[t * kStage2Rows + rank] = (uint8_t)g;
+}
+
 __global__ void tile_meta_kernel(const int64_t *__restrict__ sgk, TileDims td,
                                  int64_t *__restrict__ toff, int32_t *__restrict__ tiley,
                                  int32_t *__restrict__ tilemax) {
@@ -304,7 +322,8 @@ void dev_group_rows(const int32_t *row, int64_t nrows, int64_t n, int32_t *perm,
 
 void dev_tiles(const int32_t *gx, const int32_t *sy, const int32_t *rowmap, int64_t n,
                const TileDims &td, int32_t *perm, int32_t *yrows, int64_t *toff, int32_t *tiley,
-               int32_t *tilemax, DevScratch &sc, hipStream_t s) {
+               int32_t *tilemax, uint8_t *grow, DevScratch &sc, hipStream_t s) {
+  GVT_REQUIRE(td.rows_per_tile == kStage2Rows, GVT_ERR_ARG, "internal: stage-2 tile height");
   const int64_t nb = td.ntiles * td.rows_per_tile;
   const size_t tb = sort_temp_bytes<uint32_t>(n);
   const size_t o_kout = align256(n * 4), o_stg = o_kout + align256(n * 4);
@@ -321,6 +340,8 @@ void dev_tiles(const int32_t *gx, const int32_t *sy, const int32_t *rowmap, int6
   gather_kernel<<<grid_for(n), PB, 0, s>>>(stg, perm, n, yrows);
   bucket_starts_kernel<uint32_t><<<grid_for(n + 1), PB, 0, s>>>(kout, n, 0, nb, sgk);
   tile_meta_kernel<<<grid_for(td.ntiles), PB, 0, s>>>(sgk, td, toff, tiley, tilemax);
+  tile_order_kernel<<<(unsigned)std::max<int64_t>(1, ceil_div(td.ntiles, PB / kStage2Rows)), PB, 0, s>>>(
+      sgk, td.ntiles, grow);
   check_launch(s);
 }
 

@@ -2,38 +2,42 @@
 // each RHS class, and the keys each wave walks in stage 1.
 // Written by paper_2009_01054_amd/tune.py on gfx950; measured times (ms):
 //   LDS: ridge f64 x1; ridge f32 x1
-//          0: 0.1406, 0.0932  (score 1.000)
-//          1: 0.1855, 0.1087  (score 1.241)
+//          0: 0.1234, 0.0863  (score 1.000)
+//          1: 0.1857, 0.1080  (score 1.372)
+//   WIDE: ridge f64 x1; ridge f32 x1
+//          0: 0.1308, 0.0890  (score 1.109)
+//          1: 0.1153, 0.0820  (score 1.000)
 //   KPW: ridge f64 x1; ridge f32 x1
-//          1: 0.1326, 0.0903  (score 1.000)
-//          2: 0.1338, 0.0911  (score 1.009)
-//          4: 0.1370, 0.0992  (score 1.066)
+//          1: 0.1139, 0.0811  (score 1.000)
+//          2: 0.1170, 0.0821  (score 1.020)
+//          4: 0.1194, 0.0958  (score 1.113)
 //   R1: ridge f64 x1; ridge f32 x1
-//          8: 0.1470, 0.1255  (score 1.295)
-//         16: 0.1288, 0.0881  (score 1.015)
-//         32: 0.1280, 0.0872  (score 1.007)
-//         64: 0.1278, 0.0871  (score 1.006)
-//        128: 0.1273, 0.0865  (score 1.000)
+//          8: 0.1321, 0.1189  (score 1.322)
+//         16: 0.1137, 0.0810  (score 1.013)
+//         32: 0.1134, 0.0813  (score 1.013)
+//         64: 0.1123, 0.0810  (score 1.006)
+//        128: 0.1123, 0.0801  (score 1.000)
 //   MAXR64: ridge f64 x8; batched f64 (64 problems, 8 RHS), per iteration
-//          2: 0.8954, 12.2322  (score 1.016)
-//          4: 1.0977, 11.8597  (score 1.107)
-//          8: 1.8186, 16.2070  (score 1.666)
+//          2: 0.8539, 12.1869  (score 1.010)
+//          4: 1.0600, 11.9544  (score 1.114)
+//          8: 1.7510, 16.1165  (score 1.663)
 //   MAXR32: ridge f32 x8; batched f32 (64 problems, 8 RHS), per iteration
-//          2: 0.6320, 9.5217  (score 1.433)
-//          4: 0.4744, 6.1803  (score 1.000)
-//          8: 0.5878, 6.6582  (score 1.155)
+//          2: 0.6126, 9.3197  (score 1.358)
+//          4: 0.4995, 6.1947  (score 1.000)
+//          8: 0.5837, 6.8196  (score 1.134)
 //   R8: ridge f64 x8; ridge f32 x8; batched f32 (64 problems, 8 RHS), per iteration
-//          2: 0.9743, 0.6738, 8.0772  (score 1.240)
-//          4: 0.9744, 0.5265, 6.7524  (score 1.076)
-//          8: 0.9818, 0.5225, 6.0088  (score 1.035)
-//         16: 0.9797, 0.4777, 6.2174  (score 1.016)
-//         32: 0.9794, 0.4745, 6.1962  (score 1.012)
+//          2: 0.9196, 0.6984, 8.1135  (score 1.244)
+//          4: 0.9154, 0.5480, 6.7489  (score 1.077)
+//          8: 0.9180, 0.5335, 6.0530  (score 1.031)
+//         16: 0.9234, 0.4905, 6.1530  (score 1.010)
+//         32: 0.9268, 0.4886, 6.1764  (score 1.011)
 #pragma once
 
 namespace gvt {
 constexpr double kStage2TargetR1 = 128.0;
-constexpr double kStage2TargetR8 = 32.0;
+constexpr double kStage2TargetR8 = 16.0;
 constexpr int kStage1KeysPerWave = 1;
+constexpr int kStage1Wide = 1;
 constexpr int kMaxRhsBlockF64 = 2;
 constexpr int kMaxRhsBlockF32 = 4;
 constexpr int kStage1LdsKeysPerWave = 4;

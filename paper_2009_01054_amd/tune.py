@@ -11,14 +11,16 @@ walks key segments with one wave per key; the number of keys each wave walks
 trades waves in flight against per-wave work.
 
 Stage 1 can also stage the F2 columns of a chunk of other indices in LDS
-and read them from there (worth it only if each column is reused enough).
+and read them from there (worth it only if each column is reused enough), and
+over a contiguous range of S rows a lane can hold 16 bytes of consecutive rows
+(one vector load per pair) instead of one row.
 A product pass carries a block of up to 8 right-hand sides; larger blocks
 reuse every gathered element more often but hold more accumulators per lane,
 so the largest block a pass takes is tuned too, per product precision.
 
-This script sweeps the four knobs on synthetic workloads shaped like the
+This script sweeps these knobs on synthetic workloads shaped like the
 library's benchmarks, through the library's environment overrides
-(GVT_STAGE1_LDS, GVT_STAGE1_KPW, GVT_STAGE2_TARGET_R1, GVT_STAGE2_TARGET_R8,
+(GVT_STAGE1_LDS, GVT_STAGE1_WIDE, GVT_STAGE1_KPW, GVT_STAGE2_TARGET_R1, GVT_STAGE2_TARGET_R8,
 GVT_MAX_RHS_BLOCK_F64, GVT_MAX_RHS_BLOCK_F32; all are read when a plan is built),
 and writes the winners as a C++
 header that ``build.py`` compiles into the library:
@@ -45,6 +47,7 @@ R8_CANDIDATES = (2.0, 4.0, 8.0, 16.0, 32.0)
 KPW_CANDIDATES = (1, 2, 4)
 MAXR_CANDIDATES = (2, 4, 8)
 LDS_CANDIDATES = (0, 1)  # stage 1: direct walk, or LDS-staged columns where reused >= 1.5 times
+WIDE_CANDIDATES = (0, 1)  # stage 1 over contiguous S rows: one row per lane, or 16 bytes of rows
 
 
 def _log(*a):
@@ -64,11 +67,11 @@ def _events_ms(torch, fn, reps):
 
 
 _KNOBS = {0: "GVT_STAGE2_TARGET_R1", 1: "GVT_STAGE2_TARGET_R8", "kpw": "GVT_STAGE1_KPW",
-          "lds": "GVT_STAGE1_LDS", "maxr64": "GVT_MAX_RHS_BLOCK_F64", "maxr32": "GVT_MAX_RHS_BLOCK_F32"}
+          "lds": "GVT_STAGE1_LDS", "wide": "GVT_STAGE1_WIDE", "maxr64": "GVT_MAX_RHS_BLOCK_F64", "maxr32": "GVT_MAX_RHS_BLOCK_F32"}
 
 
 def _set_target(cls, value):
-    os.environ[_KNOBS[cls]] = (str(int(value)) if cls in ("kpw", "lds", "maxr64", "maxr32")
+    os.environ[_KNOBS[cls]] = (str(int(value)) if cls in ("kpw", "lds", "wide", "maxr64", "maxr32")
                                else repr(float(value)))
 
 
@@ -154,6 +157,7 @@ def write_header(path, results, device):
               f"constexpr double kStage2TargetR1 = {results['R1'][0]:.1f};",
               f"constexpr double kStage2TargetR8 = {results['R8'][0]:.1f};",
               f"constexpr int kStage1KeysPerWave = {int(results['KPW'][0])};",
+              f"constexpr int kStage1Wide = {int(results['WIDE'][0])};",
               f"constexpr int kMaxRhsBlockF64 = {int(results['MAXR64'][0])};",
               f"constexpr int kMaxRhsBlockF32 = {int(results['MAXR32'][0])};",
               "constexpr int kStage1LdsKeysPerWave = 4;",
@@ -184,7 +188,8 @@ def main():
     r8 = ridge_products(gvt, W, torch, 8, max(2, args.reps // 4)) + batched_iterations(
         gvt, W, torch, args.batched_problems)
     results = {}
-    for key, cls, cands, wl in (("LDS", "lds", LDS_CANDIDATES, r1), ("KPW", "kpw", KPW_CANDIDATES, r1),
+    for key, cls, cands, wl in (("LDS", "lds", LDS_CANDIDATES, r1), ("WIDE", "wide", WIDE_CANDIDATES, r1),
+                                ("KPW", "kpw", KPW_CANDIDATES, r1),
                                 ("R1", 0, R1_CANDIDATES, r1),
                                 ("MAXR64", "maxr64", MAXR_CANDIDATES,
                                  r8[:1] + batched_iterations(gvt, W, torch, args.batched_problems, "f64")),
@@ -192,8 +197,8 @@ def main():
                                 ("R8", 1, R8_CANDIDATES, r8)):
         winner, table, score = sweep(cls, cands, wl)
         results[key] = (winner, table, score, [n for n, _ in wl])
-        if key.startswith("MAXR"):
-            _set_target(cls, winner)  # the later sweeps run with the chosen block caps
+        if key.startswith("MAXR") or key == "WIDE":
+            _set_target(cls, winner)  # the later sweeps run with the chosen walk and block caps
         _log(f"[tune] class {key}: target {winner:g}")
     write_header(args.out, results, device)
     print(f"wrote {args.out}: stage-1 keys per wave {results['KPW'][0]}, R1 target {results['R1'][0]:g}, "

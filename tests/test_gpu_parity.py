@@ -448,22 +448,55 @@ def test_cg_batched_warm_start_and_cap(gvt):
 
 
 @pytest.mark.parametrize("env", [{"GVT_STAGE1_KPW": "1"}, {"GVT_STAGE1_KPW": "2"},
+                                 {"GVT_STAGE1_WIDE": "1", "GVT_STAGE1_KPW": "1"},
+                                 {"GVT_STAGE1_WIDE": "1", "GVT_STAGE1_KPW": "2"},
+                                 {"GVT_STAGE1_WIDE": "1", "GVT_STAGE1_KPW": "4"},
                                  {"GVT_STAGE1_LDS": "1", "GVT_STAGE1_LDS_KPW": "2"},
                                  {"GVT_STAGE1_LDS": "1", "GVT_STAGE1_LDS_KPW": "4"},
                                  {"GVT_STAGE1_LDS": "1", "GVT_STAGE1_LDS_KPW": "8"}])
 @pytest.mark.parametrize("nrhs", [1, 3, 8])
 def test_stage1_variants_are_bitwise_equal(gvt, env, nrhs, monkeypatch):
-    # every stage-1 variant (direct walk with 1, 2 or 4 keys per wave; LDS-staged columns with
-    # 2, 4 or 8) sums a key's segment in the same order, so products agree exactly; the
-    # other-index range (700) spans several staged chunks of 128 and a ragged last one
+    # every stage-1 variant (direct walk with 1, 2 or 4 keys per wave, one row or 16 bytes of
+    # rows per lane; LDS-staged columns with 2, 4 or 8) sums a key's segment in the same
+    # order, so products agree exactly; the other-index range (700) spans several staged
+    # chunks of 128 and a ragged last one
     p = W.make_heterogeneous(99, 0, 900, 700, 30000, 8)
     Dd, Td = dev(p["D"]), dev(p["T"])
     c, e = idx(p["c"]), idx(p["e"])
     v = dev(np.random.default_rng(5).standard_normal((len(p["c"]), nrhs)))
     monkeypatch.setenv("GVT_STAGE1_LDS", "0")
+    monkeypatch.setenv("GVT_STAGE1_WIDE", "0")
     monkeypatch.setenv("GVT_STAGE1_KPW", "4")
     ref = gvt.gvt_matvec(Dd, Td, (c, e), (c, e), v)
     for k, val in env.items():
         monkeypatch.setenv(k, val)
     got = gvt.gvt_matvec(Dd, Td, (c, e), (c, e), v)
     assert torch.equal(got, ref)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("lo,hi", [(0, 700), (3, 600), (2, 403), (5, 8), (1, 2)])
+@pytest.mark.parametrize("order", [2, 4])
+def test_stage1_wide_rows_bitwise(gvt, prec, lo, hi, order, monkeypatch):
+    # the several-rows-per-lane walk covers the 16-byte aligned part of a contiguous S-row
+    # range [lo, hi) and the one-row walk the rows before and after it: both orders of the
+    # stages, ranges with and without ragged ends, and ranges too short for the wide walk
+    r = np.random.default_rng([7, lo, hi])
+    dt = torch.float64 if prec == "f64" else torch.float32
+    D = W.gaussian_kernel(r.standard_normal((700, 3)))
+    T = W.gaussian_kernel(r.standard_normal((700, 3)))
+    c = r.integers(0, 700, 20000).astype(np.int32)
+    e = r.integers(0, 700, 20000).astype(np.int32)
+    a = r.integers(lo, hi, 9000).astype(np.int32)
+    b = r.integers(lo, hi, 9000).astype(np.int32)
+    a[:hi - lo] = np.arange(lo, hi)  # every row of the range occurs: contiguous S rows
+    b[:hi - lo] = np.arange(lo, hi)
+    Dd, Td = dev(D, dt), dev(T, dt)
+    for nrhs in (1, 2, 4, 8):
+        v = dev(r.standard_normal((len(c), nrhs)), dt)
+        args = ((idx(a), idx(b)), (idx(c), idx(e)), v)
+        monkeypatch.setenv("GVT_STAGE1_WIDE", "0")
+        ref = gvt.gvt_pairwise_matvec(["kronecker"], Dd, Td, *args, flags=order)
+        monkeypatch.setenv("GVT_STAGE1_WIDE", "1")
+        got = gvt.gvt_pairwise_matvec(["kronecker"], Dd, Td, *args, flags=order)
+        assert torch.equal(got, ref), nrhs
