@@ -273,8 +273,9 @@ int gvt_plan_profile(gvt_plan_t plan, int prec, const void *D, int64_t ldd, cons
  * gvt_plan_info — diagnostic: info[11] (host) receives the Theorem 1 FMA count
  * of the plan's term program per right-hand side, whether it is a
  * complete-data plan, the numbers of distinct terms and stage-1 buffers, the
- * first buffer's row and key counts and key index (2 = drug, 3 = target, -1 =
- * none), and the unique counts of a, b, c, e (Table 1).
+ * first buffer's row and key counts (rows: those stage 1 computes, which may
+ * close small gaps in the rows the terms read) and key index (2 = drug, 3 =
+ * target, -1 = none), and the unique counts of a, b, c, e (Table 1).
  */
 int gvt_plan_info(gvt_plan_t plan, double *info);
 

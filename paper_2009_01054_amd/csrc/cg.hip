@@ -892,8 +892,9 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
   // (p32 -> w32), [2] FP64 residual product (w -> wraw)
   GroupDesc<double> *dd_it = nullptr, *dd_res = nullptr;
   GroupDesc<float> *df_it = nullptr;
-  GroupItem *it_pack = nullptr, *it_s1 = nullptr, *it_s2[kTileClasses] = {nullptr, nullptr};
-  int64_t n_pack = 0, n_s1 = 0, n_s2[kTileClasses] = {0, 0};
+  GroupItem *it_pack = nullptr, *it_s1 = nullptr, *it_s1f = nullptr,
+            *it_s2[kTileClasses] = {nullptr, nullptr};
+  int64_t n_pack = 0, n_s1 = 0, n_s1f = 0, n_s2[kTileClasses] = {0, 0};
   bool need_cls[kTileClasses] = {false, false};
   for (int maxR : {maxR64, maxR32})
     for (int64_t r0 = 0; r0 < nlam; r0 += rhs_block(nlam - r0, maxR))
@@ -939,7 +940,6 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
       dsc.other = is.other.as<int32_t>();
       dsc.nkeys = is.nkeys;
       dsc.S = (T *)(S_base + S_off[i]);
-      dsc.nkb = group_stage1_blocks(is.nkeys, 1);  // key blocks of one row block
       dsc.F1 = F[t.fdot];
       dsc.ld1 = ldF[t.fdot];
       dsc.nx = rows_of(P, t.fdot);
@@ -955,14 +955,16 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
       }
       dsc.U = U;
       dsc.ldu = pb[i].n;
+      return group_stage1_setup(dsc, sb.row0);  // after nkeys and nrows
     };
+    std::vector<int64_t> s1blocks(nprob), s1blocks32(nprob, 0);  // stage-1 blocks per precision
     for (int i = 0; i < nprob; ++i) {
       const Prob &b = pb[i];
-      fill(h64[i], i, b.D, b.ldd, b.T, b.ldt, (const double *)(p + b.voff), wraw + b.voff);
+      s1blocks[i] = fill(h64[i], i, b.D, b.ldd, b.T, b.ldt, (const double *)(p + b.voff), wraw + b.voff);
       fill(hres[i], i, b.D, b.ldd, b.T, b.ldt, (const double *)(w + b.voff), wraw + b.voff);
       if (mprec == GVT_F32)
-        fill(h32[i], i, (const float *)b.D32, b.d, (const float *)b.T32, b.t,
-             (const float *)(p32 + b.voff), w32 + b.voff);
+        s1blocks32[i] = fill(h32[i], i, (const float *)b.D32, b.d, (const float *)b.T32, b.t,
+                             (const float *)(p32 + b.voff), w32 + b.voff);
     }
     // work lists: problems by decreasing Theorem 1 cost, each problem's blocks in order
     std::vector<int> order(nprob);
@@ -970,14 +972,15 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
       return ps.plans[x]->cost_fma > ps.plans[y]->cost_fma;
     });
-    std::vector<GroupItem> hp, h1, h2[kTileClasses];
+    std::vector<GroupItem> hp, h1, h1f, h2[kTileClasses];
     for (int i : order) {
       const GroupDesc<double> &g = h64[i];
       const int64_t np = group_pack_blocks(g.n_in);
-      const int64_t n1 = group_stage1_blocks(g.nkeys, g.nrows);
-      GVT_REQUIRE(np < (1 << 30) && n1 < (1 << 30), GVT_ERR_ARG, "problem too large");
+      const int64_t n1 = s1blocks[i], n1f = s1blocks32[i];
+      GVT_REQUIRE(np < (1 << 30) && n1 < (1 << 30) && n1f < (1 << 30), GVT_ERR_ARG, "problem too large");
       for (int64_t k = 0; k < np; ++k) hp.push_back({i, (int32_t)k});
       for (int64_t k = 0; k < n1; ++k) h1.push_back({i, (int32_t)k});
+      for (int64_t k = 0; k < n1f; ++k) h1f.push_back({i, (int32_t)k});
       const TermSpec &t = ps.plans[i]->terms[ps.plans[i]->outputs[0][0].first];
       for (int cls = 0; cls < kTileClasses; ++cls) {
         if (!need_cls[cls]) continue;
@@ -988,6 +991,7 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     }
     n_pack = (int64_t)hp.size();
     n_s1 = (int64_t)h1.size();
+    n_s1f = (int64_t)h1f.size();
     n_s2[0] = (int64_t)h2[0].size();
     n_s2[1] = (int64_t)h2[1].size();
     const size_t dsz64 = sizeof(GroupDesc<double>) * nprob, dsz32 = sizeof(GroupDesc<float>) * nprob;
@@ -1000,13 +1004,16 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     if (mprec == GVT_F32)
       GVT_HIP_CHECK(hipMemcpyAsync(df_it, h32.data(), dsz32, hipMemcpyHostToDevice, s));
     GroupItem *ib =
-        (GroupItem *)m_items.ensure(sizeof(GroupItem) * (n_pack + n_s1 + n_s2[0] + n_s2[1] + 1));
+        (GroupItem *)m_items.ensure(sizeof(GroupItem) * (n_pack + n_s1 + n_s1f + n_s2[0] + n_s2[1] + 1));
     it_pack = ib;
     it_s1 = ib + n_pack;
-    it_s2[0] = ib + n_pack + n_s1;
-    it_s2[1] = ib + n_pack + n_s1 + n_s2[0];
+    it_s1f = ib + n_pack + n_s1;
+    it_s2[0] = ib + n_pack + n_s1 + n_s1f;
+    it_s2[1] = ib + n_pack + n_s1 + n_s1f + n_s2[0];
     GVT_HIP_CHECK(hipMemcpyAsync(it_pack, hp.data(), sizeof(GroupItem) * n_pack, hipMemcpyHostToDevice, s));
     GVT_HIP_CHECK(hipMemcpyAsync(it_s1, h1.data(), sizeof(GroupItem) * n_s1, hipMemcpyHostToDevice, s));
+    if (n_s1f)
+      GVT_HIP_CHECK(hipMemcpyAsync(it_s1f, h1f.data(), sizeof(GroupItem) * n_s1f, hipMemcpyHostToDevice, s));
     for (int cls = 0; cls < kTileClasses; ++cls)
       if (n_s2[cls])
         GVT_HIP_CHECK(hipMemcpyAsync(it_s2[cls], h2[cls].data(), sizeof(GroupItem) * n_s2[cls],
@@ -1023,7 +1030,7 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     for (int64_t r0 = 0; r0 < nlam;) {
       const int R = rhs_block(nlam - r0, maxR);
       launch_group_pack(desc, it_pack, n_pack, R, r0, mask, s);
-      launch_group_stage1(desc, it_s1, n_s1, R, mask, s);
+      launch_group_stage1(desc, f64 ? it_s1 : it_s1f, f64 ? n_s1 : n_s1f, R, mask, s);
       launch_group_stage2(desc, it_s2[tile_class(R)], n_s2[tile_class(R)], R, r0, mask, s);
       r0 += R;
     }

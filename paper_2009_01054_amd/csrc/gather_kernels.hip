@@ -147,30 +147,45 @@ __global__ __launch_bounds__(256) void stage1_kernel(
 // Stage 1 over a contiguous range of S rows (S row i is F2 row row0 + i), each
 // lane holding VPL = 16 / sizeof(T) consecutive rows: one 16-byte load per pair
 // and lane fetches the lane's rows of the F2 column, so a block covers 64 * VPL
-// rows with the instruction count of 64.  Each (row, key) sum runs over the
-// key's segment in the same order as in the one-row-per-lane walk, so the two
-// agree bit for bit.  nrows must be a multiple of VPL, row0, ldc and Fc
-// 16-byte aligned in units of T (the launcher checks and hands any ragged tail
-// rows to the one-row walk).
+// rows with the load instructions of 64.  The loads need only T's own
+// alignment (the hardware serves dword-aligned 16-byte global loads).  The lane
+// that straddles the end of the range loads the range's last VPL rows and keeps
+// the ones that are its own, so no load leaves the range (nrows >= VPL).  Each
+// (row, key) sum runs over the key's segment in the same order as in the
+// one-row walk, so the two agree bit for bit.
+template <class T> struct Vec16u;  // 16 bytes of T at T's alignment
+template <> struct Vec16u<double> { typedef double type __attribute__((ext_vector_type(2), aligned(8))); };
+template <> struct Vec16u<float> { typedef float type __attribute__((ext_vector_type(4), aligned(4))); };
+
+template <class T, int R, int KPW> struct S1WideCfg {
+  static constexpr int VPL = 16 / sizeof(T);  // rows per lane
+  static constexpr int ROWS = 64 * VPL;       // rows per block
+  static constexpr int KB = 4 * KPW;          // keys per block
+  static constexpr int W = KB * R;            // staged columns
+  static constexpr int STG = ROWS * (W + 1);  // staged elements
+};
+
 template <class T, int R, int KPW>
-__global__ __launch_bounds__(256) void stage1_wide_kernel(
-    const T *__restrict__ Fc, int64_t ldc, int64_t row0, int64_t nrows,
-    const int64_t *__restrict__ seg, const int32_t *__restrict__ other, const T *__restrict__ vs,
-    int64_t nkeys, T *__restrict__ S, int64_t ldS, const int *__restrict__ gate) {
-  typedef typename Vec16<T>::type V;
-  constexpr int VPL = 16 / sizeof(T);
-  constexpr int KB = S1Cfg<T, R, KPW>::KB;
-  constexpr int W = KB * R;
-  constexpr int ROWS = 64 * VPL;
-  __shared__ T stg[ROWS * (W + 1)];
-  if (gate && *gate == 0) return;
+__device__ __forceinline__ void stage1_wide_block(const T *__restrict__ Fc, int64_t ldc, int64_t row0,
+                                                  int64_t nrows, const int64_t *__restrict__ seg,
+                                                  const int32_t *__restrict__ other,
+                                                  const T *__restrict__ vs, int64_t nkeys,
+                                                  T *__restrict__ S, int64_t ldS, int64_t kb, int64_t rb,
+                                                  T *stg) {
+  typedef S1WideCfg<T, R, KPW> C;
+  typedef typename Vec16u<T>::type V;
+  constexpr int VPL = C::VPL, KB = C::KB, W = C::W, ROWS = C::ROWS;
   const int lane = threadIdx.x & 63;
   const int w = wave_id_uniform();
-  const int64_t k0 = (int64_t)blockIdx.x * KB;
-  const int64_t rho0 = (int64_t)blockIdx.y * ROWS;
+  const int64_t k0 = kb * KB;
+  const int64_t rho0 = rb * ROWS;
   const int64_t rho = rho0 + lane * VPL;
-  // lanes past the last row load the block's first rows (in bounds) and store nothing
-  const T *fy = Fc + row0 + (rho < nrows ? rho : rho0);
+  // the lane's rows, or the range's last VPL rows for the lane that straddles
+  // its end (window rows before `shift` belong to the previous lane) and for
+  // lanes past it (shift = VPL: they keep nothing)
+  const int64_t base = rho + VPL <= nrows ? rho : nrows - VPL;
+  const int shift = (int)(rho - base < VPL ? rho - base : VPL);
+  const T *fy = Fc + row0 + base;
 #pragma unroll 1
   for (int kk = 0; kk < KPW; ++kk) {
     const int64_t k = k0 + w * KPW + kk;
@@ -192,11 +207,19 @@ __global__ __launch_bounds__(256) void stage1_wide_kernel(
         }
       }
     }
+    T *st = stg + (w * KPW + kk) * R;
+    if (shift == 0) {  // every lane but the one at the ragged end
 #pragma unroll
-    for (int j = 0; j < VPL; ++j)
+      for (int j = 0; j < VPL; ++j)
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        stg[(lane * VPL + j) * (W + 1) + (w * KPW + kk) * R + r] = acc[r][j];
+        for (int r = 0; r < R; ++r) st[(lane * VPL + j) * (W + 1) + r] = acc[r][j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < VPL; ++j)
+        if (j >= shift)
+#pragma unroll
+          for (int r = 0; r < R; ++r) st[(lane * VPL + j - shift) * (W + 1) + r] = acc[r][j];
+    }
   }
   __syncthreads();
   const int64_t kcount = (nkeys - k0) < KB ? (nkeys - k0) : KB;
@@ -213,6 +236,17 @@ __global__ __launch_bounds__(256) void stage1_wide_kernel(
       if (rho0 + rr < nrows) S[(rho0 + rr) * ldS + nkeys * R + cc] = T(0);
     }
   }
+}
+
+template <class T, int R, int KPW>
+__global__ __launch_bounds__(256) void stage1_wide_kernel(
+    const T *__restrict__ Fc, int64_t ldc, int64_t row0, int64_t nrows,
+    const int64_t *__restrict__ seg, const int32_t *__restrict__ other, const T *__restrict__ vs,
+    int64_t nkeys, T *__restrict__ S, int64_t ldS, const int *__restrict__ gate) {
+  __shared__ T stg[S1WideCfg<T, R, KPW>::STG];
+  if (gate && *gate == 0) return;
+  stage1_wide_block<T, R, KPW>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, S, ldS, blockIdx.x,
+                               blockIdx.y, stg);
 }
 
 // Stage 1 with LDS-staged columns.  The keys of a block reference the same
@@ -898,14 +932,19 @@ template <class T, int R>
 __global__ __launch_bounds__(256) void group_stage1_kernel(const GroupDesc<T> *__restrict__ desc,
                                                            const GroupItem *__restrict__ items,
                                                            const uint8_t *__restrict__ active) {
-  __shared__ T stg[64 * (S1Cfg<T, R>::KB * R + 1)];
+  constexpr int NARROW = 64 * (S1Cfg<T, R>::KB * R + 1), WIDE = S1WideCfg<T, R, 1>::STG;
+  __shared__ T stg[NARROW > WIDE ? NARROW : WIDE];
   const GroupItem it = items[blockIdx.x];
   if (active && !active[it.p]) return;
   const GroupDesc<T> &d = desc[it.p];
   const int nkb = (int)d.nkb;
   const int kb = it.li % nkb, rb = it.li / nkb;
-  stage1_block<T, R>(d.Fc, d.ldc, d.rows, d.nrows, d.seg, d.other, d.vs, d.nkeys, d.S,
-                     sbuf_row_ld<T>(d.nkeys, R), kb, rb, stg);
+  if (d.row0 >= 0)  // uniform: the problem's walk
+    stage1_wide_block<T, R, 1>(d.Fc, d.ldc, d.row0, d.nrows, d.seg, d.other, d.vs, d.nkeys, d.S,
+                               sbuf_row_ld<T>(d.nkeys, R), kb, rb, stg);
+  else
+    stage1_block<T, R>(d.Fc, d.ldc, d.rows, d.nrows, d.seg, d.other, d.vs, d.nkeys, d.S,
+                       sbuf_row_ld<T>(d.nkeys, R), kb, rb, stg);
 }
 
 template <class T, int R>
@@ -987,6 +1026,7 @@ void refresh_launch_knobs() {
 
 static int stage1_kpw() { return g_s1_kpw.load(std::memory_order_relaxed); }
 static bool stage1_use_wide() { return g_s1_wide.load(std::memory_order_relaxed) != 0; }
+bool stage1_wide_enabled() { return stage1_use_wide(); }
 
 template <class T, int R>
 static void stage1_r(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, const int64_t *seg,
@@ -1031,8 +1071,8 @@ template <class T, int R, int KPW>
 static void stage1_wide_rk(const T *Fc, int64_t ldc, int64_t row0, int64_t nrows, const int64_t *seg,
                            const int32_t *other, const T *vs, int64_t nkeys, T *S, int64_t ldS,
                            hipStream_t s, const int *gate) {
-  constexpr int ROWS = 64 * (16 / sizeof(T));
-  dim3 grid((unsigned)ceil_div(nkeys, S1Cfg<T, R, KPW>::KB), (unsigned)ceil_div(nrows, ROWS));
+  typedef S1WideCfg<T, R, KPW> C;
+  dim3 grid((unsigned)ceil_div(nkeys, C::KB), (unsigned)ceil_div(nrows, C::ROWS));
   stage1_wide_kernel<T, R, KPW><<<grid, 256, 0, s>>>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, S,
                                                       ldS, gate);
 }
@@ -1097,20 +1137,10 @@ void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows,
     }
 #undef GVT_S1L
   }
-  // contiguous rows: rows [h, h + nw) (aligned to VPL, a multiple of VPL) by the
-  // several-rows-per-lane walk, the few rows before and after by the one-row walk
-  constexpr int VPL = 16 / sizeof(T);
-  if (row0 >= 0 && stage1_use_wide() && ldc % VPL == 0 &&
-      reinterpret_cast<uintptr_t>(Fc) % 16 == 0) {
-    const int64_t h = std::min<int64_t>((VPL - row0 % VPL) % VPL, nrows);
-    const int64_t nw = (nrows - h) / VPL * VPL;
-    if (nw > 0) {
-      stage1_direct<T>(Fc, ldc, rows, h, seg, other, vs, nkeys, R, S, ldS, s, gate);
-      stage1_wide<T>(Fc, ldc, row0 + h, nw, seg, other, vs, nkeys, R, S + h * ldS, ldS, s, gate);
-      stage1_direct<T>(Fc, ldc, rows + h + nw, nrows - h - nw, seg, other, vs, nkeys, R,
-                       S + (h + nw) * ldS, ldS, s, gate);
-      return;
-    }
+  // a contiguous range of at least 16 bytes of rows: several rows per lane
+  if (row0 >= 0 && stage1_use_wide() && nrows >= 16 / (int64_t)sizeof(T)) {
+    stage1_wide<T>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, R, S, ldS, s, gate);
+    return;
   }
   stage1_direct<T>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, R, S, ldS, s, gate);
 }
@@ -1214,8 +1244,12 @@ void launch_fill(T *U, int64_t rows, int64_t cols, int64_t ld, T val, hipStream_
 
 int64_t group_pack_blocks(int64_t n_in) { return ceil_div(n_in, kGroupPackBlock); }
 
-int64_t group_stage1_blocks(int64_t nkeys, int64_t nrows) {
-  return ceil_div(nkeys, S1Cfg<double, 1>::KB) * ceil_div(nrows, 64);
+template <class T>
+int64_t group_stage1_setup(GroupDesc<T> &d, int64_t row0) {
+  const bool wide = row0 >= 0 && stage1_use_wide() && d.nrows >= S1WideCfg<T, 1, 1>::VPL;
+  d.row0 = wide ? row0 : -1;
+  d.nkb = ceil_div(d.nkeys, wide ? S1WideCfg<T, 1, 1>::KB : S1Cfg<T, 1>::KB);
+  return d.nkb * ceil_div(d.nrows, wide ? S1WideCfg<T, 1, 1>::ROWS : 64);
 }
 
 template <class T>
@@ -1259,6 +1293,7 @@ void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64
   template void launch_pack_v<T>(const T *, int64_t, const int32_t *, int64_t, int, T *,          \
                                  hipStream_t, const int *);                                      \
   template void launch_segsum<T>(const int64_t *, const T *, int64_t, int, T *, hipStream_t);    \
+  template int64_t group_stage1_setup<T>(GroupDesc<T> &, int64_t);                               \
   template void launch_stage1<T>(const T *, int64_t, const int32_t *, int64_t, int64_t,         \
                                  const int64_t *,                                                \
                                  const int32_t *, int64_t, const int32_t *, int64_t, int64_t,    \

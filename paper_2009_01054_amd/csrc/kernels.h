@@ -38,6 +38,7 @@ void launch_segsum(const int64_t *seg, const T *vs, int64_t nkeys, int R, T *out
 // Re-read the environment overrides of the tuned launch shapes (called when a
 // plan is built).
 void refresh_launch_knobs();
+bool stage1_wide_enabled();  // the several-rows-per-lane stage-1 walk is on
 
 // Stage 1: the direct segment walk, or with LDS-staged columns when each
 // column is reused enough (cseg: per-key chunk starts, nch chunks; null = direct).
@@ -106,6 +107,7 @@ template <class T> struct GroupDesc {
   const int64_t *seg;
   const int32_t *other;
   int64_t nkeys;
+  int64_t row0;  // >= 0: S row i is F2 row row0 + i, walked several rows per lane
   T *S;         // row stride sbuf_row_ld<T>(nkeys, R) for an R-column RHS block
   int64_t nkb;  // stage-1 key blocks
   // stage 2, one tile set per RHS class ([0]: blocks of 1-2 RHS, F1-row groups;
@@ -132,7 +134,11 @@ struct GroupItem {
 
 // Work items per problem for each grouped launch, in the problem's natural block order.
 int64_t group_pack_blocks(int64_t n_in);
-int64_t group_stage1_blocks(int64_t nkeys, int64_t nrows);
+// Stage 1: picks the problem's walk (several rows per lane when its S rows are
+// the contiguous range starting at F2 row row0 >= 0, else one row per lane),
+// sets d.row0 and d.nkb, and returns the problem's blocks (nkeys and nrows set).
+template <class T>
+int64_t group_stage1_setup(GroupDesc<T> &d, int64_t row0);
 
 // active[p] == 0 skips problem p (null: every problem runs).  r0: first RHS of the block.
 template <class T>

@@ -41,6 +41,7 @@ struct SBufSpec {  // one stage-1 result S = scatter of F_sc by `key` with colum
   std::vector<int32_t> rowmap;   // F_sc row -> compact S row (-1: not needed)
   std::vector<int32_t> rows;     // compact S rows -> F_sc row
   int64_t row0 = -1;             // rows[i] = row0 + i for all i (contiguous), else -1
+  int64_t nneed = 0;             // rows the terms read (rows may add a few to close gaps)
   DevMem d_rows;
   DevMem d_rowmap;               // device copy of rowmap (device-built plans)
 };

@@ -643,6 +643,18 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     }
   }
   for (SBufSpec &sb : P->sbufs) {
+    // a nearly contiguous row set (at most 1/8 of its span missing) is widened
+    // to the whole span, so that stage 1 can walk it several rows per lane;
+    // the added rows are computed and never read
+    sb.nneed = 0;
+    for (int32_t m : sb.rowmap) sb.nneed += m >= 0;
+    if (!sb.degenerate && stage1_wide_enabled()) {
+      int64_t lo = -1, hi = -1, cnt = 0;
+      for (int64_t r = 0; r < (int64_t)sb.rowmap.size(); ++r)
+        if (sb.rowmap[r] >= 0) { lo = lo < 0 ? r : lo; hi = r; ++cnt; }
+      if (cnt > 0 && (hi - lo + 1 - cnt) * 8 <= hi - lo + 1)
+        for (int64_t r = lo; r <= hi; ++r) sb.rowmap[r] = 0;
+    }
     sb.rows.clear();
     for (int64_t r = 0; r < (int64_t)sb.rowmap.size(); ++r)
       if (sb.rowmap[r] >= 0) { sb.rowmap[r] = (int32_t)sb.rows.size(); sb.rows.push_back((int32_t)r); }
@@ -683,8 +695,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   }
   // S-buffer stage-1 cost (shared scatters counted once)
   for (const SBufSpec &sb : P->sbufs)
-    P->cost_fma += sb.degenerate ? (double)sb.rows.size() * nkeys_of(P, sb.key)
-                                 : (double)sb.rows.size() * n_in_d;
+    P->cost_fma += sb.degenerate ? (double)sb.nneed * nkeys_of(P, sb.key) : (double)sb.nneed * n_in_d;
   // stage-2 costs were included in g_cost together with a per-term stage-1; remove those
   for (const RawTerm &t : raw_terms)
     if (t.type == TG) {

@@ -395,6 +395,27 @@ def test_cg_batched_f64_matches_oracle(gvt, monkeypatch, nlam, cap):
             assert abs(int(iters[k, l]) - int(it_or[l])) <= max(3, 0.1 * int(it_or[l]))
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cg_batched_stage1_walks_bitwise(gvt, monkeypatch, prec):
+    # grouped stage 1 with 16 bytes of rows per lane against one row per lane: odd row
+    # strides (column loads at 8- or 4-byte alignment), ragged row ends, and a problem with
+    # fewer S rows than 16 bytes (one-row walk in FP32); the solves agree exactly
+    shapes = [(23, 31, 400), (60, 17, 700), (41, 45, 1500), (12, 90, 500), (70, 70, 2100), (35, 9, 250),
+              (7, 3, 15)]
+    probs = _batch(99, shapes)
+    lams = [1e-1, 1.0, 10.0, 0.5, 3.0]
+    mp = gvt.F32 if prec == "f32" else gvt.F64
+    res = []
+    for wide in ("0", "1"):
+        monkeypatch.setenv("GVT_STAGE1_WIDE", wide)
+        res.append(gvt.gvt_krr_cg_batched("kronecker", _dev_problems(probs), lams, max_iter=60, tol=1e-8,
+                                          check_every=4, matvec_prec=mp))
+    (A0, i0, r0, c0), (A1, i1, r1, c1) = res
+    assert c0 == c1 and (i0 == i1).all() and (r0 == r1).all()
+    for x, y in zip(A0, A1):
+        assert torch.equal(x, y)
+
+
 def test_cg_batched_f32_products_certified(gvt):
     shapes = [(60, 50, 1500), (30, 80, 1200), (45, 45, 900), (20, 20, 300)]
     probs = _batch(96, shapes, dim=32)
@@ -477,10 +498,13 @@ def test_stage1_variants_are_bitwise_equal(gvt, env, nrhs, monkeypatch):
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("lo,hi", [(0, 700), (3, 600), (2, 403), (5, 8), (1, 2)])
 @pytest.mark.parametrize("order", [2, 4])
-def test_stage1_wide_rows_bitwise(gvt, prec, lo, hi, order, monkeypatch):
-    # the several-rows-per-lane walk covers the 16-byte aligned part of a contiguous S-row
-    # range [lo, hi) and the one-row walk the rows before and after it: both orders of the
-    # stages, ranges with and without ragged ends, and ranges too short for the wide walk
+@pytest.mark.parametrize("gaps", [False, True])
+def test_stage1_wide_rows_bitwise(gvt, prec, lo, hi, order, gaps, monkeypatch):
+    # the walk with 16 bytes of rows per lane over a contiguous S-row range [lo, hi) against
+    # one row per lane: both orders of the stages, ranges that start off a 16-byte boundary
+    # and end raggedly, and ranges shorter than 16 bytes (one-row walk either way); with
+    # `gaps` two rows of the range never occur, and the plan closes the gaps (extra S rows
+    # that no output reads) when they are a small part of the span
     r = np.random.default_rng([7, lo, hi])
     dt = torch.float64 if prec == "f64" else torch.float32
     D = W.gaussian_kernel(r.standard_normal((700, 3)))
@@ -491,6 +515,10 @@ def test_stage1_wide_rows_bitwise(gvt, prec, lo, hi, order, monkeypatch):
     b = r.integers(lo, hi, 9000).astype(np.int32)
     a[:hi - lo] = np.arange(lo, hi)  # every row of the range occurs: contiguous S rows
     b[:hi - lo] = np.arange(lo, hi)
+    if gaps:
+        for g in (lo + 1, (lo + hi) // 2):
+            a[a == g] = lo
+            b[b == g] = lo
     Dd, Td = dev(D, dt), dev(T, dt)
     for nrhs in (1, 2, 4, 8):
         v = dev(r.standard_normal((len(c), nrhs)), dt)
