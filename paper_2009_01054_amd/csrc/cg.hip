@@ -32,15 +32,16 @@ struct CgScalars {
   int pad0;
 };
 
+// Sum over the block in a fixed order: a butterfly inside each wave (every
+// lane ends with the same value, since a + b == b + a exactly), then the four
+// wave sums in order.  One barrier instead of one per tree level.
 __device__ __forceinline__ double block_sum(double v, double *sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
+  static_assert(RB == 256, "four waves per block");
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = RB / 2; s > 0; s >>= 1) {
-    if (t < s) sh[t] += sh[t + s];
-    __syncthreads();
-  }
-  const double r = sh[0];
+  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
   __syncthreads();
   return r;
 }
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(RB) void dot_partial_kernel(const double *__restric
   }
 }
 
-// Fixed-tree fold of the RNB block partials of system l by one 256-thread block.
+// Fixed-order fold of the RNB block partials of system l by one 256-thread block.
 __device__ __forceinline__ double fold_partials(const double *partial, int nlam, int l, double *sh) {
   const double v = threadIdx.x < RNB ? partial[threadIdx.x * nlam + l] : 0.0;
   return block_sum(v, sh);
@@ -68,7 +69,7 @@ __device__ __forceinline__ double fold_partials(const double *partial, int nlam,
 
 // Per iteration the vector work is three kernels: p.w, then the update of a
 // and r with alpha, then the new search direction with beta.  The step
-// lengths come from block partials folded by a fixed tree; instead of a
+// lengths come from block partials folded in a fixed order; instead of a
 // kernel of its own, every block of the next kernel folds them itself (the
 // same reads in the same order, so every block gets the same value) and
 // block 0 records the scalars.  No kernel reads a scalar field that it also
