@@ -251,18 +251,23 @@ __global__ __launch_bounds__(256) void stage1_wide_kernel(
 
 // Stage 1 with LDS-staged columns.  The keys of a block reference the same
 // F2 columns many times (every key segment runs over the same range of other
-// indices), so the block stages the columns of one chunk of
-// kStage1OtherChunk other indices, for its 64 rows, in LDS with one coalesced
-// pass, and every wave then walks the part of its keys' segments that falls
-// in the chunk, reading the column values from LDS.  The accumulators of all
-// of a wave's keys stay in registers across chunks.  Segments are sorted by
-// other index, so each key still sums its pairs in segment order: the result
-// equals the direct walk's bit for bit.  The staging buffer is reused for the
-// result tile.
+// indices), so the block stages the columns of one chunk of OC other
+// indices, for its 64 rows, in LDS (128 KB: one block per CU), and every wave
+// then walks the part of its keys' segments that falls in the chunk, reading
+// the column values from LDS.  A block has 16 waves and 16 x KPW keys, so each
+// staged column serves many pairs.  The accumulators of all of a wave's keys
+// stay in registers across chunks.  Segments are sorted by other index, so
+// each key still sums its pairs in segment order: the result equals the
+// direct walk's bit for bit.  The staging buffer is reused for the result
+// tile.
 template <class T, int R, int KPW> struct S1LdsCfg {
-  static constexpr int KB = 4 * KPW;
-  static constexpr int COLS = kStage1OtherChunk * 64;  // staged column values
-  static constexpr int STG = 64 * (KB * R + 1);        // result tile
+  static constexpr int NW = 16;                                 // waves per block
+  static constexpr int NT = NW * 64;
+  static constexpr int KB = NW * KPW;                           // keys per block
+  static constexpr int CM = (128 * 1024) / (64 * kStage1OtherChunk * (int)sizeof(T));
+  static constexpr int OC = kStage1OtherChunk * CM;             // columns per staged chunk
+  static constexpr int COLS = OC * 64;                          // staged column values
+  static constexpr int STG = 64 * (KB * R + 1);                 // result tile
   static constexpr int SIZE = COLS > STG ? COLS : STG;
 };
 
@@ -273,13 +278,14 @@ __device__ __forceinline__ void stage1_lds_block(
     const T *__restrict__ vs, int64_t nkeys, int64_t nother, T *__restrict__ S, int64_t ldS,
     int64_t kb, int64_t rb, T *lds) {
   typedef S1LdsCfg<T, R, KPW> C;
-  constexpr int OC = kStage1OtherChunk;
+  constexpr int OC = C::OC, NW = C::NW;
   constexpr int W = C::KB * R;
+  const int64_t nst = (nch + C::CM - 1) / C::CM;  // staged chunks (nch: cseg chunks)
   const int lane = threadIdx.x & 63;
   const int w = wave_id_uniform();
   const int64_t k0 = kb * C::KB;
   const int64_t rho0 = rb * 64;
-  // staging: this thread fills row `lane` of the chunk's columns oc = wave, wave + 4, ...
+  // staging: this thread fills row `lane` of the chunk's columns oc = wave, wave + NW, ...
   const int64_t frho = rho0 + lane;
   const bool frow_ok = frho < nrows;
   const int64_t fy = frow_ok ? rows[frho] : 0;  // row 0 stands in for rows past the end
@@ -295,7 +301,7 @@ __device__ __forceinline__ void stage1_lds_block(
   constexpr int VEC = 16 / (int)sizeof(T);  // values per 16-byte piece
   constexpr int LPC = 64 / VEC;             // lanes per staged column
   constexpr int CPI = 64 / LPC;             // columns per wave instruction
-  static_assert(OC % (4 * CPI) == 0, "whole instructions per wave and chunk");
+  static_assert(OC % (NW * CPI) == 0, "whole instructions per wave and chunk");
   bool dma = false;
   if (rho0 + 64 <= nrows) {  // uniform
     const int64_t y0 = rows[rho0];
@@ -303,36 +309,44 @@ __device__ __forceinline__ void stage1_lds_block(
           reinterpret_cast<uintptr_t>(Fc) % 16 == 0;
   }
   const int64_t dy0 = dma ? (int64_t)rows[rho0] : 0;
-  for (int64_t c = 0; c < nch; ++c) {
+  auto stage = [&](int64_t c, T *buf) {
     const int64_t o0 = c * OC;
-    __syncthreads();  // the previous chunk's reads are done
     if (dma) {
       // columns past the last other index load an in-range column; no key
       // segment refers to them
       const int col_in = lane / LPC, piece = lane % LPC;
-      for (int q = w; q < OC / CPI; q += 4) {
+      for (int q = w; q < OC / CPI; q += NW) {
         const int64_t o = o0 + q * CPI + col_in;
         lds_load_row16(Fc + (o < nother ? o : nother - 1) * ldc + dy0 + piece * VEC,
-                       lds + q * CPI * 64);
+                       buf + q * CPI * 64);
       }
-      __builtin_amdgcn_s_waitcnt(0);
     } else {
       // unconditional loads from clamped in-range addresses, so that they all
       // issue before the first wait; out-of-range values are replaced by zero
 #pragma unroll 8
-      for (int oc = w; oc < OC; oc += 4) {
+      for (int oc = w; oc < OC; oc += NW) {
         const int64_t o = o0 + oc;
         const T v = Fc[(o < nother ? o : nother - 1) * ldc + fy];
-        lds[oc * 64 + lane] = (o < nother && frow_ok) ? v : T(0);
+        buf[oc * 64 + lane] = (o < nother && frow_ok) ? v : T(0);
       }
     }
+  };
+  for (int64_t c = 0; c < nst; ++c) {
+    const int64_t o0 = c * OC;
+    const T *cur = lds;
+    __syncthreads();  // the previous chunk's reads are done
+    stage(c, lds);
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the chunk has landed
     __syncthreads();
-#pragma unroll 1
+    // unrolled over the wave's keys, so that each key's accumulators are fixed
+    // registers (a runtime key index turns every accumulation into selects)
+#pragma unroll
     for (int kk = 0; kk < KPW; ++kk) {
       const int64_t k = k0 + w * KPW + kk;
       if (k < nkeys) {  // uniform
-        const int64_t p0 = cseg[k * (nch + 1) + c], p1 = cseg[k * (nch + 1) + c + 1];
-        const T *col = lds + lane - o0 * 64;
+        const int64_t c0 = c * C::CM, c1 = c0 + C::CM < nch ? c0 + C::CM : nch;
+        const int64_t p0 = cseg[k * (nch + 1) + c0], p1 = cseg[k * (nch + 1) + c1];
+        const T *col = cur + lane - o0 * 64;
 #pragma unroll 8
         for (int64_t p = p0; p < p1; ++p) {
           const T f = col[(int64_t)other[p] * 64];
@@ -350,7 +364,7 @@ __device__ __forceinline__ void stage1_lds_block(
   __syncthreads();
   const int64_t kcount = (nkeys - k0) < C::KB ? (nkeys - k0) : C::KB;
   const int width = (int)kcount * R;
-  for (int idx = threadIdx.x; idx < 64 * W; idx += 256) {
+  for (int idx = threadIdx.x; idx < 64 * W; idx += C::NT) {
     const int rr = idx / W, cc = idx - rr * W;
     const int64_t orow = rho0 + rr;
     if (orow < nrows && cc < width) S[orow * ldS + k0 * R + cc] = lds[rr * (W + 1) + cc];
@@ -358,7 +372,7 @@ __device__ __forceinline__ void stage1_lds_block(
   // the last key block also clears the row padding (read by stage 2 as whole chunks)
   if (k0 + C::KB >= nkeys) {
     const int64_t padw = ldS - nkeys * R;
-    for (int64_t idx = threadIdx.x; idx < 64 * padw; idx += 256) {
+    for (int64_t idx = threadIdx.x; idx < 64 * padw; idx += C::NT) {
       const int64_t rr = idx / padw, cc = idx - rr * padw;
       if (rho0 + rr < nrows) S[(rho0 + rr) * ldS + nkeys * R + cc] = T(0);
     }
@@ -366,7 +380,7 @@ __device__ __forceinline__ void stage1_lds_block(
 }
 
 template <class T, int R, int KPW>
-__global__ __launch_bounds__(256) void stage1_lds_kernel(
+__global__ __launch_bounds__(1024) void stage1_lds_kernel(
     const T *__restrict__ Fc, int64_t ldc, const int32_t *__restrict__ rows, int64_t nrows,
     const int32_t *__restrict__ cseg, int64_t nch, const int32_t *__restrict__ other,
     const T *__restrict__ vs, int64_t nkeys, int64_t nother, T *__restrict__ S, int64_t ldS,
@@ -1045,7 +1059,7 @@ static void stage1_lds_rk(const T *Fc, int64_t ldc, const int32_t *rows, int64_t
                           int64_t nkeys, int64_t nother, T *S, int64_t ldS, hipStream_t s,
                           const int *gate) {
   dim3 grid((unsigned)ceil_div(nkeys, S1LdsCfg<T, R, KPW>::KB), (unsigned)ceil_div(nrows, 64));
-  stage1_lds_kernel<T, R, KPW><<<grid, 256, 0, s>>>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys,
+  stage1_lds_kernel<T, R, KPW><<<grid, S1LdsCfg<T, R, KPW>::NT, 0, s>>>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys,
                                                      nother, S, ldS, gate);
 }
 
@@ -1058,11 +1072,13 @@ static int stage1_lds_kpw(int R) {
 }
 
 // Whether the LDS-staged walk pays: each staged column must be used about
-// kStage1LdsMinReuse times by the block's keys (GVT_STAGE1_LDS = 0 / 1 forces it).
-static bool stage1_use_lds(int64_t npairs, int64_t nkeys, int64_t nother, int kb) {
+// kStage1LdsMinReuse times by the block's keys, and a pair's packed v values
+// (read as scalars, R x sizeof(T) bytes) must not outweigh its LDS read
+// (GVT_STAGE1_LDS = 0 / 1 forces it either way).
+static bool stage1_use_lds(int64_t npairs, int64_t nkeys, int64_t nother, int kb, int vbytes) {
   const int forced = g_s1_lds.load(std::memory_order_relaxed);
   if (forced >= 0) return forced != 0;
-  if (nkeys <= 0 || nother <= 0) return false;
+  if (nkeys <= 0 || nother <= 0 || vbytes > 8) return false;
   const double reuse = (double)npairs / (double)nkeys * kb / (double)nother;
   return reuse >= kStage1LdsMinReuse;
 }
@@ -1121,7 +1137,7 @@ void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows,
                    int64_t ldS, hipStream_t s, const int *gate) {
   if (nrows <= 0 || nkeys <= 0) return;
   const int kl = stage1_lds_kpw(R);
-  if (cseg && stage1_use_lds(npairs, nkeys, nother, 4 * kl)) {
+  if (cseg && stage1_use_lds(npairs, nkeys, nother, S1LdsCfg<T, 1, 1>::NW * kl, R * (int)sizeof(T))) {
 #define GVT_S1L(RR, KK) stage1_lds_rk<T, RR, KK>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys, nother, S, ldS, s, gate)
     switch (R * 16 + kl) {
       case 16 + 2: GVT_S1L(1, 2); return;

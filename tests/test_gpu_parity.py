@@ -476,15 +476,17 @@ def test_cg_batched_warm_start_and_cap(gvt):
                                  {"GVT_STAGE1_LDS": "1", "GVT_STAGE1_LDS_KPW": "4"},
                                  {"GVT_STAGE1_LDS": "1", "GVT_STAGE1_LDS_KPW": "8"}])
 @pytest.mark.parametrize("nrhs", [1, 3, 8])
-def test_stage1_variants_are_bitwise_equal(gvt, env, nrhs, monkeypatch):
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_stage1_variants_are_bitwise_equal(gvt, env, nrhs, prec, monkeypatch):
     # every stage-1 variant (direct walk with 1, 2 or 4 keys per wave, one row or 16 bytes of
     # rows per lane; LDS-staged columns with 2, 4 or 8) sums a key's segment in the same
     # order, so products agree exactly; the other-index range (700) spans several staged
-    # chunks of 128 and a ragged last one
+    # chunks of 128 and a ragged last one (staged 256 FP64 or 512 FP32 columns at a time)
     p = W.make_heterogeneous(99, 0, 900, 700, 30000, 8)
-    Dd, Td = dev(p["D"]), dev(p["T"])
+    dt = torch.float64 if prec == "f64" else torch.float32
+    Dd, Td = dev(p["D"], dt), dev(p["T"], dt)
     c, e = idx(p["c"]), idx(p["e"])
-    v = dev(np.random.default_rng(5).standard_normal((len(p["c"]), nrhs)))
+    v = dev(np.random.default_rng(5).standard_normal((len(p["c"]), nrhs)), dt)
     monkeypatch.setenv("GVT_STAGE1_LDS", "0")
     monkeypatch.setenv("GVT_STAGE1_WIDE", "0")
     monkeypatch.setenv("GVT_STAGE1_KPW", "4")
