@@ -18,6 +18,7 @@
 namespace gvt {
 
 static constexpr int WAVE = 64;
+static constexpr double kL2BytesPerXcd = 4.0 * 1024 * 1024;  // gfx950: 4 MB of L2 per XCD
 
 __device__ __forceinline__ int wave_id_uniform() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -242,11 +243,24 @@ template <class T, int R, int KPW>
 __global__ __launch_bounds__(256) void stage1_wide_kernel(
     const T *__restrict__ Fc, int64_t ldc, int64_t row0, int64_t nrows,
     const int64_t *__restrict__ seg, const int32_t *__restrict__ other, const T *__restrict__ vs,
-    int64_t nkeys, T *__restrict__ S, int64_t ldS, const int *__restrict__ gate) {
+    int64_t nkeys, T *__restrict__ S, int64_t ldS, int64_t nkb, int64_t per,
+    const int *__restrict__ gate) {
   __shared__ T stg[S1WideCfg<T, R, KPW>::STG];
   if (gate && *gate == 0) return;
-  stage1_wide_block<T, R, KPW>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, S, ldS, blockIdx.x,
-                               blockIdx.y, stg);
+  // per == 0: a 2-D grid (key block, row block).  Otherwise, for F2 row sets
+  // larger than an L2: workgroups go to the 8 XCDs in turn (workgroup i to
+  // XCD i % 8), and block b of the (row block, key block) order, key blocks
+  // fastest, runs as workgroup b % per of XCD b / per, so each XCD walks a
+  // contiguous run of row blocks and their F2 rows stay in its L2 while all
+  // key blocks read them.
+  int64_t kb = blockIdx.x, rb = blockIdx.y;
+  if (per > 0) {
+    const int64_t b = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (b >= nkb * ((nrows + S1WideCfg<T, R, KPW>::ROWS - 1) / S1WideCfg<T, R, KPW>::ROWS)) return;
+    kb = b % nkb;
+    rb = b / nkb;
+  }
+  stage1_wide_block<T, R, KPW>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, S, ldS, kb, rb, stg);
 }
 
 // Stage 1 with LDS-staged columns.  The keys of a block reference the same
@@ -1085,19 +1099,29 @@ static bool stage1_use_lds(int64_t npairs, int64_t nkeys, int64_t nother, int kb
 
 template <class T, int R, int KPW>
 static void stage1_wide_rk(const T *Fc, int64_t ldc, int64_t row0, int64_t nrows, const int64_t *seg,
-                           const int32_t *other, const T *vs, int64_t nkeys, T *S, int64_t ldS,
-                           hipStream_t s, const int *gate) {
+                           const int32_t *other, const T *vs, int64_t nkeys, int64_t nother, T *S,
+                           int64_t ldS, hipStream_t s, const int *gate) {
   typedef S1WideCfg<T, R, KPW> C;
-  dim3 grid((unsigned)ceil_div(nkeys, C::KB), (unsigned)ceil_div(nrows, C::ROWS));
-  stage1_wide_kernel<T, R, KPW><<<grid, 256, 0, s>>>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, S,
-                                                      ldS, gate);
+  const int64_t nkb = ceil_div(nkeys, C::KB), nrb = ceil_div(nrows, C::ROWS);
+  // XCD-grouped order when the F2 rows the walk reads exceed one XCD's L2
+  // (measured: fused four-kind workload, 5 000 x 5 000 F2, stage 1 -21% FP32,
+  // -24% FP64; ridge workload, 2 MB F2, +9% FP64: there every L2 holds all of F2)
+  if ((double)nrows * (double)nother * sizeof(T) > kL2BytesPerXcd) {
+    const int64_t per = ceil_div(nkb * nrb, 8);
+    GVT_REQUIRE(8 * per < ((int64_t)1 << 31), GVT_ERR_ARG, "stage 1: too many blocks");
+    stage1_wide_kernel<T, R, KPW><<<(unsigned)(8 * per), 256, 0, s>>>(
+        Fc, ldc, row0, nrows, seg, other, vs, nkeys, S, ldS, nkb, per, gate);
+  } else {
+    stage1_wide_kernel<T, R, KPW><<<dim3((unsigned)nkb, (unsigned)nrb), 256, 0, s>>>(
+        Fc, ldc, row0, nrows, seg, other, vs, nkeys, S, ldS, nkb, 0, gate);
+  }
 }
 
 template <class T>
 static void stage1_wide(const T *Fc, int64_t ldc, int64_t row0, int64_t nrows, const int64_t *seg,
-                        const int32_t *other, const T *vs, int64_t nkeys, int R, T *S, int64_t ldS,
-                        hipStream_t s, const int *gate) {
-#define GVT_S1W(RR, KK) stage1_wide_rk<T, RR, KK>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, S, ldS, s, gate)
+                        const int32_t *other, const T *vs, int64_t nkeys, int64_t nother, int R, T *S,
+                        int64_t ldS, hipStream_t s, const int *gate) {
+#define GVT_S1W(RR, KK) stage1_wide_rk<T, RR, KK>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, nother, S, ldS, s, gate)
   switch (R * 16 + stage1_kpw()) {
     case 16 + 1: GVT_S1W(1, 1); return;
     case 16 + 2: GVT_S1W(1, 2); return;
@@ -1155,7 +1179,7 @@ void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows,
   }
   // a contiguous range of at least 16 bytes of rows: several rows per lane
   if (row0 >= 0 && stage1_use_wide() && nrows >= 16 / (int64_t)sizeof(T)) {
-    stage1_wide<T>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, R, S, ldS, s, gate);
+    stage1_wide<T>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, nother, R, S, ldS, s, gate);
     return;
   }
   stage1_direct<T>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, R, S, ldS, s, gate);

@@ -498,6 +498,29 @@ def test_stage1_variants_are_bitwise_equal(gvt, env, nrhs, prec, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_stage1_wide_xcd_order_bitwise(gvt, prec, monkeypatch):
+    # F2 rows beyond one XCD's L2 (2 100 x 2 100 bases: 35 MB FP64, 18 MB FP32) switch the
+    # wide walk to the XCD-grouped block order; every block still runs once
+    r = np.random.default_rng(17)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    m = 2100
+    D = W.gaussian_kernel(r.standard_normal((m, 3)))
+    c = r.integers(0, m, 30000).astype(np.int32)
+    e = r.integers(0, m, 30000).astype(np.int32)
+    a = r.integers(0, m, 20000).astype(np.int32)
+    b = r.integers(0, m, 20000).astype(np.int32)
+    Dd = dev(D, dt)
+    for nrhs in (1, 2, 4):
+        v = dev(r.standard_normal((len(c), nrhs)), dt)
+        args = ((idx(a), idx(b)), (idx(c), idx(e)), v)
+        monkeypatch.setenv("GVT_STAGE1_WIDE", "0")
+        ref = gvt.gvt_matvec(Dd, Dd, *args)
+        monkeypatch.setenv("GVT_STAGE1_WIDE", "1")
+        got = gvt.gvt_matvec(Dd, Dd, *args)
+        assert torch.equal(got, ref), nrhs
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("lo,hi", [(0, 700), (3, 600), (2, 403), (5, 8), (1, 2)])
 @pytest.mark.parametrize("order", [2, 4])
 @pytest.mark.parametrize("gaps", [False, True])
