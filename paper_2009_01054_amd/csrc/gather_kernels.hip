@@ -18,7 +18,6 @@
 namespace gvt {
 
 static constexpr int WAVE = 64;
-static constexpr double kL2BytesPerXcd = 4.0 * 1024 * 1024;  // gfx950: 4 MB of L2 per XCD
 
 __device__ __forceinline__ int wave_id_uniform() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

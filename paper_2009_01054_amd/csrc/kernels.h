@@ -9,6 +9,7 @@ constexpr int kMaxCombineTerms = 16;
 // Stage-2 tiles: kStage2Rows consecutive F1 rows x at most kStage2MaxS S rows.
 constexpr int kStage2Rows = 32;
 constexpr int kStage2MaxS = 64;
+constexpr double kL2BytesPerXcd = 4.0 * 1024 * 1024;  // gfx950: 4 MB of L2 per XCD
 constexpr int kMaxCombineOut = 8;
 // Stage 1 with LDS-staged columns: other indices per staged chunk.
 constexpr int kStage1OtherChunk = 128;

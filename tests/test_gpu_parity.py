@@ -416,6 +416,24 @@ def test_cg_batched_stage1_walks_bitwise(gvt, monkeypatch, prec):
         assert torch.equal(x, y)
 
 
+def test_cg_batched_large_problem_matches_single_solves(gvt):
+    # a problem with 30 000 pairs over 760 x 740 bases beside small ones: the grouped launches
+    # (work lists of uneven length, both stage-1 walks) give the problem-by-problem solutions
+    shapes = [(760, 740, 30000), (40, 50, 900), (120, 90, 3000)]
+    probs = _batch(100, shapes, dim=32)
+    lams = [10.0, 100.0, 1000.0]
+    A, iters, rel, rc = gvt.gvt_krr_cg_batched("kronecker", _dev_problems(probs), lams, max_iter=400,
+                                               tol=1e-10, check_every=8)
+    assert rc == 0 and (rel < 1e-10).all()
+    for k, p in enumerate(probs):
+        A1, it1, rel1, rc1 = gvt.gvt_krr_cg("kronecker", dev(p["D"]), dev(p["T"]), (idx(p["c"]), idx(p["e"])),
+                                            dev(p["y"]), lams, max_iter=400, tol=1e-10)
+        assert rc1 == 0
+        a, a1 = A[k].cpu().numpy(), A1.cpu().numpy()
+        for l in range(len(lams)):
+            assert np.linalg.norm(a[:, l] - a1[:, l]) / np.linalg.norm(a1[:, l]) < 1e-8, (k, l)
+
+
 def test_cg_batched_f32_products_certified(gvt):
     shapes = [(60, 50, 1500), (30, 80, 1200), (45, 45, 900), (20, 20, 300)]
     probs = _batch(96, shapes, dim=32)
