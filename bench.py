@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GVT matvecs/sec & KRR-CG time to 1e-6 rel. residual; fraction of HBM/MFMA roofline"
 PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X published FP64 vector peak
+PEAK_HBM_TBPS = 8.0            # MI355X published HBM3E bandwidth
 PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X published FP32 vector peak (counts packed FP32)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage2_ridge_m2000_q500_n200k.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2009_01054_amd", "csrc", "gather_kernels.hip")
@@ -454,6 +455,12 @@ def main():
         "matvec_ms": round(matvec_ms, 5),
         "theorem1_fma_per_matvec": info["cost_fma"],
         "matvec_tflops": round(2.0 * info["cost_fma"] / (matvec_ms * 1e-3) / 1e12, 4),
+        # the HBM side of the same launch (counter bytes over the event time; a high share
+        # would mean re-streamed operands, not progress) and the element bytes a walk without
+        # on-chip reuse would gather (one S element per FMA)
+        "hbm_tbps": None if traffic is None else round(traffic / stage2_s / 1e12, 3),
+        "hbm_frac": None if traffic is None else round(traffic / stage2_s / 1e12 / PEAK_HBM_TBPS, 4),
+        "gathered_tbps": round(n_out * s_keys * Dp.element_size() / stage2_s / 1e12, 3),
     }
     log(f"[bench] stage ms {stage_ms}, matvec {matvec_ms:.4f} ms, plan {plan_ms:.1f} ms")
 
