@@ -539,7 +539,7 @@ def test_stage1_wide_xcd_order_bitwise(gvt, prec, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-@pytest.mark.parametrize("lo,hi", [(0, 700), (3, 600), (2, 403), (5, 8), (1, 2)])
+@pytest.mark.parametrize("lo,hi", [(0, 700), (3, 600), (2, 403), (5, 8), (4, 6), (1, 5), (1, 2)])
 @pytest.mark.parametrize("order", [2, 4])
 @pytest.mark.parametrize("gaps", [False, True])
 def test_stage1_wide_rows_bitwise(gvt, prec, lo, hi, order, gaps, monkeypatch):
