@@ -39,6 +39,17 @@
  *    Error paths never leave kernels running on the stream.
  *  - Results are deterministic: repeated calls with the same inputs give
  *    bitwise identical outputs (no floating-point atomics).
+ *  - Launch shapes come from tuned constants compiled into the library.
+ *    Environment variables read when a plan is built override them for
+ *    tuning sweeps: GVT_STAGE1_WIDE (0/1: stage 1 holds 16 bytes of
+ *    consecutive rows per lane over a contiguous row range), GVT_STAGE1_KPW
+ *    (1, 2, 4 keys per wave), GVT_STAGE1_LDS (0/1: F2 columns staged in LDS)
+ *    and GVT_STAGE1_LDS_KPW, GVT_STAGE2_TARGET_R1 / _R8 (stage-2 outputs per
+ *    group row and tile), GVT_MAX_RHS_BLOCK[_F64|_F32] (largest RHS block of
+ *    a pass), GVT_PLAN_DEVICE (0/1: plan index work on the host / device).
+ *    All of them but the RHS block give the same products bit for bit (the
+ *    block size changes which lanes sum which keys); GVT_PLAN_TIMING=1
+ *    prints the host time of each plan phase.
  */
 #ifndef GVT_H
 #define GVT_H
