@@ -516,6 +516,24 @@ def test_stage1_variants_are_bitwise_equal(gvt, env, nrhs, prec, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nrhs", [1, 2, 4, 8])
+def test_stage2_tile_targets_bitwise(gvt, prec, nrhs, monkeypatch):
+    # the stage-2 tile height (from the tuned outputs-per-row target) changes which outputs
+    # share a tile, not the order in which a lane sums an output's keys
+    p = W.make_heterogeneous(102, 0, 300, 250, 20000, 8)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    Dd, Td = dev(p["D"], dt), dev(p["T"], dt)
+    c, e = idx(p["c"]), idx(p["e"])
+    v = dev(np.random.default_rng(8).standard_normal((len(p["c"]), nrhs)), dt)
+    res = []
+    for r1, r8 in (("8", "2"), ("128", "32")):
+        monkeypatch.setenv("GVT_STAGE2_TARGET_R1", r1)
+        monkeypatch.setenv("GVT_STAGE2_TARGET_R8", r8)
+        res.append(gvt.gvt_matvec(Dd, Td, (c, e), (c, e), v))
+    assert torch.equal(res[0], res[1])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_stage1_wide_xcd_order_bitwise(gvt, prec, monkeypatch):
     # F2 rows beyond one XCD's L2 (2 100 x 2 100 bases: 35 MB FP64, 18 MB FP32) switch the
     # wide walk to the XCD-grouped block order; every block still runs once
