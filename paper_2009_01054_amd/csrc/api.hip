@@ -1,6 +1,8 @@
 // extern "C" entry points declared in include/gvt.h.
 #include <algorithm>
 #include <cstdarg>
+#include <iterator>
+#include <map>
 #include <mutex>
 
 #include "plan.h"
@@ -18,6 +20,105 @@ void set_error(const char *fmt, ...) {
   g_last_error = buf;
 }
 void clear_error() { g_last_error.clear(); }
+
+// Released device blocks are kept for reuse instead of freed: hipMalloc costs
+// tens of microseconds per call, and a ridge solve (plan, workspaces, CG
+// vectors) makes a dozen of them.  A block goes back to its device's cache
+// only after that device has finished all queued work, as hipFree would wait,
+// so no stream can still be using it when it is handed out again.  A request
+// takes the smallest cached block of at least its size and at most twice it;
+// each device's cache holds at most kBlockCacheMax bytes (the largest blocks
+// beyond that are freed), and an allocation that fails empties the cache and
+// tries once more.
+namespace {
+constexpr size_t kBlockCacheMax = (size_t)4 << 30;
+struct BlockCache {
+  std::multimap<size_t, void *> by_size;
+  size_t held = 0;
+};
+struct BlockState {
+  std::mutex mu;
+  std::map<int, BlockCache> cache;  // per device
+  std::map<void *, int> dev_of;     // device of each block handed out
+};
+// never destroyed: blocks may come back while the process exits
+BlockState &blocks() {
+  static BlockState *s = new BlockState;
+  return *s;
+}
+
+size_t block_round(size_t n) {
+  const size_t g = n >= ((size_t)1 << 20) ? ((size_t)64 << 10) : 256;
+  return (n + g - 1) / g * g;
+}
+
+void cache_drop_all(BlockCache &c) {
+  for (auto &kv : c.by_size) (void)hipFree(kv.second);
+  c.by_size.clear();
+  c.held = 0;
+}
+}  // namespace
+
+void *dev_block_get(size_t want, size_t *got) {
+  int dev = 0;
+  GVT_HIP_CHECK(hipGetDevice(&dev));
+  const size_t n = block_round(want);
+  BlockState &B = blocks();
+  std::lock_guard<std::mutex> lk(B.mu);
+  BlockCache &c = B.cache[dev];
+  auto it = c.by_size.lower_bound(n);
+  if (it != c.by_size.end() && it->first <= 2 * n) {
+    void *p = it->second;
+    *got = it->first;
+    c.held -= it->first;
+    c.by_size.erase(it);
+    B.dev_of[p] = dev;
+    return p;
+  }
+  void *p = nullptr;
+  if (hipMalloc(&p, n) != hipSuccess) {
+    (void)hipGetLastError();
+    GVT_HIP_CHECK(hipDeviceSynchronize());
+    cache_drop_all(c);
+    if (hipMalloc(&p, n) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{GVT_ERR_NOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
+    }
+  }
+  *got = n;
+  B.dev_of[p] = dev;
+  return p;
+}
+
+void dev_block_put(void *p, size_t got) {
+  BlockState &B = blocks();
+  std::lock_guard<std::mutex> lk(B.mu);
+  auto d = B.dev_of.find(p);
+  const int dev = d == B.dev_of.end() ? -1 : d->second;
+  if (d != B.dev_of.end()) B.dev_of.erase(d);
+  int cur = 0;
+  if (dev < 0 || hipGetDevice(&cur) != hipSuccess) {
+    (void)hipFree(p);
+    return;
+  }
+  if (cur != dev) (void)hipSetDevice(dev);
+  // the device finishes what may still read or write the block
+  if (hipDeviceSynchronize() != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(p);
+  } else {
+    BlockCache &c = B.cache[dev];
+    c.by_size.emplace(got, p);
+    c.held += got;
+    while (c.held > kBlockCacheMax && !c.by_size.empty()) {
+      auto last = std::prev(c.by_size.end());
+      (void)hipFree(last->second);
+      c.held -= last->first;
+      c.by_size.erase(last);
+    }
+  }
+  if (cur != dev) (void)hipSetDevice(cur);
+}
 
 // Pinned staging buffer shared by every plan upload of the process (grow-only).
 static std::mutex g_stage_mu;

@@ -55,6 +55,11 @@ template <class F> int guarded(F &&body) {
 }
 
 // ---- device memory ----------------------------------------------------------
+// Device blocks for DevMem: released blocks are kept per device for reuse
+// (see api.hip); get throws GVT_ERR_NOMEM when the device is full.
+void *dev_block_get(size_t want, size_t *got);
+void dev_block_put(void *p, size_t got);
+
 struct DevMem {
   void *p = nullptr;
   size_t bytes = 0;
@@ -73,7 +78,7 @@ struct DevMem {
   }
   ~DevMem() { release(); }
   void release() {
-    if (p && owned) (void)hipFree(p);
+    if (p && owned) dev_block_put(p, bytes);
     p = nullptr;
     bytes = 0;
     owned = true;
@@ -84,17 +89,13 @@ struct DevMem {
     bytes = nbytes;
     owned = false;
   }
-  // Grow-only; contents are not preserved.
+  // Grow-only; contents are not preserved.  `bytes` is the block's capacity.
   void *ensure(size_t nbytes) {
     if (nbytes <= bytes && p) return p;
     release();
-    size_t want = nbytes ? nbytes : 256;
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess) {
-      p = nullptr;
-      throw Error{GVT_ERR_NOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed"};
-    }
-    bytes = want;
+    size_t got = 0;
+    p = dev_block_get(nbytes ? nbytes : 256, &got);
+    bytes = got;
     return p;
   }
   template <class T> T *as() const { return static_cast<T *>(p); }
