@@ -290,6 +290,20 @@ int gvt_plan_profile(gvt_plan_t plan, int prec, const void *D, int64_t ldd, cons
  */
 int gvt_plan_info(gvt_plan_t plan, double *info);
 
+/*
+ * gvt_empty_cache — releases the memory the library keeps for reuse.  Device
+ * blocks that plans, products and solves give back are kept in a per-device
+ * cache (at most 4 GiB per device, reused by later requests of up to twice
+ * their size) instead of being freed, and plan uploads go through one pinned
+ * host staging buffer.  This frees every cached block on every device and the
+ * staging buffer; blocks held by live plans or running calls are not touched,
+ * and later calls allocate again.  *freed_bytes (host, may be NULL) receives
+ * the device bytes freed.  For callers that share the GPU with another
+ * allocator (a framework's own cache) or want memory back between phases.
+ * Thread-safe; returns GVT_OK, or GVT_ERR_HIP if selecting a device fails.
+ */
+int gvt_empty_cache(int64_t *freed_bytes);
+
 /* Message describing the calling thread's most recent error ("" if none). */
 const char *gvt_last_error(void);
 

@@ -21,6 +21,7 @@ from ._binding import (  # noqa: F401
     GvtError,
     Plan,
     gvt_dense_matvec,
+    gvt_empty_cache,
     gvt_krr_cg,
     gvt_krr_cg_batched,
     gvt_last_error,

@@ -63,8 +63,9 @@ def load_library():
     lib.gvt_krr_cg_batched.argtypes = [I, P, I, P, I, I, ctypes.c_double, I, I, P, P, P]
     lib.gvt_plan_profile.argtypes = [P, I, P, I64, P, I64, P, I64, I64, P, I64, I, P, P]
     lib.gvt_plan_info.argtypes = [P, P]
+    lib.gvt_empty_cache.argtypes = [P]
     for f in ("gvt_plan_profile", "gvt_plan_info", "gvt_plan_create", "gvt_plan_destroy", "gvt_plan_execute", "gvt_matvec",
-              "gvt_pairwise_matvec", "gvt_dense_matvec", "gvt_krr_cg", "gvt_krr_cg_batched"):
+              "gvt_pairwise_matvec", "gvt_dense_matvec", "gvt_krr_cg", "gvt_krr_cg_batched", "gvt_empty_cache"):
         getattr(lib, f).restype = I
     _lib = lib
     return lib
@@ -82,6 +83,15 @@ def gvt_last_error() -> str:
 
 def gvt_version() -> int:
     return int(load_library().gvt_version())
+
+
+def gvt_empty_cache() -> int:
+    """Free the library's cached device blocks and staging buffer; returns the
+    device bytes freed."""
+    lib = load_library()
+    freed = ctypes.c_int64(0)
+    _check(lib.gvt_empty_cache(ctypes.byref(freed)))
+    return int(freed.value)
 
 
 # ------------------------------------------------------------------ helpers

@@ -120,10 +120,39 @@ void dev_block_put(void *p, size_t got) {
   if (cur != dev) (void)hipSetDevice(cur);
 }
 
-// Pinned staging buffer shared by every plan upload of the process (grow-only).
+// Pinned staging buffer shared by every plan upload of the process (grows on
+// demand; gvt_empty_cache frees it).
 static std::mutex g_stage_mu;
 static void *g_stage = nullptr;
 static size_t g_stage_bytes = 0;
+
+// Frees every cached device block on every device and the staging buffer;
+// returns the device bytes freed.  Cached blocks are idle (each came back
+// after its device had drained), and blocks in use by plans are not cached.
+static size_t empty_caches() {
+  size_t freed = 0;
+  {
+    BlockState &B = blocks();
+    std::lock_guard<std::mutex> lk(B.mu);
+    int cur = 0;
+    GVT_HIP_CHECK(hipGetDevice(&cur));
+    struct Restore {
+      int dev;
+      ~Restore() { (void)hipSetDevice(dev); }
+    } restore{cur};
+    for (auto &kv : B.cache) {
+      if (kv.second.by_size.empty()) continue;
+      GVT_HIP_CHECK(hipSetDevice(kv.first));
+      freed += kv.second.held;
+      cache_drop_all(kv.second);
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_stage_mu);
+  if (g_stage) (void)hipHostFree(g_stage);
+  g_stage = nullptr;
+  g_stage_bytes = 0;
+  return freed;
+}
 
 void Uploads::commit(DevMem &blob) {
   size_t total = 0;
@@ -172,6 +201,14 @@ extern "C" {
 const char *gvt_last_error(void) { return g_last_error.c_str(); }
 
 int gvt_version(void) { return 100; }
+
+int gvt_empty_cache(int64_t *freed_bytes) {
+  return guarded([&]() {
+    const size_t f = empty_caches();
+    if (freed_bytes) *freed_bytes = (int64_t)f;
+    return GVT_OK;
+  });
+}
 
 int gvt_plan_create(gvt_plan_t *plan, const int *kinds, int nkinds, int64_t d_rows, int64_t d_cols,
                     int64_t t_rows, int64_t t_cols, const int32_t *out_a, const int32_t *out_b,

@@ -589,3 +589,29 @@ def test_stage1_wide_rows_bitwise(gvt, prec, lo, hi, order, gaps, monkeypatch):
         monkeypatch.setenv("GVT_STAGE1_WIDE", "1")
         got = gvt.gvt_pairwise_matvec(["kronecker"], Dd, Td, *args, flags=order)
         assert torch.equal(got, ref), nrhs
+
+
+def test_empty_cache_frees_blocks_and_later_calls_match(gvt):
+    # a one-shot product gives its plan's device blocks back to the library's cache;
+    # emptying the cache frees them (device memory does not shrink), a second call finds
+    # nothing to free, and the product computed afterwards on fresh blocks is bitwise equal
+    p = W.make_heterogeneous(99, 0, 120, 90, 6000, 6, n_out=4000)
+    D, T = dev(p["D"]), dev(p["T"])
+    args = ((idx(p["a"]), idx(p["b"])), (idx(p["c"]), idx(p["e"])), dev(p["v"]))
+    before = gvt.gvt_matvec(D, T, *args)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    freed = gvt.gvt_empty_cache()
+    free1 = torch.cuda.mem_get_info()[0]
+    assert freed > 0 and free1 >= free0
+    assert gvt.gvt_empty_cache() == 0
+    after = gvt.gvt_matvec(D, T, *args)
+    assert torch.equal(before, after)
+    ref = oracle.pairwise_matvec("kronecker", p["D"], p["T"], (p["a"], p["b"]), (p["c"], p["e"]), p["v"])
+    assert relerr(after.cpu().numpy(), ref) < 1e-10
+    # a solve after emptying allocates afresh and still converges
+    gvt.gvt_empty_cache()
+    q = W.make_heterogeneous(99, 1, 40, 30, 600, 6, labels=True)
+    A, it, rr, code = gvt.gvt_krr_cg("kronecker", dev(q["D"]), dev(q["T"]), (idx(q["c"]), idx(q["e"])),
+                                     dev(q["y"]), [1.0], max_iter=200, tol=1e-6)
+    assert code == 0 and rr[0] < 1e-6
