@@ -615,3 +615,49 @@ def test_empty_cache_frees_blocks_and_later_calls_match(gvt):
     A, it, rr, code = gvt.gvt_krr_cg("kronecker", dev(q["D"]), dev(q["T"]), (idx(q["c"]), idx(q["e"])),
                                      dev(q["y"]), [1.0], max_iter=200, tol=1e-6)
     assert code == 0 and rr[0] < 1e-6
+
+
+def test_side_streams_and_threads_match_sequential(gvt):
+    # every call runs on the caller's current stream: two host threads, each on a side
+    # stream of its own with its own plan (one device-built, one host-built) plus one-shot
+    # calls that plan internally, give bitwise the products that the default stream gives
+    # one call after another
+    import threading
+
+    probs = []
+    for i, (n, n_out) in enumerate([(60000, 20000), (9000, 4000)]):
+        p = W.make_heterogeneous(100, i, 400, 300, n, 6, n_out=n_out, nrhs=2)
+        probs.append(dict(D=dev(p["D"]), T=dev(p["T"]), out=(idx(p["a"]), idx(p["b"])),
+                          inp=(idx(p["c"]), idx(p["e"])), v=dev(p["v"])))
+
+    def run(q, reps):
+        pl = gvt.gvt_plan_create("kronecker", q["D"].shape, q["T"].shape, q["out"], q["inp"])
+        outs = [gvt.gvt_plan_execute(pl, q["D"], q["T"], q["v"]).clone() for _ in range(reps)]
+        outs.append(gvt.gvt_matvec(q["D"], q["T"], q["out"], q["inp"], q["v"]))
+        pl.close()
+        return outs
+
+    ref = [run(q, 1)[0] for q in probs]
+    torch.cuda.synchronize()
+    got, errors = [None] * len(probs), []
+
+    def work(k):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                outs = run(probs[k], 6)
+            s.synchronize()
+            got[k] = outs
+        except Exception as ex:  # reported on the main thread
+            errors.append(ex)
+
+    th = [threading.Thread(target=work, args=(k,)) for k in range(len(probs))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    for k in range(len(probs)):
+        assert len(got[k]) == 7
+        for u in got[k]:
+            assert torch.equal(u.reshape(ref[k].shape), ref[k]), k
