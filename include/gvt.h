@@ -34,6 +34,10 @@
  *    complete-data dense path only.
  *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
  *    and the call returns without synchronising unless stated.
+ *  - Threads: calls from several host threads may run at once, on streams of
+ *    their own, as long as each plan is used by one stream at a time (a plan
+ *    owns the workspaces its products write).  The library's only shared state
+ *    is its cache of device blocks and its upload staging buffer, both locked.
  *  - Errors: 0 = success, > 0 = warning (results written), < 0 = error.
  *    gvt_last_error() returns a message for the calling thread's last error.
  *    Error paths never leave kernels running on the stream.
