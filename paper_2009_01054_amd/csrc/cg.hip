@@ -20,6 +20,7 @@ namespace gvt {
 
 static constexpr int RB = 256;   // reduction block size
 static constexpr int RNB = 240;  // reduction grid (fixed for determinism)
+static constexpr int CG_PF = 4;  // elements per thread loaded ahead of a fold
 static_assert(RNB <= RB, "partials are folded by one block");
 
 enum CgState { CG_DONE = 0, CG_ACTIVE = 1, CG_PENDING = 2, CG_BREAKDOWN = 3, CG_MAXITER = 4 };
@@ -119,14 +120,37 @@ __global__ __launch_bounds__(RB) void cg_update_kernel(double *__restrict__ a, i
   for (int l = 0; l < nlam; ++l) {
     double acc = 0.0;
     if (sc[l].state == CG_ACTIVE) {  // uniform: state is not written by this kernel
+      // this thread's first CG_PF elements are loaded before the fold, so the two
+      // round trips to memory overlap; the sums keep their element order
+      const int64_t i0 = (int64_t)blockIdx.x * RB + threadIdx.x, st = (int64_t)RNB * RB;
+      double pa[CG_PF], pp[CG_PF], pr[CG_PF], pwr[CG_PF];
+#pragma unroll
+      for (int k = 0; k < CG_PF; ++k) {
+        const int64_t i = i0 + k * st;
+        if (i < n) {
+          pa[k] = a[i + l * lda];
+          pp[k] = p[i + l * n];
+          pr[k] = r[i + l * n];
+          pwr[k] = (double)wraw[i + l * n];
+        }
+      }
       const double pw = fold_partials(part_pw, nlam, l, sh);
       const double rho = sc[l].rho;
       const bool ok = pw > 0.0 && isfinite(pw);
       const double al = rho / pw;
       if (ok) {
         const double lm = lam[l];
-#pragma unroll 4
-        for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)RNB * RB) {
+#pragma unroll
+        for (int k = 0; k < CG_PF; ++k) {
+          const int64_t i = i0 + k * st;
+          if (i < n) {
+            a[i + l * lda] = pa[k] + al * pp[k];
+            const double ri = pr[k] - al * (pwr[k] + lm * pp[k]);
+            r[i + l * n] = ri;
+            acc += ri * ri;
+          }
+        }
+        for (int64_t i = i0 + CG_PF * st; i < n; i += st) {
           a[i + l * lda] += al * p[i + l * n];
           const double ri = r[i + l * n] - al * cg_w(wraw, p, lm, i + l * n);
           r[i + l * n] = ri;
@@ -175,15 +199,39 @@ __global__ __launch_bounds__(RB) void cg_p_kernel(double *__restrict__ p, float 
       if (rec) sc[l].state = CG_BREAKDOWN;
       continue;
     }
+    TV *__restrict__ vs0 = pk.vs[0];
+    TV *__restrict__ vs1 = pk.vs[1];
+    const int32_t *__restrict__ inv0 = pk.inv[0];
+    const int32_t *__restrict__ inv1 = pk.inv[1];
+    // as in the update: the first CG_PF elements' loads overlap the fold
+    const int64_t i0 = (int64_t)blockIdx.x * RB + threadIdx.x, st = (int64_t)RNB * RB;
+    double qr[CG_PF], qp[CG_PF];
+    int32_t q0[CG_PF], q1[CG_PF];
+#pragma unroll
+    for (int k = 0; k < CG_PF; ++k) {
+      const int64_t i = i0 + k * st;
+      if (i < n) {
+        qr[k] = r[i + l * n];
+        qp[k] = p[i + l * n];
+        q0[k] = vs0 ? inv0[i] : 0;
+        q1[k] = vs1 ? inv1[i] : 0;
+      }
+    }
     const double rho_new = fold_partials(part_rr, nlam, l, sh);
     const double beta = rho_new / sc[l].rho_prev;
     if (isfinite(rho_new)) {
-      TV *__restrict__ vs0 = pk.vs[0];
-      TV *__restrict__ vs1 = pk.vs[1];
-      const int32_t *__restrict__ inv0 = pk.inv[0];
-      const int32_t *__restrict__ inv1 = pk.inv[1];
-#pragma unroll 4
-      for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)RNB * RB) {
+#pragma unroll
+      for (int k = 0; k < CG_PF; ++k) {
+        const int64_t i = i0 + k * st;
+        if (i < n) {
+          const double pi = qr[k] + beta * qp[k];
+          p[i + l * n] = pi;
+          if (p32) p32[i + l * n] = (float)pi;
+          if (vs0) vs0[(int64_t)q0[k] * nlam + l] = (TV)pi;
+          if (vs1) vs1[(int64_t)q1[k] * nlam + l] = (TV)pi;
+        }
+      }
+      for (int64_t i = i0 + CG_PF * st; i < n; i += st) {
         const double pi = r[i + l * n] + beta * p[i + l * n];
         p[i + l * n] = pi;
         if (p32) p32[i + l * n] = (float)pi;
