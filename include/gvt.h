@@ -216,7 +216,10 @@ int gvt_dense_matvec(int prec, const void *M, int64_t m_rows, int64_t m_cols, in
  * FP32, everything else FP64; when the recurrence residual meets `tol` the
  * true residual is recomputed with an FP64 product and CG restarts from it
  * unless it also meets `tol`).  check_every: iterations between host
- * convergence checks (>= 1).  iters_out[nlam] and relres_out[nlam] (host)
+ * convergence checks (>= 1); on a non-null stream each such block of
+ * iterations after the first is captured once into a HIP graph and replayed,
+ * on the null stream it is launched kernel by kernel (bitwise the same
+ * results either way).  iters_out[nlam] and relres_out[nlam] (host)
  * receive the iteration counts and the TRUE relative residuals
  * ||y - (K + lambda I) a|| / ||y|| computed with an FP64 product.
  * Synchronises `stream`.  Returns GVT_OK when every system met `tol`,

@@ -661,3 +661,40 @@ def test_side_streams_and_threads_match_sequential(gvt):
         assert len(got[k]) == 7
         for u in got[k]:
             assert torch.equal(u.reshape(ref[k].shape), ref[k]), k
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cg_graph_replays_on_side_stream_bitwise(gvt, prec):
+    # on a non-null stream the CG iterations after the first are captured once into a
+    # graph and replayed (here every 2 iterations, so about 20 replays); on the null
+    # stream they are launched one by one.  Both give bitwise the same solves, single
+    # and batched, including the FP32 products' certification and restarts
+    mp = gvt.F64 if prec == "f64" else gvt.F32
+    p = W.make_heterogeneous(94, 0, 60, 50, 1500, 32, labels=True)
+    args = ("kronecker", dev(p["D"]), dev(p["T"]), (idx(p["c"]), idx(p["e"])), dev(p["y"]),
+            [1e-3, 1e-1, 1.0])
+    probs = []
+    for i, (m, q, n) in enumerate([(30, 20, 300), (50, 35, 900), (12, 40, 200)]):
+        pr = W.make_heterogeneous(98, i, m, q, n, 6, labels=True)
+        probs.append(dict(D=dev(pr["D"]), T=dev(pr["T"]), c=idx(pr["c"]), e=idx(pr["e"]), y=dev(pr["y"])))
+    torch.cuda.synchronize()
+
+    def both():
+        one = gvt.gvt_krr_cg(*args, max_iter=300, tol=1e-8, matvec_prec=mp, check_every=2)
+        many = gvt.gvt_krr_cg_batched("kronecker", probs, [1e-2, 1.0], max_iter=200, tol=1e-8,
+                                      matvec_prec=mp, check_every=2)
+        return one, many
+
+    eager = both()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        graph = both()
+    side.synchronize()
+    (A0, i0, r0, c0), (A1, i1, r1, c1) = eager[0], graph[0]
+    assert c0 == c1 and torch.equal(A0, A1) and (i0 == i1).all() and (r0 == r1).all()
+    if prec == "f64":  # the oracle needs 66, 55 and 29 iterations
+        assert c0 == 0 and (r0 < 1e-8).all()
+    (B0, j0, s0, d0), (B1, j1, s1, d1) = eager[1], graph[1]
+    assert d0 == d1 and (j0 == j1).all() and (s0 == s1).all()
+    for x, z in zip(B0, B1):
+        assert torch.equal(x, z)
