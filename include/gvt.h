@@ -38,6 +38,10 @@
  *    their own, as long as each plan is used by one stream at a time (a plan
  *    owns the workspaces its products write).  The library's only shared state
  *    is its cache of device blocks and its upload staging buffer, both locked.
+ *    Giving a device block back (the end of a solve or of a one-shot product,
+ *    gvt_plan_destroy, a plan workspace that grows) waits until the device has
+ *    finished the work queued on all its streams, as hipFree does; no lock is
+ *    held during that wait, so other threads' calls proceed meanwhile.
  *  - Errors: 0 = success, > 0 = warning (results written), < 0 = error.
  *    gvt_last_error() returns a message for the calling thread's last error.
  *    Error paths never leave kernels running on the stream.
@@ -47,8 +51,7 @@
  *    Environment variables read when a plan is built override them for
  *    tuning sweeps: GVT_STAGE1_WIDE (0/1: stage 1 holds 16 bytes of
  *    consecutive rows per lane over a contiguous row range), GVT_STAGE1_KPW
- *    (1, 2, 4 keys per wave), GVT_STAGE1_LDS (0/1: F2 columns staged in LDS)
- *    and GVT_STAGE1_LDS_KPW, GVT_STAGE2_TARGET_R1 / _R8 (stage-2 outputs per
+ *    (1, 2, 4 keys per wave), GVT_STAGE2_TARGET_R1 / _R8 (stage-2 outputs per
  *    group row and tile), GVT_MAX_RHS_BLOCK[_F64|_F32] (largest RHS block of
  *    a pass), GVT_PLAN_DEVICE (0/1: plan index work on the host / device).
  *    All of them but the RHS block give the same products bit for bit (the

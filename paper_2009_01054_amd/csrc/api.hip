@@ -92,30 +92,42 @@ void *dev_block_get(size_t want, size_t *got) {
 
 void dev_block_put(void *p, size_t got) {
   BlockState &B = blocks();
-  std::lock_guard<std::mutex> lk(B.mu);
-  auto d = B.dev_of.find(p);
-  const int dev = d == B.dev_of.end() ? -1 : d->second;
-  if (d != B.dev_of.end()) B.dev_of.erase(d);
+  int dev = -1;
+  {
+    std::lock_guard<std::mutex> lk(B.mu);
+    auto d = B.dev_of.find(p);
+    if (d != B.dev_of.end()) {
+      dev = d->second;
+      B.dev_of.erase(d);
+    }
+  }
   int cur = 0;
   if (dev < 0 || hipGetDevice(&cur) != hipSuccess) {
     (void)hipFree(p);
     return;
   }
   if (cur != dev) (void)hipSetDevice(dev);
-  // the device finishes what may still read or write the block
+  // The device finishes what may still read or write the block (every stream,
+  // as hipFree waits).  The wait holds no lock, so other threads' requests and
+  // releases go on meanwhile; the block is not in the cache until it is idle.
   if (hipDeviceSynchronize() != hipSuccess) {
     (void)hipGetLastError();
     (void)hipFree(p);
   } else {
-    BlockCache &c = B.cache[dev];
-    c.by_size.emplace(got, p);
-    c.held += got;
-    while (c.held > kBlockCacheMax && !c.by_size.empty()) {
-      auto last = std::prev(c.by_size.end());
-      (void)hipFree(last->second);
-      c.held -= last->first;
-      c.by_size.erase(last);
+    std::vector<void *> drop;
+    {
+      std::lock_guard<std::mutex> lk(B.mu);
+      BlockCache &c = B.cache[dev];
+      c.by_size.emplace(got, p);
+      c.held += got;
+      while (c.held > kBlockCacheMax && !c.by_size.empty()) {
+        auto last = std::prev(c.by_size.end());
+        drop.push_back(last->second);
+        c.held -= last->first;
+        c.by_size.erase(last);
+      }
     }
+    for (void *q : drop) (void)hipFree(q);
   }
   if (cur != dev) (void)hipSetDevice(cur);
 }

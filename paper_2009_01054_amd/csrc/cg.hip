@@ -272,9 +272,10 @@ __global__ void cg_init_kernel(CgScalars *sc, const double *__restrict__ ynorm2,
     CgScalars c;
     c.pw = c.alpha = c.beta = c.rho_prev = 0.0;
     c.iters = c.gate = c.pad0 = 0;
-    c.ynorm = yn;
+    // all-zero labels: residuals are measured against 1 (a = 0 solves the system)
+    c.ynorm = yn == 0.0 ? 1.0 : yn;
     c.rho = rho0 ? rho0[l] : *ynorm2;
-    c.state = !isfinite(yn) ? CG_BREAKDOWN : (sqrt(c.rho) / yn < tol ? CG_DONE : CG_ACTIVE);
+    c.state = !isfinite(yn) ? CG_BREAKDOWN : (sqrt(c.rho) / c.ynorm < tol ? CG_DONE : CG_ACTIVE);
     any |= c.state == CG_ACTIVE;
     sc[l] = c;
   }

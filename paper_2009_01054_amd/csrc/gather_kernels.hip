@@ -262,148 +262,6 @@ __global__ __launch_bounds__(256) void stage1_wide_kernel(
   stage1_wide_block<T, R, KPW>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, S, ldS, kb, rb, stg);
 }
 
-// Stage 1 with LDS-staged columns.  The keys of a block reference the same
-// F2 columns many times (every key segment runs over the same range of other
-// indices), so the block stages the columns of one chunk of OC other
-// indices, for its 64 rows, in LDS (128 KB: one block per CU), and every wave
-// then walks the part of its keys' segments that falls in the chunk, reading
-// the column values from LDS.  A block has 16 waves and 16 x KPW keys, so each
-// staged column serves many pairs.  The accumulators of all of a wave's keys
-// stay in registers across chunks.  Segments are sorted by other index, so
-// each key still sums its pairs in segment order: the result equals the
-// direct walk's bit for bit.  The staging buffer is reused for the result
-// tile.
-template <class T, int R, int KPW> struct S1LdsCfg {
-  static constexpr int NW = 16;                                 // waves per block
-  static constexpr int NT = NW * 64;
-  static constexpr int KB = NW * KPW;                           // keys per block
-  static constexpr int CM = (128 * 1024) / (64 * kStage1OtherChunk * (int)sizeof(T));
-  static constexpr int OC = kStage1OtherChunk * CM;             // columns per staged chunk
-  static constexpr int COLS = OC * 64;                          // staged column values
-  static constexpr int STG = 64 * (KB * R + 1);                 // result tile
-  static constexpr int SIZE = COLS > STG ? COLS : STG;
-};
-
-template <class T, int R, int KPW>
-__device__ __forceinline__ void stage1_lds_block(
-    const T *__restrict__ Fc, int64_t ldc, const int32_t *__restrict__ rows, int64_t nrows,
-    const int32_t *__restrict__ cseg, int64_t nch, const int32_t *__restrict__ other,
-    const T *__restrict__ vs, int64_t nkeys, int64_t nother, T *__restrict__ S, int64_t ldS,
-    int64_t kb, int64_t rb, T *lds) {
-  typedef S1LdsCfg<T, R, KPW> C;
-  constexpr int OC = C::OC, NW = C::NW;
-  constexpr int W = C::KB * R;
-  const int64_t nst = (nch + C::CM - 1) / C::CM;  // staged chunks (nch: cseg chunks)
-  const int lane = threadIdx.x & 63;
-  const int w = wave_id_uniform();
-  const int64_t k0 = kb * C::KB;
-  const int64_t rho0 = rb * 64;
-  // staging: this thread fills row `lane` of the chunk's columns oc = wave, wave + NW, ...
-  const int64_t frho = rho0 + lane;
-  const bool frow_ok = frho < nrows;
-  const int64_t fy = frow_ok ? rows[frho] : 0;  // row 0 stands in for rows past the end
-  T acc[KPW][R];
-#pragma unroll
-  for (int kk = 0; kk < KPW; ++kk)
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[kk][r] = T(0);
-  // A full block whose 64 rows are consecutive F rows, 16-byte aligned, reads
-  // each staged column as one contiguous run: wave-wide global-to-LDS loads
-  // then fill CPI columns per instruction without registers.  Other blocks
-  // gather the column values through registers.
-  constexpr int VEC = 16 / (int)sizeof(T);  // values per 16-byte piece
-  constexpr int LPC = 64 / VEC;             // lanes per staged column
-  constexpr int CPI = 64 / LPC;             // columns per wave instruction
-  static_assert(OC % (NW * CPI) == 0, "whole instructions per wave and chunk");
-  bool dma = false;
-  if (rho0 + 64 <= nrows) {  // uniform
-    const int64_t y0 = rows[rho0];
-    dma = rows[rho0 + 63] - y0 == 63 && y0 % VEC == 0 && ldc % VEC == 0 &&
-          reinterpret_cast<uintptr_t>(Fc) % 16 == 0;
-  }
-  const int64_t dy0 = dma ? (int64_t)rows[rho0] : 0;
-  auto stage = [&](int64_t c, T *buf) {
-    const int64_t o0 = c * OC;
-    if (dma) {
-      // columns past the last other index load an in-range column; no key
-      // segment refers to them
-      const int col_in = lane / LPC, piece = lane % LPC;
-      for (int q = w; q < OC / CPI; q += NW) {
-        const int64_t o = o0 + q * CPI + col_in;
-        lds_load_row16(Fc + (o < nother ? o : nother - 1) * ldc + dy0 + piece * VEC,
-                       buf + q * CPI * 64);
-      }
-    } else {
-      // unconditional loads from clamped in-range addresses, so that they all
-      // issue before the first wait; out-of-range values are replaced by zero
-#pragma unroll 8
-      for (int oc = w; oc < OC; oc += NW) {
-        const int64_t o = o0 + oc;
-        const T v = Fc[(o < nother ? o : nother - 1) * ldc + fy];
-        buf[oc * 64 + lane] = (o < nother && frow_ok) ? v : T(0);
-      }
-    }
-  };
-  for (int64_t c = 0; c < nst; ++c) {
-    const int64_t o0 = c * OC;
-    const T *cur = lds;
-    __syncthreads();  // the previous chunk's reads are done
-    stage(c, lds);
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the chunk has landed
-    __syncthreads();
-    // unrolled over the wave's keys, so that each key's accumulators are fixed
-    // registers (a runtime key index turns every accumulation into selects)
-#pragma unroll
-    for (int kk = 0; kk < KPW; ++kk) {
-      const int64_t k = k0 + w * KPW + kk;
-      if (k < nkeys) {  // uniform
-        const int64_t c0 = c * C::CM, c1 = c0 + C::CM < nch ? c0 + C::CM : nch;
-        const int64_t p0 = cseg[k * (nch + 1) + c0], p1 = cseg[k * (nch + 1) + c1];
-        const T *col = cur + lane - o0 * 64;
-#pragma unroll 8
-        for (int64_t p = p0; p < p1; ++p) {
-          const T f = col[(int64_t)other[p] * 64];
-#pragma unroll
-          for (int r = 0; r < R; ++r) acc[kk][r] += f * vs[p * R + r];
-        }
-      }
-    }
-  }
-  __syncthreads();  // done with the columns: the buffer becomes the result tile
-#pragma unroll
-  for (int kk = 0; kk < KPW; ++kk)
-#pragma unroll
-    for (int r = 0; r < R; ++r) lds[lane * (W + 1) + (w * KPW + kk) * R + r] = acc[kk][r];
-  __syncthreads();
-  const int64_t kcount = (nkeys - k0) < C::KB ? (nkeys - k0) : C::KB;
-  const int width = (int)kcount * R;
-  for (int idx = threadIdx.x; idx < 64 * W; idx += C::NT) {
-    const int rr = idx / W, cc = idx - rr * W;
-    const int64_t orow = rho0 + rr;
-    if (orow < nrows && cc < width) S[orow * ldS + k0 * R + cc] = lds[rr * (W + 1) + cc];
-  }
-  // the last key block also clears the row padding (read by stage 2 as whole chunks)
-  if (k0 + C::KB >= nkeys) {
-    const int64_t padw = ldS - nkeys * R;
-    for (int64_t idx = threadIdx.x; idx < 64 * padw; idx += C::NT) {
-      const int64_t rr = idx / padw, cc = idx - rr * padw;
-      if (rho0 + rr < nrows) S[(rho0 + rr) * ldS + nkeys * R + cc] = T(0);
-    }
-  }
-}
-
-template <class T, int R, int KPW>
-__global__ __launch_bounds__(1024) void stage1_lds_kernel(
-    const T *__restrict__ Fc, int64_t ldc, const int32_t *__restrict__ rows, int64_t nrows,
-    const int32_t *__restrict__ cseg, int64_t nch, const int32_t *__restrict__ other,
-    const T *__restrict__ vs, int64_t nkeys, int64_t nother, T *__restrict__ S, int64_t ldS,
-    const int *__restrict__ gate) {
-  __shared__ __attribute__((aligned(16))) T lds[S1LdsCfg<T, R, KPW>::SIZE];
-  if (gate && *gate == 0) return;
-  stage1_lds_block<T, R, KPW>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys, nother, S, ldS,
-                              blockIdx.x, blockIdx.y, lds);
-}
-
 // Degenerate stage 1 (key == other index): S[rho, k] = F2[rows[rho], k] * s[k].
 template <class T>
 __global__ void colscale_kernel(const T *__restrict__ F, int64_t ldf, const int32_t *__restrict__ rows,
@@ -1031,22 +889,15 @@ static void stage1_rk(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nro
 }
 
 // Launch knobs of stage 1: the tuned constants (tuning.h), overridable through
-// GVT_STAGE1_KPW (1, 2 or 4 keys per wave), GVT_STAGE1_LDS (0 / 1 forces the
-// LDS-staged walk off / on), GVT_STAGE1_LDS_KPW (2, 4 or 8) and
-// GVT_STAGE1_WIDE (0 / 1: several rows per lane over contiguous rows) for
-// tuning sweeps.  The environment is read when a plan is built, not per launch.
-static std::atomic<int> g_s1_kpw{kStage1KeysPerWave}, g_s1_lds{-1},
-    g_s1_lds_kpw{kStage1LdsKeysPerWave}, g_s1_wide{kStage1Wide};
+// GVT_STAGE1_KPW (1, 2 or 4 keys per wave) and GVT_STAGE1_WIDE (0 / 1: several
+// rows per lane over contiguous rows) for tuning sweeps.  The environment is
+// read when a plan is built, not per launch.
+static std::atomic<int> g_s1_kpw{kStage1KeysPerWave}, g_s1_wide{kStage1Wide};
 
 void refresh_launch_knobs() {
   const char *e1 = std::getenv("GVT_STAGE1_KPW");
   const int k = e1 ? std::atoi(e1) : kStage1KeysPerWave;
   g_s1_kpw.store((k == 1 || k == 2 || k == 4) ? k : 4, std::memory_order_relaxed);
-  const char *e2 = std::getenv("GVT_STAGE1_LDS");
-  g_s1_lds.store(e2 ? (std::atoi(e2) != 0) : -1, std::memory_order_relaxed);
-  const char *e3 = std::getenv("GVT_STAGE1_LDS_KPW");
-  const int kl = e3 ? std::atoi(e3) : kStage1LdsKeysPerWave;
-  g_s1_lds_kpw.store((kl == 2 || kl == 4 || kl == 8) ? kl : 4, std::memory_order_relaxed);
   const char *e4 = std::getenv("GVT_STAGE1_WIDE");
   g_s1_wide.store(e4 ? (std::atoi(e4) != 0) : kStage1Wide, std::memory_order_relaxed);
 }
@@ -1064,36 +915,6 @@ static void stage1_r(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrow
     case 2: stage1_rk<T, R, 2>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
     default: stage1_rk<T, R, 4>(Fc, ldc, rows, nrows, seg, other, vs, nkeys, S, ldS, s, gate); break;
   }
-}
-
-template <class T, int R, int KPW>
-static void stage1_lds_rk(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows,
-                          const int32_t *cseg, int64_t nch, const int32_t *other, const T *vs,
-                          int64_t nkeys, int64_t nother, T *S, int64_t ldS, hipStream_t s,
-                          const int *gate) {
-  dim3 grid((unsigned)ceil_div(nkeys, S1LdsCfg<T, R, KPW>::KB), (unsigned)ceil_div(nrows, 64));
-  stage1_lds_kernel<T, R, KPW><<<grid, S1LdsCfg<T, R, KPW>::NT, 0, s>>>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys,
-                                                     nother, S, ldS, gate);
-}
-
-// Keys per wave of the LDS-staged stage 1 (more keys = more reuse of each
-// staged column, bounded by the accumulator registers KPW x R).
-static int stage1_lds_kpw(int R) {
-  int k = g_s1_lds_kpw.load(std::memory_order_relaxed);
-  while (k > 2 && k * R > 16) k /= 2;
-  return k;
-}
-
-// Whether the LDS-staged walk pays: each staged column must be used about
-// kStage1LdsMinReuse times by the block's keys, and a pair's packed v values
-// (read as scalars, R x sizeof(T) bytes) must not outweigh its LDS read
-// (GVT_STAGE1_LDS = 0 / 1 forces it either way).
-static bool stage1_use_lds(int64_t npairs, int64_t nkeys, int64_t nother, int kb, int vbytes) {
-  const int forced = g_s1_lds.load(std::memory_order_relaxed);
-  if (forced >= 0) return forced != 0;
-  if (nkeys <= 0 || nother <= 0 || vbytes > 8) return false;
-  const double reuse = (double)npairs / (double)nkeys * kb / (double)nother;
-  return reuse >= kStage1LdsMinReuse;
 }
 
 template <class T, int R, int KPW>
@@ -1155,27 +976,9 @@ static void stage1_direct(const T *Fc, int64_t ldc, const int32_t *rows, int64_t
 
 template <class T>
 void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, int64_t row0,
-                   const int64_t *seg, const int32_t *cseg, int64_t nch, const int32_t *other,
-                   int64_t npairs, int64_t nother, const T *vs, int64_t nkeys, int R, T *S,
-                   int64_t ldS, hipStream_t s, const int *gate) {
+                   const int64_t *seg, const int32_t *other, int64_t nother, const T *vs,
+                   int64_t nkeys, int R, T *S, int64_t ldS, hipStream_t s, const int *gate) {
   if (nrows <= 0 || nkeys <= 0) return;
-  const int kl = stage1_lds_kpw(R);
-  if (cseg && stage1_use_lds(npairs, nkeys, nother, S1LdsCfg<T, 1, 1>::NW * kl, R * (int)sizeof(T))) {
-#define GVT_S1L(RR, KK) stage1_lds_rk<T, RR, KK>(Fc, ldc, rows, nrows, cseg, nch, other, vs, nkeys, nother, S, ldS, s, gate)
-    switch (R * 16 + kl) {
-      case 16 + 2: GVT_S1L(1, 2); return;
-      case 16 + 4: GVT_S1L(1, 4); return;
-      case 16 + 8: GVT_S1L(1, 8); return;
-      case 32 + 2: GVT_S1L(2, 2); return;
-      case 32 + 4: GVT_S1L(2, 4); return;
-      case 32 + 8: GVT_S1L(2, 8); return;
-      case 64 + 2: GVT_S1L(4, 2); return;
-      case 64 + 4: GVT_S1L(4, 4); return;
-      case 128 + 2: GVT_S1L(8, 2); return;
-      default: break;
-    }
-#undef GVT_S1L
-  }
   // a contiguous range of at least 16 bytes of rows: several rows per lane
   if (row0 >= 0 && stage1_use_wide() && nrows >= 16 / (int64_t)sizeof(T)) {
     stage1_wide<T>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, nother, R, S, ldS, s, gate);
@@ -1334,9 +1137,8 @@ void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64
   template void launch_segsum<T>(const int64_t *, const T *, int64_t, int, T *, hipStream_t);    \
   template int64_t group_stage1_setup<T>(GroupDesc<T> &, int64_t);                               \
   template void launch_stage1<T>(const T *, int64_t, const int32_t *, int64_t, int64_t,         \
-                                 const int64_t *,                                                \
-                                 const int32_t *, int64_t, const int32_t *, int64_t, int64_t,    \
-                                 const T *, int64_t, int, T *, int64_t, hipStream_t, const int *);\
+                                 const int64_t *, const int32_t *, int64_t, const T *, int64_t,  \
+                                 int, T *, int64_t, hipStream_t, const int *);\
   template void launch_colscale<T>(const T *, int64_t, const int32_t *, int64_t, const T *,      \
                                    int64_t, int, T *, int64_t, hipStream_t);                     \
   template void launch_stage2<T>(const T *, int64_t, int64_t, const int64_t *, const int32_t *,  \

@@ -11,8 +11,6 @@ constexpr int kStage2Rows = 32;
 constexpr int kStage2MaxS = 64;
 constexpr double kL2BytesPerXcd = 4.0 * 1024 * 1024;  // gfx950: 4 MB of L2 per XCD
 constexpr int kMaxCombineOut = 8;
-// Stage 1 with LDS-staged columns: other indices per staged chunk.
-constexpr int kStage1OtherChunk = 128;
 
 // Row stride (elements) of a stage-1 buffer: nkeys x R values padded to whole
 // 1 KB chunks, the unit in which stage 2 copies S rows into LDS.
@@ -41,16 +39,14 @@ void launch_segsum(const int64_t *seg, const T *vs, int64_t nkeys, int R, T *out
 void refresh_launch_knobs();
 bool stage1_wide_enabled();  // the several-rows-per-lane stage-1 walk is on
 
-// Stage 1: the direct segment walk, or with LDS-staged columns when each
-// column is reused enough (cseg: per-key chunk starts, nch chunks; null = direct).
+// Stage 1: the segment walk over the key segments of the sorted input pairs.
 // row0 >= 0 states that rows[i] = row0 + i for every i, which allows the walk
 // with several rows per lane; -1 otherwise.
 template <class T>
 void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows, int64_t row0,
-                   const int64_t *seg,
-                   const int32_t *cseg, int64_t nch, const int32_t *other, int64_t npairs,
-                   int64_t nother, const T *vs, int64_t nkeys, int R, T *S, int64_t ldS,
-                   hipStream_t s, const int *gate = nullptr);
+                   const int64_t *seg, const int32_t *other, int64_t nother, const T *vs,
+                   int64_t nkeys, int R, T *S, int64_t ldS, hipStream_t s,
+                   const int *gate = nullptr);
 template <class T>
 void launch_colscale(const T *F, int64_t ldf, const int32_t *rows, int64_t nrows, const T *sv,
                      int64_t nkeys, int R, T *S, int64_t ldS, hipStream_t s);

@@ -22,10 +22,6 @@ struct InputSort {  // input pairs sorted by one index (key segments), then by t
   DevMem inv;    // int32[n_in]: input index j -> sorted position (inverse of perm)
   DevMem other;  // int32[n_in]: the other index of the pair at that position
   DevMem seg;    // int64[nkeys + 1]: segment offsets
-  // per key, the start of each chunk of kStage1OtherChunk other indices inside
-  // its segment: int32[nkeys * (nchunks + 1)] (segments are sorted by other)
-  DevMem cseg;
-  int64_t nchunks = 0;
 };
 
 struct OutOrder {  // output pairs grouped by one output-side index

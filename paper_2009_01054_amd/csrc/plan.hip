@@ -590,7 +590,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   auto need_insort = [&](int key) { insort_needed[key == SC ? 0 : 1] = true; };
   // sort by other index first, then stably by key: segments ordered by other inside
   struct SortHost {
-    std::vector<int32_t> perm, inv, other, cseg;
+    std::vector<int32_t> perm, inv, other;
     std::vector<int64_t> seg;
   } sort_host[2];
   auto build_insort = [&](int ks) {
@@ -607,17 +607,6 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     for (int64_t p = 0; p < n_in; ++p) o.inv[o.perm[p]] = (int32_t)p;
     o.other.resize(n_in);
     for (int64_t p = 0; p < n_in; ++p) o.other[p] = h[okey][o.perm[p]];
-    // chunk starts inside each key segment (positions fit int32: n_in <= INT32_MAX)
-    const int64_t nk = nkeys_of(P, key), nch = ceil_div(nkeys_of(P, okey), kStage1OtherChunk);
-    o.cseg.resize((size_t)nk * (nch + 1));
-    for (int64_t k = 0; k < nk; ++k) {
-      int64_t p = o.seg[k];
-      for (int64_t c = 0; c <= nch; ++c) {
-        const int64_t lim = c * kStage1OtherChunk;
-        while (p < o.seg[k + 1] && o.other[p] < lim) ++p;
-        o.cseg[(size_t)k * (nch + 1) + c] = (int32_t)(c == nch ? o.seg[k + 1] : p);
-      }
-    }
   };
 
   tm.lap("term expansion");
@@ -713,12 +702,10 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       InputSort &is = P->insort[ks];
       is.nkeys = nkeys_of(P, ks == 0 ? SC : SE);
       is.nother = nkeys_of(P, ks == 0 ? SE : SC);
-      is.nchunks = ceil_div(is.nother, kStage1OtherChunk);
       L.add(is.perm, (size_t)n_in * 4);
       L.add(is.inv, (size_t)n_in * 4);
       L.add(is.other, (size_t)n_in * 4);
       L.add(is.seg, (size_t)(is.nkeys + 1) * 8);
-      L.add(is.cseg, (size_t)is.nkeys * (is.nchunks + 1) * 4);
     }
     for (int xs = 0; xs < 2; ++xs) {
       if (!outord_needed[xs] || n_out == 0) continue;
@@ -755,8 +742,8 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       InputSort &is = P->insort[ks];
       const int key = ks == 0 ? SC : SE, okey = ks == 0 ? SE : SC;
       dev_input_sort(P->idx[key].as<int32_t>(), is.nkeys, P->idx[okey].as<int32_t>(), is.nother, n_in,
-                     kStage1OtherChunk, is.perm.as<int32_t>(), is.other.as<int32_t>(),
-                     is.seg.as<int64_t>(), is.cseg.as<int32_t>(), P->scratch, s);
+                     is.perm.as<int32_t>(), is.other.as<int32_t>(), is.seg.as<int64_t>(),
+                     P->scratch, s);
       dev_invert(is.perm.as<int32_t>(), n_in, is.inv.as<int32_t>(), s);
       is.built = true;
     }
@@ -817,8 +804,6 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
           up.add(is.inv, std::move(sort_host[ks].inv));
           up.add(is.other, std::move(sort_host[ks].other));
           up.add(is.seg, std::move(sort_host[ks].seg));
-          up.add(is.cseg, std::move(sort_host[ks].cseg));
-          is.nchunks = ceil_div(is.nother, kStage1OtherChunk);
         } else {
           up.add(is.seg, std::vector<int64_t>(is.nkeys + 1, 0));
         }
@@ -970,9 +955,8 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
       ldc = rows_of(P, sb.fsc);
     }
     launch_stage1<T>(Fc, ldc, sb.d_rows.as<int32_t>(), (int64_t)sb.rows.size(), sb.row0,
-                     is.seg.as<int64_t>(), is.cseg.as<int32_t>(), is.nchunks,
-                     is.other.as<int32_t>(), P->n_in, is.nother, wsp<T>(P, W.vs[ks]), is.nkeys, R, S,
-                     ldS, s, P->gate);
+                     is.seg.as<int64_t>(), is.other.as<int32_t>(), is.nother, wsp<T>(P, W.vs[ks]),
+                     is.nkeys, R, S, ldS, s, P->gate);
   }
   mark(P, ST_STAGE1, 1, s);
   // two-factor terms: stage 2

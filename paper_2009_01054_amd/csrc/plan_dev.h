@@ -46,11 +46,10 @@ void dev_reserve(DevScratch &sc, size_t bytes, hipStream_t s);
 
 // Input pairs sorted by (key, other), stable: perm[p] = input index at sorted
 // position p, other[p] its other index, seg[k] the first position of key k
-// (seg[nkeys] = n), cseg[k * (nch + 1) + c] the first position in segment k
-// whose other index is >= c * chunk (cseg[.. + nch] = seg[k + 1]).
+// (seg[nkeys] = n).
 void dev_input_sort(const int32_t *key, int64_t nkeys, const int32_t *other, int64_t nother,
-                    int64_t n, int64_t chunk, int32_t *perm, int32_t *other_out, int64_t *seg,
-                    int32_t *cseg, DevScratch &sc, hipStream_t s);
+                    int64_t n, int32_t *perm, int32_t *other_out, int64_t *seg, DevScratch &sc,
+                    hipStream_t s);
 
 // inv[perm[p]] = p for p < n.
 void dev_invert(const int32_t *perm, int64_t n, int32_t *inv, hipStream_t s);

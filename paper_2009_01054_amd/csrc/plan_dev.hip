@@ -116,37 +116,13 @@ __global__ void split_other_kernel(const K *__restrict__ ck, int64_t n, int ob,
     other[p] = (int32_t)(ck[p] & mask);
 }
 
-// cseg[k * (nch + 1) + c]: first position in segment k with other >= c * chunk
-// (binary search: others ascend inside a segment); the last entry ends the segment
-__global__ void cseg_kernel(const int64_t *__restrict__ seg, const int32_t *__restrict__ other,
-                            int64_t nkeys, int64_t nch, int64_t chunk, int32_t *__restrict__ cseg) {
-  const int64_t total = nkeys * (nch + 1);
-  for (int64_t idx = (int64_t)blockIdx.x * PB + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * PB) {
-    const int64_t k = idx / (nch + 1), c = idx - k * (nch + 1);
-    int64_t lo = seg[k], hi = seg[k + 1];
-    if (c < nch) {
-      const int64_t lim = c * chunk;
-      while (lo < hi) {
-        const int64_t mid = lo + (hi - lo) / 2;
-        if (other[mid] < lim) lo = mid + 1;
-        else hi = mid;
-      }
-    } else {
-      lo = hi;
-    }
-    cseg[idx] = (int32_t)lo;
-  }
-}
-
 template <class K> size_t input_sort_bytes(int64_t n) {
   return 2 * align256(n * sizeof(K)) + align256(n * sizeof(int32_t)) + sort_temp_bytes<K>(n);
 }
 
 template <class K>
 void input_sort_t(const int32_t *key, int64_t nkeys, const int32_t *other, int64_t nother, int64_t n,
-                  int64_t chunk, int32_t *perm, int32_t *other_out, int64_t *seg, int32_t *cseg,
-                  DevScratch &sc, hipStream_t s) {
+                  int32_t *perm, int32_t *other_out, int64_t *seg, DevScratch &sc, hipStream_t s) {
   const int ob = bits_for(nother), kb = bits_for(nkeys);
   const size_t tb = sort_temp_bytes<K>(n);
   const size_t o_kout = align256(n * sizeof(K)), o_val = o_kout + align256(n * sizeof(K));
@@ -159,8 +135,6 @@ void input_sort_t(const int32_t *key, int64_t nkeys, const int32_t *other, int64
   sort_pairs<K>(kin, kout, val, perm, n, ob + kb, base + o_tmp, tb, s);
   split_other_kernel<K><<<grid_for(n), PB, 0, s>>>(kout, n, ob, other_out);
   bucket_starts_kernel<K><<<grid_for(n + 1), PB, 0, s>>>(kout, n, ob, nkeys, seg);
-  const int64_t nch = ceil_div(nother, chunk);
-  cseg_kernel<<<grid_for(nkeys * (nch + 1)), PB, 0, s>>>(seg, other_out, nkeys, nch, chunk, cseg);
   check_launch(s);
 }
 
@@ -292,12 +266,12 @@ size_t dev_tiles_bytes(int64_t n, int64_t nbuckets) {
 void dev_reserve(DevScratch &sc, size_t bytes, hipStream_t s) { (void)scratch_get(sc, bytes, s); }
 
 void dev_input_sort(const int32_t *key, int64_t nkeys, const int32_t *other, int64_t nother,
-                    int64_t n, int64_t chunk, int32_t *perm, int32_t *other_out, int64_t *seg,
-                    int32_t *cseg, DevScratch &sc, hipStream_t s) {
+                    int64_t n, int32_t *perm, int32_t *other_out, int64_t *seg, DevScratch &sc,
+                    hipStream_t s) {
   if (bits_for(nkeys) + bits_for(nother) <= 32)
-    input_sort_t<uint32_t>(key, nkeys, other, nother, n, chunk, perm, other_out, seg, cseg, sc, s);
+    input_sort_t<uint32_t>(key, nkeys, other, nother, n, perm, other_out, seg, sc, s);
   else
-    input_sort_t<uint64_t>(key, nkeys, other, nother, n, chunk, perm, other_out, seg, cseg, sc, s);
+    input_sort_t<uint64_t>(key, nkeys, other, nother, n, perm, other_out, seg, sc, s);
 }
 
 void dev_invert(const int32_t *perm, int64_t n, int32_t *inv, hipStream_t s) {

@@ -37,6 +37,4 @@ constexpr int kStage1KeysPerWave = 1;
 constexpr int kStage1Wide = 1;
 constexpr int kMaxRhsBlockF64 = 2;
 constexpr int kMaxRhsBlockF32 = 4;
-constexpr int kStage1LdsKeysPerWave = 4;
-constexpr double kStage1LdsMinReuse = 1e300;  // LDS-staged stage 1 off (not swept)
 }  // namespace gvt

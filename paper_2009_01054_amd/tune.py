@@ -11,10 +11,7 @@ walks key segments with one wave per key; the number of keys each wave walks
 trades waves in flight against per-wave work.
 
 Over a contiguous range of S rows a stage-1 lane can hold 16 bytes of
-consecutive rows (one vector load per pair) instead of one row.  (Stage 1 can
-also stage F2 columns in LDS; whole ridge solves ran slower with it while
-single products differed by less than their noise, so it is not swept and the
-header keeps it off; GVT_STAGE1_LDS=1 forces it.)
+consecutive rows (one vector load per pair) instead of one row.
 A product pass carries a block of up to 8 right-hand sides; larger blocks
 reuse every gathered element more often but hold more accumulators per lane,
 so the largest block a pass takes is tuned too, per product precision.
@@ -160,8 +157,6 @@ def write_header(path, results, device):
               f"constexpr int kStage1Wide = {int(results['WIDE'][0])};",
               f"constexpr int kMaxRhsBlockF64 = {int(results['MAXR64'][0])};",
               f"constexpr int kMaxRhsBlockF32 = {int(results['MAXR32'][0])};",
-              "constexpr int kStage1LdsKeysPerWave = 4;",
-              "constexpr double kStage1LdsMinReuse = 1e300;  // LDS-staged stage 1 off (not swept)",
               "}  // namespace gvt", ""]
     with open(path, "w") as f:
         f.write("\n".join(lines))

@@ -324,6 +324,24 @@ def test_cg_non_finite_labels(gvt):
     assert ei.value.code == -6 and "non-finite labels" in str(ei.value)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cg_zero_labels_single_and_batched(gvt, prec):
+    # y = 0: a = 0 solves every system; both entry points report it converged with a
+    # zero solution and residual (the residual is measured against 1 when ||y|| = 0)
+    pr = gvt.F64 if prec == "f64" else gvt.F32
+    p = W.make_heterogeneous(94, 4, 20, 16, 150, 4, labels=True)
+    y = np.zeros(len(p["c"]))
+    A, iters, rel, rc = gvt.gvt_krr_cg("kronecker", dev(p["D"]), dev(p["T"]), (idx(p["c"]), idx(p["e"])),
+                                       dev(y), [1e-2, 1.0], matvec_prec=pr)
+    assert rc == 0 and (iters == 0).all() and (rel == 0).all()
+    assert torch.count_nonzero(A) == 0
+    probs = _dev_problems([p, W.make_heterogeneous(94, 5, 12, 30, 200, 4, labels=True)])
+    probs[0]["y"] = dev(y)
+    As, it_b, rel_b, rc_b = gvt.gvt_krr_cg_batched("kronecker", probs, [1e-2, 1.0], matvec_prec=pr)
+    assert rc_b == 0 and (it_b[0] == 0).all() and (rel_b[0] == 0).all() and (rel_b[1] < 1e-6).all()
+    assert torch.count_nonzero(As[0]) == 0
+
+
 def test_cg_not_converged_status(gvt):
     p = W.make_heterogeneous(94, 1, 30, 30, 400, 4, labels=True)
     A, iters, rel, rc = gvt.gvt_krr_cg("kronecker", dev(p["D"]), dev(p["T"]), (idx(p["c"]), idx(p["e"])),
@@ -489,23 +507,17 @@ def test_cg_batched_warm_start_and_cap(gvt):
 @pytest.mark.parametrize("env", [{"GVT_STAGE1_KPW": "1"}, {"GVT_STAGE1_KPW": "2"},
                                  {"GVT_STAGE1_WIDE": "1", "GVT_STAGE1_KPW": "1"},
                                  {"GVT_STAGE1_WIDE": "1", "GVT_STAGE1_KPW": "2"},
-                                 {"GVT_STAGE1_WIDE": "1", "GVT_STAGE1_KPW": "4"},
-                                 {"GVT_STAGE1_LDS": "1", "GVT_STAGE1_LDS_KPW": "2"},
-                                 {"GVT_STAGE1_LDS": "1", "GVT_STAGE1_LDS_KPW": "4"},
-                                 {"GVT_STAGE1_LDS": "1", "GVT_STAGE1_LDS_KPW": "8"}])
+                                 {"GVT_STAGE1_WIDE": "1", "GVT_STAGE1_KPW": "4"}])
 @pytest.mark.parametrize("nrhs", [1, 3, 8])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_stage1_variants_are_bitwise_equal(gvt, env, nrhs, prec, monkeypatch):
     # every stage-1 variant (direct walk with 1, 2 or 4 keys per wave, one row or 16 bytes of
-    # rows per lane; LDS-staged columns with 2, 4 or 8) sums a key's segment in the same
-    # order, so products agree exactly; the other-index range (700) spans several staged
-    # chunks of 128 and a ragged last one (staged 256 FP64 or 512 FP32 columns at a time)
+    # rows per lane) sums a key's segment in the same order, so products agree exactly
     p = W.make_heterogeneous(99, 0, 900, 700, 30000, 8)
     dt = torch.float64 if prec == "f64" else torch.float32
     Dd, Td = dev(p["D"], dt), dev(p["T"], dt)
     c, e = idx(p["c"]), idx(p["e"])
     v = dev(np.random.default_rng(5).standard_normal((len(p["c"]), nrhs)), dt)
-    monkeypatch.setenv("GVT_STAGE1_LDS", "0")
     monkeypatch.setenv("GVT_STAGE1_WIDE", "0")
     monkeypatch.setenv("GVT_STAGE1_KPW", "4")
     ref = gvt.gvt_matvec(Dd, Td, (c, e), (c, e), v)

@@ -312,3 +312,106 @@ def test_cg_matches_dense_solve(kind):
         cond = np.linalg.cond(K + lam * np.eye(n))
         assert np.linalg.norm(A[:, l] - ref) / np.linalg.norm(ref) < 10 * cond * 1e-10
         assert rt[l] < 1e-9 and iters[l] <= 500
+
+
+# ------------------------------------------------- multi-RHS columns and strides
+def _raw_matvec(kind, D, T, out_pairs, in_pairs, V, ldv, ldu, nev):
+    """Call the C oracle directly with explicit column strides (padding filled with NaN)."""
+    import ctypes
+
+    lib = oracle._load()
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    T = D if T is None else np.ascontiguousarray(T, dtype=np.float64)
+    a, b = (np.ascontiguousarray(x, dtype=np.int32) for x in out_pairs)
+    c, e = (np.ascontiguousarray(x, dtype=np.int32) for x in in_pairs)
+    n, nrhs = V.shape
+    vbuf = np.full(ldv * nrhs, np.nan)
+    for s in range(nrhs):
+        vbuf[s * ldv: s * ldv + n] = V[:, s]
+    ubuf = np.full(ldu * nrhs, -7.5)
+    p = lambda x: x.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    rc = lib.oracle_pairwise_matvec(
+        oracle.KINDS[kind], p(D), D.shape[0], D.shape[1], D.shape[1], p(T), T.shape[0], T.shape[1],
+        T.shape[1], p(a), p(b), len(a), None, 0, p(c), p(e), n, p(vbuf), nrhs, ldv, p(ubuf), ldu, 0)
+    assert rc == 0
+    return ubuf
+
+
+@pytest.mark.parametrize("kind", HET + HOM)
+def test_multi_rhs_columns_with_padded_strides(kind):
+    """Each column of an n x 3 product with ldv > n and ldu > n_out equals the one-column
+    product bit for bit and the explicit R(a,b) K R(c,e)^T v of that column; the padding
+    of U is never written and the NaN padding of V is never read."""
+    if kind in HOM:
+        D, (a, b), (c, e), _ = _tiny_hom(21)
+        T = None
+        K = ops.corollary1_operator(kind, D)
+        nd = nt = D.shape[0]
+    else:
+        D, T, (a, b), (c, e), _ = _tiny_het(21)
+        K = ops.corollary1_operator(kind, D, T)
+        nd, nt = D.shape[0], T.shape[0]
+    r = _rng(22)
+    n, n_out = len(c), len(a)
+    V = r.standard_normal((n, 3))
+    V[:, 2] = -3.0 * V[:, 0] + V[:, 1]
+    ldv, ldu = n + 5, n_out + 3
+    ubuf = _raw_matvec(kind, D, T, (a, b), (c, e), V, ldv, ldu, n_out)
+    Rb = ops.sampling_operator(a, b, nd, nt)
+    R = ops.sampling_operator(c, e, nd, nt)
+    for s in range(3):
+        col = ubuf[s * ldu: s * ldu + n_out]
+        one = oracle.pairwise_matvec(kind, D, T, (a, b), (c, e), V[:, s])
+        assert np.array_equal(col, one)
+        ref = Rb @ K @ R.T @ V[:, s]
+        np.testing.assert_allclose(col, ref, rtol=1e-12, atol=1e-12 * max(1.0, np.abs(ref).max()))
+        assert np.all(ubuf[s * ldu + n_out: (s + 1) * ldu] == -7.5)
+
+
+# ------------------------------------ Cartesian kernel on two samples of objects
+def _cartesian_feature_kernel(Xd, Xt, ud_out, ut_out, ud_in, ut_in):
+    """Table 4a Cartesian feature map over a shared universe of objects: a pair of
+    universe objects (d, t) maps to (x_d (x) e_t, e_d (x) x_t), e the universe one-hot."""
+    nd, nt = Xd.shape[0], Xt.shape[0]
+
+    def phi(ud, ut):
+        f1 = np.einsum("ni,nj->nij", Xd[ud], np.eye(nt)[ut]).reshape(len(ud), -1)
+        f2 = np.einsum("ni,nj->nij", np.eye(nd)[ud], Xt[ut]).reshape(len(ud), -1)
+        return np.concatenate([f1, f2], axis=1)
+
+    return phi(ud_out, ut_out) @ phi(ud_in, ut_in).T
+
+
+def test_cartesian_rectangular_bases_shared_objects():
+    """Cartesian delta on rectangular two-sample bases (reading R22): row r and column c
+    of a base matrix are the same object iff r == c, so the prediction sample lists the
+    training objects first, in training order, then objects absent from training.
+    Checked against the Table 4a feature map over the object universe, with training
+    objects that are a permuted subset of the universe and prediction objects that extend
+    them; a prediction sample that permutes the shared objects breaks the correspondence."""
+    r = _rng(23)
+    Xd, Xt = r.standard_normal((9, 3)), r.standard_normal((8, 2))
+    tr_d = np.array([6, 1, 4, 0])            # training drugs (universe ids, permuted)
+    tr_t = np.array([5, 2, 7])               # training targets
+    te_d = np.concatenate([tr_d, [8, 3]])    # prediction drugs: training ones, then new
+    te_t = np.concatenate([tr_t, [0, 6, 1]])
+    D = Xd[te_d] @ Xd[tr_d].T                # 6 x 4 linear drug kernel
+    T = Xt[te_t] @ Xt[tr_t].T                # 6 x 3 linear target kernel
+    n, n_out = 15, 12
+    c = r.integers(0, len(tr_d), n).astype(np.int32); e = r.integers(0, len(tr_t), n).astype(np.int32)
+    a = r.integers(0, len(te_d), n_out).astype(np.int32); b = r.integers(0, len(te_t), n_out).astype(np.int32)
+    a[:3] = [0, 5, 2]; b[:3] = [4, 1, 0]     # shared and new objects on both sides
+    v = r.standard_normal(n)
+    Kf = _cartesian_feature_kernel(Xd, Xt, te_d[a], te_t[b], tr_d[c], tr_t[e])
+    np.testing.assert_allclose(oracle.kernel_matrix("cartesian", D, T, (a, b), (c, e)), Kf,
+                               rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(oracle.pairwise_matvec("cartesian", D, T, (a, b), (c, e), v), Kf @ v,
+                               rtol=1e-12, atol=1e-12)
+    # new objects only match nothing: their delta terms vanish (R16)
+    only_new = (te_d[a] == 8) | (te_d[a] == 3)
+    assert only_new.any()
+    # the same objects listed in another order on the prediction side break the index reading
+    perm = np.array([1, 0, 2, 3, 4, 5])
+    D2 = Xd[te_d[perm]] @ Xd[tr_d].T
+    Kf2 = _cartesian_feature_kernel(Xd, Xt, te_d[perm][a], te_t[b], tr_d[c], tr_t[e])
+    assert not np.allclose(oracle.kernel_matrix("cartesian", D2, T, (a, b), (c, e)), Kf2)
