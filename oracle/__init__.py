@@ -75,6 +75,10 @@ def _load():
             P, P, I64, P, P, I64, I64, ctypes.c_double, P, I64, P, P, P, ctypes.c_int,
         ]
         lib.oracle_max_threads.restype = ctypes.c_int
+        lib.oracle_base_kernel.restype = ctypes.c_int
+        lib.oracle_base_kernel.argtypes = [ctypes.c_int, P, I64, I64, P, I64, I64, I64, ctypes.c_double, P, I64]
+        lib.oracle_tanimoto.restype = ctypes.c_int
+        lib.oracle_tanimoto.argtypes = [P, I64, I64, P, I64, I64, I64, P, I64]
         _lib = lib
     return _lib
 
@@ -177,3 +181,35 @@ def krr_cg(kind, D, T, pairs, y, lambdas, max_iter=200, tol=1e-6, nthreads=0):
     if rc != 0:
         raise ValueError("oracle_krr_cg rejected its arguments")
     return A, iters, rr, rt
+
+
+def base_kernel(kind, X, Y=None, gamma=None):
+    """Section 5 base kernel from features (FP64): kind "linear" (<x, y>) or
+    "gaussian" (exp(-gamma ||x - y||^2)).  Y=None means Y = X."""
+    lib = _load()
+    X = _f64(X)
+    Y = X if Y is None else _f64(Y)
+    assert X.ndim == 2 and Y.ndim == 2 and X.shape[1] == Y.shape[1]
+    K = np.zeros((X.shape[0], Y.shape[0]), dtype=np.float64)
+    code = {"linear": 0, "gaussian": 1}[kind]
+    rc = lib.oracle_base_kernel(code, _ptr(X), X.shape[0], X.shape[1], _ptr(Y), Y.shape[0], Y.shape[1],
+                                X.shape[1], float(gamma if gamma is not None else 0.0), _ptr(K),
+                                max(Y.shape[0], 1))
+    if rc != 0:
+        raise ValueError("oracle_base_kernel rejected its arguments")
+    return K
+
+
+def tanimoto(Xbits, Ybits=None, nbits=None):
+    """Tanimoto kernel of packed binary vectors (rows of uint64 words, bit b of a row
+    in word b // 64 at position b % 64), FP64."""
+    lib = _load()
+    X = np.ascontiguousarray(Xbits, dtype=np.uint64)
+    Y = X if Ybits is None else np.ascontiguousarray(Ybits, dtype=np.uint64)
+    nb = 64 * X.shape[1] if nbits is None else int(nbits)
+    K = np.zeros((X.shape[0], Y.shape[0]), dtype=np.float64)
+    rc = lib.oracle_tanimoto(_ptr(X), X.shape[0], X.shape[1], _ptr(Y), Y.shape[0], Y.shape[1], nb, _ptr(K),
+                             max(Y.shape[0], 1))
+    if rc != 0:
+        raise ValueError("oracle_tanimoto rejected its arguments")
+    return K

@@ -292,3 +292,69 @@ int oracle_max_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* Base kernels from object features (Section 5: the drug and target kernels
+ * the pairwise kernels are built from).
+ *
+ *   linear    k(x, y) = <x, y>                      (Metz data: similarity rows)
+ *   gaussian  k(x, y) = exp(-gamma ||x - y||^2)     (Metz data, squared norm)
+ *
+ * X is nx x dim (row stride ldx), Y is ny x dim (ldy); K[i*ldk + j] = k(X_i, Y_j).
+ * Sums run over ascending feature index from 0.0; the Gaussian sums squared
+ * differences directly (no norm expansion).  Returns 0, or -1 on bad arguments.
+ */
+int oracle_base_kernel(int kind, const double *X, int64_t nx, int64_t ldx, const double *Y,
+                       int64_t ny, int64_t ldy, int64_t dim, double gamma, double *K, int64_t ldk)
+{
+    if ((kind != 0 && kind != 1) || nx < 0 || ny < 0 || dim < 0 || ldx < dim || ldy < dim ||
+        ldk < ny)
+        return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nx; ++i) {
+        for (int64_t j = 0; j < ny; ++j) {
+            double s = 0.0;
+            for (int64_t k = 0; k < dim; ++k) {
+                if (kind == 0) {
+                    s = s + X[i * ldx + k] * Y[j * ldy + k];
+                } else {
+                    double d = X[i * ldx + k] - Y[j * ldy + k];
+                    s = s + d * d;
+                }
+            }
+            K[i * ldk + j] = kind == 0 ? s : exp(-gamma * s);
+        }
+    }
+    return 0;
+}
+
+/*
+ * Tanimoto kernel on binary vectors (Section 5, Heterodimer data): the number
+ * of positions set in both vectors over the number set in either,
+ * sum_i min(v_i, w_i) / sum_i max(v_i, w_i).  Two all-zero vectors give 1
+ * (a vector is identical to itself; reading of 0/0).
+ *
+ * Rows are packed bit vectors of nbits bits: bit b of row i is bit (b % 64) of
+ * 64-bit word X[i*ldx + b/64].  Bits at and past nbits in the last word are
+ * ignored.  Counts are taken bit by bit; the ratio is formed in double.
+ */
+int oracle_tanimoto(const uint64_t *X, int64_t nx, int64_t ldx, const uint64_t *Y, int64_t ny,
+                    int64_t ldy, int64_t nbits, double *K, int64_t ldk)
+{
+    const int64_t words = (nbits + 63) / 64;
+    if (nx < 0 || ny < 0 || nbits < 0 || ldx < words || ldy < words || ldk < ny) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nx; ++i) {
+        for (int64_t j = 0; j < ny; ++j) {
+            int64_t both = 0, either = 0;
+            for (int64_t b = 0; b < nbits; ++b) {
+                int v = (int)((X[i * ldx + b / 64] >> (b % 64)) & 1u);
+                int w = (int)((Y[j * ldy + b / 64] >> (b % 64)) & 1u);
+                both += v & w;
+                either += v | w;
+            }
+            K[i * ldk + j] = either == 0 ? 1.0 : (double)both / (double)either;
+        }
+    }
+    return 0;
+}
