@@ -75,6 +75,14 @@ def _load():
             P, P, I64, P, P, I64, I64, ctypes.c_double, P, I64, P, P, P, ctypes.c_int,
         ]
         lib.oracle_max_threads.restype = ctypes.c_int
+        lib.oracle_auc.restype = ctypes.c_double
+        lib.oracle_auc.argtypes = [P, P, I64]
+        lib.oracle_krr_minres.restype = ctypes.c_int
+        lib.oracle_krr_minres.argtypes = [
+            ctypes.c_int, P, I64, I64, I64, P, I64, I64, I64,
+            P, P, I64, P, P, I64, I64, ctypes.c_double,
+            P, P, I64, P, I64, P, I64, P, P, P, P, P, P, P, ctypes.c_int,
+        ]
         lib.oracle_base_kernel.restype = ctypes.c_int
         lib.oracle_base_kernel.argtypes = [ctypes.c_int, P, I64, I64, P, I64, I64, I64, ctypes.c_double, P, I64]
         lib.oracle_tanimoto.restype = ctypes.c_int
@@ -213,3 +221,53 @@ def tanimoto(Xbits, Ybits=None, nbits=None):
     if rc != 0:
         raise ValueError("oracle_tanimoto rejected its arguments")
     return K
+
+
+def auc(p, labels):
+    """AUC of predictions against binary labels (> 0.5 positive), ties count 1/2; 0.5
+    when one class is empty.  Plain double loop over (positive, negative) pairs."""
+    p = _f64(p)
+    lab = _f64(labels)
+    return float(_load().oracle_auc(_ptr(p), _ptr(lab), len(p)))
+
+
+def krr_minres(kind, D, T, pairs, y, lambdas, max_iter=200, tol=1e-6, val=None, patience=0,
+               nthreads=0):
+    """MINRES on (K + lambda I) a = y from a = 0, one solve per lambda, optionally with
+    early stopping on a validation sample val = (va, vb, yval_binary).
+
+    Returns a dict: A[n, nlam] (last iterate), A_best[n, nlam] (iterate of the best
+    validation AUC), iters, relres_est, relres_true, auc_hist[max_iter, nlam] (NaN past
+    the last step), best_iter, best_auc."""
+    lib = _load()
+    D, T = _bases(kind, D, T)
+    c, e = _i32(pairs[0]), _i32(pairs[1])
+    y = _f64(y)
+    lam = _f64(np.atleast_1d(lambdas))
+    n, nlam = len(c), len(lam)
+    A = np.zeros((n, nlam), order="F")
+    Ab = np.zeros((n, nlam), order="F")
+    iters = np.zeros(nlam, dtype=np.int64)
+    rr = np.zeros(nlam)
+    rt = np.zeros(nlam)
+    hist = np.zeros((max(max_iter, 1), nlam))
+    bi = np.zeros(nlam, dtype=np.int64)
+    ba = np.zeros(nlam)
+    if val is not None:
+        va, vb, yv = _i32(val[0]), _i32(val[1]), _f64(val[2])
+        nval = len(va)
+    else:
+        va = vb = yv = None
+        nval = 0
+    rc = lib.oracle_krr_minres(
+        KINDS[kind], _ptr(D), D.shape[0], D.shape[1], D.shape[1], _ptr(T), T.shape[0], T.shape[1], T.shape[1],
+        _ptr(c), _ptr(e), n, _ptr(y), _ptr(lam), nlam, int(max_iter), float(tol),
+        _ptr(va), _ptr(vb), nval, _ptr(yv), int(patience), _ptr(A), n, _ptr(Ab), _ptr(iters), _ptr(rr),
+        _ptr(rt), _ptr(hist), _ptr(bi), _ptr(ba), int(nthreads),
+    )
+    if rc == -2:
+        raise FloatingPointError("oracle MINRES breakdown")
+    if rc != 0:
+        raise ValueError("oracle_krr_minres rejected its arguments")
+    return dict(A=A, A_best=Ab, iters=iters, relres_est=rr, relres_true=rt, auc_hist=hist[:max_iter],
+                best_iter=bi, best_auc=ba)

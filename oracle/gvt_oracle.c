@@ -358,3 +358,174 @@ int oracle_tanimoto(const uint64_t *X, int64_t nx, int64_t ldx, const uint64_t *
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Area under the ROC curve of predictions p against binary labels (label > 0.5
+ * is a positive): the fraction of (positive, negative) pairs the predictions
+ * order correctly, ties counting one half.  Plain double loop over all
+ * pairs.  One class empty: 0.5 (no pair to order; reading). */
+double oracle_auc(const double *p, const double *label, int64_t n)
+{
+    double good = 0.0;
+    int64_t np = 0, nn = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (label[i] > 0.5) ++np;
+        else ++nn;
+    }
+    if (np == 0 || nn == 0) return 0.5;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(label[i] > 0.5)) continue;
+        for (int64_t j = 0; j < n; ++j) {
+            if (label[j] > 0.5) continue;
+            if (p[i] > p[j]) good = good + 1.0;
+            else if (p[i] == p[j]) good = good + 0.5;
+        }
+    }
+    return good / ((double)np * (double)nn);
+}
+
+/*
+ * Kernel ridge regression (Section 3 eq. (1), (K + lambda I) a = y) by the
+ * minimal residual method with early stopping on a validation sample
+ * (Section 3; Section 6, early stopping ridge regression).
+ *
+ * MINRES: Lanczos on A = K + lambda I from r0 = y (a0 = 0),
+ *   beta_1 v_1 = y;  q = A v_k - beta_k v_{k-1};  alpha_k = v_k.q;
+ *   q -= alpha_k v_k;  beta_{k+1} = ||q||;  v_{k+1} = q / beta_{k+1},
+ * and the QR factorisation of the tridiagonal Lanczos matrix by Givens
+ * rotations, one new rotation per step:
+ *   eps_k = s_{k-2} beta_k,  dt = c_{k-2} beta_k,
+ *   delta_k = c_{k-1} dt + s_{k-1} alpha_k,  gbar = c_{k-1} alpha_k - s_{k-1} dt,
+ *   gamma_k = sqrt(gbar^2 + beta_{k+1}^2),  c_k = gbar / gamma_k,  s_k = beta_{k+1} / gamma_k,
+ *   tau_k = c_k phibar_{k-1},  phibar_k = -s_k phibar_{k-1}   (|phibar_k| = ||y - A a_k||),
+ *   d_k = (v_k - delta_k d_{k-1} - eps_k d_{k-2}) / gamma_k,  a_k = a_{k-1} + tau_k d_k.
+ * Stops when |phibar_k| / ||y|| < tol or after max_iter steps.
+ *
+ * Early stopping (optional, va != NULL): after every step the predictions on
+ * the validation pairs (va, vb), p = R(va, vb) K R(c, e)^T a_k, give an AUC
+ * against the binary labels yval; the best AUC (strictly larger than every
+ * earlier one, starting from a_0 = 0) and its step are kept, Abest receives
+ * a at that step, and the solve stops once `patience` steps have passed
+ * without a better AUC (patience <= 0: no early stop).  auc_hist[k*nlam + l]
+ * (may be NULL) receives the AUC after step k+1, NaN past the last step.
+ *
+ * Outputs per lambda: A (final iterate), iters, relres_est = |phibar|/||y||,
+ * relres_true = ||y - (K + lambda I) a|| / ||y|| (one more product),
+ * best_iter, best_auc.  Returns 0, -1 on bad arguments, -2 on a breakdown
+ * (a non-finite value or gamma_k = 0).
+ */
+int oracle_krr_minres(int kind, const double *D, int64_t d_rows, int64_t d_cols, int64_t ldd,
+                      const double *T, int64_t t_rows, int64_t t_cols, int64_t ldt,
+                      const int32_t *c, const int32_t *e, int64_t n, const double *y,
+                      const double *lambdas, int64_t nlam, int64_t max_iter, double tol,
+                      const int32_t *va, const int32_t *vb, int64_t nval, const double *yval,
+                      int64_t patience, double *A, int64_t lda, double *Abest, int64_t *iters,
+                      double *relres_est, double *relres_true, double *auc_hist,
+                      int64_t *best_iter, double *best_auc, int nthreads)
+{
+    if (n <= 0 || nlam <= 0 || lda < n || max_iter < 0) return -1;
+    if (va && (!vb || !yval || nval <= 0)) return -1;
+    double *vprev = (double *)malloc(sizeof(double) * (size_t)n);
+    double *v = (double *)malloc(sizeof(double) * (size_t)n);
+    double *q = (double *)malloc(sizeof(double) * (size_t)n);
+    double *d1 = (double *)malloc(sizeof(double) * (size_t)n); /* d_{k-1} */
+    double *d2 = (double *)malloc(sizeof(double) * (size_t)n); /* d_{k-2} */
+    double *pv = va ? (double *)malloc(sizeof(double) * (size_t)nval) : NULL;
+    int status = 0;
+    const double ynorm = sqrt(dot_seq(y, y, n));
+    for (int64_t l = 0; l < nlam && status == 0; ++l) {
+        const double lam = lambdas[l];
+        double *a = A + l * lda;
+        double *ab = Abest ? Abest + l * lda : NULL;
+        for (int64_t k = 0; k < n; ++k) {
+            a[k] = 0.0;
+            vprev[k] = 0.0;
+            d1[k] = 0.0;
+            d2[k] = 0.0;
+            if (ab) ab[k] = 0.0;
+        }
+        for (int64_t k = 0; k < max_iter && auc_hist; ++k) auc_hist[k * nlam + l] = NAN;
+        double beta = ynorm; /* beta_k */
+        for (int64_t k = 0; k < n; ++k) v[k] = beta > 0.0 ? y[k] / beta : 0.0;
+        double c1 = 1.0, s1 = 0.0, c2 = 1.0, s2 = 0.0; /* rotations k-1 and k-2 */
+        double phibar = beta;
+        double best = 0.5;
+        if (va) { /* a_0 = 0: every prediction ties */
+            for (int64_t i = 0; i < nval; ++i) pv[i] = 0.0;
+            best = oracle_auc(pv, yval, nval);
+        }
+        int64_t kbest = 0, it = 0;
+        while (it < max_iter && !(fabs(phibar) / (ynorm > 0.0 ? ynorm : 1.0) < tol)) {
+            /* q = A v_k - beta_k v_{k-1} */
+            if (oracle_pairwise_matvec(kind, D, d_rows, d_cols, ldd, T, t_rows, t_cols, ldt, c,
+                                       e, n, NULL, 0, c, e, n, v, 1, n, q, n, nthreads) != 0) {
+                status = -1;
+                break;
+            }
+            for (int64_t k = 0; k < n; ++k) q[k] = q[k] + lam * v[k] - beta * vprev[k];
+            const double alpha = dot_seq(v, q, n);
+            for (int64_t k = 0; k < n; ++k) q[k] = q[k] - alpha * v[k];
+            const double beta_next = sqrt(dot_seq(q, q, n));
+            /* QR update of the new tridiagonal column */
+            const double eps = s2 * beta, dt = c2 * beta;
+            const double delta = c1 * dt + s1 * alpha;
+            const double gbar = c1 * alpha - s1 * dt;
+            const double gamma = sqrt(gbar * gbar + beta_next * beta_next);
+            if (!(gamma > 0.0) || !isfinite(gamma)) {
+                status = -2;
+                break;
+            }
+            const double cs = gbar / gamma, sn = beta_next / gamma;
+            const double tau = cs * phibar;
+            phibar = -sn * phibar;
+            /* d_k and the new iterate; rotate the history */
+            for (int64_t k = 0; k < n; ++k) {
+                const double dk = (v[k] - delta * d1[k] - eps * d2[k]) / gamma;
+                d2[k] = d1[k];
+                d1[k] = dk;
+                a[k] = a[k] + tau * dk;
+            }
+            c2 = c1; s2 = s1; c1 = cs; s1 = sn;
+            for (int64_t k = 0; k < n; ++k) {
+                vprev[k] = v[k];
+                v[k] = beta_next > 0.0 ? q[k] / beta_next : 0.0;
+            }
+            beta = beta_next;
+            ++it;
+            if (va) {
+                oracle_pairwise_matvec(kind, D, d_rows, d_cols, ldd, T, t_rows, t_cols, ldt, va, vb,
+                                       nval, NULL, 0, c, e, n, a, 1, n, pv, nval, nthreads);
+                const double auc = oracle_auc(pv, yval, nval);
+                if (auc_hist) auc_hist[(it - 1) * nlam + l] = auc;
+                if (auc > best) {
+                    best = auc;
+                    kbest = it;
+                    if (ab)
+                        for (int64_t k = 0; k < n; ++k) ab[k] = a[k];
+                }
+                if (patience > 0 && it - kbest >= patience) break;
+            }
+        }
+        iters[l] = it;
+        relres_est[l] = fabs(phibar) / (ynorm > 0.0 ? ynorm : 1.0);
+        if (best_iter) best_iter[l] = kbest;
+        if (best_auc) best_auc[l] = best;
+        if (status == 0) {
+            oracle_pairwise_matvec(kind, D, d_rows, d_cols, ldd, T, t_rows, t_cols, ldt, c, e, n,
+                                   NULL, 0, c, e, n, a, 1, n, q, n, nthreads);
+            double s = 0.0;
+            for (int64_t k = 0; k < n; ++k) {
+                const double dd = y[k] - (q[k] + lam * a[k]);
+                s = s + dd * dd;
+            }
+            relres_true[l] = sqrt(s) / (ynorm > 0.0 ? ynorm : 1.0);
+        }
+    }
+    free(vprev);
+    free(v);
+    free(q);
+    free(d1);
+    free(d2);
+    free(pv);
+    return status;
+}
