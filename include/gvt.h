@@ -70,6 +70,8 @@ extern "C" {
 /* ---- status codes ---------------------------------------------------- */
 #define GVT_OK 0
 #define GVT_NOT_CONVERGED 1     /* CG hit max_iter; results are written      */
+#define GVT_TOL_NOT_MET 2       /* estimated error above the requested bound;
+                                   results are written                        */
 #define GVT_ERR_ARG (-1)        /* null pointer, negative size, ld < cols... */
 #define GVT_ERR_INDEX (-2)      /* an index is out of range                  */
 #define GVT_ERR_KIND (-3)       /* kind/base-matrix mismatch (homogeneous)   */
@@ -93,6 +95,10 @@ extern "C" {
 #define GVT_ANTISYMMETRIC 5 /* (I - P)(D (x) D)  (sign of the Table 4b function) homog.   */
 #define GVT_RANKING 6       /* (I - P)(D (x) 1)(I - P)                homogeneous         */
 #define GVT_MLPK 7          /* (I + P)(I - Q)(D (x) D)(I - Q)^T (I + P)  homogeneous      */
+
+/* ---- base kernels from features (Section 5) ----------------------------- */
+#define GVT_BASE_LINEAR 0   /* k(x, y) = <x, y>                  */
+#define GVT_BASE_GAUSSIAN 1 /* k(x, y) = exp(-gamma ||x - y||^2) */
 
 /* ---- plan flags ---------------------------------------------------------- */
 #define GVT_FLAG_SYMMETRIC_BASES 1 /* D and T are square and symmetric (training
@@ -204,6 +210,59 @@ int gvt_dense_matvec(int prec, const void *M, int64_t m_rows, int64_t m_cols, in
                      int64_t ldv, void *U, int64_t ldu, void *stream);
 
 /*
+ * gvt_dense_matvec_checked — gvt_dense_matvec with the error of the result
+ * measured and bounded (the complete-data product of Section 3's vec-trick
+ * identity, as gvt_dense_matvec).  After the product it recomputes up to 32
+ * evenly spaced rows of Umat in FP64 from the same stored operands and
+ * estimates the norm-wise relative error ||U_S - U_S,ref|| / ||U_S,ref||
+ * over those rows.  While the estimate exceeds max_relerr / 2 the product is
+ * redone in the next more accurate form (GVT_BF16X3 -> GVT_BF16X6 ->
+ * GVT_F32; inputs stay float); GVT_F64 and GVT_F32 are only measured.  The
+ * split-bf16 forms keep ~16 (bf16x3) or ~24 (bf16x6) significant bits per
+ * operand, so their error relative to |Umat| grows with cancellation in the
+ * sums, which the inputs decide.  max_relerr = 0 measures without escalating.
+ * *relerr_out (host) receives the estimate for the returned result,
+ * *prec_out (host) the precision that produced it.  Synchronises `stream`.
+ * Returns GVT_OK, GVT_TOL_NOT_MET when the last estimate still exceeds
+ * max_relerr (results written), or the errors of gvt_dense_matvec.
+ */
+int gvt_dense_matvec_checked(int prec, const void *M, int64_t m_rows, int64_t m_cols, int64_t ldm,
+                             const void *N, int64_t n_rows, int64_t n_cols, int64_t ldn,
+                             const void *V, int64_t ldv, void *U, int64_t ldu, double max_relerr,
+                             double *relerr_out, int *prec_out, void *stream);
+
+/*
+ * gvt_base_kernel — a base kernel matrix from object features (Section 5:
+ * linear kernels <x, y> and Gaussian kernels exp(-gamma ||x - y||^2) on
+ * feature or similarity-row vectors, the drug and target kernels D and T of
+ * the pairwise kernels).
+ * kind: GVT_BASE_LINEAR or GVT_BASE_GAUSSIAN.  prec: GVT_F64 (double X, Y, K;
+ * FP64 matrix cores) or GVT_F32 (float).  X: nx x dim (row stride ldx >= dim),
+ * Y: ny x dim (ldy) or NULL for Y = X (then ny must equal nx and K is exactly
+ * symmetric with, for the Gaussian, exactly 1 on the diagonal).  K: nx x ny,
+ * row stride ldk >= ny, K[i*ldk + j] = k(X_i, Y_j).  The Gaussian uses
+ * ||x||^2 + ||y||^2 - 2<x, y> clamped at 0.  Stream-ordered scratch for the
+ * row norms; asynchronous on `stream`.  Errors: GVT_ERR_ARG, GVT_ERR_HIP.
+ */
+int gvt_base_kernel(int kind, int prec, const void *X, int64_t nx, int64_t ldx, const void *Y,
+                    int64_t ny, int64_t ldy, int64_t dim, double gamma, void *K, int64_t ldk,
+                    void *stream);
+
+/*
+ * gvt_tanimoto_kernel — the Tanimoto kernel of binary feature vectors
+ * (Section 5, Heterodimer data): bits set in both over bits set in either,
+ * 1 for two all-zero vectors.  X: nx rows of packed bits, ldx >= (nbits + 63)
+ * / 64 uint64 words per row; bit b of a row is bit b % 64 of word b / 64;
+ * bits at and past nbits are ignored.  Y: ny rows (ldy) or NULL for Y = X
+ * (ny must equal nx).  K: nx x ny, double (GVT_F64) or float (GVT_F32, the
+ * double ratio rounded once), row stride ldk >= ny.  Counts are exact, so K
+ * is reproducible bit for bit.  Asynchronous on `stream`.
+ * Errors: GVT_ERR_ARG, GVT_ERR_HIP.
+ */
+int gvt_tanimoto_kernel(int prec, const uint64_t *X, int64_t nx, int64_t ldx, const uint64_t *Y,
+                        int64_t ny, int64_t ldy, int64_t nbits, void *K, int64_t ldk, void *stream);
+
+/*
  * gvt_krr_cg — kernel ridge regression, Section 3 eq. (1):
  *   (R K R^T + lambda_l I) a_l = y   for l < nlam (one shared operator,
  *   nlam right-hand sides advanced together as one batched product)
@@ -275,6 +334,60 @@ typedef struct gvt_krr_problem {
 int gvt_krr_cg_batched(int kind, const gvt_krr_problem *problems, int nprob, const double *lambdas,
                        int nlam, int max_iter, double tol, int matvec_prec, int check_every,
                        int64_t *iters_out, double *relres_out, void *stream);
+
+/*
+ * A validation sample for early stopping (all pointers DEVICE): the pairs
+ * (a[i], b[i]), i < n, index the rows of the training base kernels (as output
+ * pairs of a product with the training pairs as inputs); labels[n] (double)
+ * are binary, > 0.5 meaning positive.  patience > 0 stops a system after that
+ * many iterations without a better validation AUC; 0 never stops early.
+ */
+typedef struct gvt_validation {
+  const int32_t *a, *b;
+  int64_t n;
+  const double *labels;
+  int64_t patience;
+} gvt_validation;
+
+/*
+ * gvt_krr_minres — kernel ridge regression, Section 3 eq. (1),
+ * (R K R^T + lambda_l I) a_l = y for l < nlam, by the minimal residual method
+ * from a = 0, optionally with early stopping on a validation sample (the
+ * paper's training procedure, Sections 3 and 6).
+ *
+ * All lambdas share one Lanczos basis of K (the Krylov spaces of K + lambda I
+ * from y do not depend on lambda), so an iteration costs one product with one
+ * right-hand side (plus one with the validation pairs as outputs) for the
+ * whole grid.  Vectors and scalars are FP64; matvec_prec GVT_F64 or GVT_F32
+ * selects the products' arithmetic.  lambdas[nlam] (host) >= 0.
+ * Arguments D, T, c, e, n, y as in gvt_krr_cg.
+ *
+ * Without a validation sample (val NULL or val->n == 0) a system stops when
+ * its MINRES residual estimate |phibar_k| / ||y|| < tol (tol 0: never) or
+ * after max_iter iterations, and A (n x nlam, column stride lda, device)
+ * receives the last iterate.  With one, after every iteration the
+ * predictions on the validation pairs give an AUC per system (pairs of
+ * positives and negatives ordered correctly, ties one half); A receives the
+ * iterate of the best AUC (strictly above every earlier one, from a_0 = 0
+ * with AUC 1/2), and a system also stops after val->patience iterations
+ * without improvement.
+ * Host outputs: iters_out[nlam] iterations run, relres_out[nlam] true
+ * relative residual ||y - (K + lambda I) a|| / ||y|| of the returned A (FP64
+ * product), best_iter_out[nlam] the iteration of the returned A and
+ * best_auc_out[nlam] its AUC (NaN without validation) (both may be NULL),
+ * auc_hist[max_iter * nlam] (may be NULL) the AUC after iteration k+1 at
+ * [k * nlam + l], NaN past a system's last iteration.  check_every:
+ * iterations between host looks at the states.  Synchronises `stream`.
+ * Returns GVT_OK when every system met tol or stopped early,
+ * GVT_NOT_CONVERGED when some ran to max_iter, GVT_ERR_BREAKDOWN on a
+ * non-finite value or a zero Givens norm, other errors as gvt_krr_cg.
+ */
+int gvt_krr_minres(int kind, const double *D, int64_t d, int64_t ldd, const double *T, int64_t t,
+                   int64_t ldt, const int32_t *c, const int32_t *e, int64_t n, const double *y,
+                   const double *lambdas, int nlam, double *A, int64_t lda, int max_iter, double tol,
+                   int matvec_prec, const gvt_validation *val, int check_every, int64_t *iters_out,
+                   double *relres_out, int64_t *best_iter_out, double *best_auc_out,
+                   double *auc_hist, void *stream);
 
 /*
  * gvt_plan_profile — diagnostic: runs gvt_plan_execute `reps` times

@@ -20,13 +20,17 @@ from ._binding import (  # noqa: F401
     KINDS,
     GvtError,
     Plan,
+    gvt_base_kernel,
     gvt_dense_matvec,
+    gvt_dense_matvec_checked,
     gvt_empty_cache,
     gvt_krr_cg,
     gvt_krr_cg_batched,
+    gvt_krr_minres,
     gvt_last_error,
     gvt_matvec,
     gvt_pairwise_matvec,
+    gvt_tanimoto_kernel,
     gvt_plan_create,
     gvt_plan_destroy,
     gvt_plan_execute,

@@ -58,6 +58,12 @@ def load_library():
     lib.gvt_pairwise_matvec.argtypes = [I, P, I, P, I64, I64, I64, P, I64, I64, I64, P, P, I64, P, P, I64,
                                         P, I64, I64, P, I64, I, P]
     lib.gvt_dense_matvec.argtypes = [I, P, I64, I64, I64, P, I64, I64, I64, P, I64, P, I64, P]
+    lib.gvt_base_kernel.argtypes = [I, I, P, I64, I64, P, I64, I64, I64, ctypes.c_double, P, I64, P]
+    lib.gvt_krr_minres.argtypes = [I, P, I64, I64, P, I64, I64, P, P, I64, P, P, I, P, I64, I, ctypes.c_double,
+                                   I, P, I, P, P, P, P, P, P]
+    lib.gvt_tanimoto_kernel.argtypes = [I, P, I64, I64, P, I64, I64, I64, P, I64, P]
+    lib.gvt_dense_matvec_checked.argtypes = [I, P, I64, I64, I64, P, I64, I64, I64, P, I64, P, I64,
+                                             ctypes.c_double, P, P, P]
     lib.gvt_krr_cg.argtypes = [I, P, I64, I64, P, I64, I64, P, P, I64, P, P, I, P, I64, P, I64, I,
                                ctypes.c_double, I, I, P, P, P]
     lib.gvt_krr_cg_batched.argtypes = [I, P, I, P, I, I, ctypes.c_double, I, I, P, P, P]
@@ -65,7 +71,7 @@ def load_library():
     lib.gvt_plan_info.argtypes = [P, P]
     lib.gvt_empty_cache.argtypes = [P]
     for f in ("gvt_plan_profile", "gvt_plan_info", "gvt_plan_create", "gvt_plan_destroy", "gvt_plan_execute", "gvt_matvec",
-              "gvt_pairwise_matvec", "gvt_dense_matvec", "gvt_krr_cg", "gvt_krr_cg_batched", "gvt_empty_cache"):
+              "gvt_pairwise_matvec", "gvt_dense_matvec", "gvt_dense_matvec_checked", "gvt_base_kernel", "gvt_tanimoto_kernel", "gvt_krr_minres", "gvt_krr_cg", "gvt_krr_cg_batched", "gvt_empty_cache"):
         getattr(lib, f).restype = I
     _lib = lib
     return lib
@@ -112,7 +118,10 @@ def _ptr(t):
 
 def _ld(t):
     """Row stride of a row-major 2-D tensor (elements)."""
-    assert t.dim() == 2 and t.stride(1) == 1, "base matrices must be row-major (stride(1) == 1)"
+    assert t.dim() == 2, "expected a 2-D tensor"
+    if t.numel() == 0:
+        return max(t.shape[1], 1)
+    assert t.stride(1) == 1 or t.shape[1] == 1, "base matrices must be row-major (stride(1) == 1)"
     return max(t.stride(0), t.shape[1], 1)
 
 
@@ -281,6 +290,99 @@ def gvt_dense_matvec(M, N, Vmat, prec=None, out=None):
                                 N.shape[1], _ld(N), _ptr(Vmat), _ld(Vmat), _ptr(U), _ld(U),
                                 _stream_handle()))
     return U
+
+
+BASE_KINDS = {"linear": 0, "gaussian": 1}
+
+
+def gvt_base_kernel(kind, X, Y=None, gamma=0.0, out=None):
+    """Base kernel matrix K[i, j] = k(X_i, Y_j) from features (Section 5): "linear" or
+    "gaussian" (exp(-gamma ||x - y||^2)); Y=None gives the exactly symmetric K of X.
+    Precision follows X's dtype (float64 / float32)."""
+    torch = _torch()
+    lib = load_library()
+    p = _prec_of(X.dtype, None)
+    ny = X.shape[0] if Y is None else Y.shape[0]
+    K = out if out is not None else torch.empty((X.shape[0], ny), dtype=X.dtype, device=X.device)
+    _check(lib.gvt_base_kernel(BASE_KINDS[kind], p, _ptr(X), X.shape[0], _ld(X), _ptr(Y),
+                               ny, _ld(Y) if Y is not None else 0, X.shape[1], float(gamma), _ptr(K), _ld(K),
+                               _stream_handle()))
+    return K
+
+
+def gvt_tanimoto_kernel(Xbits, Ybits=None, nbits=None, dtype=None, out=None):
+    """Tanimoto kernel of packed binary vectors (int64 device tensors of 64-bit words,
+    bit b of a row in word b // 64 at position b % 64).  Ybits=None: Y = X."""
+    torch = _torch()
+    lib = load_library()
+    dtype = dtype or torch.float64
+    nb = 64 * Xbits.shape[1] if nbits is None else int(nbits)
+    ny = Xbits.shape[0] if Ybits is None else Ybits.shape[0]
+    K = out if out is not None else torch.empty((Xbits.shape[0], ny), dtype=dtype, device=Xbits.device)
+    _check(lib.gvt_tanimoto_kernel(_prec_of(dtype, None), _ptr(Xbits), Xbits.shape[0], _ld(Xbits), _ptr(Ybits),
+                                   ny, _ld(Ybits) if Ybits is not None else 0, nb, _ptr(K), _ld(K),
+                                   _stream_handle()))
+    return K
+
+
+def gvt_dense_matvec_checked(M, N, Vmat, prec=None, max_relerr=1e-5, out=None):
+    """Umat = M Vmat N^T with its error estimated on sampled rows against FP64 and the
+    precision raised (bf16x3 -> bf16x6 -> f32) until the estimate is within half of
+    max_relerr.  Returns (Umat, estimated relative error, precision used, status)."""
+    torch = _torch()
+    lib = load_library()
+    p = _prec_of(M.dtype, prec)
+    U = out if out is not None else torch.empty((M.shape[0], N.shape[0]), dtype=M.dtype, device=M.device)
+    est = ctypes.c_double(0.0)
+    used = ctypes.c_int(0)
+    rc = _check(lib.gvt_dense_matvec_checked(p, _ptr(M), M.shape[0], M.shape[1], _ld(M), _ptr(N), N.shape[0],
+                                             N.shape[1], _ld(N), _ptr(Vmat), _ld(Vmat), _ptr(U), _ld(U),
+                                             float(max_relerr), ctypes.byref(est), ctypes.byref(used),
+                                             _stream_handle()))
+    return U, est.value, used.value, rc
+
+
+class _Validation(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("labels", ctypes.c_void_p), ("patience", ctypes.c_int64)]
+
+
+def gvt_krr_minres(kind, D, T, pairs, y, lambdas, max_iter=200, tol=1e-6, matvec_prec=F64, val=None,
+                   patience=0, check_every=8, history=False):
+    """Ridge regression by MINRES from a = 0 (all lambdas share one Lanczos basis), optionally
+    with early stopping on a validation sample val = (a, b, labels) (device tensors; labels
+    double, > 0.5 positive).  Returns a dict with A[n, nlam] (the best-AUC iterate with
+    validation, else the last), iters, relres (true), best_iter, best_auc, auc_hist
+    ([max_iter, nlam] when history=True) and status."""
+    torch = _torch()
+    lib = load_library()
+    code = _kind_codes(kind)[0]
+    c, e = _idx(pairs[0]), _idx(pairs[1])
+    lam = np.ascontiguousarray(np.atleast_1d(np.asarray(lambdas, dtype=np.float64)))
+    nlam = len(lam)
+    n = c.numel()
+    A = torch.empty((nlam, n), dtype=torch.float64, device=D.device)
+    iters = np.zeros(nlam, dtype=np.int64)
+    rel = np.zeros(nlam)
+    bi = np.zeros(nlam, dtype=np.int64)
+    ba = np.zeros(nlam)
+    hist = np.zeros((max_iter, nlam)) if history else None
+    Tm = T if T is not None else D
+    vs = None
+    if val is not None:
+        va, vb, lab = _idx(val[0]), _idx(val[1]), val[2]
+        assert lab.dtype == torch.float64 and lab.is_cuda and lab.numel() == va.numel()
+        vs = _Validation(va.data_ptr(), vb.data_ptr(), va.numel(), lab.data_ptr(), int(patience))
+    rc = lib.gvt_krr_minres(code, _ptr(D), D.shape[0], _ld(D), _ptr(Tm), Tm.shape[0], _ld(Tm), _ptr(c), _ptr(e),
+                            n, _ptr(y), lam.ctypes.data_as(ctypes.c_void_p), nlam, _ptr(A), A.stride(0),
+                            int(max_iter), float(tol), int(matvec_prec),
+                            ctypes.byref(vs) if vs is not None else None, int(check_every),
+                            iters.ctypes.data_as(ctypes.c_void_p), rel.ctypes.data_as(ctypes.c_void_p),
+                            bi.ctypes.data_as(ctypes.c_void_p), ba.ctypes.data_as(ctypes.c_void_p),
+                            hist.ctypes.data_as(ctypes.c_void_p) if hist is not None else None,
+                            _stream_handle())
+    _check(rc)
+    return dict(A=A.t(), iters=iters, relres=rel, best_iter=bi, best_auc=ba, auc_hist=hist, status=rc)
 
 
 class _KrrProblem(ctypes.Structure):

@@ -200,6 +200,12 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
                 const double *lambdas, int nlam, double *A, int64_t lda, const double *A0,
                 int64_t lda0, int max_iter, double tol, int mprec, int check_every,
                 int64_t *iters_out, double *relres_out, hipStream_t s);
+int krr_minres_impl(int kind, const double *D, int64_t d, int64_t ldd, const double *T, int64_t t,
+                    int64_t ldt, const int32_t *c, const int32_t *e, int64_t n, const double *y,
+                    const double *lambdas, int nlam, double *A, int64_t lda, int max_iter, double tol,
+                    int mprec, const gvt_validation *val, int check_every, int64_t *iters_out,
+                    double *relres_out, int64_t *best_iter_out, double *best_auc_out, double *auc_hist,
+                    hipStream_t s);
 int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const double *lambdas,
                         int nlam, int max_iter, double tol, int mprec, int check_every,
                         int64_t *iters_out, double *relres_out, hipStream_t s);
@@ -340,9 +346,73 @@ int gvt_dense_matvec(int prec, const void *M, int64_t m_rows, int64_t m_cols, in
     GVT_REQUIRE(ldm >= m_cols && ldn >= n_cols && ldv >= n_cols && ldu >= n_rows, GVT_ERR_ARG,
                 "leading dimension too small");
     GVT_REQUIRE((m_rows == 0 || n_rows == 0) || (M && N && V && U), GVT_ERR_ARG, "null pointer");
-    dense_matvec(prec, M, m_rows, m_cols, ldm, N, n_rows, n_cols, ldn, V, ldv, U, ldu,
+    dense_matvec(prec, M, m_rows, m_cols, ldm, N, n_rows, n_cols, ldn, V, ldv, U, ldu, nullptr,
                  (hipStream_t)stream);
     return GVT_OK;
+  });
+}
+
+int gvt_base_kernel(int kind, int prec, const void *X, int64_t nx, int64_t ldx, const void *Y,
+                    int64_t ny, int64_t ldy, int64_t dim, double gamma, void *K, int64_t ldk,
+                    void *stream) {
+  return guarded([&]() {
+    GVT_REQUIRE(kind == GVT_BASE_LINEAR || kind == GVT_BASE_GAUSSIAN, GVT_ERR_ARG, "unknown base kernel");
+    GVT_REQUIRE(prec == GVT_F64 || prec == GVT_F32, GVT_ERR_ARG, "base kernels are GVT_F64 or GVT_F32");
+    GVT_REQUIRE(nx >= 0 && ny >= 0 && dim >= 0, GVT_ERR_ARG, "negative size");
+    GVT_REQUIRE(Y != nullptr || ny == nx, GVT_ERR_ARG, "Y = NULL needs ny == nx");
+    GVT_REQUIRE(ldx >= dim && (Y == nullptr || ldy >= dim) && ldk >= ny, GVT_ERR_ARG,
+                "leading dimension too small");
+    GVT_REQUIRE(nx == 0 || ny == 0 || (K && (dim == 0 || (X))), GVT_ERR_ARG, "null pointer");
+    GVT_REQUIRE(std::isfinite(gamma), GVT_ERR_ARG, "gamma is not finite");
+    base_kernel(kind, prec, X, nx, ldx, Y, ny, ldy, dim, gamma, K, ldk, (hipStream_t)stream);
+    return GVT_OK;
+  });
+}
+
+int gvt_tanimoto_kernel(int prec, const uint64_t *X, int64_t nx, int64_t ldx, const uint64_t *Y,
+                        int64_t ny, int64_t ldy, int64_t nbits, void *K, int64_t ldk, void *stream) {
+  return guarded([&]() {
+    GVT_REQUIRE(prec == GVT_F64 || prec == GVT_F32, GVT_ERR_ARG, "Tanimoto kernels are GVT_F64 or GVT_F32");
+    GVT_REQUIRE(nx >= 0 && ny >= 0 && nbits >= 0, GVT_ERR_ARG, "negative size");
+    GVT_REQUIRE(Y != nullptr || ny == nx, GVT_ERR_ARG, "Y = NULL needs ny == nx");
+    const int64_t words = (nbits + 63) / 64;
+    GVT_REQUIRE(ldx >= words && (Y == nullptr || ldy >= words) && ldk >= ny, GVT_ERR_ARG,
+                "leading dimension too small");
+    GVT_REQUIRE(nx == 0 || ny == 0 || (X && K), GVT_ERR_ARG, "null pointer");
+    tanimoto_kernel_matrix(prec, X, nx, ldx, Y, ny, ldy, nbits, K, ldk, (hipStream_t)stream);
+    return GVT_OK;
+  });
+}
+
+int gvt_dense_matvec_checked(int prec, const void *M, int64_t m_rows, int64_t m_cols, int64_t ldm,
+                             const void *N, int64_t n_rows, int64_t n_cols, int64_t ldn,
+                             const void *V, int64_t ldv, void *U, int64_t ldu, double max_relerr,
+                             double *relerr_out, int *prec_out, void *stream) {
+  return guarded([&]() {
+    GVT_REQUIRE(prec == GVT_F64 || prec == GVT_F32 || prec == GVT_BF16X3 || prec == GVT_BF16X6, GVT_ERR_ARG,
+                "unknown precision");
+    GVT_REQUIRE(m_rows >= 0 && m_cols >= 0 && n_rows >= 0 && n_cols >= 0, GVT_ERR_ARG,
+                "negative size");
+    GVT_REQUIRE(ldm >= m_cols && ldn >= n_cols && ldv >= n_cols && ldu >= n_rows, GVT_ERR_ARG,
+                "leading dimension too small");
+    GVT_REQUIRE((m_rows == 0 || n_rows == 0) || (M && N && V && U), GVT_ERR_ARG, "null pointer");
+    GVT_REQUIRE(relerr_out && prec_out && max_relerr >= 0.0, GVT_ERR_ARG,
+                "null output or negative bound");
+    const hipStream_t s = (hipStream_t)stream;
+    int p = prec;
+    double est = 0.0;
+    for (;;) {
+      dense_matvec(p, M, m_rows, m_cols, ldm, N, n_rows, n_cols, ldn, V, ldv, U, ldu, nullptr, s);
+      est = dense_sample_relerr(p, M, m_rows, m_cols, ldm, N, n_rows, n_cols, ldn, V, ldv, U, ldu, s);
+      // a sampled estimate: escalate once it reaches half the bound
+      if (max_relerr <= 0.0 || !(est > 0.5 * max_relerr)) break;
+      if (p == GVT_BF16X3) p = GVT_BF16X6;
+      else if (p == GVT_BF16X6) p = GVT_F32;
+      else break;
+    }
+    *relerr_out = est;
+    *prec_out = p;
+    return (max_relerr > 0.0 && !(est <= max_relerr)) ? GVT_TOL_NOT_MET : GVT_OK;
   });
 }
 
@@ -355,6 +425,19 @@ int gvt_krr_cg(int kind, const double *D, int64_t d, int64_t ldd, const double *
     return krr_cg_impl(kind, D, d, ldd, T, t, ldt, c, e, n, y, lambdas, nlam, A, lda, A0, lda0,
                        max_iter, tol, matvec_prec, check_every, iters_out, relres_out,
                        (hipStream_t)stream);
+  });
+}
+
+int gvt_krr_minres(int kind, const double *D, int64_t d, int64_t ldd, const double *T, int64_t t,
+                   int64_t ldt, const int32_t *c, const int32_t *e, int64_t n, const double *y,
+                   const double *lambdas, int nlam, double *A, int64_t lda, int max_iter, double tol,
+                   int matvec_prec, const gvt_validation *val, int check_every, int64_t *iters_out,
+                   double *relres_out, int64_t *best_iter_out, double *best_auc_out,
+                   double *auc_hist, void *stream) {
+  return guarded([&]() {
+    return krr_minres_impl(kind, D, d, ldd, T, t, ldt, c, e, n, y, lambdas, nlam, A, lda, max_iter, tol,
+                           matvec_prec, val, check_every, iters_out, relres_out, best_iter_out,
+                           best_auc_out, auc_hist, (hipStream_t)stream);
   });
 }
 

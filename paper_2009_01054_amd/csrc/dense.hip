@@ -19,32 +19,12 @@
 // prefetched into registers while the current LDS tile feeds the MFMAs.
 #include "common.h"
 #include "kernels.h"
+#include "mfma.h"
 
 namespace gvt {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
-
-// Output layout of the 16x16 MFMA blocks (checked with a one-hot lane probe on
-// gfx950): lane l holds column l % 16; item v holds row 4*(l/16) + v for the
-// FP32 and bf16 instructions but row (l/16) + 4*v for v_mfma_f64_16x16x4f64.
-template <class T> struct Mfma;
-template <> struct Mfma<double> {
-  typedef d4 acc_t;
-  static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
-  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-};
-template <> struct Mfma<float> {
-  typedef f4 acc_t;
-  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
-  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
 
 // C[M x N] = A[M x K] * op(B),  op(B)[k][n] = BT ? B[n*ldb + k] : B[k*ldb + n]
 template <class T, bool BT>
@@ -459,58 +439,80 @@ static void gemm(const T *A, int64_t lda, const T *B, int64_t ldb, T *C, int64_t
   gemm_mfma_kernel<T, BT><<<grid, 256, 0, s>>>(A, lda, B, ldb, C, ldc, M, N, K);
 }
 
+// Piece layout of the split-bf16 product: M and N split by rows, Vmat
+// transposed (k padded to whole k steps of the GEMM), W written as split
+// pieces by the first GEMM.  Offsets and the total are in bf16 elements; the
+// pieces of one operand are al(size) elements apart, every piece 256-byte
+// aligned.
+struct SplitLayout {
+  int64_t k1, k2, pm, pv, pw, pn, om, ov, ow, on, total;
+  static int64_t al(int64_t e) { return (e * 2 + 255) / 256 * 128; }
+  SplitLayout(int NS, int64_t mr, int64_t mc, int64_t nr, int64_t nc) {
+    const int KQ = NS == 2 ? 64 : 32;  // k padding: whole k steps of the GEMM
+    k1 = ceil_div(mc, KQ) * KQ;
+    k2 = ceil_div(nc, KQ) * KQ;
+    pm = mr * k1; pv = nc * k1; pw = mr * k2; pn = nr * k2;
+    om = 0; ov = om + NS * al(pm); ow = ov + NS * al(pv); on = ow + NS * al(pw);
+    total = on + NS * al(pn);
+  }
+  size_t bytes() const { return (size_t)total * 2 + 256; }
+};
+
 // Umat = M Vmat N^T with split-bf16 products: split M and N by rows and Vmat
-// transposed (k padded to a multiple of 32), W = M Vmat written as split
-// pieces by the first GEMM, then Umat = W N^T.
+// transposed, W = M Vmat written as split pieces by the first GEMM, then
+// Umat = W N^T.  ws: caller workspace of at least SplitLayout::bytes() (null:
+// a stream-ordered allocation).
 template <int NS>
 static void dense_split_bf16(const float *M, int64_t mr, int64_t mc, int64_t ldm, const float *N,
                              int64_t nr, int64_t nc, int64_t ldn, const float *V, int64_t ldv,
-                             float *U, int64_t ldu, hipStream_t s) {
-  constexpr int KQ = NS == 2 ? 64 : 32;  // k padding: whole k steps of the GEMM
-  const int64_t k1 = ceil_div(mc, KQ) * KQ, k2 = ceil_div(nc, KQ) * KQ;
-  const int64_t pm = mr * k1, pv = nc * k1, pw = mr * k2, pn = nr * k2;  // piece sizes
-  auto al = [](int64_t e) { return (e * 2 + 255) / 256 * 128; };          // elements, 256 B aligned
-  const int64_t om = 0, ov = om + NS * al(pm), ow = ov + NS * al(pv), on = ow + NS * al(pw);
-  const int64_t total = on + NS * al(pn);
-  void *buf = nullptr;
-  GVT_HIP_CHECK(hipMallocAsync(&buf, (size_t)total * 2 + 256, s));
+                             float *U, int64_t ldu, void *ws, hipStream_t s) {
+  const SplitLayout L(NS, mr, mc, nr, nc);
+  const int64_t k1 = L.k1, k2 = L.k2;
+  auto al = SplitLayout::al;
+  void *buf = ws;
+  if (!buf) GVT_HIP_CHECK(hipMallocAsync(&buf, L.bytes(), s));
   unsigned short *base = (unsigned short *)buf;
-  unsigned short *Ms = base + om, *Vt = base + ov, *Ws = base + ow, *Ns = base + on;
-  // pieces of one operand are al(size) elements apart
+  unsigned short *Ms = base + L.om, *Vt = base + L.ov, *Ws = base + L.ow, *Ns = base + L.on;
   split_rows_kernel<NS><<<(unsigned)ceil_div(mr * (k1 / 4), 256), 256, 0, s>>>(M, ldm, mr, mc, k1, Ms,
-                                                                             al(pm));
+                                                                             al(L.pm));
   split_rows_kernel<NS><<<(unsigned)ceil_div(nr * (k2 / 4), 256), 256, 0, s>>>(N, ldn, nr, nc, k2, Ns,
-                                                                             al(pn));
+                                                                             al(L.pn));
   split_transpose_kernel<NS><<<dim3((unsigned)ceil_div(k1, 32), (unsigned)ceil_div(nc, 32)), 256, 0, s>>>(
-      V, ldv, mc, nc, k1, Vt, al(pv));
+      V, ldv, mc, nc, k1, Vt, al(L.pv));
   dim3 g1((unsigned)ceil_div(nc, 128), (unsigned)ceil_div(mr, 128));
   constexpr int BK = NS == 2 ? 64 : 32;  // k step: LDS of two blocks per CU
-  gemm_bf16p_kernel<NS, true, BK><<<g1, 256, 0, s>>>(Ms, k1, al(pm), Vt, k1, al(pv), nullptr, 0, Ws,
-                                                      k2, al(pw), k2, mr, nc, k1);
+  gemm_bf16p_kernel<NS, true, BK><<<g1, 256, 0, s>>>(Ms, k1, al(L.pm), Vt, k1, al(L.pv), nullptr, 0, Ws,
+                                                      k2, al(L.pw), k2, mr, nc, k1);
   dim3 g2((unsigned)ceil_div(nr, 128), (unsigned)ceil_div(mr, 128));
-  gemm_bf16p_kernel<NS, false, BK><<<g2, 256, 0, s>>>(Ws, k2, al(pw), Ns, k2, al(pn), U, ldu, nullptr,
+  gemm_bf16p_kernel<NS, false, BK><<<g2, 256, 0, s>>>(Ws, k2, al(L.pw), Ns, k2, al(L.pn), U, ldu, nullptr,
                                                        0, 0, 0, mr, nr, k2);
   check_launch(s);
-  GVT_HIP_CHECK(hipFreeAsync(buf, s));
+  if (!ws) GVT_HIP_CHECK(hipFreeAsync(buf, s));
+}
+
+size_t dense_workspace_bytes(int prec, int64_t mr, int64_t mc, int64_t nr, int64_t nc) {
+  if (mr == 0 || nr == 0) return 0;
+  if (prec == GVT_BF16X3) return SplitLayout(2, mr, mc, nr, nc).bytes();
+  if (prec == GVT_BF16X6) return SplitLayout(3, mr, mc, nr, nc).bytes();
+  return (size_t)mr * nc * (prec == GVT_F64 ? sizeof(double) : sizeof(float)) + 256;
 }
 
 // Umat (mr x nr) = M (mr x mc) Vmat (mc x nc) N^T (N: nr x nc)
 void dense_matvec(int prec, const void *Mp, int64_t mr, int64_t mc, int64_t ldm, const void *Np,
                   int64_t nr, int64_t nc, int64_t ldn, const void *Vp, int64_t ldv, void *Up,
-                  int64_t ldu, hipStream_t s) {
+                  int64_t ldu, void *ws, hipStream_t s) {
   if (mr == 0 || nr == 0) return;
   if (prec == GVT_BF16X3 || prec == GVT_BF16X6) {
     if (prec == GVT_BF16X3)
       dense_split_bf16<2>((const float *)Mp, mr, mc, ldm, (const float *)Np, nr, nc, ldn,
-                          (const float *)Vp, ldv, (float *)Up, ldu, s);
+                          (const float *)Vp, ldv, (float *)Up, ldu, ws, s);
     else
       dense_split_bf16<3>((const float *)Mp, mr, mc, ldm, (const float *)Np, nr, nc, ldn,
-                          (const float *)Vp, ldv, (float *)Up, ldu, s);
+                          (const float *)Vp, ldv, (float *)Up, ldu, ws, s);
     return;
   }
-  const size_t es = prec == GVT_F64 ? sizeof(double) : sizeof(float);
-  void *W = nullptr;
-  GVT_HIP_CHECK(hipMallocAsync(&W, (size_t)mr * nc * es + 256, s));
+  void *W = ws;
+  if (!W) GVT_HIP_CHECK(hipMallocAsync(&W, dense_workspace_bytes(prec, mr, mc, nr, nc), s));
   if (prec == GVT_F64) {
     gemm<double, false>((const double *)Mp, ldm, (const double *)Vp, ldv, (double *)W, nc, mr, nc, mc, s);
     gemm<double, true>((const double *)W, nc, (const double *)Np, ldn, (double *)Up, ldu, mr, nr, nc, s);
@@ -519,7 +521,7 @@ void dense_matvec(int prec, const void *Mp, int64_t mr, int64_t mc, int64_t ldm,
     gemm<float, true>((const float *)W, nc, (const float *)Np, ldn, (float *)Up, ldu, mr, nr, nc, s);
   }
   check_launch(s);
-  GVT_HIP_CHECK(hipFreeAsync(W, s));
+  if (!ws) GVT_HIP_CHECK(hipFreeAsync(W, s));
 }
 
 }  // namespace gvt

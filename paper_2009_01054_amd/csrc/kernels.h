@@ -148,9 +148,24 @@ template <class T>
 void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64_t nitems, int R,
                          int64_t r0, const uint8_t *active, hipStream_t s);
 
-// Dense complete-data path (matrix cores).
+// Dense complete-data path (matrix cores).  ws: workspace of at least
+// dense_workspace_bytes (W or the split bf16 pieces); null = the product
+// allocates it stream-ordered.
+size_t dense_workspace_bytes(int prec, int64_t mr, int64_t mc, int64_t nr, int64_t nc);
 void dense_matvec(int prec, const void *M, int64_t mr, int64_t mc, int64_t ldm, const void *N,
                   int64_t nr, int64_t nc, int64_t ldn, const void *V, int64_t ldv, void *U,
-                  int64_t ldu, hipStream_t s);
+                  int64_t ldu, void *ws, hipStream_t s);
+// Base kernel matrices from features (linear / Gaussian Gram products on
+// matrix cores, Tanimoto by popcount).  Y null: Y = X, exactly symmetric K.
+void base_kernel(int kind, int prec, const void *X, int64_t nx, int64_t ldx, const void *Y, int64_t ny,
+                 int64_t ldy, int64_t dim, double gamma, void *K, int64_t ldk, hipStream_t s);
+void tanimoto_kernel_matrix(int prec, const uint64_t *X, int64_t nx, int64_t ldx, const uint64_t *Y,
+                            int64_t ny, int64_t ldy, int64_t nbits, void *K, int64_t ldk, hipStream_t s);
+// ||U_S - U_S,ref||_F / ||U_S,ref||_F over up to 32 evenly spaced rows S of
+// Umat = M Vmat N^T, with U_S,ref recomputed in FP64 from the stored operands
+// (double for GVT_F64, float otherwise).  Synchronises s.
+double dense_sample_relerr(int prec, const void *M, int64_t mr, int64_t mc, int64_t ldm, const void *N,
+                           int64_t nr, int64_t nc, int64_t ldn, const void *V, int64_t ldv,
+                           const void *U, int64_t ldu, hipStream_t s);
 
 }  // namespace gvt

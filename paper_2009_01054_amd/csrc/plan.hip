@@ -1060,7 +1060,7 @@ void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void 
       const size_t es = prec == GVT_F64 ? 8 : 4;
       dense_matvec(prec, D, P->d_rows, P->d_cols, ldd, T, P->t_rows, P->t_cols, ldt,
                    static_cast<const char *>(V) + r * ldv * es, P->t_cols,
-                   static_cast<char *>(U) + r * ldu * es, P->t_rows, s);
+                   static_cast<char *>(U) + r * ldu * es, P->t_rows, nullptr, s);
     }
     return;
   }
