@@ -232,6 +232,27 @@ int gvt_dense_matvec_checked(int prec, const void *M, int64_t m_rows, int64_t m_
                              double *relerr_out, int *prec_out, void *stream);
 
 /*
+ * gvt_dense_matvec_noalloc — gvt_dense_matvec for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and precisions
+ * as gvt_dense_matvec; the intermediate W (or the split bf16 pieces) lives in
+ * a static per-device workspace of 64 MiB (GVT_DENSE_NOALLOC_BYTES) that
+ * each device using the library holds until the process ends.  The call
+ * makes no hipMalloc/hipFree and no allocating library call.  Products whose
+ * workspace exceeds the limit return GVT_ERR_ARG with the sizes in
+ * gvt_last_error(): W needs m_rows x n_cols elements (8 bytes for GVT_F64,
+ * 4 for GVT_F32); the split forms need 2 (GVT_BF16X3) or 3 (GVT_BF16X6)
+ * bf16 copies of M, N, Vmat and W with k padded to 64 (32).  Every call on a
+ * device uses the same workspace: calls that overlap on one device (two
+ * streams, two threads) race and must be serialised by the caller.
+ * Asynchronous on `stream`.
+ */
+#define GVT_DENSE_NOALLOC_BYTES ((int64_t)64 << 20)
+int gvt_dense_matvec_noalloc(int prec, const void *M, int64_t m_rows, int64_t m_cols, int64_t ldm,
+                             const void *N, int64_t n_rows, int64_t n_cols, int64_t ldn,
+                             const void *V, int64_t ldv, void *U, int64_t ldu, void *stream);
+
+/*
  * gvt_base_kernel — a base kernel matrix from object features (Section 5:
  * linear kernels <x, y> and Gaussian kernels exp(-gamma ||x - y||^2) on
  * feature or similarity-row vectors, the drug and target kernels D and T of

@@ -23,6 +23,7 @@ from ._binding import (  # noqa: F401
     gvt_base_kernel,
     gvt_dense_matvec,
     gvt_dense_matvec_checked,
+    gvt_dense_matvec_noalloc,
     gvt_empty_cache,
     gvt_krr_cg,
     gvt_krr_cg_batched,

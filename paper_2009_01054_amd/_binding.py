@@ -58,6 +58,7 @@ def load_library():
     lib.gvt_pairwise_matvec.argtypes = [I, P, I, P, I64, I64, I64, P, I64, I64, I64, P, P, I64, P, P, I64,
                                         P, I64, I64, P, I64, I, P]
     lib.gvt_dense_matvec.argtypes = [I, P, I64, I64, I64, P, I64, I64, I64, P, I64, P, I64, P]
+    lib.gvt_dense_matvec_noalloc.argtypes = [I, P, I64, I64, I64, P, I64, I64, I64, P, I64, P, I64, P]
     lib.gvt_base_kernel.argtypes = [I, I, P, I64, I64, P, I64, I64, I64, ctypes.c_double, P, I64, P]
     lib.gvt_krr_minres.argtypes = [I, P, I64, I64, P, I64, I64, P, P, I64, P, P, I, P, I64, I, ctypes.c_double,
                                    I, P, I, P, P, P, P, P, P]
@@ -71,7 +72,7 @@ def load_library():
     lib.gvt_plan_info.argtypes = [P, P]
     lib.gvt_empty_cache.argtypes = [P]
     for f in ("gvt_plan_profile", "gvt_plan_info", "gvt_plan_create", "gvt_plan_destroy", "gvt_plan_execute", "gvt_matvec",
-              "gvt_pairwise_matvec", "gvt_dense_matvec", "gvt_dense_matvec_checked", "gvt_base_kernel", "gvt_tanimoto_kernel", "gvt_krr_minres", "gvt_krr_cg", "gvt_krr_cg_batched", "gvt_empty_cache"):
+              "gvt_pairwise_matvec", "gvt_dense_matvec", "gvt_dense_matvec_noalloc", "gvt_dense_matvec_checked", "gvt_base_kernel", "gvt_tanimoto_kernel", "gvt_krr_minres", "gvt_krr_cg", "gvt_krr_cg_batched", "gvt_empty_cache"):
         getattr(lib, f).restype = I
     _lib = lib
     return lib
@@ -340,6 +341,19 @@ def gvt_dense_matvec_checked(M, N, Vmat, prec=None, max_relerr=1e-5, out=None):
                                              float(max_relerr), ctypes.byref(est), ctypes.byref(used),
                                              _stream_handle()))
     return U, est.value, used.value, rc
+
+
+def gvt_dense_matvec_noalloc(M, N, Vmat, prec=None, out=None):
+    """Umat = M Vmat N^T like gvt_dense_matvec, with the library's static per-device
+    workspace instead of an allocation (calls on one device must not overlap)."""
+    torch = _torch()
+    lib = load_library()
+    p = _prec_of(M.dtype, prec)
+    U = out if out is not None else torch.empty((M.shape[0], N.shape[0]), dtype=M.dtype, device=M.device)
+    _check(lib.gvt_dense_matvec_noalloc(p, _ptr(M), M.shape[0], M.shape[1], _ld(M), _ptr(N), N.shape[0],
+                                        N.shape[1], _ld(N), _ptr(Vmat), _ld(Vmat), _ptr(U), _ld(U),
+                                        _stream_handle()))
+    return U
 
 
 class _Validation(ctypes.Structure):

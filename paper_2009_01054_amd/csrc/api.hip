@@ -416,6 +416,30 @@ int gvt_dense_matvec_checked(int prec, const void *M, int64_t m_rows, int64_t m_
   });
 }
 
+int gvt_dense_matvec_noalloc(int prec, const void *M, int64_t m_rows, int64_t m_cols, int64_t ldm,
+                             const void *N, int64_t n_rows, int64_t n_cols, int64_t ldn,
+                             const void *V, int64_t ldv, void *U, int64_t ldu, void *stream) {
+  return guarded([&]() {
+    GVT_REQUIRE(prec == GVT_F64 || prec == GVT_F32 || prec == GVT_BF16X3 || prec == GVT_BF16X6, GVT_ERR_ARG,
+                "unknown precision");
+    GVT_REQUIRE(m_rows >= 0 && m_cols >= 0 && n_rows >= 0 && n_cols >= 0, GVT_ERR_ARG,
+                "negative size");
+    GVT_REQUIRE(ldm >= m_cols && ldn >= n_cols && ldv >= n_cols && ldu >= n_rows, GVT_ERR_ARG,
+                "leading dimension too small");
+    GVT_REQUIRE((m_rows == 0 || n_rows == 0) || (M && N && V && U), GVT_ERR_ARG, "null pointer");
+    const size_t need = dense_workspace_bytes(prec, m_rows, m_cols, n_rows, n_cols);
+    if (need == 0) return GVT_OK;
+    if (need > kDenseScratchBytes) {
+      set_error("gvt_dense_matvec_noalloc: this product needs %zu bytes of workspace, more than the "
+                "%zu bytes of the static workspace", need, kDenseScratchBytes);
+      return GVT_ERR_ARG;
+    }
+    dense_matvec(prec, M, m_rows, m_cols, ldm, N, n_rows, n_cols, ldn, V, ldv, U, ldu,
+                 dense_scratch_ptr(), (hipStream_t)stream);
+    return GVT_OK;
+  });
+}
+
 int gvt_krr_cg(int kind, const double *D, int64_t d, int64_t ldd, const double *T, int64_t t,
                int64_t ldt, const int32_t *c, const int32_t *e, int64_t n, const double *y,
                const double *lambdas, int nlam, double *A, int64_t lda, const double *A0,

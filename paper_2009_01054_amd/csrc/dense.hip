@@ -17,6 +17,9 @@
 // Tiling: 256 threads (2 x 2 waves), block tile 128 x 128, each wave owns a
 // 64 x 64 sub-tile (4 x 4 MFMA blocks of 16 x 16).  Global tiles are
 // prefetched into registers while the current LDS tile feeds the MFMAs.
+#include <map>
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
 #include "mfma.h"
@@ -522,6 +525,29 @@ void dense_matvec(int prec, const void *Mp, int64_t mr, int64_t mc, int64_t ldm,
   }
   check_launch(s);
   if (!ws) GVT_HIP_CHECK(hipFreeAsync(W, s));
+}
+
+// ---- the product without allocation ----------------------------------------
+// One workspace per device for gvt_dense_matvec_noalloc, in the code object's
+// own device memory (each device that loads the library holds its copy until
+// the process ends).  Host code never passes the array's name to a kernel: in
+// host code it is only a stand-in for the symbol, so its device address is
+// looked up once per device with that device current and kept.
+static __device__ __align__(256) unsigned char dense_scratch[kDenseScratchBytes];
+
+void *dense_scratch_ptr() {
+  static std::mutex mu;
+  static std::map<int, void *> ptr_of;
+  int dev = 0;
+  GVT_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = ptr_of.find(dev);
+  if (it != ptr_of.end()) return it->second;
+  void *p = nullptr;
+  GVT_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(dense_scratch)));
+  GVT_REQUIRE(p != nullptr, GVT_ERR_HIP, "no device address for the dense workspace");
+  ptr_of[dev] = p;
+  return p;
 }
 
 }  // namespace gvt

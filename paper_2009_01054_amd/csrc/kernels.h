@@ -167,5 +167,9 @@ void tanimoto_kernel_matrix(int prec, const uint64_t *X, int64_t nx, int64_t ldx
 double dense_sample_relerr(int prec, const void *M, int64_t mr, int64_t mc, int64_t ldm, const void *N,
                            int64_t nr, int64_t nc, int64_t ldn, const void *V, int64_t ldv,
                            const void *U, int64_t ldu, hipStream_t s);
+// Workspace of gvt_dense_matvec_noalloc: kDenseScratchBytes of static device
+// memory per device; the pointer is this device's copy.
+constexpr size_t kDenseScratchBytes = (size_t)64 << 20;
+void *dense_scratch_ptr();
 
 }  // namespace gvt
