@@ -19,10 +19,14 @@ with g = dL/dp.  Losses (y in {-1, +1} for the classification losses):
 (K + lambda I) a = y, with the same lambda).  The (generalised) Hessian is
 K D K + lambda K with D = diag(d), d = d^2L/dp^2: 1, sigma(yp) sigma(-yp), [y p < 1].
 
-Truncated Newton: each step solves K (D K + lambda I) delta = -grad J approximately by
-conjugate gradients (Hessian products H v = K (d * (K v) + lambda v), two kernel products),
-stopped at max_cg iterations or when ||r|| <= min(1/2, sqrt(||grad|| / ||grad_0||)) ||grad||,
-then backtracks t = 1, 1/2, ... until J(a + t delta) <= J(a) + 1e-4 t grad.delta (at most 30
+Truncated Newton: the Newton equation K (D K + lambda I) delta = -grad J is met by any
+delta with (D K + lambda I) delta = -(g + lambda a).  That operator is self-adjoint and
+positive in the K inner product <x, y>_K = x^T K y, so each step runs conjugate gradients on
+it in that inner product: <z, A z>_K = (K z)^T (d * (K z) + lambda z) and
+<r, r>_K = r^T (K r), one kernel product K r per iteration, with K z and K delta carried by
+the same recurrences as z and delta.  CG stops after max_cg iterations or once
+sqrt(<r, r>_K) <= min(1/2, sqrt(||grad|| / ||grad_0||)) sqrt(<r_0, r_0>_K), then the step
+backtracks t = 1, 1/2, ... until J(a + t delta) <= J(a) + 1e-4 t grad.delta (at most 30
 halvings).  The outer loop stops when ||grad J|| <= tol ||grad J(0)|| or after max_newton
 steps.  Products are the oracle's Table 4b double loop; everything else is FP64 numpy.
 """
@@ -106,25 +110,30 @@ def newton(kind, D, T, pairs, y, lam, loss, max_newton=20, max_cg=50, tol=1e-8):
         eta = min(0.5, np.sqrt(gn / g0))
         x = np.zeros(n)
         Kx = np.zeros(n)
-        r = -grad
+        r = -(g + lam * a)
+        Kr = -grad
         z = r.copy()
-        rr = float(r @ r)
+        Kz = Kr.copy()
+        rho = float(r @ Kr)
+        rho0 = rho
         for _ in range(max_cg):
-            Kz = _K(kind, D, T, pairs, z)
-            Hz = _K(kind, D, T, pairs, d * Kz + lam * z)
-            zHz = float(z @ Hz)
+            Az = d * Kz + lam * z
+            zAz = float(Kz @ Az)
             cg_total += 1
-            if not zHz > 0.0:
+            if not (zAz > 0.0 and rho > 0.0):
                 break
-            alpha = rr / zHz
+            alpha = rho / zAz
             x = x + alpha * z
             Kx = Kx + alpha * Kz
-            r = r - alpha * Hz
-            rr_new = float(r @ r)
-            if np.sqrt(rr_new) <= eta * gn:
+            r = r - alpha * Az
+            Kr = _K(kind, D, T, pairs, r)
+            rho_new = float(r @ Kr)
+            if not rho_new > 0.0 or np.sqrt(rho_new) <= eta * np.sqrt(rho0):
                 break
-            z = r + (rr_new / rr) * z
-            rr = rr_new
+            beta = rho_new / rho
+            z = r + beta * z
+            Kz = Kr + beta * Kz
+            rho = rho_new
         if not np.any(x):
             break
         slope = float(grad @ x)
