@@ -221,7 +221,58 @@ def preset_dense(args, gvt, W, torch, np, dev):
         log(f"[bench] dense {name}: {ms:.3f} ms, {achieved:.1f} TFLOP/s effective, err {err:.2e}")
         del D, T, V, U
         torch.cuda.empty_cache()
+    # bf16x3 with its error measured on sampled FP64 rows (and bf16x6 where the estimate
+    # reaches half of 1e-5): the form the 1e-5 target is asserted on
+    D = torch.from_numpy(p["D"]).to(dev, torch.float32)
+    T = torch.from_numpy(p["T"]).to(dev, torch.float32)
+    V = torch.from_numpy(p["V"]).to(dev, torch.float32)
+    U = torch.empty((m, q), dtype=torch.float32, device=dev)
+    box = {}
+
+    def checked():
+        box["r"] = gvt.gvt_dense_matvec_checked(D, T, V, prec=gvt.BF16X3, max_relerr=1e-5, out=U)
+    ms = _event_ms(torch, checked, 3)
+    _, est, used, rc = box["r"]
+    res["bf16x3_checked"] = {"ms": round(ms, 4), "estimated_rel_err": est,
+                             "precision_used": {2: "bf16x3", 3: "bf16x6", 1: "f32"}.get(used, used),
+                             "rel_err_sampled_64_rows": _relerr(U[rows].double().cpu().numpy(), ref)}
+    log(f"[bench] dense bf16x3 checked: {ms:.3f} ms, estimate {est:.2e}, used {used}")
+    del D, T, V, U
+    torch.cuda.empty_cache()
+    res["incomplete_grid"] = tiles_sweep(gvt, W, torch, np, dev)
     return res
+
+
+def tiles_sweep(gvt, W, torch, np, dev):
+    """Dense-but-incomplete data: a 4096 x 2048 grid (Gaussian bases, 32-dim) sampled at
+    several densities, one product by the gather path and by dense tiles (M Vmat N^T on
+    matrix cores), FP64 and FP32; the plan's cost-model choice beside the times."""
+    m, q = 4096, 2048
+    rng = W.rng_for(4, 1)
+    Xd, Xt = rng.standard_normal((m, 32)), rng.standard_normal((q, 32))
+    D64 = torch.from_numpy(W.gaussian_kernel(Xd)).to(dev)
+    T64 = torch.from_numpy(W.gaussian_kernel(Xt)).to(dev)
+    out = {"grid": f"{m} x {q}", "rows": []}
+    for dens in (0.05, 0.1, 0.2, 0.35, 0.5):
+        n = int(dens * m * q)
+        cells = rng.choice(m * q, n, replace=False)
+        c = torch.from_numpy((cells // q).astype(np.int32)).to(dev)
+        e = torch.from_numpy((cells % q).astype(np.int32)).to(dev)
+        row = {"density": dens, "n": n}
+        for name, prec, dt in [("f64", gvt.F64, torch.float64), ("f32", gvt.F32, torch.float32)]:
+            Dp, Tp = D64.to(dt), T64.to(dt)
+            v = torch.randn(n, dtype=dt, device=dev)
+            for mode, fl in [("gather", gvt.FLAG_NO_DENSE_TILES), ("tiles", gvt.FLAG_DENSE_TILES)]:
+                pl = gvt.gvt_plan_create("kronecker", Dp.shape, Tp.shape, (c, e), (c, e),
+                                         flags=gvt.FLAG_SYMMETRIC_BASES | fl)
+                row[f"{name}_{mode}_ms"] = round(_event_ms(torch, lambda: pl.execute(Dp, Tp, v), 3), 4)
+                pl.close()
+            pl = gvt.gvt_plan_create("kronecker", Dp.shape, Tp.shape, (c, e), (c, e), flags=gvt.FLAG_SYMMETRIC_BASES)
+            row[f"{name}_auto"] = "tiles" if gvt.gvt_plan_uses_tiles(pl, prec) else "gather"
+            pl.close()
+        out["rows"].append(row)
+        log(f"[bench] incomplete grid {row}")
+    return out
 
 
 def preset_batched(args, gvt, W, torch, np, dev):
@@ -325,6 +376,109 @@ def counter_workload(args, gvt, W, torch, np, dev):
             "copy_read_bytes": nbytes, "copy_write_bytes": nbytes}
 
 
+def headline_extras(args, gvt, W, torch, np, dev, p, D, T, c, e, y, plan_ms):
+    """Records beside the headline solve, all on the ridge workload and outside its
+    timed region: base kernels built from the features then the solve; MINRES with
+    validation-AUC early stopping; the product as dense tiles against the gather path;
+    logistic regression by truncated Newton."""
+    out = {}
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(reps):
+            r = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps, r
+
+    # ---- features -> D, T -> solution (Section 5 base kernels, then the CG solve)
+    Xd = torch.from_numpy(p["Xd"]).to(dev)
+    Xt = torch.from_numpy(p["Xt"]).to(dev)
+    g = 1.0 / (2.0 * W.SIGMA ** 2)
+
+    def features_to_solution():
+        Dg = gvt.gvt_base_kernel("gaussian", Xd, None, gamma=g)
+        Tg = gvt.gvt_base_kernel("gaussian", Xt, None, gamma=g)
+        return gvt.gvt_krr_cg("kronecker", Dg, Tg, (c, e), y, [p["lam"]], max_iter=200, tol=1e-6)
+
+    kern_ms, _ = timed(lambda: (gvt.gvt_base_kernel("gaussian", Xd, None, gamma=g),
+                                gvt.gvt_base_kernel("gaussian", Xt, None, gamma=g)), reps=5)
+    f2s_ms, (_, it_f, rel_f, _) = timed(features_to_solution)
+    dbytes = (2000 * 2000 + 500 * 500) * 8
+    out["features_to_solution"] = {
+        "base_kernels_ms": round(kern_ms, 4),
+        "base_kernels_write_tbps": round(dbytes / (kern_ms * 1e-3) / 1e12, 3),
+        "total_ms": round(f2s_ms, 4), "iterations": int(it_f[0]), "true_relres": float(rel_f[0]),
+        "what": "Gaussian D (2000x2000) and T (500x500) from 64-dim features on matrix cores, then the CG solve",
+    }
+    log(f"[bench] features->solution {f2s_ms:.2f} ms (base kernels {kern_ms:.3f} ms)")
+
+    # ---- MINRES: to the CG tolerance, and with early stopping on a 75/25 split
+    mr_ms, mr = timed(lambda: gvt.gvt_krr_minres("kronecker", D, T, (c, e), y, [p["lam"]], max_iter=200,
+                                                 tol=1e-6), reps=2)
+    n = len(p["c"])
+    cut = (3 * n) // 4
+    ci, ei, yi = c[:cut].contiguous(), e[:cut].contiguous(), y[:cut].contiguous()
+    va, vb = c[cut:].contiguous(), e[cut:].contiguous()
+    yv = (y[cut:] > 0).double().contiguous()
+    lams_es = [1e-4, 1e-3, 1e-2]
+    es_ms, es = timed(lambda: gvt.gvt_krr_minres("kronecker", D, T, (ci, ei), yi, lams_es, max_iter=200, tol=0.0,
+                                                 val=(va, vb, yv), patience=10), reps=2)
+    out["minres"] = {
+        "to_tol": {"lambda": p["lam"], "iterations": int(mr["iters"][0]), "true_relres": float(mr["relres"][0]),
+                   "solve_ms": round(mr_ms, 4)},
+        "early_stopping": {
+            "split": f"first {cut} pairs train, last {n - cut} validate; labels > 0 positive",
+            "lambdas": lams_es, "patience": 10, "solve_ms": round(es_ms, 4),
+            "iterations": [int(x) for x in es["iters"]], "best_iter": [int(x) for x in es["best_iter"]],
+            "best_auc": [round(float(x), 6) for x in es["best_auc"]],
+            "products_per_iteration": 2,
+        },
+    }
+    log(f"[bench] minres {mr_ms:.2f} ms ({int(mr['iters'][0])} it); early stopping {es_ms:.2f} ms, "
+        f"best it {list(es['best_iter'])}, auc {list(es['best_auc'])}")
+
+    # ---- the product as dense tiles (M Vmat N^T on matrix cores) against the gather path
+    v64 = torch.randn(n, dtype=torch.float64, device=dev)
+    tiles = {}
+    for name, dt, pc in [("f64", torch.float64, gvt.F64), ("f32", torch.float32, gvt.F32),
+                         ("bf16x3", torch.float32, gvt.BF16X3), ("bf16x6", torch.float32, gvt.BF16X6)]:
+        Dp, Tp, vp = D.to(dt), T.to(dt), v64.to(dt)
+        row = {}
+        for mode, fl in [("gather", gvt.FLAG_NO_DENSE_TILES), ("tiles", gvt.FLAG_DENSE_TILES)]:
+            if mode == "gather" and name.startswith("bf16"):
+                continue
+            pl = gvt.gvt_plan_create("kronecker", D.shape, T.shape, (c, e), (c, e),
+                                     flags=gvt.FLAG_SYMMETRIC_BASES | fl)
+            ms, _ = timed(lambda: pl.execute(Dp, Tp, vp, prec=pc), reps=10)
+            pl.close()
+            row[mode + "_ms"] = round(ms, 4)
+        pl = gvt.gvt_plan_create("kronecker", D.shape, T.shape, (c, e), (c, e), flags=gvt.FLAG_SYMMETRIC_BASES)
+        row["auto_takes"] = "tiles" if gvt.gvt_plan_uses_tiles(pl, pc) else "gather"
+        pl.close()
+        tiles[name] = row
+    out["dense_tiles"] = {
+        "density": round(n / (2000 * 500), 4),
+        "flops_per_product": 2.0 * 2000 * 2000 * 500 + 2.0 * 2000 * 500 * 500,
+        "per_precision": tiles,
+    }
+    log(f"[bench] dense tiles {tiles}")
+
+    # ---- logistic regression by truncated Newton on the same pairs (labels: sign of y)
+    yb = torch.where(y > 0, 1.0, -1.0).to(torch.float64)
+    lg_ms, lg = timed(lambda: gvt.gvt_erm_newton("kronecker", "logistic", D, T, (c, e), yb, 1e-2, max_newton=30,
+                                                  max_cg=100, tol=1e-6), reps=1)
+    out["logistic_newton"] = {"lambda": 1e-2, "steps": lg["steps"], "cg_iterations": lg["cg_iters"],
+                              "grad_reduction": lg["gnorm"] / lg["gnorm0"], "objective": lg["J"],
+                              "solve_ms": round(lg_ms, 4), "products": 2 * lg["steps"] + 2 + lg["cg_iters"]}
+    log(f"[bench] logistic newton {lg_ms:.1f} ms, {lg['steps']} steps, {lg['cg_iters']} CG")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -381,22 +535,33 @@ def main():
         return gvt.gvt_krr_cg("kronecker", D, T, (c, e), y, lam, max_iter=200, tol=1e-6,
                               matvec_prec=prec, check_every=8)
 
-    for i in range(args.warmup):
-        _, it, rel, rc = solve(mprec)
-        log(f"[bench] warmup {i}: iters {int(it[0])} true relres {rel[0]:.3e} rc {rc}")
+    # The timed solves run on a stream of their own, where the library replays
+    # blocks of CG iterations from a captured HIP graph; the same solves on the
+    # null stream (kernel by kernel) are timed afterwards for comparison.
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        for i in range(args.warmup):
+            _, it, rel, rc = solve(mprec)
+            log(f"[bench] warmup {i}: iters {int(it[0])} true relres {rel[0]:.3e} rc {rc}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters_total = 0
     rels = []
-    solve_ms = []  # each solve ends with a device synchronisation
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        _, it, rel, rc = solve(mprec)
-        solve_ms.append((time.perf_counter() - ts) * 1e3)
-        iters_total += int(it.sum())
-        rels.append(float(rel.max()))
+    solve_ms = []  # each solve ends with a synchronisation of its stream
+    with torch.cuda.stream(side):
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            _, it, rel, rc = solve(mprec)
+            solve_ms.append((time.perf_counter() - ts) * 1e3)
+            iters_total += int(it.sum())
+            rels.append(float(rel.max()))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    eager_ms = []
+    for _ in range(max(2, args.steps // 2)):
+        ts = time.perf_counter()
+        solve(mprec)
+        eager_ms.append((time.perf_counter() - ts) * 1e3)
     ms_per_step = elapsed / args.steps * 1e3
     value = iters_total / elapsed
     log(f"[bench] timed {args.steps} solves: {ms_per_step:.2f} ms/solve, {iters_total / args.steps:.1f} "
@@ -464,6 +629,8 @@ def main():
     }
     log(f"[bench] stage ms {stage_ms}, matvec {matvec_ms:.4f} ms, plan {plan_ms:.1f} ms")
 
+    extras = headline_extras(args, gvt, W, torch, np, dev, p, D, T, c, e, y, plan_ms)
+
     cpu = cpu1 = None
     if not args.no_cpu:
         pv = {**p, "v": np.random.default_rng(7).standard_normal(n)}
@@ -500,6 +667,8 @@ def main():
             "solve_ms": {"median": round(float(np.median(solve_ms)), 4),
                          "p10": round(float(np.percentile(solve_ms, 10)), 4),
                          "p90": round(float(np.percentile(solve_ms, 90)), 4), "n": len(solve_ms)},
+            "stream": "side stream: blocks of 8 iterations replayed from a captured HIP graph",
+            "null_stream_solve_ms": round(float(np.median(eager_ms)), 4),
             "iterations": iters_total // args.steps,
             "true_relres_max": max(rels),
             "plan_ms": round(plan_ms, 3),
@@ -512,6 +681,7 @@ def main():
             },
         },
         "roofline": roofline,
+        **extras,
         "cpu_baseline": cpu,
         "cpu_baseline_one_core": cpu1,
         "kernel_source_sha": source_sha(),

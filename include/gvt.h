@@ -100,12 +100,21 @@ extern "C" {
 #define GVT_BASE_LINEAR 0   /* k(x, y) = <x, y>                  */
 #define GVT_BASE_GAUSSIAN 1 /* k(x, y) = exp(-gamma ||x - y||^2) */
 
+/* ---- losses of the regularized risk (Section 3) ------------------------- */
+#define GVT_LOSS_SQUARED 0  /* 1/2 sum (y - p)^2                    */
+#define GVT_LOSS_LOGISTIC 1 /* sum log(1 + exp(-y p)), y in {-1, 1}  */
+#define GVT_LOSS_SQHINGE 2  /* 1/2 sum max(0, 1 - y p)^2             */
+#define GVT_LOSS_HINGE 3    /* sum max(0, 1 - y p) (subgradient)     */
+
 /* ---- plan flags ---------------------------------------------------------- */
 #define GVT_FLAG_SYMMETRIC_BASES 1 /* D and T are square and symmetric (training
                                       kernels): the library may read a column as
                                       the equal row instead of transposing      */
 #define GVT_FLAG_ORDER_A 2         /* force stage order A (scatter by drug)      */
 #define GVT_FLAG_ORDER_B 4         /* force stage order B (scatter by target)    */
+#define GVT_FLAG_DENSE_TILES 8     /* single Kronecker term: always run products
+                                      as M Vmat N^T on matrix cores (dense tiles) */
+#define GVT_FLAG_NO_DENSE_TILES 16 /* never use dense tiles (gather path only)   */
 
 typedef struct gvt_plan *gvt_plan_t;
 
@@ -212,7 +221,7 @@ int gvt_dense_matvec(int prec, const void *M, int64_t m_rows, int64_t m_cols, in
 /*
  * gvt_dense_matvec_checked — gvt_dense_matvec with the error of the result
  * measured and bounded (the complete-data product of Section 3's vec-trick
- * identity, as gvt_dense_matvec).  After the product it recomputes up to 32
+ * identity, as gvt_dense_matvec).  After the product it recomputes up to 16
  * evenly spaced rows of Umat in FP64 from the same stored operands and
  * estimates the norm-wise relative error ||U_S - U_S,ref|| / ||U_S,ref||
  * over those rows.  While the estimate exceeds max_relerr / 2 the product is
@@ -411,6 +420,47 @@ int gvt_krr_minres(int kind, const double *D, int64_t d, int64_t ldd, const doub
                    double *auc_hist, void *stream);
 
 /*
+ * gvt_erm_objective — the regularized risk of Section 3 in dual coefficients
+ * and its (sub)gradient, for the losses GVT_LOSS_*:
+ *   J(a) = L(K a, y) + (lambda / 2) a^T K a,   grad J = K (g + lambda a),
+ * g = dL/dp at p = K a (the hinge loss: the subgradient -y [y p < 1]).  K is
+ * the training kernel matrix of `kind` on the pairs (c, e) (D, T, c, e, n, y
+ * as in gvt_krr_cg; classification losses take y in {-1, +1}).  a: n
+ * coefficients (device, double).  grad: n (device, double) or NULL.
+ * *obj_out (host) receives J(a).  Two products (one without grad).
+ * Synchronises `stream`.  Errors: GVT_ERR_ARG, GVT_ERR_BREAKDOWN (non-finite
+ * J), GVT_ERR_HIP, GVT_ERR_NOMEM.
+ */
+int gvt_erm_objective(int kind, int loss, const double *D, int64_t d, int64_t ldd, const double *T,
+                      int64_t t, int64_t ldt, const int32_t *c, const int32_t *e, int64_t n,
+                      const double *y, const double *a, double lambda, double *grad, double *obj_out,
+                      void *stream);
+
+/*
+ * gvt_erm_newton — minimises J (gvt_erm_objective) from a = 0 by truncated
+ * Newton, the optimiser Section 3 names for losses other than the squared
+ * one (kernel logistic regression, L2-SVM).  Each step solves
+ * K (D K + lambda I) delta = -grad J by conjugate gradients with Hessian
+ * products K (d * (K v) + lambda v), D = diag(d), d = d^2L/dp^2, stopped after
+ * max_cg iterations or once the CG residual is below
+ * min(1/2, sqrt(||grad|| / ||grad_0||)) ||grad||; then backtracks t = 1, 1/2,
+ * ... (at most 30 halvings) until J(a + t delta) <= J(a) + 1e-4 t grad.delta.
+ * Stops when ||grad J|| <= tol ||grad J(0)|| or after max_newton steps.
+ * loss: GVT_LOSS_SQUARED, _LOGISTIC or _SQHINGE (the hinge: GVT_ERR_UNSUPPORTED).
+ * lambda >= 0.  A: n coefficients out (device, double).  matvec_prec: GVT_F64
+ * or GVT_F32 products (vectors and scalars FP64).  Host outputs (may be NULL):
+ * Newton steps, total CG iterations, J and ||grad J|| at A, ||grad J(0)||.
+ * Synchronises `stream`.  Returns GVT_OK when the gradient test was met,
+ * GVT_NOT_CONVERGED after max_newton steps, GVT_ERR_BREAKDOWN on a
+ * non-finite value.
+ */
+int gvt_erm_newton(int kind, int loss, const double *D, int64_t d, int64_t ldd, const double *T,
+                   int64_t t, int64_t ldt, const int32_t *c, const int32_t *e, int64_t n,
+                   const double *y, double lambda, double *A, int max_newton, int max_cg, double tol,
+                   int matvec_prec, int *steps_out, int *cg_iters_out, double *obj_out,
+                   double *gnorm_out, double *gnorm0_out, void *stream);
+
+/*
  * gvt_plan_profile — diagnostic: runs gvt_plan_execute `reps` times
  * (synchronising `stream` after each) with HIP events recorded at the stage
  * boundaries of the generalized vec trick, and writes the mean milliseconds
@@ -433,6 +483,18 @@ int gvt_plan_profile(gvt_plan_t plan, int prec, const void *D, int64_t ldd, cons
  * target, -1 = none), and the unique counts of a, b, c, e (Table 1).
  */
 int gvt_plan_info(gvt_plan_t plan, double *info);
+
+/*
+ * gvt_plan_uses_tiles — diagnostic: 1 when products of the plan in precision
+ * prec run as dense tiles (a single Kronecker term computed as M Vmat N^T on
+ * matrix cores, Vmat the zero grid with the input vector scattered into it):
+ * always with GVT_FLAG_DENSE_TILES or environment GVT_DENSE_TILES=1 at plan
+ * creation and for the split-bf16 precisions; never with
+ * GVT_FLAG_NO_DENSE_TILES or GVT_DENSE_TILES=0; otherwise when the tuned cost
+ * model estimates the dense product faster than the gather path.  0 when the
+ * gather path runs, GVT_ERR_ARG for a null plan.
+ */
+int gvt_plan_uses_tiles(gvt_plan_t plan, int prec);
 
 /*
  * gvt_empty_cache — releases the memory the library keeps for reuse.  Device

@@ -14,6 +14,8 @@ from ._binding import (  # noqa: F401
     BF16X6,
     F32,
     F64,
+    FLAG_DENSE_TILES,
+    FLAG_NO_DENSE_TILES,
     FLAG_ORDER_A,
     FLAG_ORDER_B,
     FLAG_SYMMETRIC_BASES,
@@ -25,6 +27,8 @@ from ._binding import (  # noqa: F401
     gvt_dense_matvec_checked,
     gvt_dense_matvec_noalloc,
     gvt_empty_cache,
+    gvt_erm_newton,
+    gvt_erm_objective,
     gvt_krr_cg,
     gvt_krr_cg_batched,
     gvt_krr_minres,
@@ -37,6 +41,7 @@ from ._binding import (  # noqa: F401
     gvt_plan_execute,
     gvt_plan_info,
     gvt_plan_profile,
+    gvt_plan_uses_tiles,
     gvt_version,
     library_path,
     load_library,

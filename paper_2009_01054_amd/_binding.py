@@ -11,6 +11,7 @@ _LIB_PATH = os.path.join(_PKG, "libgvt.so")
 
 F64, F32, BF16X3, BF16X6 = 0, 1, 2, 3
 FLAG_SYMMETRIC_BASES, FLAG_ORDER_A, FLAG_ORDER_B = 1, 2, 4
+FLAG_DENSE_TILES, FLAG_NO_DENSE_TILES = 8, 16
 KINDS = {
     "kronecker": 0,
     "gaussian": 0,
@@ -60,6 +61,9 @@ def load_library():
     lib.gvt_dense_matvec.argtypes = [I, P, I64, I64, I64, P, I64, I64, I64, P, I64, P, I64, P]
     lib.gvt_dense_matvec_noalloc.argtypes = [I, P, I64, I64, I64, P, I64, I64, I64, P, I64, P, I64, P]
     lib.gvt_base_kernel.argtypes = [I, I, P, I64, I64, P, I64, I64, I64, ctypes.c_double, P, I64, P]
+    lib.gvt_erm_objective.argtypes = [I, I, P, I64, I64, P, I64, I64, P, P, I64, P, P, ctypes.c_double, P, P, P]
+    lib.gvt_erm_newton.argtypes = [I, I, P, I64, I64, P, I64, I64, P, P, I64, P, ctypes.c_double, P, I, I,
+                                   ctypes.c_double, I, P, P, P, P, P, P]
     lib.gvt_krr_minres.argtypes = [I, P, I64, I64, P, I64, I64, P, P, I64, P, P, I, P, I64, I, ctypes.c_double,
                                    I, P, I, P, P, P, P, P, P]
     lib.gvt_tanimoto_kernel.argtypes = [I, P, I64, I64, P, I64, I64, I64, P, I64, P]
@@ -70,9 +74,10 @@ def load_library():
     lib.gvt_krr_cg_batched.argtypes = [I, P, I, P, I, I, ctypes.c_double, I, I, P, P, P]
     lib.gvt_plan_profile.argtypes = [P, I, P, I64, P, I64, P, I64, I64, P, I64, I, P, P]
     lib.gvt_plan_info.argtypes = [P, P]
+    lib.gvt_plan_uses_tiles.argtypes = [P, I]
     lib.gvt_empty_cache.argtypes = [P]
-    for f in ("gvt_plan_profile", "gvt_plan_info", "gvt_plan_create", "gvt_plan_destroy", "gvt_plan_execute", "gvt_matvec",
-              "gvt_pairwise_matvec", "gvt_dense_matvec", "gvt_dense_matvec_noalloc", "gvt_dense_matvec_checked", "gvt_base_kernel", "gvt_tanimoto_kernel", "gvt_krr_minres", "gvt_krr_cg", "gvt_krr_cg_batched", "gvt_empty_cache"):
+    for f in ("gvt_plan_profile", "gvt_plan_info", "gvt_plan_uses_tiles", "gvt_plan_create", "gvt_plan_destroy", "gvt_plan_execute", "gvt_matvec",
+              "gvt_pairwise_matvec", "gvt_dense_matvec", "gvt_dense_matvec_noalloc", "gvt_dense_matvec_checked", "gvt_base_kernel", "gvt_tanimoto_kernel", "gvt_krr_minres", "gvt_erm_objective", "gvt_erm_newton", "gvt_krr_cg", "gvt_krr_cg_batched", "gvt_empty_cache"):
         getattr(lib, f).restype = I
     _lib = lib
     return lib
@@ -234,6 +239,11 @@ def gvt_plan_profile(plan: Plan, D, T, V, prec=None, reps=10, out=None):
     return ms
 
 
+def gvt_plan_uses_tiles(plan: Plan, prec) -> bool:
+    """Whether products of the plan in precision prec run as dense tiles."""
+    return bool(_check(load_library().gvt_plan_uses_tiles(plan.handle, int(prec))))
+
+
 def gvt_plan_info(plan: Plan):
     lib = load_library()
     info = np.zeros(11, dtype=np.float64)
@@ -354,6 +364,42 @@ def gvt_dense_matvec_noalloc(M, N, Vmat, prec=None, out=None):
                                         N.shape[1], _ld(N), _ptr(Vmat), _ld(Vmat), _ptr(U), _ld(U),
                                         _stream_handle()))
     return U
+
+
+LOSSES = {"squared": 0, "logistic": 1, "sqhinge": 2, "hinge": 3}
+
+
+def gvt_erm_objective(kind, loss, D, T, pairs, y, a, lam, grad=True):
+    """Regularized risk J(a) = L(K a, y) + (lam/2) a^T K a and its (sub)gradient K (g + lam a).
+    Returns (J, grad tensor or None)."""
+    torch = _torch()
+    lib = load_library()
+    c, e = _idx(pairs[0]), _idx(pairs[1])
+    Tm = T if T is not None else D
+    g = torch.empty_like(a) if grad else None
+    J = ctypes.c_double(0.0)
+    _check(lib.gvt_erm_objective(_kind_codes(kind)[0], LOSSES[loss], _ptr(D), D.shape[0], _ld(D), _ptr(Tm),
+                                 Tm.shape[0], _ld(Tm), _ptr(c), _ptr(e), c.numel(), _ptr(y), _ptr(a), float(lam),
+                                 _ptr(g), ctypes.byref(J), _stream_handle()))
+    return J.value, g
+
+
+def gvt_erm_newton(kind, loss, D, T, pairs, y, lam, max_newton=20, max_cg=50, tol=1e-8, matvec_prec=F64):
+    """Truncated Newton for the regularized risk from a = 0.  Returns a dict with a, steps,
+    cg_iters, J, gnorm, gnorm0 and status."""
+    torch = _torch()
+    lib = load_library()
+    c, e = _idx(pairs[0]), _idx(pairs[1])
+    Tm = T if T is not None else D
+    a = torch.empty(c.numel(), dtype=torch.float64, device=D.device)
+    st, cg = ctypes.c_int(0), ctypes.c_int(0)
+    J, gn, g0 = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    rc = _check(lib.gvt_erm_newton(_kind_codes(kind)[0], LOSSES[loss], _ptr(D), D.shape[0], _ld(D), _ptr(Tm),
+                                   Tm.shape[0], _ld(Tm), _ptr(c), _ptr(e), c.numel(), _ptr(y), float(lam), _ptr(a),
+                                   int(max_newton), int(max_cg), float(tol), int(matvec_prec), ctypes.byref(st),
+                                   ctypes.byref(cg), ctypes.byref(J), ctypes.byref(gn), ctypes.byref(g0),
+                                   _stream_handle()))
+    return dict(a=a, steps=st.value, cg_iters=cg.value, J=J.value, gnorm=gn.value, gnorm0=g0.value, status=rc)
 
 
 class _Validation(ctypes.Structure):

@@ -206,6 +206,13 @@ int krr_minres_impl(int kind, const double *D, int64_t d, int64_t ldd, const dou
                     int mprec, const gvt_validation *val, int check_every, int64_t *iters_out,
                     double *relres_out, int64_t *best_iter_out, double *best_auc_out, double *auc_hist,
                     hipStream_t s);
+int erm_objective_impl(int kind, int loss, const double *D, int64_t d, int64_t ldd, const double *T, int64_t t,
+                       int64_t ldt, const int32_t *c, const int32_t *e, int64_t n, const double *y,
+                       const double *a, double lambda, double *grad, double *obj_out, hipStream_t s);
+int erm_newton_impl(int kind, int loss, const double *D, int64_t d, int64_t ldd, const double *T, int64_t t,
+                    int64_t ldt, const int32_t *c, const int32_t *e, int64_t n, const double *y, double lambda,
+                    double *A, int max_newton, int max_cg, double tol, int mprec, int *steps_out,
+                    int *cg_out, double *obj_out, double *gnorm_out, double *gnorm0_out, hipStream_t s);
 int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const double *lambdas,
                         int nlam, int max_iter, double tol, int mprec, int check_every,
                         int64_t *iters_out, double *relres_out, hipStream_t s);
@@ -352,6 +359,13 @@ int gvt_dense_matvec(int prec, const void *M, int64_t m_rows, int64_t m_cols, in
   });
 }
 
+int gvt_plan_uses_tiles(gvt_plan_t plan, int prec) {
+  return guarded([&]() {
+    GVT_REQUIRE(plan, GVT_ERR_ARG, "null plan");
+    return plan_uses_tiles(plan, prec) ? 1 : 0;
+  });
+}
+
 int gvt_base_kernel(int kind, int prec, const void *X, int64_t nx, int64_t ldx, const void *Y,
                     int64_t ny, int64_t ldy, int64_t dim, double gamma, void *K, int64_t ldk,
                     void *stream) {
@@ -462,6 +476,28 @@ int gvt_krr_minres(int kind, const double *D, int64_t d, int64_t ldd, const doub
     return krr_minres_impl(kind, D, d, ldd, T, t, ldt, c, e, n, y, lambdas, nlam, A, lda, max_iter, tol,
                            matvec_prec, val, check_every, iters_out, relres_out, best_iter_out,
                            best_auc_out, auc_hist, (hipStream_t)stream);
+  });
+}
+
+int gvt_erm_objective(int kind, int loss, const double *D, int64_t d, int64_t ldd, const double *T,
+                      int64_t t, int64_t ldt, const int32_t *c, const int32_t *e, int64_t n,
+                      const double *y, const double *a, double lambda, double *grad, double *obj_out,
+                      void *stream) {
+  return guarded([&]() {
+    return erm_objective_impl(kind, loss, D, d, ldd, T, t, ldt, c, e, n, y, a, lambda, grad, obj_out,
+                              (hipStream_t)stream);
+  });
+}
+
+int gvt_erm_newton(int kind, int loss, const double *D, int64_t d, int64_t ldd, const double *T,
+                   int64_t t, int64_t ldt, const int32_t *c, const int32_t *e, int64_t n,
+                   const double *y, double lambda, double *A, int max_newton, int max_cg, double tol,
+                   int matvec_prec, int *steps_out, int *cg_iters_out, double *obj_out,
+                   double *gnorm_out, double *gnorm0_out, void *stream) {
+  return guarded([&]() {
+    return erm_newton_impl(kind, loss, D, d, ldd, T, t, ldt, c, e, n, y, lambda, A, max_newton, max_cg, tol,
+                           matvec_prec, steps_out, cg_iters_out, obj_out, gnorm_out, gnorm0_out,
+                           (hipStream_t)stream);
   });
 }
 

@@ -17,6 +17,7 @@
 // Tiling: 256 threads (2 x 2 waves), block tile 128 x 128, each wave owns a
 // 64 x 64 sub-tile (4 x 4 MFMA blocks of 16 x 16).  Global tiles are
 // prefetched into registers while the current LDS tile feeds the MFMAs.
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -34,7 +35,16 @@ template <class T, bool BT>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(const T *__restrict__ A, int64_t lda,
                                                         const T *__restrict__ B, int64_t ldb,
                                                         T *__restrict__ C, int64_t ldc, int64_t M,
-                                                        int64_t N, int64_t K) {
+                                                        int64_t N, int64_t K,
+    int64_t kchunk, int64_t cz) {
+  // split-K: block z sums k in [z kchunk, min(K, (z + 1) kchunk)) into C + z cz
+  {
+    const int64_t kz0 = (int64_t)blockIdx.z * kchunk;
+    A += kz0;
+    B += BT ? kz0 : kz0 * ldb;
+    K = K - kz0 < kchunk ? K - kz0 : kchunk;
+    C += (int64_t)blockIdx.z * cz;
+  }
   constexpr int BM = 128, BN = 128, BK = 16, PAD = 4;
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T As[BK][BM + PAD];
@@ -137,7 +147,16 @@ template <class T, bool BT>
 __global__ __launch_bounds__(256) void gemm_vec_kernel(const T *__restrict__ A, int64_t lda,
                                                        const T *__restrict__ B, int64_t ldb,
                                                        T *__restrict__ C, int64_t ldc, int64_t M,
-                                                       int64_t N, int64_t K) {
+                                                       int64_t N, int64_t K,
+    int64_t kchunk, int64_t cz) {
+  // split-K: block z sums k in [z kchunk, min(K, (z + 1) kchunk)) into C + z cz
+  {
+    const int64_t kz0 = (int64_t)blockIdx.z * kchunk;
+    A += kz0;
+    B += BT ? kz0 : kz0 * ldb;
+    K = K - kz0 < kchunk ? K - kz0 : kchunk;
+    C += (int64_t)blockIdx.z * cz;
+  }
   constexpr int VEC = 16 / sizeof(T);            // elements per 16-byte vector
   constexpr int BM = 128, BN = 128, BK = sizeof(T) == 4 ? 32 : 16;
   constexpr int AS = BK + VEC;                   // row stride: k step + 16 bytes
@@ -428,18 +447,51 @@ __global__ __launch_bounds__(256) void gemm_bf16p_kernel(
     }
 }
 
+// C = sum_z P[z] (fixed order), P[z] row-major M x N at z * M * N
+template <class T>
+__global__ void splitk_sum_kernel(const T *__restrict__ P, int splits, int64_t M, int64_t N, T *__restrict__ C,
+                                  int64_t ldc) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= M * N) return;
+  T acc = P[q];
+  for (int z = 1; z < splits; ++z) acc += P[(int64_t)z * M * N + q];
+  C[(q / N) * ldc + q % N] = acc;
+}
+
+// Number of k splits that brings a launch of M x N output tiles to about two
+// workgroups per CU (each split keeps at least 256 k's), and its workspace.
+static int gemm_splits(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ceil_div(M, 128) * ceil_div(N, 128);
+  if (tiles >= 256) return 1;
+  const int64_t want = ceil_div(512, tiles), most = K / 256;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(most, 16)));
+}
+static size_t gemm_splits_bytes(int64_t M, int64_t N, int64_t K, size_t es) {
+  const int sp = gemm_splits(M, N, K);
+  return sp > 1 ? (size_t)sp * M * N * es : 0;
+}
+
+// C[M x N] = A op(B); with too few output tiles for the chip the k range is
+// split over a third grid dimension into `part` (gemm_splits_bytes) and summed
+// in a fixed order.
 template <class T, bool BT>
 static void gemm(const T *A, int64_t lda, const T *B, int64_t ldb, T *C, int64_t ldc, int64_t M,
-                 int64_t N, int64_t K, hipStream_t s) {
-  dim3 grid((unsigned)ceil_div(N, 128), (unsigned)ceil_div(M, 128));
-  // 16-byte loads need aligned rows and whole vectors along k (and along n for B)
+                 int64_t N, int64_t K, T *part, hipStream_t s) {
   constexpr int64_t V = 16 / sizeof(T);
+  constexpr int64_t BKV = sizeof(T) == 4 ? 32 : 16;  // k step of the vector kernel
+  const int sp = part ? gemm_splits(M, N, K) : 1;
+  const int64_t kchunk = sp > 1 ? ceil_div(ceil_div(K, sp), BKV) * BKV : K;
+  const int nz = sp > 1 ? (int)ceil_div(K, kchunk) : 1;
+  dim3 grid((unsigned)ceil_div(N, 128), (unsigned)ceil_div(M, 128), (unsigned)nz);
+  T *Cout = nz > 1 ? part : C;
+  const int64_t ldo = nz > 1 ? N : ldc, cz = nz > 1 ? M * N : 0;
+  // 16-byte loads need aligned rows and whole vectors along k (and along n for B)
   auto al16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
-  if (al16(A) && al16(B) && lda % V == 0 && ldb % V == 0 && K % V == 0 && (BT || N % V == 0)) {
-    gemm_vec_kernel<T, BT><<<grid, 256, 0, s>>>(A, lda, B, ldb, C, ldc, M, N, K);
-    return;
-  }
-  gemm_mfma_kernel<T, BT><<<grid, 256, 0, s>>>(A, lda, B, ldb, C, ldc, M, N, K);
+  if (al16(A) && al16(B) && lda % V == 0 && ldb % V == 0 && K % V == 0 && (BT || N % V == 0))
+    gemm_vec_kernel<T, BT><<<grid, 256, 0, s>>>(A, lda, B, ldb, Cout, ldo, M, N, K, kchunk, cz);
+  else
+    gemm_mfma_kernel<T, BT><<<grid, 256, 0, s>>>(A, lda, B, ldb, Cout, ldo, M, N, K, kchunk, cz);
+  if (nz > 1) splitk_sum_kernel<T><<<(unsigned)ceil_div(M * N, 256), 256, 0, s>>>(part, nz, M, N, C, ldc);
 }
 
 // Piece layout of the split-bf16 product: M and N split by rows, Vmat
@@ -497,7 +549,10 @@ size_t dense_workspace_bytes(int prec, int64_t mr, int64_t mc, int64_t nr, int64
   if (mr == 0 || nr == 0) return 0;
   if (prec == GVT_BF16X3) return SplitLayout(2, mr, mc, nr, nc).bytes();
   if (prec == GVT_BF16X6) return SplitLayout(3, mr, mc, nr, nc).bytes();
-  return (size_t)mr * nc * (prec == GVT_F64 ? sizeof(double) : sizeof(float)) + 256;
+  const size_t es = prec == GVT_F64 ? sizeof(double) : sizeof(float);
+  const size_t w = ((size_t)mr * nc * es + 255) / 256 * 256;
+  const size_t sp = std::max(gemm_splits_bytes(mr, nc, mc, es), gemm_splits_bytes(mr, nr, nc, es));
+  return w + sp + 256;
 }
 
 // Umat (mr x nr) = M (mr x mc) Vmat (mc x nc) N^T (N: nr x nc)
@@ -516,12 +571,18 @@ void dense_matvec(int prec, const void *Mp, int64_t mr, int64_t mc, int64_t ldm,
   }
   void *W = ws;
   if (!W) GVT_HIP_CHECK(hipMallocAsync(&W, dense_workspace_bytes(prec, mr, mc, nr, nc), s));
+  const size_t es = prec == GVT_F64 ? sizeof(double) : sizeof(float);
+  void *part = static_cast<char *>(W) + ((size_t)mr * nc * es + 255) / 256 * 256;  // split-K partials
   if (prec == GVT_F64) {
-    gemm<double, false>((const double *)Mp, ldm, (const double *)Vp, ldv, (double *)W, nc, mr, nc, mc, s);
-    gemm<double, true>((const double *)W, nc, (const double *)Np, ldn, (double *)Up, ldu, mr, nr, nc, s);
+    gemm<double, false>((const double *)Mp, ldm, (const double *)Vp, ldv, (double *)W, nc, mr, nc, mc,
+                        (double *)part, s);
+    gemm<double, true>((const double *)W, nc, (const double *)Np, ldn, (double *)Up, ldu, mr, nr, nc,
+                       (double *)part, s);
   } else if (prec == GVT_F32) {
-    gemm<float, false>((const float *)Mp, ldm, (const float *)Vp, ldv, (float *)W, nc, mr, nc, mc, s);
-    gemm<float, true>((const float *)W, nc, (const float *)Np, ldn, (float *)Up, ldu, mr, nr, nc, s);
+    gemm<float, false>((const float *)Mp, ldm, (const float *)Vp, ldv, (float *)W, nc, mr, nc, mc,
+                       (float *)part, s);
+    gemm<float, true>((const float *)W, nc, (const float *)Np, ldn, (float *)Up, ldu, mr, nr, nc,
+                      (float *)part, s);
   }
   check_launch(s);
   if (!ws) GVT_HIP_CHECK(hipFreeAsync(W, s));

@@ -12,16 +12,16 @@
 //                      one thread per column j, the chunk of the NSAMP rows of
 //                      M staged in LDS as FP64, NSAMP accumulators per thread
 //   sample_fold_kernel P[i, j] = sum_c P_part[c][i, j]   (ascending c)
-//   sample_err_kernel  one wave per column t of Umat: the lanes split k,
-//                      Uref[i, t] = sum_k P[i, k] N[t, k], then per-block sums
-//                      of (U[r_i, t] - Uref[i, t])^2 and Uref[i, t]^2
+//   sample_err_kernel  two columns t of Umat per wave, the lanes split k over
+//                      panels of P staged in LDS: Uref[i, t] = sum_k P[i, k] N[t, k],
+//                      then per-block sums of (U[r_i, t] - Uref[i, t])^2 and Uref[i, t]^2
 //   sample_norm_kernel folds the block sums into two doubles
 #include "common.h"
 #include "kernels.h"
 
 namespace gvt {
 
-constexpr int kSampleRows = 32;  // rows of Umat sampled (fewer when Umat has fewer)
+constexpr int kSampleRows = 16;  // rows of Umat sampled (fewer when Umat has fewer)
 constexpr int kSampleKc = 64;    // k-chunk of M rows staged in LDS
 constexpr int kSampleThreads = 256;
 
@@ -75,31 +75,52 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Two output columns per wave, eight per block: each step stages a 32 x 64
+// panel of P in LDS once for the block; a lane takes one k of the panel.
+constexpr int kErrCols = 2 * (kSampleThreads / 64);
+
 template <class T>
 __global__ __launch_bounds__(kSampleThreads) void sample_err_kernel(
     const double *__restrict__ P, int ns, int64_t nc, const T *__restrict__ N, int64_t ldn,
     int64_t nr, const T *__restrict__ U, int64_t ldu, int64_t mr, double *__restrict__ blocksums) {
+  __shared__ double pp[kSampleRows][64];
   __shared__ double sh[2][kSampleThreads / 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t t = (int64_t)blockIdx.x * (kSampleThreads / 64) + w;
-  double e2 = 0.0, r2 = 0.0;
-  if (t < nr) {
-    double acc[kSampleRows];
+  const int64_t t0 = (int64_t)blockIdx.x * kErrCols + 2 * w;  // this wave's columns t0, t0 + 1
+  double acc[2][kSampleRows];
 #pragma unroll
-    for (int i = 0; i < kSampleRows; ++i) acc[i] = 0.0;
-    for (int64_t k = lane; k < nc; k += 64) {
-      const double nv = (double)N[t * ldn + k];
+  for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int i = 0; i < kSampleRows; ++i)
-        if (i < ns) acc[i] += P[(int64_t)i * nc + k] * nv;
+    for (int i = 0; i < kSampleRows; ++i) acc[c][i] = 0.0;
+  for (int64_t k0 = 0; k0 < nc; k0 += 64) {
+    for (int e = threadIdx.x; e < kSampleRows * 64; e += kSampleThreads) {
+      const int i = e >> 6, kk = e & 63;
+      pp[i][kk] = (i < ns && k0 + kk < nc) ? P[(int64_t)i * nc + k0 + kk] : 0.0;
     }
+    __syncthreads();
+    const int64_t k = k0 + lane;
+    const double n0 = (t0 < nr && k < nc) ? (double)N[t0 * ldn + k] : 0.0;
+    const double n1 = (t0 + 1 < nr && k < nc) ? (double)N[(t0 + 1) * ldn + k] : 0.0;
 #pragma unroll
     for (int i = 0; i < kSampleRows; ++i) {
-      if (i >= ns) break;
-      const double ref = wave_sum(acc[i]);
-      const double d = (double)U[sample_row(i, ns, mr) * ldu + t] - ref;
-      e2 += d * d;
-      r2 += ref * ref;
+      const double pv = pp[i][lane];
+      acc[0][i] += pv * n0;
+      acc[1][i] += pv * n1;
+    }
+    __syncthreads();
+  }
+  double e2 = 0.0, r2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int64_t t = t0 + c;
+#pragma unroll
+    for (int i = 0; i < kSampleRows; ++i) {
+      const double ref = wave_sum(acc[c][i]);  // every lane of the wave takes part
+      if (i < ns && t < nr) {
+        const double d = (double)U[sample_row(i, ns, mr) * ldu + t] - ref;
+        e2 += d * d;
+        r2 += ref * ref;
+      }
     }
   }
   if (lane == 0) {
@@ -140,7 +161,7 @@ static double sample_relerr_t(const T *M, int64_t mr, int64_t mc, int64_t ldm, c
   const int64_t nsplit = std::max<int64_t>(1, std::min<int64_t>(ceil_div(512, jb), ceil_div(mc, kSampleKc)));
   const int64_t kper = ceil_div(ceil_div(mc, nsplit), kSampleKc) * kSampleKc;
   const int64_t nsp = std::max<int64_t>(1, ceil_div(mc, kper));
-  const int64_t eb = ceil_div(nr, kSampleThreads / 64);
+  const int64_t eb = ceil_div(nr, kErrCols);
   const size_t bytes = (size_t)(nsp * ns * nc + ns * nc + 2 * eb + 2) * sizeof(double);
   DevMem buf;
   double *base = (double *)buf.ensure(bytes);

@@ -161,7 +161,7 @@ void base_kernel(int kind, int prec, const void *X, int64_t nx, int64_t ldx, con
                  int64_t ldy, int64_t dim, double gamma, void *K, int64_t ldk, hipStream_t s);
 void tanimoto_kernel_matrix(int prec, const uint64_t *X, int64_t nx, int64_t ldx, const uint64_t *Y,
                             int64_t ny, int64_t ldy, int64_t nbits, void *K, int64_t ldk, hipStream_t s);
-// ||U_S - U_S,ref||_F / ||U_S,ref||_F over up to 32 evenly spaced rows S of
+// ||U_S - U_S,ref||_F / ||U_S,ref||_F over up to 16 evenly spaced rows S of
 // Umat = M Vmat N^T, with U_S,ref recomputed in FP64 from the stored operands
 // (double for GVT_F64, float otherwise).  Synchronises s.
 double dense_sample_relerr(int prec, const void *M, int64_t mr, int64_t mc, int64_t ldm, const void *N,

@@ -15,8 +15,9 @@
 // of v_k, d_{k-1}, d_{k-2}), so the product K_val v_k of the Lanczos vector
 // with the validation rows updates every lambda's predictions: one more
 // single-RHS product per iteration.  The AUC against binary validation labels
-// counts, for every (positive, negative) pair, whether the prediction orders
-// it correctly (ties one half) in integers, so it is exact and reproducible.
+// counts the (positive, negative) pairs the predictions order correctly (ties
+// one half): the negatives' predictions are sorted and every positive counts
+// by binary search, in integers, so the AUC is exact and reproducible.
 // A system keeps its best AUC (strictly larger than every earlier one,
 // starting from a_0 = 0), copies a into the caller's output when the AUC
 // improves, and stops after `patience` iterations without improvement.
@@ -28,7 +29,7 @@
 //   mr_update  beta_{k+1} = ||q||; per system the Givens step with
 //              alpha_k + lambda; d_k, a_k; v_{k+1} = q / beta_{k+1}
 //   mr_val     the validation images of d_k and the predictions
-//   mr_auc     (positive, negative) pair counts per system and block
+//   mr_auc     sorted negatives; per positive, pair counts by binary search
 //   mr_state   AUC, best, patience, residual test, iteration count
 //   mr_best    a -> caller's output for systems whose AUC improved
 // Scalars are double-buffered by iteration parity: a kernel that computes new
@@ -37,6 +38,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+
+#include <hipcub/hipcub.hpp>
 
 #include "plan.h"
 
@@ -245,29 +248,44 @@ __global__ __launch_bounds__(MB) void mr_val_kernel(const TW *__restrict__ wv, i
   }
 }
 
-// Pair counts for the AUC: for every system, 2 x #(pos > neg) + #(pos == neg)
-// over (positive i, negative j) pairs, this block's positives against every
-// negative (negatives staged in LDS 1024 at a time).  Integer partials.
-constexpr int kAucChunk = 1024;
+// Pair counts for the AUC, for every system: 2 x #(pos > neg) + #(pos == neg)
+// over (positive, negative) pairs.  The negatives' predictions of each system
+// are gathered and sorted (one segment per system); each positive then counts
+// the negatives below it and the ties by two binary searches.  Integer counts,
+// exact whatever the order of anything.
+__global__ void mr_gather_neg_kernel(const double *__restrict__ pv, int64_t nv, int nlam,
+                                     const int32_t *__restrict__ neg, int64_t nneg, double *__restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nneg * nlam) return;
+  const int64_t l = q / nneg, j = q - l * nneg;
+  out[q] = pv[l * nv + neg[j]];
+}
+
 __global__ __launch_bounds__(MB) void mr_auc_kernel(const double *__restrict__ pv, int64_t nv, int nlam,
                                                     const int32_t *__restrict__ pos, int64_t npos,
-                                                    const int32_t *__restrict__ neg, int64_t nneg,
+                                                    const double *__restrict__ sneg, int64_t nneg,
                                                     const MrSys *so, unsigned long long *__restrict__ cnt) {
-  __shared__ double ns[kAucChunk];
   __shared__ unsigned long long shc[MB / 64];
   const int64_t ip = (int64_t)blockIdx.x * MB + threadIdx.x;
   for (int l = 0; l < nlam; ++l) {
     if (so[l].state != MR_ACTIVE) continue;  // uniform: only systems that stepped are counted
-    const double *p = pv + (int64_t)l * nv;
-    const double mine = ip < npos ? p[pos[ip]] : 0.0;
     unsigned long long c = 0;
-    for (int64_t j0 = 0; j0 < nneg; j0 += kAucChunk) {
-      const int m = (int)min((int64_t)kAucChunk, nneg - j0);
-      for (int t = threadIdx.x; t < m; t += MB) ns[t] = p[neg[j0 + t]];
-      __syncthreads();
-      if (ip < npos)
-        for (int t = 0; t < m; ++t) c += (mine > ns[t]) ? 2ull : (mine == ns[t] ? 1ull : 0ull);
-      __syncthreads();
+    if (ip < npos) {
+      const double x = pv[(int64_t)l * nv + pos[ip]];
+      const double *a = sneg + (int64_t)l * nneg;
+      int64_t lo = 0, hi = nneg;  // first element >= x
+      while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+      }
+      int64_t lo2 = lo, hi2 = nneg;  // first element > x
+      while (lo2 < hi2) {
+        const int64_t mid = lo2 + (hi2 - lo2) / 2;
+        if (a[mid] <= x) lo2 = mid + 1;
+        else hi2 = mid;
+      }
+      c = (unsigned long long)lo + (unsigned long long)lo2;  // 2 less + equal
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
@@ -463,6 +481,10 @@ int krr_minres_impl(int kind, const double *D, int64_t d, int64_t ldd, const dou
   double *wv = nullptr, *pd1 = nullptr, *pd2 = nullptr, *pvv = nullptr;
   int32_t *dpos = nullptr, *dneg = nullptr;
   unsigned long long *cnt = nullptr;
+  DevMem m_sort;
+  double *gneg = nullptr, *sneg = nullptr;
+  char *stemp = nullptr;
+  size_t sort_bytes = 0;
   const int64_t auc_blocks = std::max<int64_t>(1, ceil_div(npos, MB));
   if (have_val) {
     wv = (double *)m_wv.ensure(nv * 8);
@@ -477,6 +499,16 @@ int krr_minres_impl(int kind, const double *D, int64_t d, int64_t ldd, const dou
     if (npos) GVT_HIP_CHECK(hipMemcpyAsync(dpos, hpos.data(), npos * 4, hipMemcpyHostToDevice, s));
     if (nneg) GVT_HIP_CHECK(hipMemcpyAsync(dneg, hneg.data(), nneg * 4, hipMemcpyHostToDevice, s));
     cnt = (unsigned long long *)m_cnt.ensure((size_t)auc_blocks * nlam * 8);
+    // sorted negatives: gathered predictions, their sorted copy, sort temp
+    const int64_t nn2 = std::max<int64_t>(nneg * nlam, 1);
+    size_t tb = 0;
+    GVT_HIP_CHECK(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, (const double *)nullptr, (double *)nullptr,
+                                                    (int)std::max<int64_t>(nneg, 1), 0, 64, s));
+    sort_bytes = tb;
+    char *sb = (char *)m_sort.ensure((size_t)nn2 * 16 + 256 + tb);
+    gneg = (double *)sb;
+    sneg = gneg + nn2;
+    stemp = sb + (size_t)nn2 * 16 + 256;
   }
   double *hist_dev = nullptr;
   DevMem m_hist;
@@ -526,7 +558,16 @@ int krr_minres_impl(int kind, const double *D, int64_t d, int64_t ldd, const dou
         mr_val_kernel<float><<<MNB, MB, 0, s>>>(wv32, nv, nlam, so, sn, pd1, pd2, pvv);
       else
         mr_val_kernel<double><<<MNB, MB, 0, s>>>(wv, nv, nlam, so, sn, pd1, pd2, pvv);
-      mr_auc_kernel<<<(unsigned)auc_blocks, MB, 0, s>>>(pvv, nv, nlam, dpos, npos, dneg, nneg, so, cnt);
+      if (nneg > 0) {
+        mr_gather_neg_kernel<<<mg1(nneg * nlam), 256, 0, s>>>(pvv, nv, nlam, dneg, nneg, gneg);
+        // one device-wide sort per system (a segmented sort gives each segment one workgroup)
+        for (int l = 0; l < nlam; ++l) {
+          size_t tb = sort_bytes;
+          GVT_HIP_CHECK(hipcub::DeviceRadixSort::SortKeys(stemp, tb, gneg + (int64_t)l * nneg,
+                                                          sneg + (int64_t)l * nneg, (int)nneg, 0, 64, s));
+        }
+      }
+      mr_auc_kernel<<<(unsigned)auc_blocks, MB, 0, s>>>(pvv, nv, nlam, dpos, npos, sneg, nneg, so, cnt);
     }
     mr_state_kernel<<<1, 64, 0, s>>>(sn, so, nlam, cnt, (int)auc_blocks, npos, nneg, have_val ? 1 : 0,
                                      have_val ? (int)val->patience : 0, tol, ynorm, max_iter, hist_dev, run);

@@ -130,6 +130,14 @@ struct gvt_plan {
   hipStream_t last_stream = nullptr;
   // Theorem 1 cost of the chosen term program (FMA count per RHS), for reporting
   double cost_fma = 0.0;
+  // Dense tiles for dense-but-incomplete data: a plan of one Kronecker term may
+  // run its product as the complete-data contraction M Vmat N^T on matrix
+  // cores, with v scattered into a zero grid Vmat (duplicates summed in the
+  // sorted order) and the outputs gathered from Umat.  mode: 0 chosen per call
+  // by the cost model (tuning.h), 1 always, -1 never.
+  bool tiles_ok = false;
+  int tiles_mode = 0;
+  gvt::DevMem tiles_ws;  // Vmat, Umat and the dense product's workspace
   // optional stage timing: events recorded at stage-group boundaries
   hipEvent_t *prof = nullptr;  // [kStages][2] start/stop, or null
 };
@@ -162,6 +170,8 @@ inline int rhs_block(int64_t left, int max_rhs) {
 int stage2_block_rows(const gvt_plan *P, const TermSpec &t, int cls);
 void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,
                   const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu, hipStream_t s);
+// Whether a product in precision prec takes the dense-tile form (see tiles_ok).
+bool plan_uses_tiles(const gvt_plan *P, int prec);
 // Where a product with one block of R right-hand sides (R a block size the
 // plan runs whole: rhs_block(R, max_rhs) == R) reads its input in key order:
 // for each input sort k < the returned count, element (j, r) of the input

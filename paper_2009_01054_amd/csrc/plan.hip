@@ -11,6 +11,7 @@
 // scatters, segment sums, GEMVs and terms are shared across all kinds of the
 // plan.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -820,7 +821,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       }
     }
     tm.lap("input sorts + term orderings");
-    bool need_idx = false;
+    bool need_idx = nkinds == 1 && kinds[0] == GVT_KRONECKER;  // dense tiles gather by (a, b)
     for (const TermSpec &t : P->terms) need_idx = need_idx || t.type != TG;
     if (need_idx)
       for (int i = 0; i < 4; ++i) up.add(P->idx[i], h[i]);
@@ -829,6 +830,13 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   }
   P->direct = nkinds == 1 && P->outputs[0].size() == 1 && P->outputs[0][0].second == 1.0 &&
               P->terms[P->outputs[0][0].first].type == TG;
+  {
+    const TermSpec &t0 = P->terms[P->outputs[0][0].first];
+    P->tiles_ok = P->direct && kinds[0] == GVT_KRONECKER && n_in > 0 && n_out > 0 && t0.sbuf >= 0 &&
+                  !P->sbufs[t0.sbuf].degenerate;
+    P->tiles_mode = (flags & GVT_FLAG_DENSE_TILES) ? 1 : (flags & GVT_FLAG_NO_DENSE_TILES) ? -1 : 0;
+    if (const char *ev = std::getenv("GVT_DENSE_TILES")) P->tiles_mode = std::atoi(ev) != 0 ? 1 : -1;
+  }
   for (auto &o : P->outputs)
     GVT_REQUIRE(o.size() <= (size_t)kMaxCombineTerms, GVT_ERR_ARG, "too many terms");
   GVT_REQUIRE(P->terms.size() <= (size_t)kMaxCombineTerms, GVT_ERR_ARG,
@@ -1039,6 +1047,86 @@ void execute_t(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ldt, c
 
 }  // namespace
 
+// ---- dense tiles ---------------------------------------------------------------
+// Vmat[c, e] = sum of v_j over the pairs j = (c, e).  One thread per position
+// of the sorted input pairs (key segments, the other index ascending inside
+// each): a position that starts a run of equal (key, other) sums the run in
+// sorted order and stores it; the others store nothing.
+template <class T>
+__global__ void tiles_scatter_kernel(const int32_t *__restrict__ perm, const int32_t *__restrict__ other,
+                                     const int32_t *__restrict__ keyidx, int64_t n, const T *__restrict__ v,
+                                     int key_is_c, int64_t tcols, T *__restrict__ Vmat) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t o = other[p], k = keyidx[perm[p]];
+  if (p > 0 && other[p - 1] == o && keyidx[perm[p - 1]] == k) return;  // inside a run
+  T acc = v[perm[p]];
+  for (int64_t q = p + 1; q < n && other[q] == o && keyidx[perm[q]] == k; ++q) acc += v[perm[q]];
+  const int64_t c = key_is_c ? k : o, e = key_is_c ? o : k;
+  Vmat[c * tcols + e] = acc;
+}
+
+template <class T>
+__global__ void tiles_zero_kernel(T *__restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = T(0);
+}
+
+// u[i] = Umat[a_i, b_i]
+template <class T>
+__global__ void tiles_gather_kernel(const T *__restrict__ Umat, int64_t ldum, const int32_t *__restrict__ a,
+                                    const int32_t *__restrict__ b, int64_t n, T *__restrict__ u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) u[i] = Umat[(int64_t)a[i] * ldum + b[i]];
+}
+
+bool plan_uses_tiles(const gvt_plan *P, int prec) {
+  if (!P->tiles_ok || P->tiles_mode < 0) return false;
+  if (P->tiles_mode > 0 || prec == GVT_BF16X3 || prec == GVT_BF16X6) return true;
+  // time estimates per RHS: the gather path's Theorem 1 flops against the
+  // dense product's two GEMMs plus its extra traffic (Vmat written twice,
+  // Umat written and gathered).  A GEMM with few 128 x 128 output tiles
+  // leaves matrix cores idle: its rate scales with min(1, tiles / kTilesFull).
+  const double es = prec == GVT_F64 ? 8.0 : 4.0;
+  const double rate = prec == GVT_F64 ? kTilesRateF64 : kTilesRateF32;
+  auto gemm_s = [&](double m, double n, double k) {
+    const double tiles = std::ceil(m / 128.0) * std::ceil(n / 128.0);
+    return 2.0 * m * n * k / (rate * std::min(1.0, tiles / kTilesFull));
+  };
+  const double bytes = es * (2.0 * P->d_cols * P->t_cols + 2.0 * P->d_rows * P->t_rows + P->d_rows * P->t_cols);
+  const double t_dense = gemm_s((double)P->d_rows, (double)P->t_cols, (double)P->d_cols) +
+                         gemm_s((double)P->d_rows, (double)P->t_rows, (double)P->t_cols) + bytes / 4.0e12;
+  const double t_gather = 2.0 * P->cost_fma / (prec == GVT_F64 ? kGatherRateF64 : kGatherRateF32);
+  return t_dense < t_gather;
+}
+
+template <class T>
+static void execute_tiles(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *Tm, int64_t ldt,
+                          const T *V, int64_t nrhs, int64_t ldv, T *U, int64_t ldu, hipStream_t s) {
+  const TermSpec &t0 = P->terms[P->outputs[0][0].first];
+  const SBufSpec &sb = P->sbufs[t0.sbuf];
+  const int ks = sb.key == SC ? 0 : 1;
+  const InputSort &is = P->insort[ks];
+  GVT_REQUIRE(is.built, GVT_ERR_ARG, "internal: dense tiles without the input sort");
+  const int64_t nv = P->d_cols * P->t_cols, nu = P->d_rows * P->t_rows;
+  const size_t al = 256;
+  const size_t vb = ((size_t)nv * sizeof(T) + al - 1) / al * al, ub = ((size_t)nu * sizeof(T) + al - 1) / al * al;
+  const size_t wb = dense_workspace_bytes(prec, P->d_rows, P->d_cols, P->t_rows, P->t_cols);
+  char *base = static_cast<char *>(P->tiles_ws.ensure(vb + ub + wb));
+  T *Vmat = reinterpret_cast<T *>(base), *Umat = reinterpret_cast<T *>(base + vb);
+  void *wsd = base + vb + ub;
+  for (int64_t r = 0; r < nrhs; ++r) {
+    tiles_zero_kernel<T><<<(unsigned)std::min<int64_t>(ceil_div(nv, 256), 4096), 256, 0, s>>>(Vmat, nv);
+    tiles_scatter_kernel<T><<<(unsigned)ceil_div(P->n_in, 256), 256, 0, s>>>(
+        is.perm.as<int32_t>(), is.other.as<int32_t>(), P->idx[sb.key].as<int32_t>(), P->n_in, V + r * ldv,
+        sb.key == SC ? 1 : 0, P->t_cols, Vmat);
+    dense_matvec(prec, D, P->d_rows, P->d_cols, ldd, Tm, P->t_rows, P->t_cols, ldt, Vmat, P->t_cols, Umat,
+                 P->t_rows, wsd, s);
+    tiles_gather_kernel<T><<<(unsigned)ceil_div(P->n_out, 256), 256, 0, s>>>(
+        Umat, P->t_rows, P->idx[0].as<int32_t>(), P->idx[1].as<int32_t>(), P->n_out, U + r * ldu);
+  }
+}
+
 void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,
                   const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu, hipStream_t s) {
   GVT_REQUIRE(P, GVT_ERR_ARG, "null plan");
@@ -1064,8 +1152,16 @@ void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void 
     }
     return;
   }
+  if (plan_uses_tiles(P, prec)) {
+    if (prec == GVT_F64)
+      execute_tiles<double>(P, prec, D, ldd, T, ldt, (const double *)V, nrhs, ldv, (double *)U, ldu, s);
+    else
+      execute_tiles<float>(P, prec, D, ldd, T, ldt, (const float *)V, nrhs, ldv, (float *)U, ldu, s);
+    check_launch(s);
+    return;
+  }
   GVT_REQUIRE(prec == GVT_F64 || prec == GVT_F32, GVT_ERR_UNSUPPORTED,
-              "split-bf16 products are provided on the complete-data (matrix-core) path only");
+              "split-bf16 products are provided on the matrix-core paths only (complete data, dense tiles)");
   if (prec == GVT_F64)
     execute_t<double>(P, (const double *)D, ldd, (const double *)T, ldt, (const double *)V, nrhs,
                       ldv, (double *)U, ldu, s);

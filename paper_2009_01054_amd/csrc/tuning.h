@@ -37,4 +37,14 @@ constexpr int kStage1KeysPerWave = 1;
 constexpr int kStage1Wide = 1;
 constexpr int kMaxRhsBlockF64 = 2;
 constexpr int kMaxRhsBlockF32 = 4;
+// Dense-tile cost model (a plan of one Kronecker term): effective rates of the
+// gather path (Theorem 1 flops per second, ridge workload) and of the
+// matrix-core GEMMs of M Vmat N^T (complete-data workload, 8192 x 4096), and
+// the output-tile count at which a GEMM keeps the matrix cores busy (the
+// ridge workload's 2000 x 500 GEMMs, 64 tiles, ran at 1/6 of the full rate).
+constexpr double kGatherRateF64 = 9.3e12;
+constexpr double kGatherRateF32 = 11.6e12;
+constexpr double kTilesRateF64 = 56.0e12;
+constexpr double kTilesRateF32 = 118.0e12;
+constexpr double kTilesFull = 384.0;
 }  // namespace gvt
