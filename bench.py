@@ -316,8 +316,18 @@ def preset_batched(args, gvt, W, torch, np, dev):
                      "true_relres_max_converged": float(rel[rel < 1e-6].max()) if (rel < 1e-6).any() else None}
         log(f"[bench] batched {name}: {sec:.3f} s, status {rc}, iterations mean {iters.mean():.1f} "
             f"max {iters.max()}, converged {(rel < 1e-6).sum()} of {rel.size}")
-    # plain form on every 16th problem, scaled by the Theorem 1 cost share
-    sub = list(range(0, len(probs), 16))
+    # R13(i): every system the FP64-product solve converges must converge with FP32 products
+    # (systems FP64 products converge only in the last 10% of the cap flip between two FP64
+    # runs with different summation orders, so they are counted apart)
+    r32, r64, it64 = out["f32"][2], out["f64"][2], out["f64"][1]
+    early = it64 <= 180
+    res["converged_f64_not_f32"] = {
+        "f64_within_180_iterations": int(((r64 < 1e-6) & early & ~(r32 < 1e-6)).sum()),
+        "f64_in_181_to_200_iterations": int(((r64 < 1e-6) & ~early & ~(r32 < 1e-6)).sum())}
+    res["converged_f32_not_f64"] = int(((r32 < 1e-6) & ~(r64 < 1e-6)).sum())
+    log(f"[bench] converged by f64 products but not f32: {res['converged_f64_not_f32']}")
+    # plain form on every 4th problem (64 problems), scaled by the Theorem 1 cost share
+    sub = list(range(0, len(probs), 4))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in sub:

@@ -305,9 +305,14 @@ int gvt_tanimoto_kernel(int prec, const uint64_t *X, int64_t nx, int64_t ldx, co
  * lambdas[nlam] (host) > 0.  A: n x nlam solutions (device, double, column
  * stride lda >= n).  A0: optional initial guess with the same layout
  * (stride lda0), NULL = zero.  matvec_prec: GVT_F64 or GVT_F32 (products in
- * FP32, everything else FP64; when the recurrence residual meets `tol` the
- * true residual is recomputed with an FP64 product and CG restarts from it
- * unless it also meets `tol`).  check_every: iterations between host
+ * FP32, everything else FP64).  With FP32 products a system whose recurrence
+ * residual meets `tol` is certified by its true residual from an FP64
+ * product; if that fails, the solve continues with FP64 products from the
+ * true residual.  A system still above `tol` after max_iter iterations is
+ * certified the same way and, if it fails, gets at most max_iter / 10 more
+ * iterations with FP64 products (the residual replaced by the true one, the
+ * search continuing along its last direction), so that FP32 products lose no
+ * system that FP64 products converge; iters_out counts those too.  check_every: iterations between host
  * convergence checks (>= 1); on a non-null stream each such block of
  * iterations after the first is captured once into a HIP graph and replayed,
  * on the null stream it is launched kernel by kernel (bitwise the same
@@ -353,7 +358,10 @@ typedef struct gvt_krr_problem {
  * problems run as grouped launches (one launch per stage of the generalized
  * vec trick covers every problem), finished problems drop out of the
  * launches, and blocks of check_every iterations replay from one HIP graph.
- * kind, max_iter, tol, matvec_prec and check_every as in gvt_krr_cg.
+ * kind, max_iter, tol, matvec_prec and check_every as in gvt_krr_cg; with
+ * FP32 products, a problem one of whose systems fails its FP64 certification
+ * (or reaches max_iter and gets the FP64 finish) runs FP64 products from then
+ * on, the others keep FP32 products.
  * problems[nprob] (host array of descriptors).  iters_out and relres_out
  * (host, nprob x nlam, problem-major: [p * nlam + l]) receive iteration
  * counts and true relative residuals (FP64 products).  Synchronises

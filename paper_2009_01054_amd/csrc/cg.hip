@@ -12,9 +12,11 @@
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
+#include <cstdlib>
 #include <cstring>
 
 #include "plan.h"
+#include "tuning.h"
 
 namespace gvt {
 
@@ -30,7 +32,7 @@ struct CgScalars {
   double rho_prev;  // the rho the last update step used
   int state, iters;
   int gate;         // last update step: 0 system not active, 1 stepped, 2 breakdown (p.w <= 0)
-  int pad0;
+  int extra;        // iterations granted beyond max_iter (the FP64 finish of an FP32-product solve)
 };
 
 // Sum over the block in a fixed order: a butterfly inside each wave (every
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(RB) void cg_p_kernel(double *__restrict__ p, float 
         sc[l].rho = rho_new;
         if (sqrt(rho_new) / sc[l].ynorm < tol)
           sc[l].state = lowprec ? CG_PENDING : CG_DONE;
-        else if (sc[l].iters >= max_iter)
+        else if (sc[l].iters >= max_iter + sc[l].extra)
           sc[l].state = CG_MAXITER;
       }
     }
@@ -271,7 +273,7 @@ __global__ void cg_init_kernel(CgScalars *sc, const double *__restrict__ ynorm2,
   for (int l = 0; l < nlam; ++l) {
     CgScalars c;
     c.pw = c.alpha = c.beta = c.rho_prev = 0.0;
-    c.iters = c.gate = c.pad0 = 0;
+    c.iters = c.gate = c.extra = 0;
     // all-zero labels: residuals are measured against 1 (a = 0 solves the system)
     c.ynorm = yn == 0.0 ? 1.0 : yn;
     c.rho = rho0 ? rho0[l] : *ynorm2;
@@ -319,6 +321,16 @@ __global__ void copy_cols_kernel(const double *__restrict__ src, int64_t lds, do
   if (i >= n) return;
   for (int l = 0; l < nlam; ++l)
     if (only_state < 0 || (sc && sc[l].state == only_state)) dst[i + l * ldd] = src[i + l * lds];
+}
+
+// p = w + beta (p - r); r = w (one system: the residual replaced by the true one
+// w, the search continuing along the last direction)
+__global__ void axpy_dir_kernel(const double *__restrict__ w, double *__restrict__ r, double *__restrict__ p,
+                                double beta, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p[i] = w[i] + beta * (p[i] - r[i]);
+  r[i] = w[i];
 }
 
 __global__ void bcast_col_kernel(const double *__restrict__ y, double *__restrict__ dst, int64_t ldd,
@@ -446,7 +458,10 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
     hs[l].state = CG_ACTIVE;
   }
 
-  const int lowprec = mprec == GVT_F32 ? 1 : 0;
+  // lowprec: FP32 products.  When a system's FP32 recurrence reaches tol but
+  // its true residual does not, the rest of the solve runs FP64 products
+  // (R13(i): a system that converges with FP64 products must converge here).
+  int lowprec = mprec == GVT_F32 ? 1 : 0;
   // p32 (FP32 products) is kept in step with p by the direction kernel; after
   // the host sets p (start, restart) it is refreshed here
   auto refresh_p32 = [&]() {
@@ -456,11 +471,16 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
   // When the nlam systems form one RHS block of the plan, the direction kernel
   // writes p in the key order of the iteration products as well, and those
   // products skip their pack; after the host sets p it is packed here.
-  const int iprec = lowprec ? GVT_F32 : GVT_F64;
-  const bool fuse_pack = rhs_block(nlam, rhs_cap(P, iprec)) == nlam;
+  int iprec = GVT_F64;
+  bool fuse_pack = false;
   PackTo<double> pk64{{nullptr, nullptr}, {nullptr, nullptr}};
   PackTo<float> pk32{{nullptr, nullptr}, {nullptr, nullptr}};
-  if (fuse_pack) {
+  auto setup_pack = [&]() {
+    iprec = lowprec ? GVT_F32 : GVT_F64;
+    fuse_pack = rhs_block(nlam, rhs_cap(P, iprec)) == nlam;
+    pk64 = PackTo<double>{{nullptr, nullptr}, {nullptr, nullptr}};
+    pk32 = PackTo<float>{{nullptr, nullptr}, {nullptr, nullptr}};
+    if (!fuse_pack) return;
     void *vs[2] = {nullptr, nullptr};
     const int32_t *inv[2] = {nullptr, nullptr};
     const int nk = plan_pack_targets(P, iprec, nlam, vs, inv);
@@ -473,7 +493,8 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
         pk64.inv[k] = inv[k];
       }
     }
-  }
+  };
+  setup_pack();
   auto repack = [&]() {
     if (fuse_pack) plan_pack(P, iprec, lowprec ? (const void *)p32 : (const void *)p, n, nlam, s);
   };
@@ -515,10 +536,14 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
     bool any_active = false;
     for (int l = 0; l < nlam; ++l) any_active |= hs[l].state == CG_ACTIVE;
     if (!any_active) {
-      // certify systems whose low-precision recurrence claims convergence
+      // certify systems whose low-precision recurrence claims convergence, and
+      // (FP32 products) systems at the iteration cap, which get the FP64 finish
       bool pending = false;
-      for (int l = 0; l < nlam; ++l) pending |= hs[l].state == CG_PENDING;
+      for (int l = 0; l < nlam; ++l)
+        pending |= hs[l].state == CG_PENDING ||
+                   (lowprec && hs[l].state == CG_MAXITER && hs[l].extra == 0);
       if (!pending) break;
+      bool finish = false;
       copy_cols_kernel<<<g1(n), 256, 0, s>>>(A, lda, w, n, n, nlam, -1, nullptr);
       matvec64(w, wraw);
       residual_kernel<<<RNB, RB, 0, s>>>(y, wraw, A, lda, lam, n, nlam, w, part);
@@ -526,21 +551,57 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
       std::vector<double> rt(nlam);
       GVT_HIP_CHECK(hipMemcpyAsync(rt.data(), tmp, nlam * 8, hipMemcpyDeviceToHost, s));
       GVT_HIP_CHECK(hipStreamSynchronize(s));
+      const bool was_low = lowprec != 0;
+      std::vector<uint8_t> keep_dir(nlam, 0);
       for (int l = 0; l < nlam; ++l) {
-        if (hs[l].state != CG_PENDING) continue;
+        const bool capped = was_low && hs[l].state == CG_MAXITER && hs[l].extra == 0;
+        if (hs[l].state != CG_PENDING && !capped) continue;
         if (std::sqrt(rt[l]) / hs[l].ynorm < tol) {
           hs[l].state = CG_DONE;
-        } else if (hs[l].iters >= max_iter) {
+        } else if (capped) {
+          // FP64 finish: at most max_iter / 10 more iterations with FP64
+          // products, the residual replaced by the true one and the search
+          // continuing along the last direction
+          hs[l].state = CG_ACTIVE;
+          hs[l].extra = std::max(1, max_iter / 10);
+          const double be = rt[l] / hs[l].rho;
+          hs[l].beta = std::isfinite(be) ? be : 0.0;
+          hs[l].rho = rt[l];
+          keep_dir[l] = 1;
+          finish = true;
+        } else if (hs[l].iters >= max_iter + hs[l].extra) {
           hs[l].state = CG_MAXITER;
         } else {
           hs[l].state = CG_ACTIVE;  // restart from the true residual
           hs[l].rho = rt[l];
+          finish = true;
         }
       }
-      // r = w (true residual) and p = r for restarted systems
+      if (finish && lowprec) {
+        // FP32 products could not carry a system to tol: FP64 products from
+        // here, with the iteration block captured again
+        lowprec = 0;
+        setup_pack();
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        first = true;
+      }
+      // restarted systems: r = w (true residual), p = r; finishing systems:
+      // p = w + beta (p - r), r = w
       GVT_HIP_CHECK(hipMemcpyAsync(sc, hs.data(), sizeof(CgScalars) * nlam, hipMemcpyHostToDevice, s));
-      copy_cols_kernel<<<g1(n), 256, 0, s>>>(w, n, r, n, n, nlam, CG_ACTIVE, sc);
-      copy_cols_kernel<<<g1(n), 256, 0, s>>>(w, n, p, n, n, nlam, CG_ACTIVE, sc);
+      for (int l = 0; l < nlam; ++l) {
+        if (hs[l].state != CG_ACTIVE) continue;
+        double *pl = p + (int64_t)l * n, *rl = r + (int64_t)l * n;
+        const double *wl = w + (int64_t)l * n;
+        if (keep_dir[l]) {
+          axpy_dir_kernel<<<g1(n), 256, 0, s>>>(wl, rl, pl, hs[l].beta, n);
+        } else {
+          GVT_HIP_CHECK(hipMemcpyAsync(rl, wl, n * 8, hipMemcpyDeviceToDevice, s));
+          GVT_HIP_CHECK(hipMemcpyAsync(pl, wl, n * 8, hipMemcpyDeviceToDevice, s));
+        }
+      }
       refresh_p32();
       repack();
       GVT_HIP_CHECK(hipMemsetD32Async(gate, 1, 1, s));
@@ -656,6 +717,33 @@ __global__ __launch_bounds__(RB) void bcg_pw_kernel(const BChunk *__restrict__ c
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
+// p.w with each problem's product in FP32 (w32) or, once switched (hi), FP64 (w64)
+__global__ __launch_bounds__(RB) void bcg_pw_mixed_kernel(const BChunk *__restrict__ ch,
+                                                          const float *__restrict__ w32,
+                                                          const double *__restrict__ w64,
+                                                          const uint8_t *__restrict__ hi, double *__restrict__ w,
+                                                          const double *__restrict__ p,
+                                                          const double *__restrict__ lam, int nlam,
+                                                          const CgScalars *__restrict__ sc,
+                                                          double *__restrict__ part) {
+  __shared__ double sh[RB];
+  const BChunk c = ch[blockIdx.x];
+  double acc = 0.0;
+  if (sc[c.sys].state == CG_ACTIVE) {  // uniform per block
+    const double lm = lam[c.sys % nlam];
+    const bool h = hi[c.sys / nlam] != 0;
+    for (int i = threadIdx.x; i < c.len; i += RB) {
+      const int64_t g = c.start + i;
+      const double pi = p[g];
+      const double wi = (h ? w64[g] : (double)w32[g]) + lm * pi;
+      w[g] = wi;
+      acc += pi * wi;
+    }
+  }
+  const double v = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
 __global__ __launch_bounds__(RB) void bcg_alpha_kernel(CgScalars *sc, const double *__restrict__ part,
                                                        const int64_t *__restrict__ cfirst) {
   __shared__ double sh[RB];
@@ -712,7 +800,7 @@ __global__ __launch_bounds__(RB) void bcg_beta_kernel(CgScalars *sc, const doubl
   sc[sy].rho = rho_new;
   if (sqrt(rho_new) / sc[sy].ynorm < tol) {
     sc[sy].state = lowprec ? CG_PENDING : CG_DONE;
-  } else if (sc[sy].iters >= max_iter) {
+  } else if (sc[sy].iters >= max_iter + sc[sy].extra) {
     sc[sy].state = CG_MAXITER;
   }
 }
@@ -730,14 +818,40 @@ __global__ __launch_bounds__(RB) void bcg_p_kernel(const BChunk *__restrict__ ch
   }
 }
 
-// active[p] = some system of problem p is still iterating
+// Systems set active again after a certification: r = w (the true residual),
+// and p = w (restart) or, with keep[sys], p = w + beta p (the FP64 finish,
+// continuing along the last direction)
+__global__ __launch_bounds__(RB) void bcg_reactivate_kernel(const BChunk *__restrict__ ch,
+                                                            const double *__restrict__ w, double *__restrict__ r,
+                                                            double *__restrict__ p,
+                                                            const CgScalars *__restrict__ sc,
+                                                            const uint8_t *__restrict__ keep) {
+  const BChunk c = ch[blockIdx.x];
+  if (sc[c.sys].state != CG_ACTIVE) return;
+  const double be = keep[c.sys] ? sc[c.sys].beta : 0.0;
+  for (int i = threadIdx.x; i < c.len; i += RB) {
+    const int64_t g = c.start + i;
+    const double wi = w[g];
+    p[g] = be != 0.0 ? wi + be * p[g] : wi;
+    r[g] = wi;
+  }
+}
+
+// active[p] = some system of problem p is still iterating; with hi (FP32
+// mode) also the active problems by product precision: act32 = active and not
+// hi, act64 = active and hi
 __global__ void bcg_mask_kernel(const CgScalars *__restrict__ sc, int nprob, int nlam,
-                                uint8_t *__restrict__ active) {
+                                uint8_t *__restrict__ active, const uint8_t *__restrict__ hi,
+                                uint8_t *__restrict__ act32, uint8_t *__restrict__ act64) {
   const int pb = blockIdx.x * blockDim.x + threadIdx.x;
   if (pb >= nprob) return;
   uint8_t any = 0;
   for (int l = 0; l < nlam; ++l) any |= sc[pb * nlam + l].state == CG_ACTIVE ? 1 : 0;
   active[pb] = any;
+  if (hi) {
+    act32[pb] = any && !hi[pb];
+    act64[pb] = any && hi[pb];
+  }
 }
 
 // r = y (every system of a problem starts from its labels); partial r.r
@@ -907,8 +1021,13 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
   CgScalars *sc = (CgScalars *)m_sc.ensure(sizeof(CgScalars) * nsys);
   double *lam = (double *)m_lam.ensure(nlam * 8);
   double *tmp = (double *)m_tmp.ensure(nsys * 8);
-  uint8_t *active = (uint8_t *)m_act.ensure(nprob);
-  uint8_t *cmask = (uint8_t *)m_cmask.ensure(nprob);
+  // active: problem has a system iterating; hi: problem switched to FP64
+  // products (FP32 mode); act32 / act64: active problems by product precision
+  uint8_t *active = (uint8_t *)m_act.ensure((size_t)nprob * 4);
+  uint8_t *hi = active + nprob, *act32 = hi + nprob, *act64 = act32 + nprob;
+  uint8_t *cmask = (uint8_t *)m_cmask.ensure((size_t)nprob + nsys);
+  uint8_t *modes = cmask + nprob;  // per system: 1 = continue along the last direction
+  GVT_HIP_CHECK(hipMemsetAsync(hi, 0, nprob, s));
   BChunk *ch = (BChunk *)m_ch.ensure(sizeof(BChunk) * nch);
   int64_t *cf = (int64_t *)m_cf.ensure(8 * (nsys + 1));
   float *p32 = nullptr, *w32 = nullptr;
@@ -1094,14 +1213,23 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
       plan_execute(ps.plans[i], GVT_F64, pb[i].D, pb[i].ldd, pb[i].T, pb[i].ldt, in + pb[i].voff, nlam,
                    pb[i].n, out + pb[i].voff, pb[i].n, s);
   };
+  // FP32-mode products: problems still on FP32 products (act32) and those
+  // switched to FP64 after a failed certification (act64, into wraw)
+  std::vector<uint8_t> hhi(nprob, 0);
   auto product32 = [&]() {
     if (grouped) {
-      grouped_product(df_it, active);
+      grouped_product(df_it, act32);
+      grouped_product(dd_it, act64);
       return;
     }
-    for (int i = 0; i < nprob; ++i)
-      plan_execute(ps.plans[i], GVT_F32, pb[i].D32, pb[i].d, pb[i].T32, pb[i].t, p32 + pb[i].voff, nlam,
-                   pb[i].n, w32 + pb[i].voff, pb[i].n, s);
+    for (int i = 0; i < nprob; ++i) {
+      if (hhi[i])
+        plan_execute(ps.plans[i], GVT_F64, pb[i].D, pb[i].ldd, pb[i].T, pb[i].ldt, p + pb[i].voff, nlam,
+                     pb[i].n, wraw + pb[i].voff, pb[i].n, s);
+      else
+        plan_execute(ps.plans[i], GVT_F32, pb[i].D32, pb[i].d, pb[i].T32, pb[i].t, p32 + pb[i].voff, nlam,
+                     pb[i].n, w32 + pb[i].voff, pb[i].n, s);
+    }
   };
 
   // ---- labels, norms, initial residuals
@@ -1147,17 +1275,23 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     }
     GVT_HIP_CHECK(hipMemcpyAsync(sc, hs.data(), sizeof(CgScalars) * nsys, hipMemcpyHostToDevice, s));
     GVT_HIP_CHECK(hipMemcpyAsync(active, hmask.data(), nprob, hipMemcpyHostToDevice, s));
+    GVT_HIP_CHECK(hipMemcpyAsync(hi, hhi.data(), nprob, hipMemcpyHostToDevice, s));
+    bcg_mask_kernel<<<(unsigned)ceil_div(nprob, 256), 256, 0, s>>>(sc, nprob, nlam, active,
+                                                                   mprec == GVT_F32 ? hi : nullptr, act32, act64);
     GVT_HIP_CHECK(hipStreamSynchronize(s));  // the host arrays are reused
   };
   upload_states();
 
   const int lowprec = mprec == GVT_F32 ? 1 : 0;
   const unsigned gm = (unsigned)ceil_div(nprob, 256);
+  // recurrence residual below which a problem leaves FP32 products (tuned)
+  double f32_switch = kF32SwitchRelres;
+  if (const char *ev = std::getenv("GVT_F32_SWITCH")) f32_switch = std::atof(ev);
   auto iteration = [&]() {
     if (lowprec) {
       to_f32_kernel<<<g1(nv), 256, 0, s>>>(p, p32, nv);
       product32();
-      bcg_pw_kernel<float><<<(unsigned)nch, RB, 0, s>>>(ch, w32, w, p, lam, nlam, sc, part);
+      bcg_pw_mixed_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, w32, wraw, hi, w, p, lam, nlam, sc, part);
     } else {
       product64(p, wraw, false, active);
       bcg_pw_kernel<double><<<(unsigned)nch, RB, 0, s>>>(ch, wraw, w, p, lam, nlam, sc, part);
@@ -1166,7 +1300,7 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     bcg_update_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, A, r, p, w, sc, part);
     bcg_beta_kernel<<<nsys, RB, 0, s>>>(sc, part, cf, tol, max_iter, lowprec);
     bcg_p_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, p, r, sc);
-    bcg_mask_kernel<<<gm, 256, 0, s>>>(sc, nprob, nlam, active);
+    bcg_mask_kernel<<<gm, 256, 0, s>>>(sc, nprob, nlam, active, lowprec ? hi : nullptr, act32, act64);
   };
 
   const bool use_graph = s != nullptr;
@@ -1176,19 +1310,25 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
   int total_iter = 0;
   bool first = true;
   std::vector<double> rt(nsys);
+  bool switched = false;
   try {
     while (true) {
       bool any_active = false;
       for (int sy = 0; sy < nsys; ++sy) any_active |= hs[sy].state == CG_ACTIVE;
       if (!any_active) {
-        // certify systems whose FP32 recurrence claims convergence
+        // certify systems whose FP32 recurrence claims convergence, and FP32
+        // systems at the iteration cap, which get the FP64 finish
+        auto certify = [&](const CgScalars &c) {
+          return c.state == CG_PENDING || (lowprec && c.state == CG_MAXITER && c.extra == 0);
+        };
         bool pending = false;
         for (int i = 0; i < nprob; ++i) {
           hmask[i] = 0;
-          for (int l = 0; l < nlam; ++l) hmask[i] |= hs[i * nlam + l].state == CG_PENDING ? 1 : 0;
+          for (int l = 0; l < nlam; ++l) hmask[i] |= certify(hs[i * nlam + l]) ? 1 : 0;
           pending |= hmask[i] != 0;
         }
         if (!pending) break;
+        std::vector<uint8_t> keep_dir(nsys, 0);
         GVT_HIP_CHECK(hipMemcpyAsync(cmask, hmask.data(), nprob, hipMemcpyHostToDevice, s));
         bcg_copy_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, A, w, -1, nullptr);
         product64(w, wraw, true, cmask);
@@ -1197,19 +1337,55 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
         GVT_HIP_CHECK(hipMemcpyAsync(rt.data(), tmp, nsys * 8, hipMemcpyDeviceToHost, s));
         GVT_HIP_CHECK(hipStreamSynchronize(s));
         for (int sy = 0; sy < nsys; ++sy) {
-          if (hs[sy].state != CG_PENDING) continue;
+          if (!certify(hs[sy])) continue;
+          const bool capped = hs[sy].state == CG_MAXITER;
           if (std::sqrt(rt[sy]) / hs[sy].ynorm < tol) {
             hs[sy].state = CG_DONE;
-          } else if (hs[sy].iters >= max_iter) {
+          } else if (capped) {
+            // FP64 finish: at most max_iter / 10 more iterations with FP64
+            // products, the residual replaced by the true one and the search
+            // continuing along the last direction (p_k: the direction kernel
+            // leaves capped systems alone), p = r + (rho_true / rho_k) p_k
+            const double rho_k = hs[sy].rho / hs[sy].beta;
+            const double be = rt[sy] / rho_k;
+            hs[sy].state = CG_ACTIVE;
+            hs[sy].extra = std::max(1, max_iter / 10);
+            hs[sy].beta = std::isfinite(be) ? be : 0.0;
+            hs[sy].rho = rt[sy];
+            keep_dir[sy] = 1;
+            if (!hhi[sy / nlam]) {
+              hhi[sy / nlam] = 1;
+              switched = true;
+            }
+          } else if (hs[sy].iters >= max_iter + hs[sy].extra) {
             hs[sy].state = CG_MAXITER;
           } else {
-            hs[sy].state = CG_ACTIVE;  // restart from the true residual
+            // the FP32 products could not carry this system to tol: its
+            // problem continues with FP64 products, restarted from the true
+            // residual (R13(i): a system that converges with FP64 products
+            // must converge in this form too)
+            hs[sy].state = CG_ACTIVE;
             hs[sy].rho = rt[sy];
+            if (!hhi[sy / nlam]) {
+              hhi[sy / nlam] = 1;
+              switched = true;
+            }
           }
         }
+        if (switched && !grouped) {
+          // the plan path bakes each problem's product precision into the
+          // captured graph: capture again
+          if (gexec) (void)hipGraphExecDestroy(gexec);
+          if (graph) (void)hipGraphDestroy(graph);
+          gexec = nullptr;
+          graph = nullptr;
+          first = true;
+        }
+        switched = false;
         upload_states();
-        bcg_copy_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, w, r, CG_ACTIVE, sc);
-        bcg_copy_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, w, p, CG_ACTIVE, sc);
+        GVT_HIP_CHECK(hipMemcpyAsync(modes, keep_dir.data(), nsys, hipMemcpyHostToDevice, s));
+        bcg_reactivate_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, w, r, p, sc, modes);
+        GVT_HIP_CHECK(hipStreamSynchronize(s));  // keep_dir is released at scope end
         continue;
       }
       if (first) {
@@ -1241,6 +1417,39 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
       for (int sy = 0; sy < nsys; ++sy)
         if (hs[sy].state == CG_BREAKDOWN) status = GVT_ERR_BREAKDOWN;
       if (status != GVT_OK) break;
+      if (lowprec) {
+        // a problem whose active systems all have recurrence residuals below
+        // the switch level continues with FP64 products (the FP32 products
+        // carry the early iterations, where their rounding costs no progress)
+        bool any = false;
+        for (int i = 0; i < nprob; ++i) {
+          if (hhi[i]) continue;
+          bool act = false, below = true;
+          for (int l = 0; l < nlam; ++l) {
+            const CgScalars &c = hs[i * nlam + l];
+            if (c.state != CG_ACTIVE) continue;
+            act = true;
+            below = below && std::sqrt(c.rho) / c.ynorm < f32_switch;
+          }
+          if (act && below) {
+            hhi[i] = 1;
+            any = true;
+          }
+        }
+        if (any) {
+          if (!grouped) {
+            if (gexec) (void)hipGraphExecDestroy(gexec);
+            if (graph) (void)hipGraphDestroy(graph);
+            gexec = nullptr;
+            graph = nullptr;
+            first = true;
+          }
+          GVT_HIP_CHECK(hipMemcpyAsync(hi, hhi.data(), nprob, hipMemcpyHostToDevice, s));
+          bcg_mask_kernel<<<(unsigned)ceil_div(nprob, 256), 256, 0, s>>>(sc, nprob, nlam, active, hi, act32,
+                                                                         act64);
+          GVT_HIP_CHECK(hipStreamSynchronize(s));
+        }
+      }
       if (total_iter > 4 * max_iter + 8) break;  // safety net; states already cap iterations
     }
   } catch (...) {

@@ -172,8 +172,14 @@ def test_batched_full_size_problem_sample(gvt):
     lams = list(W.LAMBDA_GRID)
     A, iters, rel, rc = gvt.gvt_krr_cg_batched("kronecker", dp, lams, max_iter=200, tol=1e-6,
                                                matvec_prec=gvt.F32)
-    assert rc in (0, 1)
-    assert ((rel < 1e-6) | (iters == 200)).all()
+    A64, it64, rel64, rc64 = gvt.gvt_krr_cg_batched("kronecker", dp, lams, max_iter=200, tol=1e-6,
+                                                    matvec_prec=gvt.F64)
+    assert rc in (0, 1) and rc64 in (0, 1)
+    # R13(i): every system the FP64-product solve converges within 90% of the cap converges
+    # with FP32 products (in the last 10% even two FP64 runs disagree); the others either
+    # converge or used the whole budget (the cap plus the FP64 finish)
+    assert (rel[(rel64 < 1e-6) & (it64 <= 180)] < 1e-6).all()
+    assert ((rel < 1e-6) | (iters >= 200)).all()
     q = probs[0]
     A_or, it_or, _, rt_or = oracle.krr_cg("kronecker", q["D"], q["T"], (q["c"], q["e"]), q["y"], lams,
                                           max_iter=200, tol=1e-6)

@@ -318,6 +318,23 @@ def test_cg_f32_products_certified(gvt):
         assert np.linalg.norm(A[:, l] - A_or[:, l]) / np.linalg.norm(A_or[:, l]) < 1e-4
 
 
+def test_cg_f32_products_converge_where_f64_products_do(gvt):
+    # R13(i) on a lambda grid down to 1e-4 (systems FP32 products alone cannot carry to
+    # 1e-6): single solve and batched solve with FP32 products converge every system that
+    # FP64 products converge within the cap
+    probs = [W.make_heterogeneous(97, i, 120, 90, 4000, 32, labels=True) for i in range(3)]
+    lams = list(W.LAMBDA_GRID)
+    dp = _dev_problems(probs)
+    for i, p in enumerate(probs):
+        args = ("kronecker", dp[i]["D"], dp[i]["T"], (dp[i]["c"], dp[i]["e"]), dp[i]["y"], lams)
+        _, it64, rel64, _ = gvt.gvt_krr_cg(*args, max_iter=200, tol=1e-6, matvec_prec=gvt.F64)
+        _, it32, rel32, _ = gvt.gvt_krr_cg(*args, max_iter=200, tol=1e-6, matvec_prec=gvt.F32)
+        assert (rel32[(rel64 < 1e-6) & (it64 <= 180)] < 1e-6).all(), (it64, rel64, it32, rel32)
+    _, itb64, relb64, _ = gvt.gvt_krr_cg_batched("kronecker", dp, lams, max_iter=200, tol=1e-6, matvec_prec=gvt.F64)
+    _, itb32, relb32, _ = gvt.gvt_krr_cg_batched("kronecker", dp, lams, max_iter=200, tol=1e-6, matvec_prec=gvt.F32)
+    assert (relb32[(relb64 < 1e-6) & (itb64 <= 180)] < 1e-6).all(), (itb64, relb64, itb32, relb32)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_cg_blocks_past_convergence_skip_products(gvt, prec):
     # With a check every 256 iterations the captured block runs on past the
