@@ -14,10 +14,13 @@
 //   BF16X6 the same with a three-way split x = hi + mid + lo and the six
 //          products down to the FP32 rounding level.
 //
-// Tiling: 256 threads (2 x 2 waves), block tile 128 x 128, each wave owns a
-// 64 x 64 sub-tile (4 x 4 MFMA blocks of 16 x 16).  Global tiles are
-// prefetched into registers while the current LDS tile feeds the MFMAs.
+// FP64/FP32 tiling: 256 threads (2 x 2 waves), block tile 128 x 128, each wave
+// owns a 64 x 64 sub-tile (4 x 4 MFMA blocks of 16 x 16), global tiles
+// prefetched into registers while the current LDS tile feeds the MFMAs.  The
+// bf16x3 product has its own kernel (256 x 128 tiles, operands copied straight
+// into a three-stage LDS ring); bf16x6 keeps the 128 x 128 split kernel.
 #include <algorithm>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 
@@ -29,6 +32,7 @@ namespace gvt {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // C[M x N] = A[M x K] * op(B),  op(B)[k][n] = BT ? B[n*ldb + k] : B[k*ldb + n]
 template <class T, bool BT>
@@ -280,8 +284,19 @@ __device__ __forceinline__ void split_bf16(float x, unsigned short (&s)[NS]) {
 }
 
 // ---- operand splitting (one bandwidth-bound pass per operand) ---------------
-// P[k*ps + r*cols_pad + c] = piece k of X[r][c] for c < cols, 0 for
-// cols <= c < cols_pad.  Four columns per thread.
+// Where piece k of element (r, c) of a split operand with cols_pad columns
+// (a multiple of 32) is stored.  Three pieces: one plane per piece,
+// k*ps + r*cols_pad + c.  Two pieces: the planes interleaved per 32-column
+// block, r*2*cols_pad + (c/32)*64 + 32k + c%32, so that the hi and lo halves
+// of a 32-wide k step of a row are one contiguous 128-byte line.
+template <int NS>
+__device__ __forceinline__ int64_t piece_at(int k, int64_t r, int64_t c, int64_t cols_pad, int64_t ps) {
+  if (NS == 2) return r * 2 * cols_pad + (c >> 5) * 64 + 32 * k + (c & 31);
+  return k * ps + r * cols_pad + c;
+}
+
+// Piece k of X[r][c] for c < cols, 0 for cols <= c < cols_pad, at
+// piece_at(k, r, c).  Four columns per thread.
 template <int NS>
 __global__ void split_rows_kernel(const float *__restrict__ X, int64_t ldx, int64_t rows,
                                   int64_t cols, int64_t cols_pad, unsigned short *__restrict__ P,
@@ -297,12 +312,13 @@ __global__ void split_rows_kernel(const float *__restrict__ X, int64_t ldx, int6
   for (int k = 0; k < NS; ++k) {
     typedef unsigned short us4 __attribute__((ext_vector_type(4)));
     us4 v = {sp[0][k], sp[1][k], sp[2][k], sp[3][k]};
-    *reinterpret_cast<us4 *>(P + k * ps + r * cols_pad + c0) = v;
+    *reinterpret_cast<us4 *>(P + piece_at<NS>(k, r, c0, cols_pad, ps)) = v;
   }
 }
 
-// P[k*ps + c*rows_pad + r] = piece k of X[r][c] (X: rows x cols), 0 for
-// rows <= r < rows_pad: the transposed split, through 32 x 32 LDS tiles.
+// Piece k of X[r][c] (X: rows x cols) at piece_at(k, c, r) with rows_pad
+// columns, 0 for rows <= r < rows_pad: the transposed split, through 32 x 32
+// LDS tiles.
 template <int NS>
 __global__ __launch_bounds__(256) void split_transpose_kernel(const float *__restrict__ X, int64_t ldx,
                                                               int64_t rows, int64_t cols,
@@ -323,21 +339,21 @@ __global__ __launch_bounds__(256) void split_transpose_kernel(const float *__res
       unsigned short sp[NS];
       split_bf16<NS>(tile[tx][j], sp);
 #pragma unroll
-      for (int k = 0; k < NS; ++k) P[k * ps + c * rows_pad + r] = sp[k];
+      for (int k = 0; k < NS; ++k) P[piece_at<NS>(k, c, r, rows_pad, ps)] = sp[k];
     }
   }
 }
 
 // Split-operand GEMM on bf16 MFMA with FP32 accumulation, on operands split
-// beforehand: C[M x N] = sum of the kept piece products of A (M x Kp) and
-// B (N x Kp), both row-major along k with Kp a multiple of 32 (zero-padded).
-// NS = 2 keeps hi*hi + hi*lo + lo*hi (bf16x3); NS = 3 keeps every product
-// whose order is at most the FP32 rounding level: hh + hm + mh + hl + lh + mm
-// (bf16x6).  SPLIT_OUT writes C as NS split pieces (row stride ldcs, piece
-// stride cps, columns up to ncols_pad, the padding being exact zeros) for a
-// following GEMM; otherwise C is FP32.  Each thread prefetches the next k
-// step of every piece with 16-byte loads while the MFMAs consume the LDS
-// tile.
+// beforehand into three planes (piece_at<3>): C[M x N] = sum of the kept
+// piece products of A (M x Kp) and B (N x Kp), both row-major along k with Kp
+// a multiple of 32 (zero-padded).  NS = 3 keeps every product whose order is
+// at most the FP32 rounding level: hh + hm + mh + hl + lh + mm (bf16x6).
+// SPLIT_OUT writes C as NS split pieces (row stride ldcs, piece stride cps,
+// columns up to ncols_pad, the padding being exact zeros) for a following
+// GEMM; otherwise C is FP32.  Block tile 128 x 128, each wave 64 x 64; each
+// thread prefetches the next k step of every piece with 16-byte loads while
+// the MFMAs consume the LDS tile.
 template <int NS, bool SPLIT_OUT, int BK>
 __global__ __launch_bounds__(256) void gemm_bf16p_kernel(
     const unsigned short *__restrict__ A, int64_t lda, int64_t aps,
@@ -447,6 +463,189 @@ __global__ __launch_bounds__(256) void gemm_bf16p_kernel(
     }
 }
 
+// ---- bf16x3 product: large tiles, operands copied straight into LDS --------
+// C = Ahi Bhi^T + Ahi Blo^T + Alo Bhi^T on two-piece operands (piece_at<2>,
+// Kp a multiple of 32, so a row's k step is one 128-byte line: hi then lo).
+// 256 threads (2 x 2 waves), block tile 256 x 128, each wave 128 x 64
+// (8 x 4 MFMA blocks of 16 x 16).  The hi*hi products and the two correction
+// products go to separate accumulators, updated by MFMAs only (so they stay in
+// the accumulation registers) and added once at the end: the corrections are
+// summed at their own scale instead of rounding into the large running sum
+// three times per k step.
+//
+// Operand tiles go from global memory straight to LDS (global_load_lds_dwordx4:
+// lane l of a wave writes its 16 bytes at the wave's LDS base + 16 l) through
+// three LDS stages: the copy of k step kk + 2 is issued before the MFMAs of
+// step kk.  One copy instruction moves 8 rows x 128 bytes; lane l takes row
+// l / 8 and the 16-byte chunk that the XOR permutation (row bits 0-3) puts at
+// position l % 8, which spreads the 16 rows of a fragment read over distinct
+// banks.  Each wave waits for its own copies (vmcnt) before the barrier that
+// ends a step; the barrier is a bare s_barrier, since a __syncthreads fence
+// would also wait for the copies still in flight.  A and B share one LDS
+// array: with two, the compiler makes every fragment read wait for all copies.
+//
+// Workgroups go to the 8 XCDs round-robin by id; ids are remapped so that each
+// XCD runs a contiguous run of tiles, taken in groups of 4 tile rows, which
+// share operand panels in that XCD's L2.
+
+// s_waitcnt with only the vector-memory count limited (gfx9 encoding: vmcnt in
+// bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima), and
+// with only the LDS/scalar count at zero
+#define GVT_WAIT_VMCNT(n) __builtin_amdgcn_s_waitcnt(((n) & 15) | (((n) >> 4) << 14) | (7 << 4) | (15 << 8))
+#define GVT_WAIT_LGKMCNT0() __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4))
+
+__device__ __forceinline__ int bf16x3_swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+
+template <bool SPLIT_OUT>
+__global__ __launch_bounds__(256, 1) void gemm_bf16x3_kernel(
+    const unsigned short *__restrict__ A, const unsigned short *__restrict__ B, float *__restrict__ C,
+    int64_t ldc, unsigned short *__restrict__ Cs, int64_t ncols_pad, int64_t M, int64_t N, int64_t Kp,
+    int tiles_m, int tiles_n) {
+  constexpr int WTM = 8, WTN = 4, BM = 256, BN = 128, NST = 3;
+  constexpr int CPA = BM / 32, CPB = BN / 32;  // copy instructions per wave and stage (8 rows each)
+  constexpr int NCOPY = CPA + CPB;
+  __shared__ u32x4 Ls[NST][BM + BN][8];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wm = wid >> 1, wn = wid & 1;
+  const int64_t ld = 2 * Kp;  // row stride of both operands
+
+  int t = blockIdx.x;
+  const int total = tiles_m * tiles_n;
+  if ((total & 7) == 0) t = (t & 7) * (total >> 3) + (t >> 3);
+  constexpr int GM = 4;
+  const int grp = t / (GM * tiles_n), first = grp * GM, gs = min(tiles_m - first, GM);
+  const int tin = t - grp * GM * tiles_n;
+  const int64_t m0 = (int64_t)(first + tin % gs) * BM, n0 = (int64_t)(tin / gs) * BN;
+
+  // copy q of this wave fills LDS rows wid*(BM/4) + 8q + lane/8 (A) or
+  // BM + wid*(BN/4) + 8q + lane/8 (B); rows past M (N) read row 0 instead
+  // (they only reach rows and columns of the tile that are not stored, and
+  // padding columns of a split output are written as zeros)
+  const int crow = lane >> 3;
+  const unsigned short *ap[CPA], *bp[CPB];
+#pragma unroll
+  for (int q = 0; q < CPA; ++q) {
+    const int64_t r = m0 + wid * (BM / 4) + 8 * q + crow;
+    const int ch = (lane & 7) ^ bf16x3_swz(8 * (q & 1) + crow);
+    ap[q] = A + (r < M ? r * ld : 0) + 8 * ch;
+  }
+#pragma unroll
+  for (int q = 0; q < CPB; ++q) {
+    const int64_t r = n0 + wid * (BN / 4) + 8 * q + crow;
+    const int ch = (lane & 7) ^ bf16x3_swz(8 * (q & 1) + crow);
+    bp[q] = B + (r < N ? r * ld : 0) + 8 * ch;
+  }
+#define GVT_BF16X3_COPY(st, kk)                                                                   \
+  _Pragma("unroll") for (int q = 0; q < CPA; ++q) __builtin_amdgcn_global_load_lds(              \
+      (const void *)(ap[q] + 64 * (kk)),                                                          \
+      (__attribute__((address_space(3))) void *)&Ls[st][wid * (BM / 4) + 8 * q][0], 16, 0, 0);    \
+  _Pragma("unroll") for (int q = 0; q < CPB; ++q) __builtin_amdgcn_global_load_lds(              \
+      (const void *)(bp[q] + 64 * (kk)),                                                          \
+      (__attribute__((address_space(3))) void *)&Ls[st][BM + wid * (BN / 4) + 8 * q][0], 16, 0, 0);
+
+  f4 acc[WTM][WTN], cor[WTM][WTN];
+#pragma unroll
+  for (int i = 0; i < WTM; ++i)
+#pragma unroll
+    for (int j = 0; j < WTN; ++j) {
+      acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      cor[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  // fragment reads: lane -> row lane % 16 of a 16-row block, chunk lane / 16
+  // of the piece (chunks 0-3 hi, 4-7 lo)
+  const int fr = lane & 15;
+  const int fh = (lane >> 4) ^ bf16x3_swz(fr), fl = (4 + (lane >> 4)) ^ bf16x3_swz(fr);
+  const int ar0 = wm * 16 * WTM + fr, br0 = BM + wn * 16 * WTN + fr;
+  const int64_t nk = Kp / 32;
+  if (nk > 0) {
+    GVT_BF16X3_COPY(0, 0)
+  }
+  if (nk > 1) {
+    GVT_BF16X3_COPY(1, 1)
+    GVT_WAIT_VMCNT(NCOPY);
+  } else {
+    GVT_WAIT_VMCNT(0);
+  }
+  __builtin_amdgcn_s_barrier();
+  int st = 0;
+  for (int64_t kk = 0; kk < nk; ++kk) {
+    const bool ahead = kk + 2 < nk;
+    if (ahead) {
+      const int s2 = st == 0 ? 2 : st - 1;  // (kk + 2) mod 3
+      GVT_BF16X3_COPY(s2, kk + 2)
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // all of B, then A one 16-row block ahead of its MFMAs (the scheduling
+    // barriers keep each block's reads in front of the previous block's
+    // MFMAs, so the waits overlap with MFMA execution)
+    bf8 bh[WTN], bl[WTN];
+#pragma unroll
+    for (int j = 0; j < WTN; ++j) {
+      bh[j] = __builtin_bit_cast(bf8, Ls[st][br0 + 16 * j][fh]);
+      bl[j] = __builtin_bit_cast(bf8, Ls[st][br0 + 16 * j][fl]);
+    }
+    bf8 ah = __builtin_bit_cast(bf8, Ls[st][ar0][fh]);
+    bf8 al = __builtin_bit_cast(bf8, Ls[st][ar0][fl]);
+#pragma unroll
+    for (int i = 0; i < WTM; ++i) {
+      bf8 ahn = ah, aln = al;
+      if (i + 1 < WTM) {
+        ahn = __builtin_bit_cast(bf8, Ls[st][ar0 + 16 * (i + 1)][fh]);
+        aln = __builtin_bit_cast(bf8, Ls[st][ar0 + 16 * (i + 1)][fl]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < WTN; ++j)
+        cor[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[j], cor[i][j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < WTN; ++j)
+        cor[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[j], cor[i][j], 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < WTN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      ah = ahn;
+      al = aln;
+    }
+    // this wave's copies of step kk + 1 have landed (those of kk + 2 may
+    // still be in flight) and its reads of step kk are done; then the barrier
+    if (ahead) {
+      GVT_WAIT_VMCNT(NCOPY);
+    } else {
+      GVT_WAIT_VMCNT(0);
+    }
+    GVT_WAIT_LGKMCNT0();
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    st = st == 2 ? 0 : st + 1;
+  }
+#pragma unroll
+  for (int i = 0; i < WTM; ++i)
+#pragma unroll
+    for (int j = 0; j < WTN; ++j) {
+      const int64_t col = n0 + wn * 16 * WTN + j * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = m0 + wm * 16 * WTM + i * 16 + 4 * (lane >> 4) + v;
+        const float x = col >= N ? 0.f : acc[i][j][v] + cor[i][j][v];
+        if (SPLIT_OUT) {
+          if (row < M && col < ncols_pad) {
+            unsigned short sp[2];
+            split_bf16<2>(x, sp);
+            Cs[piece_at<2>(0, row, col, ncols_pad, 0)] = sp[0];
+            Cs[piece_at<2>(1, row, col, ncols_pad, 0)] = sp[1];
+          }
+        } else if (row < M && col < N) {
+          C[row * ldc + col] = x;
+        }
+      }
+    }
+}
+#undef GVT_BF16X3_COPY
+#undef GVT_WAIT_VMCNT
+#undef GVT_WAIT_LGKMCNT0
+
 // C = sum_z P[z] (fixed order), P[z] row-major M x N at z * M * N
 template <class T>
 __global__ void splitk_sum_kernel(const T *__restrict__ P, int splits, int64_t M, int64_t N, T *__restrict__ C,
@@ -503,7 +702,7 @@ struct SplitLayout {
   int64_t k1, k2, pm, pv, pw, pn, om, ov, ow, on, total;
   static int64_t al(int64_t e) { return (e * 2 + 255) / 256 * 128; }
   SplitLayout(int NS, int64_t mr, int64_t mc, int64_t nr, int64_t nc) {
-    const int KQ = NS == 2 ? 64 : 32;  // k padding: whole k steps of the GEMM
+    const int KQ = 32;  // k padding: whole k steps of the GEMMs
     k1 = ceil_div(mc, KQ) * KQ;
     k2 = ceil_div(nc, KQ) * KQ;
     pm = mr * k1; pv = nc * k1; pw = mr * k2; pn = nr * k2;
@@ -512,6 +711,18 @@ struct SplitLayout {
   }
   size_t bytes() const { return (size_t)total * 2 + 256; }
 };
+
+// One bf16x3 product: C (M x N) from two-piece operands with Kp k's.
+template <bool SPLIT_OUT>
+static void launch_bf16x3(const unsigned short *A, const unsigned short *B, float *C, int64_t ldc,
+                          unsigned short *Cs, int64_t ncols_pad, int64_t M, int64_t N, int64_t Kp,
+                          hipStream_t s) {
+  const int64_t tm = ceil_div(M, 256), tn = ceil_div(N, 128);
+  if (tm == 0 || tn == 0) return;
+  GVT_REQUIRE(tm * tn < (int64_t)1 << 31, GVT_ERR_ARG, "dense product too large for one launch");
+  gemm_bf16x3_kernel<SPLIT_OUT><<<(unsigned)(tm * tn), 256, 0, s>>>(A, B, C, ldc, Cs, ncols_pad, M, N, Kp,
+                                                                   (int)tm, (int)tn);
+}
 
 // Umat = M Vmat N^T with split-bf16 products: split M and N by rows and Vmat
 // transposed, W = M Vmat written as split pieces by the first GEMM, then
@@ -534,13 +745,17 @@ static void dense_split_bf16(const float *M, int64_t mr, int64_t mc, int64_t ldm
                                                                              al(L.pn));
   split_transpose_kernel<NS><<<dim3((unsigned)ceil_div(k1, 32), (unsigned)ceil_div(nc, 32)), 256, 0, s>>>(
       V, ldv, mc, nc, k1, Vt, al(L.pv));
-  dim3 g1((unsigned)ceil_div(nc, 128), (unsigned)ceil_div(mr, 128));
-  constexpr int BK = NS == 2 ? 64 : 32;  // k step: LDS of two blocks per CU
-  gemm_bf16p_kernel<NS, true, BK><<<g1, 256, 0, s>>>(Ms, k1, al(L.pm), Vt, k1, al(L.pv), nullptr, 0, Ws,
-                                                      k2, al(L.pw), k2, mr, nc, k1);
-  dim3 g2((unsigned)ceil_div(nr, 128), (unsigned)ceil_div(mr, 128));
-  gemm_bf16p_kernel<NS, false, BK><<<g2, 256, 0, s>>>(Ws, k2, al(L.pw), Ns, k2, al(L.pn), U, ldu, nullptr,
-                                                       0, 0, 0, mr, nr, k2);
+  if constexpr (NS == 2) {
+    launch_bf16x3<true>(Ms, Vt, nullptr, 0, Ws, k2, mr, nc, k1, s);
+    launch_bf16x3<false>(Ws, Ns, U, ldu, nullptr, 0, mr, nr, k2, s);
+  } else {
+    dim3 g1((unsigned)ceil_div(nc, 128), (unsigned)ceil_div(mr, 128));
+    gemm_bf16p_kernel<NS, true, 32><<<g1, 256, 0, s>>>(Ms, k1, al(L.pm), Vt, k1, al(L.pv), nullptr, 0, Ws,
+                                                        k2, al(L.pw), k2, mr, nc, k1);
+    dim3 g2((unsigned)ceil_div(nr, 128), (unsigned)ceil_div(mr, 128));
+    gemm_bf16p_kernel<NS, false, 32><<<g2, 256, 0, s>>>(Ws, k2, al(L.pw), Ns, k2, al(L.pn), U, ldu,
+                                                         nullptr, 0, 0, 0, mr, nr, k2);
+  }
   check_launch(s);
   if (!ws) GVT_HIP_CHECK(hipFreeAsync(buf, s));
 }
