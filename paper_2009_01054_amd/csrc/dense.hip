@@ -475,8 +475,8 @@ __global__ __launch_bounds__(256) void gemm_bf16p_kernel(
 //
 // Operand tiles go from global memory straight to LDS (global_load_lds_dwordx4:
 // lane l of a wave writes its 16 bytes at the wave's LDS base + 16 l) through
-// three LDS stages: the copy of k step kk + 2 is issued before the MFMAs of
-// step kk.  One copy instruction moves 8 rows x 128 bytes; lane l takes row
+// three LDS stages: the copies of k step kk + 2 are issued among the MFMAs
+// of step kk.  One copy instruction moves 8 rows x 128 bytes; lane l takes row
 // l / 8 and the 16-byte chunk that the XOR permutation (row bits 0-3) puts at
 // position l % 8, which spreads the 16 rows of a fragment read over distinct
 // banks.  Each wave waits for its own copies (vmcnt) before the barrier that
@@ -535,13 +535,16 @@ __global__ __launch_bounds__(256, 1) void gemm_bf16x3_kernel(
     const int ch = (lane & 7) ^ bf16x3_swz(8 * (q & 1) + crow);
     bp[q] = B + (r < N ? r * ld : 0) + 8 * ch;
   }
+#define GVT_BF16X3_COPY_A(st, q, kk)                                                              \
+  __builtin_amdgcn_global_load_lds((const void *)(ap[q] + 64 * (kk)),                             \
+      (__attribute__((address_space(3))) void *)&Ls[st][wid * (BM / 4) + 8 * (q)][0], 16, 0, 0)
+#define GVT_BF16X3_COPY_B(st, q, kk)                                                              \
+  __builtin_amdgcn_global_load_lds((const void *)(bp[q] + 64 * (kk)),                             \
+      (__attribute__((address_space(3))) void *)&Ls[st][BM + wid * (BN / 4) + 8 * (q)][0], 16, 0, 0)
 #define GVT_BF16X3_COPY(st, kk)                                                                   \
-  _Pragma("unroll") for (int q = 0; q < CPA; ++q) __builtin_amdgcn_global_load_lds(              \
-      (const void *)(ap[q] + 64 * (kk)),                                                          \
-      (__attribute__((address_space(3))) void *)&Ls[st][wid * (BM / 4) + 8 * q][0], 16, 0, 0);    \
-  _Pragma("unroll") for (int q = 0; q < CPB; ++q) __builtin_amdgcn_global_load_lds(              \
-      (const void *)(bp[q] + 64 * (kk)),                                                          \
-      (__attribute__((address_space(3))) void *)&Ls[st][BM + wid * (BN / 4) + 8 * q][0], 16, 0, 0);
+  _Pragma("unroll") for (int q = 0; q < CPA; ++q) GVT_BF16X3_COPY_A(st, q, kk);                   \
+  _Pragma("unroll") for (int q = 0; q < CPB; ++q) GVT_BF16X3_COPY_B(st, q, kk);
+  static_assert(CPA == WTM && CPB <= WTM, "one A copy (and at most one B copy) per MFMA group");
 
   f4 acc[WTM][WTN], cor[WTM][WTN];
 #pragma unroll
@@ -571,14 +574,12 @@ __global__ __launch_bounds__(256, 1) void gemm_bf16x3_kernel(
   int st = 0;
   for (int64_t kk = 0; kk < nk; ++kk) {
     const bool ahead = kk + 2 < nk;
-    if (ahead) {
-      const int s2 = st == 0 ? 2 : st - 1;  // (kk + 2) mod 3
-      GVT_BF16X3_COPY(s2, kk + 2)
-    }
-    __builtin_amdgcn_sched_barrier(0);
+    const int s2 = st == 0 ? 2 : st - 1;  // (kk + 2) mod 3
     // all of B, then A one 16-row block ahead of its MFMAs (the scheduling
     // barriers keep each block's reads in front of the previous block's
-    // MFMAs, so the waits overlap with MFMA execution)
+    // MFMAs, so the waits overlap with MFMA execution); the copies of step
+    // kk + 2 are spread over the MFMA groups, one A copy (and one B copy in
+    // the first CPB groups) each, which keeps the memory pipeline fed evenly
     bf8 bh[WTN], bl[WTN];
 #pragma unroll
     for (int j = 0; j < WTN; ++j) {
@@ -593,6 +594,10 @@ __global__ __launch_bounds__(256, 1) void gemm_bf16x3_kernel(
       if (i + 1 < WTM) {
         ahn = __builtin_bit_cast(bf8, Ls[st][ar0 + 16 * (i + 1)][fh]);
         aln = __builtin_bit_cast(bf8, Ls[st][ar0 + 16 * (i + 1)][fl]);
+      }
+      if (ahead) {
+        GVT_BF16X3_COPY_A(s2, i, kk + 2);
+        if (i < CPB) GVT_BF16X3_COPY_B(s2, i, kk + 2);
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -643,6 +648,8 @@ __global__ __launch_bounds__(256, 1) void gemm_bf16x3_kernel(
     }
 }
 #undef GVT_BF16X3_COPY
+#undef GVT_BF16X3_COPY_A
+#undef GVT_BF16X3_COPY_B
 #undef GVT_WAIT_VMCNT
 #undef GVT_WAIT_LGKMCNT0
 
