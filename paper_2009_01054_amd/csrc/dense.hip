@@ -665,11 +665,11 @@ __global__ void splitk_sum_kernel(const T *__restrict__ P, int splits, int64_t M
 }
 
 // Number of k splits that brings a launch of M x N output tiles to about two
-// workgroups per CU (each split keeps at least 256 k's), and its workspace.
+// workgroups per CU (each split keeps at least 128 k's), and its workspace.
 static int gemm_splits(int64_t M, int64_t N, int64_t K) {
   const int64_t tiles = ceil_div(M, 128) * ceil_div(N, 128);
   if (tiles >= 256) return 1;
-  const int64_t want = ceil_div(512, tiles), most = K / 256;
+  const int64_t want = ceil_div(512, tiles), most = K / 128;
   return (int)std::max<int64_t>(1, std::min<int64_t>(want, std::min<int64_t>(most, 16)));
 }
 static size_t gemm_splits_bytes(int64_t M, int64_t N, int64_t K, size_t es) {

@@ -193,8 +193,10 @@ def test_index_errors(gvt):
     with pytest.raises(gvt.GvtError) as ei:
         gvt.gvt_pairwise_matvec(["symmetric"], D, T, (a, a), (a, a), dev(np.ones(2)))
     assert ei.value.code == -3
+    # split-bf16 products run on matrix cores only: a single Kronecker term of
+    # incomplete data goes through dense tiles, a two-term kind has no such path
     with pytest.raises(gvt.GvtError) as ei:
-        gvt.gvt_pairwise_matvec(["kronecker"], D, T, (a, a), (a, a), dev(np.ones(2)), prec=gvt.BF16X3)
+        gvt.gvt_pairwise_matvec(["cartesian"], D, T, (a, a), (a, a), dev(np.ones(2)), prec=gvt.BF16X3)
     assert ei.value.code == -7
 
 
