@@ -837,12 +837,25 @@ __global__ __launch_bounds__(RB) void bcg_reactivate_kernel(const BChunk *__rest
   }
 }
 
+// Masks of the iteration products per RHS block: the grouped products run
+// the systems of a problem in blocks of RHS (the block layout of each product
+// precision, block b = systems [start[b], start[b + 1])), and a block whose
+// systems have all stopped costs no product work.
+struct BlockMasks {
+  const int32_t *start64, *start32;  // block starts (nb + 1 entries) of the FP64 / FP32 layouts
+  int nb64, nb32;
+  uint8_t *bm64, *bm32;  // [b * nprob + p]; null: not kept
+};
+
 // active[p] = some system of problem p is still iterating; with hi (FP32
 // mode) also the active problems by product precision: act32 = active and not
-// hi, act64 = active and hi
+// hi, act64 = active and hi.  Per RHS block (bm): bm64 = the block has an
+// active system and the problem is on FP64 products (every problem in FP64
+// mode, hi null); bm32 = the block has an active system and the problem is
+// still on FP32 products.
 __global__ void bcg_mask_kernel(const CgScalars *__restrict__ sc, int nprob, int nlam,
                                 uint8_t *__restrict__ active, const uint8_t *__restrict__ hi,
-                                uint8_t *__restrict__ act32, uint8_t *__restrict__ act64) {
+                                uint8_t *__restrict__ act32, uint8_t *__restrict__ act64, BlockMasks bm) {
   const int pb = blockIdx.x * blockDim.x + threadIdx.x;
   if (pb >= nprob) return;
   uint8_t any = 0;
@@ -851,6 +864,21 @@ __global__ void bcg_mask_kernel(const CgScalars *__restrict__ sc, int nprob, int
   if (hi) {
     act32[pb] = any && !hi[pb];
     act64[pb] = any && hi[pb];
+  }
+  auto block_any = [&](int l0, int l1) {
+    uint8_t a = 0;
+    for (int l = l0; l < l1; ++l) a |= sc[pb * nlam + l].state == CG_ACTIVE ? 1 : 0;
+    return a;
+  };
+  if (bm.bm64) {
+    const uint8_t on = hi ? hi[pb] : 1;
+    for (int b = 0; b < bm.nb64; ++b)
+      bm.bm64[(int64_t)b * nprob + pb] = on && block_any(bm.start64[b], bm.start64[b + 1]);
+  }
+  if (bm.bm32) {
+    const uint8_t on = hi ? !hi[pb] : 0;
+    for (int b = 0; b < bm.nb32; ++b)
+      bm.bm32[(int64_t)b * nprob + pb] = on && block_any(bm.start32[b], bm.start32[b + 1]);
   }
 }
 
@@ -1025,6 +1053,22 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
   // products (FP32 mode); act32 / act64: active problems by product precision
   uint8_t *active = (uint8_t *)m_act.ensure((size_t)nprob * 4);
   uint8_t *hi = active + nprob, *act32 = hi + nprob, *act64 = act32 + nprob;
+  // per-RHS-block masks of the iteration products and the block layouts
+  std::vector<int32_t> hstart;
+  auto add_layout = [&](int maxR) {
+    const int nb0 = (int)hstart.size();
+    for (int64_t r0 = 0; r0 < nlam; r0 += rhs_block(nlam - r0, maxR)) hstart.push_back((int32_t)r0);
+    hstart.push_back((int32_t)nlam);
+    return (int)hstart.size() - nb0 - 1;
+  };
+  const int nb64 = add_layout(maxR64), nb32 = add_layout(maxR32);
+  DevMem m_bm;
+  const size_t bmbytes = ((size_t)(nb64 + nb32) * nprob + 15) / 16 * 16;
+  uint8_t *bmbase = (uint8_t *)m_bm.ensure(bmbytes + hstart.size() * 4);
+  int32_t *dstart = (int32_t *)(bmbase + bmbytes);
+  GVT_HIP_CHECK(hipMemcpyAsync(dstart, hstart.data(), hstart.size() * 4, hipMemcpyHostToDevice, s));
+  const BlockMasks bmk{dstart, dstart + nb64 + 1, nb64, nb32, bmbase,
+                       mprec == GVT_F32 ? bmbase + (size_t)nb64 * nprob : nullptr};
   uint8_t *cmask = (uint8_t *)m_cmask.ensure((size_t)nprob + nsys);
   uint8_t *modes = cmask + nprob;  // per system: 1 = continue along the last direction
   GVT_HIP_CHECK(hipMemsetAsync(hi, 0, nprob, s));
@@ -1193,20 +1237,25 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
 
   // ---- products of every problem: out = K in (RHS blocks of at most the
   // precision's cap)
-  auto grouped_product = [&](auto *desc, const uint8_t *mask) {
+  // (per_block: mask holds one per-problem mask per RHS block of the
+  // precision's layout, block b at mask + b * nprob)
+  auto grouped_product = [&](auto *desc, const uint8_t *mask, bool per_block) {
     constexpr bool f64 = std::is_same<std::remove_pointer_t<decltype(desc)>, GroupDesc<double>>::value;
     const int maxR = f64 ? maxR64 : maxR32;
-    for (int64_t r0 = 0; r0 < nlam;) {
+    int64_t b = 0;
+    for (int64_t r0 = 0; r0 < nlam; ++b) {
       const int R = rhs_block(nlam - r0, maxR);
-      launch_group_pack(desc, it_pack, n_pack, R, r0, mask, s);
-      launch_group_stage1(desc, f64 ? it_s1 : it_s1f, f64 ? n_s1 : n_s1f, R, mask, s);
-      launch_group_stage2(desc, it_s2[tile_class(R)], n_s2[tile_class(R)], R, r0, mask, s);
+      const uint8_t *mk = per_block ? mask + b * nprob : mask;
+      launch_group_pack(desc, it_pack, n_pack, R, r0, mk, s);
+      launch_group_stage1(desc, f64 ? it_s1 : it_s1f, f64 ? n_s1 : n_s1f, R, mk, s);
+      launch_group_stage2(desc, it_s2[tile_class(R)], n_s2[tile_class(R)], R, r0, mk, s);
       r0 += R;
     }
   };
-  auto product64 = [&](const double *in, double *out, bool residual_set, const uint8_t *mask) {
+  auto product64 = [&](const double *in, double *out, bool residual_set, const uint8_t *mask,
+                       bool per_block = false) {
     if (grouped) {
-      grouped_product(residual_set ? dd_res : dd_it, mask);
+      grouped_product(residual_set ? dd_res : dd_it, mask, per_block);
       return;
     }
     for (int i = 0; i < nprob; ++i)
@@ -1218,8 +1267,8 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
   std::vector<uint8_t> hhi(nprob, 0);
   auto product32 = [&]() {
     if (grouped) {
-      grouped_product(df_it, act32);
-      grouped_product(dd_it, act64);
+      grouped_product(df_it, bmk.bm32, true);
+      grouped_product(dd_it, bmk.bm64, true);
       return;
     }
     for (int i = 0; i < nprob; ++i) {
@@ -1277,7 +1326,8 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     GVT_HIP_CHECK(hipMemcpyAsync(active, hmask.data(), nprob, hipMemcpyHostToDevice, s));
     GVT_HIP_CHECK(hipMemcpyAsync(hi, hhi.data(), nprob, hipMemcpyHostToDevice, s));
     bcg_mask_kernel<<<(unsigned)ceil_div(nprob, 256), 256, 0, s>>>(sc, nprob, nlam, active,
-                                                                   mprec == GVT_F32 ? hi : nullptr, act32, act64);
+                                                                   mprec == GVT_F32 ? hi : nullptr, act32, act64,
+                                                                   bmk);
     GVT_HIP_CHECK(hipStreamSynchronize(s));  // the host arrays are reused
   };
   upload_states();
@@ -1293,14 +1343,14 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
       product32();
       bcg_pw_mixed_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, w32, wraw, hi, w, p, lam, nlam, sc, part);
     } else {
-      product64(p, wraw, false, active);
+      product64(p, wraw, false, bmk.bm64, true);
       bcg_pw_kernel<double><<<(unsigned)nch, RB, 0, s>>>(ch, wraw, w, p, lam, nlam, sc, part);
     }
     bcg_alpha_kernel<<<nsys, RB, 0, s>>>(sc, part, cf);
     bcg_update_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, A, r, p, w, sc, part);
     bcg_beta_kernel<<<nsys, RB, 0, s>>>(sc, part, cf, tol, max_iter, lowprec);
     bcg_p_kernel<<<(unsigned)nch, RB, 0, s>>>(ch, p, r, sc);
-    bcg_mask_kernel<<<gm, 256, 0, s>>>(sc, nprob, nlam, active, lowprec ? hi : nullptr, act32, act64);
+    bcg_mask_kernel<<<gm, 256, 0, s>>>(sc, nprob, nlam, active, lowprec ? hi : nullptr, act32, act64, bmk);
   };
 
   const bool use_graph = s != nullptr;
@@ -1446,7 +1496,7 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
           }
           GVT_HIP_CHECK(hipMemcpyAsync(hi, hhi.data(), nprob, hipMemcpyHostToDevice, s));
           bcg_mask_kernel<<<(unsigned)ceil_div(nprob, 256), 256, 0, s>>>(sc, nprob, nlam, active, hi, act32,
-                                                                         act64);
+                                                                         act64, bmk);
           GVT_HIP_CHECK(hipStreamSynchronize(s));
         }
       }
