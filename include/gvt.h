@@ -31,7 +31,8 @@
  *  - Element type follows the precision: GVT_F64 uses double for D, T, V, U;
  *    GVT_F32 uses float.  GVT_BF16X3 (bf16 split products with FP32
  *    accumulation on matrix cores) uses float storage and is available on the
- *    complete-data dense path only.
+ *    matrix-core paths only: complete data, and dense tiles of two-factor
+ *    terms (gvt_plan_uses_tiles); a plan's other terms then run in FP32.
  *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
  *    and the call returns without synchronising unless stated.
  *  - Threads: calls from several host threads may run at once, on streams of
@@ -164,7 +165,8 @@ int gvt_plan_destroy(gvt_plan_t plan);
  * product with a block of the other kind builds that set (device or host
  * work, and allocation), so that first call must not be captured into a
  * graph (GVT_ERR_ARG if it is).
- * Errors: GVT_ERR_ARG, GVT_ERR_UNSUPPORTED (GVT_BF16X3 on the gather path),
+ * Errors: GVT_ERR_ARG, GVT_ERR_UNSUPPORTED (a split-bf16 precision for a plan
+ * whose two-factor terms cannot run as dense tiles, or that has none),
  * GVT_ERR_HIP, GVT_ERR_NOMEM.
  */
 int gvt_plan_execute(gvt_plan_t plan, int prec, const void *D, int64_t ldd, const void *T,
@@ -494,13 +496,20 @@ int gvt_plan_info(gvt_plan_t plan, double *info);
 
 /*
  * gvt_plan_uses_tiles — diagnostic: 1 when products of the plan in precision
- * prec run as dense tiles (a single Kronecker term computed as M Vmat N^T on
- * matrix cores, Vmat the zero grid with the input vector scattered into it):
- * always with GVT_FLAG_DENSE_TILES or environment GVT_DENSE_TILES=1 at plan
- * creation and for the split-bf16 precisions; never with
- * GVT_FLAG_NO_DENSE_TILES or GVT_DENSE_TILES=0; otherwise when the tuned cost
- * model estimates the dense product faster than the gather path.  0 when the
- * gather path runs, GVT_ERR_ARG for a null plan.
+ * prec run as dense tiles (a Kronecker term computed as M Vmat N^T on matrix
+ * cores, Vmat the zero grid with the input vector scattered into it, the
+ * outputs gathered from the result): for a single Kronecker term the whole
+ * product; for several kinds or terms every two-factor term (Corollary 1's
+ * terms of the form R(D (x) T)R^T keyed by the input pair (c, e); terms with
+ * equal base matrices share one dense product, each gathering its own output
+ * order), with the one-factor and match terms and the per-kind sums on the
+ * gather path, which is possible when no two-factor term is keyed by (c, c)
+ * or (e, e) (MLPK has such terms).  Taken always with GVT_FLAG_DENSE_TILES or
+ * environment GVT_DENSE_TILES=1 at plan creation and for the split-bf16
+ * precisions; never with GVT_FLAG_NO_DENSE_TILES or GVT_DENSE_TILES=0;
+ * otherwise when the tuned cost model estimates the dense products faster
+ * than the gather path.  0 when the gather path runs, GVT_ERR_ARG for a null
+ * plan.
  */
 int gvt_plan_uses_tiles(gvt_plan_t plan, int prec);
 

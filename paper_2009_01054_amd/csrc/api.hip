@@ -362,7 +362,7 @@ int gvt_dense_matvec(int prec, const void *M, int64_t m_rows, int64_t m_cols, in
 int gvt_plan_uses_tiles(gvt_plan_t plan, int prec) {
   return guarded([&]() {
     GVT_REQUIRE(plan, GVT_ERR_ARG, "null plan");
-    return plan_uses_tiles(plan, prec) ? 1 : 0;
+    return plan_uses_tiles(plan, prec) || plan_uses_gtiles(plan, prec) ? 1 : 0;
   });
 }
 

@@ -77,6 +77,18 @@ struct TermSpec {
   bool operator==(const TermSpec &) const = delete;
 };
 
+// Multi-term dense tiles: a two-factor term u_i = sum_j F_dot[x_i, key_j]
+// F_sc[y_i, other_j] v_j keyed (c, e) or (e, c) is the gather of
+// Umat = F_A Vmat F_B^T at (p_i, q_i), with Vmat[c, e] = sum of v over the
+// pairs (c, e); terms with the same F_A, F_B share Umat.
+struct TileTerm {
+  int ti, p, q;  // term index, output selectors (SA / SB) of Umat's row and column
+};
+struct TileGroup {
+  int fa, fb;  // Umat = F[fa] Vmat F[fb]^T
+  std::vector<TileTerm> terms;
+};
+
 struct GemvSpec {
   int f = FD, sq = 0, key = SC;
 };
@@ -138,6 +150,13 @@ struct gvt_plan {
   bool tiles_ok = false;
   int tiles_mode = 0;
   gvt::DevMem tiles_ws;  // Vmat, Umat and the dense product's workspace
+  // The same for plans of several terms (not direct): every two-factor term
+  // goes through one dense product per operator group (TileGroup) and a
+  // gather into its term vector; one-factor and match terms and the per-kind
+  // combination stay on the gather path.  Possible when every two-factor term
+  // is keyed by (c, e) or (e, c); the same mode and cost model decide.
+  std::vector<gvt::TileGroup> tgroups;
+  bool gtiles_ok = false;
   // optional stage timing: events recorded at stage-group boundaries
   hipEvent_t *prof = nullptr;  // [kStages][2] start/stop, or null
 };
@@ -170,8 +189,11 @@ inline int rhs_block(int64_t left, int max_rhs) {
 int stage2_block_rows(const gvt_plan *P, const TermSpec &t, int cls);
 void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void *T, int64_t ldt,
                   const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu, hipStream_t s);
-// Whether a product in precision prec takes the dense-tile form (see tiles_ok).
+// Whether a product in precision prec takes the dense-tile form (see tiles_ok),
+// and whether a multi-term product runs its two-factor terms as dense tiles
+// (see gtiles_ok).
 bool plan_uses_tiles(const gvt_plan *P, int prec);
+bool plan_uses_gtiles(const gvt_plan *P, int prec);
 // Where a product with one block of R right-hand sides (R a block size the
 // plan runs whole: rhs_block(R, max_rhs) == R) reads its input in key order:
 // for each input sort k < the returned count, element (j, r) of the input

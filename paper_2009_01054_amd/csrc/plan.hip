@@ -683,6 +683,32 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
       P->cost_fma += n_out_d * (n_in_d / std::max<double>(1.0, (double)nkeys_of(P, ts.key)));
     }
   }
+  // two-factor terms as dense-tile groups (gvt_plan::tgroups): a term keyed
+  // (e, c) is the same operator with F_A, F_B and the gather indices swapped
+  {
+    bool ok = true;
+    std::vector<TileGroup> groups;
+    for (size_t ti = 0; ti < P->terms.size() && ok; ++ti) {
+      const TermSpec &ts = P->terms[ti];
+      if (ts.type != TG) continue;
+      const SBufSpec &sb = P->sbufs[ts.sbuf];
+      int fa, fb, pp, qq;
+      if (sb.key == SC && sb.other == SE) {
+        fa = ts.fdot; fb = sb.fsc; pp = ts.x; qq = ts.y;
+      } else if (sb.key == SE && sb.other == SC) {
+        fa = sb.fsc; fb = ts.fdot; pp = ts.y; qq = ts.x;
+      } else {
+        ok = false;
+        break;
+      }
+      ok = cols_of(P, fa) == nkeys_of(P, SC) && cols_of(P, fb) == nkeys_of(P, SE);
+      size_t g = 0;
+      while (g < groups.size() && !(groups[g].fa == fa && groups[g].fb == fb)) ++g;
+      if (g == groups.size()) groups.push_back(TileGroup{fa, fb, {}});
+      groups[g].terms.push_back(TileTerm{(int)ti, pp, qq});
+    }
+    if (ok && n_in > 0 && n_out > 0) P->tgroups = std::move(groups);
+  }
   // S-buffer stage-1 cost (shared scatters counted once)
   for (const SBufSpec &sb : P->sbufs)
     P->cost_fma += sb.degenerate ? (double)sb.nneed * nkeys_of(P, sb.key) : (double)sb.nneed * n_in_d;
@@ -823,6 +849,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
     tm.lap("input sorts + term orderings");
     bool need_idx = nkinds == 1 && kinds[0] == GVT_KRONECKER;  // dense tiles gather by (a, b)
     for (const TermSpec &t : P->terms) need_idx = need_idx || t.type != TG;
+    need_idx = need_idx || !P->tgroups.empty();  // multi-term dense tiles gather by (a, b)
     if (need_idx)
       for (int i = 0; i < 4; ++i) up.add(P->idx[i], h[i]);
     up.commit(P->blob);
@@ -830,6 +857,7 @@ void plan_build(gvt_plan *P, const int *kinds, int nkinds, int64_t d_rows, int64
   }
   P->direct = nkinds == 1 && P->outputs[0].size() == 1 && P->outputs[0][0].second == 1.0 &&
               P->terms[P->outputs[0][0].first].type == TG;
+  P->gtiles_ok = !P->direct && !P->tgroups.empty();
   {
     const TermSpec &t0 = P->terms[P->outputs[0][0].first];
     P->tiles_ok = P->direct && kinds[0] == GVT_KRONECKER && n_in > 0 && n_out > 0 && t0.sbuf >= 0 &&
@@ -901,9 +929,19 @@ inline void mark(gvt_plan *P, int stage, int edge, hipStream_t s) {
   if (P->prof) GVT_HIP_CHECK(hipEventRecord(P->prof[stage * 2 + edge], s));
 }
 
+}  // namespace
+template <class T>
+void execute_gtiles(gvt_plan *P, int gprec, const T *const *F, const int64_t *ldF, const T *V, int R,
+                    int64_t ldv, T *const *tvec, hipStream_t s);
+namespace {
+
+// One block of R RHS through the term program.  gprec != 0: the two-factor
+// terms go through dense tiles in that precision (gvt_plan::tgroups) instead
+// of stages 1 and 2.
 template <class T>
 void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ldt, const T *V,
-                   int R, int64_t ldv, T *U, int64_t ldu, int64_t block_stride, hipStream_t s) {
+                   int R, int64_t ldv, T *U, int64_t ldu, int64_t block_stride, hipStream_t s,
+                   int gprec) {
   layout_workspace<T>(P, R);
   Workspace &W = P->ws[prec_slot<T>()];
   const T *F[2] = {D, P->homogeneous ? D : Tm};
@@ -936,7 +974,7 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
   // stage 1 (shared scatters)
   mark(P, ST_STAGE1, 0, s);
   bool transposed[2] = {false, false};
-  for (size_t i = 0; i < P->sbufs.size(); ++i) {
+  for (size_t i = 0; i < P->sbufs.size() && !gprec; ++i) {
     const SBufSpec &sb = P->sbufs[i];
     const int ks = sb.key == SC ? 0 : 1;
     const InputSort &is = P->insort[ks];
@@ -969,7 +1007,12 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
   mark(P, ST_STAGE1, 1, s);
   // two-factor terms: stage 2
   mark(P, ST_STAGE2, 0, s);
-  for (size_t ti = 0; ti < P->terms.size(); ++ti) {
+  if (gprec) {
+    std::vector<T *> tv(P->terms.size(), nullptr);
+    for (size_t ti = 0; ti < P->terms.size(); ++ti) tv[ti] = wsp<T>(P, W.tvec[ti]);
+    execute_gtiles<T>(P, gprec, F, ldF, V, R, ldv, tv.data(), s);
+  }
+  for (size_t ti = 0; ti < P->terms.size() && !gprec; ++ti) {
     const TermSpec &t = P->terms[ti];
     if (t.type == TG) {
       const SBufSpec &sb = P->sbufs[t.sbuf];
@@ -1026,7 +1069,7 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
 
 template <class T>
 void execute_t(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ldt, const T *V,
-               int64_t nrhs, int64_t ldv, T *U, int64_t ldu, hipStream_t s) {
+               int64_t nrhs, int64_t ldv, T *U, int64_t ldu, hipStream_t s, int gprec = 0) {
   const int64_t block_stride = nrhs * ldu;
   if (P->n_out == 0) return;
   if (P->n_in == 0) {
@@ -1040,7 +1083,7 @@ void execute_t(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ldt, c
     const int64_t left = nrhs - r0;
     const int R = rhs_block(left, P->max_rhs[prec_slot<T>()]);
     plan_ensure_tiles(P, tile_class(R), s);
-    execute_block<T>(P, D, ldd, Tm, ldt, V + r0 * ldv, R, ldv, U + r0 * ldu, ldu, block_stride, s);
+    execute_block<T>(P, D, ldd, Tm, ldt, V + r0 * ldv, R, ldv, U + r0 * ldu, ldu, block_stride, s, gprec);
     r0 += R;
   }
 }
@@ -1080,24 +1123,91 @@ __global__ void tiles_gather_kernel(const T *__restrict__ Umat, int64_t ldum, co
   if (i < n) u[i] = Umat[(int64_t)a[i] * ldum + b[i]];
 }
 
-bool plan_uses_tiles(const gvt_plan *P, int prec) {
-  if (!P->tiles_ok || P->tiles_mode < 0) return false;
-  if (P->tiles_mode > 0 || prec == GVT_BF16X3 || prec == GVT_BF16X6) return true;
-  // time estimates per RHS: the gather path's Theorem 1 flops against the
-  // dense product's two GEMMs plus its extra traffic (Vmat written twice,
-  // Umat written and gathered).  A GEMM with few 128 x 128 output tiles
-  // leaves matrix cores idle: its rate scales with min(1, tiles / kTilesFull).
+// u[i * stride] = Umat[p_i, q_i]
+template <class T>
+__global__ void tiles_gather_term_kernel(const T *__restrict__ Umat, int64_t ldum, const int32_t *__restrict__ p,
+                                         const int32_t *__restrict__ q, int64_t n, T *__restrict__ u,
+                                         int64_t stride) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) u[i * stride] = Umat[(int64_t)p[i] * ldum + q[i]];
+}
+
+// Time estimates per RHS of a dense product of the plan's shapes against the
+// gather path's Theorem 1 flops (ngroups dense products).  A GEMM with few
+// 128 x 128 output tiles leaves matrix cores idle: its rate scales with
+// min(1, tiles / kTilesFull).
+static bool dense_beats_gather(const gvt_plan *P, int prec, int64_t fa_rows, int64_t fb_rows, int ngroups) {
   const double es = prec == GVT_F64 ? 8.0 : 4.0;
   const double rate = prec == GVT_F64 ? kTilesRateF64 : kTilesRateF32;
   auto gemm_s = [&](double m, double n, double k) {
     const double tiles = std::ceil(m / 128.0) * std::ceil(n / 128.0);
     return 2.0 * m * n * k / (rate * std::min(1.0, tiles / kTilesFull));
   };
-  const double bytes = es * (2.0 * P->d_cols * P->t_cols + 2.0 * P->d_rows * P->t_rows + P->d_rows * P->t_cols);
-  const double t_dense = gemm_s((double)P->d_rows, (double)P->t_cols, (double)P->d_cols) +
-                         gemm_s((double)P->d_rows, (double)P->t_rows, (double)P->t_cols) + bytes / 4.0e12;
+  const double bytes = es * (2.0 * P->d_cols * P->t_cols + 2.0 * fa_rows * fb_rows + fa_rows * P->t_cols);
+  const double t_dense = ngroups * (gemm_s((double)fa_rows, (double)P->t_cols, (double)P->d_cols) +
+                                    gemm_s((double)fa_rows, (double)fb_rows, (double)P->t_cols) + bytes / 4.0e12);
   const double t_gather = 2.0 * P->cost_fma / (prec == GVT_F64 ? kGatherRateF64 : kGatherRateF32);
   return t_dense < t_gather;
+}
+
+bool plan_uses_gtiles(const gvt_plan *P, int prec) {
+  if (!P->gtiles_ok || P->tiles_mode < 0) return false;
+  if (P->tiles_mode > 0 || prec == GVT_BF16X3 || prec == GVT_BF16X6) return true;
+  int64_t ra = 0, rb = 0;
+  for (const TileGroup &g : P->tgroups) {
+    ra = std::max(ra, rows_of(P, g.fa));
+    rb = std::max(rb, rows_of(P, g.fb));
+  }
+  return dense_beats_gather(P, prec, ra, rb, (int)P->tgroups.size());
+}
+
+// The two-factor terms of a multi-term plan as dense tiles: per RHS column r
+// and operator group, Vmat[c, e] from v (duplicates summed in the sorted
+// order), Umat = F_A Vmat F_B^T in precision gprec, and each term's outputs
+// gathered into column r of its term vector (row stride R).
+template <class T>
+void execute_gtiles(gvt_plan *P, int gprec, const T *const *F, const int64_t *ldF, const T *V, int R,
+                    int64_t ldv, T *const *tvec, hipStream_t s) {
+  const int ks = P->insort[0].built ? 0 : 1;  // either input sort yields Vmat[c, e]
+  const InputSort &is = P->insort[ks];
+  GVT_REQUIRE(is.built, GVT_ERR_ARG, "internal: dense tiles without an input sort");
+  int64_t ra = 0, rb = 0;
+  for (const TileGroup &g : P->tgroups) {
+    ra = std::max(ra, rows_of(P, g.fa));
+    rb = std::max(rb, rows_of(P, g.fb));
+  }
+  const int64_t nv = P->d_cols * P->t_cols, nu = ra * rb;
+  const size_t al = 256;
+  const size_t vb = ((size_t)nv * sizeof(T) + al - 1) / al * al, ub = ((size_t)nu * sizeof(T) + al - 1) / al * al;
+  const size_t wb = dense_workspace_bytes(gprec, ra, P->d_cols, rb, P->t_cols);
+  char *base = static_cast<char *>(P->tiles_ws.ensure(vb + ub + wb));
+  T *Vmat = reinterpret_cast<T *>(base), *Umat = reinterpret_cast<T *>(base + vb);
+  void *wsd = base + vb + ub;
+  for (int r = 0; r < R; ++r) {
+    tiles_zero_kernel<T><<<(unsigned)std::min<int64_t>(ceil_div(nv, 256), 4096), 256, 0, s>>>(Vmat, nv);
+    tiles_scatter_kernel<T><<<(unsigned)ceil_div(P->n_in, 256), 256, 0, s>>>(
+        is.perm.as<int32_t>(), is.other.as<int32_t>(), P->idx[ks == 0 ? SC : SE].as<int32_t>(), P->n_in,
+        V + r * ldv, ks == 0 ? 1 : 0, P->t_cols, Vmat);
+    for (const TileGroup &g : P->tgroups) {
+      const int64_t na = rows_of(P, g.fa), nb = rows_of(P, g.fb);
+      dense_matvec(gprec, F[g.fa], na, P->d_cols, ldF[g.fa], F[g.fb], nb, P->t_cols, ldF[g.fb], Vmat,
+                   P->t_cols, Umat, nb, wsd, s);
+      for (const TileTerm &tt : g.terms)
+        tiles_gather_term_kernel<T><<<(unsigned)ceil_div(P->n_out, 256), 256, 0, s>>>(
+            Umat, nb, P->idx[tt.p].as<int32_t>(), P->idx[tt.q].as<int32_t>(), P->n_out, tvec[tt.ti] + r,
+            (int64_t)R);
+    }
+  }
+}
+template void execute_gtiles<double>(gvt_plan *, int, const double *const *, const int64_t *, const double *, int,
+                                     int64_t, double *const *, hipStream_t);
+template void execute_gtiles<float>(gvt_plan *, int, const float *const *, const int64_t *, const float *, int,
+                                    int64_t, float *const *, hipStream_t);
+
+bool plan_uses_tiles(const gvt_plan *P, int prec) {
+  if (!P->tiles_ok || P->tiles_mode < 0) return false;
+  if (P->tiles_mode > 0 || prec == GVT_BF16X3 || prec == GVT_BF16X6) return true;
+  return dense_beats_gather(P, prec, P->d_rows, P->t_rows, 1);
 }
 
 template <class T>
@@ -1160,14 +1270,16 @@ void plan_execute(gvt_plan *P, int prec, const void *D, int64_t ldd, const void 
     check_launch(s);
     return;
   }
-  GVT_REQUIRE(prec == GVT_F64 || prec == GVT_F32, GVT_ERR_UNSUPPORTED,
-              "split-bf16 products are provided on the matrix-core paths only (complete data, dense tiles)");
+  const bool gt = plan_uses_gtiles(P, prec);
+  GVT_REQUIRE(gt || prec == GVT_F64 || prec == GVT_F32, GVT_ERR_UNSUPPORTED,
+              "split-bf16 products are provided on the matrix-core paths only (complete data, dense tiles "
+              "of two-factor terms keyed by (c, e))");
   if (prec == GVT_F64)
     execute_t<double>(P, (const double *)D, ldd, (const double *)T, ldt, (const double *)V, nrhs,
-                      ldv, (double *)U, ldu, s);
+                      ldv, (double *)U, ldu, s, gt ? prec : 0);
   else
     execute_t<float>(P, (const float *)D, ldd, (const float *)T, ldt, (const float *)V, nrhs, ldv,
-                     (float *)U, ldu, s);
+                     (float *)U, ldu, s, gt ? prec : 0);
   check_launch(s);
 }
 

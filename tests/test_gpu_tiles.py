@@ -135,3 +135,69 @@ def test_cg_with_tiles_products(gvt, monkeypatch, prec):
                                               max_iter=400, tol=1e-6)
         for l in range(2):
             assert np.linalg.norm(A[:, l] - A_or[:, l]) / np.linalg.norm(A_or[:, l]) < 1e-5
+
+
+# ------------------------------------------------------- plans of several terms
+def _run_kinds(gvt, kinds, p, prec, flags, v):
+    dt = torch.float64 if prec == "f64" else torch.float32
+    pc = {"f64": gvt.F64, "f32": gvt.F32, "bf16x3": gvt.BF16X3, "bf16x6": gvt.BF16X6}[prec]
+    D, T = dev(p["D"], dt), dev(p["T"], dt)
+    plan = gvt.gvt_plan_create(kinds, D.shape, T.shape, (idx(p["a"]), idx(p["b"])),
+                               (idx(p["c"]), idx(p["e"])), flags=flags)
+    uses = gvt.gvt_plan_uses_tiles(plan, pc)
+    u = plan.execute(D, T, dev(v, dt), prec=pc)  # (kinds, n_out[, rhs])
+    plan.close()
+    return u.double().cpu().numpy(), uses
+
+
+HOM_KINDS = [["symmetric"], ["antisymmetric"], ["poly2d"], ["symmetric", "antisymmetric", "cartesian", "poly2d"]]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x6", "bf16x3"])
+@pytest.mark.parametrize("kinds", HOM_KINDS, ids=["sym", "anti", "poly2d", "fused4"])
+def test_multiterm_tiles_match_oracle(gvt, prec, kinds):
+    # homogeneous kinds: both gather orders of the two-factor terms share one dense product
+    # D Vmat D; one-factor (Poly2D) and match (Cartesian) terms stay on the gather path.
+    # A separate output sample, duplicated input pairs, two RHS.
+    p = W.make_homogeneous(108, 0, 160, 4000, 8, n_out=2500, kernel="gaussian")
+    p["c"][:30] = p["c"][30:60]
+    p["e"][:30] = p["e"][30:60]
+    v = np.random.default_rng(109).standard_normal((len(p["c"]), 2))
+    u, uses = _run_kinds(gvt, kinds, p, prec, gvt.FLAG_DENSE_TILES, v)
+    assert uses == 1
+    for k, kind in enumerate(kinds):
+        ref = oracle.pairwise_matvec(kind, p["D"], None, (p["a"], p["b"]), (p["c"], p["e"]), v)
+        err = relerr(u[k], ref)
+        print(kind, prec, err)
+        assert err < TOL[prec], (kind, prec, err)
+        if prec == "f64":
+            g, guse = _run_kinds(gvt, kinds, p, prec, gvt.FLAG_NO_DENSE_TILES, v)
+            assert guse == 0 and relerr(g[k], ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_multiterm_tiles_heterogeneous(gvt, prec):
+    # Kronecker + Poly2D + linear on a rectangular grid: one group D Vmat T^T serves the
+    # Kronecker term and Poly2D's cross term; the one-factor terms run on the gather path
+    kinds = ["kronecker", "poly2d", "linear"]
+    p = W.make_heterogeneous(110, 0, 120, 90, 3000, 6, n_out=2000)
+    v = np.random.default_rng(111).standard_normal(len(p["c"]))
+    u, uses = _run_kinds(gvt, kinds, p, prec, gvt.FLAG_DENSE_TILES, v)
+    assert uses == 1
+    for k, kind in enumerate(kinds):
+        ref = oracle.pairwise_matvec(kind, p["D"], p["T"], (p["a"], p["b"]), (p["c"], p["e"]), v)
+        assert relerr(u[k], ref) < TOL[prec], (kind, prec)
+
+
+def test_multiterm_tiles_not_for_degenerate_terms(gvt):
+    # MLPK keys two of its two-factor terms by (c, c) and (e, e): no dense-tile form, so
+    # its split-bf16 products are unsupported and FP64 runs the gather path
+    p = W.make_homogeneous(112, 0, 60, 800, 6, kernel="gaussian")
+    D = dev(p["D"])
+    plan = gvt.gvt_plan_create(["mlpk"], D.shape, D.shape, (idx(p["a"]), idx(p["b"])),
+                               (idx(p["c"]), idx(p["e"])), flags=gvt.FLAG_DENSE_TILES)
+    assert gvt.gvt_plan_uses_tiles(plan, gvt.F64) == 0
+    with pytest.raises(gvt.GvtError) as ei:
+        plan.execute(D.float(), D.float(), dev(p["v"], torch.float32), prec=gvt.BF16X3)
+    assert ei.value.code == -7
+    plan.close()
