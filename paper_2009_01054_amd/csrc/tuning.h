@@ -2,51 +2,50 @@
 // each RHS class, and the keys each wave walks in stage 1.
 // Written by paper_2009_01054_amd/tune.py on gfx950; measured times (ms):
 //   WIDE: ridge f64 x1; ridge f32 x1
-//          0: 0.1264, 0.0897  (score 1.129)
-//          1: 0.1091, 0.0815  (score 1.000)
+//          0: 0.1287, 0.0912  (score 1.118)
+//          1: 0.1121, 0.0838  (score 1.000)
 //   KPW: ridge f64 x1; ridge f32 x1
-//          1: 0.1079, 0.0815  (score 1.000)
-//          2: 0.1099, 0.0851  (score 1.031)
-//          4: 0.1137, 0.0939  (score 1.102)
+//          1: 0.1098, 0.0837  (score 1.004)
+//          2: 0.1117, 0.0830  (score 1.009)
+//          4: 0.1148, 0.0933  (score 1.084)
 //   R1: ridge f64 x1; ridge f32 x1; batched f64 (64 problems, 8 RHS), per iteration
-//          8: 0.1257, 0.1211, 9.0697  (score 1.162)
-//         16: 0.1158, 0.0859, 8.9787  (score 1.005)
-//         32: 0.1162, 0.0869, 9.0060  (score 1.011)
-//         64: 0.1148, 0.0858, 11.3898  (score 1.084)
-//        128: 0.1142, 0.0864, 9.0310  (score 1.005)
+//          8: 0.1271, 0.1213, 9.0141  (score 1.221)
+//         16: 0.1059, 0.0802, 9.0393  (score 1.001)
+//         32: 0.1068, 0.0803, 9.0507  (score 1.005)
+//         64: 0.1059, 0.0802, 9.0557  (score 1.002)
+//        128: 0.1068, 0.0801, 9.0480  (score 1.004)
 //   MAXR64: ridge f64 x8; batched f64 (64 problems, 8 RHS), per iteration
-//          2: 0.8625, 9.0377  (score 1.000)
-//          4: 1.0308, 11.3215  (score 1.224)
-//          8: 1.7661, 14.2640  (score 1.798)
+//          2: 0.7881, 9.0392  (score 1.000)
+//          4: 0.9883, 11.5277  (score 1.265)
+//          8: 1.6924, 14.4786  (score 1.855)
 //   MAXR32: ridge f32 x8; batched f32 (64 problems, 8 RHS), per iteration
-//          2: 0.5783, 5.6837  (score 1.178)
-//          4: 0.4749, 4.9903  (score 1.000)
-//          8: 0.5802, 5.6796  (score 1.179)
+//          2: 0.5567, 5.7363  (score 1.182)
+//          4: 0.4514, 5.0667  (score 1.000)
+//          8: 0.5503, 5.8510  (score 1.187)
 //   R8: ridge f64 x8; ridge f32 x8; batched f32 (64 problems, 8 RHS), per iteration
-//          2: 0.8699, 0.6954, 6.7380  (score 1.269)
-//          4: 0.8610, 0.5280, 5.4298  (score 1.074)
-//          8: 0.8705, 0.5492, 4.8566  (score 1.052)
-//         16: 0.8599, 0.4813, 5.1444  (score 1.022)
-//         32: 0.8686, 0.4776, 4.9891  (score 1.012)
+//          2: 0.7943, 0.6553, 6.9319  (score 1.275)
+//          4: 0.7873, 0.4926, 5.5461  (score 1.073)
+//          8: 0.7885, 0.5108, 4.9480  (score 1.047)
+//         16: 0.7902, 0.4490, 5.0690  (score 1.011)
+//         32: 0.7852, 0.4476, 5.0768  (score 1.009)
 #pragma once
 
 namespace gvt {
-constexpr double kStage2TargetR1 = 128.0;
+constexpr double kStage2TargetR1 = 16.0;
 constexpr double kStage2TargetR8 = 32.0;
 constexpr int kStage1KeysPerWave = 1;
 constexpr int kStage1Wide = 1;
 constexpr int kMaxRhsBlockF64 = 2;
 constexpr int kMaxRhsBlockF32 = 4;
-// Dense-tile cost model (a plan of one Kronecker term): effective rates of the
-// gather path (Theorem 1 flops per second, ridge workload) and of the
-// matrix-core GEMMs of M Vmat N^T (complete-data workload, 8192 x 4096), and
-// the output-tile count at which a GEMM keeps the matrix cores busy (the
-// ridge workload's 2000 x 500 GEMMs, 64 tiles, ran at 1/6 of the full rate).
-constexpr double kGatherRateF64 = 9.3e12;
-constexpr double kGatherRateF32 = 11.6e12;
-constexpr double kTilesRateF64 = 56.0e12;
-constexpr double kTilesRateF32 = 118.0e12;
-constexpr double kTilesFull = 384.0;
+// Dense-tile cost model: effective rates of the gather path (Theorem 1 flops
+// per second, ridge workload) and of the matrix-core product M Vmat N^T
+// (complete data, 4096 x 2048), and the output-tile count at which a GEMM
+// keeps the matrix cores busy (from the ridge workload's shapes, 64 tiles).
+constexpr double kGatherRateF64 = 8.45e+12;
+constexpr double kGatherRateF32 = 1.15e+13;
+constexpr double kTilesRateF64 = 4.46e+13;
+constexpr double kTilesRateF32 = 1.03e+14;
+constexpr double kTilesFull = 131.3;
 // Batched CG with FP32 products: a problem whose active systems all have
 // recurrence residuals below this level continues with FP64 products
 // (GVT_F32_SWITCH overrides; 0 keeps FP32 products until certification).

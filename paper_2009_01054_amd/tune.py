@@ -20,8 +20,9 @@ This script sweeps these knobs on synthetic workloads shaped like the
 library's benchmarks, through the library's environment overrides
 (GVT_STAGE1_WIDE, GVT_STAGE1_KPW, GVT_STAGE2_TARGET_R1, GVT_STAGE2_TARGET_R8,
 GVT_MAX_RHS_BLOCK_F64, GVT_MAX_RHS_BLOCK_F32; all are read when a plan is built),
-and writes the winners as a C++
-header that ``build.py`` compiles into the library:
+measures the rates of the dense-tile cost model (gather path against matrix-core
+products), and writes the winners and rates as a C++ header that ``build.py``
+compiles into the library:
 
     python -m paper_2009_01054_amd.tune --out paper_2009_01054_amd/csrc/tuning.h
 
@@ -99,8 +100,8 @@ def ridge_products(gvt, W, torch, nrhs, reps):
 
 def batched_iterations(gvt, W, torch, nprob, prec="f32"):
     """Workload: per-iteration time of the batched ridge solver (FP32 or FP64
-    products) on the first `nprob` problems of the 256-problem set (difference
-    of two capped solves)."""
+    products) on the first `nprob` problems of the 256-problem set (median of
+    three differences of two capped solves)."""
     dev = torch.device("cuda:0")
     shapes = W.config5_shapes()[:nprob]
     probs = [W.config5_problem(i, sh) for i, sh in enumerate(shapes)]
@@ -117,10 +118,65 @@ def batched_iterations(gvt, W, torch, nprob, prec="f32"):
         return time.perf_counter() - t0
 
     def run():
+        # median of three differences: one slow short solve would otherwise
+        # read as a fast iteration
         solve(3)
-        return (solve(19) - solve(3)) / 16 * 1e3
+        d = sorted((solve(19) - solve(3)) / 16 * 1e3 for _ in range(3))
+        return d[1]
 
     return [(f"batched {prec} ({nprob} problems, 8 RHS), per iteration", run)]
+
+
+def cost_model(gvt, W, torch, reps):
+    """Rates of the dense-tile cost model (tuning.h): the gather path's Theorem 1 flops per
+    second on the ridge products; the matrix-core rate of the complete-data product on a
+    4096 x 2048 grid; and the output-tile count at which a GEMM keeps the matrix cores busy,
+    from the dense product of the ridge workload's shapes (2000 x 500 outputs, 64 tiles of
+    128 x 128 per GEMM): rate(64 tiles) = full rate x 64 / kTilesFull."""
+    dev = torch.device("cuda:0")
+    p = W.config2()
+    c, e = torch.from_numpy(p["c"]).to(dev), torch.from_numpy(p["e"]).to(dev)
+    n = len(p["c"])
+    rng = W.rng_for(4, 2)
+    m, q = 4096, 2048
+    Dm = torch.from_numpy(W.gaussian_kernel(rng.standard_normal((m, 32)))).to(dev)
+    Tq = torch.from_numpy(W.gaussian_kernel(rng.standard_normal((q, 32)))).to(dev)
+    Vm = torch.from_numpy(rng.standard_normal((m, q))).to(dev)
+    Vr = torch.from_numpy(rng.standard_normal((2000, 500))).to(dev)
+    out, tiles_full = {}, []
+    for name, dt, pc in [("F64", torch.float64, gvt.F64), ("F32", torch.float32, gvt.F32)]:
+        D, T = torch.from_numpy(p["D"]).to(dev, dt), torch.from_numpy(p["T"]).to(dev, dt)
+        v = torch.randn(n, dtype=dt, device=dev)
+        plan = gvt.gvt_plan_create("kronecker", D.shape, T.shape, (c, e), (c, e),
+                                   flags=gvt.FLAG_SYMMETRIC_BASES | gvt.FLAG_NO_DENSE_TILES)
+        cost = gvt.gvt_plan_info(plan)["cost_fma"]
+        ms = _events_ms(torch, lambda: plan.execute(D, T, v), reps)
+        plan.close()
+        out[f"kGatherRate{name}"] = 2.0 * cost / (ms * 1e-3)
+        Dd, Td, Vd = Dm.to(dt), Tq.to(dt), Vm.to(dt)
+        ms = _events_ms(torch, lambda: gvt.gvt_dense_matvec(Dd, Td, Vd, prec=pc), max(2, reps // 4))
+        full = 2.0 * (m * m * q + m * q * q) / (ms * 1e-3)
+        out[f"kTilesRate{name}"] = full
+        Vs = Vr.to(dt)
+        ms = _events_ms(torch, lambda: gvt.gvt_dense_matvec(D, T, Vs, prec=pc), reps)
+        small = 2.0 * (2000 * 2000 * 500 + 2000 * 500 * 500) / (ms * 1e-3)
+        tiles_full.append(64.0 * full / small)
+        _log(f"[tune] cost model {name}: gather {out[f'kGatherRate{name}'] / 1e12:.2f} TFLOP/s, "
+             f"dense {full / 1e12:.1f} TFLOP/s, ridge-shape dense {small / 1e12:.1f} TFLOP/s")
+    out["kTilesFull"] = max(64.0, math.sqrt(tiles_full[0] * tiles_full[1]))
+    return out
+
+
+# Not swept (a full batched solve per candidate): the residual level below which a
+# batched FP32-product problem moves to FP64 products, with the measurement behind it.
+F32_SWITCH = ("0.0", [
+    "Batched CG with FP32 products: a problem whose active systems all have",
+    "recurrence residuals below this level continues with FP64 products",
+    "(GVT_F32_SWITCH overrides; 0 keeps FP32 products until certification).",
+    "Measured on the 256-problem workload: switching at 1e-2, 1e-3 or 1e-4 took",
+    "6.39, 5.48 and 5.18 s against 4.97 s without, and converged 1532, 1537 and",
+    "1536 systems against 1536: the systems FP32 products miss are those FP64",
+    "products converge only in the last 10% of the iteration cap."])
 
 
 def sweep(cls, candidates, workloads):
@@ -141,7 +197,7 @@ def sweep(cls, candidates, workloads):
     return winner, table, score
 
 
-def write_header(path, results, device):
+def write_header(path, results, device, rates):
     lines = ["// Tuned launch shapes: stage-2 tile targets (outputs per group row per tile) for",
              "// each RHS class, and the keys each wave walks in stage 1.",
              "// Written by paper_2009_01054_amd/tune.py on " + device + "; measured times (ms):"]
@@ -157,7 +213,17 @@ def write_header(path, results, device):
               f"constexpr int kStage1Wide = {int(results['WIDE'][0])};",
               f"constexpr int kMaxRhsBlockF64 = {int(results['MAXR64'][0])};",
               f"constexpr int kMaxRhsBlockF32 = {int(results['MAXR32'][0])};",
-              "}  // namespace gvt", ""]
+              "// Dense-tile cost model: effective rates of the gather path (Theorem 1 flops",
+              "// per second, ridge workload) and of the matrix-core product M Vmat N^T",
+              "// (complete data, 4096 x 2048), and the output-tile count at which a GEMM",
+              "// keeps the matrix cores busy (from the ridge workload's shapes, 64 tiles).",
+              f"constexpr double kGatherRateF64 = {rates['kGatherRateF64']:.3g};",
+              f"constexpr double kGatherRateF32 = {rates['kGatherRateF32']:.3g};",
+              f"constexpr double kTilesRateF64 = {rates['kTilesRateF64']:.3g};",
+              f"constexpr double kTilesRateF32 = {rates['kTilesRateF32']:.3g};",
+              f"constexpr double kTilesFull = {rates['kTilesFull']:.1f};"]
+    lines += ["// " + t for t in F32_SWITCH[1]]
+    lines += [f"constexpr double kF32SwitchRelres = {F32_SWITCH[0]};", "}  // namespace gvt", ""]
     with open(path, "w") as f:
         f.write("\n".join(lines))
 
@@ -199,7 +265,8 @@ def main():
         if key.startswith("MAXR") or key == "WIDE":
             _set_target(cls, winner)  # the later sweeps run with the chosen walk and block caps
         _log(f"[tune] class {key}: target {winner:g}")
-    write_header(args.out, results, device)
+    rates = cost_model(gvt, W, torch, args.reps)
+    write_header(args.out, results, device, rates)
     print(f"wrote {args.out}: stage-1 keys per wave {results['KPW'][0]}, R1 target {results['R1'][0]:g}, "
           f"largest RHS block F64 {results['MAXR64'][0]} / F32 {results['MAXR32'][0]}, "
           f"R8 target {results['R8'][0]:g}")
