@@ -195,27 +195,37 @@ __global__ __launch_bounds__(MB) void mr_update_kernel(double *__restrict__ v, d
                                                        const MrShared *sho, MrShared *shn,
                                                        const MrSys *so, MrSys *sn, double *__restrict__ x,
                                                        double *__restrict__ d1, double *__restrict__ d2) {
+  // (elementwise after the fold: any grid; the fold reads the MNB partials)
   __shared__ double sh[MB / 64];
   __shared__ MrSys st[64];
+  __shared__ double sdl[64], sep[64], sig[64], stau[64];
+  __shared__ int son[64];
   const double beta_next = sqrt(mr_fold(part_b, sh));
   const double alpha = *alpha_in, beta = sho->beta;
   if (threadIdx.x < nlam) {
     const int l = threadIdx.x;
     MrSys s = so[l];
-    if (s.state == MR_ACTIVE) mr_givens(so[l], s, alpha + lam[l], beta, beta_next);
+    const bool was = s.state == MR_ACTIVE;
+    if (was) mr_givens(so[l], s, alpha + lam[l], beta, beta_next);
     st[l] = s;
+    son[l] = was && s.state == MR_ACTIVE;
+    sdl[l] = s.delta;
+    sep[l] = s.eps;
+    sig[l] = s.gamma;
+    stau[l] = s.tau;
   }
   __syncthreads();
   const double ib = beta_next > 0.0 ? 1.0 / beta_next : 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * MB + threadIdx.x; i < n; i += (int64_t)MNB * MB) {
+  for (int64_t i = (int64_t)blockIdx.x * MB + threadIdx.x; i < n; i += (int64_t)gridDim.x * MB) {
     const double vi = v[i];
     for (int l = 0; l < nlam; ++l) {
-      if (so[l].state != MR_ACTIVE || st[l].state != MR_ACTIVE) continue;
+      if (!son[l]) continue;
       const int64_t o = i + (int64_t)l * n;
-      const double dk = (vi - st[l].delta * d1[o] - st[l].eps * d2[o]) / st[l].gamma;
-      d2[o] = d1[o];
+      const double a1 = d1[o];
+      const double dk = (vi - sdl[l] * a1 - sep[l] * d2[o]) / sig[l];
+      d2[o] = a1;
       d1[o] = dk;
-      x[o] += st[l].tau * dk;
+      x[o] += stau[l] * dk;
     }
     const double vn = q[i] * ib;
     vprev[i] = vi;
@@ -235,24 +245,37 @@ __global__ __launch_bounds__(MB) void mr_val_kernel(const TW *__restrict__ wv, i
                                                     const MrSys *so, const MrSys *sn,
                                                     double *__restrict__ pd1, double *__restrict__ pd2,
                                                     double *__restrict__ pv) {
-  for (int64_t i = (int64_t)blockIdx.x * MB + threadIdx.x; i < nv; i += (int64_t)MNB * MB) {
+  __shared__ double sdl[64], sep[64], sig[64], stau[64];
+  __shared__ int son[64];
+  if (threadIdx.x < nlam) {
+    const int l = threadIdx.x;
+    son[l] = so[l].state == MR_ACTIVE && sn[l].state == MR_ACTIVE;
+    sdl[l] = sn[l].delta;
+    sep[l] = sn[l].eps;
+    sig[l] = sn[l].gamma;
+    stau[l] = sn[l].tau;
+  }
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * MB + threadIdx.x; i < nv; i += (int64_t)gridDim.x * MB) {
     const double w = (double)wv[i];
     for (int l = 0; l < nlam; ++l) {
-      if (so[l].state != MR_ACTIVE || sn[l].state != MR_ACTIVE) continue;
+      if (!son[l]) continue;
       const int64_t o = i + (int64_t)l * nv;
-      const double dk = (w - sn[l].delta * pd1[o] - sn[l].eps * pd2[o]) / sn[l].gamma;
-      pd2[o] = pd1[o];
+      const double a1 = pd1[o];
+      const double dk = (w - sdl[l] * a1 - sep[l] * pd2[o]) / sig[l];
+      pd2[o] = a1;
       pd1[o] = dk;
-      pv[o] += sn[l].tau * dk;
+      pv[o] += stau[l] * dk;
     }
   }
 }
 
-// Pair counts for the AUC, for every system: 2 x #(pos > neg) + #(pos == neg)
-// over (positive, negative) pairs.  The negatives' predictions of each system
-// are gathered and sorted (one segment per system); each positive then counts
-// the negatives below it and the ties by two binary searches.  Integer counts,
-// exact whatever the order of anything.
+// lab[q] = q / div (the system of gathered negative q)
+__global__ void mr_iota_div_kernel(int32_t *__restrict__ lab, int64_t n, int64_t div) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) lab[q] = (int32_t)(q / div);
+}
+
 __global__ void mr_gather_neg_kernel(const double *__restrict__ pv, int64_t nv, int nlam,
                                      const int32_t *__restrict__ neg, int64_t nneg, double *__restrict__ out) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -396,6 +419,8 @@ struct PlanHolder {
   }
 };
 dim3 mg1(int64_t n) { return dim3((unsigned)ceil_div(std::max<int64_t>(n, 1), 256)); }
+// elementwise kernels of MB threads, one element per thread (capped grid-stride)
+dim3 mgrid(int64_t n) { return dim3((unsigned)std::min<int64_t>(ceil_div(std::max<int64_t>(n, 1), MB), 8192)); }
 }  // namespace
 
 int krr_minres_impl(int kind, const double *D, int64_t d, int64_t ldd, const double *T, int64_t t,
@@ -485,6 +510,10 @@ int krr_minres_impl(int kind, const double *D, int64_t d, int64_t ldd, const dou
   double *gneg = nullptr, *sneg = nullptr;
   char *stemp = nullptr;
   size_t sort_bytes = 0;
+  double *kneg = nullptr;                                   // negatives sorted by value (all systems)
+  int32_t *lab1 = nullptr, *lab2 = nullptr, *lab3 = nullptr;  // system index per gathered negative
+  int sys_bits = 1;
+  while ((1 << sys_bits) < nlam) ++sys_bits;
   const int64_t auc_blocks = std::max<int64_t>(1, ceil_div(npos, MB));
   if (have_val) {
     wv = (double *)m_wv.ensure(nv * 8);
@@ -499,16 +528,29 @@ int krr_minres_impl(int kind, const double *D, int64_t d, int64_t ldd, const dou
     if (npos) GVT_HIP_CHECK(hipMemcpyAsync(dpos, hpos.data(), npos * 4, hipMemcpyHostToDevice, s));
     if (nneg) GVT_HIP_CHECK(hipMemcpyAsync(dneg, hneg.data(), nneg * 4, hipMemcpyHostToDevice, s));
     cnt = (unsigned long long *)m_cnt.ensure((size_t)auc_blocks * nlam * 8);
-    // sorted negatives: gathered predictions, their sorted copy, sort temp
+    // sorted negatives of every system: the gathered predictions sorted once by
+    // value (the system index riding along), then stably by system index, so
+    // each system's run is its negatives in the order a sort of that system
+    // alone gives (two sorts in place of one per system)
     const int64_t nn2 = std::max<int64_t>(nneg * nlam, 1);
-    size_t tb = 0;
-    GVT_HIP_CHECK(hipcub::DeviceRadixSort::SortKeys(nullptr, tb, (const double *)nullptr, (double *)nullptr,
-                                                    (int)std::max<int64_t>(nneg, 1), 0, 64, s));
-    sort_bytes = tb;
-    char *sb = (char *)m_sort.ensure((size_t)nn2 * 16 + 256 + tb);
+    size_t tb1 = 0, tb2 = 0;
+    GVT_HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb1, (const double *)nullptr, (double *)nullptr,
+                                                     (const int32_t *)nullptr, (int32_t *)nullptr, (int)nn2, 0,
+                                                     64, s));
+    GVT_HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb2, (const int32_t *)nullptr, (int32_t *)nullptr,
+                                                     (const double *)nullptr, (double *)nullptr, (int)nn2, 0,
+                                                     sys_bits, s));
+    sort_bytes = std::max(tb1, tb2);
+    const size_t arrays = ((size_t)nn2 * 36 + 255) / 256 * 256;
+    char *sb = (char *)m_sort.ensure(arrays + sort_bytes + 256);
     gneg = (double *)sb;
     sneg = gneg + nn2;
-    stemp = sb + (size_t)nn2 * 16 + 256;
+    kneg = sneg + nn2;
+    lab1 = (int32_t *)(kneg + nn2);
+    lab2 = lab1 + nn2;
+    lab3 = lab2 + nn2;
+    stemp = sb + arrays;
+    mr_iota_div_kernel<<<mg1(nn2), 256, 0, s>>>(lab1, nn2, std::max<int64_t>(nneg, 1));
   }
   double *hist_dev = nullptr;
   DevMem m_hist;
@@ -551,21 +593,21 @@ int krr_minres_impl(int kind, const double *D, int64_t d, int64_t ldd, const dou
       else plan_execute(PV, GVT_F64, D, ldd, T, ldt, v, 1, n, wv, nv, s);
     }
     mr_beta_kernel<<<MNB, MB, 0, s>>>(v, n, part, q, part_b, alpha);
-    mr_update_kernel<<<MNB, MB, 0, s>>>(v, vprev, v32, q, n, nlam, lam, alpha, part_b, sho, shn, so, sn, x, d1,
+    mr_update_kernel<<<mgrid(n), MB, 0, s>>>(v, vprev, v32, q, n, nlam, lam, alpha, part_b, sho, shn, so, sn, x, d1,
                                         d2);
     if (have_val) {
       if (lowprec)
-        mr_val_kernel<float><<<MNB, MB, 0, s>>>(wv32, nv, nlam, so, sn, pd1, pd2, pvv);
+        mr_val_kernel<float><<<mgrid(nv), MB, 0, s>>>(wv32, nv, nlam, so, sn, pd1, pd2, pvv);
       else
-        mr_val_kernel<double><<<MNB, MB, 0, s>>>(wv, nv, nlam, so, sn, pd1, pd2, pvv);
+        mr_val_kernel<double><<<mgrid(nv), MB, 0, s>>>(wv, nv, nlam, so, sn, pd1, pd2, pvv);
       if (nneg > 0) {
         mr_gather_neg_kernel<<<mg1(nneg * nlam), 256, 0, s>>>(pvv, nv, nlam, dneg, nneg, gneg);
-        // one device-wide sort per system (a segmented sort gives each segment one workgroup)
-        for (int l = 0; l < nlam; ++l) {
-          size_t tb = sort_bytes;
-          GVT_HIP_CHECK(hipcub::DeviceRadixSort::SortKeys(stemp, tb, gneg + (int64_t)l * nneg,
-                                                          sneg + (int64_t)l * nneg, (int)nneg, 0, 64, s));
-        }
+        // (a segmented sort would give each system's run one workgroup)
+        const int nn2 = (int)(nneg * nlam);
+        size_t tb = sort_bytes;
+        GVT_HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(stemp, tb, gneg, kneg, lab1, lab2, nn2, 0, 64, s));
+        tb = sort_bytes;
+        GVT_HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(stemp, tb, lab2, lab3, kneg, sneg, nn2, 0, sys_bits, s));
       }
       mr_auc_kernel<<<(unsigned)auc_blocks, MB, 0, s>>>(pvv, nv, nlam, dpos, npos, sneg, nneg, so, cnt);
     }
