@@ -286,8 +286,13 @@ __global__ void colscale_kernel(const T *__restrict__ F, int64_t ldf, const int3
 // tiles of 32 consecutive F1 rows x one block of at most 64 S rows, orders
 // the outputs by (tile, x, S row), and numbers the tiles so that the S-row
 // block index is the fastest-varying digit.  Workgroups are dealt to the
-// eight XCDs round-robin, so with a multiple of eight S-row blocks each XCD
-// only ever touches its own slice of S, which then stays in that XCD's L2.
+// eight XCDs round-robin by id; the kernel remaps ids so that XCD x runs the
+// F1 blocks x, x + 8, ..., each with all its S blocks in turn: an XCD reads
+// one eighth of F1 once, and its tiles in flight walk the key chunks of all
+// of S together, so S is shared through L2 (ridge workload, FP64: 100 MB
+// fetched per launch against 266 MB when each XCD owned one S block and
+// streamed all of F1, and 64 against 68-70 us).  GVT_STAGE2_XCD=0 restores
+// the S-block order.
 // Inside a tile one 16-lane group owns one F1 row: it holds that row's slice
 // of the current key chunk in registers (loaded once per chunk) and walks
 // its outputs, reading the S rows from a shared LDS tile (one 1 KB chunk per
@@ -479,11 +484,22 @@ __global__ __launch_bounds__(kStage2Rows * 16) void stage2_kernel(
     const int32_t *__restrict__ tiley, const int32_t *__restrict__ tilemax,
     const uint8_t *__restrict__ grow, const int32_t *__restrict__ yrows,
     const int32_t *__restrict__ perm, int nyb, const T *__restrict__ S, int64_t ldS, int64_t nkeys,
-    T coef, T *__restrict__ out, int64_t ldi, int64_t ldr, const int *__restrict__ gate) {
+    T coef, T *__restrict__ out, int64_t ldi, int64_t ldr, const int *__restrict__ gate, int nxb,
+    int by_f1) {
   __shared__ S2Smem<T, R> sm;
   if (gate && *gate == 0) return;
+  int t = blockIdx.x;
+  if (by_f1) {
+    // workgroups go to the 8 XCDs round-robin by id: XCD x runs the F1 blocks
+    // xb = x (mod 8), each with all its S blocks in turn (F1 blocks padded to a
+    // multiple of 8; padding tiles return at once)
+    const int x = t & 7, k = t >> 3;
+    const int xb = (k / nyb) * 8 + x, yb = k % nyb;
+    if (xb >= nxb) return;
+    t = xb * nyb + yb;
+  }
   stage2_tile<T, R>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef,
-                    out, ldi, ldr, blockIdx.x, sm);
+                    out, ldi, ldr, t, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1001,13 +1017,18 @@ void launch_stage2(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff,
                    const int32_t *yrows, const int32_t *perm, const T *S, int64_t ldS, int64_t nkeys,
                    int R, T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s, const int *gate) {
   if (ntiles <= 0) return;
-  dim3 grid((unsigned)ntiles);
+  static const int by_f1 = [] {
+    const char *ev = std::getenv("GVT_STAGE2_XCD");
+    return ev ? std::atoi(ev) : 1;
+  }();
+  const int nxb = (int)(ntiles / nyb);
+  dim3 grid((unsigned)(by_f1 ? (int64_t)ceil_div(nxb, 8) * 8 * nyb : ntiles));
   const int nt = S2Cfg<T, 1>::NT;
   switch (R) {
-    case 1: stage2_kernel<T, 1><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
-    case 2: stage2_kernel<T, 2><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
-    case 4: stage2_kernel<T, 4><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
-    case 8: stage2_kernel<T, 8><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate); break;
+    case 1: stage2_kernel<T, 1><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate, nxb, by_f1); break;
+    case 2: stage2_kernel<T, 2><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate, nxb, by_f1); break;
+    case 4: stage2_kernel<T, 4><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate, nxb, by_f1); break;
+    case 8: stage2_kernel<T, 8><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate, nxb, by_f1); break;
     default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in stage 2"};
   }
 }

@@ -187,8 +187,9 @@ namespace {
 //  class 1 (4-8 RHS): groups of kStage2Rows consecutive compact S rows x
 //    blocks of F1 rows staged in LDS; per output the F1 row.
 // The staged block is at most stage2_block_rows() rows high; more than four
-// blocks are rounded up to a multiple of 8 so that each XCD keeps one slice
-// of the staged matrix in its L2.  One stable counting sort on (tile, group
+// blocks are rounded up to a multiple of 8, so that in class 1 each XCD keeps
+// one slice of the staged matrix in its L2 (class 0 assigns XCDs by F1 block
+// at launch; the padding blocks are empty tiles).  One stable counting sort on (tile, group
 // row) orders the outputs; the order inside a group row does not matter.
 // With `up` the arrays join the plan's upload, else they are copied into the
 // tile set's own allocation at once.
