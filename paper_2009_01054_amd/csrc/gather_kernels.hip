@@ -291,8 +291,11 @@ __global__ void colscale_kernel(const T *__restrict__ F, int64_t ldf, const int3
 // one eighth of F1 once, and its tiles in flight walk the key chunks of all
 // of S together, so S is shared through L2 (ridge workload, FP64: 100 MB
 // fetched per launch against 266 MB when each XCD owned one S block and
-// streamed all of F1, and 64 against 68-70 us).  GVT_STAGE2_XCD=0 restores
-// the S-block order.
+// streamed all of F1, and 64 against 68-70 us).  S is then re-read once per
+// F1 block, which the memory-side cache serves while F1 and S fit in it; past
+// that the launch keeps the S-block order (fused four-kind FP64 product at
+// m = 5000: 400 MB, stage 2 4.36 against 4.84 ms by F1 block).
+// GVT_STAGE2_XCD=0 / 1 forces either order.
 // Inside a tile one 16-lane group owns one F1 row: it holds that row's slice
 // of the current key chunk in registers (loaded once per chunk) and walks
 // its outputs, reading the S rows from a shared LDS tile (one 1 KB chunk per
@@ -910,7 +913,12 @@ static void stage1_rk(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nro
 // read when a plan is built, not per launch.
 static std::atomic<int> g_s1_kpw{kStage1KeysPerWave}, g_s1_wide{kStage1Wide};
 
+// Stage-2 XCD order: -1 chosen per launch, 0 by S block, 1 by F1 block (GVT_STAGE2_XCD).
+static std::atomic<int> g_s2_xcd{-1};
+
 void refresh_launch_knobs() {
+  const char *e5 = std::getenv("GVT_STAGE2_XCD");
+  g_s2_xcd.store(e5 ? (std::atoi(e5) != 0) : -1, std::memory_order_relaxed);
   const char *e1 = std::getenv("GVT_STAGE1_KPW");
   const int k = e1 ? std::atoi(e1) : kStage1KeysPerWave;
   g_s1_kpw.store((k == 1 || k == 2 || k == 4) ? k : 4, std::memory_order_relaxed);
@@ -1014,13 +1022,16 @@ void launch_colscale(const T *F, int64_t ldf, const int32_t *rows, int64_t nrows
 template <class T>
 void launch_stage2(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff, const int32_t *tiley,
                    const int32_t *tilemax, const uint8_t *grow, int64_t ntiles, int nyb,
-                   const int32_t *yrows, const int32_t *perm, const T *S, int64_t ldS, int64_t nkeys,
-                   int R, T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s, const int *gate) {
+                   const int32_t *yrows, const int32_t *perm, const T *S, int64_t ldS, int64_t nsrows,
+                   int64_t nkeys, int R, T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s,
+                   const int *gate) {
   if (ntiles <= 0) return;
-  static const int by_f1 = [] {
-    const char *ev = std::getenv("GVT_STAGE2_XCD");
-    return ev ? std::atoi(ev) : 1;
-  }();
+  // XCDs by F1 block re-read S once per F1 block: from the memory-side cache
+  // while F1 and S fit in it together, from HBM otherwise, where XCDs by S
+  // block (each keeping its slice of S) cost less
+  const int xo = g_s2_xcd.load(std::memory_order_relaxed);
+  const double bytes = (double)sizeof(T) * ((double)nx * (double)nkeys + (double)nsrows * (double)ldS);
+  const int by_f1 = xo >= 0 ? xo : bytes <= kMallBytes;
   const int nxb = (int)(ntiles / nyb);
   dim3 grid((unsigned)(by_f1 ? (int64_t)ceil_div(nxb, 8) * 8 * nyb : ntiles));
   const int nt = S2Cfg<T, 1>::NT;
@@ -1165,8 +1176,8 @@ void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64
   template void launch_stage2<T>(const T *, int64_t, int64_t, const int64_t *, const int32_t *,  \
                                  const int32_t *, const uint8_t *, int64_t, int, const int32_t *,\
                                  const int32_t *,                                                \
-                                 const T *, int64_t, int64_t, int, T, T *, int64_t, int64_t,     \
-                                 hipStream_t, const int *);                                      \
+                                 const T *, int64_t, int64_t, int64_t, int, T, T *, int64_t,     \
+                                 int64_t, hipStream_t, const int *);                             \
   template void launch_stage2y<T>(const T *, int64_t, const int64_t *, const int32_t *,          \
                                   const int32_t *, const uint8_t *, int64_t, int,                 \
                                   const int32_t *, const int32_t *,                               \

@@ -10,6 +10,7 @@ constexpr int kMaxCombineTerms = 16;
 constexpr int kStage2Rows = 32;
 constexpr int kStage2MaxS = 64;
 constexpr double kL2BytesPerXcd = 4.0 * 1024 * 1024;  // gfx950: 4 MB of L2 per XCD
+constexpr double kMallBytes = 256.0 * 1024 * 1024;    // MI355X: 256 MB memory-side cache
 constexpr int kMaxCombineOut = 8;
 
 // Row stride (elements) of a stage-1 buffer: nkeys x R values padded to whole
@@ -53,8 +54,8 @@ void launch_colscale(const T *F, int64_t ldf, const int32_t *rows, int64_t nrows
 template <class T>
 void launch_stage2(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff, const int32_t *tiley,
                    const int32_t *tilemax, const uint8_t *grow, int64_t ntiles, int nyb,
-                   const int32_t *yrows, const int32_t *perm, const T *S, int64_t ldS, int64_t nkeys,
-                   int R, T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s,
+                   const int32_t *yrows, const int32_t *perm, const T *S, int64_t ldS, int64_t nsrows,
+                   int64_t nkeys, int R, T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s,
                    const int *gate = nullptr);
 // Stage 2 with S-row grouped tiles (blocks of R = 4 or 8 RHS).
 template <class T>

@@ -187,10 +187,11 @@ namespace {
 //  class 1 (4-8 RHS): groups of kStage2Rows consecutive compact S rows x
 //    blocks of F1 rows staged in LDS; per output the F1 row.
 // The staged block is at most stage2_block_rows() rows high; more than four
-// blocks are rounded up to a multiple of 8, so that in class 1 each XCD keeps
-// one slice of the staged matrix in its L2 (class 0 assigns XCDs by F1 block
-// at launch; the padding blocks are empty tiles).  One stable counting sort on (tile, group
-// row) orders the outputs; the order inside a group row does not matter.
+// blocks are rounded up to a multiple of 8, so that an XCD can keep one slice
+// of the staged matrix in its L2 (always in class 1; class 0 picks the order
+// at launch, by F1 block or by S block; the padding blocks are empty tiles).
+// One stable counting sort on (tile, group row) orders the outputs; the order
+// inside a group row does not matter.
 // With `up` the arrays join the plan's upload, else they are copied into the
 // tile set's own allocation at once.
 struct TileHost {
@@ -1024,9 +1025,8 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
         launch_stage2<T>(F[t.fdot], ldF[t.fdot], rows_of(P, t.fdot), tl.tileoff.as<int64_t>(),
                          tl.tiley.as<int32_t>(), tl.tilemax.as<int32_t>(), tl.grow.as<uint8_t>(),
                          tl.ntiles, tl.nyb, tl.yrows.as<int32_t>(), tl.perm.as<int32_t>(),
-                         wsp<T>(P, W.sbuf[t.sbuf]),
-                         sbuf_ld<T>(P, t.sbuf, R), nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s,
-                         P->gate);
+                         wsp<T>(P, W.sbuf[t.sbuf]), sbuf_ld<T>(P, t.sbuf, R), (int64_t)sb.rows.size(),
+                         nkeys_of(P, sb.key), R, T(1), out, ldi, ldr, s, P->gate);
       else
         launch_stage2y<T>(F[t.fdot], ldF[t.fdot], tl.tileoff.as<int64_t>(), tl.tiley.as<int32_t>(),
                           tl.tilemax.as<int32_t>(), tl.grow.as<uint8_t>(), tl.ntiles, tl.nyb,

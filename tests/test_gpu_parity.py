@@ -606,6 +606,33 @@ def test_stage1_wide_xcd_order_bitwise(gvt, prec, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("m,q", [(700, 300), (33, 900), (300, 40), (5, 700)])
+@pytest.mark.parametrize("order", [2, 4])
+def test_stage2_xcd_orders_bitwise(gvt, prec, m, q, order, monkeypatch):
+    # the stage-2 tiles dealt to the XCDs by F1 block and by S block: each tile writes its
+    # own outputs, so both orders give the same bits; F1-block counts that are not a
+    # multiple of 8 (padding workgroups return at once), S-block counts of 1-4 and past 4
+    # (padded to a multiple of 8), one and two RHS per pass
+    r = np.random.default_rng([11, m, q, order])
+    dt = torch.float64 if prec == "f64" else torch.float32
+    D = W.gaussian_kernel(r.standard_normal((m, 3)))
+    T = W.gaussian_kernel(r.standard_normal((q, 3)))
+    c = r.integers(0, m, 30000).astype(np.int32)
+    e = r.integers(0, q, 30000).astype(np.int32)
+    a = r.integers(0, m, 20000).astype(np.int32)
+    b = r.integers(0, q, 20000).astype(np.int32)
+    Dd, Td = dev(D, dt), dev(T, dt)
+    for nrhs in (1, 2, 3):
+        v = dev(r.standard_normal((len(c), nrhs)), dt)
+        args = ((idx(a), idx(b)), (idx(c), idx(e)), v)
+        monkeypatch.setenv("GVT_STAGE2_XCD", "0")
+        ref = gvt.gvt_pairwise_matvec(["kronecker"], Dd, Td, *args, flags=order)
+        monkeypatch.setenv("GVT_STAGE2_XCD", "1")
+        got = gvt.gvt_pairwise_matvec(["kronecker"], Dd, Td, *args, flags=order)
+        assert torch.equal(got, ref), nrhs
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("lo,hi", [(0, 700), (3, 600), (2, 403), (5, 8), (4, 6), (1, 5), (1, 2)])
 @pytest.mark.parametrize("order", [2, 4])
 @pytest.mark.parametrize("gaps", [False, True])
