@@ -8,8 +8,10 @@
 // sum is a sequential loop or a fixed lane tree: results are deterministic
 // (no atomics).  Several right-hand sides (R) ride along in the innermost
 // dimension so that each gathered base-matrix element feeds R FMAs.
+#include <algorithm>
 #include <atomic>
 #include <cstdlib>
+#include <mutex>
 
 #include "common.h"
 #include "kernels.h"
@@ -328,6 +330,192 @@ __device__ __forceinline__ int wave_max_of_groups(int x) {
   x = max(x, __shfl_xor(x, 16));
   x = max(x, __shfl_xor(x, 32));
   return __builtin_amdgcn_readfirstlane(x);
+}
+
+// Stage 1 with a slice of F2 resident in LDS.  A workgroup owns RB = 16 x VPL
+// consecutive S rows, 256 bytes of each F2 column, and first copies those rows
+// of every column into LDS (column o at byte 256 o); it then walks the
+// segments of a range of keys.  Each 16-lane group of a wave walks one key, so
+// a wave has four keys in flight: the group's lanes load the (other, v) of 16
+// consecutive pairs, and at each step a DPP row broadcast hands every lane of
+// the group that pair's column and v; the lane reads its VPL rows of the
+// column with one 16-byte LDS read and accumulates.  Operand bytes come from
+// LDS instead of through the vector-memory path, which bounds the walks that
+// load a column slice per pair.  Each (row, key) sum runs over the segment in
+// order, as in the other walks, so all of them agree bit for bit (steps past
+// a segment's end add F2 x 0, which leaves a finite sum unchanged).  The last
+// row block starts nrows - RB rows in, so no copy leaves the rows the buffer
+// needs; its lanes keep only the rows past the previous block.
+template <class T> struct S1SliceCfg {
+  static constexpr int VPL = 16 / sizeof(T);  // rows per lane
+  static constexpr int RB = 16 * VPL;         // rows per block: 256 bytes of a column
+  static constexpr int NW = 16;               // waves per workgroup
+  static constexpr int NT = 64 * NW;
+};
+// Largest number of F2 columns whose slices fit in LDS.
+constexpr int64_t kS1SliceMaxCols = 600;
+
+// value of lane s of this lane's 16-lane row (DPP row_newbcast)
+template <int S> __device__ __forceinline__ int row_bcast(int x) {
+  return __builtin_amdgcn_mov_dpp(x, 0x150 + S, 0xf, 0xf, false);
+}
+template <int S> __device__ __forceinline__ float row_bcast(float x) {
+  return __int_as_float(row_bcast<S>(__float_as_int(x)));
+}
+// 64-bit values move in one DPP instruction (gfx90a and later allow row_newbcast on them)
+template <int S> __device__ __forceinline__ long long row_bcast(long long x) {
+  return __builtin_amdgcn_update_dpp(0LL, x, 0x150 + S, 0xf, 0xf, false);
+}
+template <int S> __device__ __forceinline__ double row_bcast(double x) {
+  return __longlong_as_double(row_bcast<S>(__double_as_longlong(x)));
+}
+
+template <class T, int R>
+__global__ __launch_bounds__(S1SliceCfg<T>::NT) void stage1_slice_kernel(
+    const T *__restrict__ Fc, int64_t ldc, int64_t row0, int64_t nrows,
+    const int64_t *__restrict__ seg, const int32_t *__restrict__ other, const T *__restrict__ vs,
+    int64_t nkeys, int64_t nother, T *__restrict__ S, int64_t ldS, int64_t kpr,
+    const int *__restrict__ gate) {
+  typedef S1SliceCfg<T> C;
+  typedef typename Vec16u<T>::type VG;  // 16 bytes at T's alignment (global)
+  typedef typename Vec16<T>::type VL;   // 16-byte aligned (LDS)
+  constexpr int VPL = C::VPL, RB = C::RB;
+  constexpr bool kPackCV = sizeof(T) == 4 && R == 1;
+  extern __shared__ __attribute__((aligned(16))) unsigned char s1s_lds[];
+  if (gate && *gate == 0) return;
+  const int64_t rstart = (int64_t)blockIdx.y * RB;                      // first row stored
+  const int64_t base = rstart + RB <= nrows ? rstart : nrows - RB;     // window inside [0, nrows)
+  const int shift = (int)(rstart - base);                              // window rows before rstart
+  {
+    // piece q = 16 o + pc: 16 bytes of column o at byte 16 q; a thread's eight
+    // pieces are loaded together, then stored
+    const T *src = Fc + row0 + base;
+    const int64_t nvec = nother * 16;
+    for (int64_t q0 = threadIdx.x; q0 < nvec; q0 += 8 * C::NT) {
+      VL tmp[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t q = q0 + (int64_t)u * C::NT;
+        if (q < nvec) tmp[u] = *reinterpret_cast<const VG *>(src + (q >> 4) * ldc + (q & 15) * VPL);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t q = q0 + (int64_t)u * C::NT;
+        if (q < nvec) *reinterpret_cast<VL *>(s1s_lds + q * 16) = tmp[u];
+      }
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4, sub = lane & 15;
+  const int sub16 = sub * 16;  // this lane's 16 bytes of a column slice
+  const int wv = threadIdx.x >> 6;
+  const int64_t k0 = (int64_t)blockIdx.x * kpr;
+  const int64_t k1 = k0 + kpr < nkeys ? k0 + kpr : nkeys;
+  // segment bounds of the group's key, loaded one key quad ahead
+  int64_t s0n = 0, s1n = 0;
+  if (k0 + 4 * wv + g < k1) {
+    s0n = seg[k0 + 4 * wv + g];
+    s1n = seg[k0 + 4 * wv + g + 1];
+  }
+  for (int64_t kq = k0 + 4 * wv; kq < k1; kq += 4 * C::NW) {  // uniform
+    const int64_t k = kq + g;
+    const bool kv = k < k1;
+    const int64_t s0 = s0n, s1 = s1n;
+    if (kq + 4 * C::NW + g < k1) {
+      s0n = seg[kq + 4 * C::NW + g];
+      s1n = seg[kq + 4 * C::NW + g + 1];
+    }
+    const int maxlen = wave_max_of_groups((int)(s1 - s0));
+    T acc[VPL][R];
+#pragma unroll
+    for (int j = 0; j < VPL; ++j)
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[j][r] = T(0);
+    // the (other, v) of the group's next 16 pairs, loaded one window ahead
+    int64_t pn = s0 + sub;
+    bool inn = pn < s1;
+    int coln = inn ? other[pn] * 256 : 0;  // byte offset of the pair's column slice
+    T vln[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) vln[r] = inn ? vs[pn * R + r] : T(0);
+    for (int w0 = 0; w0 < maxlen; w0 += 16) {
+      const int col = coln;
+      T vl[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) vl[r] = vln[r];
+      if (w0 + 16 < maxlen) {  // uniform
+        pn += 16;
+        inn = pn < s1;
+        coln = inn ? other[pn] * 256 : 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) vln[r] = inn ? vs[pn * R + r] : T(0);
+      }
+      const int nst = maxlen - w0;  // uniform
+// the window's column reads are issued first (16 in flight, 8 with eight RHS), then the sums
+// (FP32 with one RHS: the column offset and v move together in one 64-bit broadcast)
+#define GVT_S1S_RD(SS)                                                                     \
+  if constexpr (kPackCV) {                                                                 \
+    const long long cv = row_bcast<SS>(colv);                                              \
+    xv[SS] = __int_as_float((int)(cv >> 32));                                              \
+    tv[SS] = *reinterpret_cast<const VL *>(s1s_lds + (int)(cv & 0xffffffffll) + sub16);    \
+  } else {                                                                                 \
+    tv[SS] = *reinterpret_cast<const VL *>(s1s_lds + row_bcast<SS>(col) + sub16);          \
+  }
+#define GVT_S1S_ACC(SS)                                                                    \
+  _Pragma("unroll") for (int r = 0; r < R; ++r) {                                          \
+    T x;                                                                                   \
+    if constexpr (kPackCV) x = xv[SS];                                                     \
+    else x = row_bcast<SS>(vl[r]);                                                         \
+    _Pragma("unroll") for (int j = 0; j < VPL; ++j) acc[j][r] += tv[SS][j] * x;            \
+  }
+#define GVT_S1S_RD4(S4) GVT_S1S_RD(S4) GVT_S1S_RD(S4 + 1) GVT_S1S_RD(S4 + 2) GVT_S1S_RD(S4 + 3)
+#define GVT_S1S_ACC4(S4) GVT_S1S_ACC(S4) GVT_S1S_ACC(S4 + 1) GVT_S1S_ACC(S4 + 2) GVT_S1S_ACC(S4 + 3)
+      VL tv[16];
+      [[maybe_unused]] T xv[16];
+      [[maybe_unused]] long long colv = 0;
+      if constexpr (kPackCV)
+        colv = ((long long)__float_as_int((float)vl[0]) << 32) | (long long)(unsigned)col;
+      if constexpr (R < 8) {
+        if (nst > 8) {  // a whole window (or most of the last one)
+          GVT_S1S_RD4(0) GVT_S1S_RD4(4) GVT_S1S_RD4(8) GVT_S1S_RD4(12)
+          GVT_S1S_ACC4(0) GVT_S1S_ACC4(4) GVT_S1S_ACC4(8) GVT_S1S_ACC4(12)
+        } else {  // the last window's first eight steps
+          GVT_S1S_RD4(0) GVT_S1S_RD4(4)
+          GVT_S1S_ACC4(0) GVT_S1S_ACC4(4)
+        }
+      } else {  // eight RHS: eight reads in flight (registers)
+        GVT_S1S_RD4(0) GVT_S1S_RD4(4)
+        GVT_S1S_ACC4(0) GVT_S1S_ACC4(4)
+        if (nst > 8) {
+          GVT_S1S_RD4(8) GVT_S1S_RD4(12)
+          GVT_S1S_ACC4(8) GVT_S1S_ACC4(12)
+        }
+      }
+#undef GVT_S1S_ACC4
+#undef GVT_S1S_RD4
+#undef GVT_S1S_ACC
+#undef GVT_S1S_RD
+    }
+    if (kv) {
+#pragma unroll
+      for (int j = 0; j < VPL; ++j) {
+        const int rr = sub * VPL + j;
+        if (rr >= shift)
+#pragma unroll
+          for (int r = 0; r < R; ++r) S[(base + rr) * ldS + k * R + r] = acc[j][r];
+      }
+    }
+  }
+  // the last key range also clears the padding columns of the block's rows
+  // (stage 2 reads S rows as whole chunks)
+  if (k1 == nkeys) {
+    const int64_t padw = ldS - nkeys * R;
+    const int64_t nr = (nrows - rstart < RB ? nrows - rstart : RB);
+    for (int64_t idx = threadIdx.x; idx < nr * padw; idx += C::NT) {
+      const int64_t rr = idx / padw, cc = idx - rr * padw;
+      S[(rstart + rr) * ldS + nkeys * R + cc] = T(0);
+    }
+  }
 }
 
 template <class T, int R> struct S2Cfg {
@@ -915,8 +1103,15 @@ static std::atomic<int> g_s1_kpw{kStage1KeysPerWave}, g_s1_wide{kStage1Wide};
 
 // Stage-2 XCD order: -1 chosen per launch, 0 by S block, 1 by F1 block (GVT_STAGE2_XCD).
 static std::atomic<int> g_s2_xcd{-1};
+// Stage 1 over an F2 slice resident in LDS where it fits (GVT_STAGE1_SLICE=0: off),
+// with about this many workgroups per launch (GVT_STAGE1_SLICE_WGS).
+static std::atomic<int> g_s1_slice{1}, g_s1_slice_wgs{256};
 
 void refresh_launch_knobs() {
+  const char *e6 = std::getenv("GVT_STAGE1_SLICE");
+  g_s1_slice.store(e6 ? (std::atoi(e6) != 0) : 1, std::memory_order_relaxed);
+  const char *e7 = std::getenv("GVT_STAGE1_SLICE_WGS");
+  g_s1_slice_wgs.store(e7 ? std::max(1, std::atoi(e7)) : 256, std::memory_order_relaxed);
   const char *e5 = std::getenv("GVT_STAGE2_XCD");
   g_s2_xcd.store(e5 ? (std::atoi(e5) != 0) : -1, std::memory_order_relaxed);
   const char *e1 = std::getenv("GVT_STAGE1_KPW");
@@ -927,6 +1122,7 @@ void refresh_launch_knobs() {
 }
 
 static int stage1_kpw() { return g_s1_kpw.load(std::memory_order_relaxed); }
+static bool stage1_use_slice() { return g_s1_slice.load(std::memory_order_relaxed) != 0; }
 static bool stage1_use_wide() { return g_s1_wide.load(std::memory_order_relaxed) != 0; }
 bool stage1_wide_enabled() { return stage1_use_wide(); }
 
@@ -984,6 +1180,47 @@ static void stage1_wide(const T *Fc, int64_t ldc, int64_t row0, int64_t nrows, c
 #undef GVT_S1W
 }
 
+// The slice walk: a grid of (key ranges, row blocks), about one workgroup per
+// CU (one fits at a time: the slices take up to 150 KB of LDS, and each
+// workgroup copies its slice once; ridge workload, FP64: 23 us with 256
+// workgroups, 26 with 512 or 1024), key ranges in whole rounds of the
+// workgroup's 64 groups where the keys allow.
+template <class T, int R>
+static void stage1_slice_r(const T *Fc, int64_t ldc, int64_t row0, int64_t nrows, const int64_t *seg,
+                           const int32_t *other, const T *vs, int64_t nkeys, int64_t nother, T *S,
+                           int64_t ldS, hipStream_t s, const int *gate) {
+  typedef S1SliceCfg<T> C;
+  const int64_t nrb = ceil_div(nrows, (int64_t)C::RB);
+  const int64_t want = std::max<int64_t>(1, ceil_div((int64_t)g_s1_slice_wgs.load(std::memory_order_relaxed), nrb));
+  const int64_t nkr = std::max<int64_t>(1, std::min<int64_t>(want, ceil_div(nkeys, (int64_t)64)));
+  const int64_t kpr = ceil_div(nkeys, nkr);
+  const size_t lds = (size_t)nother * 256;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    // allow the slices' dynamic LDS (the launch reports an error if the device has less)
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(&stage1_slice_kernel<T, R>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(kS1SliceMaxCols * 256)) != hipSuccess)
+      (void)hipGetLastError();
+  });
+  GVT_REQUIRE(nrb < 65536, GVT_ERR_ARG, "internal: too many stage-1 row blocks");
+  stage1_slice_kernel<T, R><<<dim3((unsigned)ceil_div(nkeys, kpr), (unsigned)nrb), C::NT, lds, s>>>(
+      Fc, ldc, row0, nrows, seg, other, vs, nkeys, nother, S, ldS, kpr, gate);
+}
+
+template <class T>
+static bool stage1_slice(const T *Fc, int64_t ldc, int64_t row0, int64_t nrows, const int64_t *seg,
+                         const int32_t *other, const T *vs, int64_t nkeys, int64_t nother, int R, T *S,
+                         int64_t ldS, hipStream_t s, const int *gate) {
+  switch (R) {
+    case 1: stage1_slice_r<T, 1>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, nother, S, ldS, s, gate); return true;
+    case 2: stage1_slice_r<T, 2>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, nother, S, ldS, s, gate); return true;
+    case 4: stage1_slice_r<T, 4>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, nother, S, ldS, s, gate); return true;
+    case 8: stage1_slice_r<T, 8>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, nother, S, ldS, s, gate); return true;
+    default: return false;
+  }
+}
+
 template <class T>
 static void stage1_direct(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows,
                           const int64_t *seg, const int32_t *other, const T *vs, int64_t nkeys, int R,
@@ -1003,6 +1240,12 @@ void launch_stage1(const T *Fc, int64_t ldc, const int32_t *rows, int64_t nrows,
                    const int64_t *seg, const int32_t *other, int64_t nother, const T *vs,
                    int64_t nkeys, int R, T *S, int64_t ldS, hipStream_t s, const int *gate) {
   if (nrows <= 0 || nkeys <= 0) return;
+  // a contiguous range of at least one row block whose F2 columns' slices fit
+  // in LDS: the slice walk
+  if (row0 >= 0 && stage1_use_slice() && nrows >= S1SliceCfg<T>::RB && nother >= 1 &&
+      nother <= kS1SliceMaxCols &&
+      stage1_slice<T>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, nother, R, S, ldS, s, gate))
+    return;
   // a contiguous range of at least 16 bytes of rows: several rows per lane
   if (row0 >= 0 && stage1_use_wide() && nrows >= 16 / (int64_t)sizeof(T)) {
     stage1_wide<T>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, nother, R, S, ldS, s, gate);

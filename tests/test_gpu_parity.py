@@ -606,6 +606,44 @@ def test_stage1_wide_xcd_order_bitwise(gvt, prec, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("q,lo,hi", [(37, 0, 37), (300, 3, 300), (600, 0, 600), (130, 1, 129),
+                                     (64, 0, 64), (96, 10, 90), (601, 0, 601)])
+@pytest.mark.parametrize("order", [2, 4])
+def test_stage1_slice_bitwise(gvt, prec, q, lo, hi, order, monkeypatch):
+    # the walk over an F2 slice resident in LDS (a block of 32 FP64 or 64 FP32 rows, up to
+    # 600 F2 columns) against the one-row walk: one block exactly, several, a ragged last
+    # block (shifted to end at the last row), ranges shorter than a block and F2 wider than
+    # the slice limit (other walks either way); keys without pairs, duplicate pairs, and
+    # RHS blocks of 1, 2, 4 and 8
+    r = np.random.default_rng([13, q, lo, hi, order])
+    dt = torch.float64 if prec == "f64" else torch.float32
+    D = W.gaussian_kernel(r.standard_normal((q, 3)))
+    T = W.gaussian_kernel(r.standard_normal((q, 3)))
+    c = r.integers(0, q, 24000).astype(np.int32)
+    e = r.integers(0, q, 24000).astype(np.int32)
+    keep = (c % 7 != 3) & (e % 5 != 2)  # some drugs and targets never occur
+    c, e = c[keep], e[keep]
+    c = np.concatenate([c, c[:400]])  # duplicate pairs
+    e = np.concatenate([e, e[:400]])
+    a = r.integers(lo, hi, 9000).astype(np.int32)
+    b = r.integers(lo, hi, 9000).astype(np.int32)
+    a[:hi - lo] = np.arange(lo, hi)  # every row of the range occurs: contiguous S rows
+    b[:hi - lo] = np.arange(lo, hi)
+    Dd, Td = dev(D, dt), dev(T, dt)
+    monkeypatch.setenv("GVT_MAX_RHS_BLOCK", "8")
+    for nrhs in (1, 2, 4, 8, 5):
+        v = dev(r.standard_normal((len(c), nrhs)), dt)
+        args = ((idx(a), idx(b)), (idx(c), idx(e)), v)
+        monkeypatch.setenv("GVT_STAGE1_SLICE", "0")
+        monkeypatch.setenv("GVT_STAGE1_WIDE", "0")
+        ref = gvt.gvt_pairwise_matvec(["kronecker"], Dd, Td, *args, flags=order)
+        monkeypatch.setenv("GVT_STAGE1_SLICE", "1")
+        monkeypatch.setenv("GVT_STAGE1_WIDE", "1")
+        got = gvt.gvt_pairwise_matvec(["kronecker"], Dd, Td, *args, flags=order)
+        assert torch.equal(got, ref), nrhs
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("m,q", [(700, 300), (33, 900), (300, 40), (5, 700)])
 @pytest.mark.parametrize("order", [2, 4])
 def test_stage2_xcd_orders_bitwise(gvt, prec, m, q, order, monkeypatch):
