@@ -1105,9 +1105,10 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
   // (p32 -> w32), [2] FP64 residual product (w -> wraw)
   GroupDesc<double> *dd_it = nullptr, *dd_res = nullptr;
   GroupDesc<float> *df_it = nullptr;
-  GroupItem *it_pack = nullptr, *it_s1 = nullptr, *it_s1f = nullptr,
-            *it_s2[kTileClasses] = {nullptr, nullptr};
-  int64_t n_pack = 0, n_s1 = 0, n_s1f = 0, n_s2[kTileClasses] = {0, 0};
+  GroupItem *it_pack = nullptr, *it_s1 = nullptr, *it_s1f = nullptr, *it_s1s = nullptr,
+            *it_s1fs = nullptr, *it_s2[kTileClasses] = {nullptr, nullptr};
+  int64_t n_pack = 0, n_s1 = 0, n_s1f = 0, n_s1s = 0, n_s1fs = 0, n_s2[kTileClasses] = {0, 0};
+  size_t lds_s1s = 0, lds_s1fs = 0;  // dynamic LDS of the slice walks (FP64, FP32)
   bool need_cls[kTileClasses] = {false, false};
   for (int maxR : {maxR64, maxR32})
     for (int64_t r0 = 0; r0 < nlam; r0 += rhs_block(nlam - r0, maxR))
@@ -1152,6 +1153,7 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
       dsc.seg = is.seg.as<int64_t>();
       dsc.other = is.other.as<int32_t>();
       dsc.nkeys = is.nkeys;
+      dsc.nother = is.nother;
       dsc.S = (T *)(S_base + S_off[i]);
       dsc.F1 = F[t.fdot];
       dsc.ld1 = ldF[t.fdot];
@@ -1168,7 +1170,7 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
       }
       dsc.U = U;
       dsc.ldu = pb[i].n;
-      return group_stage1_setup(dsc, sb.row0);  // after nkeys and nrows
+      return group_stage1_setup(dsc, sb.row0);  // after n_in, nkeys, nrows and nother
     };
     std::vector<int64_t> s1blocks(nprob), s1blocks32(nprob, 0);  // stage-1 blocks per precision
     for (int i = 0; i < nprob; ++i) {
@@ -1185,15 +1187,20 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
       return ps.plans[x]->cost_fma > ps.plans[y]->cost_fma;
     });
-    std::vector<GroupItem> hp, h1, h1f, h2[kTileClasses];
+    std::vector<GroupItem> hp, h1, h1f, h1s, h1fs, h2[kTileClasses];
     for (int i : order) {
       const GroupDesc<double> &g = h64[i];
       const int64_t np = group_pack_blocks(g.n_in);
       const int64_t n1 = s1blocks[i], n1f = s1blocks32[i];
       GVT_REQUIRE(np < (1 << 30) && n1 < (1 << 30) && n1f < (1 << 30), GVT_ERR_ARG, "problem too large");
       for (int64_t k = 0; k < np; ++k) hp.push_back({i, (int32_t)k});
-      for (int64_t k = 0; k < n1; ++k) h1.push_back({i, (int32_t)k});
-      for (int64_t k = 0; k < n1f; ++k) h1f.push_back({i, (int32_t)k});
+      // stage 1: the slice walk's problems in lists of their own
+      std::vector<GroupItem> &l1 = g.slice ? h1s : h1;
+      for (int64_t k = 0; k < n1; ++k) l1.push_back({i, (int32_t)k});
+      std::vector<GroupItem> &l1f = h32[i].slice ? h1fs : h1f;
+      for (int64_t k = 0; k < n1f; ++k) l1f.push_back({i, (int32_t)k});
+      lds_s1s = std::max(lds_s1s, group_stage1_slice_lds(g));
+      if (mprec == GVT_F32) lds_s1fs = std::max(lds_s1fs, group_stage1_slice_lds(h32[i]));
       const TermSpec &t = ps.plans[i]->terms[ps.plans[i]->outputs[0][0].first];
       for (int cls = 0; cls < kTileClasses; ++cls) {
         if (!need_cls[cls]) continue;
@@ -1205,6 +1212,8 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     n_pack = (int64_t)hp.size();
     n_s1 = (int64_t)h1.size();
     n_s1f = (int64_t)h1f.size();
+    n_s1s = (int64_t)h1s.size();
+    n_s1fs = (int64_t)h1fs.size();
     n_s2[0] = (int64_t)h2[0].size();
     n_s2[1] = (int64_t)h2[1].size();
     const size_t dsz64 = sizeof(GroupDesc<double>) * nprob, dsz32 = sizeof(GroupDesc<float>) * nprob;
@@ -1216,17 +1225,23 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     GVT_HIP_CHECK(hipMemcpyAsync(dd_res, hres.data(), dsz64, hipMemcpyHostToDevice, s));
     if (mprec == GVT_F32)
       GVT_HIP_CHECK(hipMemcpyAsync(df_it, h32.data(), dsz32, hipMemcpyHostToDevice, s));
-    GroupItem *ib =
-        (GroupItem *)m_items.ensure(sizeof(GroupItem) * (n_pack + n_s1 + n_s1f + n_s2[0] + n_s2[1] + 1));
+    GroupItem *ib = (GroupItem *)m_items.ensure(
+        sizeof(GroupItem) * (n_pack + n_s1 + n_s1f + n_s1s + n_s1fs + n_s2[0] + n_s2[1] + 1));
     it_pack = ib;
-    it_s1 = ib + n_pack;
-    it_s1f = ib + n_pack + n_s1;
-    it_s2[0] = ib + n_pack + n_s1 + n_s1f;
-    it_s2[1] = ib + n_pack + n_s1 + n_s1f + n_s2[0];
+    it_s1 = it_pack + n_pack;
+    it_s1f = it_s1 + n_s1;
+    it_s1s = it_s1f + n_s1f;
+    it_s1fs = it_s1s + n_s1s;
+    it_s2[0] = it_s1fs + n_s1fs;
+    it_s2[1] = it_s2[0] + n_s2[0];
     GVT_HIP_CHECK(hipMemcpyAsync(it_pack, hp.data(), sizeof(GroupItem) * n_pack, hipMemcpyHostToDevice, s));
     GVT_HIP_CHECK(hipMemcpyAsync(it_s1, h1.data(), sizeof(GroupItem) * n_s1, hipMemcpyHostToDevice, s));
     if (n_s1f)
       GVT_HIP_CHECK(hipMemcpyAsync(it_s1f, h1f.data(), sizeof(GroupItem) * n_s1f, hipMemcpyHostToDevice, s));
+    if (n_s1s)
+      GVT_HIP_CHECK(hipMemcpyAsync(it_s1s, h1s.data(), sizeof(GroupItem) * n_s1s, hipMemcpyHostToDevice, s));
+    if (n_s1fs)
+      GVT_HIP_CHECK(hipMemcpyAsync(it_s1fs, h1fs.data(), sizeof(GroupItem) * n_s1fs, hipMemcpyHostToDevice, s));
     for (int cls = 0; cls < kTileClasses; ++cls)
       if (n_s2[cls])
         GVT_HIP_CHECK(hipMemcpyAsync(it_s2[cls], h2[cls].data(), sizeof(GroupItem) * n_s2[cls],
@@ -1248,6 +1263,8 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
       const uint8_t *mk = per_block ? mask + b * nprob : mask;
       launch_group_pack(desc, it_pack, n_pack, R, r0, mk, s);
       launch_group_stage1(desc, f64 ? it_s1 : it_s1f, f64 ? n_s1 : n_s1f, R, mk, s);
+      launch_group_stage1_slice(desc, f64 ? it_s1s : it_s1fs, f64 ? n_s1s : n_s1fs, R, mk,
+                                f64 ? lds_s1s : lds_s1fs, s);
       launch_group_stage2(desc, it_s2[tile_class(R)], n_s2[tile_class(R)], R, r0, mk, s);
       r0 += R;
     }

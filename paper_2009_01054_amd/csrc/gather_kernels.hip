@@ -370,33 +370,44 @@ template <int S> __device__ __forceinline__ double row_bcast(double x) {
   return __longlong_as_double(row_bcast<S>(__double_as_longlong(x)));
 }
 
+// Body of one slice-walk workgroup (key range kr of kpr keys, row block rb);
+// shared by the single-product kernel and the grouped kernel of batched
+// products.  s1s_lds: the dynamic LDS of at least nother x 256 bytes.
 template <class T, int R>
-__global__ __launch_bounds__(S1SliceCfg<T>::NT) void stage1_slice_kernel(
+__device__ __forceinline__ void stage1_slice_block(
     const T *__restrict__ Fc, int64_t ldc, int64_t row0, int64_t nrows,
     const int64_t *__restrict__ seg, const int32_t *__restrict__ other, const T *__restrict__ vs,
-    int64_t nkeys, int64_t nother, T *__restrict__ S, int64_t ldS, int64_t kpr,
-    const int *__restrict__ gate) {
+    int64_t nkeys, int64_t nother, T *__restrict__ S, int64_t ldS, int64_t kpr, int64_t kr, int64_t rb,
+    unsigned char *s1s_lds) {
   typedef S1SliceCfg<T> C;
   typedef typename Vec16u<T>::type VG;  // 16 bytes at T's alignment (global)
   typedef typename Vec16<T>::type VL;   // 16-byte aligned (LDS)
   constexpr int VPL = C::VPL, RB = C::RB;
   constexpr bool kPackCV = sizeof(T) == 4 && R == 1;
-  extern __shared__ __attribute__((aligned(16))) unsigned char s1s_lds[];
-  if (gate && *gate == 0) return;
-  const int64_t rstart = (int64_t)blockIdx.y * RB;                      // first row stored
+  // Global address space spelled out: the pointers may come from a descriptor
+  // in memory, and loads through flat pointers would also count against the
+  // LDS wait counter, so every wait for a column read would wait for them too.
+  typedef const __attribute__((address_space(1))) VG *GVG;
+  const __attribute__((address_space(1))) T *Fg = (const __attribute__((address_space(1))) T *)Fc;
+  const __attribute__((address_space(1))) int64_t *segg = (const __attribute__((address_space(1))) int64_t *)seg;
+  const __attribute__((address_space(1))) int32_t *otherg =
+      (const __attribute__((address_space(1))) int32_t *)other;
+  const __attribute__((address_space(1))) T *vsg = (const __attribute__((address_space(1))) T *)vs;
+  __attribute__((address_space(1))) T *Sg = (__attribute__((address_space(1))) T *)S;
+  const int64_t rstart = rb * RB;                                      // first row stored
   const int64_t base = rstart + RB <= nrows ? rstart : nrows - RB;     // window inside [0, nrows)
   const int shift = (int)(rstart - base);                              // window rows before rstart
   {
     // piece q = 16 o + pc: 16 bytes of column o at byte 16 q; a thread's eight
     // pieces are loaded together, then stored
-    const T *src = Fc + row0 + base;
+    const __attribute__((address_space(1))) T *src = Fg + row0 + base;
     const int64_t nvec = nother * 16;
     for (int64_t q0 = threadIdx.x; q0 < nvec; q0 += 8 * C::NT) {
       VL tmp[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int64_t q = q0 + (int64_t)u * C::NT;
-        if (q < nvec) tmp[u] = *reinterpret_cast<const VG *>(src + (q >> 4) * ldc + (q & 15) * VPL);
+        if (q < nvec) tmp[u] = *reinterpret_cast<GVG>(src + (q >> 4) * ldc + (q & 15) * VPL);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -409,21 +420,21 @@ __global__ __launch_bounds__(S1SliceCfg<T>::NT) void stage1_slice_kernel(
   const int lane = threadIdx.x & 63, g = lane >> 4, sub = lane & 15;
   const int sub16 = sub * 16;  // this lane's 16 bytes of a column slice
   const int wv = threadIdx.x >> 6;
-  const int64_t k0 = (int64_t)blockIdx.x * kpr;
+  const int64_t k0 = kr * kpr;
   const int64_t k1 = k0 + kpr < nkeys ? k0 + kpr : nkeys;
   // segment bounds of the group's key, loaded one key quad ahead
   int64_t s0n = 0, s1n = 0;
   if (k0 + 4 * wv + g < k1) {
-    s0n = seg[k0 + 4 * wv + g];
-    s1n = seg[k0 + 4 * wv + g + 1];
+    s0n = segg[k0 + 4 * wv + g];
+    s1n = segg[k0 + 4 * wv + g + 1];
   }
   for (int64_t kq = k0 + 4 * wv; kq < k1; kq += 4 * C::NW) {  // uniform
     const int64_t k = kq + g;
     const bool kv = k < k1;
     const int64_t s0 = s0n, s1 = s1n;
     if (kq + 4 * C::NW + g < k1) {
-      s0n = seg[kq + 4 * C::NW + g];
-      s1n = seg[kq + 4 * C::NW + g + 1];
+      s0n = segg[kq + 4 * C::NW + g];
+      s1n = segg[kq + 4 * C::NW + g + 1];
     }
     const int maxlen = wave_max_of_groups((int)(s1 - s0));
     T acc[VPL][R];
@@ -434,10 +445,10 @@ __global__ __launch_bounds__(S1SliceCfg<T>::NT) void stage1_slice_kernel(
     // the (other, v) of the group's next 16 pairs, loaded one window ahead
     int64_t pn = s0 + sub;
     bool inn = pn < s1;
-    int coln = inn ? other[pn] * 256 : 0;  // byte offset of the pair's column slice
+    int coln = inn ? otherg[pn] * 256 : 0;  // byte offset of the pair's column slice
     T vln[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) vln[r] = inn ? vs[pn * R + r] : T(0);
+    for (int r = 0; r < R; ++r) vln[r] = inn ? vsg[pn * R + r] : T(0);
     for (int w0 = 0; w0 < maxlen; w0 += 16) {
       const int col = coln;
       T vl[R];
@@ -446,9 +457,9 @@ __global__ __launch_bounds__(S1SliceCfg<T>::NT) void stage1_slice_kernel(
       if (w0 + 16 < maxlen) {  // uniform
         pn += 16;
         inn = pn < s1;
-        coln = inn ? other[pn] * 256 : 0;
+        coln = inn ? otherg[pn] * 256 : 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) vln[r] = inn ? vs[pn * R + r] : T(0);
+        for (int r = 0; r < R; ++r) vln[r] = inn ? vsg[pn * R + r] : T(0);
       }
       const int nst = maxlen - w0;  // uniform
 // the window's column reads are issued first (16 in flight, 8 with eight RHS), then the sums
@@ -502,7 +513,7 @@ __global__ __launch_bounds__(S1SliceCfg<T>::NT) void stage1_slice_kernel(
         const int rr = sub * VPL + j;
         if (rr >= shift)
 #pragma unroll
-          for (int r = 0; r < R; ++r) S[(base + rr) * ldS + k * R + r] = acc[j][r];
+          for (int r = 0; r < R; ++r) Sg[(base + rr) * ldS + k * R + r] = acc[j][r];
       }
     }
   }
@@ -513,9 +524,21 @@ __global__ __launch_bounds__(S1SliceCfg<T>::NT) void stage1_slice_kernel(
     const int64_t nr = (nrows - rstart < RB ? nrows - rstart : RB);
     for (int64_t idx = threadIdx.x; idx < nr * padw; idx += C::NT) {
       const int64_t rr = idx / padw, cc = idx - rr * padw;
-      S[(rstart + rr) * ldS + nkeys * R + cc] = T(0);
+      Sg[(rstart + rr) * ldS + nkeys * R + cc] = T(0);
     }
   }
+}
+
+template <class T, int R>
+__global__ __launch_bounds__(S1SliceCfg<T>::NT) void stage1_slice_kernel(
+    const T *__restrict__ Fc, int64_t ldc, int64_t row0, int64_t nrows,
+    const int64_t *__restrict__ seg, const int32_t *__restrict__ other, const T *__restrict__ vs,
+    int64_t nkeys, int64_t nother, T *__restrict__ S, int64_t ldS, int64_t kpr,
+    const int *__restrict__ gate) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char s1s_lds[];
+  if (gate && *gate == 0) return;
+  stage1_slice_block<T, R>(Fc, ldc, row0, nrows, seg, other, vs, nkeys, nother, S, ldS, kpr, blockIdx.x,
+                           blockIdx.y, s1s_lds);
 }
 
 template <class T, int R> struct S2Cfg {
@@ -1040,6 +1063,19 @@ __global__ __launch_bounds__(256) void group_stage1_kernel(const GroupDesc<T> *_
 }
 
 template <class T, int R>
+__global__ __launch_bounds__(S1SliceCfg<T>::NT) void group_stage1_slice_kernel(
+    const GroupDesc<T> *__restrict__ desc, const GroupItem *__restrict__ items,
+    const uint8_t *__restrict__ active) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char s1s_lds[];
+  const GroupItem it = items[blockIdx.x];
+  if (active && !active[it.p]) return;
+  const GroupDesc<T> &d = desc[it.p];
+  const int64_t kr = it.li % d.nkr, rb = it.li / d.nkr;
+  stage1_slice_block<T, R>(d.Fc, d.ldc, d.row0, d.nrows, d.seg, d.other, d.vs, d.nkeys, d.nother, d.S,
+                           sbuf_row_ld<T>(d.nkeys, R), d.kpr, kr, rb, s1s_lds);
+}
+
+template <class T, int R>
 __global__ __launch_bounds__(kStage2Rows * 16) void group_stage2_kernel(const GroupDesc<T> *__restrict__ desc,
                                                            const GroupItem *__restrict__ items,
                                                            int64_t r0,
@@ -1363,6 +1399,22 @@ int64_t group_pack_blocks(int64_t n_in) { return ceil_div(n_in, kGroupPackBlock)
 
 template <class T>
 int64_t group_stage1_setup(GroupDesc<T> &d, int64_t row0) {
+  // the slice walk where the slice fits and the problem has pairs enough to
+  // pay for copying it (at least 8 per F2 column); about 12 500 pairs per
+  // workgroup, as many as the single product's workgroups walk on the ridge
+  // workload
+  d.slice = 0;
+  d.nkr = d.kpr = 0;
+  if (row0 >= 0 && stage1_use_slice() && d.nrows >= S1SliceCfg<T>::RB && d.nother >= 1 &&
+      d.nother <= kS1SliceMaxCols && d.n_in >= 8 * d.nother && d.nkeys > 0) {
+    d.slice = 1;
+    d.row0 = row0;
+    const int64_t nkr = std::max<int64_t>(1, std::min(ceil_div(d.n_in, (int64_t)12500), ceil_div(d.nkeys, (int64_t)64)));
+    d.kpr = ceil_div(d.nkeys, nkr);
+    d.nkr = ceil_div(d.nkeys, d.kpr);
+    d.nkb = 0;
+    return d.nkr * ceil_div(d.nrows, (int64_t)S1SliceCfg<T>::RB);
+  }
   const bool wide = row0 >= 0 && stage1_use_wide() && d.nrows >= S1WideCfg<T, 1, 1>::VPL;
   d.row0 = wide ? row0 : -1;
   d.nkb = ceil_div(d.nkeys, wide ? S1WideCfg<T, 1, 1>::KB : S1Cfg<T, 1>::KB);
@@ -1390,6 +1442,33 @@ void launch_group_stage1(const GroupDesc<T> *desc, const GroupItem *items, int64
   }
 }
 
+template <class T, int R>
+static void group_slice_r(const GroupDesc<T> *desc, const GroupItem *items, int64_t nitems,
+                          const uint8_t *active, size_t lds, hipStream_t s) {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(&group_stage1_slice_kernel<T, R>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(kS1SliceMaxCols * 256)) != hipSuccess)
+      (void)hipGetLastError();
+  });
+  group_stage1_slice_kernel<T, R><<<(unsigned)nitems, S1SliceCfg<T>::NT, lds, s>>>(desc, items, active);
+}
+
+template <class T>
+void launch_group_stage1_slice(const GroupDesc<T> *desc, const GroupItem *items, int64_t nitems, int R,
+                               const uint8_t *active, size_t lds, hipStream_t s) {
+  if (nitems <= 0) return;
+  GVT_REQUIRE(lds <= (size_t)kS1SliceMaxCols * 256, GVT_ERR_ARG, "internal: slice larger than LDS");
+  switch (R) {
+    case 1: group_slice_r<T, 1>(desc, items, nitems, active, lds, s); break;
+    case 2: group_slice_r<T, 2>(desc, items, nitems, active, lds, s); break;
+    case 4: group_slice_r<T, 4>(desc, items, nitems, active, lds, s); break;
+    case 8: group_slice_r<T, 8>(desc, items, nitems, active, lds, s); break;
+    default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in grouped stage 1"};
+  }
+}
+
 template <class T>
 void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64_t nitems, int R,
                          int64_t r0, const uint8_t *active, hipStream_t s) {
@@ -1411,6 +1490,8 @@ void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64
                                  hipStream_t, const int *);                                      \
   template void launch_segsum<T>(const int64_t *, const T *, int64_t, int, T *, hipStream_t);    \
   template int64_t group_stage1_setup<T>(GroupDesc<T> &, int64_t);                               \
+  template void launch_group_stage1_slice<T>(const GroupDesc<T> *, const GroupItem *, int64_t, int, \
+                                             const uint8_t *, size_t, hipStream_t);               \
   template void launch_stage1<T>(const T *, int64_t, const int32_t *, int64_t, int64_t,         \
                                  const int64_t *, const int32_t *, int64_t, const T *, int64_t,  \
                                  int, T *, int64_t, hipStream_t, const int *);\

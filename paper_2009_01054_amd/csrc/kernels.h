@@ -108,6 +108,10 @@ template <class T> struct GroupDesc {
   int64_t row0;  // >= 0: S row i is F2 row row0 + i, walked several rows per lane
   T *S;         // row stride sbuf_row_ld<T>(nkeys, R) for an R-column RHS block
   int64_t nkb;  // stage-1 key blocks
+  // stage 1 over an F2 slice resident in LDS (slice != 0): nother F2 columns,
+  // nkr key ranges of kpr keys per row block
+  int64_t nother, kpr, nkr;
+  int slice;
   // stage 2, one tile set per RHS class ([0]: blocks of 1-2 RHS, F1-row groups;
   // [1]: blocks of 4-8 RHS, S-row groups, where tiley holds each tile's F1-row
   // block, yrows each output's F1 row and nyb the number of F1-row blocks)
@@ -132,11 +136,17 @@ struct GroupItem {
 
 // Work items per problem for each grouped launch, in the problem's natural block order.
 int64_t group_pack_blocks(int64_t n_in);
-// Stage 1: picks the problem's walk (several rows per lane when its S rows are
-// the contiguous range starting at F2 row row0 >= 0, else one row per lane),
-// sets d.row0 and d.nkb, and returns the problem's blocks (nkeys and nrows set).
+// Stage 1: picks the problem's walk (over an F2 slice in LDS, or several rows
+// per lane, when its S rows are the contiguous range starting at F2 row
+// row0 >= 0; else one row per lane), sets d.slice, d.row0, d.nkb (d.kpr, d.nkr)
+// and returns the problem's blocks (n_in, nkeys, nrows and nother set).
+// Problems with d.slice set go in the work list of launch_group_stage1_slice.
 template <class T>
 int64_t group_stage1_setup(GroupDesc<T> &d, int64_t row0);
+// Dynamic LDS the slice walk of a problem needs.
+template <class T> inline size_t group_stage1_slice_lds(const GroupDesc<T> &d) {
+  return d.slice ? (size_t)d.nother * 256 : 0;
+}
 
 // active[p] == 0 skips problem p (null: every problem runs).  r0: first RHS of the block.
 template <class T>
@@ -145,6 +155,10 @@ void launch_group_pack(const GroupDesc<T> *desc, const GroupItem *items, int64_t
 template <class T>
 void launch_group_stage1(const GroupDesc<T> *desc, const GroupItem *items, int64_t nitems, int R,
                          const uint8_t *active, hipStream_t s);
+// lds: the largest group_stage1_slice_lds of the listed problems.
+template <class T>
+void launch_group_stage1_slice(const GroupDesc<T> *desc, const GroupItem *items, int64_t nitems, int R,
+                               const uint8_t *active, size_t lds, hipStream_t s);
 template <class T>
 void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64_t nitems, int R,
                          int64_t r0, const uint8_t *active, hipStream_t s);

@@ -471,6 +471,28 @@ def test_cg_batched_stage1_walks_bitwise(gvt, monkeypatch, prec):
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cg_batched_stage1_slice_bitwise(gvt, monkeypatch, prec):
+    # grouped stage 1 over F2 slices in LDS beside problems that keep the other walks
+    # (F2 wider than the slice limit, too few pairs per F2 column, fewer S rows than an FP32
+    # block), RHS blocks of 1, 2 and 4, against the one-row walk everywhere: exact agreement
+    shapes = [(100, 80, 3000), (200, 150, 6000), (700, 650, 8000), (60, 50, 200), (90, 300, 5000),
+              (40, 40, 1200), (130, 120, 9000)]
+    probs = _batch(101, shapes)
+    lams = [1e-1, 1.0, 10.0, 0.5, 3.0]
+    mp = gvt.F32 if prec == "f32" else gvt.F64
+    res = []
+    for walk in ("narrow", "slice"):
+        monkeypatch.setenv("GVT_STAGE1_SLICE", "1" if walk == "slice" else "0")
+        monkeypatch.setenv("GVT_STAGE1_WIDE", "1" if walk == "slice" else "0")
+        res.append(gvt.gvt_krr_cg_batched("kronecker", _dev_problems(probs), lams, max_iter=60, tol=1e-8,
+                                          check_every=4, matvec_prec=mp))
+    (A0, i0, r0, c0), (A1, i1, r1, c1) = res
+    assert c0 == c1 and (i0 == i1).all() and (r0 == r1).all()
+    for x, y in zip(A0, A1):
+        assert torch.equal(x, y)
+
+
 def test_cg_batched_large_problem_matches_single_solves(gvt):
     # a problem with 30 000 pairs over 760 x 740 bases beside small ones: the grouped launches
     # (work lists of uneven length, both stage-1 walks) give the problem-by-problem solutions
