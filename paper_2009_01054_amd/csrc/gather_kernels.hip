@@ -1139,15 +1139,16 @@ static std::atomic<int> g_s1_kpw{kStage1KeysPerWave}, g_s1_wide{kStage1Wide};
 
 // Stage-2 XCD order: -1 chosen per launch, 0 by S block, 1 by F1 block (GVT_STAGE2_XCD).
 static std::atomic<int> g_s2_xcd{-1};
-// Stage 1 over an F2 slice resident in LDS where it fits (GVT_STAGE1_SLICE=0: off),
-// with about this many workgroups per launch (GVT_STAGE1_SLICE_WGS).
-static std::atomic<int> g_s1_slice{1}, g_s1_slice_wgs{256};
+// Stage 1 over an F2 slice resident in LDS where it fits (tuned kStage1Slice;
+// GVT_STAGE1_SLICE overrides), with about this many workgroups per launch
+// (kStage1SliceWgs; GVT_STAGE1_SLICE_WGS).
+static std::atomic<int> g_s1_slice{kStage1Slice}, g_s1_slice_wgs{kStage1SliceWgs};
 
 void refresh_launch_knobs() {
   const char *e6 = std::getenv("GVT_STAGE1_SLICE");
-  g_s1_slice.store(e6 ? (std::atoi(e6) != 0) : 1, std::memory_order_relaxed);
+  g_s1_slice.store(e6 ? (std::atoi(e6) != 0) : kStage1Slice, std::memory_order_relaxed);
   const char *e7 = std::getenv("GVT_STAGE1_SLICE_WGS");
-  g_s1_slice_wgs.store(e7 ? std::max(1, std::atoi(e7)) : 256, std::memory_order_relaxed);
+  g_s1_slice_wgs.store(e7 ? std::max(1, std::atoi(e7)) : kStage1SliceWgs, std::memory_order_relaxed);
   const char *e5 = std::getenv("GVT_STAGE2_XCD");
   g_s2_xcd.store(e5 ? (std::atoi(e5) != 0) : -1, std::memory_order_relaxed);
   const char *e1 = std::getenv("GVT_STAGE1_KPW");

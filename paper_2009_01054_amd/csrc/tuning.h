@@ -1,51 +1,61 @@
 // Tuned launch shapes: stage-2 tile targets (outputs per group row per tile) for
-// each RHS class, and the keys each wave walks in stage 1.
+// each RHS class, the stage-1 walks (F2 slices in LDS and their workgroups per
+// launch, 16 bytes of rows per lane) and the keys each wave walks in stage 1.
 // Written by paper_2009_01054_amd/tune.py on gfx950; measured times (ms):
+//   SLICE: ridge f64 x1; ridge f32 x1; batched f64 (64 problems, 8 RHS), per iteration
+//          0: 0.1126, 0.0847, 9.0405  (score 1.228)
+//          1: 0.0896, 0.0679, 7.6560  (score 1.000)
+//   SLICEWGS: ridge f64 x1; ridge f32 x1
+//        128: 0.1024, 0.0725  (score 1.127)
+//        256: 0.0885, 0.0663  (score 1.002)
+//        512: 0.0909, 0.0660  (score 1.014)
 //   WIDE: ridge f64 x1; ridge f32 x1
-//          0: 0.1287, 0.0912  (score 1.118)
-//          1: 0.1121, 0.0838  (score 1.000)
+//          0: 0.1159, 0.0841  (score 1.106)
+//          1: 0.1018, 0.0783  (score 1.000)
 //   KPW: ridge f64 x1; ridge f32 x1
-//          1: 0.1098, 0.0837  (score 1.004)
-//          2: 0.1117, 0.0830  (score 1.009)
-//          4: 0.1148, 0.0933  (score 1.084)
+//          1: 0.1012, 0.0782  (score 1.000)
+//          2: 0.1043, 0.0790  (score 1.021)
+//          4: 0.1093, 0.0924  (score 1.130)
 //   R1: ridge f64 x1; ridge f32 x1; batched f64 (64 problems, 8 RHS), per iteration
-//          8: 0.1271, 0.1213, 9.0141  (score 1.221)
-//         16: 0.1059, 0.0802, 9.0393  (score 1.001)
-//         32: 0.1068, 0.0803, 9.0507  (score 1.005)
-//         64: 0.1059, 0.0802, 9.0557  (score 1.002)
-//        128: 0.1068, 0.0801, 9.0480  (score 1.004)
+//          8: 0.1095, 0.1150, 7.6473  (score 1.292)
+//         16: 0.0903, 0.0663, 7.6420  (score 1.009)
+//         32: 0.0892, 0.0664, 7.6991  (score 1.007)
+//         64: 0.0887, 0.0659, 7.6905  (score 1.002)
+//        128: 0.0890, 0.0666, 7.6941  (score 1.007)
 //   MAXR64: ridge f64 x8; batched f64 (64 problems, 8 RHS), per iteration
-//          2: 0.7881, 9.0392  (score 1.000)
-//          4: 0.9883, 11.5277  (score 1.265)
-//          8: 1.6924, 14.4786  (score 1.855)
+//          2: 0.7641, 7.6564  (score 1.000)
+//          4: 1.0073, 9.2551  (score 1.262)
+//          8: 1.6973, 13.6275  (score 1.988)
 //   MAXR32: ridge f32 x8; batched f32 (64 problems, 8 RHS), per iteration
-//          2: 0.5567, 5.7363  (score 1.182)
-//          4: 0.4514, 5.0667  (score 1.000)
-//          8: 0.5503, 5.8510  (score 1.187)
+//          2: 0.5030, 5.2170  (score 1.152)
+//          4: 0.4014, 4.9257  (score 1.000)
+//          8: 0.5300, 5.6682  (score 1.233)
 //   R8: ridge f64 x8; ridge f32 x8; batched f32 (64 problems, 8 RHS), per iteration
-//          2: 0.7943, 0.6553, 6.9319  (score 1.275)
-//          4: 0.7873, 0.4926, 5.5461  (score 1.073)
-//          8: 0.7885, 0.5108, 4.9480  (score 1.047)
-//         16: 0.7902, 0.4490, 5.0690  (score 1.011)
-//         32: 0.7852, 0.4476, 5.0768  (score 1.009)
+//          2: 0.7634, 0.6074, 6.7219  (score 1.295)
+//          4: 0.7671, 0.4399, 5.4001  (score 1.083)
+//          8: 0.7576, 0.4654, 4.7869  (score 1.055)
+//         16: 0.7683, 0.3960, 4.9243  (score 1.014)
+//         32: 0.7588, 0.3979, 4.8987  (score 1.010)
 #pragma once
 
 namespace gvt {
-constexpr double kStage2TargetR1 = 16.0;
+constexpr double kStage2TargetR1 = 64.0;
 constexpr double kStage2TargetR8 = 32.0;
 constexpr int kStage1KeysPerWave = 1;
 constexpr int kStage1Wide = 1;
+constexpr int kStage1Slice = 1;
+constexpr int kStage1SliceWgs = 256;
 constexpr int kMaxRhsBlockF64 = 2;
 constexpr int kMaxRhsBlockF32 = 4;
 // Dense-tile cost model: effective rates of the gather path (Theorem 1 flops
 // per second, ridge workload) and of the matrix-core product M Vmat N^T
 // (complete data, 4096 x 2048), and the output-tile count at which a GEMM
 // keeps the matrix cores busy (from the ridge workload's shapes, 64 tiles).
-constexpr double kGatherRateF64 = 8.45e+12;
-constexpr double kGatherRateF32 = 1.15e+13;
-constexpr double kTilesRateF64 = 4.46e+13;
-constexpr double kTilesRateF32 = 1.03e+14;
-constexpr double kTilesFull = 131.3;
+constexpr double kGatherRateF64 = 9.97e+12;
+constexpr double kGatherRateF32 = 1.34e+13;
+constexpr double kTilesRateF64 = 4.32e+13;
+constexpr double kTilesRateF32 = 1.04e+14;
+constexpr double kTilesFull = 150.9;
 // Batched CG with FP32 products: a problem whose active systems all have
 // recurrence residuals below this level continues with FP64 products
 // (GVT_F32_SWITCH overrides; 0 keeps FP32 products until certification).

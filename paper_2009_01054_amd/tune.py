@@ -11,15 +11,20 @@ walks key segments with one wave per key; the number of keys each wave walks
 trades waves in flight against per-wave work.
 
 Over a contiguous range of S rows a stage-1 lane can hold 16 bytes of
-consecutive rows (one vector load per pair) instead of one row.
+consecutive rows (one vector load per pair) instead of one row, and where the
+F2 columns' slices of a block of rows fit in LDS the walk can read them from
+there (the slice walk), with a tuned number of workgroups per launch; the
+wide-walk knobs are measured with the slice walk off, since that walk serves
+the buffers the slice does not fit.
 A product pass carries a block of up to 8 right-hand sides; larger blocks
 reuse every gathered element more often but hold more accumulators per lane,
 so the largest block a pass takes is tuned too, per product precision.
 
 This script sweeps these knobs on synthetic workloads shaped like the
 library's benchmarks, through the library's environment overrides
-(GVT_STAGE1_WIDE, GVT_STAGE1_KPW, GVT_STAGE2_TARGET_R1, GVT_STAGE2_TARGET_R8,
-GVT_MAX_RHS_BLOCK_F64, GVT_MAX_RHS_BLOCK_F32; all are read when a plan is built),
+(GVT_STAGE1_SLICE, GVT_STAGE1_SLICE_WGS, GVT_STAGE1_WIDE, GVT_STAGE1_KPW,
+GVT_STAGE2_TARGET_R1, GVT_STAGE2_TARGET_R8, GVT_MAX_RHS_BLOCK_F64,
+GVT_MAX_RHS_BLOCK_F32; all are read when a plan is built),
 measures the rates of the dense-tile cost model (gather path against matrix-core
 products), and writes the winners and rates as a C++ header that ``build.py``
 compiles into the library:
@@ -46,6 +51,8 @@ R8_CANDIDATES = (2.0, 4.0, 8.0, 16.0, 32.0)
 KPW_CANDIDATES = (1, 2, 4)
 MAXR_CANDIDATES = (2, 4, 8)
 WIDE_CANDIDATES = (0, 1)  # stage 1 over contiguous S rows: one row per lane, or 16 bytes of rows
+SLICE_CANDIDATES = (0, 1)  # stage 1 over F2 slices in LDS where they fit
+SLICE_WGS_CANDIDATES = (128, 256, 512)  # workgroups of a slice-walk launch
 
 
 def _log(*a):
@@ -65,11 +72,13 @@ def _events_ms(torch, fn, reps):
 
 
 _KNOBS = {0: "GVT_STAGE2_TARGET_R1", 1: "GVT_STAGE2_TARGET_R8", "kpw": "GVT_STAGE1_KPW",
-          "wide": "GVT_STAGE1_WIDE", "maxr64": "GVT_MAX_RHS_BLOCK_F64", "maxr32": "GVT_MAX_RHS_BLOCK_F32"}
+          "wide": "GVT_STAGE1_WIDE", "maxr64": "GVT_MAX_RHS_BLOCK_F64", "maxr32": "GVT_MAX_RHS_BLOCK_F32",
+          "slice": "GVT_STAGE1_SLICE", "slicewgs": "GVT_STAGE1_SLICE_WGS"}
+_INT_KNOBS = ("kpw", "wide", "maxr64", "maxr32", "slice", "slicewgs")
 
 
 def _set_target(cls, value):
-    os.environ[_KNOBS[cls]] = (str(int(value)) if cls in ("kpw", "wide", "maxr64", "maxr32")
+    os.environ[_KNOBS[cls]] = (str(int(value)) if cls in _INT_KNOBS
                                else repr(float(value)))
 
 
@@ -199,7 +208,8 @@ def sweep(cls, candidates, workloads):
 
 def write_header(path, results, device, rates):
     lines = ["// Tuned launch shapes: stage-2 tile targets (outputs per group row per tile) for",
-             "// each RHS class, and the keys each wave walks in stage 1.",
+             "// each RHS class, the stage-1 walks (F2 slices in LDS and their workgroups per",
+             "// launch, 16 bytes of rows per lane) and the keys each wave walks in stage 1.",
              "// Written by paper_2009_01054_amd/tune.py on " + device + "; measured times (ms):"]
     for key, (winner, table, score, names) in results.items():
         lines.append(f"//   {key}: " + "; ".join(names))
@@ -211,6 +221,8 @@ def write_header(path, results, device, rates):
               f"constexpr double kStage2TargetR8 = {results['R8'][0]:.1f};",
               f"constexpr int kStage1KeysPerWave = {int(results['KPW'][0])};",
               f"constexpr int kStage1Wide = {int(results['WIDE'][0])};",
+              f"constexpr int kStage1Slice = {int(results['SLICE'][0])};",
+              f"constexpr int kStage1SliceWgs = {int(results['SLICEWGS'][0])};",
               f"constexpr int kMaxRhsBlockF64 = {int(results['MAXR64'][0])};",
               f"constexpr int kMaxRhsBlockF32 = {int(results['MAXR32'][0])};",
               "// Dense-tile cost model: effective rates of the gather path (Theorem 1 flops",
@@ -254,16 +266,25 @@ def main():
     # the class-0 target sets the tile height only where target / density is
     # below 64 rows, which the ridge products (density 0.2) never reach; the
     # batched FP64 solver's smaller, denser problems (blocks of 2 RHS) do
-    for key, cls, cands, wl in (("WIDE", "wide", WIDE_CANDIDATES, r1),
+    # the slice walk first (on the ridge products and the batched FP64 solver, whose
+    # smaller problems take it where their slices fit), then the wide walk's knobs
+    # with the slice walk off: that walk serves the buffers the slice does not fit
+    for key, cls, cands, wl in (("SLICE", "slice", SLICE_CANDIDATES, r1 + b64),
+                                ("SLICEWGS", "slicewgs", SLICE_WGS_CANDIDATES, r1),
+                                ("WIDE", "wide", WIDE_CANDIDATES, r1),
                                 ("KPW", "kpw", KPW_CANDIDATES, r1),
                                 ("R1", 0, R1_CANDIDATES, r1 + b64),
                                 ("MAXR64", "maxr64", MAXR_CANDIDATES, r8[:1] + b64),
                                 ("MAXR32", "maxr32", MAXR_CANDIDATES, r8[1:]),
                                 ("R8", 1, R8_CANDIDATES, r8)):
+        if key == "WIDE":
+            _set_target("slice", 0)
         winner, table, score = sweep(cls, cands, wl)
         results[key] = (winner, table, score, [n for n, _ in wl])
-        if key.startswith("MAXR") or key == "WIDE":
-            _set_target(cls, winner)  # the later sweeps run with the chosen walk and block caps
+        if key.startswith("MAXR") or key in ("WIDE", "SLICE", "SLICEWGS"):
+            _set_target(cls, winner)  # the later sweeps run with the chosen walks and block caps
+        if key == "KPW":
+            _set_target("slice", results["SLICE"][0])
         _log(f"[tune] class {key}: target {winner:g}")
     rates = cost_model(gvt, W, torch, args.reps)
     write_header(args.out, results, device, rates)

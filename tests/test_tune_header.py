@@ -14,7 +14,8 @@ CSRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
 
 def test_written_header_defines_every_tuned_constant(tmp_path):
     results = {}
-    for key, win in (("WIDE", 1), ("KPW", 1), ("R1", 64.0), ("MAXR64", 2), ("MAXR32", 4), ("R8", 16.0)):
+    for key, win in (("SLICE", 1), ("SLICEWGS", 256), ("WIDE", 1), ("KPW", 1), ("R1", 64.0), ("MAXR64", 2),
+                     ("MAXR32", 4), ("R8", 16.0)):
         results[key] = (win, {win: [0.1, 0.2]}, {win: 1.0}, ["workload a", "workload b"])
     rates = {"kGatherRateF64": 9.1e12, "kGatherRateF32": 1.2e13, "kTilesRateF64": 5.5e13,
              "kTilesRateF32": 1.2e14, "kTilesFull": 300.0}
