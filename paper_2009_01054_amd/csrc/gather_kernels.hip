@@ -717,6 +717,163 @@ __global__ __launch_bounds__(kStage2Rows * 16) void stage2_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Stage 2 at low output density (one RHS).  A workgroup takes a dual tile:
+// 128 F1 rows x the S rows of two consecutive S-row blocks, the union of 4 x 2
+// tiles of stage2_kernel (the same output order, perm and tile offsets).  Both
+// operands are staged in LDS in chunks of 256 bytes of every row (128 F1 rows
+// and up to 128 S rows, 64 KB per chunk, two buffers: the next chunk's rows are
+// copied global-to-LDS while the current one is walked), so a staged row
+// serves all of the tile's outputs in its row, about 5 at 4% density against
+// 1.3 for an S row staged for 32 F1 rows.  The workgroup's 64 groups of 16
+// lanes take its outputs in turn (output i to group i mod 64, at most 16 per
+// group and pass); per chunk a group reads each output's two rows (one 16-byte
+// LDS read each per lane) and accumulates in registers.  Each lane sums the
+// same keys in the same order as in stage2_kernel (16 consecutive bytes of
+// every 256), and the lanes meet in the same DPP row sum, so the two kernels
+// give the same bits.  Dual tiles go to the XCDs in regions of 4 x 8 (512 F1
+// rows, up to 1 024 S rows), so an XCD's 32 CUs walk rows that share its L2.
+template <class T> struct S2dCfg {
+  static constexpr int NG = 64, NT = NG * 16;  // 16-lane groups, threads
+  static constexpr int SX = 4, SY = 2;         // stage2_kernel tiles per dual tile
+  static constexpr int XT = SX * kStage2Rows;  // 128 F1 rows
+  static constexpr int YT = SY * kStage2MaxS;  // at most 128 S rows
+  static constexpr int CB = 256;               // bytes of a row per chunk
+  static constexpr int KC = CB / (int)sizeof(T);
+  static constexpr int VEC = 16 / (int)sizeof(T);
+  static constexpr int OPG = 16;               // outputs per group per pass
+  static constexpr int NV = (XT + YT) * CB / 16;  // one chunk's rows in 16-byte units (64 KB)
+  static constexpr int RX = 4, RY = 8;         // dual tiles per XCD region
+};
+
+template <class T>
+__global__ __launch_bounds__(S2dCfg<T>::NT) void stage2_dual_kernel(
+    const T *__restrict__ F1, int64_t ld1, int64_t nx, const int64_t *__restrict__ tileoff,
+    const int32_t *__restrict__ tiley, int nxb, int nyb, const int32_t *__restrict__ yrows,
+    const int32_t *__restrict__ perm, const T *__restrict__ S, int64_t ldS, int64_t nsrows, int64_t nkeys,
+    T coef, T *__restrict__ out, int64_t ldi, const int *__restrict__ gate) {
+  typedef S2dCfg<T> C;
+  typedef typename Vec16<T>::type V;
+  // the two chunk buffers are separate arrays: the copies into one then provably
+  // do not write what the walk of the other reads, and its reads need not wait
+  __shared__ V buf0[C::NV], buf1[C::NV];
+  __shared__ int32_t soff[C::SX * C::SY][kStage2Rows + 1];
+  if (gate && *gate == 0) return;
+  // workgroup -> XCD region -> dual tile (padding workgroups return at once)
+  const int ndx = (nxb + C::SX - 1) / C::SX, ndy = (nyb + C::SY - 1) / C::SY;
+  const int nry = (ndy + C::RY - 1) / C::RY, nreg = ((ndx + C::RX - 1) / C::RX) * nry;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int reg = (slot / (C::RX * C::RY)) * 8 + xcd, loc = slot % (C::RX * C::RY);
+  if (reg >= nreg) return;
+  const int dx = (reg / nry) * C::RX + loc / C::RY, dy = (reg % nry) * C::RY + loc % C::RY;
+  if (dx >= ndx || dy >= ndy) return;
+  const int tid = threadIdx.x, sub = tid & 15, g = tid >> 4;
+  // sub-tile st = (sx, sy): the positions where its 32 rows' outputs start
+  for (int i = tid; i < C::SX * C::SY * (kStage2Rows + 1); i += C::NT) {
+    const int st = i / (kStage2Rows + 1), j = i % (kStage2Rows + 1);
+    const int xb = dx * C::SX + (st >> 1), yb = dy * C::SY + (st & 1);
+    soff[st][j] = (xb < nxb && yb < nyb) ? (int32_t)tileoff[((int64_t)xb * nyb + yb) * (kStage2Rows + 1) + j] : 0;
+  }
+  const int64_t ct0 = (int64_t)(dx * C::SX) * nyb + dy * C::SY;
+  const int64_t y0 = tiley[2 * ct0];
+  const int64_t nyr = tiley[2 * ct0 + 1] + (dy * C::SY + 1 < nyb ? tiley[2 * ct0 + 3] : 0);
+  __syncthreads();
+  int cum[C::SX * C::SY + 1];
+  cum[0] = 0;
+#pragma unroll
+  for (int st = 0; st < C::SX * C::SY; ++st) cum[st + 1] = cum[st] + (soff[st][kStage2Rows] - soff[st][0]);
+  const int ntot = cum[C::SX * C::SY];
+  const int64_t nch = (nkeys + C::KC - 1) / C::KC;
+  const int wv = tid >> 6, ln = tid & 63;
+  // copy chunk c into buffer bd: 256 rows of 256 bytes, four rows per wave
+  // instruction (lane l: row 4 i + l / 16, bytes 16 (l % 16)); F1 rows past the
+  // matrix read row 0 and S rows past the block its first row, and keys past
+  // nkeys (whole 16-byte pieces, nkeys being a multiple of VEC) read the row's
+  // first piece: their S partner is a zero of the row padding or they belong to
+  // no output, so every staged value is finite and contributes nothing
+  auto issue = [&](int64_t c, V *bd) {
+    const int64_t kp = c * C::KC + (int64_t)(ln & 15) * C::VEC;
+    for (int i = wv; i < (C::XT + C::YT) / 4; i += C::NT / 64) {
+      const int r = 4 * i + (ln >> 4);
+      const T *src;
+      if (r < C::XT) {
+        const int64_t x = (int64_t)dx * C::XT + r;
+        src = F1 + (x < nx ? x : 0) * ld1 + (kp < nkeys ? kp : 0);
+      } else {
+        const int64_t yr = r - C::XT;
+        src = S + (y0 + (yr < nyr ? yr : 0)) * ldS + kp;
+      }
+      lds_load_row16(src, bd + 4 * i * (C::CB / 16));
+    }
+  };
+  for (int pass0 = 0; pass0 < ntot; pass0 += C::NG * C::OPG) {  // uniform
+    const int cnt = min(C::OPG, max(0, (ntot - pass0 - g + C::NG - 1) / C::NG));
+    // lane `sub` resolves output `sub` of its group: where its rows sit in a
+    // chunk buffer (16-byte units) and its index
+    int offa = 0, offb = 0;
+    int64_t outi = 0;
+    {
+      const int idx = pass0 + g + C::NG * sub;
+      if (sub < cnt) {
+        int st = 0, cst = 0;  // the sub-tile holding output idx, and its first output
+#pragma unroll
+        for (int u = 1; u < C::SX * C::SY; ++u)
+          if (idx >= cum[u]) {
+            st = u;
+            cst = cum[u];
+          }
+        const int q = soff[st][0] + (idx - cst);
+        int lo = 0, hi = kStage2Rows;  // the row r with soff[st][r] <= q < soff[st][r + 1]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (soff[st][mid] <= q) lo = mid;
+          else hi = mid;
+        }
+        offa = ((st >> 1) * kStage2Rows + lo) * (C::CB / 16);
+        offb = (C::XT + (int)(yrows[q] - y0)) * (C::CB / 16);
+        outi = perm[q];
+      }
+    }
+    int oa[C::OPG], ob[C::OPG];
+#pragma unroll
+    for (int o = 0; o < C::OPG; ++o) {
+      oa[o] = __shfl(offa, (tid & 48) + o, 64) + sub;
+      ob[o] = __shfl(offb, (tid & 48) + o, 64) + sub;
+    }
+    T acc[C::OPG];
+#pragma unroll
+    for (int o = 0; o < C::OPG; ++o) acc[o] = T(0);
+    __syncthreads();  // the previous pass's reads of the buffers are done
+    issue(0, buf0);
+    // chunk c walks buffer c mod 2 while chunk c + 1 is copied into the other;
+    // the loop is unrolled by two so each half names its buffers at compile time
+    auto walk = [&](int64_t c, const V *bc, V *bn) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of chunk c have landed
+      __syncthreads();                // everyone's have, and chunk c - 1 is walked
+      if (c + 1 < nch) issue(c + 1, bn);
+#pragma unroll
+      for (int o = 0; o < C::OPG; ++o) {
+        if (o < cnt) {
+          const V a = bc[oa[o]];
+          const V b = bc[ob[o]];
+#pragma unroll
+          for (int j = 0; j < C::VEC; ++j) acc[o] += a[j] * b[j];
+        }
+      }
+    };
+    for (int64_t c = 0; c < nch; c += 2) {
+      walk(c, buf0, buf1);
+      if (c + 1 < nch) walk(c + 1, buf1, buf0);
+    }
+    const int wn = wave_max_of_groups(cnt);
+#pragma unroll
+    for (int o = 0; o < C::OPG; ++o) {
+      if (o < wn) acc[o] = row16_sum(acc[o]);
+      if (sub == o && o < cnt) out[outi * ldi] = coef * acc[o];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Stage 2 for blocks of R >= 4 right-hand sides, grouped by S row.  Each S
 // element carries R values, so the roles swap: a 16-lane group owns one S row
 // and holds that row's slice of the current key chunk (KPL keys x R values per
@@ -1139,12 +1296,17 @@ static std::atomic<int> g_s1_kpw{kStage1KeysPerWave}, g_s1_wide{kStage1Wide};
 
 // Stage-2 XCD order: -1 chosen per launch, 0 by S block, 1 by F1 block (GVT_STAGE2_XCD).
 static std::atomic<int> g_s2_xcd{-1};
+// Stage 2 over dual tiles at low output density: -1 chosen per launch, 0 off,
+// 1 wherever it applies (GVT_STAGE2_DUAL).
+static std::atomic<int> g_s2_dual{-1};
 // Stage 1 over an F2 slice resident in LDS where it fits (tuned kStage1Slice;
 // GVT_STAGE1_SLICE overrides), with about this many workgroups per launch
 // (kStage1SliceWgs; GVT_STAGE1_SLICE_WGS).
 static std::atomic<int> g_s1_slice{kStage1Slice}, g_s1_slice_wgs{kStage1SliceWgs};
 
 void refresh_launch_knobs() {
+  const char *e8 = std::getenv("GVT_STAGE2_DUAL");
+  g_s2_dual.store(e8 ? (std::atoi(e8) != 0) : -1, std::memory_order_relaxed);
   const char *e6 = std::getenv("GVT_STAGE1_SLICE");
   g_s1_slice.store(e6 ? (std::atoi(e6) != 0) : kStage1Slice, std::memory_order_relaxed);
   const char *e7 = std::getenv("GVT_STAGE1_SLICE_WGS");
@@ -1322,6 +1484,31 @@ void launch_stage2(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff,
     case 8: stage2_kernel<T, 8><<<grid, nt, 0, s>>>(F1, ld1, nx, tileoff, tiley, tilemax, grow, yrows, perm, nyb, S, ldS, nkeys, coef, out, ldi, ldr, gate, nxb, by_f1); break;
     default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in stage 2"};
   }
+}
+
+// Stage 2 over dual tiles where it applies: one RHS, F1 rows 16-byte aligned
+// (global-to-LDS copies), nkeys a multiple of the vector length, and a low
+// output density (auto: at most 700 outputs per dual tile on average, so one
+// pass of 1 024 output slots serves a tile).  Returns false where it does not.
+template <class T>
+bool launch_stage2_dual(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff, const int32_t *tiley,
+                        int64_t ntiles, int nyb, const int32_t *yrows, const int32_t *perm, const T *S,
+                        int64_t ldS, int64_t nsrows, int64_t nkeys, int64_t n_out, T coef, T *out, int64_t ldi,
+                        hipStream_t s, const int *gate) {
+  typedef S2dCfg<T> C;
+  const int mode = g_s2_dual.load(std::memory_order_relaxed);
+  if (mode == 0 || ntiles <= 0 || nyb <= 0) return false;
+  if (((uintptr_t)F1 & 15) != 0 || (ld1 * (int64_t)sizeof(T)) % 16 != 0 || nkeys % C::VEC != 0) return false;
+  const int64_t nxb = ntiles / nyb;
+  const int64_t ndx = ceil_div(nxb, (int64_t)C::SX), ndy = ceil_div((int64_t)nyb, (int64_t)C::SY);
+  if (mode < 0 && (double)n_out > 700.0 * (double)(ndx * ndy)) return false;
+  const int64_t nreg = ceil_div(ndx, (int64_t)C::RX) * ceil_div(ndy, (int64_t)C::RY);
+  const int64_t nwg = ceil_div(nreg, (int64_t)8) * 8 * C::RX * C::RY;
+  GVT_REQUIRE(nwg < ((int64_t)1 << 31) && nxb < ((int64_t)1 << 30), GVT_ERR_ARG, "too many stage-2 tiles");
+  (void)nsrows;
+  stage2_dual_kernel<T><<<(unsigned)nwg, C::NT, 0, s>>>(F1, ld1, nx, tileoff, tiley, (int)nxb, nyb, yrows, perm,
+                                                        S, ldS, nsrows, nkeys, coef, out, ldi, gate);
+  return true;
 }
 
 template <class T>
@@ -1503,6 +1690,10 @@ void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64
                                  const int32_t *,                                                \
                                  const T *, int64_t, int64_t, int64_t, int, T, T *, int64_t,     \
                                  int64_t, hipStream_t, const int *);                             \
+  template bool launch_stage2_dual<T>(const T *, int64_t, int64_t, const int64_t *, const int32_t *, \
+                                      int64_t, int, const int32_t *, const int32_t *, const T *,   \
+                                      int64_t, int64_t, int64_t, int64_t, T, T *, int64_t,         \
+                                      hipStream_t, const int *);                                    \
   template void launch_stage2y<T>(const T *, int64_t, const int64_t *, const int32_t *,          \
                                   const int32_t *, const uint8_t *, int64_t, int,                 \
                                   const int32_t *, const int32_t *,                               \

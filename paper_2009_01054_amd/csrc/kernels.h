@@ -57,6 +57,14 @@ void launch_stage2(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff,
                    const int32_t *yrows, const int32_t *perm, const T *S, int64_t ldS, int64_t nsrows,
                    int64_t nkeys, int R, T coef, T *out, int64_t ldi, int64_t ldr, hipStream_t s,
                    const int *gate = nullptr);
+// Stage 2 with one RHS over dual tiles (128 F1 rows x two S-row blocks of the
+// same tiles, both operands staged in LDS) at low output density; returns
+// false, launching nothing, where it does not apply.
+template <class T>
+bool launch_stage2_dual(const T *F1, int64_t ld1, int64_t nx, const int64_t *tileoff, const int32_t *tiley,
+                        int64_t ntiles, int nyb, const int32_t *yrows, const int32_t *perm, const T *S,
+                        int64_t ldS, int64_t nsrows, int64_t nkeys, int64_t n_out, T coef, T *out, int64_t ldi,
+                        hipStream_t s, const int *gate = nullptr);
 // Stage 2 with S-row grouped tiles (blocks of R = 4 or 8 RHS).
 template <class T>
 void launch_stage2y(const T *F1, int64_t ld1, const int64_t *tileoff, const int32_t *tilex,

@@ -1021,7 +1021,14 @@ void execute_block(gvt_plan *P, const T *D, int64_t ldd, const T *Tm, int64_t ld
       T *out = P->direct ? U : wsp<T>(P, W.tvec[ti]);
       const int64_t ldi = P->direct ? 1 : R, ldr = P->direct ? ldu : 1;
       const TileSet &tl = t.tiles[tile_class(R)];
-      if (tile_class(R) == 0)
+      if (tile_class(R) == 0 && R == 1 &&
+          launch_stage2_dual<T>(F[t.fdot], ldF[t.fdot], rows_of(P, t.fdot), tl.tileoff.as<int64_t>(),
+                                tl.tiley.as<int32_t>(), tl.ntiles, tl.nyb, tl.yrows.as<int32_t>(),
+                                tl.perm.as<int32_t>(), wsp<T>(P, W.sbuf[t.sbuf]), sbuf_ld<T>(P, t.sbuf, R),
+                                (int64_t)sb.rows.size(), nkeys_of(P, sb.key), P->n_out, T(1), out, ldi, s,
+                                P->gate)) {
+        // low output density: dual tiles
+      } else if (tile_class(R) == 0)
         launch_stage2<T>(F[t.fdot], ldF[t.fdot], rows_of(P, t.fdot), tl.tileoff.as<int64_t>(),
                          tl.tiley.as<int32_t>(), tl.tilemax.as<int32_t>(), tl.grow.as<uint8_t>(),
                          tl.ntiles, tl.nyb, tl.yrows.as<int32_t>(), tl.perm.as<int32_t>(),

@@ -666,6 +666,40 @@ def test_stage1_slice_bitwise(gvt, prec, q, lo, hi, order, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["het700x500", "het260x1000", "het333x501", "fused600"])
+@pytest.mark.parametrize("order", [2, 4])
+def test_stage2_dual_tiles_vs_oracle(gvt, monkeypatch, prec, case, order):
+    # stage 2 over dual tiles (128 F1 rows x two S-row blocks, both operands staged in LDS)
+    # forced wherever it applies, at 3-4% output density: ragged dual tiles at both edges,
+    # several sub-tiles empty, a fused multi-kind plan (two-factor terms of both orders),
+    # and key counts that are not a multiple of the vector length (the kernel declines and
+    # the one-sided kernel runs); against the oracle, and bitwise against the one-sided
+    # kernel (each lane sums the same keys in the same order, and the lanes meet the same way)
+    kinds = ["kronecker"]
+    if case == "fused600":
+        kinds = ["symmetric", "antisymmetric", "cartesian", "poly2d"]
+        p = W.make_homogeneous(97, order, 600, 15000, 5, n_out=12000, kernel="gaussian")
+        T = None
+    else:
+        m, q = {"het700x500": (700, 500), "het260x1000": (260, 1000), "het333x501": (333, 501)}[case]
+        p = W.make_heterogeneous(96, order, m, q, 20000, 6, n_out=int(0.035 * m * q))
+        T = p["T"]
+    dt = tdt(prec)
+    Dd = dev(p["D"], dt)
+    Td = Dd if T is None else dev(T, dt)
+    args = ((idx(p["a"]), idx(p["b"])), (idx(p["c"]), idx(p["e"])), dev(p["v"], dt))
+    res = {}
+    for dual in ("1", "0"):
+        monkeypatch.setenv("GVT_STAGE2_DUAL", dual)
+        res[dual] = gvt.gvt_pairwise_matvec(kinds, Dd, Td, *args, flags=order | gvt.FLAG_SYMMETRIC_BASES)
+    for k, kind in enumerate(kinds):
+        ref = oracle.pairwise_matvec(kind, p["D"], T, (p["a"], p["b"]), (p["c"], p["e"]), p["v"])
+        got = res["1"][k].cpu().double().numpy()
+        assert relerr(got, ref) < TOL[prec], kind
+        assert torch.equal(res["1"][k], res["0"][k]), kind
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("m,q", [(700, 300), (33, 900), (300, 40), (5, 700)])
 @pytest.mark.parametrize("order", [2, 4])
 def test_stage2_xcd_orders_bitwise(gvt, prec, m, q, order, monkeypatch):
