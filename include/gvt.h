@@ -50,14 +50,20 @@
  *    bitwise identical outputs (no floating-point atomics).
  *  - Launch shapes come from tuned constants compiled into the library.
  *    Environment variables read when a plan is built override them for
- *    tuning sweeps: GVT_STAGE1_WIDE (0/1: stage 1 holds 16 bytes of
- *    consecutive rows per lane over a contiguous row range), GVT_STAGE1_KPW
- *    (1, 2, 4 keys per wave), GVT_STAGE2_TARGET_R1 / _R8 (stage-2 outputs per
- *    group row and tile), GVT_MAX_RHS_BLOCK[_F64|_F32] (largest RHS block of
- *    a pass), GVT_PLAN_DEVICE (0/1: plan index work on the host / device).
- *    All of them but the RHS block give the same products bit for bit (the
- *    block size changes which lanes sum which keys); GVT_PLAN_TIMING=1
- *    prints the host time of each plan phase.
+ *    tuning sweeps: GVT_STAGE1_SLICE (0/1: stage 1 reads a contiguous row
+ *    range's F2 columns from a slice held in LDS where it fits),
+ *    GVT_STAGE1_SLICE_WGS (workgroups of such a launch), GVT_STAGE1_WIDE (0/1:
+ *    stage 1 holds 16 bytes of consecutive rows per lane over a contiguous row
+ *    range), GVT_STAGE1_KPW (1, 2, 4 keys per wave), GVT_STAGE2_TARGET_R1 /
+ *    _R8 (stage-2 outputs per group row and tile), GVT_STAGE2_XCD (0/1: stage-2
+ *    tiles dealt to the XCDs by S block / by F1 block; unset: by working set),
+ *    GVT_STAGE2_DUAL (0/1: stage 2 with one RHS stages both operands of
+ *    128 x 128 tiles in LDS; unset: at low output density),
+ *    GVT_MAX_RHS_BLOCK[_F64|_F32] (largest RHS block of a pass),
+ *    GVT_PLAN_DEVICE (0/1: plan index work on the host / device).  All of them
+ *    but the RHS block give the same products bit for bit (the block size
+ *    changes which lanes sum which keys); GVT_PLAN_TIMING=1 prints the host
+ *    time of each plan phase.
  */
 #ifndef GVT_H
 #define GVT_H
