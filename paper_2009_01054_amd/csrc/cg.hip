@@ -345,13 +345,19 @@ __global__ void to_f32_kernel(const double *__restrict__ x, float *__restrict__ 
   if (i < count) y[i] = (float)x[i];
 }
 
+// FP32 copy of a base matrix with row stride ldy >= cols; the padding columns
+// are written as zeros.
 __global__ void mat_to_f32_kernel(const double *__restrict__ x, int64_t ldx, float *__restrict__ y,
-                                  int64_t rows, int64_t cols) {
+                                  int64_t ldy, int64_t rows, int64_t cols) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rows * cols) return;
-  const int64_t r = idx / cols, c = idx - r * cols;
-  y[idx] = (float)x[r * ldx + c];
+  if (idx >= rows * ldy) return;
+  const int64_t r = idx / ldy, c = idx - r * ldy;
+  y[idx] = c < cols ? (float)x[r * ldx + c] : 0.0f;
 }
+
+// Row stride of the FP32 copies: whole 64-byte lines, so that every row starts
+// on a 16-byte boundary and the stage-2 kernels stage F1 in vector pieces.
+inline int64_t f32_copy_ld(int64_t cols) { return (cols + 15) / 16 * 16; }
 
 // ---------------------------------------------------------------------------
 namespace {
@@ -410,15 +416,16 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
   double *tmp = (double *)m_tmp.ensure(128 * 8 + 256);
   int *gate = reinterpret_cast<int *>(tmp + 128);  // run flag of the iteration products
   float *p32 = nullptr, *w32 = nullptr, *D32 = nullptr, *T32 = nullptr;
+  const int64_t ldd32 = f32_copy_ld(d), ldt32 = hom ? ldd32 : f32_copy_ld(t);
   GVT_HIP_CHECK(hipMemcpyAsync(lam, lambdas, nlam * 8, hipMemcpyHostToDevice, s));
   if (mprec == GVT_F32) {
     p32 = (float *)m_p32.ensure(nv * 4);
     w32 = (float *)m_w32.ensure(nv * 4);
-    D32 = (float *)m_D32.ensure((size_t)d * d * 4);
-    mat_to_f32_kernel<<<g1(d * d), 256, 0, s>>>(D, ldd, D32, d, d);
+    D32 = (float *)m_D32.ensure((size_t)d * ldd32 * 4);
+    mat_to_f32_kernel<<<g1(d * ldd32), 256, 0, s>>>(D, ldd, D32, ldd32, d, d);
     if (!hom) {
-      T32 = (float *)m_T32.ensure((size_t)t * t * 4);
-      mat_to_f32_kernel<<<g1(t * t), 256, 0, s>>>(T, ldt, T32, t, t);
+      T32 = (float *)m_T32.ensure((size_t)t * ldt32 * 4);
+      mat_to_f32_kernel<<<g1(t * ldt32), 256, 0, s>>>(T, ldt, T32, ldt32, t, t);
     } else {
       T32 = D32;
     }
@@ -506,7 +513,7 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
     P->gate = gate;
     P->prepacked = fuse_pack && packed;
     if (lowprec) {
-      plan_execute(P, GVT_F32, D32, d, T32, t, p32, nlam, n, w32, n, s);
+      plan_execute(P, GVT_F32, D32, ldd32, T32, ldt32, p32, nlam, n, w32, n, s);
       cg_pw_kernel<float><<<RNB, RB, 0, s>>>(w32, p, lam, n, nlam, sc, part);
       cg_update_kernel<float><<<RNB, RB, 0, s>>>(A, lda, r, p, w32, lam, n, nlam, sc, part, part2);
     } else {
@@ -971,6 +978,7 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     const double *D, *T;
     int64_t d, t, ldd, ldt, n, noff, voff;
     float *D32, *T32;
+    int64_t ldd32, ldt32;  // row strides of the FP32 copies
   };
   std::vector<Prob> pb(nprob);
   PlanSet ps;
@@ -1082,21 +1090,25 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
     p32 = (float *)m_p32.ensure(nv * 4);
     w32 = (float *)m_w32.ensure(nv * 4);
     size_t tot = 0;
-    for (int i = 0; i < nprob; ++i)
-      tot += (size_t)(pb[i].d * pb[i].d + (hom ? 0 : pb[i].t * pb[i].t));
+    for (int i = 0; i < nprob; ++i) {
+      Prob &b = pb[i];
+      b.ldd32 = f32_copy_ld(b.d);
+      b.ldt32 = hom ? b.ldd32 : f32_copy_ld(b.t);
+      tot += (size_t)(b.d * b.ldd32 + (hom ? 0 : b.t * b.ldt32));
+    }
     float *base = (float *)m_mat32.ensure(tot * 4);
     size_t off = 0;
     for (int i = 0; i < nprob; ++i) {
       Prob &b = pb[i];
       b.D32 = base + off;
-      off += (size_t)(b.d * b.d);
-      mat_to_f32_kernel<<<g1(b.d * b.d), 256, 0, s>>>(b.D, b.ldd, b.D32, b.d, b.d);
+      off += (size_t)(b.d * b.ldd32);
+      mat_to_f32_kernel<<<g1(b.d * b.ldd32), 256, 0, s>>>(b.D, b.ldd, b.D32, b.ldd32, b.d, b.d);
       if (hom) {
         b.T32 = b.D32;
       } else {
         b.T32 = base + off;
-        off += (size_t)(b.t * b.t);
-        mat_to_f32_kernel<<<g1(b.t * b.t), 256, 0, s>>>(b.T, b.ldt, b.T32, b.t, b.t);
+        off += (size_t)(b.t * b.ldt32);
+        mat_to_f32_kernel<<<g1(b.t * b.ldt32), 256, 0, s>>>(b.T, b.ldt, b.T32, b.ldt32, b.t, b.t);
       }
     }
   }
@@ -1178,7 +1190,7 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
       s1blocks[i] = fill(h64[i], i, b.D, b.ldd, b.T, b.ldt, (const double *)(p + b.voff), wraw + b.voff);
       fill(hres[i], i, b.D, b.ldd, b.T, b.ldt, (const double *)(w + b.voff), wraw + b.voff);
       if (mprec == GVT_F32)
-        s1blocks32[i] = fill(h32[i], i, (const float *)b.D32, b.d, (const float *)b.T32, b.t,
+        s1blocks32[i] = fill(h32[i], i, (const float *)b.D32, b.ldd32, (const float *)b.T32, b.ldt32,
                              (const float *)(p32 + b.voff), w32 + b.voff);
     }
     // work lists: problems by decreasing Theorem 1 cost, each problem's blocks in order
@@ -1293,7 +1305,7 @@ int krr_cg_batched_impl(int kind, const gvt_krr_problem *pr, int nprob, const do
         plan_execute(ps.plans[i], GVT_F64, pb[i].D, pb[i].ldd, pb[i].T, pb[i].ldt, p + pb[i].voff, nlam,
                      pb[i].n, wraw + pb[i].voff, pb[i].n, s);
       else
-        plan_execute(ps.plans[i], GVT_F32, pb[i].D32, pb[i].d, pb[i].T32, pb[i].t, p32 + pb[i].voff, nlam,
+        plan_execute(ps.plans[i], GVT_F32, pb[i].D32, pb[i].ldd32, pb[i].T32, pb[i].ldt32, p32 + pb[i].voff, nlam,
                      pb[i].n, w32 + pb[i].voff, pb[i].n, s);
     }
   };

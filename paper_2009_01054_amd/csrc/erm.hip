@@ -197,12 +197,15 @@ __global__ void e_widen_kernel(const float *__restrict__ x, int64_t n, double *_
   if (i < n) y[i] = (double)x[i];
 }
 
-__global__ void e_f32_kernel(const double *__restrict__ x, int64_t ldx, float *__restrict__ y, int64_t rows,
-                             int64_t cols) {
+// FP32 copy of a base matrix with row stride ldy >= cols (padding written as
+// zeros): rows of whole 64-byte lines start on 16-byte boundaries, so the
+// stage-2 kernels stage F1 in vector pieces.
+__global__ void e_f32_kernel(const double *__restrict__ x, int64_t ldx, float *__restrict__ y, int64_t ldy,
+                             int64_t rows, int64_t cols) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rows * cols) return;
-  const int64_t r = idx / cols, c = idx - r * cols;
-  y[idx] = (float)x[r * ldx + c];
+  if (idx >= rows * ldy) return;
+  const int64_t r = idx / ldy, c = idx - r * ldy;
+  y[idx] = c < cols ? (float)x[r * ldx + c] : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -228,6 +231,7 @@ struct Erm {
   double lam;
   hipStream_t s;
   float *D32 = nullptr, *T32 = nullptr;
+  int64_t ldd32 = 0, ldt32 = 0;  // row strides of the FP32 copies
   double *part = nullptr, *fold = nullptr;  // 2 x ENB partials, 8 fold results
   float *in32 = nullptr, *out32 = nullptr;  // FP32 product staging
 
@@ -237,7 +241,7 @@ struct Erm {
       plan_execute(P, GVT_F64, D, ldd, T, ldt, X, 1, n, Y, n, s);
     } else {
       e_axpby_kernel<<<eg1(n), 256, 0, s>>>(1.0, X, 0.0, n, nullptr, in32);  // in32 = (float)X
-      plan_execute(P, GVT_F32, D32, d, T32, t, in32, 1, n, out32, n, s);
+      plan_execute(P, GVT_F32, D32, ldd32, T32, ldt32, in32, 1, n, out32, n, s);
       e_widen_kernel<<<eg1(n), 256, 0, s>>>(out32, n, Y);
     }
   }
@@ -325,14 +329,17 @@ int erm_newton_impl(int kind, int loss, const double *D, int64_t d, int64_t ldd,
     float *f = (float *)m_32.ensure((size_t)n * 4 * 2);
     E.in32 = f;
     E.out32 = f + n;
-    E.D32 = (float *)m_D32.ensure((size_t)d * d * 4);
-    e_f32_kernel<<<eg1(d * d), 256, 0, s>>>(D, ldd, E.D32, d, d);
+    E.ldd32 = (d + 15) / 16 * 16;
+    E.D32 = (float *)m_D32.ensure((size_t)d * E.ldd32 * 4);
+    e_f32_kernel<<<eg1(d * E.ldd32), 256, 0, s>>>(D, ldd, E.D32, E.ldd32, d, d);
     const bool hom = T == D;
     if (!hom) {
-      E.T32 = (float *)m_T32.ensure((size_t)t * t * 4);
-      e_f32_kernel<<<eg1(t * t), 256, 0, s>>>(T, ldt, E.T32, t, t);
+      E.ldt32 = (t + 15) / 16 * 16;
+      E.T32 = (float *)m_T32.ensure((size_t)t * E.ldt32 * 4);
+      e_f32_kernel<<<eg1(t * E.ldt32), 256, 0, s>>>(T, ldt, E.T32, E.ldt32, t, t);
     } else {
       E.T32 = E.D32;
+      E.ldt32 = E.ldd32;
     }
   }
   GVT_HIP_CHECK(hipMemsetAsync(A, 0, (size_t)n * 8, s));

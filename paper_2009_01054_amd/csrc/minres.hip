@@ -399,12 +399,15 @@ __global__ __launch_bounds__(MB) void mr_fold_kernel(const double *__restrict__ 
   if (threadIdx.x == 0) out[blockIdx.x] = v;
 }
 
+// FP32 copy of a base matrix with row stride ldy >= cols (padding written as
+// zeros): rows of whole 64-byte lines start on 16-byte boundaries, so the
+// stage-2 kernels stage F1 in vector pieces.
 __global__ void mr_to_f32_kernel(const double *__restrict__ x, int64_t ldx, float *__restrict__ y,
-                                 int64_t rows, int64_t cols) {
+                                 int64_t ldy, int64_t rows, int64_t cols) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rows * cols) return;
-  const int64_t r = idx / cols, c = idx - r * cols;
-  y[idx] = (float)x[r * ldx + c];
+  if (idx >= rows * ldy) return;
+  const int64_t r = idx / ldy, c = idx - r * ldy;
+  y[idx] = c < cols ? (float)x[r * ldx + c] : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -490,15 +493,16 @@ int krr_minres_impl(int kind, const double *D, int64_t d, int64_t ldd, const dou
   GVT_HIP_CHECK(hipMemcpyAsync(lam, lambdas, nlam * 8, hipMemcpyHostToDevice, s));
   const bool lowprec = mprec == GVT_F32;
   float *v32 = nullptr, *w32 = nullptr, *D32 = nullptr, *T32 = nullptr, *wv32 = nullptr;
+  const int64_t ldd32 = (d + 15) / 16 * 16, ldt32 = hom ? ldd32 : (t + 15) / 16 * 16;
   if (lowprec) {
     v32 = (float *)m_v32.ensure(n * 4);
     w32 = (float *)m_w32.ensure((size_t)(n + nv) * 4);
     wv32 = w32 + n;
-    D32 = (float *)m_D32.ensure((size_t)d * d * 4);
-    mr_to_f32_kernel<<<mg1(d * d), 256, 0, s>>>(D, ldd, D32, d, d);
+    D32 = (float *)m_D32.ensure((size_t)d * ldd32 * 4);
+    mr_to_f32_kernel<<<mg1(d * ldd32), 256, 0, s>>>(D, ldd, D32, ldd32, d, d);
     if (!hom) {
-      T32 = (float *)m_T32.ensure((size_t)t * t * 4);
-      mr_to_f32_kernel<<<mg1(t * t), 256, 0, s>>>(T, ldt, T32, t, t);
+      T32 = (float *)m_T32.ensure((size_t)t * ldt32 * 4);
+      mr_to_f32_kernel<<<mg1(t * ldt32), 256, 0, s>>>(T, ldt, T32, ldt32, t, t);
     } else {
       T32 = D32;
     }
@@ -581,7 +585,7 @@ int krr_minres_impl(int kind, const double *D, int64_t d, int64_t ldd, const dou
     P->gate = run;
     if (PV) PV->gate = run;
     if (lowprec) {
-      plan_execute(P, GVT_F32, D32, d, T32, t, v32, 1, n, w32, n, s);
+      plan_execute(P, GVT_F32, D32, ldd32, T32, ldt32, v32, 1, n, w32, n, s);
       mr_alpha_kernel<float><<<MNB, MB, 0, s>>>(w32, v, vprev, n, sho, q, part);
     } else {
       plan_execute(P, GVT_F64, D, ldd, T, ldt, v, 1, n, w, n, s);
@@ -589,7 +593,7 @@ int krr_minres_impl(int kind, const double *D, int64_t d, int64_t ldd, const dou
     }
     if (have_val) {
       // K_val v_k before v moves on
-      if (lowprec) plan_execute(PV, GVT_F32, D32, d, T32, t, v32, 1, n, wv32, nv, s);
+      if (lowprec) plan_execute(PV, GVT_F32, D32, ldd32, T32, ldt32, v32, 1, n, wv32, nv, s);
       else plan_execute(PV, GVT_F64, D, ldd, T, ldt, v, 1, n, wv, nv, s);
     }
     mr_beta_kernel<<<MNB, MB, 0, s>>>(v, n, part, q, part_b, alpha);
