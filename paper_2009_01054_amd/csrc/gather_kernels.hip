@@ -1006,6 +1006,161 @@ __device__ __forceinline__ void stage2y_tile(
   }
 }
 
+// The same tile for blocks of 4 RHS with its key chunks pipelined: chunk c + 1
+// is in flight while chunk c is walked.  The tile's F1 rows go from global
+// memory straight into one of two LDS buffers (an F1 row's chunk is 16 pieces
+// of 16 bytes, four rows per wave instruction) and each lane's S slice into one
+// of two register sets.  Where F1 rows do not start on 16-byte boundaries, and
+// for a piece that ends past the last key, the lanes stage their F1 pieces
+// themselves through registers (zeros past the last key); S rows are whole
+// zero-padded chunks.  With no staging registers in the walk a lane affords
+// twice the accumulators (half the passes over the tile's chunks) at two waves
+// per SIMD, and reads the F1 pieces of OB outputs together.  Every FMA is the
+// one stage2y_tile makes, in the same order: the results are bitwise equal.
+// (Measured, FP64 / FP32 4-RHS blocks on one MI355X, 200 000 outputs: 2000 x
+// 500 grid 446 / 170 us -> 284 / 116 us, 1000 x 1000 grid 237 / 94 us -> 162 /
+// 70 us.  The S chunks staged in LDS as well cost more LDS traffic than they
+// saved: 336 / 194 us on the 2000 x 500 grid at four waves per SIMD.)
+template <class T> struct S2ypCfg {
+  typedef S2yCfg<T, 4> B;
+  static constexpr int OPG = 2 * B::OPG;  // outputs per group per pass
+  static constexpr int OB = 4;            // outputs per batch of F1 reads
+  static constexpr int NP = kStage2MaxS * 16;  // F1 buffer: kStage2MaxS rows x 16 pieces
+  static_assert(OPG % OB == 0 && OPG % 4 == 0, "whole batches, whole 32-bit words of meta");
+};
+
+__host__ __device__ inline bool stage2y_rows16(const void *F1, int64_t ld1, size_t es) {
+  return reinterpret_cast<uintptr_t>(F1) % 16 == 0 && (ld1 * (int64_t)es) % 16 == 0;
+}
+
+template <class T>
+__device__ __forceinline__ void stage2y_tile_pipelined(
+    const T *__restrict__ F1, int64_t ld1, const int64_t *__restrict__ tileoff,
+    const int32_t *__restrict__ tilex, const int32_t *__restrict__ tilemax,
+    const uint8_t *__restrict__ grow, const int32_t *__restrict__ xrows,
+    const int32_t *__restrict__ perm, int nxb, const T *__restrict__ S, int64_t ldS, int64_t nsr,
+    int64_t nkeys, T coef, T *__restrict__ out, int64_t ldi, int64_t ldr, int t,
+    typename Vec16<T>::type *fb0, typename Vec16<T>::type *fb1, unsigned char (*meta)[S2ypCfg<T>::OPG]) {
+  constexpr int R = 4;
+  typedef S2yCfg<T, R> C;
+  typedef S2ypCfg<T> P;
+  typedef typename Vec16<T>::type V16;
+  constexpr int VEC = 16 / sizeof(T);
+  static_assert(C::KC * sizeof(T) == 256, "an F1 row's chunk is 16 pieces of 16 bytes");
+  static_assert(C::KPL * R == 4 * VEC, "a lane's S slice is four pieces");
+  const int maxcnt = tilemax[t];
+  if (maxcnt == 0) return;  // uniform: empty tile
+  const int gb = t / nxb;
+  const int64_t x0 = tilex[2 * t], nxr = tilex[2 * t + 1];
+  const int sub = threadIdx.x % C::LPO, grp = threadIdx.x / C::LPO;
+  const int gr = grow[(int64_t)t * C::NG + grp];  // rows by descending output count
+  const int64_t qb = tileoff[(int64_t)t * (C::NG + 1) + gr];
+  const int cnt = (int)(tileoff[(int64_t)t * (C::NG + 1) + gr + 1] - qb);
+  const int nch = (int)((nkeys + C::KC - 1) / C::KC);
+  const int nk = (int)nkeys;
+  const int wv = threadIdx.x / 64, ln = threadIdx.x % 64;
+  const int nri = (int)((nxr + 3) / 4);  // wave instructions per F1 chunk, four rows each
+  const bool rows16 = stage2y_rows16(F1, ld1, sizeof(T));
+  // chunk c of the tile's F1 rows into bd (row r at pieces 16 r .. 16 r + 15)
+  auto issue = [&](int c, V16 *bd) {
+    const int kp = c * C::KC + (ln & 15) * VEC;
+    for (int i = wv; i < nri; i += C::NT / 64) {
+      const int r = 4 * i + (ln >> 4);
+      const T *src = F1 + (x0 + (r < nxr ? r : 0)) * ld1;
+      V16 *dst = bd + 4 * i * 16;  // the wave's base: lane ln lands at dst[ln]
+      if (rows16 && kp + VEC <= nk) {
+        lds_load_row16(src + kp, dst);
+      } else {
+        V16 v;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) v[e] = kp + e < nk ? src[kp + e] : T(0);
+        dst[ln] = v;
+      }
+    }
+  };
+  // this lane's S slice of chunk c: keys c KC + sub KPL .. + KPL - 1, R values
+  // each (rows past the buffer read row 0: they have no outputs)
+  const int64_t yrow = (int64_t)gb * C::NG + gr;
+  const T *sl = S + (yrow < nsr ? yrow : 0) * ldS + sub * (C::KPL * R);
+  auto sload = [&](int c, T (&v)[C::KPL][R]) {
+#pragma unroll
+    for (int u0 = 0; u0 < 4; ++u0) {
+      const V16 w = *reinterpret_cast<const V16 *>(sl + (int64_t)c * (C::KC * R) + u0 * VEC);
+#pragma unroll
+      for (int u = 0; u < VEC; ++u) v[(u0 * VEC + u) / R][(u0 * VEC + u) % R] = w[u];
+    }
+  };
+  for (int pass0 = 0; pass0 < maxcnt; pass0 += P::OPG) {
+    const int npass = (cnt - pass0) < P::OPG ? (cnt - pass0) : P::OPG;  // may be <= 0
+    __syncthreads();  // the previous pass's reads of the buffers and meta are done
+    for (int o = sub; o < P::OPG; o += C::LPO)
+      meta[grp][o] = (o < npass) ? (unsigned char)(xrows[qb + pass0 + o] - x0) : 0;
+    // this group's F1 rows for the pass, packed four to a register
+    __syncthreads();
+    unsigned mp[P::OPG / 4];
+#pragma unroll
+    for (int q = 0; q < P::OPG / 4; ++q) mp[q] = *reinterpret_cast<const unsigned *>(&meta[grp][4 * q]);
+    T acc[P::OPG][R];
+#pragma unroll
+    for (int o = 0; o < P::OPG; ++o)
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[o][r] = T(0);
+    T sa[C::KPL][R], sb[C::KPL][R];
+    issue(0, fb0);
+    sload(0, sa);
+    // chunk c walks F1 buffer and S set c mod 2 while chunk c + 1 comes into
+    // the others; the loop is unrolled by two so each half names its buffers
+    // at compile time
+    auto walk = [&](int c, const V16 *bc, V16 *bn, T (&sv)[C::KPL][R], T (&svn)[C::KPL][R]) {
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies and loads of chunk c have landed
+      __syncthreads();                // everyone's have, and chunk c - 1 is walked
+      if (c + 1 < nch) {
+        issue(c + 1, bn);
+        sload(c + 1, svn);
+      }
+      // outputs in batches of OB behind one branch, their F1 reads in flight
+      // together; slots past npass read F1 row 0 (meta is 0 there) into
+      // accumulators that are never stored
+#pragma unroll
+      for (int o0 = 0; o0 < P::OPG; o0 += P::OB) {
+        if (o0 < npass) {
+          V16 f[P::OB];
+#pragma unroll
+          for (int q = 0; q < P::OB; ++q) {
+            const int o = o0 + q;
+            f[q] = bc[(int)((mp[o >> 2] >> (8 * (o & 3))) & 0xffu) * 16 + sub];
+          }
+#pragma unroll
+          for (int q = 0; q < P::OB; ++q)
+#pragma unroll
+            for (int kk = 0; kk < C::KPL; ++kk)
+#pragma unroll
+              for (int r = 0; r < R; ++r) acc[o0 + q][r] += f[q][kk] * sv[kk][r];
+        }
+      }
+    };
+    for (int c = 0; c < nch; c += 2) {
+      walk(c, fb0, fb1, sa, sb);
+      if (c + 1 < nch) walk(c + 1, fb1, fb0, sb, sa);
+    }
+    // lane partial sums meet inside each 16-lane row; slots past every
+    // group's count in this wave are skipped (wave-uniform bound)
+    const int wn = wave_max_of_groups(npass);
+#pragma unroll
+    for (int o = 0; o < P::OPG; ++o) {
+      if (o < wn) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[o][r] = row16_sum(acc[o][r]);
+      }
+      if (sub == 0 && o < npass) {
+        const int64_t i = perm[qb + pass0 + o];
+#pragma unroll
+        for (int r = 0; r < R; ++r) out[i * ldi + r * ldr] = coef * acc[o][r];
+      }
+    }
+  }
+}
+
 template <class T, int R>
 __global__ __launch_bounds__(kStage2Rows * 16) __attribute__((amdgpu_waves_per_eu(4))) void stage2y_kernel(
     const T *__restrict__ F1, int64_t ld1, const int64_t *__restrict__ tileoff,
@@ -1018,6 +1173,21 @@ __global__ __launch_bounds__(kStage2Rows * 16) __attribute__((amdgpu_waves_per_e
   if (gate && *gate == 0) return;
   stage2y_tile<T, R>(F1, ld1, tileoff, tilex, tilemax, grow, xrows, perm, nxb, S, ldS, nsr, nkeys, coef,
                      out, ldi, ldr, blockIdx.x, sm);
+}
+
+template <class T>
+__global__ __launch_bounds__(kStage2Rows * 16) __attribute__((amdgpu_waves_per_eu(2))) void stage2y_pipelined_kernel(
+    const T *__restrict__ F1, int64_t ld1, const int64_t *__restrict__ tileoff,
+    const int32_t *__restrict__ tilex, const int32_t *__restrict__ tilemax,
+    const uint8_t *__restrict__ grow, const int32_t *__restrict__ xrows,
+    const int32_t *__restrict__ perm, int nxb, const T *__restrict__ S, int64_t ldS, int64_t nsr,
+    int64_t nkeys, T coef, T *__restrict__ out, int64_t ldi, int64_t ldr,
+    const int *__restrict__ gate) {
+  __shared__ typename Vec16<T>::type fb0[S2ypCfg<T>::NP], fb1[S2ypCfg<T>::NP];
+  __shared__ __attribute__((aligned(4))) unsigned char meta[S2yCfg<T, 4>::NG][S2ypCfg<T>::OPG];
+  if (gate && *gate == 0) return;
+  stage2y_tile_pipelined<T>(F1, ld1, tileoff, tilex, tilemax, grow, xrows, perm, nxb, S, ldS, nsr, nkeys,
+                            coef, out, ldi, ldr, blockIdx.x, fb0, fb1, meta);
 }
 
 // ---------------------------------------------------------------------------
@@ -1261,6 +1431,20 @@ __global__ __launch_bounds__(kStage2Rows * 16) __attribute__((amdgpu_waves_per_e
                      d.U + r0 * d.ldu, 1, d.ldu, it.li, sm);
 }
 
+template <class T>
+__global__ __launch_bounds__(kStage2Rows * 16) __attribute__((amdgpu_waves_per_eu(2))) void group_stage2y_pipelined_kernel(
+    const GroupDesc<T> *__restrict__ desc, const GroupItem *__restrict__ items, int64_t r0,
+    const uint8_t *__restrict__ active) {
+  __shared__ typename Vec16<T>::type fb0[S2ypCfg<T>::NP], fb1[S2ypCfg<T>::NP];
+  __shared__ __attribute__((aligned(4))) unsigned char meta[S2yCfg<T, 4>::NG][S2ypCfg<T>::OPG];
+  const GroupItem it = items[blockIdx.x];
+  if (active && !active[it.p]) return;
+  const GroupDesc<T> &d = desc[it.p];
+  stage2y_tile_pipelined<T>(d.F1, d.ld1, d.tileoff[1], d.tiley[1], d.tilemax[1], d.grow[1], d.yrows[1],
+                            d.perm_out[1], (int)d.nyb[1], d.S, sbuf_row_ld<T>(d.nkeys, 4), d.nrows, d.nkeys, T(1),
+                            d.U + r0 * d.ldu, 1, d.ldu, it.li, fb0, fb1, meta);
+}
+
 // ===========================================================================
 // Launchers
 // ===========================================================================
@@ -1303,8 +1487,14 @@ static std::atomic<int> g_s2_dual{-1};
 // GVT_STAGE1_SLICE overrides), with about this many workgroups per launch
 // (kStage1SliceWgs; GVT_STAGE1_SLICE_WGS).
 static std::atomic<int> g_s1_slice{kStage1Slice}, g_s1_slice_wgs{kStage1SliceWgs};
+// Stage 2 of 4-RHS blocks with its key chunks pipelined (GVT_STAGE2Y_PIPELINED=0
+// switches it off).
+static std::atomic<int> g_s2y_pipe{1};
+static int stage2y_use_pipelined() { return g_s2y_pipe.load(std::memory_order_relaxed); }
 
 void refresh_launch_knobs() {
+  const char *e9 = std::getenv("GVT_STAGE2Y_PIPELINED");
+  g_s2y_pipe.store(e9 ? (std::atoi(e9) != 0) : 1, std::memory_order_relaxed);
   const char *e8 = std::getenv("GVT_STAGE2_DUAL");
   g_s2_dual.store(e8 ? (std::atoi(e8) != 0) : -1, std::memory_order_relaxed);
   const char *e6 = std::getenv("GVT_STAGE1_SLICE");
@@ -1520,7 +1710,12 @@ void launch_stage2y(const T *F1, int64_t ld1, const int64_t *tileoff, const int3
   if (ntiles <= 0) return;
   dim3 grid((unsigned)ntiles);
   switch (R) {
-    case 4: stage2y_kernel<T, 4><<<grid, kStage2Rows * 16, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, grow, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate); break;
+    case 4:
+      if (stage2y_use_pipelined())
+        stage2y_pipelined_kernel<T><<<grid, kStage2Rows * 16, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, grow, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate);
+      else
+        stage2y_kernel<T, 4><<<grid, kStage2Rows * 16, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, grow, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate);
+      break;
     case 8: stage2y_kernel<T, 8><<<grid, kStage2Rows * 16, 0, s>>>(F1, ld1, tileoff, tilex, tilemax, grow, xrows, perm, nxb, S, ldS, nsr, nkeys, coef, out, ldi, ldr, gate); break;
     default: throw Error{GVT_ERR_ARG, "internal: S-row grouped stage 2 needs a block of 4 or 8 RHS"};
   }
@@ -1667,7 +1862,12 @@ void launch_group_stage2(const GroupDesc<T> *desc, const GroupItem *items, int64
   switch (R) {
     case 1: group_stage2_kernel<T, 1><<<g, nt, 0, s>>>(desc, items, r0, active); break;
     case 2: group_stage2_kernel<T, 2><<<g, nt, 0, s>>>(desc, items, r0, active); break;
-    case 4: group_stage2y_kernel<T, 4><<<g, kStage2Rows * 16, 0, s>>>(desc, items, r0, active); break;
+    case 4:
+      if (stage2y_use_pipelined())
+        group_stage2y_pipelined_kernel<T><<<g, kStage2Rows * 16, 0, s>>>(desc, items, r0, active);
+      else
+        group_stage2y_kernel<T, 4><<<g, kStage2Rows * 16, 0, s>>>(desc, items, r0, active);
+      break;
     case 8: group_stage2y_kernel<T, 8><<<g, kStage2Rows * 16, 0, s>>>(desc, items, r0, active); break;
     default: throw Error{GVT_ERR_ARG, "internal: unsupported RHS block in grouped stage 2"};
   }

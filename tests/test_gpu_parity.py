@@ -700,6 +700,54 @@ def test_stage2_dual_tiles_vs_oracle(gvt, monkeypatch, prec, case, order):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["het77x131", "het130x64", "het523x611", "het262x96pad", "fused600"])
+@pytest.mark.parametrize("nrhs", [4, 5, 8])
+def test_stage2y_pipelined_vs_oracle(gvt, monkeypatch, prec, case, nrhs):
+    # stage 2 of 4-RHS blocks with its key chunks pipelined (F1 chunks copied into LDS, S
+    # slices into registers, one chunk ahead) against the register-staged kernel, bitwise
+    # (each lane makes the same FMAs in the same order), and against the oracle: key counts
+    # that are not a multiple of the 16-byte piece (the last piece staged by its lanes),
+    # ragged tiles, base matrices whose rows do not start on 16-byte boundaries (a view with
+    # row stride 263 / 97: every F1 piece staged by its lanes), a fused multi-kind plan, and
+    # 5 or 8 RHS (blocks of 4 and 1, two blocks of 4)
+    monkeypatch.setenv("GVT_MAX_RHS_BLOCK", "4")
+    monkeypatch.setenv("GVT_DENSE_TILES", "0")
+    kinds, flags = ["kronecker"], 0
+    dt = tdt(prec)
+    r = np.random.default_rng([13, nrhs, len(case)])
+    if case == "fused600":
+        kinds, flags = ["symmetric", "antisymmetric", "cartesian", "poly2d"], gvt.FLAG_SYMMETRIC_BASES
+        p = W.make_homogeneous(98, nrhs, 600, 15000, 5, n_out=12000, kernel="gaussian")
+        T = None
+    else:
+        m, q, n = {"het77x131": (77, 131, 3000), "het130x64": (130, 64, 5000),
+                   "het523x611": (523, 611, 60000), "het262x96pad": (262, 96, 8000)}[case]
+        p = W.make_heterogeneous(99, nrhs, m, q, n, 6)
+        T = p["T"]
+    v = r.standard_normal((len(p["c"]), nrhs))
+    if case == "het262x96pad":
+        # row strides 263 and 97 elements: rows off 16-byte boundaries in both precisions
+        Dbig = torch.zeros((262, 263), dtype=dt, device="cuda")
+        Tbig = torch.zeros((96, 97), dtype=dt, device="cuda")
+        Dbig[:, :262] = dev(p["D"], dt)
+        Tbig[:, :96] = dev(T, dt)
+        Dd, Td = Dbig[:, :262], Tbig[:, :96]
+    else:
+        Dd = dev(p["D"], dt)
+        Td = Dd if T is None else dev(T, dt)
+    args = ((idx(p["a"]), idx(p["b"])), (idx(p["c"]), idx(p["e"])), dev(v, dt))
+    res = {}
+    for pipe in ("1", "0"):
+        monkeypatch.setenv("GVT_STAGE2Y_PIPELINED", pipe)
+        res[pipe] = gvt.gvt_pairwise_matvec(kinds, Dd, Td, *args, flags=flags)
+    for k, kind in enumerate(kinds):
+        ref = oracle.pairwise_matvec(kind, p["D"], T, (p["a"], p["b"]), (p["c"], p["e"]), v)
+        got = res["1"][k].cpu().double().numpy()
+        assert relerr(got, ref) < TOL[prec], kind
+        assert torch.equal(res["1"][k], res["0"][k]), kind
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("m,q", [(700, 300), (33, 900), (300, 40), (5, 700)])
 @pytest.mark.parametrize("order", [2, 4])
 def test_stage2_xcd_orders_bitwise(gvt, prec, m, q, order, monkeypatch):
