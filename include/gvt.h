@@ -59,6 +59,8 @@
  *    tiles dealt to the XCDs by S block / by F1 block; unset: by working set),
  *    GVT_STAGE2_DUAL (0/1: stage 2 with one RHS stages both operands of
  *    128 x 128 tiles in LDS; unset: at low output density),
+ *    GVT_STAGE2Y_PIPELINED (0/1, default 1: stage 2 of 4-RHS blocks copies
+ *    the next key chunk while it walks the current one),
  *    GVT_MAX_RHS_BLOCK[_F64|_F32] (largest RHS block of a pass),
  *    GVT_PLAN_DEVICE (0/1: plan index work on the host / device).  All of them
  *    but the RHS block give the same products bit for bit (the block size

@@ -3,43 +3,43 @@
 // launch, 16 bytes of rows per lane) and the keys each wave walks in stage 1.
 // Written by paper_2009_01054_amd/tune.py on gfx950; measured times (ms):
 //   SLICE: ridge f64 x1; ridge f32 x1; batched f64 (64 problems, 8 RHS), per iteration
-//          0: 0.1126, 0.0847, 9.0405  (score 1.228)
-//          1: 0.0896, 0.0679, 7.6560  (score 1.000)
+//          0: 0.1111, 0.0835, 9.0360  (score 1.208)
+//          1: 0.0919, 0.0673, 7.6964  (score 1.000)
 //   SLICEWGS: ridge f64 x1; ridge f32 x1
-//        128: 0.1024, 0.0725  (score 1.127)
-//        256: 0.0885, 0.0663  (score 1.002)
-//        512: 0.0909, 0.0660  (score 1.014)
+//        128: 0.1046, 0.0735  (score 1.136)
+//        256: 0.0901, 0.0663  (score 1.002)
+//        512: 0.0921, 0.0661  (score 1.011)
 //   WIDE: ridge f64 x1; ridge f32 x1
-//          0: 0.1159, 0.0841  (score 1.106)
-//          1: 0.1018, 0.0783  (score 1.000)
+//          0: 0.1178, 0.0845  (score 1.110)
+//          1: 0.1026, 0.0787  (score 1.000)
 //   KPW: ridge f64 x1; ridge f32 x1
-//          1: 0.1012, 0.0782  (score 1.000)
-//          2: 0.1043, 0.0790  (score 1.021)
-//          4: 0.1093, 0.0924  (score 1.130)
+//          1: 0.1024, 0.0782  (score 1.000)
+//          2: 0.1064, 0.0794  (score 1.027)
+//          4: 0.1105, 0.0913  (score 1.122)
 //   R1: ridge f64 x1; ridge f32 x1; batched f64 (64 problems, 8 RHS), per iteration
-//          8: 0.1095, 0.1150, 7.6473  (score 1.292)
-//         16: 0.0903, 0.0663, 7.6420  (score 1.009)
-//         32: 0.0892, 0.0664, 7.6991  (score 1.007)
-//         64: 0.0887, 0.0659, 7.6905  (score 1.002)
-//        128: 0.0890, 0.0666, 7.6941  (score 1.007)
+//          8: 0.1118, 0.1105, 7.6529  (score 1.273)
+//         16: 0.0905, 0.0668, 7.6706  (score 1.004)
+//         32: 0.0910, 0.0668, 7.6751  (score 1.005)
+//         64: 0.0901, 0.0672, 7.6821  (score 1.004)
+//        128: 0.0908, 0.0666, 7.6806  (score 1.004)
 //   MAXR64: ridge f64 x8; batched f64 (64 problems, 8 RHS), per iteration
-//          2: 0.7641, 7.6564  (score 1.000)
-//          4: 1.0073, 9.2551  (score 1.262)
-//          8: 1.6973, 13.6275  (score 1.988)
+//          2: 0.7698, 7.6857  (score 1.047)
+//          4: 0.7018, 8.6544  (score 1.061)
+//          8: 1.7399, 13.6073  (score 2.095)
 //   MAXR32: ridge f32 x8; batched f32 (64 problems, 8 RHS), per iteration
-//          2: 0.5030, 5.2170  (score 1.152)
-//          4: 0.4014, 4.9257  (score 1.000)
-//          8: 0.5300, 5.6682  (score 1.233)
+//          2: 0.4884, 5.2164  (score 1.396)
+//          4: 0.3073, 4.2559  (score 1.000)
+//          8: 0.5343, 5.1715  (score 1.454)
 //   R8: ridge f64 x8; ridge f32 x8; batched f32 (64 problems, 8 RHS), per iteration
-//          2: 0.7634, 0.6074, 6.7219  (score 1.295)
-//          4: 0.7671, 0.4399, 5.4001  (score 1.083)
-//          8: 0.7576, 0.4654, 4.7869  (score 1.055)
-//         16: 0.7683, 0.3960, 4.9243  (score 1.014)
-//         32: 0.7588, 0.3979, 4.8987  (score 1.010)
+//          2: 0.7697, 0.5493, 7.4313  (score 1.462)
+//          4: 0.7689, 0.4653, 5.6606  (score 1.263)
+//          8: 0.7668, 0.3992, 4.7361  (score 1.130)
+//         16: 0.7681, 0.3066, 4.3063  (score 1.003)
+//         32: 0.7688, 0.3070, 4.2745  (score 1.001)
 #pragma once
 
 namespace gvt {
-constexpr double kStage2TargetR1 = 64.0;
+constexpr double kStage2TargetR1 = 16.0;
 constexpr double kStage2TargetR8 = 32.0;
 constexpr int kStage1KeysPerWave = 1;
 constexpr int kStage1Wide = 1;
@@ -52,10 +52,10 @@ constexpr int kMaxRhsBlockF32 = 4;
 // (complete data, 4096 x 2048), and the output-tile count at which a GEMM
 // keeps the matrix cores busy (from the ridge workload's shapes, 64 tiles).
 constexpr double kGatherRateF64 = 9.97e+12;
-constexpr double kGatherRateF32 = 1.34e+13;
-constexpr double kTilesRateF64 = 4.32e+13;
-constexpr double kTilesRateF32 = 1.04e+14;
-constexpr double kTilesFull = 150.9;
+constexpr double kGatherRateF32 = 1.37e+13;
+constexpr double kTilesRateF64 = 4.5e+13;
+constexpr double kTilesRateF32 = 1.01e+14;
+constexpr double kTilesFull = 142.6;
 // Batched CG with FP32 products: a problem whose active systems all have
 // recurrence residuals below this level continues with FP64 products
 // (GVT_F32_SWITCH overrides; 0 keeps FP32 products until certification).
