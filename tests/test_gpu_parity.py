@@ -493,6 +493,29 @@ def test_cg_batched_stage1_slice_bitwise(gvt, monkeypatch, prec):
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cg_batched_stage2y_pipelined_bitwise(gvt, monkeypatch, prec):
+    # the grouped 4-RHS stage 2 with pipelined key chunks against the register-staged one
+    # over problems of odd and even sizes (FP64 bases of odd size: rows off 16-byte
+    # boundaries, staged by the lanes), 8 systems per problem in two blocks of 4: the whole
+    # solve agrees bit for bit
+    monkeypatch.setenv("GVT_MAX_RHS_BLOCK", "4")
+    shapes = [(100, 80, 3000), (201, 150, 6000), (77, 131, 4000), (60, 50, 200), (90, 300, 5000),
+              (33, 47, 1200), (130, 120, 9000)]
+    probs = _batch(102, shapes)
+    lams = [1e-1, 1.0, 10.0, 0.5, 3.0, 0.2, 2.0, 30.0]
+    mp = gvt.F32 if prec == "f32" else gvt.F64
+    res = []
+    for pipe in ("0", "1"):
+        monkeypatch.setenv("GVT_STAGE2Y_PIPELINED", pipe)
+        res.append(gvt.gvt_krr_cg_batched("kronecker", _dev_problems(probs), lams, max_iter=60, tol=1e-8,
+                                          check_every=4, matvec_prec=mp))
+    (A0, i0, r0, c0), (A1, i1, r1, c1) = res
+    assert c0 == c1 and (i0 == i1).all() and (r0 == r1).all()
+    for x, y in zip(A0, A1):
+        assert torch.equal(x, y)
+
+
 def test_cg_batched_large_problem_matches_single_solves(gvt):
     # a problem with 30 000 pairs over 760 x 740 bases beside small ones: the grouped launches
     # (work lists of uneven length, both stage-1 walks) give the problem-by-problem solutions
