@@ -62,7 +62,9 @@
  *    GVT_STAGE2Y_PIPELINED (0/1, default 1: stage 2 of 4-RHS blocks copies
  *    the next key chunk while it walks the current one),
  *    GVT_MAX_RHS_BLOCK[_F64|_F32] (largest RHS block of a pass),
- *    GVT_PLAN_DEVICE (0/1: plan index work on the host / device).  All of them
+ *    GVT_PLAN_DEVICE (0/1: plan index work on the host / device),
+ *    GVT_PLAN_LIBRARY_SORT (1: device plans sort with hipCUB's radix sort
+ *    instead of the library's own).  All of them
  *    but the RHS block give the same products bit for bit (the block size
  *    changes which lanes sum which keys); GVT_PLAN_TIMING=1 prints the host
  *    time of each plan phase.

@@ -5,7 +5,9 @@
 // array equals the one a stable host counting sort gives.
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
 #include <climits>
+#include <cstdlib>
 
 #include "kernels.h"
 #include "plan_dev.h"
@@ -62,9 +64,136 @@ __global__ __launch_bounds__(PB) void probe_kernel(ProbeArgs a, unsigned long lo
   if (mism) *notnat = 1;
 }
 
-// ---- sorting helpers ----------------------------------------------------------
+// ---- sorting -----------------------------------------------------------------------
+// Stable LSD radix sort of (key, value) pairs by the low nbits bits of the key,
+// in passes of digits of at most kRsMaxW bits (the key width split evenly).  A
+// pass is three launches with no waiting between workgroups:
+//   count:   per tile of kRsTile pairs, the count of each digit value;
+//   tscan:   per digit value (one thread each), the exclusive prefix of its
+//            counts over the tiles, in place, and its total;
+//   scatter: per tile, every pair goes to base(digit) + prefix(digit, tile) +
+//            the pairs of the same digit before it in the tile, where base is
+//            the exclusive prefix of the totals (scanned by each block).
+// The scatter walks its tile in rounds of kRsT pairs; within a round a pair's
+// rank among its wave's pairs of the same digit comes from ballots on the digit
+// bits, and the counts of the waves before it from per-wave counts in LDS
+// tagged with the round.  Pairs keep their order within a digit in every pass,
+// so the result is the unique stable order, as a library sort's.
+constexpr int kRsT = 256;                 // threads per block
+constexpr int kRsRounds = 8;              // rounds of kRsT pairs per tile
+constexpr int kRsTile = kRsT * kRsRounds;
+constexpr int kRsMaxW = 10;               // widest digit
+constexpr int kRsMaxB = 1 << kRsMaxW;
+
 template <class K>
-size_t sort_temp_bytes(int64_t n) {
+__global__ __launch_bounds__(kRsT) void rs_count_kernel(const K *__restrict__ key, int64_t n, int sh, int width,
+                                                        int64_t nt, uint32_t *__restrict__ cnt) {
+  __shared__ uint32_t h[kRsMaxB];
+  const int nb = 1 << width;
+  for (int b = threadIdx.x; b < nb; b += kRsT) h[b] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+  for (int j = 0; j < kRsRounds; ++j) {
+    const int64_t p = base + (int64_t)j * kRsT + threadIdx.x;
+    if (p < n) atomicAdd(&h[(int)((key[p] >> sh) & (K)(nb - 1))], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += kRsT) cnt[(int64_t)b * nt + blockIdx.x] = h[b];
+}
+
+__global__ __launch_bounds__(kRsT) void rs_tscan_kernel(uint32_t *__restrict__ cnt, int64_t nt, int nb,
+                                                        uint32_t *__restrict__ total) {
+  const int b = blockIdx.x * kRsT + threadIdx.x;
+  if (b >= nb) return;
+  uint32_t *c = cnt + (int64_t)b * nt;
+  uint32_t run = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    const uint32_t e = c[t];
+    c[t] = run;
+    run += e;
+  }
+  total[b] = run;
+}
+
+template <class K>
+__global__ __launch_bounds__(kRsT) void rs_scatter_kernel(const K *__restrict__ kin, const int32_t *__restrict__ vin,
+                                                          K *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
+                                                          int sh, int width, int64_t nt,
+                                                          const uint32_t *__restrict__ cnt,
+                                                          const uint32_t *__restrict__ total) {
+  constexpr int NW = kRsT / 64;
+  __shared__ uint32_t run[kRsMaxB];
+  __shared__ uint32_t wc[NW][kRsMaxB];  // (round + 1) << 8 | the wave's count of a digit
+  __shared__ uint32_t part[kRsT];
+  const int nb = 1 << width;
+  const int per = nb / kRsT > 0 ? nb / kRsT : 1;  // digits per thread in the base scan
+  // base(digit): exclusive prefix of the totals; each thread sums `per` digits
+  uint32_t s = 0;
+  const int b0 = threadIdx.x * per;
+  for (int b = b0; b < b0 + per && b < nb; ++b) s += total[b];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < kRsT; o <<= 1) {
+    const uint32_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t acc = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int b = b0; b < b0 + per && b < nb; ++b) {
+    run[b] = acc + cnt[(int64_t)b * nt + blockIdx.x];
+    acc += total[b];
+  }
+  for (int i = threadIdx.x; i < NW * kRsMaxB; i += kRsT) (&wc[0][0])[i] = 0;
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const unsigned long long below = (1ull << lane) - 1;
+  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+  for (int j = 0; j < kRsRounds; ++j) {
+    const int64_t p = base + (int64_t)j * kRsT + threadIdx.x;
+    const bool valid = p < n;
+    const K k = valid ? kin[p] : K(0);
+    const int32_t v = valid ? vin[p] : 0;
+    const int d = valid ? (int)((k >> sh) & (K)(nb - 1)) : nb;  // nb: past the end
+    // the lanes of this wave whose pairs have the same digit (and validity)
+    unsigned long long same = ~0ull;
+    for (int bit = 0; bit <= width; ++bit) {
+      const unsigned long long bl = __ballot((d >> bit) & 1);
+      same &= ((d >> bit) & 1) ? bl : ~bl;
+    }
+    const int rank = __popcll(same & below);
+    const uint32_t tag = (uint32_t)(j + 1) << 8;
+    __syncthreads();  // the previous round's readers of run and wc are done
+    if (valid && rank == 0) wc[w][d] = tag | (uint32_t)__popcll(same);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + (uint32_t)rank;
+      for (int w2 = 0; w2 < w; ++w2) {
+        const uint32_t e = wc[w2][d];
+        if ((e & ~0xffu) == tag) pos += e & 0xffu;
+      }
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kRsT) {
+      uint32_t add = 0;
+      for (int w2 = 0; w2 < NW; ++w2) {
+        const uint32_t e = wc[w2][b];
+        if ((e & ~0xffu) == tag) add += e & 0xffu;
+      }
+      run[b] += add;
+    }
+  }
+}
+
+// GVT_PLAN_LIBRARY_SORT=1: the library's radix sort (hipCUB) instead, for comparison
+bool use_library_sort() {
+  const char *e = std::getenv("GVT_PLAN_LIBRARY_SORT");
+  return e && std::atoi(e) != 0;
+}
+
+template <class K>
+size_t library_sort_bytes(int64_t n) {
   size_t b = 0;
   GVT_HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const K *)nullptr, (K *)nullptr,
                                                    (const int32_t *)nullptr, (int32_t *)nullptr,
@@ -73,12 +202,58 @@ size_t sort_temp_bytes(int64_t n) {
 }
 
 template <class K>
+size_t radix_sort_bytes(int64_t n) {
+  const int64_t nt = ceil_div(n > 0 ? n : 1, kRsTile);
+  return align256(n * sizeof(K)) + align256(n * sizeof(int32_t)) + align256((size_t)kRsMaxB * nt * 4) +
+         align256((size_t)kRsMaxB * 4);
+}
+
+template <class K>
+size_t sort_temp_bytes(int64_t n) {
+  return std::max(radix_sort_bytes<K>(n), library_sort_bytes<K>(n));
+}
+
+template <class K>
+void radix_sort_pairs(const K *kin, K *kout, const int32_t *vin, int32_t *vout, int64_t n, int nbits, void *temp,
+                      hipStream_t s) {
+  GVT_REQUIRE(n < ((int64_t)1 << 31), GVT_ERR_ARG, "internal: sort of 2^31 pairs or more");
+  const int64_t nt = ceil_div(n, kRsTile);
+  char *t = static_cast<char *>(temp);
+  K *ktmp = reinterpret_cast<K *>(t);
+  int32_t *vtmp = reinterpret_cast<int32_t *>(t + align256(n * sizeof(K)));
+  uint32_t *cnt = reinterpret_cast<uint32_t *>(t + align256(n * sizeof(K)) + align256(n * 4));
+  uint32_t *total = cnt + align256((size_t)kRsMaxB * nt * 4) / 4;
+  const int bits = nbits > 0 ? nbits : 1;
+  const int passes = (bits + kRsMaxW - 1) / kRsMaxW;
+  const int width = (bits + passes - 1) / passes;
+  const K *ks = kin;
+  const int32_t *vs = vin;
+  for (int q = 0; q < passes; ++q) {
+    const int sh = q * width, wq = std::min(width, bits - sh);
+    // the last pass writes the output; the passes alternate between it and the temporaries
+    const bool to_out = (passes - 1 - q) % 2 == 0;
+    K *kd = to_out ? kout : ktmp;
+    int32_t *vd = to_out ? vout : vtmp;
+    rs_count_kernel<K><<<(unsigned)nt, kRsT, 0, s>>>(ks, n, sh, wq, nt, cnt);
+    rs_tscan_kernel<<<(unsigned)ceil_div(1 << wq, kRsT), kRsT, 0, s>>>(cnt, nt, 1 << wq, total);
+    rs_scatter_kernel<K><<<(unsigned)nt, kRsT, 0, s>>>(ks, vs, kd, vd, n, sh, wq, nt, cnt, total);
+    ks = kd;
+    vs = vd;
+  }
+  check_launch(s);
+}
+
+template <class K>
 void sort_pairs(const K *kin, K *kout, const int32_t *vin, int32_t *vout, int64_t n, int nbits,
                 void *temp, size_t temp_bytes, hipStream_t s) {
   if (n <= 0) return;
-  size_t tb = temp_bytes;
-  GVT_HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(temp, tb, kin, kout, vin, vout, (int)n, 0,
-                                                   nbits > 0 ? nbits : 1, s));
+  if (use_library_sort()) {
+    size_t tb = temp_bytes;
+    GVT_HIP_CHECK(hipcub::DeviceRadixSort::SortPairs(temp, tb, kin, kout, vin, vout, (int)n, 0,
+                                                     nbits > 0 ? nbits : 1, s));
+    return;
+  }
+  radix_sort_pairs<K>(kin, kout, vin, vout, n, nbits, temp, s);
 }
 
 __global__ void iota_kernel(int32_t *v, int64_t n) {

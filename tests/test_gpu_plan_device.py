@@ -159,6 +159,31 @@ def test_wide_key_range(gvt, monkeypatch):
     assert relerr(d.cpu().numpy(), ref) < 1e-10
 
 
+@pytest.mark.parametrize("n", [1, 2047, 2048, 2049, 300001])
+def test_own_sort_matches_library_sort(gvt, monkeypatch, n):
+    # the plan's stable radix sort (one to three passes of up to 10-bit digits, tiles of
+    # 2048 pairs, a ragged last tile) against the library's radix sort on device-built
+    # plans: a stable sort's order is unique, so the products agree bit for bit
+    r = np.random.default_rng([16, n])
+    m, q = 1500, 900
+    D = W.gaussian_kernel(r.standard_normal((m, 3)))
+    T = W.gaussian_kernel(r.standard_normal((q, 3)))
+    c = r.integers(0, m, n).astype(np.int32)
+    e = r.integers(0, q, n).astype(np.int32)
+    a = r.integers(0, m, 5000).astype(np.int32)
+    b = r.integers(0, q, 5000).astype(np.int32)
+    v = r.standard_normal((n, 2))
+    Dd, Td = dev(D), dev(T)
+    monkeypatch.setenv("GVT_PLAN_DEVICE", "1")
+    res = []
+    for lib in ("1", "0"):
+        monkeypatch.setenv("GVT_PLAN_LIBRARY_SORT", lib)
+        res.append(gvt.gvt_matvec(Dd, Td, (idx(a), idx(b)), (idx(c), idx(e)), dev(v)))
+    assert torch.equal(res[0], res[1])
+    ref = oracle.pairwise_matvec("kronecker", D, T, (a, b), (c, e), v)
+    assert relerr(res[1].cpu().numpy(), ref) < 1e-10
+
+
 def test_index_errors_on_device(gvt, monkeypatch):
     monkeypatch.setenv("GVT_PLAN_DEVICE", "1")
     D = dev(np.eye(5)); T = dev(np.eye(4))
