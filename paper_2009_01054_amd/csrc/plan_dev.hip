@@ -69,7 +69,7 @@ __global__ __launch_bounds__(PB) void probe_kernel(ProbeArgs a, unsigned long lo
 // in passes of digits of at most kRsMaxW bits (the key width split evenly).  A
 // pass is three launches with no waiting between workgroups:
 //   count:   per tile of kRsTile pairs, the count of each digit value;
-//   tscan:   per digit value (one thread each), the exclusive prefix of its
+//   tscan:   per digit value (one wave each), the exclusive prefix of its
 //            counts over the tiles, in place, and its total;
 //   scatter: per tile, every pair goes to base(digit) + prefix(digit, tile) +
 //            the pairs of the same digit before it in the tile, where base is
@@ -77,10 +77,11 @@ __global__ __launch_bounds__(PB) void probe_kernel(ProbeArgs a, unsigned long lo
 // The scatter walks its tile in rounds of kRsT pairs; within a round a pair's
 // rank among its wave's pairs of the same digit comes from ballots on the digit
 // bits, and the counts of the waves before it from per-wave counts in LDS
-// tagged with the round.  Pairs keep their order within a digit in every pass,
+// tagged with the round; after the round each (digit, wave) leader adds its
+// count to the digit's running position (integer LDS atomics).  Pairs keep their order within a digit in every pass,
 // so the result is the unique stable order, as a library sort's.
 constexpr int kRsT = 256;                 // threads per block
-constexpr int kRsRounds = 8;              // rounds of kRsT pairs per tile
+constexpr int kRsRounds = 4;  // rounds of kRsT pairs per tile (ridge plans: 0.187 ms, 0.194 with 2, 0.206 with 8)
 constexpr int kRsTile = kRsT * kRsRounds;
 constexpr int kRsMaxW = 10;               // widest digit
 constexpr int kRsMaxB = 1 << kRsMaxW;
@@ -101,18 +102,25 @@ __global__ __launch_bounds__(kRsT) void rs_count_kernel(const K *__restrict__ ke
   for (int b = threadIdx.x; b < nb; b += kRsT) cnt[(int64_t)b * nt + blockIdx.x] = h[b];
 }
 
+// one wave per digit value: 64 tiles' counts per step, scanned across the wave
 __global__ __launch_bounds__(kRsT) void rs_tscan_kernel(uint32_t *__restrict__ cnt, int64_t nt, int nb,
                                                         uint32_t *__restrict__ total) {
-  const int b = blockIdx.x * kRsT + threadIdx.x;
-  if (b >= nb) return;
+  const int b = blockIdx.x * (kRsT / 64) + threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (b >= nb) return;  // wave-uniform
   uint32_t *c = cnt + (int64_t)b * nt;
-  uint32_t run = 0;
-  for (int64_t t = 0; t < nt; ++t) {
-    const uint32_t e = c[t];
-    c[t] = run;
-    run += e;
+  uint32_t carry = 0;
+  for (int64_t t0 = 0; t0 < nt; t0 += 64) {
+    const int64_t t = t0 + lane;
+    const uint32_t e = t < nt ? c[t] : 0u;
+    uint32_t x = e;  // inclusive prefix over the wave
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (t < nt) c[t] = carry + x - e;
+    carry += __shfl(x, 63, 64);
   }
-  total[b] = run;
+  if (lane == 0) total[b] = carry;
 }
 
 template <class K>
@@ -174,15 +182,9 @@ __global__ __launch_bounds__(kRsT) void rs_scatter_kernel(const K *__restrict__ 
       kout[pos] = k;
       vout[pos] = v;
     }
-    __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += kRsT) {
-      uint32_t add = 0;
-      for (int w2 = 0; w2 < NW; ++w2) {
-        const uint32_t e = wc[w2][b];
-        if ((e & ~0xffu) == tag) add += e & 0xffu;
-      }
-      run[b] += add;
-    }
+    __syncthreads();  // every position of the round is taken
+    // each (digit, wave) leader moves its digit's running position past its pairs
+    if (valid && rank == 0) atomicAdd(&run[d], (uint32_t)__popcll(same));
   }
 }
 
@@ -235,7 +237,7 @@ void radix_sort_pairs(const K *kin, K *kout, const int32_t *vin, int32_t *vout, 
     K *kd = to_out ? kout : ktmp;
     int32_t *vd = to_out ? vout : vtmp;
     rs_count_kernel<K><<<(unsigned)nt, kRsT, 0, s>>>(ks, n, sh, wq, nt, cnt);
-    rs_tscan_kernel<<<(unsigned)ceil_div(1 << wq, kRsT), kRsT, 0, s>>>(cnt, nt, 1 << wq, total);
+    rs_tscan_kernel<<<(unsigned)ceil_div(1 << wq, kRsT / 64), kRsT, 0, s>>>(cnt, nt, 1 << wq, total);
     rs_scatter_kernel<K><<<(unsigned)nt, kRsT, 0, s>>>(ks, vs, kd, vd, n, sh, wq, nt, cnt, total);
     ks = kd;
     vs = vd;
@@ -360,14 +362,18 @@ __global__ void tile_order_kernel(const int64_t *__restrict__ sgk, int64_t ntile
 __global__ void tile_meta_kernel(const int64_t *__restrict__ sgk, TileDims td,
                                  int64_t *__restrict__ toff, int32_t *__restrict__ tiley,
                                  int32_t *__restrict__ tilemax) {
-  const int64_t R = td.rows_per_tile;
+  constexpr int R = kStage2Rows;  // the caller checks td.rows_per_tile
   for (int64_t t = (int64_t)blockIdx.x * PB + threadIdx.x; t < td.ntiles;
        t += (int64_t)gridDim.x * PB) {
+    int64_t b[R + 1];  // the tile's group starts, all loads in flight together
+#pragma unroll
+    for (int g = 0; g <= R; ++g) b[g] = sgk[t * R + g];
     int32_t mx = 0;
-    for (int64_t g = 0; g <= R; ++g) {
-      toff[t * (R + 1) + g] = sgk[t * R + g];
+#pragma unroll
+    for (int g = 0; g <= R; ++g) {
+      toff[t * (R + 1) + g] = b[g];
       if (g < R) {
-        const int64_t c = sgk[t * R + g + 1] - sgk[t * R + g];
+        const int64_t c = b[g + 1] - b[g];
         mx = c > mx ? (int32_t)c : mx;
       }
     }
