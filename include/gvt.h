@@ -487,8 +487,11 @@ int gvt_erm_newton(int kind, int loss, const double *D, int64_t d, int64_t ldd, 
  * of each stage group to stage_ms[4] (host): [0] input gather + segment sums
  * + one-factor GEMVs, [1] stage 1 (scatters into S), [2] stage 2 (gather-dot
  * of every two-factor term), [3] match terms, gathers and the per-kind
- * combination.  nrhs <= 8.  Gather path only (GVT_ERR_UNSUPPORTED for a
- * complete-data plan).
+ * combination.  Stage 2's launches run 8 times back to back within their
+ * events and [2] is the mean per product, free of the events' own overhead
+ * (every stage-2 kernel overwrites its outputs, so U is the product).
+ * nrhs <= 8.  Gather path only (GVT_ERR_UNSUPPORTED for a complete-data
+ * plan).
  */
 int gvt_plan_profile(gvt_plan_t plan, int prec, const void *D, int64_t ldd, const void *T,
                      int64_t ldt, const void *V, int64_t nrhs, int64_t ldv, void *U, int64_t ldu,

@@ -164,6 +164,8 @@ struct gvt_plan {
 namespace gvt {
 // stage groups reported by gvt_plan_profile
 enum Stage { ST_PREP = 0, ST_STAGE1 = 1, ST_STAGE2 = 2, ST_OTHER = 3, kStages = 4 };
+// back-to-back repeats of a product's stage-2 launches under gvt_plan_profile
+constexpr int kProfileStage2Repeat = 8;
 int64_t rows_of(const gvt_plan *P, int f);
 int64_t cols_of(const gvt_plan *P, int f);
 int64_t nkeys_of(const gvt_plan *P, int key);
