@@ -1018,9 +1018,9 @@ __device__ __forceinline__ void stage2y_tile(
 // per SIMD, and reads the F1 pieces of OB outputs together.  Every FMA is the
 // one stage2y_tile makes, in the same order: the results are bitwise equal.
 // (Measured, FP64 / FP32 4-RHS blocks on one MI355X, 200 000 outputs: 2000 x
-// 500 grid 446 / 170 us -> 284 / 116 us, 1000 x 1000 grid 237 / 94 us -> 162 /
-// 70 us.  The S chunks staged in LDS as well cost more LDS traffic than they
-// saved: 336 / 194 us on the 2000 x 500 grid at four waves per SIMD.)
+// 500 grid 446 / 170 us -> 285 / 118 us, 1000 x 1000 grid 237 / 94 us -> 158 /
+// 69 us.  The S chunks staged in LDS as well cost more LDS traffic than they
+// saved: 329 / 194 us on the 2000 x 500 grid at four waves per SIMD.)
 template <class T> struct S2ypCfg {
   typedef S2yCfg<T, 4> B;
   static constexpr int OPG = 2 * B::OPG;  // outputs per group per pass
