@@ -536,6 +536,13 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
   const bool use_graph = s != nullptr;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
+  hipStream_t cap = nullptr;  // capture stream (default priority)
+  struct CapStream {
+    hipStream_t &c;
+    ~CapStream() {
+      if (c) (void)hipStreamDestroy(c);
+    }
+  } cap_guard{cap};
   int status = GVT_OK;
   int total_iter = 0;
   bool first = true;
@@ -621,16 +628,29 @@ int krr_cg_impl(int kind, const double *D, int64_t d, int64_t ldd, const double 
       ++total_iter;
       first = false;
       if (use_graph) {
-        GVT_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        // the first block also runs eagerly on s, and while the device works
+        // through it the same block is captured on a stream of the solve's own
+        // (a graph holds kernels and arguments, not a stream) and instantiated;
+        // the iterations run as before, the host checks after this block
+        for (int k = 0; k < check_every; ++k) iteration();
+        total_iter += check_every;
+        if (!cap) GVT_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        const hipStream_t run_s = s;
+        s = cap;  // the iteration's launches follow s
+        GVT_HIP_CHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         try {
           for (int k = 0; k < check_every; ++k) iteration();
         } catch (...) {
+          s = run_s;
+          P->last_stream = run_s;
           hipGraph_t g = nullptr;
-          (void)hipStreamEndCapture(s, &g);
+          (void)hipStreamEndCapture(cap, &g);
           if (g) (void)hipGraphDestroy(g);
           throw;
         }
-        GVT_HIP_CHECK(hipStreamEndCapture(s, &graph));
+        s = run_s;
+        P->last_stream = run_s;
+        GVT_HIP_CHECK(hipStreamEndCapture(cap, &graph));
         GVT_HIP_CHECK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
       }
     } else if (use_graph) {
