@@ -61,6 +61,25 @@ def test_ridge_product_sampled_rows(gvt, ridge, prec):
     assert relerr(u[rows], ref) < (1e-10 if prec == "f64" else 1e-5)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ridge_product_four_rhs_sampled_rows(gvt, ridge, prec, monkeypatch):
+    # four RHS in one pass over the full ridge workload: the S-row grouped stage 2 with its
+    # key chunks pipelined (the kernel of 4-RHS blocks in both precisions here)
+    monkeypatch.setenv("GVT_MAX_RHS_BLOCK", "4")
+    p = ridge
+    dt = torch.float64 if prec == "f64" else torch.float32
+    D, T = dev(p["D"], dt), dev(p["T"], dt)
+    c, e = dev(p["c"]), dev(p["e"])
+    V = np.random.default_rng(33).standard_normal((len(p["c"]), 4))
+    plan = gvt.gvt_plan_create("kronecker", D.shape, T.shape, (c, e), (c, e), flags=gvt.FLAG_SYMMETRIC_BASES)
+    u = plan.execute(D, T, dev(V, dt))[0].double().cpu().numpy()
+    plan.close()
+    rows = np.random.default_rng(34).choice(len(p["c"]), 256, replace=False)
+    ref = oracle.pairwise_matvec("kronecker", p["D"], p["T"], (p["c"], p["e"]), (p["c"], p["e"]), V, rows=rows)
+    for r in range(4):
+        assert relerr(u[rows, r], ref[:, r]) < (1e-10 if prec == "f64" else 1e-5), r
+
+
 def test_ridge_cg_true_residual_sampled(gvt, ridge):
     # the headline solve: its reported true residual, and the oracle's residual on sampled rows
     p = ridge
