@@ -184,6 +184,31 @@ def test_own_sort_matches_library_sort(gvt, monkeypatch, n):
     assert relerr(res[1].cpu().numpy(), ref) < 1e-10
 
 
+@pytest.mark.parametrize("ncol", [1500, 70000])
+def test_own_sort_matches_library_sort_at_scale(gvt, monkeypatch, ncol):
+    # 4 000 037 pairs (3 907 tiles, a ragged last one): 21-bit keys in three passes over a
+    # 1500 x 900 grid, and 34-bit keys in four passes over 70000 x 70000 index ranges;
+    # products of device-built plans agree bit for bit with either sort
+    r = np.random.default_rng([17, ncol])
+    n = 4_000_037
+    rows_d, rows_t = (1500, 900) if ncol == 1500 else (5, 4)
+    cols_t = 900 if ncol == 1500 else ncol
+    D = r.standard_normal((rows_d, ncol))
+    T = r.standard_normal((rows_t, cols_t))
+    c = r.integers(0, ncol, n).astype(np.int32)
+    e = r.integers(0, cols_t, n).astype(np.int32)
+    a = r.integers(0, rows_d, 3000).astype(np.int32)
+    b = r.integers(0, rows_t, 3000).astype(np.int32)
+    v = r.standard_normal(n)
+    Dd, Td = dev(D), dev(T)
+    monkeypatch.setenv("GVT_PLAN_DEVICE", "1")
+    res = []
+    for lib in ("1", "0"):
+        monkeypatch.setenv("GVT_PLAN_LIBRARY_SORT", lib)
+        res.append(gvt.gvt_matvec(Dd, Td, (idx(a), idx(b)), (idx(c), idx(e)), dev(v)))
+    assert torch.equal(res[0], res[1])
+
+
 def test_index_errors_on_device(gvt, monkeypatch):
     monkeypatch.setenv("GVT_PLAN_DEVICE", "1")
     D = dev(np.eye(5)); T = dev(np.eye(4))
