@@ -905,6 +905,28 @@ def test_side_streams_and_threads_match_sequential(gvt):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cg_four_lambdas_graph_bitwise(gvt, monkeypatch, prec):
+    # four lambdas: one block of 4 RHS, so the iterations' products take the pipelined
+    # S-row grouped stage 2 under the run flag, replayed from a graph on a side stream
+    # and launched one by one on the null stream; bitwise the same solves, converged
+    monkeypatch.setenv("GVT_MAX_RHS_BLOCK", "4")
+    mp = gvt.F64 if prec == "f64" else gvt.F32
+    p = W.make_heterogeneous(95, 1, 300, 200, 12000, 16, labels=True)
+    # (the oracle's CG needs 119, 87, 64 and 44 iterations to 1e-7: the systems stop one
+    # by one inside the block)
+    args = ("kronecker", dev(p["D"]), dev(p["T"]), (idx(p["c"]), idx(p["e"])), dev(p["y"]),
+            [0.5, 1.0, 2.0, 5.0])
+    torch.cuda.synchronize()
+    A0, i0, r0, c0 = gvt.gvt_krr_cg(*args, max_iter=300, tol=1e-6, matvec_prec=mp, check_every=3)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        A1, i1, r1, c1 = gvt.gvt_krr_cg(*args, max_iter=300, tol=1e-6, matvec_prec=mp, check_every=3)
+    side.synchronize()
+    assert c0 == c1 and torch.equal(A0, A1) and (i0 == i1).all() and (r0 == r1).all()
+    assert c0 == 0 and (r0 < 1e-6).all()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_cg_graph_replays_on_side_stream_bitwise(gvt, prec):
     # on a non-null stream the CG iterations after the first are captured once into a
     # graph and replayed (here every 2 iterations, so about 20 replays); on the null
